@@ -1,0 +1,410 @@
+/*
+ * FP64 CPU oracle of the hPF-MD (MD-SCF) timestep -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain loops in the order the method defines them, no blocking, no fusion.
+ * See hpf_oracle.h for the conventions. The quantities and the readings of
+ * the paper they rest on:
+ *
+ *   O1 cell coordinate  u = fl32(x * s), s = fl32(M / L); c = floor(u) mod M;
+ *                       f = fl32(u - floor(u)).
+ *   O2 1-D weights      q = floor(f * 2^S); w0 = 2^S - q, w1 = q. Vertex
+ *                       c + a (a in {0,1}^3, periodic) receives the product
+ *                       W_a = w_ax * w_ay * w_az; sum_a W_a = 2^3S exactly.
+ *                       (MD-SCF section: a bead spreads its density fractions
+ *                       over the eight vertices of its cell; the number of
+ *                       vertices equals the number of cells, Algorithm 1
+ *                       Kernel 2, so the vertex mesh is periodic.)
+ *   O3 counts           n_K(v) = sum over beads of type K of W_a  (uint64).
+ *   O4 normalisation    phi_K = n_K / (2^3S rho0 dV), rho0 = N / V_box,
+ *                       dV = V_box / M^3 (reading: the paper does not state it;
+ *                       this choice makes a uniform melt give sum_K phi_K = 1).
+ *   O5 potential        V_K = kT sum_K' chi_KK' phi_K' + (1/kappa)(sum_K phi_K - 1)
+ *                       (eq. 4; eq. 5 is its two-species case).
+ *   O6 gradient         g_K,d(v) = (V_K(v + e_d) - V_K(v - e_d)) / (2 h_d),
+ *                       h_d = L_d / M_d, periodic (reading of Algorithm 1
+ *                       Kernel 3: a centred difference at the vertex instead of
+ *                       the staggered pair).
+ *   O7 gather           F_i = -sum_a (W_a / 2^3S) g_{T_i}(c_i + a): the field
+ *                       force of eq. 6, interpolated with the same weights used
+ *                       for the density (Algorithm 1 Kernel 4, reading).
+ *   O8 bonds            U = k (r - r0)^2 (eq. 7, no factor 1/2); d = minimum
+ *                       image of x_j - x_i; F_i += 2k (r - r0) d / r.
+ *   O9 velocity Verlet  (Integration methods section) with unit mass by
+ *                       default and wrapping into the periodic box.
+ *   O10 energies        KE = sum m v^2 / 2; E_bond = sum over bonds of U;
+ *                       W = rho0 dV sum_v [ kT/2 sum_KK' chi phi_K phi_K'
+ *                       + 1/(2 kappa) (sum_K phi_K - 1)^2 ], the functional
+ *                       whose derivative by the bead count at v is V_K(v).
+ *
+ * Pins (what fixes each function independently of this file) are in the
+ * CPU test suite: partition of unity, hand-derived single-bead weights,
+ * uniform melt, linear potential, whole-cell translation, permutation
+ * invariance, a brute-force pair-kernel evaluation for 1-3 beads, the
+ * closed-form bond force, the exact velocity-Verlet recurrence of a harmonic
+ * dimer, and a finite-difference check of dW/dn = V.
+ */
+#include "hpf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const double TWO_3S = 281474976710656.0; /* 2^48 = (2^S)^3 */
+
+void or_mesh_init(or_mesh_t* m, const float L[3], const int32_t M[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        m->L[d] = (double)L[d];
+        m->M[d] = M[d];
+        m->s[d] = (float)((double)M[d] / (double)L[d]);
+    }
+}
+
+int or_cell_weights(double x, float s, int32_t M, int32_t* c, uint32_t w[2])
+{
+    if (!isfinite(x))
+        return 1;
+    float u = (float)(x * (double)s);          /* O1: one FP32 rounding */
+    if (!(fabsf(u) < 16777216.0f))
+        return 1;
+    double fl = floor((double)u);
+    float f = (float)((double)u - fl);         /* fractional part, FP32 */
+    uint32_t q = (uint32_t)floor((double)f * (double)OR_ONE);   /* O2 */
+    int64_t ci = ((int64_t)fl) % M;
+    if (ci < 0)
+        ci += M;
+    *c = (int32_t)ci;
+    w[0] = OR_ONE - q;
+    w[1] = q;
+    return 0;
+}
+
+/* Cell and weights of bead i in all three dimensions; 0 if valid. */
+static int bead_cell(const double* R, int64_t i, const or_mesh_t* m, int32_t c[3],
+                     uint32_t w[3][2])
+{
+    for (int d = 0; d < 3; ++d)
+        if (or_cell_weights(R[3 * i + d], m->s[d], m->M[d], &c[d], w[d]))
+            return 1;
+    return 0;
+}
+
+static int64_t vertex_index(const or_mesh_t* m, int32_t x, int32_t y, int32_t z)
+{
+    return ((int64_t)z * m->M[1] + y) * m->M[0] + x;
+}
+
+int64_t or_density(const double* R, const uint8_t* T, int64_t N, const or_mesh_t* m,
+                   int32_t K, uint64_t* counts)
+{
+    const int64_t nm = (int64_t)m->M[0] * m->M[1] * m->M[2];
+    int64_t skipped = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int32_t c[3];
+        uint32_t w[3][2];
+        if (T[i] >= K || bead_cell(R, i, m, c, w)) {
+            ++skipped;
+            continue;
+        }
+        uint64_t* nk = counts + (int64_t)T[i] * nm;
+        for (int az = 0; az < 2; ++az)
+            for (int ay = 0; ay < 2; ++ay)
+                for (int ax = 0; ax < 2; ++ax) {
+                    int32_t vx = (c[0] + ax) % m->M[0];
+                    int32_t vy = (c[1] + ay) % m->M[1];
+                    int32_t vz = (c[2] + az) % m->M[2];
+                    uint64_t Wa = (uint64_t)w[0][ax] * w[1][ay] * w[2][az];
+                    nk[vertex_index(m, vx, vy, vz)] += Wa;
+                }
+    }
+    return skipped;
+}
+
+void or_potential(const uint64_t* counts, const or_mesh_t* m, int64_t n_beads, int32_t K,
+                  double kT, double inv_kappa, const double* chi, double* V, double* W)
+{
+    const int64_t nm = (int64_t)m->M[0] * m->M[1] * m->M[2];
+    const double vol = m->L[0] * m->L[1] * m->L[2];
+    const double rho0 = (double)n_beads / vol;
+    const double dV = vol / (double)nm;
+    double w_sum = 0.0;
+    for (int64_t v = 0; v < nm; ++v) {
+        double phi[OR_MAX_TYPES];
+        double total = 0.0;
+        for (int k = 0; k < K; ++k) {
+            phi[k] = n_beads > 0 ? (double)counts[k * nm + v] / (TWO_3S * rho0 * dV) : 0.0;
+            total += phi[k];
+        }
+        double delta = total - 1.0;
+        double inter = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double mix = 0.0;
+            for (int kk = 0; kk < K; ++kk)
+                mix += chi[k * K + kk] * phi[kk];
+            V[k * nm + v] = kT * mix + inv_kappa * delta;
+            inter += phi[k] * mix;
+        }
+        w_sum += 0.5 * kT * inter + 0.5 * inv_kappa * delta * delta;
+    }
+    if (W)
+        *W = rho0 * dV * w_sum;
+}
+
+void or_gradient(const double* V, const or_mesh_t* m, int32_t K, double* G)
+{
+    const int32_t Mx = m->M[0], My = m->M[1], Mz = m->M[2];
+    const int64_t nm = (int64_t)Mx * My * Mz;
+    const double h[3] = {m->L[0] / Mx, m->L[1] / My, m->L[2] / Mz};
+    for (int k = 0; k < K; ++k) {
+        const double* Vk = V + k * nm;
+        for (int32_t z = 0; z < Mz; ++z)
+            for (int32_t y = 0; y < My; ++y)
+                for (int32_t x = 0; x < Mx; ++x) {
+                    int64_t v = vertex_index(m, x, y, z);
+                    double* g = G + 3 * (k * nm + v);
+                    g[0] = (Vk[vertex_index(m, (x + 1) % Mx, y, z)] -
+                            Vk[vertex_index(m, (x + Mx - 1) % Mx, y, z)]) / (2.0 * h[0]);
+                    g[1] = (Vk[vertex_index(m, x, (y + 1) % My, z)] -
+                            Vk[vertex_index(m, x, (y + My - 1) % My, z)]) / (2.0 * h[1]);
+                    g[2] = (Vk[vertex_index(m, x, y, (z + 1) % Mz)] -
+                            Vk[vertex_index(m, x, y, (z + Mz - 1) % Mz)]) / (2.0 * h[2]);
+                }
+    }
+}
+
+int64_t or_gather(const double* R, const uint8_t* T, int64_t N, const or_mesh_t* m,
+                  int32_t K, const double* G, double* F)
+{
+    const int64_t nm = (int64_t)m->M[0] * m->M[1] * m->M[2];
+    int64_t skipped = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double f[3] = {0.0, 0.0, 0.0};
+        int32_t c[3];
+        uint32_t w[3][2];
+        if (T[i] >= K || bead_cell(R, i, m, c, w)) {
+            ++skipped;
+        } else {
+            const double* Gk = G + 3 * (int64_t)T[i] * nm;
+            for (int az = 0; az < 2; ++az)
+                for (int ay = 0; ay < 2; ++ay)
+                    for (int ax = 0; ax < 2; ++ax) {
+                        int64_t v = vertex_index(m, (c[0] + ax) % m->M[0],
+                                                 (c[1] + ay) % m->M[1], (c[2] + az) % m->M[2]);
+                        double Wa = (double)((uint64_t)w[0][ax] * w[1][ay] * w[2][az]) / TWO_3S;
+                        for (int d = 0; d < 3; ++d)
+                            f[d] -= Wa * Gk[3 * v + d];
+                    }
+        }
+        for (int d = 0; d < 3; ++d)
+            F[3 * i + d] = f[d];
+    }
+    return skipped;
+}
+
+void or_bonds(const double* R, int64_t N, const int32_t* bonds, int32_t D, double k,
+              double r0, const double L[3], double* F, double* E)
+{
+    double e = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        for (int32_t b = 0; b < D; ++b) {
+            int32_t j = bonds[(int64_t)b * N + i];
+            if (j < 0)
+                continue;
+            double d[3], r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                d[a] = R[3 * (int64_t)j + a] - R[3 * i + a];
+                d[a] -= L[a] * nearbyint(d[a] / L[a]);    /* minimum image */
+                r2 += d[a] * d[a];
+            }
+            double r = sqrt(r2);
+            double coef;                                  /* F_i = coef * d */
+            if (r0 == 0.0)
+                coef = 2.0 * k;
+            else
+                coef = r > 0.0 ? 2.0 * k * (r - r0) / r : 0.0;
+            for (int a = 0; a < 3; ++a)
+                F[3 * i + a] += coef * d[a];
+            e += k * (r - r0) * (r - r0);
+        }
+    }
+    if (E)
+        *E = 0.5 * e;                                     /* each bond seen twice */
+}
+
+static double wrap_coord(double x, double L)
+{
+    double r = fmod(x, L);
+    if (r < 0.0)
+        r += L;
+    if (r >= L)
+        r = 0.0;
+    return r;
+}
+
+void or_verlet_half1(double* R, double* V, const double* F, const double* inv_mass,
+                     int64_t N, double dt, const double L[3])
+{
+    for (int64_t i = 0; i < N; ++i) {
+        double im = inv_mass ? inv_mass[i] : 1.0;
+        for (int a = 0; a < 3; ++a) {
+            V[3 * i + a] += 0.5 * dt * F[3 * i + a] * im;
+            R[3 * i + a] = wrap_coord(R[3 * i + a] + dt * V[3 * i + a], L[a]);
+        }
+    }
+}
+
+void or_verlet_half2(double* V, const double* F, const double* inv_mass, int64_t N,
+                     double dt, double* out4)
+{
+    double ke = 0.0, p[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < N; ++i) {
+        double im = inv_mass ? inv_mass[i] : 1.0;
+        double mass = 1.0 / im;
+        for (int a = 0; a < 3; ++a) {
+            V[3 * i + a] += 0.5 * dt * F[3 * i + a] * im;
+            ke += 0.5 * mass * V[3 * i + a] * V[3 * i + a];
+            p[a] += mass * V[3 * i + a];
+        }
+    }
+    if (out4) {
+        out4[0] = ke;
+        out4[1] = p[0];
+        out4[2] = p[1];
+        out4[3] = p[2];
+    }
+}
+
+int64_t or_forces(const double* R, const uint8_t* T, int64_t N, const or_params_t* p,
+                  double* F_field, double* F_bond, double* energies2)
+{
+    const or_mesh_t* m = p->mesh;
+    const int64_t nm = (int64_t)m->M[0] * m->M[1] * m->M[2];
+    uint64_t* counts = calloc((size_t)(p->K * nm), sizeof(uint64_t));
+    double* V = malloc(sizeof(double) * (size_t)(p->K * nm));
+    double* G = malloc(sizeof(double) * (size_t)(3 * p->K * nm));
+    if (!counts || !V || !G) {
+        free(counts);
+        free(V);
+        free(G);
+        return -1;
+    }
+    double W = 0.0, Eb = 0.0;
+    int64_t skipped = or_density(R, T, N, m, p->K, counts);
+    or_potential(counts, m, N, p->K, p->kT, p->inv_kappa, p->chi, V, &W);
+    or_gradient(V, m, p->K, G);
+    or_gather(R, T, N, m, p->K, G, F_field);
+    memset(F_bond, 0, sizeof(double) * (size_t)(3 * N));
+    or_bonds(R, N, p->bonds, p->D, p->k_bond, p->r0, m->L, F_bond, &Eb);
+    if (energies2) {
+        energies2[0] = W;
+        energies2[1] = Eb;
+    }
+    free(counts);
+    free(V);
+    free(G);
+    return skipped;
+}
+
+static double kinetic(const double* V, const double* inv_mass, int64_t N)
+{
+    double ke = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        double mass = inv_mass ? 1.0 / inv_mass[i] : 1.0;
+        for (int a = 0; a < 3; ++a)
+            ke += 0.5 * mass * V[3 * i + a] * V[3 * i + a];
+    }
+    return ke;
+}
+
+int or_run(double* R, double* V, const uint8_t* T, const double* inv_mass, int64_t N,
+           const or_params_t* p, double dt, int32_t n_steps, double* energies)
+{
+    double* Ff = malloc(sizeof(double) * (size_t)(3 * N + 1));
+    double* Fb = malloc(sizeof(double) * (size_t)(3 * N + 1));
+    double* F = malloc(sizeof(double) * (size_t)(3 * N + 1));
+    if (!Ff || !Fb || !F) {
+        free(Ff);
+        free(Fb);
+        free(F);
+        return -1;
+    }
+    double e2[2];
+    int rc = 0;
+    if (or_forces(R, T, N, p, Ff, Fb, e2) < 0)
+        rc = -1;
+    for (int64_t j = 0; j < 3 * N; ++j)
+        F[j] = Ff[j] + Fb[j];
+    double ke = kinetic(V, inv_mass, N);
+    energies[0] = ke;
+    energies[1] = e2[1];
+    energies[2] = e2[0];
+    energies[3] = ke + e2[0] + e2[1];
+    for (int32_t s = 1; s <= n_steps && rc == 0; ++s) {
+        double out4[4];
+        or_verlet_half1(R, V, F, inv_mass, N, dt, p->mesh->L);
+        if (or_forces(R, T, N, p, Ff, Fb, e2) < 0)
+            rc = -1;
+        for (int64_t j = 0; j < 3 * N; ++j)
+            F[j] = Ff[j] + Fb[j];
+        or_verlet_half2(V, F, inv_mass, N, dt, out4);
+        double* e = energies + 4 * (int64_t)s;
+        e[0] = out4[0];
+        e[1] = e2[1];
+        e[2] = e2[0];
+        e[3] = out4[0] + e2[0] + e2[1];
+    }
+    free(Ff);
+    free(Fb);
+    free(F);
+    return rc;
+}
+
+typedef struct {
+    uint32_t key;
+    int32_t tag;
+    int64_t idx;
+} sort_item;
+
+static int cmp_item(const void* a, const void* b)
+{
+    const sort_item* x = a;
+    const sort_item* y = b;
+    if (x->key != y->key)
+        return x->key < y->key ? -1 : 1;
+    if (x->tag != y->tag)
+        return x->tag < y->tag ? -1 : 1;
+    return 0;
+}
+
+int or_sort_perm(const double* R, const int32_t* tag, int64_t N, const or_mesh_t* m,
+                 int32_t B, int64_t* perm, uint32_t* keys)
+{
+    sort_item* it = malloc(sizeof(sort_item) * (size_t)(N > 0 ? N : 1));
+    if (!it)
+        return -1;
+    int32_t nb[3];
+    for (int d = 0; d < 3; ++d)
+        nb[d] = (m->M[d] + B - 1) / B;
+    for (int64_t i = 0; i < N; ++i) {
+        int32_t c[3];
+        uint32_t w[3][2];
+        uint32_t key = 0xFFFFFFFFu;
+        if (!bead_cell(R, i, m, c, w)) {
+            uint32_t brick = ((uint32_t)(c[2] / B) * (uint32_t)nb[1] + (uint32_t)(c[1] / B)) *
+                                 (uint32_t)nb[0] + (uint32_t)(c[0] / B);
+            uint32_t local = ((uint32_t)(c[2] % B) * (uint32_t)B + (uint32_t)(c[1] % B)) *
+                                 (uint32_t)B + (uint32_t)(c[0] % B);
+            key = brick * (uint32_t)(B * B * B) + local;
+        }
+        it[i].key = key;
+        it[i].tag = tag[i];
+        it[i].idx = i;
+        if (keys)
+            keys[i] = key;
+    }
+    qsort(it, (size_t)N, sizeof(sort_item), cmp_item);
+    for (int64_t i = 0; i < N; ++i)
+        perm[i] = it[i].idx;
+    free(it);
+    return 0;
+}

@@ -1,0 +1,114 @@
+/*
+ * FP64 CPU oracle of the hybrid particle-field MD (MD-SCF / hPF-MD) timestep.
+ *
+ * TEST INFRASTRUCTURE ONLY. This is the plain, slow, obviously-correct
+ * reference that the HIP path is checked against. Only the test suite, the
+ * package smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product path never does. It shares no code, header, table or helper with
+ * the HIP library.
+ *
+ * Every floating-point quantity is computed in double precision. The one
+ * place where floating point decides an integer -- the cell coordinate
+ * u = x * s that picks a bead's cell and its fixed-point cloud-in-cell
+ * weights -- is taken in FP32 (one IEEE single rounding of the exact
+ * product), because that quantisation is part of the method's encoding and
+ * both sides must take the same integer decision.
+ *
+ * Paper: Zhu et al., "GALAMOST: GPU-accelerated large-scale molecular
+ * simulation toolkit" (arXiv 1310.2041), section "The MD-SCF treatment of
+ * interparticle forces", eqs. (4)-(6), Algorithm 1; section "Bonded forces",
+ * eq. (7); section "Integration methods" (velocity Verlet, periodic box).
+ *
+ * Parity status per function is listed in the header comment of each
+ * function in hpf_oracle.c.
+ */
+#ifndef HPF_ORACLE_H
+#define HPF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_FIX_BITS 16                 /* S: bits of the 1-D fixed-point weight */
+#define OR_ONE (1u << OR_FIX_BITS)     /* 2^S */
+#define OR_MAX_TYPES 8
+
+typedef struct {
+    double L[3];   /* box edges (the FP32 box widened to double) */
+    int32_t M[3];  /* mesh points = cells per edge (periodic) */
+    float s[3];    /* quantisation scale, fl32(M / L) */
+} or_mesh_t;
+
+/* Fill a mesh description from the FP32 box edges and the mesh size. */
+void or_mesh_init(or_mesh_t* m, const float L[3], const int32_t M[3]);
+
+/* O1-O2 for one coordinate: cell index c (mod M) and the two 1-D weights
+ * w[0] = 2^S - q (lower vertex), w[1] = q (upper vertex). Returns 0, or 1
+ * when the coordinate is not finite or |x*s| >= 2^24 (bead skipped). */
+int or_cell_weights(double x, float s, int32_t M, int32_t* c, uint32_t w[2]);
+
+/* O3: counts[K][Mz][My][Mx] += fixed-point CIC weights of every bead.
+ * R is double [N][3]. Returns the number of skipped (invalid) beads. */
+int64_t or_density(const double* R, const uint8_t* T, int64_t N, const or_mesh_t* m,
+                   int32_t K, uint64_t* counts);
+
+/* O4-O5 and O10(W): potential V[K][M^3] from the counts (eq. 4), plus the
+ * field energy W if W != NULL. n_beads is the total bead count that fixes
+ * the mean density rho0 = N / V_box. */
+void or_potential(const uint64_t* counts, const or_mesh_t* m, int64_t n_beads, int32_t K,
+                  double kT, double inv_kappa, const double* chi, double* V, double* W);
+
+/* O6: centred periodic gradient G[K][M^3][3] of V. */
+void or_gradient(const double* V, const or_mesh_t* m, int32_t K, double* G);
+
+/* O7: field force F[N][3] = -sum_a (W_a / 2^3S) G_{T_i}(c_i + a) (overwrites F). */
+int64_t or_gather(const double* R, const uint8_t* T, int64_t N, const or_mesh_t* m,
+                  int32_t K, const double* G, double* F);
+
+/* O8: harmonic bonds U = k (r - r0)^2 (eq. 7); F[N][3] += ; *E (if non-NULL)
+ * receives the bond energy, every bond counted once. bonds is the table
+ * [D][N] of partner indices (-1 = none). */
+void or_bonds(const double* R, int64_t N, const int32_t* bonds, int32_t D, double k,
+              double r0, const double L[3], double* F, double* E);
+
+/* O9: first half of velocity Verlet: v += dt/2 F/m; x += dt v; wrap to [0, L). */
+void or_verlet_half1(double* R, double* V, const double* F, const double* inv_mass,
+                     int64_t N, double dt, const double L[3]);
+/* O9: second half: v += dt/2 F/m. out4 (if non-NULL) = {KE, Px, Py, Pz}. */
+void or_verlet_half2(double* V, const double* F, const double* inv_mass, int64_t N,
+                     double dt, double* out4);
+
+/* Full force evaluation (O1-O8). F is overwritten; energies (nullable)
+ * receive {W, E_bond}. Work arrays are allocated internally. Returns the
+ * number of skipped beads, or -1 on allocation failure. */
+typedef struct {
+    const or_mesh_t* mesh;
+    int32_t K;
+    double kT, inv_kappa;
+    const double* chi;      /* [K][K] */
+    const int32_t* bonds;   /* [D][N] */
+    int32_t D;
+    double k_bond, r0;
+} or_params_t;
+
+int64_t or_forces(const double* R, const uint8_t* T, int64_t N, const or_params_t* p,
+                  double* F_field, double* F_bond, double* energies2);
+
+/* n_steps of velocity Verlet from (R, V). energies [n_steps+1][4] receives
+ * {KE, E_bond, W, E_tot} at the start and after every step. inv_mass may be
+ * NULL (unit masses). Returns 0, or -1 on allocation failure. */
+int or_run(double* R, double* V, const uint8_t* T, const double* inv_mass, int64_t N,
+           const or_params_t* p, double dt, int32_t n_steps, double* energies);
+
+/* a0: cell-sort permutation. key = brick-major cell index with bricks of
+ * B^3 cells; perm receives the bead order sorted by (key, tag). keys
+ * (nullable) receives each bead's key in the input order. */
+int or_sort_perm(const double* R, const int32_t* tag, int64_t N, const or_mesh_t* m,
+                 int32_t B, int64_t* perm, uint32_t* keys);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
