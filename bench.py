@@ -1,0 +1,211 @@
+"""hPF-MD throughput benchmark on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c3]
+
+A step is one pass of the whole hot path over the synthetic workload:
+velocity-Verlet half kick + drift + wrap, the cell sort (every
+``--sort-every`` steps), density scatter, field potential, field gradient,
+force gather, bond forces, second half kick, and the FP64 energy / momentum
+reductions. Inputs are resident in HBM before the timed region starts.
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "hPF-MD particle-steps/s at 1M & 10M beads; %HBM peak; batched vs plain speedup"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(name: str, N: int, K: int, nm: int, D: int) -> float:
+    """Bytes a kernel must move per launch (each array read / written once)."""
+    return {
+        "verlet_half1": 80.0 * N,                   # R, Vel read+write; F read
+        "density_scatter": 17.0 * N + 8.0 * K * nm,  # R, T read; counts written once
+        "field_potential": 20.0 * K * nm,            # counts read + cleared; V written
+        "field_gradient": 20.0 * K * nm,             # V read; G written
+        "force_gather": 33.0 * N + 16.0 * K * nm,    # R, T read; F written; G read once
+        "bond_forces": (48.0 + 4.0 * D) * N,         # R, bond table, F read; F written
+        "verlet_half2": 48.0 * N,                    # Vel read+write; F read
+        "reduce": 6 * 1024 * 8.0,
+    }[name]
+
+
+class Timers:
+    """HIP events around every call of the step, on torch's current stream
+    (the stream the library launches on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = {}
+
+    def wrap(self, name, fn, *a, **kw):
+        ev0 = self.torch.cuda.Event(enable_timing=True)
+        ev1 = self.torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        fn(*a, **kw)
+        ev1.record()
+        self.pairs.setdefault(name, []).append((ev0, ev1))
+
+    def summary(self):
+        out = {}
+        for k, v in self.pairs.items():
+            ts = [a.elapsed_time(b) for a, b in v]
+            out[k] = {"avg_us": 1e3 * sum(ts) / len(ts), "launches": len(ts)}
+        return out
+
+
+def timed_step(st, hpf, engine, tm, sort):
+    import torch  # noqa: F401
+    tm.wrap("verlet_half1", hpf.verlet_step, st.R, st.Vel, st.F, st.dt, st.box, 1)
+    if sort:
+        tm.wrap("sort_by_cell", st.sort)
+    tm.wrap("density_scatter", hpf.hpf_density_scatter, st.R, st.T, st.mesh, st.K, st.counts)
+    tm.wrap("field_potential", hpf.hpf_field_potential, st.counts, st.mesh, st.field, st.V,
+            st.part[engine.ROW_W])
+    tm.wrap("field_gradient", hpf.hpf_field_gradient, st.V, st.mesh, st.K, st.G)
+    tm.wrap("force_gather", hpf.hpf_force_gather, st.R, st.T, st.mesh, st.K, st.G, st.F)
+    tm.wrap("bond_forces", hpf.bond_forces, st.R, st.bonds, st.k_bond, st.r0, st.box, st.F,
+            st.part[engine.ROW_EB])
+    tm.wrap("verlet_half2", hpf.verlet_step, None, st.Vel, st.F, st.dt, st.box, 2,
+            kin_part=st.part[engine.ROW_KE:engine.ROW_KE + 4])
+    tm.wrap("reduce", hpf.hpf_reduce_partials, st.part, engine.N_ROWS, st.energy)
+    st.steps_done += 1
+
+
+def run_workload(cfg, steps, warmup, sort_every, instrument=True):
+    import torch
+
+    from paper_1310_2041_amd import engine, hpf
+    from synth import workloads as wl
+
+    spec = wl.SPECS[cfg]
+    s = wl.build(spec)
+    st = engine.HpfState.from_system(s)
+    del s
+    st.start(sort=True)
+    for _ in range(warmup):
+        st.step(report=True, sort=sort_every > 0 and st.steps_done % sort_every == 0)
+    torch.cuda.synchronize()
+    tm = Timers(torch)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record()
+    for _ in range(steps):
+        do_sort = sort_every > 0 and st.steps_done % sort_every == 0
+        if instrument:
+            timed_step(st, hpf, engine, tm, do_sort)
+        else:
+            st.step(report=True, sort=do_sort)
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    flags = hpf.hpf_get_device_status()
+    e = st.energies()
+    return {"spec": spec, "N": st.N, "K": st.K, "nm": st.nm, "D": st.bonds.shape[0],
+            "ms_total": ms, "wall_s": wall, "kernels": tm.summary() if instrument else {},
+            "flags": flags, "energies": e}
+
+
+def cpu_baseline(cfg, n_steps):
+    """The FP64 oracle (single-threaded C) on a bounded sample of the workload."""
+    import oracle
+    from synth import workloads as wl
+
+    s = wl.build(wl.SPECS[cfg])
+    t0 = time.perf_counter()
+    oracle.forces(s)
+    t_force = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.run(s, n_steps)
+    t_run = time.perf_counter() - t0
+    t_steps = max(t_run - t_force, 1e-9)      # run() evaluates the initial forces first
+    return {"value": s.N * n_steps / t_steps, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_steps} velocity-Verlet steps of the full {s.N}-bead {cfg} workload "
+                      f"(FP64 C oracle, one thread; {t_steps:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--also", default="c2", help="second workload reported under 'also' ('' = none)")
+    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the hPF-MD path here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    r = run_workload(args.config, args.steps, args.warmup, args.sort_every)
+    ms_step = r["ms_total"] / args.steps
+    value = r["N"] * args.steps / (r["ms_total"] * 1e-3)
+    kern = r["kernels"]
+    per_kernel = {}
+    for name, k in kern.items():
+        if name == "sort_by_cell":
+            continue
+        b = algorithmic_bytes(name, r["N"], r["K"], r["nm"], r["D"])
+        per_kernel[name] = {"avg_us": round(k["avg_us"], 2), "alg_GBs": round(b / (k["avg_us"] * 1e-6) / 1e9, 1)}
+    if "sort_by_cell" in kern:
+        per_kernel["sort_by_cell"] = {"avg_us": round(kern["sort_by_cell"]["avg_us"], 2),
+                                      "launches": kern["sort_by_cell"]["launches"]}
+    dom = max((n for n in per_kernel if n != "sort_by_cell"), key=lambda n: per_kernel[n]["avg_us"])
+    dom_bytes = algorithmic_bytes(dom, r["N"], r["K"], r["nm"], r["D"])
+    achieved = dom_bytes / (kern[dom]["avg_us"] * 1e-6) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+u64",
+        "data": "synthetic",
+        "config": {"workload": r["spec"].name, "beads": r["N"], "species": r["K"],
+                   "mesh": [r["spec"].M] * 3, "box": r["spec"].L, "sort_every": args.sort_every,
+                   "energy_report_every": 1, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "kernels": per_kernel,
+        "device_flags": r["flags"],
+    }
+    if args.also and args.also != args.config:
+        r2 = run_workload(args.also, args.steps, args.warmup, args.sort_every, instrument=False)
+        out["also"] = {"workload": r2["spec"].name, "beads": r2["N"],
+                       "value": r2["N"] * args.steps / (r2["ms_total"] * 1e-3),
+                       "ms_per_step": r2["ms_total"] / args.steps,
+                       "note": "working set fits the 256 MB Infinity Cache"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,251 @@
+/*
+ * hpf.h -- C ABI of libhpf, the MI355X (gfx950) hybrid particle-field MD step.
+ *
+ * The library computes one timestep of hybrid particle-field molecular
+ * dynamics (hPF-MD; "MD-SCF" in Zhu et al., GALAMOST, arXiv 1310.2041):
+ * beads deposit onto a periodic density mesh, a local field potential is
+ * built from the Flory-Huggins chi matrix and a compressibility term, its
+ * mesh gradient is interpolated back onto the beads as forces, harmonic bond
+ * forces are added and velocity Verlet advances the system.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers to memory owned by the caller
+ *    (hipMalloc or a framework allocator). The library never allocates and
+ *    never frees them. Small parameter structs and the box array are HOST
+ *    pointers, read during the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call only enqueues work on it and returns; results are valid once
+ *    the stream has reached that point.
+ *  - Bead arrays are structure-of-arrays, one row per bead, in storage order
+ *    i = 0..N-1: positions R, velocities Vel and forces F are float[N][4]
+ *    with (x, y, z, w); w is written as 0 and otherwise ignored. Types T are
+ *    uint8[N] in [0, K).
+ *  - Mesh arrays are [K][Mz][My][Mx] with x fastest. A mesh point is a cell
+ *    corner; the mesh is periodic, so there are as many points as cells.
+ *  - Return value: HPF_OK, or a negative hpf_status_t for errors detected on
+ *    the host before anything is enqueued (nothing is enqueued then).
+ *    Conditions that only the device can see (a bead that cannot be binned,
+ *    a mesh count near overflow, a non-finite coordinate after an update)
+ *    set sticky bits that hpf_get_device_status() reads.
+ *  - No C++ exception crosses this interface.
+ *  - Results do not depend on the order in which beads are stored, except
+ *    for the rounding order of FP64 energy sums; hpf_sort_by_cell() produces
+ *    a canonical order, after which every result is bitwise reproducible.
+ */
+#ifndef HPF_H
+#define HPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HPF_ABI_VERSION 1
+#define HPF_FIX_BITS 16     /* S: fractional bits of a 1-D cloud-in-cell weight */
+#define HPF_MAX_TYPES 8     /* K <= 8 species */
+#define HPF_NPART 1024      /* slots per component of an FP64 partial-sum buffer */
+#define HPF_MAX_BONDS 16    /* D <= 16 bond-table rows */
+
+typedef int32_t hpf_status_t;
+#define HPF_OK 0
+#define HPF_EINVAL (-1)     /* an argument is invalid (null pointer, bad size or mesh) */
+#define HPF_EHIP (-2)       /* the HIP runtime reported an error while enqueueing */
+#define HPF_ESPACE (-3)     /* a caller-provided workspace is too small */
+
+/* Sticky device status bits (hpf_get_device_status). */
+#define HPF_FLAG_BAD_BEAD 0x1u   /* a bead with a non-finite or out-of-range position
+                                    (|x*s| >= 2^24) or a type >= K was skipped */
+#define HPF_FLAG_OVERFLOW 0x2u   /* a mesh count reached 2^62 (risk of u64 wrap) */
+#define HPF_FLAG_NONFINITE 0x4u  /* verlet_step produced a non-finite coordinate */
+#define HPF_FLAG_BAD_BOND 0x8u   /* a bond-table entry was outside [-1, N) */
+#define HPF_FLAG_SORT_ORDER 0x10u /* a cell held more beads than the in-cell tag sort
+                                     handles; that cell's beads kept placement order */
+
+/* Periodic box and density mesh.
+ *  L      box edge lengths, > 0.
+ *  M      mesh points (= cells) per edge, >= 3.
+ *  s      cells per unit length, fl32(M / L): the bead coordinate in cell
+ *         units is u = fl32(x * s) (one IEEE single rounding).
+ *  c_norm volume fraction per fixed-point count, 1 / (2^48 rho0 dV) with
+ *         rho0 = N / (Lx Ly Lz) and dV = Lx Ly Lz / (Mx My Mz); i.e.
+ *         Mx My Mz / (2^48 N). 0 when N = 0.
+ * hpf_mesh_make() fills s and c_norm from L, M and N. */
+typedef struct hpf_mesh {
+    float L[3];
+    int32_t M[3];
+    float s[3];
+    int32_t reserved;
+    double c_norm;
+} hpf_mesh_t;
+
+/* Field parameters of eq. (4) (MD-SCF section):
+ *   V_K = kT sum_K' chi[K][K'] phi_K' + inv_kappa (sum_K phi_K - 1).
+ * chi is row-major K x K (entry [a*K + b]); it should be symmetric. */
+typedef struct hpf_field {
+    int32_t K;
+    int32_t reserved;
+    double kT;
+    double inv_kappa;
+    double chi[HPF_MAX_TYPES * HPF_MAX_TYPES];
+} hpf_field_t;
+
+/* Library ABI version (HPF_ABI_VERSION). */
+int32_t hpf_abi_version(void);
+
+/* Human-readable text for a status code. */
+const char* hpf_status_string(hpf_status_t status);
+
+/* Host helper: fill `out` from box edges L[3] (host), mesh sizes M[3] (host)
+ * and the bead count N >= 0. Returns HPF_EINVAL for L <= 0 or M < 3. */
+hpf_status_t hpf_mesh_make(const float* L, const int32_t* M, int64_t n_beads,
+                           hpf_mesh_t* out);
+
+/* ---------------------------------------------------------------------------
+ * hpf_density_scatter -- density assignment (MD-SCF section: every bead
+ * spreads its density fractions over the eight vertices of its cell;
+ * Algorithm 1 Kernels 1-2 compute the same sums by gathering).
+ *
+ * For bead i with u_d = fl32(x_d * s_d), c_d = floor(u_d) mod M_d,
+ * f_d = fl32(u_d - floor(u_d)), q_d = floor(f_d * 2^16), the 1-D weights are
+ * (2^16 - q_d, q_d) and vertex c + a (a in {0,1}^3, periodic) receives the
+ * product W_a of its three 1-D weights; the eight W_a sum to 2^48.
+ *   counts[T_i][c + a] += W_a        (uint64, exact, order independent)
+ *
+ * R       float[N][4] device; T uint8[N] device; N >= 0.
+ * mesh    host; K in [1, HPF_MAX_TYPES].
+ * counts  uint64[K][Mz][My][Mx] device, ACCUMULATED into (zero it first, or
+ *         let hpf_field_potential clear it after reading).
+ * Beads with a non-finite position, |u_d| >= 2^24 or T_i >= K are skipped
+ * and set HPF_FLAG_BAD_BEAD. Fastest when beads are stored in cell order
+ * (hpf_sort_by_cell); correct for any order.
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_density_scatter(const float* R, const uint8_t* T, int64_t N,
+                                 const hpf_mesh_t* mesh, int32_t K, uint64_t* counts,
+                                 void* stream);
+
+/* ---------------------------------------------------------------------------
+ * hpf_field_potential -- external potential of eq. (4) at every mesh point.
+ *
+ *   phi_K = counts_K * c_norm                  (FP64)
+ *   V_K   = kT sum_K' chi[K][K'] phi_K' + inv_kappa (sum_K phi_K - 1)
+ * computed in FP64 and stored as FP32; counts are then set to 0 (read and
+ * clear), so the next scatter can accumulate into them.
+ *
+ * counts  uint64[K][M^3] device, read then zeroed.
+ * V       float[K][M^3] device, overwritten.
+ * w_part  nullable, double[HPF_NPART] device: receives partial sums of the
+ *         field energy W = rho0 dV sum_v [ kT/2 sum_KK' chi phi_K phi_K'
+ *         + inv_kappa/2 (sum_K phi_K - 1)^2 ] (the functional whose
+ *         derivative by the bead count at v is V_K(v)); reduce with
+ *         hpf_reduce_partials(w_part, 1, ...).
+ * A count >= 2^62 sets HPF_FLAG_OVERFLOW.
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_field_potential(uint64_t* counts, const hpf_mesh_t* mesh,
+                                 const hpf_field_t* field, float* V, double* w_part,
+                                 void* stream);
+
+/* ---------------------------------------------------------------------------
+ * hpf_field_gradient -- mesh gradient of the potential (Algorithm 1
+ * Kernel 3, read as a centred periodic difference at the mesh point):
+ *   G_K(v) = ( (V_K(v+e_x) - V_K(v-e_x)) / (2 h_x), ... y, ... z, V_K(v) )
+ * with 1/(2 h_d) = s_d / 2.
+ *
+ * V  float[K][M^3] device.  G float[K][M^3][4] device, overwritten; the 4th
+ * component carries V_K(v) itself.
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_field_gradient(const float* V, const hpf_mesh_t* mesh, int32_t K,
+                                float* G, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * hpf_force_gather -- field force on every bead, eq. (6) (Algorithm 1
+ * Kernel 4, read as interpolation with the density-assignment weights):
+ *   F_i = - sum_a (W_a(i) / 2^48) G_{T_i}(c_i + a)
+ *
+ * R float[N][4], T uint8[N], G float[K][M^3][4] device.
+ * F float[N][4] device, OVERWRITTEN (w = 0). Skipped beads (see
+ * hpf_density_scatter) get F = 0.
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_force_gather(const float* R, const uint8_t* T, int64_t N,
+                              const hpf_mesh_t* mesh, int32_t K, const float* G, float* F,
+                              void* stream);
+
+/* ---------------------------------------------------------------------------
+ * bond_forces -- harmonic bonds U = k (r - r0)^2 (eq. (7), no factor 1/2),
+ * one thread per bead summing over its own bonds, so each bond is evaluated
+ * from both ends (Bonded forces section). With d = minimum image of
+ * x_j - x_i and r = |d|:  F_i += 2 k (r - r0) d / r  (r0 = 0: F_i += 2 k d;
+ * r = 0 with r0 != 0: no force).
+ *
+ * bonds  int32[D][N] device, the table form of the paper: bonds[b*N + i] is
+ *        the storage index of the b-th partner of bead i, -1 for none;
+ *        D in [0, HPF_MAX_BONDS]. Entries outside [-1, N) are skipped and set
+ *        HPF_FLAG_BAD_BOND.
+ * box    host float[3], the periodic box edges.
+ * F      float[N][4] device, ACCUMULATED into (x, y, z).
+ * e_part nullable double[HPF_NPART] device: partial sums of the bond energy
+ *        sum over bonds of k (r - r0)^2.
+ * ------------------------------------------------------------------------- */
+hpf_status_t bond_forces(const float* R, int64_t N, const int32_t* bonds, int32_t D,
+                         float k, float r0, const float* box, float* F, double* e_part,
+                         void* stream);
+
+/* ---------------------------------------------------------------------------
+ * verlet_step -- velocity Verlet (Integration methods section), split into
+ * its two half steps around the force evaluation:
+ *   half = 1:  v += dt/2 F/m;  x += dt v;  x wrapped into [0, L)
+ *   half = 2:  v += dt/2 F/m
+ * inv_mass   nullable float[N] device (NULL = unit masses).
+ * box        host float[3].  dt > 0.
+ * kin_part   nullable double[4][HPF_NPART] device (half = 2 only): partial
+ *            sums of {KE = sum m v^2 / 2, Px, Py, Pz} after the update.
+ * A non-finite updated coordinate sets HPF_FLAG_NONFINITE.
+ * ------------------------------------------------------------------------- */
+hpf_status_t verlet_step(float* R, float* Vel, const float* F, const float* inv_mass,
+                         int64_t N, float dt, const float* box, int32_t half,
+                         double* kin_part, void* stream);
+
+/* Deterministic FP64 reduction of partial-sum buffers: out[c] = sum of
+ * part[c*HPF_NPART .. (c+1)*HPF_NPART) in a fixed tree order, c < ncomp.
+ * part and out are device pointers; ncomp in [1, 8]. */
+hpf_status_t hpf_reduce_partials(const double* part, int32_t ncomp, double* out,
+                                 void* stream);
+
+/* ---------------------------------------------------------------------------
+ * hpf_sort_by_cell -- put beads in canonical cell order (the paper reorders
+ * particle data for cache hits and bins beads into a cell list; Algorithm 1
+ * Kernel 1). The key of a bead is its cell in brick-major order: bricks of
+ * B^3 cells, bricks numbered x fastest, cells x fastest inside a brick,
+ *   key = ((bz*NBy + by)*NBx + bx) * B^3 + (lz*B + ly)*B + lx,  NB_d = ceil(M_d/B).
+ * Beads that cannot be binned get key NK = NBx*NBy*NBz*B^3 and go last.
+ * Output order: ascending (key, tag). Positions, velocities, types and tags
+ * are permuted into the *_out arrays and the bond table is permuted and its
+ * entries renumbered to the new storage indices.
+ *
+ * B            brick edge in cells, 1..16 (0 selects 8).
+ * *_in / *_out device arrays of N rows (Vel/tag/bonds may be NULL together
+ *              with their outputs; D may be 0); in and out must not alias.
+ * cell_start   nullable uint32[NK + 2] device: cell_start[k] = index of the
+ *              first bead with key >= k (so cell_start[NK] = number of
+ *              binned beads, cell_start[NK+1] = N).
+ * work         device workspace of at least hpf_sort_workspace_bytes()
+ *              bytes (HPF_ESPACE otherwise).
+ * ------------------------------------------------------------------------- */
+size_t hpf_sort_workspace_bytes(int64_t N, const hpf_mesh_t* mesh, int32_t B);
+hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N,
+                              const float* R_in, const float* Vel_in, const uint8_t* T_in,
+                              const int32_t* tag_in, const int32_t* bonds_in, int32_t D,
+                              float* R_out, float* Vel_out, uint8_t* T_out, int32_t* tag_out,
+                              int32_t* bonds_out, uint32_t* cell_start, void* work,
+                              size_t work_bytes, void* stream);
+
+/* Read (and optionally clear) the sticky device status bits of the current
+ * device. Synchronises `stream`. flags is a HOST pointer. */
+hpf_status_t hpf_get_device_status(uint32_t* flags, int32_t clear, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPF_H */

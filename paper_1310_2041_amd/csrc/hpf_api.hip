@@ -1,0 +1,244 @@
+// Host side of the C ABI: argument checks, kernel-argument packing, dispatch.
+// Every entry point validates on the host and enqueues on the caller's
+// stream; nothing here allocates device memory.
+//
+// This file is the library's single translation unit: it includes the kernel
+// sources below, so the device status word needs no relocatable device code.
+#include <algorithm>
+#include <cmath>
+
+#include "hpf_common.hpp"
+
+namespace hpf {
+
+__device__ uint32_t g_status = 0;
+
+static bool mesh_ok(const hpf_mesh_t* m)
+{
+    if (!m)
+        return false;
+    for (int d = 0; d < 3; ++d) {
+        if (!(m->L[d] > 0.0f) || !std::isfinite(m->L[d]))
+            return false;
+        if (m->M[d] < 3 || m->M[d] > (1 << 20))
+            return false;
+        if (!(m->s[d] > 0.0f) || !std::isfinite(m->s[d]))
+            return false;
+    }
+    if ((int64_t)m->M[0] * m->M[1] * m->M[2] > (1LL << 34))
+        return false;
+    return std::isfinite(m->c_norm) && m->c_norm >= 0.0;
+}
+
+static MeshK mesh_k(const hpf_mesh_t* m)
+{
+    MeshK k;
+    for (int d = 0; d < 3; ++d) {
+        k.L[d] = m->L[d];
+        k.halfL[d] = 0.5f * m->L[d];
+        k.s[d] = m->s[d];
+        k.M[d] = m->M[d];
+    }
+    k.nm = (int64_t)m->M[0] * m->M[1] * m->M[2];
+    k.c_norm = m->c_norm;
+    return k;
+}
+
+static bool box_ok(const float* box)
+{
+    if (!box)
+        return false;
+    for (int d = 0; d < 3; ++d)
+        if (!(box[d] > 0.0f) || !std::isfinite(box[d]))
+            return false;
+    return true;
+}
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace hpf
+
+#include "hpf_scatter.hip"
+#include "hpf_field.hip"
+#include "hpf_particles.hip"
+#include "hpf_sort.hip"
+
+using namespace hpf;
+
+extern "C" {
+
+int32_t hpf_abi_version(void) { return HPF_ABI_VERSION; }
+
+const char* hpf_status_string(hpf_status_t status)
+{
+    switch (status) {
+    case HPF_OK: return "ok";
+    case HPF_EINVAL: return "invalid argument";
+    case HPF_EHIP: return "HIP runtime error";
+    case HPF_ESPACE: return "workspace too small";
+    default: return "unknown status";
+    }
+}
+
+hpf_status_t hpf_mesh_make(const float* L, const int32_t* M, int64_t n_beads, hpf_mesh_t* out)
+{
+    if (!L || !M || !out || n_beads < 0)
+        return HPF_EINVAL;
+    hpf_mesh_t m{};
+    int64_t nm = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (!(L[d] > 0.0f) || !std::isfinite(L[d]) || M[d] < 3 || M[d] > (1 << 20))
+            return HPF_EINVAL;
+        m.L[d] = L[d];
+        m.M[d] = M[d];
+        m.s[d] = (float)((double)M[d] / (double)L[d]);
+        nm *= M[d];
+    }
+    m.c_norm = n_beads > 0 ? (double)nm / (281474976710656.0 * (double)n_beads) : 0.0;
+    *out = m;
+    return HPF_OK;
+}
+
+hpf_status_t hpf_density_scatter(const float* R, const uint8_t* T, int64_t N, const hpf_mesh_t* mesh,
+                                 int32_t K, uint64_t* counts, void* stream)
+{
+    if (N < 0 || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES || !counts)
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !T))
+        return HPF_EINVAL;
+    return launch_density_scatter(R, T, N, mesh_k(mesh), K, counts, as_stream(stream));
+}
+
+hpf_status_t hpf_field_potential(uint64_t* counts, const hpf_mesh_t* mesh, const hpf_field_t* field,
+                                 float* V, double* w_part, void* stream)
+{
+    if (!counts || !V || !mesh_ok(mesh) || !field || field->K < 1 || field->K > HPF_MAX_TYPES)
+        return HPF_EINVAL;
+    const int K = field->K;
+    PotK p{};
+    for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b) {
+            const double c = field->chi[a * K + b];
+            if (!std::isfinite(c))
+                return HPF_EINVAL;
+            p.A[a * K + b] = field->kT * c;
+        }
+    if (!std::isfinite(field->kT) || !std::isfinite(field->inv_kappa))
+        return HPF_EINVAL;
+    p.inv_kappa = field->inv_kappa;
+    p.rho0_dV = mesh->c_norm > 0.0 ? 1.0 / (mesh->c_norm * 281474976710656.0) : 0.0;
+    return launch_field_potential(counts, mesh_k(mesh), K, p, V, w_part, as_stream(stream));
+}
+
+hpf_status_t hpf_field_gradient(const float* V, const hpf_mesh_t* mesh, int32_t K, float* G, void* stream)
+{
+    if (!V || !G || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES)
+        return HPF_EINVAL;
+    if ((mesh->M[0] + 63) / 64 > 65535 || mesh->M[2] > 65535)
+        return HPF_EINVAL;
+    return launch_field_gradient(V, mesh_k(mesh), K, G, as_stream(stream));
+}
+
+hpf_status_t hpf_force_gather(const float* R, const uint8_t* T, int64_t N, const hpf_mesh_t* mesh,
+                              int32_t K, const float* G, float* F, void* stream)
+{
+    if (N < 0 || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES || !G)
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !T || !F))
+        return HPF_EINVAL;
+    return launch_force_gather(R, T, N, mesh_k(mesh), K, G, F, as_stream(stream));
+}
+
+hpf_status_t bond_forces(const float* R, int64_t N, const int32_t* bonds, int32_t D, float k, float r0,
+                         const float* box, float* F, double* e_part, void* stream)
+{
+    if (N < 0 || N > 0x7fffffffLL || D < 0 || D > HPF_MAX_BONDS || !box_ok(box) ||
+        !std::isfinite(k) || !std::isfinite(r0))
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !F || (D > 0 && !bonds)))
+        return HPF_EINVAL;
+    BoxK b;
+    for (int d = 0; d < 3; ++d) {
+        b.L[d] = box[d];
+        b.halfL[d] = 0.5f * box[d];
+    }
+    return launch_bond_forces(R, N, bonds, D, k, r0, b, F, e_part, as_stream(stream));
+}
+
+hpf_status_t verlet_step(float* R, float* Vel, const float* F, const float* inv_mass, int64_t N, float dt,
+                         const float* box, int32_t half, double* kin_part, void* stream)
+{
+    if (N < 0 || !box_ok(box) || !(dt > 0.0f) || !std::isfinite(dt) || (half != 1 && half != 2))
+        return HPF_EINVAL;
+    if (N > 0 && (!Vel || !F || (half == 1 && !R)))
+        return HPF_EINVAL;
+    BoxK b;
+    for (int d = 0; d < 3; ++d) {
+        b.L[d] = box[d];
+        b.halfL[d] = 0.5f * box[d];
+    }
+    return launch_verlet(R, Vel, F, inv_mass, N, dt, b, half, kin_part, as_stream(stream));
+}
+
+hpf_status_t hpf_reduce_partials(const double* part, int32_t ncomp, double* out, void* stream)
+{
+    if (!part || !out || ncomp < 1 || ncomp > 8)
+        return HPF_EINVAL;
+    return launch_reduce_partials(part, ncomp, out, as_stream(stream));
+}
+
+size_t hpf_sort_workspace_bytes(int64_t N, const hpf_mesh_t* mesh, int32_t B)
+{
+    if (!mesh_ok(mesh))
+        return 0;
+    size_t bytes = 0, off[6];
+    if (!sort_layout(N, mesh->M, B, nullptr, &bytes, off))
+        return 0;
+    return bytes;
+}
+
+hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N, const float* R_in,
+                              const float* Vel_in, const uint8_t* T_in, const int32_t* tag_in,
+                              const int32_t* bonds_in, int32_t D, float* R_out, float* Vel_out,
+                              uint8_t* T_out, int32_t* tag_out, int32_t* bonds_out, uint32_t* cell_start,
+                              void* work, size_t work_bytes, void* stream)
+{
+    if (!mesh_ok(mesh) || N < 0 || D < 0 || D > HPF_MAX_BONDS)
+        return HPF_EINVAL;
+    if (N > 0 && (!R_in || !T_in || !R_out || !T_out))
+        return HPF_EINVAL;
+    if (!Vel_in != !Vel_out || !tag_in != !tag_out || (D > 0 && (!bonds_in || !bonds_out)))
+        return HPF_EINVAL;
+    if (N > 0 && (R_in == R_out || (Vel_in && Vel_in == Vel_out) || T_in == T_out ||
+                  (tag_in && tag_in == tag_out) || (D > 0 && bonds_in == bonds_out)))
+        return HPF_EINVAL;
+    SortK sk;
+    size_t bytes = 0, off[6];
+    if (!sort_layout(N, mesh->M, B, &sk, &bytes, off))
+        return HPF_EINVAL;
+    if (!work || work_bytes < bytes)
+        return HPF_ESPACE;
+    sk.m = mesh_k(mesh);
+    return launch_sort(sk, N, R_in, Vel_in, T_in, tag_in, bonds_in, D, R_out, Vel_out, T_out, tag_out,
+                       bonds_out, cell_start, static_cast<char*>(work), off, as_stream(stream));
+}
+
+hpf_status_t hpf_get_device_status(uint32_t* flags, int32_t clear, void* stream)
+{
+    if (!flags)
+        return HPF_EINVAL;
+    if (hipStreamSynchronize(as_stream(stream)) != hipSuccess)
+        return HPF_EHIP;
+    uint32_t v = 0;
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_status), sizeof(v), 0, hipMemcpyDeviceToHost) != hipSuccess)
+        return HPF_EHIP;
+    if (clear) {
+        const uint32_t z = 0;
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_status), &z, sizeof(z), 0, hipMemcpyHostToDevice) != hipSuccess)
+            return HPF_EHIP;
+    }
+    *flags = v;
+    return HPF_OK;
+}
+
+}  // extern "C"

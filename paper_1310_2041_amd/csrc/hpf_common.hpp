@@ -1,0 +1,155 @@
+// Internal device helpers of libhpf (gfx950, wave64). Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hpf.h"
+
+namespace hpf {
+
+constexpr int kWave = 64;
+constexpr uint32_t kOne = 1u << HPF_FIX_BITS;          // 2^S
+constexpr float kInvOne = 1.0f / 65536.0f;              // 2^-S, exact
+
+// Sticky device status word (one per device); read by hpf_get_device_status.
+extern __device__ uint32_t g_status;
+
+__device__ __forceinline__ void raise_flag(uint32_t bit) { atomicOr(&g_status, bit); }
+
+// Mesh description as passed to kernels (by value).
+struct MeshK {
+    float L[3];
+    float halfL[3];
+    float s[3];
+    int32_t M[3];
+    int64_t nm;         // Mx * My * Mz
+    double c_norm;
+};
+
+// Cell index and upper 1-D fixed-point weight of one coordinate.
+// u = fl32(x * s) (single rounding, no contraction), c = floor(u) mod M,
+// f = fl32(u - floor(u)), q = floor(f * 2^S). The lower weight is 2^S - q.
+// Returns false for a coordinate that cannot be binned (non-finite or
+// |u| >= 2^24).
+__device__ __forceinline__ bool cell_coord(float x, float s, int32_t M, int32_t& c, uint32_t& q)
+{
+    const float u = __fmul_rn(x, s);
+    if (!(fabsf(u) < 16777216.0f))
+        return false;
+    const float fl = floorf(u);
+    const float f = __fsub_rn(u, fl);
+    q = (uint32_t)__fmul_rn(f, 65536.0f);
+    int32_t ci = (int32_t)fl;
+    if ((uint32_t)ci >= (uint32_t)M) {
+        ci %= M;
+        if (ci < 0)
+            ci += M;
+    }
+    c = ci;
+    return true;
+}
+
+struct BeadCell {
+    int32_t c[3];
+    uint32_t q[3];
+};
+
+__device__ __forceinline__ bool bead_cell(const float4& r, const MeshK& m, BeadCell& b)
+{
+    bool ok = cell_coord(r.x, m.s[0], m.M[0], b.c[0], b.q[0]);
+    ok = cell_coord(r.y, m.s[1], m.M[1], b.c[1], b.q[1]) && ok;
+    ok = cell_coord(r.z, m.s[2], m.M[2], b.c[2], b.q[2]) && ok;
+    return ok;
+}
+
+__device__ __forceinline__ int32_t next_wrap(int32_t c, int32_t M) { return c + 1 == M ? 0 : c + 1; }
+__device__ __forceinline__ int32_t prev_wrap(int32_t c, int32_t M) { return c == 0 ? M - 1 : c - 1; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (WG b on XCD b % 8).
+// Map them so that each XCD works on one contiguous range of logical blocks:
+// neighbouring tiles then share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks)
+{
+    const int64_t per = nblocks >> 3, rem = nblocks & 7;
+    const int64_t xcd = b & 7, idx = b >> 3;
+    const int64_t base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    return base + idx;
+}
+
+// Fixed-order wave64 sum (butterfly), identical result in every lane.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Fixed-order block sum of one double per thread. `scratch` holds one double
+// per wave. Result valid in thread 0. blockDim.x must be a multiple of 64.
+__device__ __forceinline__ double block_sum(double v, double* scratch)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0)
+        scratch[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x / kWave;
+        for (int w = 0; w < nw; ++w)
+            t += scratch[w];
+    }
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v = max(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Minimum-image separation x_j - x_i along one axis of a periodic box for
+// coordinates inside [0, L). When the raw difference exceeds half a box the
+// wrapped coordinate is formed first (x_j - L or x_i - L is exact by Sterbenz's
+// lemma), so the result carries a rounding error of the short bond vector
+// rather than of the box length. Far-away inputs fall back to rint.
+__device__ __forceinline__ float min_image(float xj, float xi, float L, float halfL)
+{
+    float d = xj - xi;
+    if (fabsf(d) > halfL) {
+        if (fabsf(d) < 1.5f * L)
+            d = d > 0.0f ? (xj - L) - xi : xj - (xi - L);
+        else
+            d = d - L * rintf(d / L);
+    }
+    return d;
+}
+
+// Wrap a coordinate into [0, L): fmod is exact; a result that rounds up to L
+// after adding L becomes 0.
+__device__ __forceinline__ float wrap_coord(float x, float L)
+{
+    if (x >= 0.0f && x < L)
+        return x;
+    float r = fmodf(x, L);
+    if (r < 0.0f)
+        r += L;
+    if (r >= L)
+        r = 0.0f;
+    return r;
+}
+
+}  // namespace hpf

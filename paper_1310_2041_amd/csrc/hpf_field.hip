@@ -1,0 +1,129 @@
+// Mesh-side kernels: the external potential of eq. (4) from the fixed-point
+// counts, and its centred periodic gradient (Algorithm 1 Kernel 3, read as a
+// centred difference at the mesh point). Both are streaming, HBM-bound
+// passes over the mesh.
+#include "hpf_common.hpp"
+
+namespace hpf {
+
+struct PotK {
+    double A[HPF_MAX_TYPES * HPF_MAX_TYPES];   // kT * chi, row-major K x K
+    double inv_kappa;
+    double rho0_dV;                            // N / (Mx My Mz), scales the energy
+};
+
+constexpr int kPotThreads = 256;
+
+// One thread per mesh point (grid-stride): phi_K = n_K c_norm in FP64,
+// V_K = sum_K' A_KK' phi_K' + inv_kappa (sum phi - 1) stored as FP32, counts
+// cleared for the next scatter. Optional FP64 field-energy partials.
+template <int K>
+__global__ __launch_bounds__(kPotThreads) void k_field_potential(unsigned long long* __restrict__ counts,
+                                                                 MeshK m, PotK p,
+                                                                 float* __restrict__ V,
+                                                                 double* __restrict__ w_part)
+{
+    __shared__ double scratch[kPotThreads / kWave];
+    const int64_t nm = m.nm;
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    double wsum = 0.0;
+    bool over = false;
+    for (int64_t v = b * kPotThreads + threadIdx.x; v < nm; v += (int64_t)gridDim.x * kPotThreads) {
+        double phi[K];
+        double tot = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const unsigned long long n = counts[k * nm + v];
+            over |= n >= (1ull << 62);
+            phi[k] = (double)n * m.c_norm;
+            tot += phi[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            counts[k * nm + v] = 0ull;
+        const double delta = tot - 1.0;
+        double inter = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double mix = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk)
+                mix += p.A[k * K + kk] * phi[kk];
+            V[k * nm + v] = (float)(mix + p.inv_kappa * delta);
+            inter += phi[k] * mix;
+        }
+        wsum += 0.5 * inter + 0.5 * p.inv_kappa * delta * delta;
+    }
+    if (over)
+        raise_flag(HPF_FLAG_OVERFLOW);
+    if (w_part) {
+        const double s = block_sum(wsum, scratch);
+        if (threadIdx.x == 0)
+            w_part[b] = s * p.rho0_dV;
+    }
+}
+
+hpf_status_t launch_field_potential(uint64_t* counts, const MeshK& m, int K, const PotK& p,
+                                    float* V, double* w_part, hipStream_t s)
+{
+    int64_t nb = (m.nm + kPotThreads - 1) / kPotThreads;
+    if (w_part || nb > 8192)
+        nb = w_part ? HPF_NPART : 8192;
+    auto* c = reinterpret_cast<unsigned long long*>(counts);
+    const dim3 g((unsigned)nb), bl(kPotThreads);
+    switch (K) {
+    case 1: hipLaunchKernelGGL(k_field_potential<1>, g, bl, 0, s, c, m, p, V, w_part); break;
+    case 2: hipLaunchKernelGGL(k_field_potential<2>, g, bl, 0, s, c, m, p, V, w_part); break;
+    case 3: hipLaunchKernelGGL(k_field_potential<3>, g, bl, 0, s, c, m, p, V, w_part); break;
+    case 4: hipLaunchKernelGGL(k_field_potential<4>, g, bl, 0, s, c, m, p, V, w_part); break;
+    case 5: hipLaunchKernelGGL(k_field_potential<5>, g, bl, 0, s, c, m, p, V, w_part); break;
+    case 6: hipLaunchKernelGGL(k_field_potential<6>, g, bl, 0, s, c, m, p, V, w_part); break;
+    case 7: hipLaunchKernelGGL(k_field_potential<7>, g, bl, 0, s, c, m, p, V, w_part); break;
+    case 8: hipLaunchKernelGGL(k_field_potential<8>, g, bl, 0, s, c, m, p, V, w_part); break;
+    default: return HPF_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+constexpr int kGradX = 64, kGradY = 4;
+
+// One thread per mesh point: a 64 x 4 block covers a patch of an xy plane,
+// so the +-x neighbours are in the same or adjacent cache lines and the +-y
+// and +-z rows are re-read from L2 by neighbouring blocks.
+__global__ __launch_bounds__(kGradX * kGradY) void k_field_gradient(const float* __restrict__ V,
+                                                                    MeshK m, int K,
+                                                                    float4* __restrict__ G)
+{
+    const int x = blockIdx.x * kGradX + threadIdx.x;
+    const int y = blockIdx.y * kGradY + threadIdx.y;
+    const int z = blockIdx.z;
+    const int Mx = m.M[0], My = m.M[1], Mz = m.M[2];
+    if (x >= Mx || y >= My)
+        return;
+    const int xp = next_wrap(x, Mx), xm = prev_wrap(x, Mx);
+    const int64_t row = ((int64_t)z * My + y) * Mx;
+    const int64_t rowyp = ((int64_t)z * My + next_wrap(y, My)) * Mx;
+    const int64_t rowym = ((int64_t)z * My + prev_wrap(y, My)) * Mx;
+    const int64_t rowzp = ((int64_t)next_wrap(z, Mz) * My + y) * Mx;
+    const int64_t rowzm = ((int64_t)prev_wrap(z, Mz) * My + y) * Mx;
+    const float hx = 0.5f * m.s[0], hy = 0.5f * m.s[1], hz = 0.5f * m.s[2];
+    for (int k = 0; k < K; ++k) {
+        const float* Vk = V + k * m.nm;
+        float4 g;
+        g.x = (Vk[row + xp] - Vk[row + xm]) * hx;
+        g.y = (Vk[rowyp + x] - Vk[rowym + x]) * hy;
+        g.z = (Vk[rowzp + x] - Vk[rowzm + x]) * hz;
+        g.w = Vk[row + x];
+        G[k * m.nm + row + x] = g;
+    }
+}
+
+hpf_status_t launch_field_gradient(const float* V, const MeshK& m, int K, float* G, hipStream_t s)
+{
+    const dim3 g((m.M[0] + kGradX - 1) / kGradX, (m.M[1] + kGradY - 1) / kGradY, m.M[2]);
+    hipLaunchKernelGGL(k_field_gradient, g, dim3(kGradX, kGradY), 0, s, V, m, K,
+                       reinterpret_cast<float4*>(G));
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+}  // namespace hpf

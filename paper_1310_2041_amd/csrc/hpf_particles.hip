@@ -1,0 +1,313 @@
+// Per-bead kernels: force interpolation from the gradient mesh (eq. 6,
+// Algorithm 1 Kernel 4), harmonic bonds (eq. 7) and the two half steps of
+// velocity Verlet. One thread per bead; each workgroup walks a contiguous
+// range of beads, and ranges are laid out so that consecutive ranges run on
+// the same XCD (cell-sorted beads then share that XCD's L2 for mesh reads).
+#include "hpf_common.hpp"
+
+namespace hpf {
+
+constexpr int kPThreads = 256;
+
+struct Range {
+    int64_t begin, end;
+    int64_t block;   // logical block id (partial-sum slot)
+};
+
+// Contiguous bead range of this workgroup when gridDim.x blocks split N beads.
+__device__ __forceinline__ Range block_range(int64_t N)
+{
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t per = ((N + gridDim.x - 1) / gridDim.x + kPThreads - 1) / kPThreads * kPThreads;
+    Range r;
+    r.block = b;
+    r.begin = min(N, b * per);
+    r.end = min(N, r.begin + per);
+    return r;
+}
+
+// ---------------------------------------------------------------- gather ---
+
+__global__ __launch_bounds__(kPThreads) void k_force_gather(const float4* __restrict__ R,
+                                                            const uint8_t* __restrict__ T,
+                                                            int64_t N, MeshK m, int K,
+                                                            const float4* __restrict__ G,
+                                                            float4* __restrict__ F)
+{
+    const Range rg = block_range(N);
+    bool bad = false;
+    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+        const float4 r = R[i];
+        const int t = T[i];
+        BeadCell b;
+        float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (bead_cell(r, m, b) && t < K) {
+            const float4* Gk = G + t * m.nm;
+            const int32_t Mx = m.M[0], My = m.M[1], Mz = m.M[2];
+            const int32_t x0 = b.c[0], x1 = next_wrap(x0, Mx);
+            const int32_t y0 = b.c[1], y1 = next_wrap(y0, My);
+            const int32_t z0 = b.c[2], z1 = next_wrap(z0, Mz);
+            const int64_t r00 = ((int64_t)z0 * My + y0) * Mx, r10 = ((int64_t)z0 * My + y1) * Mx;
+            const int64_t r01 = ((int64_t)z1 * My + y0) * Mx, r11 = ((int64_t)z1 * My + y1) * Mx;
+            const float4 g000 = Gk[r00 + x0], g100 = Gk[r00 + x1];
+            const float4 g010 = Gk[r10 + x0], g110 = Gk[r10 + x1];
+            const float4 g001 = Gk[r01 + x0], g101 = Gk[r01 + x1];
+            const float4 g011 = Gk[r11 + x0], g111 = Gk[r11 + x1];
+            // 1-D weights are exact FP32 dyadics (w / 2^16).
+            const float ax1 = (float)b.q[0] * kInvOne, ax0 = (float)(kOne - b.q[0]) * kInvOne;
+            const float ay1 = (float)b.q[1] * kInvOne, ay0 = (float)(kOne - b.q[1]) * kInvOne;
+            const float az1 = (float)b.q[2] * kInvOne, az0 = (float)(kOne - b.q[2]) * kInvOne;
+            // separable trilinear interpolation: x, then y, then z
+            float3 e00, e10, e01, e11, f0, f1;
+            e00.x = ax0 * g000.x + ax1 * g100.x;
+            e00.y = ax0 * g000.y + ax1 * g100.y;
+            e00.z = ax0 * g000.z + ax1 * g100.z;
+            e10.x = ax0 * g010.x + ax1 * g110.x;
+            e10.y = ax0 * g010.y + ax1 * g110.y;
+            e10.z = ax0 * g010.z + ax1 * g110.z;
+            e01.x = ax0 * g001.x + ax1 * g101.x;
+            e01.y = ax0 * g001.y + ax1 * g101.y;
+            e01.z = ax0 * g001.z + ax1 * g101.z;
+            e11.x = ax0 * g011.x + ax1 * g111.x;
+            e11.y = ax0 * g011.y + ax1 * g111.y;
+            e11.z = ax0 * g011.z + ax1 * g111.z;
+            f0.x = ay0 * e00.x + ay1 * e10.x;
+            f0.y = ay0 * e00.y + ay1 * e10.y;
+            f0.z = ay0 * e00.z + ay1 * e10.z;
+            f1.x = ay0 * e01.x + ay1 * e11.x;
+            f1.y = ay0 * e01.y + ay1 * e11.y;
+            f1.z = ay0 * e01.z + ay1 * e11.z;
+            out.x = -(az0 * f0.x + az1 * f1.x);
+            out.y = -(az0 * f0.y + az1 * f1.y);
+            out.z = -(az0 * f0.z + az1 * f1.z);
+        } else {
+            bad = true;
+        }
+        F[i] = out;
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+}
+
+static int64_t bead_blocks(int64_t N, int64_t cap)
+{
+    int64_t nb = (N + kPThreads - 1) / kPThreads;
+    if (nb > cap)
+        nb = cap;
+    return nb < 1 ? 1 : nb;
+}
+
+hpf_status_t launch_force_gather(const float* R, const uint8_t* T, int64_t N, const MeshK& m,
+                                 int K, const float* G, float* F, hipStream_t s)
+{
+    if (N == 0)
+        return HPF_OK;
+    hipLaunchKernelGGL(k_force_gather, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads),
+                       0, s, reinterpret_cast<const float4*>(R), T, N, m, K,
+                       reinterpret_cast<const float4*>(G), reinterpret_cast<float4*>(F));
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+// ----------------------------------------------------------------- bonds ---
+
+struct BoxK {
+    float L[3];
+    float halfL[3];
+};
+
+// F_i += sum_j 2k (r - r0) d / r over the bead's own table row; E partials
+// accumulate k (r - r0)^2 / 2 per bond end (each bond is seen from both ends).
+template <bool kR0Zero>
+__global__ __launch_bounds__(kPThreads) void k_bond_forces(const float4* __restrict__ R, int64_t N,
+                                                           const int32_t* __restrict__ bonds, int D,
+                                                           float k, float r0, BoxK box,
+                                                           float4* __restrict__ F,
+                                                           double* __restrict__ e_part)
+{
+    __shared__ double scratch[kPThreads / kWave];
+    const Range rg = block_range(N);
+    const float two_k = 2.0f * k;
+    double e = 0.0;
+    bool bad = false;
+    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+        const float4 xi = R[i];
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        float ei = 0.0f;
+        for (int b = 0; b < D; ++b) {
+            const int32_t j = bonds[(int64_t)b * N + i];
+            if (j < 0)
+                continue;
+            if (j >= N) {
+                bad = true;
+                continue;
+            }
+            const float4 xj = R[j];
+            const float dx = min_image(xj.x, xi.x, box.L[0], box.halfL[0]);
+            const float dy = min_image(xj.y, xi.y, box.L[1], box.halfL[1]);
+            const float dz = min_image(xj.z, xi.z, box.L[2], box.halfL[2]);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            float coef;
+            if (kR0Zero) {
+                coef = two_k;
+                ei += k * r2;
+            } else {
+                const float r = sqrtf(r2);
+                const float dr = r - r0;
+                coef = r > 0.0f ? two_k * dr / r : 0.0f;
+                ei += k * dr * dr;
+            }
+            fx += coef * dx;
+            fy += coef * dy;
+            fz += coef * dz;
+        }
+        float4 f = F[i];
+        f.x += fx;
+        f.y += fy;
+        f.z += fz;
+        F[i] = f;
+        e += 0.5 * (double)ei;
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BOND);
+    if (e_part) {
+        const double s = block_sum(e, scratch);
+        if (threadIdx.x == 0)
+            e_part[rg.block] = s;
+    }
+}
+
+hpf_status_t launch_bond_forces(const float* R, int64_t N, const int32_t* bonds, int D, float k,
+                                float r0, const BoxK& box, float* F, double* e_part, hipStream_t s)
+{
+    if (N == 0 && !e_part)
+        return HPF_OK;
+    const int64_t nb = e_part ? HPF_NPART : bead_blocks(N, 1 << 20);
+    const dim3 g((unsigned)nb), bl(kPThreads);
+    auto* Rp = reinterpret_cast<const float4*>(R);
+    auto* Fp = reinterpret_cast<float4*>(F);
+    if (r0 == 0.0f)
+        hipLaunchKernelGGL(k_bond_forces<true>, g, bl, 0, s, Rp, N, bonds, D, k, r0, box, Fp, e_part);
+    else
+        hipLaunchKernelGGL(k_bond_forces<false>, g, bl, 0, s, Rp, N, bonds, D, k, r0, box, Fp, e_part);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+// ---------------------------------------------------------------- verlet ---
+
+__global__ __launch_bounds__(kPThreads) void k_verlet_half1(float4* __restrict__ R,
+                                                            float4* __restrict__ Vel,
+                                                            const float4* __restrict__ F,
+                                                            const float* __restrict__ inv_mass,
+                                                            int64_t N, float dt, BoxK box)
+{
+    const Range rg = block_range(N);
+    const float hdt = 0.5f * dt;
+    bool bad = false;
+    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+        const float im = inv_mass ? inv_mass[i] : 1.0f;
+        const float4 f = F[i];
+        float4 v = Vel[i];
+        float4 r = R[i];
+        v.x += hdt * (f.x * im);
+        v.y += hdt * (f.y * im);
+        v.z += hdt * (f.z * im);
+        r.x = wrap_coord(r.x + dt * v.x, box.L[0]);
+        r.y = wrap_coord(r.y + dt * v.y, box.L[1]);
+        r.z = wrap_coord(r.z + dt * v.z, box.L[2]);
+        r.w = 0.0f;
+        v.w = 0.0f;
+        bad |= !(isfinite(r.x) && isfinite(r.y) && isfinite(r.z) && isfinite(v.x) &&
+                 isfinite(v.y) && isfinite(v.z));
+        Vel[i] = v;
+        R[i] = r;
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_NONFINITE);
+}
+
+__global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__ Vel,
+                                                            const float4* __restrict__ F,
+                                                            const float* __restrict__ inv_mass,
+                                                            int64_t N, float dt,
+                                                            double* __restrict__ kin_part)
+{
+    __shared__ double scratch[kPThreads / kWave];
+    const Range rg = block_range(N);
+    const float hdt = 0.5f * dt;
+    double ke = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+    bool bad = false;
+    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+        const float im = inv_mass ? inv_mass[i] : 1.0f;
+        const float4 f = F[i];
+        float4 v = Vel[i];
+        v.x += hdt * (f.x * im);
+        v.y += hdt * (f.y * im);
+        v.z += hdt * (f.z * im);
+        v.w = 0.0f;
+        bad |= !(isfinite(v.x) && isfinite(v.y) && isfinite(v.z));
+        Vel[i] = v;
+        const double mass = 1.0 / (double)im;
+        const double vx = v.x, vy = v.y, vz = v.z;
+        ke += 0.5 * mass * (vx * vx + vy * vy + vz * vz);
+        px += mass * vx;
+        py += mass * vy;
+        pz += mass * vz;
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_NONFINITE);
+    if (kin_part) {
+        const double a = block_sum(ke, scratch);
+        const double b = block_sum(px, scratch);
+        const double c = block_sum(py, scratch);
+        const double d = block_sum(pz, scratch);
+        if (threadIdx.x == 0) {
+            kin_part[0 * HPF_NPART + rg.block] = a;
+            kin_part[1 * HPF_NPART + rg.block] = b;
+            kin_part[2 * HPF_NPART + rg.block] = c;
+            kin_part[3 * HPF_NPART + rg.block] = d;
+        }
+    }
+}
+
+hpf_status_t launch_verlet(float* R, float* Vel, const float* F, const float* inv_mass, int64_t N,
+                           float dt, const BoxK& box, int half, double* kin_part, hipStream_t s)
+{
+    if (N == 0 && !(half == 2 && kin_part))
+        return HPF_OK;
+    auto* Rp = reinterpret_cast<float4*>(R);
+    auto* Vp = reinterpret_cast<float4*>(Vel);
+    auto* Fp = reinterpret_cast<const float4*>(F);
+    if (half == 1) {
+        hipLaunchKernelGGL(k_verlet_half1, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads),
+                           0, s, Rp, Vp, Fp, inv_mass, N, dt, box);
+    } else {
+        const int64_t nb = kin_part ? HPF_NPART : bead_blocks(N, 1 << 20);
+        hipLaunchKernelGGL(k_verlet_half2, dim3((unsigned)nb), dim3(kPThreads), 0, s, Vp, Fp,
+                           inv_mass, N, dt, kin_part);
+    }
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+// ------------------------------------------------------------- reduction ---
+
+// out[c] = sum of part[c][0..HPF_NPART) in a fixed order (one block per c).
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ part,
+                                                         double* __restrict__ out)
+{
+    __shared__ double scratch[256 / kWave];
+    const double* p = part + (int64_t)blockIdx.x * HPF_NPART;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < HPF_NPART; i += 256)
+        v += p[i];
+    const double s = block_sum(v, scratch);
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = s;
+}
+
+hpf_status_t launch_reduce_partials(const double* part, int ncomp, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_partials, dim3(ncomp), dim3(256), 0, s, part, out);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+}  // namespace hpf

@@ -1,0 +1,230 @@
+// Density assignment: fixed-point cloud-in-cell scatter of beads onto the
+// periodic vertex mesh (MD-SCF section; Algorithm 1 Kernels 1-2 compute the
+// same sums by gathering over a cell list).
+//
+// The paper avoids atomics because floating-point atomic adds serialise and
+// are order dependent. Here every weight is an integer (a product of three
+// 16-bit 1-D weights, 2^48 per bead), so atomic adds are exact and the mesh
+// is identical for any bead order. Each workgroup takes a contiguous chunk of
+// beads, finds the periodic bounding box of their cells and, when the box fits
+// in LDS, accumulates into an LDS copy of that box (ds_add_u64) and flushes
+// its non-zero entries with one global u64 atomic each. With beads in cell
+// order (hpf_sort_by_cell) a chunk covers a compact region, so global atomic
+// traffic drops from 8 per bead to roughly one per touched mesh point; an
+// unsorted chunk falls back to direct global atomics and stays exact.
+#include "hpf_common.hpp"
+
+namespace hpf {
+
+constexpr int kScThreads = 256;
+constexpr int kScPer = 8;                       // beads per thread
+constexpr int kScChunk = kScThreads * kScPer;   // beads per workgroup
+constexpr int kScLds = 6144;                    // u64 LDS entries (48 KiB)
+
+__device__ __forceinline__ void atomic_add_global_u64(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_add_lds_u64(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__global__ __launch_bounds__(kScThreads) void k_density_scatter(const float4* __restrict__ R,
+                                                                const uint8_t* __restrict__ T,
+                                                                int64_t N, MeshK m, int K,
+                                                                unsigned long long* __restrict__ counts)
+{
+    __shared__ unsigned long long box[kScLds];
+    __shared__ int red[kScThreads / kWave][12];
+    __shared__ int info[8];
+
+    const int tid = threadIdx.x;
+    const int64_t chunk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = chunk * kScChunk;
+
+    int32_t c[kScPer][3];
+    uint32_t q[kScPer][3];
+    int ty[kScPer];
+    int lo[2][3], hi[2][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[0][d] = lo[1][d] = 0x7fffffff;
+        hi[0][d] = hi[1][d] = -0x7fffffff;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < kScPer; ++j) {
+        const int64_t i = base + (int64_t)j * kScThreads + tid;
+        ty[j] = -1;
+        if (i < N) {
+            const float4 r = R[i];
+            const int t = T[i];
+            BeadCell b;
+            if (bead_cell(r, m, b) && t < K) {
+                ty[j] = t;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    c[j][d] = b.c[d];
+                    q[j][d] = b.q[d];
+                    const int cs = b.c[d] < (m.M[d] >> 1) ? b.c[d] + m.M[d] : b.c[d];
+                    lo[0][d] = min(lo[0][d], b.c[d]);
+                    hi[0][d] = max(hi[0][d], b.c[d]);
+                    lo[1][d] = min(lo[1][d], cs);
+                    hi[1][d] = max(hi[1][d], cs);
+                }
+            } else {
+                bad = true;
+            }
+        }
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+
+    // Periodic bounding box of the chunk: per axis, the raw cell range or the
+    // range with the lower half shifted up by M, whichever is shorter.
+    const int lane = tid & (kWave - 1), wid = tid / kWave;
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int a = wave_min(lo[v][d]);
+            const int b = wave_max(hi[v][d]);
+            if (lane == 0) {
+                red[wid][v * 6 + d] = a;
+                red[wid][v * 6 + 3 + d] = b;
+            }
+        }
+    __syncthreads();
+    if (tid == 0) {
+        int l2[2][3], h2[2][3];
+        for (int v = 0; v < 2; ++v)
+            for (int d = 0; d < 3; ++d) {
+                l2[v][d] = 0x7fffffff;
+                h2[v][d] = -0x7fffffff;
+                for (int w = 0; w < kScThreads / kWave; ++w) {
+                    l2[v][d] = min(l2[v][d], red[w][v * 6 + d]);
+                    h2[v][d] = max(h2[v][d], red[w][v * 6 + 3 + d]);
+                }
+            }
+        int use = 0;   // 0: nothing to do, 1: LDS box, 2: direct global atomics
+        long long total = K;
+        int shift = 0;   // bit d set: shifted variant on axis d
+        if (l2[0][0] <= h2[0][0]) {
+            for (int d = 0; d < 3; ++d) {
+                const int v = (h2[1][d] - l2[1][d]) < (h2[0][d] - l2[0][d]) ? 1 : 0;
+                info[d] = l2[v][d];                        // origin (extended coords)
+                info[3 + d] = h2[v][d] - l2[v][d] + 2;     // vertices along d
+                total *= info[3 + d];
+                shift |= v << d;
+            }
+            use = total <= kScLds ? 1 : 2;
+        }
+        info[7] = shift;
+        info[6] = use;
+    }
+    __syncthreads();
+    const int use = info[6];
+    if (use == 0)
+        return;
+
+    if (use == 1) {
+        const int ox = info[0], oy = info[1], oz = info[2];
+        const int dx = info[3], dy = info[4], dz = info[5];
+        const int shift = info[7];
+        const int total = K * dx * dy * dz;
+        for (int e = tid; e < total; e += kScThreads)
+            box[e] = 0ull;
+        __syncthreads();
+        const int sxy = dx * dy;
+#pragma unroll
+        for (int j = 0; j < kScPer; ++j) {
+            if (ty[j] < 0)
+                continue;
+            int l[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                int cc = c[j][d];
+                if ((shift >> d) & 1)
+                    cc = cc < (m.M[d] >> 1) ? cc + m.M[d] : cc;
+                l[d] = cc - (d == 0 ? ox : d == 1 ? oy : oz);
+            }
+            const uint64_t wx0 = kOne - q[j][0], wx1 = q[j][0];
+            const uint64_t wy0 = kOne - q[j][1], wy1 = q[j][1];
+            const uint64_t wz0 = kOne - q[j][2], wz1 = q[j][2];
+            unsigned long long* p = box + ((ty[j] * dz + l[2]) * dy + l[1]) * dx + l[0];
+            const uint64_t w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
+            atomic_add_lds_u64(p, wx0 * w00);
+            atomic_add_lds_u64(p + 1, wx1 * w00);
+            atomic_add_lds_u64(p + dx, wx0 * w10);
+            atomic_add_lds_u64(p + dx + 1, wx1 * w10);
+            atomic_add_lds_u64(p + sxy, wx0 * w01);
+            atomic_add_lds_u64(p + sxy + 1, wx1 * w01);
+            atomic_add_lds_u64(p + sxy + dx, wx0 * w11);
+            atomic_add_lds_u64(p + sxy + dx + 1, wx1 * w11);
+        }
+        __syncthreads();
+        for (int e = tid; e < total; e += kScThreads) {
+            const unsigned long long v = box[e];
+            if (!v)
+                continue;
+            int r = e;
+            const int lx = r % dx;
+            r /= dx;
+            const int ly = r % dy;
+            r /= dy;
+            const int lz = r % dz;
+            const int t = r / dz;
+            int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+            while (gx >= m.M[0]) gx -= m.M[0];
+            while (gy >= m.M[1]) gy -= m.M[1];
+            while (gz >= m.M[2]) gz -= m.M[2];
+            atomic_add_global_u64(counts + (int64_t)t * m.nm +
+                                      ((int64_t)gz * m.M[1] + gy) * m.M[0] + gx, v);
+        }
+        return;
+    }
+
+    // Chunk too spread out for the LDS box: direct global atomics.
+#pragma unroll
+    for (int j = 0; j < kScPer; ++j) {
+        if (ty[j] < 0)
+            continue;
+        const int32_t x0 = c[j][0], x1 = next_wrap(x0, m.M[0]);
+        const int32_t y0 = c[j][1], y1 = next_wrap(y0, m.M[1]);
+        const int32_t z0 = c[j][2], z1 = next_wrap(z0, m.M[2]);
+        const uint64_t wx0 = kOne - q[j][0], wx1 = q[j][0];
+        const uint64_t wy0 = kOne - q[j][1], wy1 = q[j][1];
+        const uint64_t wz0 = kOne - q[j][2], wz1 = q[j][2];
+        unsigned long long* nk = counts + (int64_t)ty[j] * m.nm;
+        const int64_t r00 = ((int64_t)z0 * m.M[1] + y0) * m.M[0];
+        const int64_t r10 = ((int64_t)z0 * m.M[1] + y1) * m.M[0];
+        const int64_t r01 = ((int64_t)z1 * m.M[1] + y0) * m.M[0];
+        const int64_t r11 = ((int64_t)z1 * m.M[1] + y1) * m.M[0];
+        atomic_add_global_u64(nk + r00 + x0, wx0 * wy0 * wz0);
+        atomic_add_global_u64(nk + r00 + x1, wx1 * wy0 * wz0);
+        atomic_add_global_u64(nk + r10 + x0, wx0 * wy1 * wz0);
+        atomic_add_global_u64(nk + r10 + x1, wx1 * wy1 * wz0);
+        atomic_add_global_u64(nk + r01 + x0, wx0 * wy0 * wz1);
+        atomic_add_global_u64(nk + r01 + x1, wx1 * wy0 * wz1);
+        atomic_add_global_u64(nk + r11 + x0, wx0 * wy1 * wz1);
+        atomic_add_global_u64(nk + r11 + x1, wx1 * wy1 * wz1);
+    }
+}
+
+hpf_status_t launch_density_scatter(const float* R, const uint8_t* T, int64_t N, const MeshK& m,
+                                    int K, uint64_t* counts, hipStream_t s)
+{
+    if (N == 0)
+        return HPF_OK;
+    const int64_t nb = (N + kScChunk - 1) / kScChunk;
+    if (nb > 0x7fffffff)
+        return HPF_EINVAL;
+    hipLaunchKernelGGL(k_density_scatter, dim3((unsigned)nb), dim3(kScThreads), 0, s,
+                       reinterpret_cast<const float4*>(R), T, N, m, K,
+                       reinterpret_cast<unsigned long long*>(counts));
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+}  // namespace hpf

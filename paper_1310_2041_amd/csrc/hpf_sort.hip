@@ -1,0 +1,330 @@
+// Canonical cell ordering of the beads (the paper reorders particle data for
+// cache hits and bins beads into a cell list, Algorithm 1 Kernel 1).
+//
+// Counting sort on a brick-major cell key: histogram (u32 atomics), an
+// exclusive scan over all keys, placement with per-key cursors, then each
+// key's segment is sorted by tag so the result -- ascending (key, tag) -- is
+// independent of the atomic placement order. Finally the bead arrays are
+// gathered into the output buffers and the bond table is permuted and
+// renumbered through the inverse permutation.
+#include "hpf_common.hpp"
+
+namespace hpf {
+
+struct SortK {
+    MeshK m;
+    int32_t B;
+    int32_t nb[3];
+    uint32_t NK;        // number of cell keys; key NK = "cannot be binned"
+};
+
+constexpr int kSortThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kSortThreads * kScanPer;   // entries per scan block
+constexpr int kScanTopThreads = 1024;
+constexpr int kScanTopPer = 8;
+constexpr int kMaxScanTiles = kScanTopThreads * kScanTopPer;
+constexpr int kSegSortMax = 256;                       // longest segment sorted by tag
+
+__global__ __launch_bounds__(kSortThreads) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kSortThreads)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_copy_u32(const uint32_t* __restrict__ a,
+                                                           uint32_t* __restrict__ b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kSortThreads)
+        b[i] = a[i];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_keys(const float4* __restrict__ R, int64_t N,
+                                                            SortK sk, uint32_t* __restrict__ keys,
+                                                            uint32_t* __restrict__ hist)
+{
+    const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    if (i >= N)
+        return;
+    BeadCell b;
+    uint32_t key = sk.NK;
+    if (bead_cell(R[i], sk.m, b)) {
+        const int B = sk.B;
+        const uint32_t brick = ((uint32_t)(b.c[2] / B) * (uint32_t)sk.nb[1] + (uint32_t)(b.c[1] / B)) *
+                                   (uint32_t)sk.nb[0] + (uint32_t)(b.c[0] / B);
+        const uint32_t local = ((uint32_t)(b.c[2] % B) * (uint32_t)B + (uint32_t)(b.c[1] % B)) *
+                                   (uint32_t)B + (uint32_t)(b.c[0] % B);
+        key = brick * (uint32_t)(B * B * B) + local;
+    }
+    keys[i] = key;
+    atomicAdd(hist + key, 1u);
+}
+
+// Inclusive wave64 scan.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off, kWave);
+        if (lane >= off)
+            v += t;
+    }
+    return v;
+}
+
+// Exclusive block scan of one value per thread; returns the exclusive prefix
+// and the block total through *total.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total)
+{
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1)
+        sh[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < NT / kWave; ++w) {
+            const uint32_t t = sh[w];
+            sh[w] = run;
+            run += t;
+        }
+        sh[NT / kWave] = run;
+    }
+    __syncthreads();
+    const uint32_t r = sh[wid] + inc - v;
+    *total = sh[NT / kWave];
+    __syncthreads();
+    return r;
+}
+
+// Per-tile exclusive scan in place; tile totals to tile_sums.
+__global__ __launch_bounds__(kSortThreads) void k_scan_tiles(uint32_t* __restrict__ a, int64_t n,
+                                                             uint32_t* __restrict__ tile_sums)
+{
+    __shared__ uint32_t sh[kSortThreads / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        v[j] = base + j < n ? a[base + j] : 0u;
+        sum += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan<kSortThreads>(sum, sh, &total);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        if (base + j < n)
+            a[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 0)
+        tile_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanTopThreads) void k_scan_top(uint32_t* __restrict__ t, int n)
+{
+    __shared__ uint32_t sh[kScanTopThreads / kWave + 1];
+    const int base = threadIdx.x * kScanTopPer;
+    uint32_t v[kScanTopPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanTopPer; ++j) {
+        v[j] = base + j < n ? t[base + j] : 0u;
+        sum += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan<kScanTopThreads>(sum, sh, &total);
+#pragma unroll
+    for (int j = 0; j < kScanTopPer; ++j) {
+        if (base + j < n)
+            t[base + j] = run;
+        run += v[j];
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_scan_add(uint32_t* __restrict__ a, int64_t n,
+                                                           const uint32_t* __restrict__ tile_sums)
+{
+    const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    if (i < n)
+        a[i] += tile_sums[i / kScanTile];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_place(const uint32_t* __restrict__ keys, int64_t N,
+                                                             uint32_t* __restrict__ cursor,
+                                                             int32_t* __restrict__ perm)
+{
+    const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    if (i >= N)
+        return;
+    const uint32_t pos = atomicAdd(cursor + keys[i], 1u);
+    perm[pos] = (int32_t)i;
+}
+
+// Sort every key's segment of perm by tag (by input index when there are no
+// tags); insertion sort, segments are a few beads long. Longer segments keep
+// their placement order and raise a flag.
+__global__ __launch_bounds__(kSortThreads) void k_sort_segments(const uint32_t* __restrict__ start,
+                                                                int64_t nseg,
+                                                                const int32_t* __restrict__ tag,
+                                                                int32_t* __restrict__ perm)
+{
+    const int64_t k = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    if (k >= nseg)
+        return;
+    const uint32_t a = start[k], b = start[k + 1];
+    const uint32_t len = b - a;
+    if (len <= 1)
+        return;
+    if (len > (uint32_t)kSegSortMax) {
+        raise_flag(HPF_FLAG_SORT_ORDER);
+        return;
+    }
+    for (uint32_t i = a + 1; i < b; ++i) {
+        const int32_t pi = perm[i];
+        const int32_t ti = tag ? tag[pi] : pi;
+        uint32_t j = i;
+        while (j > a) {
+            const int32_t pj = perm[j - 1];
+            if ((tag ? tag[pj] : pj) <= ti)
+                break;
+            perm[j] = pj;
+            --j;
+        }
+        perm[j] = pi;
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_permute(const int32_t* __restrict__ perm, int64_t N,
+                                                               const float4* __restrict__ R_in,
+                                                               const float4* __restrict__ V_in,
+                                                               const uint8_t* __restrict__ T_in,
+                                                               const int32_t* __restrict__ tag_in,
+                                                               float4* __restrict__ R_out,
+                                                               float4* __restrict__ V_out,
+                                                               uint8_t* __restrict__ T_out,
+                                                               int32_t* __restrict__ tag_out,
+                                                               int32_t* __restrict__ inv)
+{
+    const int64_t p = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    if (p >= N)
+        return;
+    const int32_t o = perm[p];
+    R_out[p] = R_in[o];
+    if (V_in)
+        V_out[p] = V_in[o];
+    T_out[p] = T_in[o];
+    if (tag_in)
+        tag_out[p] = tag_in[o];
+    inv[o] = (int32_t)p;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_bonds(const int32_t* __restrict__ perm,
+                                                             const int32_t* __restrict__ inv, int64_t N,
+                                                             const int32_t* __restrict__ bonds_in, int D,
+                                                             int32_t* __restrict__ bonds_out)
+{
+    const int64_t p = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    if (p >= N)
+        return;
+    const int32_t o = perm[p];
+    bool bad = false;
+    for (int b = 0; b < D; ++b) {
+        const int32_t j = bonds_in[(int64_t)b * N + o];
+        int32_t nj = -1;
+        if (j >= 0 && j < N)
+            nj = inv[j];
+        else if (j >= N || j < -1)
+            bad = true;
+        bonds_out[(int64_t)b * N + p] = nj;
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BOND);
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool sort_layout(int64_t N, const int32_t M[3], int B, SortK* sk_out, size_t* bytes,
+                 size_t off[6])
+{
+    if (B == 0)
+        B = 8;
+    if (B < 1 || B > 16 || N < 0 || N > 0x7ffffff0LL)
+        return false;
+    int64_t nk = (int64_t)B * B * B;
+    int32_t nb[3];
+    for (int d = 0; d < 3; ++d) {
+        nb[d] = (M[d] + B - 1) / B;
+        nk *= nb[d];
+    }
+    const int64_t nscan = nk + 2;
+    const int64_t ntiles = (nscan + kScanTile - 1) / kScanTile;
+    if (ntiles > kMaxScanTiles)
+        return false;
+    if (sk_out) {
+        sk_out->B = B;
+        for (int d = 0; d < 3; ++d)
+            sk_out->nb[d] = nb[d];
+        sk_out->NK = (uint32_t)nk;
+    }
+    size_t o = 0;
+    off[0] = o; o += align_up(sizeof(uint32_t) * (size_t)(N > 0 ? N : 1));    // keys
+    off[1] = o; o += align_up(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));     // perm
+    off[2] = o; o += align_up(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));     // inv
+    off[3] = o; o += align_up(sizeof(uint32_t) * (size_t)nscan);              // start
+    off[4] = o; o += align_up(sizeof(uint32_t) * (size_t)nscan);              // cursor
+    off[5] = o; o += align_up(sizeof(uint32_t) * (size_t)ntiles);             // tile sums
+    *bytes = o;
+    return true;
+}
+
+static unsigned grid_for(int64_t n) { return (unsigned)((n + kSortThreads - 1) / kSortThreads); }
+
+hpf_status_t launch_sort(const SortK& sk, int64_t N, const float* R_in, const float* V_in,
+                         const uint8_t* T_in, const int32_t* tag_in, const int32_t* bonds_in, int D,
+                         float* R_out, float* V_out, uint8_t* T_out, int32_t* tag_out,
+                         int32_t* bonds_out, uint32_t* cell_start, char* work, const size_t off[6],
+                         hipStream_t s)
+{
+    uint32_t* keys = reinterpret_cast<uint32_t*>(work + off[0]);
+    int32_t* perm = reinterpret_cast<int32_t*>(work + off[1]);
+    int32_t* inv = reinterpret_cast<int32_t*>(work + off[2]);
+    uint32_t* start = cell_start ? cell_start : reinterpret_cast<uint32_t*>(work + off[3]);
+    uint32_t* cursor = reinterpret_cast<uint32_t*>(work + off[4]);
+    uint32_t* tiles = reinterpret_cast<uint32_t*>(work + off[5]);
+    const int64_t nscan = (int64_t)sk.NK + 2;
+    const int64_t ntiles = (nscan + kScanTile - 1) / kScanTile;
+    const unsigned gfill = (unsigned)std::min<int64_t>(grid_for(nscan), 4096);
+
+    hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, nscan, 0u);
+    if (N > 0)
+        hipLaunchKernelGGL(k_sort_keys, dim3(grid_for(N)), dim3(kSortThreads), 0, s,
+                           reinterpret_cast<const float4*>(R_in), N, sk, keys, start);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, start, nscan,
+                       tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, s, tiles, (int)ntiles);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(nscan)), dim3(kSortThreads), 0, s, start, nscan,
+                       tiles);
+    if (N > 0) {
+        hipLaunchKernelGGL(k_copy_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, cursor, nscan);
+        hipLaunchKernelGGL(k_sort_place, dim3(grid_for(N)), dim3(kSortThreads), 0, s, keys, N,
+                           cursor, perm);
+        hipLaunchKernelGGL(k_sort_segments, dim3(grid_for(nscan - 1)), dim3(kSortThreads), 0, s,
+                           start, nscan - 1, tag_in, perm);
+        hipLaunchKernelGGL(k_sort_permute, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, N,
+                           reinterpret_cast<const float4*>(R_in), reinterpret_cast<const float4*>(V_in),
+                           T_in, tag_in, reinterpret_cast<float4*>(R_out),
+                           reinterpret_cast<float4*>(V_out), T_out, tag_out, inv);
+        if (D > 0 && bonds_in)
+            hipLaunchKernelGGL(k_sort_bonds, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, inv,
+                               N, bonds_in, D, bonds_out);
+    }
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+}  // namespace hpf

@@ -1,0 +1,279 @@
+"""Python binding of libhpf (include/hpf.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls, takes torch
+tensors that live on the GPU (plus host-side parameter structs), checks
+dtypes, shapes and contiguity, and passes raw device pointers and the current
+HIP stream to the library. All arithmetic happens in the library's kernels.
+If the library is not built, importing this module raises; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhpf.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "hpf.h")
+
+HPF_FIX_BITS = 16
+HPF_MAX_TYPES = 8
+HPF_NPART = 1024
+HPF_MAX_BONDS = 16
+
+HPF_FLAG_BAD_BEAD = 0x1
+HPF_FLAG_OVERFLOW = 0x2
+HPF_FLAG_NONFINITE = 0x4
+HPF_FLAG_BAD_BOND = 0x8
+HPF_FLAG_SORT_ORDER = 0x10
+
+
+class HpfError(RuntimeError):
+    def __init__(self, fn: str, status: int, text: str):
+        super().__init__(f"{fn} failed: {text} (status {status})")
+        self.status = status
+
+
+class Mesh(C.Structure):
+    """hpf_mesh_t"""
+    _fields_ = [("L", C.c_float * 3), ("M", C.c_int32 * 3), ("s", C.c_float * 3),
+                ("reserved", C.c_int32), ("c_norm", C.c_double)]
+
+
+class Field(C.Structure):
+    """hpf_field_t"""
+    _fields_ = [("K", C.c_int32), ("reserved", C.c_int32), ("kT", C.c_double),
+                ("inv_kappa", C.c_double), ("chi", C.c_double * (HPF_MAX_TYPES * HPF_MAX_TYPES))]
+
+
+_lib = None
+_P = C.c_void_p
+
+_SIGNATURES = {
+    "hpf_abi_version": ([], C.c_int32),
+    "hpf_status_string": ([C.c_int32], C.c_char_p),
+    "hpf_mesh_make": ([_P, _P, C.c_int64, C.POINTER(Mesh)], C.c_int32),
+    "hpf_density_scatter": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P], C.c_int32),
+    "hpf_field_potential": ([_P, C.POINTER(Mesh), C.POINTER(Field), _P, _P, _P], C.c_int32),
+    "hpf_field_gradient": ([_P, C.POINTER(Mesh), C.c_int32, _P, _P], C.c_int32),
+    "hpf_force_gather": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, _P], C.c_int32),
+    "bond_forces": ([_P, C.c_int64, _P, C.c_int32, C.c_float, C.c_float, _P, _P, _P, _P],
+                    C.c_int32),
+    "verlet_step": ([_P, _P, _P, _P, C.c_int64, C.c_float, _P, C.c_int32, _P, _P], C.c_int32),
+    "hpf_reduce_partials": ([_P, C.c_int32, _P, _P], C.c_int32),
+    "hpf_sort_workspace_bytes": ([C.c_int64, C.POINTER(Mesh), C.c_int32], C.c_size_t),
+    "hpf_sort_by_cell": ([C.POINTER(Mesh), C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
+                          _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int32),
+    "hpf_get_device_status": ([C.POINTER(C.c_uint32), C.c_int32, _P], C.c_int32),
+}
+
+
+def lib():
+    """Load libhpf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1310_2041_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        if L.hpf_abi_version() != 1:
+            raise ImportError("libhpf ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+def declared_functions() -> list:
+    """Names of the functions declared in include/hpf.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(\w+)\s*\([^;{]*\)\s*;", text)) -
+                  {"if", "while", "for", "return", "sizeof"})
+
+
+def _check(fn: str, status: int):
+    if status != 0:
+        raise HpfError(fn, status, lib().hpf_status_string(status).decode())
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _dev(t: torch.Tensor | None, name: str, dtype=None, shape=None, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr()) if t.numel() else None
+
+
+_U64 = (torch.int64, torch.uint64) if hasattr(torch, "uint64") else (torch.int64,)
+
+
+def hpf_mesh_make(L, M, n_beads: int) -> Mesh:
+    Lf = (C.c_float * 3)(*[float(x) for x in (L if hasattr(L, "__len__") else (L,) * 3)])
+    Mi = (C.c_int32 * 3)(*[int(x) for x in (M if hasattr(M, "__len__") else (M,) * 3)])
+    m = Mesh()
+    _check("hpf_mesh_make", lib().hpf_mesh_make(Lf, Mi, int(n_beads), C.byref(m)))
+    return m
+
+
+def make_field(K: int, kT: float, inv_kappa: float, chi) -> Field:
+    f = Field()
+    f.K = int(K)
+    f.kT = float(kT)
+    f.inv_kappa = float(inv_kappa)
+    flat = [float(chi[a][b]) for a in range(K) for b in range(K)]
+    for i, v in enumerate(flat):
+        f.chi[i] = v
+    return f
+
+
+def _nm(mesh: Mesh) -> int:
+    return mesh.M[0] * mesh.M[1] * mesh.M[2]
+
+
+def _box(mesh_or_box):
+    if isinstance(mesh_or_box, Mesh):
+        return (C.c_float * 3)(*mesh_or_box.L)
+    v = [float(x) for x in (mesh_or_box if hasattr(mesh_or_box, "__len__") else (mesh_or_box,) * 3)]
+    return (C.c_float * 3)(*v)
+
+
+def hpf_density_scatter(R, T, mesh: Mesh, K: int, counts, stream=None):
+    N = R.shape[0]
+    r = _dev(R, "R", torch.float32, (N, 4))
+    t = _dev(T, "T", torch.uint8, (N,))
+    c = _dev(counts, "counts", _U64, (K, _nm(mesh)))
+    _check("hpf_density_scatter",
+           lib().hpf_density_scatter(r, t, N, C.byref(mesh), K, c, _stream(stream)))
+
+
+def hpf_field_potential(counts, mesh: Mesh, field: Field, V, w_part=None, stream=None):
+    nm, K = _nm(mesh), field.K
+    c = _dev(counts, "counts", _U64, (K, nm))
+    v = _dev(V, "V", torch.float32, (K, nm))
+    w = _dev(w_part, "w_part", torch.float64, None, allow_none=True)
+    if w_part is not None and w_part.numel() < HPF_NPART:
+        raise ValueError("w_part needs HPF_NPART slots")
+    _check("hpf_field_potential",
+           lib().hpf_field_potential(c, C.byref(mesh), C.byref(field), v, w, _stream(stream)))
+
+
+def hpf_field_gradient(V, mesh: Mesh, K: int, G, stream=None):
+    nm = _nm(mesh)
+    v = _dev(V, "V", torch.float32, (K, nm))
+    g = _dev(G, "G", torch.float32, (K, nm, 4))
+    _check("hpf_field_gradient", lib().hpf_field_gradient(v, C.byref(mesh), K, g, _stream(stream)))
+
+
+def hpf_force_gather(R, T, mesh: Mesh, K: int, G, F, stream=None):
+    N, nm = R.shape[0], _nm(mesh)
+    r = _dev(R, "R", torch.float32, (N, 4))
+    t = _dev(T, "T", torch.uint8, (N,))
+    g = _dev(G, "G", torch.float32, (K, nm, 4))
+    f = _dev(F, "F", torch.float32, (N, 4))
+    _check("hpf_force_gather",
+           lib().hpf_force_gather(r, t, N, C.byref(mesh), K, g, f, _stream(stream)))
+
+
+def bond_forces(R, bonds, k: float, r0: float, box, F, e_part=None, stream=None):
+    N = R.shape[0]
+    D = bonds.shape[0] if bonds is not None else 0
+    r = _dev(R, "R", torch.float32, (N, 4))
+    b = _dev(bonds, "bonds", torch.int32, (D, N), allow_none=True) if D else None
+    f = _dev(F, "F", torch.float32, (N, 4))
+    e = _dev(e_part, "e_part", torch.float64, None, allow_none=True)
+    if e_part is not None and e_part.numel() < HPF_NPART:
+        raise ValueError("e_part needs HPF_NPART slots")
+    _check("bond_forces", lib().bond_forces(r, N, b, D, float(k), float(r0), _box(box), f, e,
+                                            _stream(stream)))
+
+
+def verlet_step(R, Vel, F, dt: float, box, half: int, inv_mass=None, kin_part=None, stream=None):
+    N = Vel.shape[0]
+    r = _dev(R, "R", torch.float32, (N, 4), allow_none=(half == 2))
+    v = _dev(Vel, "Vel", torch.float32, (N, 4))
+    f = _dev(F, "F", torch.float32, (N, 4))
+    im = _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True)
+    kp = _dev(kin_part, "kin_part", torch.float64, None, allow_none=True)
+    if kin_part is not None and kin_part.numel() < 4 * HPF_NPART:
+        raise ValueError("kin_part needs 4 * HPF_NPART slots")
+    _check("verlet_step", lib().verlet_step(r, v, f, im, N, float(dt), _box(box), int(half), kp,
+                                            _stream(stream)))
+
+
+def hpf_reduce_partials(part, ncomp: int, out, stream=None):
+    p = _dev(part, "part", torch.float64)
+    o = _dev(out, "out", torch.float64)
+    if part.numel() < ncomp * HPF_NPART or out.numel() < ncomp:
+        raise ValueError("partial buffer or output too small")
+    _check("hpf_reduce_partials", lib().hpf_reduce_partials(p, int(ncomp), o, _stream(stream)))
+
+
+def hpf_sort_workspace_bytes(N: int, mesh: Mesh, B: int = 8) -> int:
+    n = lib().hpf_sort_workspace_bytes(int(N), C.byref(mesh), int(B))
+    if n == 0:
+        raise HpfError("hpf_sort_workspace_bytes", -1, "invalid mesh, size or brick")
+    return int(n)
+
+
+def sort_key_count(mesh: Mesh, B: int = 8) -> int:
+    """NK: number of cell keys of the brick-major order (cell_start needs NK + 2)."""
+    B = B or 8
+    n = B ** 3
+    for d in range(3):
+        n *= (mesh.M[d] + B - 1) // B
+    return n
+
+
+def hpf_sort_by_cell(mesh: Mesh, B: int, R_in, Vel_in, T_in, tag_in, bonds_in, R_out, Vel_out,
+                     T_out, tag_out, bonds_out, work, cell_start=None, stream=None):
+    N = R_in.shape[0]
+    D = bonds_in.shape[0] if bonds_in is not None else 0
+    args = [
+        _dev(R_in, "R_in", torch.float32, (N, 4)),
+        _dev(Vel_in, "Vel_in", torch.float32, (N, 4), allow_none=True),
+        _dev(T_in, "T_in", torch.uint8, (N,)),
+        _dev(tag_in, "tag_in", torch.int32, (N,), allow_none=True),
+        _dev(bonds_in, "bonds_in", torch.int32, (D, N), allow_none=True) if D else None,
+        int(D),
+        _dev(R_out, "R_out", torch.float32, (N, 4)),
+        _dev(Vel_out, "Vel_out", torch.float32, (N, 4), allow_none=True),
+        _dev(T_out, "T_out", torch.uint8, (N,)),
+        _dev(tag_out, "tag_out", torch.int32, (N,), allow_none=True),
+        _dev(bonds_out, "bonds_out", torch.int32, (D, N), allow_none=True) if D else None,
+    ]
+    cs = None
+    if cell_start is not None:
+        nk = sort_key_count(mesh, B)
+        cs = _dev(cell_start, "cell_start", torch.int32, (nk + 2,))
+    w = _dev(work, "work", torch.uint8)
+    _check("hpf_sort_by_cell",
+           lib().hpf_sort_by_cell(C.byref(mesh), int(B), N, *args, cs, w, work.numel(),
+                                  _stream(stream)))
+
+
+def hpf_get_device_status(clear: bool = True, stream=None) -> int:
+    flags = C.c_uint32(0)
+    _check("hpf_get_device_status",
+           lib().hpf_get_device_status(C.byref(flags), int(bool(clear)), _stream(stream)))
+    return int(flags.value)

@@ -1,0 +1,106 @@
+"""Whole-step GPU parity: forces of the full hot path against the FP64 oracle,
+energies along trajectories, determinism, and the full-size workloads."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from gpu_util import by_tag, counts_np, host, rel_max  # noqa: E402
+from paper_1310_2041_amd import engine, hpf  # noqa: E402
+from synth import workloads as wl  # noqa: E402
+
+
+def gpu_forces(s, sort=True):
+    """(counts, F_field, F_bond, energies) from the HIP path, in tag order."""
+    st = engine.HpfState.from_system(s)
+    if sort:
+        st.sort()
+    hpf.hpf_density_scatter(st.R, st.T, st.mesh, st.K, st.counts)
+    counts = counts_np(st.counts, s.K, s.M)
+    st.counts.zero_()
+    st.field_forces(report=True)
+    Ff = host(st.F)[:, :3].copy()
+    st.F.zero_()
+    st.bond_forces(report=True)
+    Fb = host(st.F)[:, :3].copy()
+    hpf.hpf_reduce_partials(st.part, engine.N_ROWS, st.energy)
+    e = host(st.energy)
+    tag = host(st.tag)
+    return counts, by_tag(Ff, tag, s.N), by_tag(Fb, tag, s.N), {"W": e[0], "E_bond": e[1]}
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_single_step_forces(cfg):
+    s = wl.build(wl.SPECS[cfg])
+    counts, Ff, Fb, e = gpu_forces(s)
+    c_or, _ = oracle.density(s.R, s.T, s.L, s.M, s.K)
+    assert np.array_equal(counts, c_or)
+    Ff_or, Fb_or, e_or = oracle.forces(s)
+    ef, eb = rel_max(Ff, Ff_or), rel_max(Fb, Fb_or)
+    print(f"{cfg}: field rel max-norm {ef:.3e}, bond {eb:.3e}")
+    assert ef <= 1e-5
+    assert eb <= 1e-5
+    assert e["W"] == pytest.approx(e_or["W"], rel=1e-9)
+    assert e["E_bond"] == pytest.approx(e_or["E_bond"], rel=1e-6)
+    assert hpf.hpf_get_device_status() == 0
+
+
+def test_single_step_forces_three_species():
+    s = wl.small_system(3000, 12, 29.0, 24, K=3, n_solvent=40000, seed=51)
+    counts, Ff, Fb, _ = gpu_forces(s)
+    c_or, _ = oracle.density(s.R, s.T, s.L, s.M, s.K)
+    assert np.array_equal(counts, c_or)
+    Ff_or, Fb_or, _ = oracle.forces(s)
+    assert rel_max(Ff, Ff_or) <= 1e-5
+    assert rel_max(Fb, Fb_or) <= 1e-5
+
+
+@pytest.mark.slow
+def test_full_size_10m_blend_counts_and_forces():
+    """The 10M-bead blend at full size, in the benchmark's launch configuration."""
+    s = wl.build(wl.SPECS["c3"])
+    counts, Ff, Fb, _ = gpu_forces(s)
+    c_or, _ = oracle.density(s.R, s.T, s.L, s.M, s.K)
+    assert np.array_equal(counts, c_or)
+    del counts, c_or
+    Ff_or, Fb_or, _ = oracle.forces(s)
+    ef, eb = rel_max(Ff, Ff_or), rel_max(Fb, Fb_or)
+    print(f"c3: field rel max-norm {ef:.3e}, bond {eb:.3e}")
+    assert ef <= 1e-5
+    assert eb <= 1e-5
+
+
+def _gpu_energy_trace(s, n, sort_every=10):
+    st = engine.HpfState.from_system(s)
+    st.start(sort=True)
+    e0 = st.energies()
+    trace = [e0] + st.run(n, report_every=1, sort_every=sort_every)
+    return np.array([[e["KE"], e["E_bond"], e["W"], e["E_tot"]] for e in trace]), st
+
+
+def test_c1_100_steps_energies():
+    s = wl.build(wl.SPECS["c1"])
+    Eg, st = _gpu_energy_trace(s, 100)
+    _, _, Eo = oracle.run(s, 100)
+    rel = np.abs(Eg - Eo) / np.abs(Eo)
+    print("max per-step rel diff (KE, Eb, W, Etot):", rel.max(0))
+    print("mean-energy rel diff:", np.abs(Eg.mean(0) - Eo.mean(0)) / np.abs(Eo.mean(0)))
+    # the first steps follow the oracle closely; later ones drift apart chaotically
+    assert rel[:20].max() <= 1e-4
+    assert rel[:, 3].max() <= 1e-3
+    assert hpf.hpf_get_device_status() == 0
+
+
+def test_determinism_bitwise():
+    s = wl.build(wl.SPECS["c1"])
+    Ea, a = _gpu_energy_trace(s, 40, sort_every=7)
+    sp, _ = wl.permuted(s, seed=3)     # a different storage order gives the same run
+    Eb, b = _gpu_energy_trace(sp, 40, sort_every=7)
+    assert np.array_equal(Ea, Eb)
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
