@@ -68,7 +68,7 @@ def timed_step(st, hpf, engine, tm, sort):
     tm.wrap("verlet_half1", hpf.verlet_step, st.R, st.Vel, st.F, st.dt, st.box, 1)
     if sort:
         tm.wrap("sort_by_cell", st.sort)
-    tm.wrap("density_scatter", hpf.hpf_density_scatter, st.R, st.T, st.mesh, st.K, st.counts)
+    tm.wrap("density_scatter", st.scatter)
     tm.wrap("field_potential", hpf.hpf_field_potential, st.counts, st.mesh, st.field, st.V,
             st.part[engine.ROW_W])
     tm.wrap("field_gradient", hpf.hpf_field_gradient, st.V, st.mesh, st.K, st.G)

@@ -127,6 +127,36 @@ hpf_status_t hpf_density_scatter(const float* R, const uint8_t* T, int64_t N,
                                  void* stream);
 
 /* ---------------------------------------------------------------------------
+ * hpf_density_scatter_cells -- the same counts as hpf_density_scatter, for
+ * beads stored in the order of hpf_sort_by_cell (positions may have moved
+ * since that sort). The paper computes these sums by gathering at the mesh
+ * points over a cell list (Algorithm 1 Kernel 2); here each B^3 brick of cells
+ * deposits its listed beads into an LDS box of (B + 1 + 2*halo)^3 points that
+ * is stored to a per-brick partial buffer, and one thread per mesh point adds
+ * the boxes covering it. Beads that moved more than `halo` cells out of their
+ * brick since the sort, and beads the sort could not bin, are added
+ * afterwards with global atomics. Counts are exact for any drift.
+ *
+ * cell_start  uint32[NK + 2] device, from the hpf_sort_by_cell call that
+ *             produced the current storage order, with the same B.
+ * B           brick edge 3..8 (0 selects 8); halo 0..2 cells, halo < B. Every
+ *             M_d must be >= B + 1 + 2*halo, and K (B + 1 + 2 halo)^3 * 8 bytes
+ *             must fit in 160 KiB of LDS (HPF_EINVAL otherwise).
+ * counts      uint64[K][Mz][My][Mx] device, OVERWRITTEN (need not be zero).
+ * work        device workspace of at least
+ *             hpf_scatter_workspace_bytes(N, mesh, K, B, halo) bytes (stray
+ *             list and partial boxes); 0 from that call means invalid sizes.
+ * Skipped beads set HPF_FLAG_BAD_BEAD as in hpf_density_scatter.
+ * ------------------------------------------------------------------------- */
+size_t hpf_scatter_workspace_bytes(int64_t N, const hpf_mesh_t* mesh, int32_t K, int32_t B,
+                                   int32_t halo);
+hpf_status_t hpf_density_scatter_cells(const float* R, const uint8_t* T, int64_t N,
+                                       const hpf_mesh_t* mesh, int32_t K,
+                                       const uint32_t* cell_start, int32_t B, int32_t halo,
+                                       uint64_t* counts, void* work, size_t work_bytes,
+                                       void* stream);
+
+/* ---------------------------------------------------------------------------
  * hpf_field_potential -- external potential of eq. (4) at every mesh point.
  *
  *   phi_K = counts_K * c_norm                  (FP64)

@@ -59,6 +59,7 @@ static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 }  // namespace hpf
 
 #include "hpf_scatter.hip"
+#include "hpf_scatter_cells.hip"
 #include "hpf_field.hip"
 #include "hpf_particles.hip"
 #include "hpf_sort.hip"
@@ -107,6 +108,64 @@ hpf_status_t hpf_density_scatter(const float* R, const uint8_t* T, int64_t N, co
     if (N > 0 && (!R || !T))
         return HPF_EINVAL;
     return launch_density_scatter(R, T, N, mesh_k(mesh), K, counts, as_stream(stream));
+}
+
+static bool scatter_cells_setup(int64_t N, const hpf_mesh_t* mesh, int32_t K, int32_t B, int32_t halo,
+                                TileK* tk, size_t* stray_bytes, size_t* total_bytes)
+{
+    if (N < 0 || N > 0x7ffffff0LL || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES)
+        return false;
+    if (B == 0)
+        B = 8;
+    if (B < 3 || B > kTcMaxB || halo < 0 || halo > kTcMaxHalo || halo >= B)
+        return false;
+    for (int d = 0; d < 3; ++d)
+        if (mesh->M[d] < B + 1 + 2 * halo)
+            return false;
+    const int P = B + 1 + 2 * halo;
+    if (scatter_cells_smem(K, P) > 160 * 1024)
+        return false;
+    int64_t nk = (int64_t)B * B * B, nt = 1;
+    for (int d = 0; d < 3; ++d) {
+        tk->nb[d] = (mesh->M[d] + B - 1) / B;
+        nk *= tk->nb[d];
+        nt *= tk->nb[d];
+    }
+    if (nt > 0x7fffffffLL || nk > 0xfffffff0LL)
+        return false;
+    tk->m = mesh_k(mesh);
+    tk->B = B;
+    tk->h = halo;
+    tk->P = P;
+    tk->NK = (uint32_t)nk;
+    tk->ntiles = nt;
+    *stray_bytes = (sizeof(uint32_t) * (size_t)(N + 64) + 255) & ~(size_t)255;
+    *total_bytes = *stray_bytes + scatter_cells_partials(nt, K, P);
+    return true;
+}
+
+size_t hpf_scatter_workspace_bytes(int64_t N, const hpf_mesh_t* mesh, int32_t K, int32_t B, int32_t halo)
+{
+    TileK tk;
+    size_t sb = 0, tb = 0;
+    return scatter_cells_setup(N, mesh, K, B, halo, &tk, &sb, &tb) ? tb : 0;
+}
+
+hpf_status_t hpf_density_scatter_cells(const float* R, const uint8_t* T, int64_t N, const hpf_mesh_t* mesh,
+                                       int32_t K, const uint32_t* cell_start, int32_t B, int32_t halo,
+                                       uint64_t* counts, void* work, size_t work_bytes, void* stream)
+{
+    TileK tk;
+    size_t sb = 0, tb = 0;
+    if (!counts || !cell_start || !scatter_cells_setup(N, mesh, K, B, halo, &tk, &sb, &tb))
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !T))
+        return HPF_EINVAL;
+    if (!work || work_bytes < tb)
+        return HPF_ESPACE;
+    char* w = static_cast<char*>(work);
+    return launch_scatter_cells(R, T, N, tk, K, cell_start, counts, reinterpret_cast<uint32_t*>(w),
+                                reinterpret_cast<unsigned long long*>(w + sb), as_stream(stream));
 }
 
 hpf_status_t hpf_field_potential(uint64_t* counts, const hpf_mesh_t* mesh, const hpf_field_t* field,
@@ -191,7 +250,7 @@ size_t hpf_sort_workspace_bytes(int64_t N, const hpf_mesh_t* mesh, int32_t B)
 {
     if (!mesh_ok(mesh))
         return 0;
-    size_t bytes = 0, off[6];
+    size_t bytes = 0, off[7];
     if (!sort_layout(N, mesh->M, B, nullptr, &bytes, off))
         return 0;
     return bytes;
@@ -213,7 +272,7 @@ hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N, cons
                   (tag_in && tag_in == tag_out) || (D > 0 && bonds_in == bonds_out)))
         return HPF_EINVAL;
     SortK sk;
-    size_t bytes = 0, off[6];
+    size_t bytes = 0, off[7];
     if (!sort_layout(N, mesh->M, B, &sk, &bytes, off))
         return HPF_EINVAL;
     if (!work || work_bytes < bytes)

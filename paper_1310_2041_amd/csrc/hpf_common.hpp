@@ -121,6 +121,45 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
+// Inclusive wave64 scan.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off, kWave);
+        if (lane >= off)
+            v += t;
+    }
+    return v;
+}
+
+// Exclusive block scan of one value per thread; returns the exclusive prefix
+// and the block total through *total.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total)
+{
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1)
+        sh[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < NT / kWave; ++w) {
+            const uint32_t t = sh[w];
+            sh[w] = run;
+            run += t;
+        }
+        sh[NT / kWave] = run;
+    }
+    __syncthreads();
+    const uint32_t r = sh[wid] + inc - v;
+    *total = sh[NT / kWave];
+    __syncthreads();
+    return r;
+}
+
 // Minimum-image separation x_j - x_i along one axis of a periodic box for
 // coordinates inside [0, L). When the raw difference exceeds half a box the
 // wrapped coordinate is formed first (x_j - L or x_i - L is exact by Sterbenz's

@@ -1,0 +1,354 @@
+// Density assignment over the cell list (beads in hpf_sort_by_cell order).
+//
+// The paper gathers: one thread per mesh point collects the fractions of the
+// beads in the eight cells around it (Algorithm 1 Kernel 2), so no two threads
+// write one point. Here the deposit is pushed from the beads, but still
+// without global atomics and with exact integer sums:
+//
+//   pass 1  one workgroup per B^3 brick of cells reads the beads listed in
+//           the brick (a contiguous range after the sort) and accumulates
+//           their fixed-point weights in an LDS box of P = B + 1 + 2h mesh
+//           points per axis, h = drift halo in cells; the box is stored to a
+//           per-brick partial buffer;
+//   pass 2  one thread per mesh point adds the partial boxes covering it
+//           (per axis the own brick and at most one neighbour) and stores the
+//           count;
+//   fixup   beads that moved more than h cells out of their brick since the
+//           sort, and beads the sort could not bin, are added with global u64
+//           atomics.
+//
+// Every bead is deposited exactly once, integer addition is exact and order
+// free, so the counts equal those of hpf_density_scatter bit for bit.
+#include "hpf_common.hpp"
+
+namespace hpf {
+
+constexpr int kTcThreads = 256;
+constexpr int kTcMaxB = 8;
+constexpr int kTcMaxHalo = 2;
+constexpr int kStrayStage = 1024;   // strays a workgroup stages in LDS before appending
+
+struct TileK {
+    MeshK m;
+    int32_t B;          // brick edge (tile of owned mesh points)
+    int32_t h;          // drift halo in cells
+    int32_t nb[3];      // bricks per axis
+    uint32_t NK;        // number of cell keys
+    int32_t P;          // B + 1 + 2h: mesh points per axis of a brick's deposit box
+    int64_t ntiles;
+};
+
+__device__ __forceinline__ uint32_t brick_key(int cx, int cy, int cz, int B, const int nb[3])
+{
+    const uint32_t brick = ((uint32_t)(cz / B) * (uint32_t)nb[1] + (uint32_t)(cy / B)) * (uint32_t)nb[0] +
+                           (uint32_t)(cx / B);
+    const uint32_t local = ((uint32_t)(cz % B) * (uint32_t)B + (uint32_t)(cy % B)) * (uint32_t)B +
+                           (uint32_t)(cx % B);
+    return brick * (uint32_t)(B * B * B) + local;
+}
+
+__device__ __forceinline__ int wrap_idx(int c, int M)
+{
+    c %= M;
+    return c < 0 ? c + M : c;
+}
+
+// Periodic difference a - b folded into [-M/2, M/2].
+__device__ __forceinline__ int periodic_delta(int a, int b, int M)
+{
+    int d = a - b;
+    if (d > M / 2)
+        d -= M;
+    else if (d < -(M / 2))
+        d += M;
+    return d;
+}
+
+__device__ __forceinline__ void lds_add_u64(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+
+// Pass 1: one workgroup per brick deposits the beads listed in that brick --
+// one contiguous range of the cell-sorted arrays -- into an LDS box of
+// P = B + 1 + 2h mesh points per axis starting h points below the brick (a
+// bead that drifted at most h cells reaches points [x0 - h, x0 + B + h]). A
+// thread takes kScBatch consecutive beads, so the lanes of one LDS atomic
+// mostly sit in different cells. The box goes to a per-brick partial buffer
+// with plain stores. Beads outside the box (strays) and beads that cannot be
+// binned are staged and appended to the stray list.
+constexpr int kScBatch = 4;
+
+__global__ __launch_bounds__(kTcThreads) void k_scatter_bricks(const float4* __restrict__ R,
+                                                               const uint8_t* __restrict__ T, int K,
+                                                               TileK tk,
+                                                               const uint32_t* __restrict__ cell_start,
+                                                               unsigned long long* __restrict__ partials,
+                                                               uint32_t* __restrict__ strays)
+{
+    extern __shared__ unsigned long long smem[];
+    __shared__ uint32_t stray_buf[kStrayStage];
+    __shared__ uint32_t stray_n, stray_base;
+    const int tid = threadIdx.x;
+    const int B = tk.B, h = tk.h, P = tk.P;
+    const int Mx = tk.m.M[0], My = tk.m.M[1], Mz = tk.m.M[2];
+    const int64_t brick = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(brick % tk.nb[0]);
+    const int by = (int)((brick / tk.nb[0]) % tk.nb[1]);
+    const int bz = (int)(brick / ((int64_t)tk.nb[0] * tk.nb[1]));
+    const int x0 = bx * B, y0 = by * B, z0 = bz * B;
+    const int ox = min(B, Mx - x0), oy = min(B, My - y0), oz = min(B, Mz - z0);
+    const int P2 = P * P, P3 = P2 * P;
+    const int nbox = K * P3;
+    unsigned long long* box = smem;
+    for (int e = tid; e < nbox; e += kTcThreads)
+        box[e] = 0ull;
+    if (tid == 0)
+        stray_n = 0;
+    __syncthreads();
+
+    const uint32_t B3 = (uint32_t)(B * B * B);
+    const uint32_t first = cell_start[(uint32_t)brick * B3];
+    const uint32_t last = cell_start[(uint32_t)(brick + 1) * B3];
+    for (uint32_t j0 = first; j0 < last; j0 += kTcThreads * kScBatch) {
+        float4 rj[kScBatch];
+        int tj[kScBatch];
+        const uint32_t jb = j0 + tid * kScBatch;
+#pragma unroll
+        for (int u = 0; u < kScBatch; ++u) {
+            if (jb + u < last) {
+                rj[u] = R[jb + u];
+                tj[u] = T[jb + u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kScBatch; ++u) {
+            const uint32_t p = jb + u;
+            if (p >= last)
+                continue;
+            const int t = tj[u];
+            BeadCell b;
+            const bool ok = bead_cell(rj[u], tk.m, b) && t < K;
+            // current cell relative to the box origin (x0 - h, ...), periodic
+            int lx = 0, ly = 0, lz = 0;
+            if (ok) {
+                lx = periodic_delta(b.c[0], x0, Mx) + h;
+                ly = periodic_delta(b.c[1], y0, My) + h;
+                lz = periodic_delta(b.c[2], z0, Mz) + h;
+            }
+            if (!ok || lx < 0 || lx > ox - 1 + 2 * h || ly < 0 || ly > oy - 1 + 2 * h || lz < 0 ||
+                lz > oz - 1 + 2 * h) {
+                const uint32_t slot = atomicAdd(&stray_n, 1u);
+                if (slot < (uint32_t)kStrayStage)
+                    stray_buf[slot] = p;
+                else
+                    strays[1 + atomicAdd(strays, 1u)] = p;       // stage full: direct append
+                continue;
+            }
+            // corner weights from two products: with w0 = 2^S - w1 per axis,
+            // W(0, ., .) = 2^S W_yz - W(1, ., .), and likewise along y and z
+            const uint64_t yz11 = (uint64_t)b.q[1] * b.q[2];
+            const uint64_t yz01 = ((uint64_t)b.q[2] << HPF_FIX_BITS) - yz11;   // wy0 wz1
+            const uint64_t yz10 = ((uint64_t)b.q[1] << HPF_FIX_BITS) - yz11;   // wy1 wz0
+            const uint64_t yz00 = ((uint64_t)kOne << HPF_FIX_BITS) - yz11 - yz01 - yz10;
+            unsigned long long* c0 = box + t * P3 + (lz * P + ly) * P + lx;
+            const uint64_t q0 = b.q[0];
+            lds_add_u64(c0, (yz00 << HPF_FIX_BITS) - yz00 * q0);
+            lds_add_u64(c0 + 1, yz00 * q0);
+            lds_add_u64(c0 + P, (yz10 << HPF_FIX_BITS) - yz10 * q0);
+            lds_add_u64(c0 + P + 1, yz10 * q0);
+            lds_add_u64(c0 + P2, (yz01 << HPF_FIX_BITS) - yz01 * q0);
+            lds_add_u64(c0 + P2 + 1, yz01 * q0);
+            lds_add_u64(c0 + P2 + P, (yz11 << HPF_FIX_BITS) - yz11 * q0);
+            lds_add_u64(c0 + P2 + P + 1, yz11 * q0);
+        }
+    }
+    __syncthreads();
+    // one global reservation per workgroup for its staged strays
+    const uint32_t nst = min(stray_n, (uint32_t)kStrayStage);
+    if (tid == 0 && nst)
+        stray_base = atomicAdd(strays, nst);
+    __syncthreads();
+    for (uint32_t i = tid; i < nst; i += kTcThreads)
+        strays[1 + stray_base + i] = stray_buf[i];
+    unsigned long long* out = partials + brick * (int64_t)nbox;
+    for (int e = tid; e < nbox; e += kTcThreads)
+        out[e] = box[e];
+}
+
+// Pass 2: one thread per mesh point sums the partial boxes that cover it and
+// stores the count. Along an axis the box of brick b spans points
+// [bB - h, bB + ob + h] (ob = the brick's width), periodically. With h < B
+// only bricks b0 - 2 .. b0 + 2 (b0 = v / B) can reach v; the +-2 ones matter
+// only next to the periodic seam when the last brick is narrower than h.
+struct Cover {
+    int n;
+    int brick[5];
+    int local[5];
+};
+
+__device__ __forceinline__ Cover covering(int v, int B, int h, int nb, int M)
+{
+    Cover c;
+    c.n = 0;
+    const int b0 = v / B;
+#pragma unroll
+    for (int db = -2; db <= 2; ++db) {
+        int b = b0 + db;
+        if (b < 0)
+            b += nb;
+        else if (b >= nb)
+            b -= nb;
+        if (b < 0 || b >= nb)
+            continue;                       // fewer than 3 bricks on this axis
+        const int ob = min(B, M - b * B);
+        int l = v - (b * B - h);
+        if (l < 0)
+            l += M;
+        else if (l >= M)
+            l -= M;
+        bool dup = false;
+        for (int i = 0; i < c.n; ++i)
+            dup |= c.brick[i] == b;
+        if (!dup && l <= ob + 2 * h) {
+            c.brick[c.n] = b;
+            c.local[c.n] = l;
+            ++c.n;
+        }
+    }
+    return c;
+}
+
+// One workgroup per brick: the cover lists of the brick's coordinates along
+// each axis are built once in LDS, then each thread sums the partial boxes for
+// its points (consecutive threads -> consecutive x -> coalesced reads).
+__global__ __launch_bounds__(256) void k_scatter_sum(const unsigned long long* __restrict__ partials,
+                                                     TileK tk, int K,
+                                                     unsigned long long* __restrict__ counts)
+{
+    __shared__ Cover cov[3][kTcMaxB];
+    const int tid = threadIdx.x;
+    const int B = tk.B, h = tk.h, P = tk.P, P3 = P * P * P;
+    const int64_t brick = xcd_block(blockIdx.x, gridDim.x);
+    const int bxyz[3] = {(int)(brick % tk.nb[0]), (int)((brick / tk.nb[0]) % tk.nb[1]),
+                         (int)(brick / ((int64_t)tk.nb[0] * tk.nb[1]))};
+    int o[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        o[d] = min(B, tk.m.M[d] - bxyz[d] * B);
+    if (tid < 3 * B) {
+        const int d = tid / B, i = tid % B;
+        if (i < o[d])
+            cov[d][i] = covering(bxyz[d] * B + i, B, h, tk.nb[d], tk.m.M[d]);
+    }
+    __syncthreads();
+    const int npts = o[0] * o[1] * o[2];
+    const int Mx = tk.m.M[0], My = tk.m.M[1];
+    for (int e = tid; e < npts; e += 256) {
+        const int ix = e % o[0], r1 = e / o[0], iy = r1 % o[1], iz = r1 / o[1];
+        const Cover& cx = cov[0][ix];
+        const Cover& cy = cov[1][iy];
+        const Cover& cz = cov[2][iz];
+        const int64_t dst = ((int64_t)(bxyz[2] * B + iz) * My + (bxyz[1] * B + iy)) * Mx + bxyz[0] * B + ix;
+        for (int k = 0; k < K; ++k) {
+            unsigned long long sum = 0;
+            for (int a = 0; a < cz.n; ++a)
+                for (int b2 = 0; b2 < cy.n; ++b2) {
+                    const int64_t row = ((int64_t)cz.brick[a] * tk.nb[1] + cy.brick[b2]) * tk.nb[0];
+                    const int loc = (cz.local[a] * P + cy.local[b2]) * P;
+                    for (int c = 0; c < cx.n; ++c)
+                        sum += partials[((row + cx.brick[c]) * K + k) * P3 + loc + cx.local[c]];
+                }
+            counts[(int64_t)k * tk.m.nm + dst] = sum;
+        }
+    }
+}
+
+__device__ __forceinline__ void atomic_add_u64_agent(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Global-atomic deposit of the stray beads and of the beads the sort could not
+// bin (storage indices [cell_start[NK], N)).
+__global__ __launch_bounds__(kTcThreads) void k_scatter_strays(const float4* __restrict__ R,
+                                                               const uint8_t* __restrict__ T, int64_t N,
+                                                               int K, MeshK m, uint32_t NK,
+                                                               const uint32_t* __restrict__ cell_start,
+                                                               const uint32_t* __restrict__ strays,
+                                                               unsigned long long* __restrict__ counts)
+{
+    const int64_t nstray = strays[0];
+    const int64_t tail0 = cell_start[NK];
+    const int64_t total = nstray + (N - tail0);
+    bool bad = false;
+    for (int64_t j = (int64_t)blockIdx.x * kTcThreads + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * kTcThreads) {
+        const int64_t p = j < nstray ? (int64_t)strays[1 + j] : tail0 + (j - nstray);
+        const float4 r = R[p];
+        const int t = T[p];
+        BeadCell b;
+        if (!(bead_cell(r, m, b) && t < K)) {
+            bad = true;
+            continue;
+        }
+        const int32_t x0 = b.c[0], x1 = next_wrap(x0, m.M[0]);
+        const int32_t y0 = b.c[1], y1 = next_wrap(y0, m.M[1]);
+        const int32_t z0 = b.c[2], z1 = next_wrap(z0, m.M[2]);
+        const uint64_t wx0 = kOne - b.q[0], wx1 = b.q[0];
+        const uint64_t wy0 = kOne - b.q[1], wy1 = b.q[1];
+        const uint64_t wz0 = kOne - b.q[2], wz1 = b.q[2];
+        unsigned long long* nk = counts + (int64_t)t * m.nm;
+        const int64_t r00 = ((int64_t)z0 * m.M[1] + y0) * m.M[0];
+        const int64_t r10 = ((int64_t)z0 * m.M[1] + y1) * m.M[0];
+        const int64_t r01 = ((int64_t)z1 * m.M[1] + y0) * m.M[0];
+        const int64_t r11 = ((int64_t)z1 * m.M[1] + y1) * m.M[0];
+        atomic_add_u64_agent(nk + r00 + x0, wx0 * wy0 * wz0);
+        atomic_add_u64_agent(nk + r00 + x1, wx1 * wy0 * wz0);
+        atomic_add_u64_agent(nk + r10 + x0, wx0 * wy1 * wz0);
+        atomic_add_u64_agent(nk + r10 + x1, wx1 * wy1 * wz0);
+        atomic_add_u64_agent(nk + r01 + x0, wx0 * wy0 * wz1);
+        atomic_add_u64_agent(nk + r01 + x1, wx1 * wy0 * wz1);
+        atomic_add_u64_agent(nk + r11 + x0, wx0 * wy1 * wz1);
+        atomic_add_u64_agent(nk + r11 + x1, wx1 * wy1 * wz1);
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+}
+
+__global__ void k_zero_u32_one(uint32_t* p) { *p = 0u; }
+
+size_t scatter_cells_smem(int K, int P)
+{
+    return sizeof(unsigned long long) * (size_t)K * P * P * P;
+}
+
+size_t scatter_cells_partials(int64_t ntiles, int K, int P)
+{
+    return sizeof(unsigned long long) * (size_t)ntiles * K * P * P * P;
+}
+
+hpf_status_t launch_scatter_cells(const float* R, const uint8_t* T, int64_t N, const TileK& tk, int K,
+                                  const uint32_t* cell_start, uint64_t* counts, uint32_t* strays,
+                                  unsigned long long* partials, hipStream_t s)
+{
+    auto* c = reinterpret_cast<unsigned long long*>(counts);
+    auto* Rp = reinterpret_cast<const float4*>(R);
+    const size_t smem = scatter_cells_smem(K, tk.P);
+    if (smem > 65536) {
+        // gfx950 has 160 KiB of LDS per CU; opt in above the 64 KiB default
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter_bricks),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+            return HPF_EINVAL;
+    }
+    hipLaunchKernelGGL(k_zero_u32_one, dim3(1), dim3(1), 0, s, strays);
+    hipLaunchKernelGGL(k_scatter_bricks, dim3((unsigned)tk.ntiles), dim3(kTcThreads), smem, s, Rp, T, K, tk,
+                       cell_start, partials, strays);
+    hipLaunchKernelGGL(k_scatter_sum, dim3((unsigned)tk.ntiles), dim3(256), 0, s, partials, tk, K, c);
+    hipLaunchKernelGGL(k_scatter_strays, dim3(512), dim3(kTcThreads), 0, s, Rp, T, N, K, tk.m, tk.NK,
+                       cell_start, strays, c);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+}  // namespace hpf

@@ -41,64 +41,50 @@ __global__ __launch_bounds__(kSortThreads) void k_copy_u32(const uint32_t* __res
         b[i] = a[i];
 }
 
+// Runs of equal keys inside a wavefront: beads arrive nearly in cell order,
+// so neighbouring lanes usually share a key. Returns the lane mask of run
+// heads; *len = length of the run this lane heads (heads only), *head = the
+// head lane of this lane's run.
+__device__ __forceinline__ void wave_runs(uint32_t key, bool active, int* head, int* len)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t prev = __shfl_up(key, 1, kWave);
+    const bool is_head = active && (lane == 0 || prev != key);
+    const uint64_t heads = __ballot(is_head);
+    const uint64_t act = __ballot(active);
+    // head of my run: highest head lane <= lane
+    const uint64_t below = heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1));
+    *head = below ? 63 - __builtin_clzll(below) : lane;
+    // run length: up to the next head or the last active lane
+    const uint64_t above = heads & ~((2ull << lane) - 1 | (lane == 63 ? ~0ull : 0ull));
+    const int next = above ? __builtin_ctzll(above) : 64 - __builtin_clzll(act);
+    *len = next - lane;
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_sort_keys(const float4* __restrict__ R, int64_t N,
                                                             SortK sk, uint32_t* __restrict__ keys,
                                                             uint32_t* __restrict__ hist)
 {
     const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
-    if (i >= N)
-        return;
-    BeadCell b;
+    const bool active = i < N;
     uint32_t key = sk.NK;
-    if (bead_cell(R[i], sk.m, b)) {
-        const int B = sk.B;
-        const uint32_t brick = ((uint32_t)(b.c[2] / B) * (uint32_t)sk.nb[1] + (uint32_t)(b.c[1] / B)) *
-                                   (uint32_t)sk.nb[0] + (uint32_t)(b.c[0] / B);
-        const uint32_t local = ((uint32_t)(b.c[2] % B) * (uint32_t)B + (uint32_t)(b.c[1] % B)) *
-                                   (uint32_t)B + (uint32_t)(b.c[0] % B);
-        key = brick * (uint32_t)(B * B * B) + local;
-    }
-    keys[i] = key;
-    atomicAdd(hist + key, 1u);
-}
-
-// Inclusive wave64 scan.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t t = __shfl_up(v, off, kWave);
-        if (lane >= off)
-            v += t;
-    }
-    return v;
-}
-
-// Exclusive block scan of one value per thread; returns the exclusive prefix
-// and the block total through *total.
-template <int NT>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total)
-{
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    const uint32_t inc = wave_incl_scan(v);
-    if (lane == kWave - 1)
-        sh[wid] = inc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < NT / kWave; ++w) {
-            const uint32_t t = sh[w];
-            sh[w] = run;
-            run += t;
+    if (active) {
+        BeadCell b;
+        if (bead_cell(R[i], sk.m, b)) {
+            const int B = sk.B;
+            const uint32_t brick = ((uint32_t)(b.c[2] / B) * (uint32_t)sk.nb[1] + (uint32_t)(b.c[1] / B)) *
+                                       (uint32_t)sk.nb[0] + (uint32_t)(b.c[0] / B);
+            const uint32_t local = ((uint32_t)(b.c[2] % B) * (uint32_t)B + (uint32_t)(b.c[1] % B)) *
+                                       (uint32_t)B + (uint32_t)(b.c[0] % B);
+            key = brick * (uint32_t)(B * B * B) + local;
         }
-        sh[NT / kWave] = run;
+        keys[i] = key;
     }
-    __syncthreads();
-    const uint32_t r = sh[wid] + inc - v;
-    *total = sh[NT / kWave];
-    __syncthreads();
-    return r;
+    int head, len;
+    wave_runs(key, active, &head, &len);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (active && head == lane)
+        atomicAdd(hist + key, (uint32_t)len);
 }
 
 // Per-tile exclusive scan in place; tile totals to tile_sums.
@@ -155,23 +141,38 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_add(uint32_t* __restrict_
         a[i] += tile_sums[i / kScanTile];
 }
 
+// Placement: each run of equal keys in a wavefront reserves its slots with
+// one atomic; tags travel with the permutation so the in-cell sort reads
+// them contiguously.
 __global__ __launch_bounds__(kSortThreads) void k_sort_place(const uint32_t* __restrict__ keys, int64_t N,
+                                                             const int32_t* __restrict__ tag,
                                                              uint32_t* __restrict__ cursor,
-                                                             int32_t* __restrict__ perm)
+                                                             int32_t* __restrict__ perm,
+                                                             int32_t* __restrict__ ptag)
 {
     const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
-    if (i >= N)
-        return;
-    const uint32_t pos = atomicAdd(cursor + keys[i], 1u);
-    perm[pos] = (int32_t)i;
+    const bool active = i < N;
+    const uint32_t key = active ? keys[i] : 0xffffffffu;
+    int head, len;
+    wave_runs(key, active, &head, &len);
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t base = 0;
+    if (active && head == lane)
+        base = atomicAdd(cursor + key, (uint32_t)len);
+    base = __shfl(base, head, kWave);
+    if (active) {
+        const uint32_t pos = base + (uint32_t)(lane - head);
+        perm[pos] = (int32_t)i;
+        ptag[pos] = tag ? tag[i] : (int32_t)i;
+    }
 }
 
-// Sort every key's segment of perm by tag (by input index when there are no
-// tags); insertion sort, segments are a few beads long. Longer segments keep
-// their placement order and raise a flag.
+// Sort every key's segment of (perm, ptag) by tag (by input index when there
+// are no tags); insertion sort over contiguous entries, segments are a few
+// beads long. Longer segments keep their placement order and raise a flag.
 __global__ __launch_bounds__(kSortThreads) void k_sort_segments(const uint32_t* __restrict__ start,
                                                                 int64_t nseg,
-                                                                const int32_t* __restrict__ tag,
+                                                                int32_t* __restrict__ ptag,
                                                                 int32_t* __restrict__ perm)
 {
     const int64_t k = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
@@ -185,18 +186,22 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_segments(const uint32_t* 
         raise_flag(HPF_FLAG_SORT_ORDER);
         return;
     }
+    bool sorted = true;
+    for (uint32_t i = a + 1; i < b; ++i)
+        sorted &= ptag[i - 1] <= ptag[i];
+    if (sorted)
+        return;
     for (uint32_t i = a + 1; i < b; ++i) {
         const int32_t pi = perm[i];
-        const int32_t ti = tag ? tag[pi] : pi;
+        const int32_t ti = ptag[i];
         uint32_t j = i;
-        while (j > a) {
-            const int32_t pj = perm[j - 1];
-            if ((tag ? tag[pj] : pj) <= ti)
-                break;
-            perm[j] = pj;
+        while (j > a && ptag[j - 1] > ti) {
+            perm[j] = perm[j - 1];
+            ptag[j] = ptag[j - 1];
             --j;
         }
         perm[j] = pi;
+        ptag[j] = ti;
     }
 }
 
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_bonds(const int32_t* __re
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool sort_layout(int64_t N, const int32_t M[3], int B, SortK* sk_out, size_t* bytes,
-                 size_t off[6])
+                 size_t off[7])
 {
     if (B == 0)
         B = 8;
@@ -279,6 +284,7 @@ bool sort_layout(int64_t N, const int32_t M[3], int B, SortK* sk_out, size_t* by
     off[3] = o; o += align_up(sizeof(uint32_t) * (size_t)nscan);              // start
     off[4] = o; o += align_up(sizeof(uint32_t) * (size_t)nscan);              // cursor
     off[5] = o; o += align_up(sizeof(uint32_t) * (size_t)ntiles);             // tile sums
+    off[6] = o; o += align_up(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));     // tags in perm order
     *bytes = o;
     return true;
 }
@@ -288,7 +294,7 @@ static unsigned grid_for(int64_t n) { return (unsigned)((n + kSortThreads - 1) /
 hpf_status_t launch_sort(const SortK& sk, int64_t N, const float* R_in, const float* V_in,
                          const uint8_t* T_in, const int32_t* tag_in, const int32_t* bonds_in, int D,
                          float* R_out, float* V_out, uint8_t* T_out, int32_t* tag_out,
-                         int32_t* bonds_out, uint32_t* cell_start, char* work, const size_t off[6],
+                         int32_t* bonds_out, uint32_t* cell_start, char* work, const size_t off[7],
                          hipStream_t s)
 {
     uint32_t* keys = reinterpret_cast<uint32_t*>(work + off[0]);
@@ -297,6 +303,7 @@ hpf_status_t launch_sort(const SortK& sk, int64_t N, const float* R_in, const fl
     uint32_t* start = cell_start ? cell_start : reinterpret_cast<uint32_t*>(work + off[3]);
     uint32_t* cursor = reinterpret_cast<uint32_t*>(work + off[4]);
     uint32_t* tiles = reinterpret_cast<uint32_t*>(work + off[5]);
+    int32_t* ptag = reinterpret_cast<int32_t*>(work + off[6]);
     const int64_t nscan = (int64_t)sk.NK + 2;
     const int64_t ntiles = (nscan + kScanTile - 1) / kScanTile;
     const unsigned gfill = (unsigned)std::min<int64_t>(grid_for(nscan), 4096);
@@ -313,9 +320,9 @@ hpf_status_t launch_sort(const SortK& sk, int64_t N, const float* R_in, const fl
     if (N > 0) {
         hipLaunchKernelGGL(k_copy_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, cursor, nscan);
         hipLaunchKernelGGL(k_sort_place, dim3(grid_for(N)), dim3(kSortThreads), 0, s, keys, N,
-                           cursor, perm);
+                           tag_in, cursor, perm, ptag);
         hipLaunchKernelGGL(k_sort_segments, dim3(grid_for(nscan - 1)), dim3(kSortThreads), 0, s,
-                           start, nscan - 1, tag_in, perm);
+                           start, nscan - 1, ptag, perm);
         hipLaunchKernelGGL(k_sort_permute, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, N,
                            reinterpret_cast<const float4*>(R_in), reinterpret_cast<const float4*>(V_in),
                            T_in, tag_in, reinterpret_cast<float4*>(R_out),

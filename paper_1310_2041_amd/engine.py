@@ -28,7 +28,7 @@ class HpfState:
     """One periodic system on the GPU: beads, bond table, mesh buffers."""
 
     def __init__(self, R, Vel, T, tag, bonds, L, M, K, kT, inv_kappa, chi, k_bond, r0, dt,
-                 device="cuda", sort_brick=8):
+                 device="cuda", sort_brick=8, halo=1):
         dev = torch.device(device)
         self.N = int(R.shape[0])
         self.K = int(K)
@@ -40,6 +40,8 @@ class HpfState:
         self.field = hpf.make_field(self.K, kT, inv_kappa, chi)
         self.box = self.L
         self.B = int(sort_brick)
+        self.halo = int(halo)
+        self.sorted = False      # storage order comes from hpf_sort_by_cell
         nm = self.mesh.M[0] * self.mesh.M[1] * self.mesh.M[2]
         self.nm = nm
 
@@ -63,6 +65,10 @@ class HpfState:
                                 dtype=torch.uint8, device=dev)
         self.cell_start = torch.empty(hpf.sort_key_count(self.mesh, self.B) + 2,
                                       dtype=torch.int32, device=dev)
+        # the cell-list scatter needs every mesh edge >= B + 1 + 2*halo (0 bytes = unsupported)
+        ws = hpf.hpf_scatter_workspace_bytes(self.N, self.mesh, self.K, self.B, self.halo)
+        self.cells_ok = ws > 0
+        self.scatter_work = torch.empty(max(ws, 1), dtype=torch.uint8, device=dev)
         # mesh buffers; counts start at zero and are cleared by the potential pass
         self.counts = torch.zeros((self.K, nm), dtype=torch.int64, device=dev)
         self.V = torch.empty((self.K, nm), dtype=torch.float32, device=dev)
@@ -89,10 +95,19 @@ class HpfState:
         self.T, self.T2 = self.T2, self.T
         self.tag, self.tag2 = self.tag2, self.tag
         self.bonds, self.bonds2 = self.bonds2, self.bonds
+        self.sorted = True
+
+    def scatter(self, stream=None):
+        """Density counts: cell-list owner tiles when sorted, else the generic scatter."""
+        if self.sorted and self.cells_ok:
+            hpf.hpf_density_scatter_cells(self.R, self.T, self.mesh, self.K, self.cell_start, self.B,
+                                          self.halo, self.counts, self.scatter_work, stream)
+        else:
+            hpf.hpf_density_scatter(self.R, self.T, self.mesh, self.K, self.counts, stream)
 
     def field_forces(self, report=False, stream=None):
         """F = field force (scatter, potential, gradient, gather)."""
-        hpf.hpf_density_scatter(self.R, self.T, self.mesh, self.K, self.counts, stream)
+        self.scatter(stream)
         hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V,
                                 self.part[ROW_W] if report else None, stream)
         hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)

@@ -57,6 +57,10 @@ _SIGNATURES = {
     "hpf_status_string": ([C.c_int32], C.c_char_p),
     "hpf_mesh_make": ([_P, _P, C.c_int64, C.POINTER(Mesh)], C.c_int32),
     "hpf_density_scatter": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P], C.c_int32),
+    "hpf_scatter_workspace_bytes": ([C.c_int64, C.POINTER(Mesh), C.c_int32, C.c_int32, C.c_int32],
+                                    C.c_size_t),
+    "hpf_density_scatter_cells": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, C.c_int32,
+                                   C.c_int32, _P, _P, C.c_size_t, _P], C.c_int32),
     "hpf_field_potential": ([_P, C.POINTER(Mesh), C.POINTER(Field), _P, _P, _P], C.c_int32),
     "hpf_field_gradient": ([_P, C.POINTER(Mesh), C.c_int32, _P, _P], C.c_int32),
     "hpf_force_gather": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, _P], C.c_int32),
@@ -165,6 +169,24 @@ def hpf_density_scatter(R, T, mesh: Mesh, K: int, counts, stream=None):
     c = _dev(counts, "counts", _U64, (K, _nm(mesh)))
     _check("hpf_density_scatter",
            lib().hpf_density_scatter(r, t, N, C.byref(mesh), K, c, _stream(stream)))
+
+
+def hpf_scatter_workspace_bytes(N: int, mesh: Mesh, K: int, B: int = 8, halo: int = 1) -> int:
+    """Workspace of hpf_density_scatter_cells; 0 when the sizes are not supported."""
+    return int(lib().hpf_scatter_workspace_bytes(int(N), C.byref(mesh), int(K), int(B), int(halo)))
+
+
+def hpf_density_scatter_cells(R, T, mesh: Mesh, K: int, cell_start, B: int, halo: int, counts, work,
+                              stream=None):
+    N = R.shape[0]
+    r = _dev(R, "R", torch.float32, (N, 4))
+    t = _dev(T, "T", torch.uint8, (N,))
+    cs = _dev(cell_start, "cell_start", torch.int32, (sort_key_count(mesh, B) + 2,))
+    c = _dev(counts, "counts", _U64, (K, _nm(mesh)))
+    w = _dev(work, "work", (torch.uint8, torch.int32))
+    _check("hpf_density_scatter_cells",
+           lib().hpf_density_scatter_cells(r, t, N, C.byref(mesh), K, cs, int(B), int(halo), c, w,
+                                           work.numel() * work.element_size(), _stream(stream)))
 
 
 def hpf_field_potential(counts, mesh: Mesh, field: Field, V, w_part=None, stream=None):
