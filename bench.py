@@ -35,6 +35,8 @@ def algorithmic_bytes(name: str, N: int, K: int, nm: int, D: int) -> float:
         "force_gather": 33.0 * N + 16.0 * K * nm,    # R, T read; F written; G read once
         "bond_forces": (48.0 + 4.0 * D) * N,         # R, bond table, F read; F written
         "verlet_half2": 48.0 * N,                    # Vel read+write; F read
+        # R, Vel, T, bond table read; R_next, Vel written; G read once
+        "advance": (65.0 + 4.0 * D) * N + 16.0 * K * nm,
         "reduce": 6 * 1024 * 8.0,
     }[name]
 
@@ -81,7 +83,22 @@ def timed_step(st, hpf, engine, tm, sort):
     st.steps_done += 1
 
 
-def run_workload(cfg, steps, warmup, sort_every, instrument=True):
+def timed_step_fused(st, hpf, engine, tm, sort):
+    if sort:
+        tm.wrap("sort_by_cell", st.sort)
+    tm.wrap("density_scatter", st.scatter)
+    tm.wrap("field_potential", hpf.hpf_field_potential, st.counts, st.mesh, st.field, st.V,
+            st.part[engine.ROW_W])
+    tm.wrap("field_gradient", hpf.hpf_field_gradient, st.V, st.mesh, st.K, st.G)
+    tm.wrap("advance", hpf.hpf_advance, st.R, st.R2, st.Vel, st.T, st.mesh, st.K, st.G, st.bonds,
+            st.k_bond, st.r0, st.box, st.dt, e_part=st.part[engine.ROW_EB],
+            kin_part=st.part[engine.ROW_KE:engine.ROW_KE + 4])
+    st.R, st.R2 = st.R2, st.R
+    tm.wrap("reduce", hpf.hpf_reduce_partials, st.part, engine.N_ROWS, st.energy)
+    st.steps_done += 1
+
+
+def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True):
     import torch
 
     from paper_1310_2041_amd import engine, hpf
@@ -92,8 +109,11 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True):
     st = engine.HpfState.from_system(s)
     del s
     st.start(sort=True)
+    if fused:
+        st.prime()
+    step = st.step_fused if fused else st.step
     for _ in range(warmup):
-        st.step(report=True, sort=sort_every > 0 and st.steps_done % sort_every == 0)
+        step(report=True, sort=sort_every > 0 and st.steps_done % sort_every == 0)
     torch.cuda.synchronize()
     tm = Timers(torch)
     t0 = torch.cuda.Event(enable_timing=True)
@@ -103,9 +123,9 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True):
     for _ in range(steps):
         do_sort = sort_every > 0 and st.steps_done % sort_every == 0
         if instrument:
-            timed_step(st, hpf, engine, tm, do_sort)
+            (timed_step_fused if fused else timed_step)(st, hpf, engine, tm, do_sort)
         else:
-            st.step(report=True, sort=do_sort)
+            step(report=True, sort=do_sort)
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -144,6 +164,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--also", default="c2", help="second workload reported under 'also' ('' = none)")
     ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--mode", default="fused", choices=["fused", "api"],
+                    help="fused: hpf_advance; api: the six separate calls")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -158,7 +180,8 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
 
-    r = run_workload(args.config, args.steps, args.warmup, args.sort_every)
+    fused = args.mode == "fused"
+    r = run_workload(args.config, args.steps, args.warmup, args.sort_every, fused=fused)
     ms_step = r["ms_total"] / args.steps
     value = r["N"] * args.steps / (r["ms_total"] * 1e-3)
     kern = r["kernels"]
@@ -189,7 +212,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": r["spec"].name, "beads": r["N"], "species": r["K"],
                    "mesh": [r["spec"].M] * 3, "box": r["spec"].L, "sort_every": args.sort_every,
-                   "energy_report_every": 1, "parallelism": "single-gpu"},
+                   "energy_report_every": 1, "step": args.mode, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None},
@@ -197,7 +220,8 @@ def main():
         "device_flags": r["flags"],
     }
     if args.also and args.also != args.config:
-        r2 = run_workload(args.also, args.steps, args.warmup, args.sort_every, instrument=False)
+        r2 = run_workload(args.also, args.steps, args.warmup, args.sort_every, instrument=False,
+                          fused=fused)
         out["also"] = {"workload": r2["spec"].name, "beads": r2["N"],
                        "value": r2["N"] * args.steps / (r2["ms_total"] * 1e-3),
                        "ms_per_step": r2["ms_total"] / args.steps,

@@ -46,7 +46,7 @@ extern "C" {
 #define HPF_ABI_VERSION 1
 #define HPF_FIX_BITS 16     /* S: fractional bits of a 1-D cloud-in-cell weight */
 #define HPF_MAX_TYPES 8     /* K <= 8 species */
-#define HPF_NPART 1024      /* slots per component of an FP64 partial-sum buffer */
+#define HPF_NPART 4096      /* slots per component of an FP64 partial-sum buffer */
 #define HPF_MAX_BONDS 16    /* D <= 16 bond-table rows */
 
 typedef int32_t hpf_status_t;
@@ -236,6 +236,33 @@ hpf_status_t bond_forces(const float* R, int64_t N, const int32_t* bonds, int32_
 hpf_status_t verlet_step(float* R, float* Vel, const float* F, const float* inv_mass,
                          int64_t N, float dt, const float* box, int32_t half,
                          double* kin_part, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * hpf_advance -- one fused pass over the beads that produces exactly the
+ * results of this call sequence (bit for bit):
+ *     hpf_force_gather(R, ..., F); bond_forces(R, ..., F, e_part);
+ *     verlet_step(half = 2, kin_part); verlet_step(half = 1)
+ * i.e. the field force (eq. 6) and bond forces (eq. 7) at x_n, the second
+ * half kick of step n (kinetic-energy and momentum partials at v_n) and the
+ * first half kick and drift of step n + 1 (Integration methods section).
+ *
+ * R       float[N][4] device, x_n, read only (bond partners are read here).
+ * R_next  float[N][4] device, receives x_{n+1} wrapped into the box; must not
+ *         alias R.
+ * Vel     float[N][4] device, v_{n-1/2} in, v_{n+1/2} out.
+ * G       float[K][M^3][4] device, the gradient mesh of x_n.
+ * bonds, D, k, r0, box, inv_mass, dt: as in bond_forces / verlet_step.
+ * F_out   nullable float[N][4] device: receives the total force at x_n.
+ * e_part  nullable double[HPF_NPART]; kin_part nullable double[4][HPF_NPART]:
+ *         as in bond_forces and verlet_step(half = 2).
+ * Sets HPF_FLAG_BAD_BEAD / HPF_FLAG_BAD_BOND / HPF_FLAG_NONFINITE like the
+ * separate calls.
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_advance(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
+                         const hpf_mesh_t* mesh, int32_t K, const float* G, const int32_t* bonds,
+                         int32_t D, float k, float r0, const float* box, const float* inv_mass,
+                         float dt, float* F_out, double* e_part, double* kin_part,
+                         void* stream);
 
 /* Deterministic FP64 reduction of partial-sum buffers: out[c] = sum of
  * part[c*HPF_NPART .. (c+1)*HPF_NPART) in a fixed tree order, c < ncomp.

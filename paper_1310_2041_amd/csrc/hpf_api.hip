@@ -239,6 +239,26 @@ hpf_status_t verlet_step(float* R, float* Vel, const float* F, const float* inv_
     return launch_verlet(R, Vel, F, inv_mass, N, dt, b, half, kin_part, as_stream(stream));
 }
 
+hpf_status_t hpf_advance(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
+                         const hpf_mesh_t* mesh, int32_t K, const float* G, const int32_t* bonds, int32_t D,
+                         float k, float r0, const float* box, const float* inv_mass, float dt, float* F_out,
+                         double* e_part, double* kin_part, void* stream)
+{
+    if (N < 0 || N > 0x7fffffffLL || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES || D < 0 ||
+        D > HPF_MAX_BONDS || !box_ok(box) || !std::isfinite(k) || !std::isfinite(r0) || !(dt > 0.0f) ||
+        !std::isfinite(dt))
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !R_next || !Vel || !T || !G || (D > 0 && !bonds) || R == R_next))
+        return HPF_EINVAL;
+    BoxK b;
+    for (int d = 0; d < 3; ++d) {
+        b.L[d] = box[d];
+        b.halfL[d] = 0.5f * box[d];
+    }
+    return launch_advance(R, R_next, Vel, T, N, mesh_k(mesh), K, G, bonds, D, k, r0, b, inv_mass, dt, F_out,
+                          e_part, kin_part, as_stream(stream));
+}
+
 hpf_status_t hpf_reduce_partials(const double* part, int32_t ncomp, double* out, void* stream)
 {
     if (!part || !out || ncomp < 1 || ncomp > 8)

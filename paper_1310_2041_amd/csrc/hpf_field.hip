@@ -28,6 +28,9 @@ __global__ __launch_bounds__(kPotThreads) void k_field_potential(unsigned long l
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
     double wsum = 0.0;
     bool over = false;
+    if (w_part && blockIdx.x == 0)                 // slots beyond this grid read as zero
+        for (int i = gridDim.x + threadIdx.x; i < HPF_NPART; i += kPotThreads)
+            w_part[i] = 0.0;
     for (int64_t v = b * kPotThreads + threadIdx.x; v < nm; v += (int64_t)gridDim.x * kPotThreads) {
         double phi[K];
         double tot = 0.0;
@@ -67,8 +70,9 @@ hpf_status_t launch_field_potential(uint64_t* counts, const MeshK& m, int K, con
                                     float* V, double* w_part, hipStream_t s)
 {
     int64_t nb = (m.nm + kPotThreads - 1) / kPotThreads;
-    if (w_part || nb > 8192)
-        nb = w_part ? HPF_NPART : 8192;
+    const int64_t cap = w_part ? HPF_NPART : 8192;
+    if (nb > cap)
+        nb = cap;
     auto* c = reinterpret_cast<unsigned long long*>(counts);
     const dim3 g((unsigned)nb), bl(kPotThreads);
     switch (K) {

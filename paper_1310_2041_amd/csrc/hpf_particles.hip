@@ -1,8 +1,12 @@
 // Per-bead kernels: force interpolation from the gradient mesh (eq. 6,
-// Algorithm 1 Kernel 4), harmonic bonds (eq. 7) and the two half steps of
-// velocity Verlet. One thread per bead; each workgroup walks a contiguous
-// range of beads, and ranges are laid out so that consecutive ranges run on
-// the same XCD (cell-sorted beads then share that XCD's L2 for mesh reads).
+// Algorithm 1 Kernel 4), harmonic bonds (eq. 7), the two half steps of
+// velocity Verlet, and a fused kernel that runs all of them in one pass.
+//
+// One thread per bead; each workgroup walks a contiguous range of beads, and
+// ranges are laid out so that consecutive ranges run on the same XCD
+// (cell-sorted beads then share that XCD's L2 for mesh and partner reads).
+// The separate kernels and the fused one call the same device functions in
+// the same order, so they produce bitwise identical results.
 #include "hpf_common.hpp"
 
 namespace hpf {
@@ -26,7 +30,159 @@ __device__ __forceinline__ Range block_range(int64_t N)
     return r;
 }
 
-// ---------------------------------------------------------------- gather ---
+// Partial-sum slots beyond the launched grid are cleared by block 0, so a
+// reduction over all HPF_NPART slots sees only this launch's sums.
+__device__ __forceinline__ void clear_unused_slots(double* part, int rows)
+{
+    if (part && blockIdx.x == 0)
+        for (int r = 0; r < rows; ++r)
+            for (int i = gridDim.x + threadIdx.x; i < HPF_NPART; i += kPThreads)
+                part[r * HPF_NPART + i] = 0.0;
+}
+
+struct BoxK {
+    float L[3];
+    float halfL[3];
+};
+
+// ------------------------------------------------------- device functions --
+
+// Field force on one bead: -sum_a (W_a / 2^48) G_t(c + a), separable
+// trilinear interpolation with the exact FP32 dyadic 1-D weights.
+__device__ __forceinline__ bool field_force(const float4& r, int t, const MeshK& m, int K,
+                                            const float4* __restrict__ G, float3& f)
+{
+    BeadCell b;
+    f = make_float3(0.0f, 0.0f, 0.0f);
+    if (!(bead_cell(r, m, b) && t < K))
+        return false;
+    const float4* Gk = G + t * m.nm;
+    const int32_t Mx = m.M[0], My = m.M[1], Mz = m.M[2];
+    const int32_t x0 = b.c[0], x1 = next_wrap(x0, Mx);
+    const int32_t y0 = b.c[1], y1 = next_wrap(y0, My);
+    const int32_t z0 = b.c[2], z1 = next_wrap(z0, Mz);
+    const int64_t r00 = ((int64_t)z0 * My + y0) * Mx, r10 = ((int64_t)z0 * My + y1) * Mx;
+    const int64_t r01 = ((int64_t)z1 * My + y0) * Mx, r11 = ((int64_t)z1 * My + y1) * Mx;
+    const float4 g000 = Gk[r00 + x0], g100 = Gk[r00 + x1];
+    const float4 g010 = Gk[r10 + x0], g110 = Gk[r10 + x1];
+    const float4 g001 = Gk[r01 + x0], g101 = Gk[r01 + x1];
+    const float4 g011 = Gk[r11 + x0], g111 = Gk[r11 + x1];
+    const float ax1 = (float)b.q[0] * kInvOne, ax0 = (float)(kOne - b.q[0]) * kInvOne;
+    const float ay1 = (float)b.q[1] * kInvOne, ay0 = (float)(kOne - b.q[1]) * kInvOne;
+    const float az1 = (float)b.q[2] * kInvOne, az0 = (float)(kOne - b.q[2]) * kInvOne;
+    float3 e00, e10, e01, e11, f0, f1;
+    e00.x = ax0 * g000.x + ax1 * g100.x;
+    e00.y = ax0 * g000.y + ax1 * g100.y;
+    e00.z = ax0 * g000.z + ax1 * g100.z;
+    e10.x = ax0 * g010.x + ax1 * g110.x;
+    e10.y = ax0 * g010.y + ax1 * g110.y;
+    e10.z = ax0 * g010.z + ax1 * g110.z;
+    e01.x = ax0 * g001.x + ax1 * g101.x;
+    e01.y = ax0 * g001.y + ax1 * g101.y;
+    e01.z = ax0 * g001.z + ax1 * g101.z;
+    e11.x = ax0 * g011.x + ax1 * g111.x;
+    e11.y = ax0 * g011.y + ax1 * g111.y;
+    e11.z = ax0 * g011.z + ax1 * g111.z;
+    f0.x = ay0 * e00.x + ay1 * e10.x;
+    f0.y = ay0 * e00.y + ay1 * e10.y;
+    f0.z = ay0 * e00.z + ay1 * e10.z;
+    f1.x = ay0 * e01.x + ay1 * e11.x;
+    f1.y = ay0 * e01.y + ay1 * e11.y;
+    f1.z = ay0 * e01.z + ay1 * e11.z;
+    f.x = -(az0 * f0.x + az1 * f1.x);
+    f.y = -(az0 * f0.y + az1 * f1.y);
+    f.z = -(az0 * f0.z + az1 * f1.z);
+    return true;
+}
+
+// Sum of the harmonic bond forces on bead i over its table row, and its
+// bond energy k (r - r0)^2 summed over its bonds (FP32).
+template <bool kR0Zero>
+__device__ __forceinline__ float3 bond_sum(int64_t i, const float4& xi, const float4* __restrict__ R,
+                                           int64_t N, const int32_t* __restrict__ bonds, int D, float k,
+                                           float r0, const BoxK& box, float& ei, bool& bad)
+{
+    const float two_k = 2.0f * k;
+    float3 f = make_float3(0.0f, 0.0f, 0.0f);
+    ei = 0.0f;
+    for (int b = 0; b < D; ++b) {
+        const int32_t j = bonds[(int64_t)b * N + i];
+        if (j < 0)
+            continue;
+        if (j >= N) {
+            bad = true;
+            continue;
+        }
+        const float4 xj = R[j];
+        const float dx = min_image(xj.x, xi.x, box.L[0], box.halfL[0]);
+        const float dy = min_image(xj.y, xi.y, box.L[1], box.halfL[1]);
+        const float dz = min_image(xj.z, xi.z, box.L[2], box.halfL[2]);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        float coef;
+        if (kR0Zero) {
+            coef = two_k;
+            ei += k * r2;
+        } else {
+            const float r = sqrtf(r2);
+            const float dr = r - r0;
+            coef = r > 0.0f ? two_k * dr / r : 0.0f;
+            ei += k * dr * dr;
+        }
+        f.x += coef * dx;
+        f.y += coef * dy;
+        f.z += coef * dz;
+    }
+    return f;
+}
+
+__device__ __forceinline__ void kick(float4& v, const float4& f, float im, float hdt)
+{
+    v.x += hdt * (f.x * im);
+    v.y += hdt * (f.y * im);
+    v.z += hdt * (f.z * im);
+    v.w = 0.0f;
+}
+
+__device__ __forceinline__ void drift(float4& r, const float4& v, float dt, const BoxK& box)
+{
+    r.x = wrap_coord(r.x + dt * v.x, box.L[0]);
+    r.y = wrap_coord(r.y + dt * v.y, box.L[1]);
+    r.z = wrap_coord(r.z + dt * v.z, box.L[2]);
+    r.w = 0.0f;
+}
+
+__device__ __forceinline__ bool finite4(const float4& a)
+{
+    return isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
+}
+
+struct KinAcc {
+    double ke = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+    __device__ __forceinline__ void add(const float4& v, float im)
+    {
+        const double mass = 1.0 / (double)im;
+        const double vx = v.x, vy = v.y, vz = v.z;
+        ke += 0.5 * mass * (vx * vx + vy * vy + vz * vz);
+        px += mass * vx;
+        py += mass * vy;
+        pz += mass * vz;
+    }
+    __device__ __forceinline__ void store(double* part, int64_t slot, double* scratch)
+    {
+        const double a = block_sum(ke, scratch);
+        const double b = block_sum(px, scratch);
+        const double c = block_sum(py, scratch);
+        const double d = block_sum(pz, scratch);
+        if (threadIdx.x == 0) {
+            part[0 * HPF_NPART + slot] = a;
+            part[1 * HPF_NPART + slot] = b;
+            part[2 * HPF_NPART + slot] = c;
+            part[3 * HPF_NPART + slot] = d;
+        }
+    }
+};
+
+// ---------------------------------------------------------------- kernels --
 
 __global__ __launch_bounds__(kPThreads) void k_force_gather(const float4* __restrict__ R,
                                                             const uint8_t* __restrict__ T,
@@ -37,57 +193,161 @@ __global__ __launch_bounds__(kPThreads) void k_force_gather(const float4* __rest
     const Range rg = block_range(N);
     bool bad = false;
     for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
-        const float4 r = R[i];
-        const int t = T[i];
-        BeadCell b;
-        float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (bead_cell(r, m, b) && t < K) {
-            const float4* Gk = G + t * m.nm;
-            const int32_t Mx = m.M[0], My = m.M[1], Mz = m.M[2];
-            const int32_t x0 = b.c[0], x1 = next_wrap(x0, Mx);
-            const int32_t y0 = b.c[1], y1 = next_wrap(y0, My);
-            const int32_t z0 = b.c[2], z1 = next_wrap(z0, Mz);
-            const int64_t r00 = ((int64_t)z0 * My + y0) * Mx, r10 = ((int64_t)z0 * My + y1) * Mx;
-            const int64_t r01 = ((int64_t)z1 * My + y0) * Mx, r11 = ((int64_t)z1 * My + y1) * Mx;
-            const float4 g000 = Gk[r00 + x0], g100 = Gk[r00 + x1];
-            const float4 g010 = Gk[r10 + x0], g110 = Gk[r10 + x1];
-            const float4 g001 = Gk[r01 + x0], g101 = Gk[r01 + x1];
-            const float4 g011 = Gk[r11 + x0], g111 = Gk[r11 + x1];
-            // 1-D weights are exact FP32 dyadics (w / 2^16).
-            const float ax1 = (float)b.q[0] * kInvOne, ax0 = (float)(kOne - b.q[0]) * kInvOne;
-            const float ay1 = (float)b.q[1] * kInvOne, ay0 = (float)(kOne - b.q[1]) * kInvOne;
-            const float az1 = (float)b.q[2] * kInvOne, az0 = (float)(kOne - b.q[2]) * kInvOne;
-            // separable trilinear interpolation: x, then y, then z
-            float3 e00, e10, e01, e11, f0, f1;
-            e00.x = ax0 * g000.x + ax1 * g100.x;
-            e00.y = ax0 * g000.y + ax1 * g100.y;
-            e00.z = ax0 * g000.z + ax1 * g100.z;
-            e10.x = ax0 * g010.x + ax1 * g110.x;
-            e10.y = ax0 * g010.y + ax1 * g110.y;
-            e10.z = ax0 * g010.z + ax1 * g110.z;
-            e01.x = ax0 * g001.x + ax1 * g101.x;
-            e01.y = ax0 * g001.y + ax1 * g101.y;
-            e01.z = ax0 * g001.z + ax1 * g101.z;
-            e11.x = ax0 * g011.x + ax1 * g111.x;
-            e11.y = ax0 * g011.y + ax1 * g111.y;
-            e11.z = ax0 * g011.z + ax1 * g111.z;
-            f0.x = ay0 * e00.x + ay1 * e10.x;
-            f0.y = ay0 * e00.y + ay1 * e10.y;
-            f0.z = ay0 * e00.z + ay1 * e10.z;
-            f1.x = ay0 * e01.x + ay1 * e11.x;
-            f1.y = ay0 * e01.y + ay1 * e11.y;
-            f1.z = ay0 * e01.z + ay1 * e11.z;
-            out.x = -(az0 * f0.x + az1 * f1.x);
-            out.y = -(az0 * f0.y + az1 * f1.y);
-            out.z = -(az0 * f0.z + az1 * f1.z);
-        } else {
-            bad = true;
-        }
-        F[i] = out;
+        float3 f;
+        bad |= !field_force(R[i], T[i], m, K, G, f);
+        F[i] = make_float4(f.x, f.y, f.z, 0.0f);
     }
     if (bad)
         raise_flag(HPF_FLAG_BAD_BEAD);
 }
+
+// F_i += sum_j 2k (r - r0) d / r over the bead's own table row; E partials
+// accumulate k (r - r0)^2 / 2 per bond end (each bond is seen from both ends).
+template <bool kR0Zero>
+__global__ __launch_bounds__(kPThreads) void k_bond_forces(const float4* __restrict__ R, int64_t N,
+                                                           const int32_t* __restrict__ bonds, int D,
+                                                           float k, float r0, BoxK box,
+                                                           float4* __restrict__ F,
+                                                           double* __restrict__ e_part)
+{
+    __shared__ double scratch[kPThreads / kWave];
+    const Range rg = block_range(N);
+    clear_unused_slots(e_part, 1);
+    double e = 0.0;
+    bool bad = false;
+    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+        const float4 xi = R[i];
+        float ei;
+        const float3 fb = bond_sum<kR0Zero>(i, xi, R, N, bonds, D, k, r0, box, ei, bad);
+        float4 f = F[i];
+        f.x += fb.x;
+        f.y += fb.y;
+        f.z += fb.z;
+        F[i] = f;
+        e += 0.5 * (double)ei;
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BOND);
+    if (e_part) {
+        const double s = block_sum(e, scratch);
+        if (threadIdx.x == 0)
+            e_part[rg.block] = s;
+    }
+}
+
+__global__ __launch_bounds__(kPThreads) void k_verlet_half1(float4* __restrict__ R,
+                                                            float4* __restrict__ Vel,
+                                                            const float4* __restrict__ F,
+                                                            const float* __restrict__ inv_mass,
+                                                            int64_t N, float dt, BoxK box)
+{
+    const Range rg = block_range(N);
+    const float hdt = 0.5f * dt;
+    bool bad = false;
+    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+        const float im = inv_mass ? inv_mass[i] : 1.0f;
+        float4 v = Vel[i];
+        float4 r = R[i];
+        kick(v, F[i], im, hdt);
+        drift(r, v, dt, box);
+        bad |= !(finite4(r) && finite4(v));
+        Vel[i] = v;
+        R[i] = r;
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_NONFINITE);
+}
+
+__global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__ Vel,
+                                                            const float4* __restrict__ F,
+                                                            const float* __restrict__ inv_mass,
+                                                            int64_t N, float dt,
+                                                            double* __restrict__ kin_part)
+{
+    __shared__ double scratch[kPThreads / kWave];
+    const Range rg = block_range(N);
+    clear_unused_slots(kin_part, 4);
+    const float hdt = 0.5f * dt;
+    KinAcc acc;
+    bool bad = false;
+    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+        const float im = inv_mass ? inv_mass[i] : 1.0f;
+        float4 v = Vel[i];
+        kick(v, F[i], im, hdt);
+        bad |= !finite4(v);
+        Vel[i] = v;
+        acc.add(v, im);
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_NONFINITE);
+    if (kin_part)
+        acc.store(kin_part, rg.block, scratch);
+}
+
+// Fused pass over the beads: field force + bond forces at x_n, second half
+// kick of step n (kinetic-energy partials at v_n), first half kick and drift
+// of step n + 1. Positions go to R_next so that bond partners are always read
+// at x_n.
+template <bool kR0Zero>
+__global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict__ R,
+                                                       float4* __restrict__ R_next,
+                                                       float4* __restrict__ Vel,
+                                                       const uint8_t* __restrict__ T, int64_t N,
+                                                       MeshK m, int K, const float4* __restrict__ G,
+                                                       const int32_t* __restrict__ bonds, int D,
+                                                       float k, float r0, BoxK box,
+                                                       const float* __restrict__ inv_mass, float dt,
+                                                       float4* __restrict__ F_out,
+                                                       double* __restrict__ e_part,
+                                                       double* __restrict__ kin_part)
+{
+    __shared__ double scratch[kPThreads / kWave];
+    const Range rg = block_range(N);
+    clear_unused_slots(e_part, 1);
+    clear_unused_slots(kin_part, 4);
+    const float hdt = 0.5f * dt;
+    KinAcc acc;
+    double e = 0.0;
+    bool bad_bead = false, bad_bond = false, nonfinite = false;
+    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+        float4 r = R[i];
+        float3 ff;
+        bad_bead |= !field_force(r, T[i], m, K, G, ff);
+        float ei;
+        const float3 fb = bond_sum<kR0Zero>(i, r, R, N, bonds, D, k, r0, box, ei, bad_bond);
+        float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
+        f.x += fb.x;
+        f.y += fb.y;
+        f.z += fb.z;
+        e += 0.5 * (double)ei;
+        if (F_out)
+            F_out[i] = f;
+        const float im = inv_mass ? inv_mass[i] : 1.0f;
+        float4 v = Vel[i];
+        kick(v, f, im, hdt);                 // v_n
+        acc.add(v, im);
+        kick(v, f, im, hdt);                 // v_{n+1/2}
+        drift(r, v, dt, box);                // x_{n+1}
+        nonfinite |= !(finite4(r) && finite4(v));
+        Vel[i] = v;
+        R_next[i] = r;
+    }
+    if (bad_bead)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+    if (bad_bond)
+        raise_flag(HPF_FLAG_BAD_BOND);
+    if (nonfinite)
+        raise_flag(HPF_FLAG_NONFINITE);
+    if (e_part) {
+        const double s = block_sum(e, scratch);
+        if (threadIdx.x == 0)
+            e_part[rg.block] = s;
+    }
+    if (kin_part)
+        acc.store(kin_part, rg.block, scratch);
+}
+
+// ---------------------------------------------------------------- launches --
 
 static int64_t bead_blocks(int64_t N, int64_t cap)
 {
@@ -108,80 +368,12 @@ hpf_status_t launch_force_gather(const float* R, const uint8_t* T, int64_t N, co
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
-// ----------------------------------------------------------------- bonds ---
-
-struct BoxK {
-    float L[3];
-    float halfL[3];
-};
-
-// F_i += sum_j 2k (r - r0) d / r over the bead's own table row; E partials
-// accumulate k (r - r0)^2 / 2 per bond end (each bond is seen from both ends).
-template <bool kR0Zero>
-__global__ __launch_bounds__(kPThreads) void k_bond_forces(const float4* __restrict__ R, int64_t N,
-                                                           const int32_t* __restrict__ bonds, int D,
-                                                           float k, float r0, BoxK box,
-                                                           float4* __restrict__ F,
-                                                           double* __restrict__ e_part)
-{
-    __shared__ double scratch[kPThreads / kWave];
-    const Range rg = block_range(N);
-    const float two_k = 2.0f * k;
-    double e = 0.0;
-    bool bad = false;
-    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
-        const float4 xi = R[i];
-        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-        float ei = 0.0f;
-        for (int b = 0; b < D; ++b) {
-            const int32_t j = bonds[(int64_t)b * N + i];
-            if (j < 0)
-                continue;
-            if (j >= N) {
-                bad = true;
-                continue;
-            }
-            const float4 xj = R[j];
-            const float dx = min_image(xj.x, xi.x, box.L[0], box.halfL[0]);
-            const float dy = min_image(xj.y, xi.y, box.L[1], box.halfL[1]);
-            const float dz = min_image(xj.z, xi.z, box.L[2], box.halfL[2]);
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            float coef;
-            if (kR0Zero) {
-                coef = two_k;
-                ei += k * r2;
-            } else {
-                const float r = sqrtf(r2);
-                const float dr = r - r0;
-                coef = r > 0.0f ? two_k * dr / r : 0.0f;
-                ei += k * dr * dr;
-            }
-            fx += coef * dx;
-            fy += coef * dy;
-            fz += coef * dz;
-        }
-        float4 f = F[i];
-        f.x += fx;
-        f.y += fy;
-        f.z += fz;
-        F[i] = f;
-        e += 0.5 * (double)ei;
-    }
-    if (bad)
-        raise_flag(HPF_FLAG_BAD_BOND);
-    if (e_part) {
-        const double s = block_sum(e, scratch);
-        if (threadIdx.x == 0)
-            e_part[rg.block] = s;
-    }
-}
-
 hpf_status_t launch_bond_forces(const float* R, int64_t N, const int32_t* bonds, int D, float k,
                                 float r0, const BoxK& box, float* F, double* e_part, hipStream_t s)
 {
     if (N == 0 && !e_part)
         return HPF_OK;
-    const int64_t nb = e_part ? HPF_NPART : bead_blocks(N, 1 << 20);
+    const int64_t nb = bead_blocks(N, e_part ? HPF_NPART : (1 << 20));
     const dim3 g((unsigned)nb), bl(kPThreads);
     auto* Rp = reinterpret_cast<const float4*>(R);
     auto* Fp = reinterpret_cast<float4*>(F);
@@ -190,83 +382,6 @@ hpf_status_t launch_bond_forces(const float* R, int64_t N, const int32_t* bonds,
     else
         hipLaunchKernelGGL(k_bond_forces<false>, g, bl, 0, s, Rp, N, bonds, D, k, r0, box, Fp, e_part);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
-}
-
-// ---------------------------------------------------------------- verlet ---
-
-__global__ __launch_bounds__(kPThreads) void k_verlet_half1(float4* __restrict__ R,
-                                                            float4* __restrict__ Vel,
-                                                            const float4* __restrict__ F,
-                                                            const float* __restrict__ inv_mass,
-                                                            int64_t N, float dt, BoxK box)
-{
-    const Range rg = block_range(N);
-    const float hdt = 0.5f * dt;
-    bool bad = false;
-    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
-        const float im = inv_mass ? inv_mass[i] : 1.0f;
-        const float4 f = F[i];
-        float4 v = Vel[i];
-        float4 r = R[i];
-        v.x += hdt * (f.x * im);
-        v.y += hdt * (f.y * im);
-        v.z += hdt * (f.z * im);
-        r.x = wrap_coord(r.x + dt * v.x, box.L[0]);
-        r.y = wrap_coord(r.y + dt * v.y, box.L[1]);
-        r.z = wrap_coord(r.z + dt * v.z, box.L[2]);
-        r.w = 0.0f;
-        v.w = 0.0f;
-        bad |= !(isfinite(r.x) && isfinite(r.y) && isfinite(r.z) && isfinite(v.x) &&
-                 isfinite(v.y) && isfinite(v.z));
-        Vel[i] = v;
-        R[i] = r;
-    }
-    if (bad)
-        raise_flag(HPF_FLAG_NONFINITE);
-}
-
-__global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__ Vel,
-                                                            const float4* __restrict__ F,
-                                                            const float* __restrict__ inv_mass,
-                                                            int64_t N, float dt,
-                                                            double* __restrict__ kin_part)
-{
-    __shared__ double scratch[kPThreads / kWave];
-    const Range rg = block_range(N);
-    const float hdt = 0.5f * dt;
-    double ke = 0.0, px = 0.0, py = 0.0, pz = 0.0;
-    bool bad = false;
-    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
-        const float im = inv_mass ? inv_mass[i] : 1.0f;
-        const float4 f = F[i];
-        float4 v = Vel[i];
-        v.x += hdt * (f.x * im);
-        v.y += hdt * (f.y * im);
-        v.z += hdt * (f.z * im);
-        v.w = 0.0f;
-        bad |= !(isfinite(v.x) && isfinite(v.y) && isfinite(v.z));
-        Vel[i] = v;
-        const double mass = 1.0 / (double)im;
-        const double vx = v.x, vy = v.y, vz = v.z;
-        ke += 0.5 * mass * (vx * vx + vy * vy + vz * vz);
-        px += mass * vx;
-        py += mass * vy;
-        pz += mass * vz;
-    }
-    if (bad)
-        raise_flag(HPF_FLAG_NONFINITE);
-    if (kin_part) {
-        const double a = block_sum(ke, scratch);
-        const double b = block_sum(px, scratch);
-        const double c = block_sum(py, scratch);
-        const double d = block_sum(pz, scratch);
-        if (threadIdx.x == 0) {
-            kin_part[0 * HPF_NPART + rg.block] = a;
-            kin_part[1 * HPF_NPART + rg.block] = b;
-            kin_part[2 * HPF_NPART + rg.block] = c;
-            kin_part[3 * HPF_NPART + rg.block] = d;
-        }
-    }
 }
 
 hpf_status_t launch_verlet(float* R, float* Vel, const float* F, const float* inv_mass, int64_t N,
@@ -281,10 +396,33 @@ hpf_status_t launch_verlet(float* R, float* Vel, const float* F, const float* in
         hipLaunchKernelGGL(k_verlet_half1, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads),
                            0, s, Rp, Vp, Fp, inv_mass, N, dt, box);
     } else {
-        const int64_t nb = kin_part ? HPF_NPART : bead_blocks(N, 1 << 20);
+        const int64_t nb = bead_blocks(N, kin_part ? HPF_NPART : (1 << 20));
         hipLaunchKernelGGL(k_verlet_half2, dim3((unsigned)nb), dim3(kPThreads), 0, s, Vp, Fp,
                            inv_mass, N, dt, kin_part);
     }
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
+                            const MeshK& m, int K, const float* G, const int32_t* bonds, int D, float k,
+                            float r0, const BoxK& box, const float* inv_mass, float dt, float* F_out,
+                            double* e_part, double* kin_part, hipStream_t s)
+{
+    if (N == 0 && !e_part && !kin_part)
+        return HPF_OK;
+    const int64_t nb = bead_blocks(N, (e_part || kin_part) ? HPF_NPART : (1 << 20));
+    const dim3 g((unsigned)nb), bl(kPThreads);
+    auto* Rp = reinterpret_cast<const float4*>(R);
+    auto* Rn = reinterpret_cast<float4*>(R_next);
+    auto* Vp = reinterpret_cast<float4*>(Vel);
+    auto* Gp = reinterpret_cast<const float4*>(G);
+    auto* Fo = reinterpret_cast<float4*>(F_out);
+    if (r0 == 0.0f)
+        hipLaunchKernelGGL(k_advance<true>, g, bl, 0, s, Rp, Rn, Vp, T, N, m, K, Gp, bonds, D, k, r0, box,
+                           inv_mass, dt, Fo, e_part, kin_part);
+    else
+        hipLaunchKernelGGL(k_advance<false>, g, bl, 0, s, Rp, Rn, Vp, T, N, m, K, Gp, bonds, D, k, r0,
+                           box, inv_mass, dt, Fo, e_part, kin_part);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 

@@ -141,6 +141,41 @@ class HpfState:
                         kin_part=self.part[ROW_KE:ROW_KE + 4], stream=stream)
         hpf.hpf_reduce_partials(self.part, N_ROWS, self.energy, stream)
 
+    # ------------------------------------------------------------ fused path
+
+    def prime(self, stream=None):
+        """First half step after start(): (x_0, v_0, F_0) -> (x_1, v_1/2)."""
+        hpf.verlet_step(self.R, self.Vel, self.F, self.dt, self.box, 1, stream=stream)
+
+    def step_fused(self, report=False, sort=False, stream=None):
+        """(x_n, v_n-1/2) -> (x_n+1, v_n+1/2) with hpf_advance; energies of step n.
+
+        Bitwise equal to step() followed by the next step's first half step."""
+        if sort:
+            self.sort(stream)
+        self.scatter(stream)
+        hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V,
+                                self.part[ROW_W] if report else None, stream)
+        hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
+        hpf.hpf_advance(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G,
+                        self.bonds if self.bonds.shape[0] else None, self.k_bond, self.r0, self.box,
+                        self.dt, e_part=self.part[ROW_EB] if report else None,
+                        kin_part=self.part[ROW_KE:ROW_KE + 4] if report else None, stream=stream)
+        self.R, self.R2 = self.R2, self.R
+        if report:
+            hpf.hpf_reduce_partials(self.part, N_ROWS, self.energy, stream)
+        self.steps_done += 1
+
+    def run_fused(self, n_steps, report_every=0, sort_every=10, stream=None):
+        out = []
+        for i in range(n_steps):
+            rep = report_every > 0 and (i + 1) % report_every == 0
+            self.step_fused(report=rep, sort=sort_every > 0 and (self.steps_done % sort_every == 0),
+                            stream=stream)
+            if rep:
+                out.append(self.energies())
+        return out
+
     def energies(self) -> dict:
         """{KE, E_bond, W, E_tot, P} of the last reporting step (synchronises)."""
         e = self.energy.cpu().numpy()

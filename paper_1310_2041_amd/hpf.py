@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "hpf.h")
 
 HPF_FIX_BITS = 16
 HPF_MAX_TYPES = 8
-HPF_NPART = 1024
+HPF_NPART = 4096
 HPF_MAX_BONDS = 16
 
 HPF_FLAG_BAD_BEAD = 0x1
@@ -68,6 +68,8 @@ _SIGNATURES = {
                     C.c_int32),
     "verlet_step": ([_P, _P, _P, _P, C.c_int64, C.c_float, _P, C.c_int32, _P, _P], C.c_int32),
     "hpf_reduce_partials": ([_P, C.c_int32, _P, _P], C.c_int32),
+    "hpf_advance": ([_P, _P, _P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, C.c_int32,
+                     C.c_float, C.c_float, _P, _P, C.c_float, _P, _P, _P, _P], C.c_int32),
     "hpf_sort_workspace_bytes": ([C.c_int64, C.POINTER(Mesh), C.c_int32], C.c_size_t),
     "hpf_sort_by_cell": ([C.POINTER(Mesh), C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
                           _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int32),
@@ -241,6 +243,32 @@ def verlet_step(R, Vel, F, dt: float, box, half: int, inv_mass=None, kin_part=No
         raise ValueError("kin_part needs 4 * HPF_NPART slots")
     _check("verlet_step", lib().verlet_step(r, v, f, im, N, float(dt), _box(box), int(half), kp,
                                             _stream(stream)))
+
+
+def hpf_advance(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float, r0: float, box,
+                dt: float, inv_mass=None, F_out=None, e_part=None, kin_part=None, stream=None):
+    N = R.shape[0]
+    D = bonds.shape[0] if bonds is not None else 0
+    args = [
+        _dev(R, "R", torch.float32, (N, 4)),
+        _dev(R_next, "R_next", torch.float32, (N, 4)),
+        _dev(Vel, "Vel", torch.float32, (N, 4)),
+        _dev(T, "T", torch.uint8, (N,)),
+        N, C.byref(mesh), int(K),
+        _dev(G, "G", torch.float32, (K, _nm(mesh), 4)),
+        _dev(bonds, "bonds", torch.int32, (D, N), allow_none=True) if D else None,
+        int(D), float(k), float(r0), _box(box),
+        _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True),
+        float(dt),
+        _dev(F_out, "F_out", torch.float32, (N, 4), allow_none=True),
+        _dev(e_part, "e_part", torch.float64, None, allow_none=True),
+        _dev(kin_part, "kin_part", torch.float64, None, allow_none=True),
+    ]
+    if e_part is not None and e_part.numel() < HPF_NPART:
+        raise ValueError("e_part needs HPF_NPART slots")
+    if kin_part is not None and kin_part.numel() < 4 * HPF_NPART:
+        raise ValueError("kin_part needs 4 * HPF_NPART slots")
+    _check("hpf_advance", lib().hpf_advance(*args, _stream(stream)))
 
 
 def hpf_reduce_partials(part, ncomp: int, out, stream=None):

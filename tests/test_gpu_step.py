@@ -104,3 +104,40 @@ def test_determinism_bitwise():
     assert np.array_equal(Ea, Eb)
     for x, y in zip(a.host_beads(), b.host_beads()):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("cfg,steps,sort_every", [("c1", 30, 7), ("c2", 12, 5)])
+def test_fused_advance_equals_separate_calls_bitwise(cfg, steps, sort_every):
+    """hpf_advance reproduces gather + bonds + both half steps of the six calls bit for bit."""
+    s = wl.build(wl.SPECS[cfg])
+    a = engine.HpfState.from_system(s)
+    a.start(sort=True)
+    Ea = a.run(steps, report_every=1, sort_every=sort_every)
+    a.prime()                                  # the next step's first half
+    b = engine.HpfState.from_system(s)
+    b.start(sort=True)
+    b.prime()
+    Eb = b.run_fused(steps, report_every=1, sort_every=sort_every)
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
+    for ea, eb in zip(Ea, Eb):
+        for key in ("KE", "E_bond", "W"):
+            assert ea[key] == eb[key]
+        assert np.array_equal(ea["P"], eb["P"])
+    assert hpf.hpf_get_device_status() == 0
+
+
+def test_fused_advance_force_output_and_aliasing():
+    s = wl.build(wl.SPECS["c1"])
+    st = engine.HpfState.from_system(s)
+    st.start(sort=True)
+    F_ref = st.F.clone()                       # forces at x_0 from the separate calls
+    F_out = torch.empty_like(st.F)
+    V0 = st.Vel.clone()
+    hpf.hpf_advance(st.R, st.R2, st.Vel, st.T, st.mesh, st.K, st.G, st.bonds, st.k_bond, st.r0,
+                    st.box, st.dt, F_out=F_out)
+    assert torch.equal(F_out, F_ref)
+    with pytest.raises(hpf.HpfError):
+        hpf.hpf_advance(st.R, st.R, st.Vel, st.T, st.mesh, st.K, st.G, st.bonds, st.k_bond, st.r0,
+                        st.box, st.dt)
+    del V0
