@@ -28,8 +28,9 @@ __global__ __launch_bounds__(kPotThreads) void k_field_potential(unsigned long l
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
     double wsum = 0.0;
     bool over = false;
-    if (w_part && blockIdx.x == 0)                 // slots beyond this grid read as zero
-        for (int i = gridDim.x + threadIdx.x; i < HPF_NPART; i += kPotThreads)
+    if (w_part)                                    // slots beyond this grid read as zero
+        for (int64_t i = (int64_t)gridDim.x + blockIdx.x + (int64_t)threadIdx.x * gridDim.x; i < HPF_NPART;
+             i += (int64_t)kPotThreads * gridDim.x)
             w_part[i] = 0.0;
     for (int64_t v = b * kPotThreads + threadIdx.x; v < nm; v += (int64_t)gridDim.x * kPotThreads) {
         double phi[K];

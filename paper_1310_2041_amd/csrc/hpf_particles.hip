@@ -13,31 +13,52 @@ namespace hpf {
 
 constexpr int kPThreads = 256;
 
-struct Range {
-    int64_t begin, end;
-    int64_t block;   // logical block id (partial-sum slot)
+// Work split of a per-bead kernel. The beads are cut into 8 contiguous
+// ranges, one per XCD (workgroup b runs on XCD b % 8). Inside its range an
+// XCD's workgroups take 256-bead chunks in turn (chunk c goes to the XCD's
+// workgroup c mod n), so the chunks in flight at any moment are neighbours:
+// with cell-sorted beads the gradient mesh and bond partners they touch form
+// a compact window that stays in that XCD's L2 while it sweeps the range.
+// The partial-sum slot of a workgroup is its launch index.
+struct BeadWalk {
+    int64_t begin, end;      // this XCD's range
+    int64_t first, stride;   // first chunk start and chunk stride of this workgroup
+    int64_t block;
 };
 
-// Contiguous bead range of this workgroup when gridDim.x blocks split N beads.
-__device__ __forceinline__ Range block_range(int64_t N)
+__device__ __forceinline__ BeadWalk bead_walk(int64_t N)
 {
-    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t per = ((N + gridDim.x - 1) / gridDim.x + kPThreads - 1) / kPThreads * kPThreads;
-    Range r;
-    r.block = b;
-    r.begin = min(N, b * per);
-    r.end = min(N, r.begin + per);
-    return r;
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t ng = nb < 8 ? nb : 8;             // groups = XCDs that received workgroups
+    const int64_t g = b % ng, idx = b / ng;
+    const int64_t per_group = nb / ng + (g < nb % ng ? 1 : 0);
+    const int64_t chunk = kPThreads;
+    const int64_t nchunk = (N + chunk - 1) / chunk;
+    const int64_t c0 = nchunk * g / ng, c1 = nchunk * (g + 1) / ng;
+    BeadWalk w;
+    w.begin = min(N, c0 * chunk);
+    w.end = min(N, c1 * chunk);
+    w.first = w.begin + idx * chunk;
+    w.stride = per_group * chunk;
+    w.block = b;
+    return w;
 }
 
-// Partial-sum slots beyond the launched grid are cleared by block 0, so a
-// reduction over all HPF_NPART slots sees only this launch's sums.
+#define FOR_BEADS(w, i)                                                                   \
+    for (int64_t _c = (w).first; _c < (w).end; _c += (w).stride)                          \
+        for (int64_t i = _c + threadIdx.x; i < min(_c + (int64_t)kPThreads, (w).end); i += kPThreads)
+
+// Partial-sum slots beyond the launched grid are cleared (slot s by block
+// s mod grid), so a reduction over all HPF_NPART slots sees only this
+// launch's sums.
 __device__ __forceinline__ void clear_unused_slots(double* part, int rows)
 {
-    if (part && blockIdx.x == 0)
-        for (int r = 0; r < rows; ++r)
-            for (int i = gridDim.x + threadIdx.x; i < HPF_NPART; i += kPThreads)
-                part[r * HPF_NPART + i] = 0.0;
+    if (!part)
+        return;
+    for (int r = 0; r < rows; ++r)
+        for (int64_t i = (int64_t)gridDim.x + blockIdx.x + (int64_t)threadIdx.x * gridDim.x; i < HPF_NPART;
+             i += (int64_t)kPThreads * gridDim.x)
+            part[r * HPF_NPART + i] = 0.0;
 }
 
 struct BoxK {
@@ -190,9 +211,9 @@ __global__ __launch_bounds__(kPThreads) void k_force_gather(const float4* __rest
                                                             const float4* __restrict__ G,
                                                             float4* __restrict__ F)
 {
-    const Range rg = block_range(N);
+    const BeadWalk w = bead_walk(N);
     bool bad = false;
-    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+    FOR_BEADS(w, i) {
         float3 f;
         bad |= !field_force(R[i], T[i], m, K, G, f);
         F[i] = make_float4(f.x, f.y, f.z, 0.0f);
@@ -211,11 +232,11 @@ __global__ __launch_bounds__(kPThreads) void k_bond_forces(const float4* __restr
                                                            double* __restrict__ e_part)
 {
     __shared__ double scratch[kPThreads / kWave];
-    const Range rg = block_range(N);
+    const BeadWalk w = bead_walk(N);
     clear_unused_slots(e_part, 1);
     double e = 0.0;
     bool bad = false;
-    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+    FOR_BEADS(w, i) {
         const float4 xi = R[i];
         float ei;
         const float3 fb = bond_sum<kR0Zero>(i, xi, R, N, bonds, D, k, r0, box, ei, bad);
@@ -231,7 +252,7 @@ __global__ __launch_bounds__(kPThreads) void k_bond_forces(const float4* __restr
     if (e_part) {
         const double s = block_sum(e, scratch);
         if (threadIdx.x == 0)
-            e_part[rg.block] = s;
+            e_part[w.block] = s;
     }
 }
 
@@ -241,10 +262,10 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half1(float4* __restrict__
                                                             const float* __restrict__ inv_mass,
                                                             int64_t N, float dt, BoxK box)
 {
-    const Range rg = block_range(N);
+    const BeadWalk w = bead_walk(N);
     const float hdt = 0.5f * dt;
     bool bad = false;
-    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+    FOR_BEADS(w, i) {
         const float im = inv_mass ? inv_mass[i] : 1.0f;
         float4 v = Vel[i];
         float4 r = R[i];
@@ -265,12 +286,12 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__
                                                             double* __restrict__ kin_part)
 {
     __shared__ double scratch[kPThreads / kWave];
-    const Range rg = block_range(N);
+    const BeadWalk w = bead_walk(N);
     clear_unused_slots(kin_part, 4);
     const float hdt = 0.5f * dt;
     KinAcc acc;
     bool bad = false;
-    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+    FOR_BEADS(w, i) {
         const float im = inv_mass ? inv_mass[i] : 1.0f;
         float4 v = Vel[i];
         kick(v, F[i], im, hdt);
@@ -281,7 +302,7 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__
     if (bad)
         raise_flag(HPF_FLAG_NONFINITE);
     if (kin_part)
-        acc.store(kin_part, rg.block, scratch);
+        acc.store(kin_part, w.block, scratch);
 }
 
 // Fused pass over the beads: field force + bond forces at x_n, second half
@@ -302,14 +323,14 @@ __global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict_
                                                        double* __restrict__ kin_part)
 {
     __shared__ double scratch[kPThreads / kWave];
-    const Range rg = block_range(N);
+    const BeadWalk w = bead_walk(N);
     clear_unused_slots(e_part, 1);
     clear_unused_slots(kin_part, 4);
     const float hdt = 0.5f * dt;
     KinAcc acc;
     double e = 0.0;
     bool bad_bead = false, bad_bond = false, nonfinite = false;
-    for (int64_t i = rg.begin + threadIdx.x; i < rg.end; i += kPThreads) {
+    FOR_BEADS(w, i) {
         float4 r = R[i];
         float3 ff;
         bad_bead |= !field_force(r, T[i], m, K, G, ff);
@@ -341,10 +362,10 @@ __global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict_
     if (e_part) {
         const double s = block_sum(e, scratch);
         if (threadIdx.x == 0)
-            e_part[rg.block] = s;
+            e_part[w.block] = s;
     }
     if (kin_part)
-        acc.store(kin_part, rg.block, scratch);
+        acc.store(kin_part, w.block, scratch);
 }
 
 // ---------------------------------------------------------------- launches --

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_keys(const float4* __rest
                                                             SortK sk, uint32_t* __restrict__ keys,
                                                             uint32_t* __restrict__ hist)
 {
-    const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
     const bool active = i < N;
     uint32_t key = sk.NK;
     if (active) {
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_place(const uint32_t* __r
                                                              int32_t* __restrict__ perm,
                                                              int32_t* __restrict__ ptag)
 {
-    const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
     const bool active = i < N;
     const uint32_t key = active ? keys[i] : 0xffffffffu;
     int head, len;
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_permute(const int32_t* __
                                                                int32_t* __restrict__ tag_out,
                                                                int32_t* __restrict__ inv)
 {
-    const int64_t p = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    const int64_t p = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
     if (p >= N)
         return;
     const int32_t o = perm[p];
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_bonds(const int32_t* __re
                                                              const int32_t* __restrict__ bonds_in, int D,
                                                              int32_t* __restrict__ bonds_out)
 {
-    const int64_t p = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    const int64_t p = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
     if (p >= N)
         return;
     const int32_t o = perm[p];

@@ -269,3 +269,38 @@ def test_sort_is_canonical_for_any_input_order():
     b.sort()
     for x, y in zip(a.host_beads(), b.host_beads()):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("n_chains,chain_len", [(1, 1), (1, 3), (7, 5), (300, 7), (1100, 20)])
+def test_per_bead_kernels_ragged_sizes(n_chains, chain_len):
+    """Tiny and ragged bead counts through gather, bonds, Verlet and the fused pass."""
+    s = wl.small_system(n_chains, chain_len, 9.0, 9, seed=n_chains + chain_len)
+    rng = np.random.default_rng(1)
+    nm = 9 ** 3
+    G = rng.standard_normal((2, nm, 4)).astype(np.float32)
+    F_or = oracle.gather(s.R, s.T, s.L, s.M, G[..., :3].reshape(2, 9, 9, 9, 3).astype(np.float64))
+    Fb_or, _ = oracle.bonds(s.R, s.bonds, s.k_bond, s.r0, s.L)
+    mesh = hpf.hpf_mesh_make(s.L, s.M, s.N)
+    R, T, Gd = dev(s.R, torch.float32), dev(s.T, torch.uint8), dev(G, torch.float32)
+    bonds = dev(s.bonds, torch.int32)
+    F = torch.zeros((s.N, 4), dtype=torch.float32, device="cuda")
+    hpf.hpf_force_gather(R, T, mesh, 2, Gd, F)
+    assert rel_max(host(F)[:, :3], F_or) <= 1e-6
+    hpf.bond_forces(R, bonds, s.k_bond, s.r0, s.L, F)
+    assert rel_max(host(F)[:, :3], F_or + Fb_or) <= 1e-6
+    # fused pass == separate calls, bit for bit
+    V1 = dev(s.V, torch.float32)
+    V2 = V1.clone()
+    R1 = R.clone()
+    part1 = torch.zeros((4, hpf.HPF_NPART), dtype=torch.float64, device="cuda")
+    part2 = torch.ones((4, hpf.HPF_NPART), dtype=torch.float64, device="cuda")   # stale slots
+    hpf.verlet_step(None, V1, F, 0.03, s.L, 2, kin_part=part1)
+    hpf.verlet_step(R1, V1, F, 0.03, s.L, 1)
+    R2 = torch.empty_like(R)
+    hpf.hpf_advance(R, R2, V2, T, mesh, 2, Gd, bonds, s.k_bond, s.r0, s.L, 0.03, kin_part=part2)
+    assert torch.equal(R1, R2) and torch.equal(V1, V2)
+    o1 = torch.zeros(4, dtype=torch.float64, device="cuda")
+    o2 = torch.zeros(4, dtype=torch.float64, device="cuda")
+    hpf.hpf_reduce_partials(part1, 4, o1)
+    hpf.hpf_reduce_partials(part2, 4, o2)
+    assert torch.equal(o1, o2)
