@@ -137,6 +137,90 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True):
             "flags": flags, "energies": e}
 
 
+def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
+    """64 uneven A10B10 replicas: batched entry points vs one single-system call chain
+    per replica, both captured in a HIP graph of `steps_per_graph` steps and replayed."""
+    import torch
+
+    from paper_1310_2041_amd import engine
+    from synth import workloads as wl
+
+    specs = wl.replica_specs()
+    systems = [wl.build_replica(sp, r) for r, sp in enumerate(specs)]
+    n_beads = sum(s.N for s in systems)
+
+    def time_graph(g):
+        g.launch()                                   # warm-up replay
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(g.stream)
+        for _ in range(replays):
+            g.launch()
+        e1.record(g.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / (replays * steps_per_graph)
+
+    batch = engine.BatchState(systems, sort_every=sort_every)
+    batch.start()
+    chosen, trials = (batch.tune(trial_steps=3) if tune else (None, []))
+    torch.cuda.synchronize()
+    gb = engine.Graph(lambda: batch.step(steps_per_graph, report_last=True))
+    ms_batched = time_graph(gb)
+    del gb
+
+    states = [engine.HpfState.from_system(s) for s in systems]
+    for st in states:
+        st.start(sort=True)
+        st.prime()
+    torch.cuda.synchronize()
+
+    def plain():
+        for i in range(steps_per_graph):
+            for st in states:
+                st.step_fused(report=(i == steps_per_graph - 1),
+                              sort=sort_every > 0 and st.steps_done % sort_every == 0)
+
+    gp = engine.Graph(plain)
+    ms_plain = time_graph(gp)
+    del gp
+    return {"workload": "c4_64_replica_a10b10_sweep", "replicas": len(systems), "beads": n_beads,
+            "batched_value": n_beads / (ms_batched * 1e-3), "plain_value": n_beads / (ms_plain * 1e-3),
+            "batched_ms_per_step": ms_batched, "plain_ms_per_step": ms_plain,
+            "speedup": ms_plain / ms_batched, "tuned": chosen,
+            "tune_trial_ms": [round(t, 4) for t in trials],
+            "note": "both paths replayed from HIP graphs of %d steps" % steps_per_graph}
+
+
+# rocprofv3 kernel names behind each timed call of the step
+ROCPROF_KERNELS = {
+    "advance": ["hpf::k_advance<true>", "hpf::k_advance<false>"],
+    "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum",
+                        "hpf::k_scatter_strays"],
+    "field_potential": ["hpf::k_field_potential<%d>" % k for k in range(1, 9)],
+    "field_gradient": ["hpf::k_field_gradient"],
+}
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of
+    `workload`, or None when there is none or the kernel sources changed since."""
+    from paper_1310_2041_amd.profile_summary import source_hash
+    path = os.path.join(ROOT, "profiles", f"{workload}_step.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != source_hash():
+        return None
+    tot, found = 0.0, False
+    for k in ROCPROF_KERNELS.get(kernel, []):
+        e = d["kernels"].get(k)
+        if e and e.get("fetch_bytes") is not None and e.get("write_bytes") is not None:
+            tot += e["fetch_bytes"] + e["write_bytes"]
+            found = True
+    return tot if found else None
+
+
 def cpu_baseline(cfg, n_steps):
     """The FP64 oracle (single-threaded C) on a bounded sample of the workload."""
     import oracle
@@ -168,6 +252,7 @@ def main():
                     help="fused: hpf_advance; api: the six separate calls")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batched sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hPF-MD path here runs on a single MI355X "
@@ -215,7 +300,8 @@ def main():
                    "energy_report_every": 1, "step": args.mode, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "algorithmic_bytes": dom_bytes,
+                     "traffic": measured_traffic(r["spec"].name, dom)},
         "kernels": per_kernel,
         "device_flags": r["flags"],
     }
@@ -226,6 +312,8 @@ def main():
                        "value": r2["N"] * args.steps / (r2["ms_total"] * 1e-3),
                        "ms_per_step": r2["ms_total"] / args.steps,
                        "note": "working set fits the 256 MB Infinity Cache"}
+    if not args.no_batch:
+        out["batched_sweep"] = run_batched_sweep()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps)
     print(json.dumps(out), flush=True)

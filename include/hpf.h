@@ -298,6 +298,92 @@ hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N,
                               int32_t* bonds_out, uint32_t* cell_start, void* work,
                               size_t work_bytes, void* stream);
 
+/* ===========================================================================
+ * Batched replicas (a phase-diagram sweep): many independent systems of
+ * uneven size, box and chi advanced by one set of kernel launches per phase.
+ *
+ * The caller concatenates the replicas' beads (replica r owns storage indices
+ * [bead_offset, bead_offset + n_beads), offsets contiguous and increasing; the
+ * bond table is [D][N_total] with GLOBAL indices; tags must be unique and
+ * increasing in the initial order) and provides two sets of bead buffers
+ * (current / ping-pong), one concatenated mesh set (replica r's
+ * [K][M_r^3] block follows replica r-1's, in replica order) and a workspace.
+ * The batch sorts all replicas with one counting sort over disjoint key
+ * ranges and runs the cell scatter, potential, gradient and fused advance as
+ * one launch each over a work list of (replica, range) items. Each replica's
+ * beads follow bit for bit the trajectory of the single-system calls; FP64
+ * energy sums differ only in summation grouping.
+ * ========================================================================= */
+typedef struct hpf_replica {
+    int64_t bead_offset;
+    int64_t n_beads;
+    float L[3];
+    int32_t M[3];            /* each M_d >= brick + 5 */
+    double kT;
+    double inv_kappa;
+    double chi[HPF_MAX_TYPES * HPF_MAX_TYPES];   /* row-major K x K */
+} hpf_replica_t;
+
+typedef struct hpf_batch_config {
+    int32_t K;               /* species, same for all replicas */
+    int32_t D;               /* bond-table rows */
+    float k_bond, r0, dt;    /* eq. (7) and the time step, same for all replicas */
+    int32_t brick;           /* sort brick edge B, 3..8 (0 selects 8) */
+    int32_t halo;            /* cell-scatter drift halo, 0..2, < B */
+    int32_t sort_every;      /* re-sort every n steps (0: never after start) */
+    int32_t bead_chunk;      /* beads per work item, >= 512 */
+    int32_t mesh_chunk;      /* mesh points per potential work item, >= 2048 */
+} hpf_batch_config_t;
+
+typedef struct hpf_batch_buffers {
+    float* R[2];             /* float[N_total][4] each */
+    float* Vel[2];
+    uint8_t* T[2];
+    int32_t* tag[2];
+    int32_t* bonds[2];       /* int32[D][N_total] each (NULL when D = 0) */
+    uint64_t* counts;        /* sum_r K M_r^3 */
+    float* V;                /* sum_r K M_r^3 */
+    float* G;                /* sum_r K M_r^3 * 4 */
+} hpf_batch_buffers_t;
+
+typedef struct hpf_batch hpf_batch_t;   /* host object; owns no device memory */
+
+/* Workspace bytes for these replicas and configuration (0 = invalid). */
+size_t hpf_batch_workspace_bytes(const hpf_replica_t* reps, int32_t n_rep,
+                                 const hpf_batch_config_t* cfg);
+/* Build the replica table and work lists (synchronous host->device copies into
+ * `work`). Buffers and workspace must outlive the batch and not move. */
+hpf_status_t hpf_batch_create(const hpf_replica_t* reps, int32_t n_rep,
+                              const hpf_batch_config_t* cfg, const hpf_batch_buffers_t* bufs,
+                              void* work, size_t work_bytes, hpf_batch_t** out);
+/* Sort, forces at x_0 with energies, then the first half step. */
+hpf_status_t hpf_batch_start(hpf_batch_t* batch, void* stream);
+/* n_steps fused steps (sorting on the configured cadence); with report_last,
+ * the energies of the last step are reduced per replica. */
+hpf_status_t hpf_batch_step(hpf_batch_t* batch, int32_t n_steps, int32_t report_last,
+                            void* stream);
+/* Device pointers of the current bead buffers and of the per-replica energies
+ * double[n_rep][8] = {KE, E_bond, W, E_tot, Px, Py, Pz, 0}. Any may be NULL. */
+hpf_status_t hpf_batch_current(const hpf_batch_t* batch, float** R, float** Vel, uint8_t** T,
+                               int32_t** tag, int32_t** bonds, double** energies);
+/* Autotuner: times trial_steps steps for each candidate (halo in {1,2},
+ * bead_chunk in {1024..8192}, mesh_chunk in {4096,16384}) on the live
+ * system, keeps the fastest and returns it in *chosen; trial_ms (nullable,
+ * >= 16 floats) receives the per-step times, *n_trials their count. The
+ * trials advance the simulation. Synchronises the stream. */
+hpf_status_t hpf_batch_tune(hpf_batch_t* batch, int32_t trial_steps, void* stream,
+                            hpf_batch_config_t* chosen, float* trial_ms, int32_t* n_trials);
+hpf_status_t hpf_batch_destroy(hpf_batch_t* batch);
+
+/* HIP graphs around any sequence of library calls: capture what is enqueued
+ * on `stream` (not the null stream) between begin and end, then replay it
+ * with one launch. Buffers used during capture must outlive the graph. */
+typedef struct hpf_graph hpf_graph_t;
+hpf_status_t hpf_graph_begin(void* stream);
+hpf_status_t hpf_graph_end(void* stream, hpf_graph_t** out);
+hpf_status_t hpf_graph_launch(hpf_graph_t* graph, void* stream);
+hpf_status_t hpf_graph_destroy(hpf_graph_t* graph);
+
 /* Read (and optionally clear) the sticky device status bits of the current
  * device. Synchronises `stream`. flags is a HOST pointer. */
 hpf_status_t hpf_get_device_status(uint32_t* flags, int32_t clear, void* stream);

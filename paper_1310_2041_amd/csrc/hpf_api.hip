@@ -321,3 +321,5 @@ hpf_status_t hpf_get_device_status(uint32_t* flags, int32_t clear, void* stream)
 }
 
 }  // extern "C"
+
+#include "hpf_batch.hip"

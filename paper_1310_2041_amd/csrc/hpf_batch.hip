@@ -1,0 +1,874 @@
+// Batched replicas: many independent hPF-MD systems of uneven size and chi
+// (a phase-diagram sweep) advanced by one set of kernel launches per phase.
+//
+// The replicas live in one concatenated set of bead arrays (replica r owns
+// beads [off_r, off_r + N_r); bond-table entries are global indices) and one
+// concatenated set of meshes (replica r's [K][M_r^3] block at K * moff_r).
+// Cell keys of replica r are offset by key_base_r, so one counting sort over
+// the concatenated key space sorts every replica inside its own bead range,
+// and the single-system sort kernels are reused unchanged. Every other phase
+// walks a host-built work list of (replica, range) items, one workgroup per
+// item, and calls the same device functions as the single-system kernels, so
+// each replica's beads follow exactly the trajectory they would follow alone.
+#include <algorithm>
+#include <vector>
+
+#include "hpf_common.hpp"
+
+namespace hpf {
+
+struct RepK {
+    MeshK m;
+    BoxK box;
+    PotK p;
+    int64_t bead_off, N;
+    int64_t moff;          // first mesh point of the replica in the concatenated meshes
+    uint32_t key_base, NK;
+    int32_t nb[3];
+    int64_t brick_off;     // first brick of the replica in the concatenated brick numbering
+    int64_t nbricks;
+};
+
+struct ItemK {
+    int32_t rep;
+    int32_t aux;
+    int64_t begin, end;
+};
+
+constexpr int kBThreads = 256;
+
+__device__ __forceinline__ TileK tile_of(const RepK& r, int B, int h)
+{
+    TileK t;
+    t.m = r.m;
+    t.B = B;
+    t.h = h;
+    t.P = B + 1 + 2 * h;
+    t.nb[0] = r.nb[0];
+    t.nb[1] = r.nb[1];
+    t.nb[2] = r.nb[2];
+    t.NK = r.NK;
+    t.ntiles = r.nbricks;
+    return t;
+}
+
+// ---------------------------------------------------------------- sort keys
+
+__global__ __launch_bounds__(kBThreads) void k_batch_keys(const RepK* __restrict__ reps,
+                                                          const ItemK* __restrict__ items, int B,
+                                                          const float4* __restrict__ R,
+                                                          uint32_t* __restrict__ keys,
+                                                          uint32_t* __restrict__ hist)
+{
+    const ItemK it = items[blockIdx.x];
+    const RepK& rp = reps[it.rep];
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int64_t base = it.begin; base < it.end; base += kBThreads) {
+        const int64_t i = base + threadIdx.x;
+        const bool active = i < it.end;
+        uint32_t key = rp.key_base + rp.NK;
+        if (active) {
+            BeadCell b;
+            if (bead_cell(R[i], rp.m, b))
+                key = rp.key_base + brick_key(b.c[0], b.c[1], b.c[2], B, rp.nb);
+            keys[i] = key;
+        }
+        int head, len;
+        wave_runs(key, active, &head, &len);
+        if (active && head == lane)
+            atomicAdd(hist + key, (uint32_t)len);
+    }
+}
+
+// ------------------------------------------------------------- cell scatter
+
+__global__ __launch_bounds__(kTcThreads) void k_batch_scatter_bricks(const RepK* __restrict__ reps,
+                                                                     const ItemK* __restrict__ items,
+                                                                     int B, int h, int K,
+                                                                     const float4* __restrict__ R,
+                                                                     const uint8_t* __restrict__ T,
+                                                                     const uint32_t* __restrict__ cell_start,
+                                                                     unsigned long long* __restrict__ partials,
+                                                                     uint32_t* __restrict__ strays)
+{
+    const ItemK it = items[blockIdx.x];
+    const RepK& rp = reps[it.rep];
+    const TileK tk = tile_of(rp, B, h);
+    const int P = tk.P;
+    scatter_brick_body(R, T, K, tk, cell_start + rp.key_base, it.begin,
+                       partials + (rp.brick_off + it.begin) * (int64_t)K * P * P * P, strays);
+}
+
+__global__ __launch_bounds__(256) void k_batch_scatter_sum(const RepK* __restrict__ reps,
+                                                           const ItemK* __restrict__ items, int B, int h,
+                                                           int K,
+                                                           const unsigned long long* __restrict__ partials,
+                                                           unsigned long long* __restrict__ counts)
+{
+    const ItemK it = items[blockIdx.x];
+    const RepK& rp = reps[it.rep];
+    const TileK tk = tile_of(rp, B, h);
+    const int P = tk.P;
+    scatter_sum_body(partials + rp.brick_off * (int64_t)K * P * P * P, tk, K, it.begin,
+                     counts + (int64_t)K * rp.moff);
+}
+
+__device__ __forceinline__ int find_rep(const RepK* reps, int nrep, int64_t p)
+{
+    int lo = 0, hi = nrep - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (reps[mid].bead_off <= p)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Strays of all replicas (global indices in one list) and each replica's
+// beads that the sort could not bin, with global atomics.
+__global__ __launch_bounds__(kTcThreads) void k_batch_scatter_strays(const RepK* __restrict__ reps, int nrep,
+                                                                     int K, const float4* __restrict__ R,
+                                                                     const uint8_t* __restrict__ T,
+                                                                     const uint32_t* __restrict__ cell_start,
+                                                                     const uint32_t* __restrict__ strays,
+                                                                     unsigned long long* __restrict__ counts)
+{
+    const int64_t nstray = strays[0];
+    bool bad = false;
+    for (int64_t j = (int64_t)blockIdx.x * kTcThreads + threadIdx.x; j < nstray;
+         j += (int64_t)gridDim.x * kTcThreads) {
+        const int64_t p = strays[1 + j];
+        const RepK& rp = reps[find_rep(reps, nrep, p)];
+        bad |= !deposit_global(R[p], T[p], K, rp.m, counts + (int64_t)K * rp.moff);
+    }
+    // unbinned tails: replica r's beads with key key_base_r + NK_r
+    for (int r = blockIdx.x; r < nrep; r += gridDim.x) {
+        const RepK& rp = reps[r];
+        const int64_t a = cell_start[rp.key_base + rp.NK], b = cell_start[rp.key_base + rp.NK + 1];
+        for (int64_t p = a + threadIdx.x; p < b; p += kTcThreads)
+            bad |= !deposit_global(R[p], T[p], K, rp.m, counts + (int64_t)K * rp.moff);
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+}
+
+// ---------------------------------------------------------- potential, grad
+
+template <int K>
+__global__ __launch_bounds__(kPotThreads) void k_batch_potential(const RepK* __restrict__ reps,
+                                                                 const ItemK* __restrict__ items,
+                                                                 unsigned long long* __restrict__ counts,
+                                                                 float* __restrict__ V,
+                                                                 double* __restrict__ w_part)
+{
+    __shared__ double scratch[kPotThreads / kWave];
+    const ItemK it = items[blockIdx.x];
+    const RepK& rp = reps[it.rep];
+    double wsum = 0.0;
+    bool over = false;
+    unsigned long long* c = counts + (int64_t)K * rp.moff;
+    float* v = V + (int64_t)K * rp.moff;
+    for (int64_t q = it.begin + threadIdx.x; q < it.end; q += kPotThreads)
+        wsum += potential_point<K>(c, v, rp.m.nm, q, rp.m.c_norm, rp.p, over);
+    if (over)
+        raise_flag(HPF_FLAG_OVERFLOW);
+    if (w_part) {
+        const double s = block_sum(wsum, scratch);
+        if (threadIdx.x == 0)
+            w_part[blockIdx.x] = s * rp.p.rho0_dV;
+    }
+}
+
+// one workgroup per (replica, z plane)
+__global__ __launch_bounds__(256) void k_batch_gradient(const RepK* __restrict__ reps,
+                                                        const ItemK* __restrict__ items, int K,
+                                                        const float* __restrict__ V,
+                                                        float4* __restrict__ G)
+{
+    const ItemK it = items[blockIdx.x];
+    const RepK& rp = reps[it.rep];
+    const int Mx = rp.m.M[0], My = rp.m.M[1];
+    const int z = (int)it.begin;
+    for (int e = threadIdx.x; e < Mx * My; e += 256)
+        gradient_point(V + (int64_t)K * rp.moff, rp.m, K, e % Mx, e / Mx, z, G + (int64_t)K * rp.moff);
+}
+
+// ------------------------------------------------------------------ advance
+
+template <bool kR0Zero>
+__global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restrict__ reps,
+                                                             const ItemK* __restrict__ items, int K,
+                                                             const float4* __restrict__ R,
+                                                             float4* __restrict__ R_next,
+                                                             float4* __restrict__ Vel,
+                                                             const uint8_t* __restrict__ T, int64_t Ntot,
+                                                             const float4* __restrict__ G,
+                                                             const int32_t* __restrict__ bonds, int D, float k,
+                                                             float r0, float dt,
+                                                             double* __restrict__ e_part,
+                                                             double* __restrict__ kin_part, int nslot)
+{
+    __shared__ double scratch[kPThreads / kWave];
+    const ItemK it = items[blockIdx.x];
+    const RepK& rp = reps[it.rep];
+    const float4* Gr = G + (int64_t)K * rp.moff;
+    const float hdt = 0.5f * dt;
+    KinAcc acc;
+    double e = 0.0;
+    bool bad_bead = false, bad_bond = false, nonfinite = false;
+    for (int64_t i = it.begin + threadIdx.x; i < it.end; i += kPThreads)
+        advance_bead<kR0Zero>(i, R, R_next, Vel, T, Ntot, rp.m, K, Gr, bonds, D, k, r0, rp.box, nullptr,
+                              dt, hdt, nullptr, acc, e, bad_bead, bad_bond, nonfinite);
+    if (bad_bead)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+    if (bad_bond)
+        raise_flag(HPF_FLAG_BAD_BOND);
+    if (nonfinite)
+        raise_flag(HPF_FLAG_NONFINITE);
+    if (e_part) {
+        const double s = block_sum(e, scratch);
+        if (threadIdx.x == 0)
+            e_part[blockIdx.x] = s;
+    }
+    if (kin_part)
+        acc.store_rows(kin_part, nslot, blockIdx.x, scratch);
+}
+
+// per replica: energies {KE, E_bond, W, E_tot, Px, Py, Pz, 0} from the item
+// partials, each summed in item order by one lane
+__global__ __launch_bounds__(64) void k_batch_reduce(const int64_t* __restrict__ bead_items,
+                                                     const int64_t* __restrict__ mesh_items,
+                                                     const double* __restrict__ w_part,
+                                                     const double* __restrict__ e_part,
+                                                     const double* __restrict__ kin_part, int nslot,
+                                                     double* __restrict__ out)
+{
+    __shared__ double sums[6];
+    const int r = blockIdx.x;
+    const int c = threadIdx.x;
+    if (c < 6) {
+        double s = 0.0;
+        if (c == 0) {
+            for (int64_t i = mesh_items[r]; i < mesh_items[r + 1]; ++i)
+                s += w_part[i];
+        } else if (c == 1) {
+            for (int64_t i = bead_items[r]; i < bead_items[r + 1]; ++i)
+                s += e_part[i];
+        } else {
+            const double* row = kin_part + (int64_t)(c - 2) * nslot;
+            for (int64_t i = bead_items[r]; i < bead_items[r + 1]; ++i)
+                s += row[i];
+        }
+        sums[c] = s;
+    }
+    __syncthreads();
+    if (c == 0) {
+        double* o = out + (int64_t)r * 8;
+        o[0] = sums[2];                    // KE
+        o[1] = sums[1];                    // E_bond
+        o[2] = sums[0];                    // W
+        o[3] = sums[2] + sums[1] + sums[0];
+        o[4] = sums[3];
+        o[5] = sums[4];
+        o[6] = sums[5];
+        o[7] = 0.0;
+    }
+}
+
+}  // namespace hpf
+
+// ======================================================================
+// Host side: replica table, work lists, workspace, launches, autotuner.
+// ======================================================================
+
+namespace hpf {
+
+// prime: forces at x_0, energies with v_0, then the first half step
+template <bool kR0Zero>
+__global__ __launch_bounds__(kPThreads) void k_batch_prime(const RepK* __restrict__ reps,
+                                                           const ItemK* __restrict__ items, int K,
+                                                           const float4* __restrict__ R,
+                                                           float4* __restrict__ R_next,
+                                                           float4* __restrict__ Vel,
+                                                           const uint8_t* __restrict__ T, int64_t Ntot,
+                                                           const float4* __restrict__ G,
+                                                           const int32_t* __restrict__ bonds, int D, float k,
+                                                           float r0, float dt, double* __restrict__ e_part,
+                                                           double* __restrict__ kin_part, int nslot)
+{
+    __shared__ double scratch[kPThreads / kWave];
+    const ItemK it = items[blockIdx.x];
+    const RepK& rp = reps[it.rep];
+    const float4* Gr = G + (int64_t)K * rp.moff;
+    const float hdt = 0.5f * dt;
+    KinAcc acc;
+    double e = 0.0;
+    bool bad_bead = false, bad_bond = false, nonfinite = false;
+    for (int64_t i = it.begin + threadIdx.x; i < it.end; i += kPThreads) {
+        float4 r = R[i];
+        float3 ff;
+        bad_bead |= !field_force(r, T[i], rp.m, K, Gr, ff);
+        float ei;
+        const float3 fb = bond_sum<kR0Zero>(i, r, R, Ntot, bonds, D, k, r0, rp.box, ei, bad_bond);
+        float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
+        f.x += fb.x;
+        f.y += fb.y;
+        f.z += fb.z;
+        e += 0.5 * (double)ei;
+        float4 v = Vel[i];
+        acc.add(v, 1.0f);
+        kick(v, f, 1.0f, hdt);
+        drift(r, v, dt, rp.box);
+        nonfinite |= !(finite4(r) && finite4(v));
+        Vel[i] = v;
+        R_next[i] = r;
+    }
+    if (bad_bead)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+    if (bad_bond)
+        raise_flag(HPF_FLAG_BAD_BOND);
+    if (nonfinite)
+        raise_flag(HPF_FLAG_NONFINITE);
+    if (e_part) {
+        const double s = block_sum(e, scratch);
+        if (threadIdx.x == 0)
+            e_part[blockIdx.x] = s;
+    }
+    if (kin_part)
+        acc.store_rows(kin_part, nslot, blockIdx.x, scratch);
+}
+
+constexpr int kMinBeadChunk = 512;
+constexpr int kMinMeshChunk = 2048;
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+    int64_t Ntot = 0, nm_tot = 0, bricks_tot = 0;
+    uint32_t NKT = 0;                    // keys of all replicas, invalid buckets included
+    int64_t max_bead_items = 0, max_mesh_items = 0, max_planes = 0;
+    size_t off_reps, off_bead_items, off_brick_items, off_mesh_items, off_plane_items, off_bead_ioff,
+        off_mesh_ioff, off_keys, off_perm, off_inv, off_start, off_cursor, off_tiles, off_ptag, off_strays,
+        off_partials, off_wpart, off_epart, off_kpart, off_energy, total;
+};
+
+static bool batch_layout(const hpf_replica_t* reps, int nrep, const hpf_batch_config_t* cfg, BatchLayout* L)
+{
+    if (!reps || nrep < 1 || !cfg || cfg->K < 1 || cfg->K > HPF_MAX_TYPES || cfg->D < 0 ||
+        cfg->D > HPF_MAX_BONDS)
+        return false;
+    const int B = cfg->brick == 0 ? 8 : cfg->brick;
+    if (B < 3 || B > kTcMaxB)
+        return false;
+    const int Pmax = B + 1 + 2 * kTcMaxHalo;
+    int64_t nkt = 0, expect_off = 0;
+    for (int r = 0; r < nrep; ++r) {
+        const hpf_replica_t& q = reps[r];
+        if (q.n_beads < 0 || q.bead_offset != expect_off)
+            return false;
+        expect_off += q.n_beads;
+        int64_t nk = (int64_t)B * B * B, nbr = 1, nm = 1;
+        for (int d = 0; d < 3; ++d) {
+            if (!(q.L[d] > 0.0f) || q.M[d] < B + 1 + 2 * kTcMaxHalo || q.M[d] > 4096)
+                return false;
+            const int nb = (q.M[d] + B - 1) / B;
+            nk *= nb;
+            nbr *= nb;
+            nm *= q.M[d];
+        }
+        nkt += nk + 1;
+        L->bricks_tot += nbr;
+        L->nm_tot += nm;
+        L->max_bead_items += (q.n_beads + kMinBeadChunk - 1) / kMinBeadChunk;
+        L->max_mesh_items += (nm + kMinMeshChunk - 1) / kMinMeshChunk;
+        L->max_planes += q.M[2];
+    }
+    L->Ntot = expect_off;
+    if (L->Ntot > 0x7ffffff0LL || nkt + 2 > (int64_t)kMaxScanTiles * kScanTile)
+        return false;
+    L->NKT = (uint32_t)nkt;
+    const int64_t N1 = L->Ntot > 0 ? L->Ntot : 1;
+    const int64_t nscan = nkt + 1;
+    const int64_t ntiles = (nscan + kScanTile - 1) / kScanTile;
+    size_t o = 0;
+    L->off_reps = o; o += al256(sizeof(RepK) * nrep);
+    L->off_bead_items = o; o += al256(sizeof(ItemK) * (L->max_bead_items + 1));
+    L->off_brick_items = o; o += al256(sizeof(ItemK) * (L->bricks_tot + 1));
+    L->off_mesh_items = o; o += al256(sizeof(ItemK) * (L->max_mesh_items + 1));
+    L->off_plane_items = o; o += al256(sizeof(ItemK) * (L->max_planes + 1));
+    L->off_bead_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
+    L->off_mesh_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
+    L->off_keys = o; o += al256(sizeof(uint32_t) * N1);
+    L->off_perm = o; o += al256(sizeof(int32_t) * N1);
+    L->off_inv = o; o += al256(sizeof(int32_t) * N1);
+    L->off_start = o; o += al256(sizeof(uint32_t) * (nscan + 1));
+    L->off_cursor = o; o += al256(sizeof(uint32_t) * (nscan + 1));
+    L->off_tiles = o; o += al256(sizeof(uint32_t) * (ntiles + 1));
+    L->off_ptag = o; o += al256(sizeof(int32_t) * N1);
+    L->off_strays = o; o += al256(sizeof(uint32_t) * (N1 + 64));
+    L->off_partials = o; o += al256(sizeof(unsigned long long) * L->bricks_tot * cfg->K * Pmax * Pmax * Pmax);
+    L->off_wpart = o; o += al256(sizeof(double) * (L->max_mesh_items + 1));
+    L->off_epart = o; o += al256(sizeof(double) * (L->max_bead_items + 1));
+    L->off_kpart = o; o += al256(sizeof(double) * 4 * (L->max_bead_items + 1));
+    L->off_energy = o; o += al256(sizeof(double) * 8 * nrep);
+    L->total = o;
+    return true;
+}
+
+}  // namespace hpf
+
+struct hpf_batch {
+    int nrep = 0;
+    hpf_batch_config_t cfg{};
+    hpf::BatchLayout L;
+    std::vector<hpf::RepK> reps;
+    std::vector<hpf_replica_t> desc;
+    char* work = nullptr;
+    hpf_batch_buffers_t buf{};
+    int rcur = 0;        // current position buffer
+    int scur = 0;        // current velocity / type / tag / bond buffer
+    int64_t steps_done = 0;
+    int64_t n_bead_items = 0, n_brick_items = 0, n_mesh_items = 0, n_planes = 0;
+    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(work + off); }
+};
+
+namespace hpf {
+
+static hpf_status_t batch_build_items(hpf_batch* b)
+{
+    const hpf_batch_config_t& c = b->cfg;
+    std::vector<ItemK> bead, brick, mesh, plane;
+    std::vector<int64_t> bead_off(b->nrep + 1), mesh_off(b->nrep + 1);
+    for (int r = 0; r < b->nrep; ++r) {
+        const RepK& rp = b->reps[r];
+        bead_off[r] = (int64_t)bead.size();
+        for (int64_t s = 0; s < rp.N; s += c.bead_chunk)
+            bead.push_back({r, 0, rp.bead_off + s, rp.bead_off + std::min<int64_t>(rp.N, s + c.bead_chunk)});
+        mesh_off[r] = (int64_t)mesh.size();
+        for (int64_t s = 0; s < rp.m.nm; s += c.mesh_chunk)
+            mesh.push_back({r, 0, s, std::min<int64_t>(rp.m.nm, s + c.mesh_chunk)});
+        for (int64_t k = 0; k < rp.nbricks; ++k)
+            brick.push_back({r, 0, k, k + 1});
+        for (int z = 0; z < rp.m.M[2]; ++z)
+            plane.push_back({r, 0, z, z + 1});
+    }
+    bead_off[b->nrep] = (int64_t)bead.size();
+    mesh_off[b->nrep] = (int64_t)mesh.size();
+    if ((int64_t)bead.size() > b->L.max_bead_items || (int64_t)mesh.size() > b->L.max_mesh_items)
+        return HPF_EINVAL;
+    b->n_bead_items = (int64_t)bead.size();
+    b->n_brick_items = (int64_t)brick.size();
+    b->n_mesh_items = (int64_t)mesh.size();
+    b->n_planes = (int64_t)plane.size();
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+        return bytes == 0 || hipMemcpy(b->work + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up(b->L.off_bead_items, bead.data(), sizeof(ItemK) * bead.size()) ||
+        !up(b->L.off_brick_items, brick.data(), sizeof(ItemK) * brick.size()) ||
+        !up(b->L.off_mesh_items, mesh.data(), sizeof(ItemK) * mesh.size()) ||
+        !up(b->L.off_plane_items, plane.data(), sizeof(ItemK) * plane.size()) ||
+        !up(b->L.off_bead_ioff, bead_off.data(), sizeof(int64_t) * bead_off.size()) ||
+        !up(b->L.off_mesh_ioff, mesh_off.data(), sizeof(int64_t) * mesh_off.size()))
+        return HPF_EHIP;
+    return HPF_OK;
+}
+
+static hpf_status_t batch_sort(hpf_batch* b, hipStream_t s)
+{
+    const BatchLayout& L = b->L;
+    const int64_t N = L.Ntot;
+    const int o = b->scur, n = 1 - b->scur;
+    uint32_t* keys = b->at<uint32_t>(L.off_keys);
+    int32_t* perm = b->at<int32_t>(L.off_perm);
+    int32_t* inv = b->at<int32_t>(L.off_inv);
+    uint32_t* start = b->at<uint32_t>(L.off_start);
+    uint32_t* cursor = b->at<uint32_t>(L.off_cursor);
+    uint32_t* tiles = b->at<uint32_t>(L.off_tiles);
+    int32_t* ptag = b->at<int32_t>(L.off_ptag);
+    const int64_t nscan = (int64_t)L.NKT + 1;
+    const int64_t ntiles = (nscan + kScanTile - 1) / kScanTile;
+    const unsigned gfill = (unsigned)std::min<int64_t>((nscan + kSortThreads - 1) / kSortThreads, 4096);
+    auto grid_of = [](int64_t n) { return (unsigned)((n + kSortThreads - 1) / kSortThreads); };
+    const int B = b->cfg.brick;
+    hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, nscan, 0u);
+    if (b->n_bead_items > 0)
+        hipLaunchKernelGGL(k_batch_keys, dim3((unsigned)b->n_bead_items), dim3(kBThreads), 0, s,
+                           b->at<RepK>(L.off_reps), b->at<ItemK>(L.off_bead_items), B,
+                           reinterpret_cast<const float4*>(b->buf.R[b->rcur]), keys, start);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, start, nscan, tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, s, tiles, (int)ntiles);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_of(nscan)), dim3(kSortThreads), 0, s, start, nscan, tiles);
+    if (N > 0) {
+        hipLaunchKernelGGL(k_copy_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, cursor, nscan);
+        hipLaunchKernelGGL(k_sort_place, dim3(grid_of(N)), dim3(kSortThreads), 0, s, keys, N,
+                           b->buf.tag[o], cursor, perm, ptag);
+        hipLaunchKernelGGL(k_sort_segments, dim3(grid_of(nscan - 1)), dim3(kSortThreads), 0, s, start,
+                           nscan - 1, ptag, perm);
+        hipLaunchKernelGGL(k_sort_permute, dim3(grid_of(N)), dim3(kSortThreads), 0, s, perm, N,
+                           reinterpret_cast<const float4*>(b->buf.R[b->rcur]),
+                           reinterpret_cast<const float4*>(b->buf.Vel[o]), b->buf.T[o], b->buf.tag[o],
+                           reinterpret_cast<float4*>(b->buf.R[1 - b->rcur]),
+                           reinterpret_cast<float4*>(b->buf.Vel[n]), b->buf.T[n], b->buf.tag[n], inv);
+        if (b->cfg.D > 0)
+            hipLaunchKernelGGL(k_sort_bonds, dim3(grid_of(N)), dim3(kSortThreads), 0, s, perm, inv, N,
+                               b->buf.bonds[o], b->cfg.D, b->buf.bonds[n]);
+    }
+    b->rcur = 1 - b->rcur;
+    b->scur = n;
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)
+{
+    const BatchLayout& L = b->L;
+    const int K = b->cfg.K, B = b->cfg.brick, h = b->cfg.halo;
+    const int P = B + 1 + 2 * h;
+    const RepK* reps = b->at<RepK>(L.off_reps);
+    auto* counts = reinterpret_cast<unsigned long long*>(b->buf.counts);
+    uint32_t* strays = b->at<uint32_t>(L.off_strays);
+    auto* partials = b->at<unsigned long long>(L.off_partials);
+    const uint32_t* cs = b->at<uint32_t>(L.off_start);
+    const auto* R = reinterpret_cast<const float4*>(b->buf.R[b->rcur]);
+    const uint8_t* T = b->buf.T[b->scur];
+    const size_t smem = scatter_cells_smem(K, P);
+    if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_scatter_bricks),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+        return HPF_EINVAL;
+    hipLaunchKernelGGL(k_zero_u32_one, dim3(1), dim3(1), 0, s, strays);
+    hipLaunchKernelGGL(k_batch_scatter_bricks, dim3((unsigned)b->n_brick_items), dim3(kTcThreads), smem, s, reps,
+                       b->at<ItemK>(L.off_brick_items), B, h, K, R, T, cs, partials, strays);
+    hipLaunchKernelGGL(k_batch_scatter_sum, dim3((unsigned)b->n_brick_items), dim3(256), 0, s, reps,
+                       b->at<ItemK>(L.off_brick_items), B, h, K, partials, counts);
+    hipLaunchKernelGGL(k_batch_scatter_strays, dim3(256), dim3(kTcThreads), 0, s, reps, b->nrep, K, R, T, cs,
+                       strays, counts);
+    double* w = report ? b->at<double>(L.off_wpart) : nullptr;
+    const dim3 gm((unsigned)b->n_mesh_items), bm(kPotThreads);
+    const ItemK* mi = b->at<ItemK>(L.off_mesh_items);
+    switch (K) {
+    case 1: hipLaunchKernelGGL(k_batch_potential<1>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
+    case 2: hipLaunchKernelGGL(k_batch_potential<2>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
+    case 3: hipLaunchKernelGGL(k_batch_potential<3>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
+    case 4: hipLaunchKernelGGL(k_batch_potential<4>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
+    case 5: hipLaunchKernelGGL(k_batch_potential<5>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
+    case 6: hipLaunchKernelGGL(k_batch_potential<6>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
+    case 7: hipLaunchKernelGGL(k_batch_potential<7>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
+    case 8: hipLaunchKernelGGL(k_batch_potential<8>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
+    default: return HPF_EINVAL;
+    }
+    hipLaunchKernelGGL(k_batch_gradient, dim3((unsigned)b->n_planes), dim3(256), 0, s, reps,
+                       b->at<ItemK>(L.off_plane_items), K, b->buf.V, reinterpret_cast<float4*>(b->buf.G));
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipStream_t s)
+{
+    const BatchLayout& L = b->L;
+    const hpf_batch_config_t& c = b->cfg;
+    const dim3 g((unsigned)b->n_bead_items), bl(kPThreads);
+    const RepK* reps = b->at<RepK>(L.off_reps);
+    const ItemK* items = b->at<ItemK>(L.off_bead_items);
+    const auto* R = reinterpret_cast<const float4*>(b->buf.R[b->rcur]);
+    auto* Rn = reinterpret_cast<float4*>(b->buf.R[1 - b->rcur]);
+    auto* Vel = reinterpret_cast<float4*>(b->buf.Vel[b->scur]);
+    const uint8_t* T = b->buf.T[b->scur];
+    const int32_t* bonds = c.D > 0 ? b->buf.bonds[b->scur] : nullptr;
+    const auto* G = reinterpret_cast<const float4*>(b->buf.G);
+    double* e = report ? b->at<double>(L.off_epart) : nullptr;
+    double* kp = report ? b->at<double>(L.off_kpart) : nullptr;
+    const int nslot = (int)(L.max_bead_items + 1);
+    if (b->n_bead_items > 0) {
+        if (prime) {
+            if (c.r0 == 0.0f)
+                hipLaunchKernelGGL(k_batch_prime<true>, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot, G,
+                                   bonds, c.D, c.k_bond, c.r0, c.dt, e, kp, nslot);
+            else
+                hipLaunchKernelGGL(k_batch_prime<false>, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot, G,
+                                   bonds, c.D, c.k_bond, c.r0, c.dt, e, kp, nslot);
+        } else {
+            if (c.r0 == 0.0f)
+                hipLaunchKernelGGL(k_batch_advance<true>, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot, G,
+                                   bonds, c.D, c.k_bond, c.r0, c.dt, e, kp, nslot);
+            else
+                hipLaunchKernelGGL(k_batch_advance<false>, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot,
+                                   G, bonds, c.D, c.k_bond, c.r0, c.dt, e, kp, nslot);
+        }
+    }
+    b->rcur = 1 - b->rcur;
+    if (report)
+        hipLaunchKernelGGL(k_batch_reduce, dim3(b->nrep), dim3(64), 0, s, b->at<int64_t>(L.off_bead_ioff),
+                           b->at<int64_t>(L.off_mesh_ioff), b->at<double>(L.off_wpart), e, kp, nslot,
+                           b->at<double>(L.off_energy));
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+}  // namespace hpf
+
+using namespace hpf;
+
+extern "C" {
+
+size_t hpf_batch_workspace_bytes(const hpf_replica_t* reps, int32_t n_rep, const hpf_batch_config_t* cfg)
+{
+    BatchLayout L;
+    return batch_layout(reps, n_rep, cfg, &L) ? L.total : 0;
+}
+
+hpf_status_t hpf_batch_create(const hpf_replica_t* reps, int32_t n_rep, const hpf_batch_config_t* cfg,
+                              const hpf_batch_buffers_t* bufs, void* work, size_t work_bytes, hpf_batch_t** out)
+{
+    if (!out || !bufs)
+        return HPF_EINVAL;
+    *out = nullptr;
+    BatchLayout L;
+    if (!batch_layout(reps, n_rep, cfg, &L))
+        return HPF_EINVAL;
+    if (!work || work_bytes < L.total)
+        return HPF_ESPACE;
+    hpf_batch_config_t c = *cfg;
+    if (c.brick == 0)
+        c.brick = 8;
+    if (c.halo < 0 || c.halo > kTcMaxHalo || c.halo >= c.brick || !(c.dt > 0.0f) || c.sort_every < 0 ||
+        c.bead_chunk < kMinBeadChunk || c.mesh_chunk < kMinMeshChunk)
+        return HPF_EINVAL;
+    for (int i = 0; i < 2; ++i)
+        if (L.Ntot > 0 && (!bufs->R[i] || !bufs->Vel[i] || !bufs->T[i] || !bufs->tag[i] ||
+                           (c.D > 0 && !bufs->bonds[i])))
+            return HPF_EINVAL;
+    if (!bufs->counts || !bufs->V || !bufs->G)
+        return HPF_EINVAL;
+    hpf_batch* b = new (std::nothrow) hpf_batch;
+    if (!b)
+        return HPF_EINVAL;
+    b->nrep = n_rep;
+    b->cfg = c;
+    b->L = L;
+    b->work = static_cast<char*>(work);
+    b->buf = *bufs;
+    b->desc.assign(reps, reps + n_rep);
+    uint32_t key_base = 0;
+    int64_t moff = 0, brick_off = 0;
+    const int B = c.brick;
+    for (int r = 0; r < n_rep; ++r) {
+        const hpf_replica_t& q = reps[r];
+        hpf_mesh_t mesh;
+        const float Lr[3] = {q.L[0], q.L[1], q.L[2]};
+        if (hpf_mesh_make(Lr, q.M, q.n_beads, &mesh) != HPF_OK) {
+            delete b;
+            return HPF_EINVAL;
+        }
+        RepK rk{};
+        rk.m = mesh_k(&mesh);
+        for (int d = 0; d < 3; ++d) {
+            rk.box.L[d] = q.L[d];
+            rk.box.halfL[d] = 0.5f * q.L[d];
+            rk.nb[d] = (q.M[d] + B - 1) / B;
+        }
+        for (int a = 0; a < c.K; ++a)
+            for (int bb = 0; bb < c.K; ++bb)
+                rk.p.A[a * c.K + bb] = q.kT * q.chi[a * c.K + bb];
+        rk.p.inv_kappa = q.inv_kappa;
+        rk.p.rho0_dV = mesh.c_norm > 0.0 ? 1.0 / (mesh.c_norm * 281474976710656.0) : 0.0;
+        rk.bead_off = q.bead_offset;
+        rk.N = q.n_beads;
+        rk.moff = moff;
+        rk.key_base = key_base;
+        rk.nbricks = (int64_t)rk.nb[0] * rk.nb[1] * rk.nb[2];
+        rk.NK = (uint32_t)(rk.nbricks * B * B * B);
+        rk.brick_off = brick_off;
+        key_base += rk.NK + 1;
+        moff += rk.m.nm;
+        brick_off += rk.nbricks;
+        b->reps.push_back(rk);
+    }
+    if (hipMemcpy(b->work + L.off_reps, b->reps.data(), sizeof(RepK) * n_rep, hipMemcpyHostToDevice) != hipSuccess) {
+        delete b;
+        return HPF_EHIP;
+    }
+    const hpf_status_t st = batch_build_items(b);
+    if (st != HPF_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return HPF_OK;
+}
+
+hpf_status_t hpf_batch_destroy(hpf_batch_t* b)
+{
+    delete b;
+    return HPF_OK;
+}
+
+hpf_status_t hpf_batch_start(hpf_batch_t* b, void* stream)
+{
+    if (!b)
+        return HPF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    hpf_status_t st = batch_sort(b, s);
+    if (st == HPF_OK)
+        st = batch_fields(b, true, s);
+    if (st == HPF_OK)
+        st = batch_particles(b, true, true, s);
+    b->steps_done = 0;
+    return st;
+}
+
+hpf_status_t hpf_batch_step(hpf_batch_t* b, int32_t n_steps, int32_t report_last, void* stream)
+{
+    if (!b || n_steps < 0)
+        return HPF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    for (int i = 0; i < n_steps; ++i) {
+        const bool report = report_last && i == n_steps - 1;
+        hpf_status_t st = HPF_OK;
+        if (b->cfg.sort_every > 0 && b->steps_done % b->cfg.sort_every == 0)
+            st = batch_sort(b, s);
+        if (st == HPF_OK)
+            st = batch_fields(b, report, s);
+        if (st == HPF_OK)
+            st = batch_particles(b, false, report, s);
+        if (st != HPF_OK)
+            return st;
+        ++b->steps_done;
+    }
+    return HPF_OK;
+}
+
+hpf_status_t hpf_batch_current(const hpf_batch_t* b, float** R, float** Vel, uint8_t** T, int32_t** tag,
+                               int32_t** bonds, double** energies)
+{
+    if (!b)
+        return HPF_EINVAL;
+    if (R)
+        *R = b->buf.R[b->rcur];
+    if (Vel)
+        *Vel = b->buf.Vel[b->scur];
+    if (T)
+        *T = b->buf.T[b->scur];
+    if (tag)
+        *tag = b->buf.tag[b->scur];
+    if (bonds)
+        *bonds = b->buf.bonds[b->scur];
+    if (energies)
+        *energies = reinterpret_cast<double*>(b->work + b->L.off_energy);
+    return HPF_OK;
+}
+
+hpf_status_t hpf_batch_tune(hpf_batch_t* b, int32_t trial_steps, void* stream, hpf_batch_config_t* chosen,
+                            float* trial_ms, int32_t* n_trials)
+{
+    if (!b || trial_steps < 1)
+        return HPF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    const int bead_opts[] = {1024, 2048, 4096, 8192};
+    const int mesh_opts[] = {4096, 16384};
+    const int halo_opts[] = {1, 2};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return HPF_EHIP;
+    hpf_batch_config_t best = b->cfg;
+    float best_ms = 1e30f;
+    int t = 0;
+    hpf_status_t st = HPF_OK;
+    for (int hb : halo_opts)
+        for (int bc : bead_opts)
+            for (int mc : mesh_opts) {
+                if (hb >= b->cfg.brick)
+                    continue;
+                b->cfg.halo = hb;
+                b->cfg.bead_chunk = bc;
+                b->cfg.mesh_chunk = mc;
+                if ((st = batch_build_items(b)) != HPF_OK)
+                    goto done;
+                if ((st = hpf_batch_step(b, 1, 0, stream)) != HPF_OK)      // warm-up
+                    goto done;
+                if (hipEventRecord(e0, s) != hipSuccess) {
+                    st = HPF_EHIP;
+                    goto done;
+                }
+                if ((st = hpf_batch_step(b, trial_steps, 0, stream)) != HPF_OK)
+                    goto done;
+                float ms = 0.0f;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    st = HPF_EHIP;
+                    goto done;
+                }
+                ms /= trial_steps;
+                if (trial_ms)
+                    trial_ms[t] = ms;
+                ++t;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = b->cfg;
+                }
+            }
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->cfg = best;
+    if (st == HPF_OK)
+        st = batch_build_items(b);
+    if (chosen)
+        *chosen = b->cfg;
+    if (n_trials)
+        *n_trials = t;
+    return st;
+}
+
+// ------------------------------------------------------------------ graphs
+
+struct hpf_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+hpf_status_t hpf_graph_begin(void* stream)
+{
+    if (!stream)
+        return HPF_EINVAL;   // the null stream cannot be captured
+    return hipStreamBeginCapture(as_stream(stream), hipStreamCaptureModeThreadLocal) == hipSuccess ? HPF_OK
+                                                                                                  : HPF_EHIP;
+}
+
+hpf_status_t hpf_graph_end(void* stream, hpf_graph_t** out)
+{
+    if (!stream || !out)
+        return HPF_EINVAL;
+    *out = nullptr;
+    hpf_graph* g = new (std::nothrow) hpf_graph;
+    if (!g)
+        return HPF_EINVAL;
+    if (hipStreamEndCapture(as_stream(stream), &g->graph) != hipSuccess ||
+        hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+        if (g->graph)
+            (void)hipGraphDestroy(g->graph);
+        delete g;
+        return HPF_EHIP;
+    }
+    *out = g;
+    return HPF_OK;
+}
+
+hpf_status_t hpf_graph_launch(hpf_graph_t* g, void* stream)
+{
+    if (!g)
+        return HPF_EINVAL;
+    return hipGraphLaunch(g->exec, as_stream(stream)) == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+hpf_status_t hpf_graph_destroy(hpf_graph_t* g)
+{
+    if (!g)
+        return HPF_EINVAL;
+    if (g->exec)
+        (void)hipGraphExecDestroy(g->exec);
+    if (g->graph)
+        (void)hipGraphDestroy(g->graph);
+    delete g;
+    return HPF_OK;
+}
+
+}  // extern "C"

@@ -14,9 +14,42 @@ struct PotK {
 
 constexpr int kPotThreads = 256;
 
-// One thread per mesh point (grid-stride): phi_K = n_K c_norm in FP64,
+// Potential at mesh point q of one system: phi_K = n_K c_norm in FP64,
 // V_K = sum_K' A_KK' phi_K' + inv_kappa (sum phi - 1) stored as FP32, counts
-// cleared for the next scatter. Optional FP64 field-energy partials.
+// cleared for the next scatter. Returns the point's field-energy term
+// (without the rho0 dV factor).
+template <int K>
+__device__ __forceinline__ double potential_point(unsigned long long* __restrict__ counts,
+                                                  float* __restrict__ V, int64_t nm, int64_t q,
+                                                  double c_norm, const PotK& p, bool& over)
+{
+    double phi[K];
+    double tot = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const unsigned long long n = counts[k * nm + q];
+        over |= n >= (1ull << 62);
+        phi[k] = (double)n * c_norm;
+        tot += phi[k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        counts[k * nm + q] = 0ull;
+    const double delta = tot - 1.0;
+    double inter = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double mix = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk)
+            mix += p.A[k * K + kk] * phi[kk];
+        V[k * nm + q] = (float)(mix + p.inv_kappa * delta);
+        inter += phi[k] * mix;
+    }
+    return 0.5 * inter + 0.5 * p.inv_kappa * delta * delta;
+}
+
+// One thread per mesh point (grid-stride); optional FP64 field-energy partials.
 template <int K>
 __global__ __launch_bounds__(kPotThreads) void k_field_potential(unsigned long long* __restrict__ counts,
                                                                  MeshK m, PotK p,
@@ -32,32 +65,8 @@ __global__ __launch_bounds__(kPotThreads) void k_field_potential(unsigned long l
         for (int64_t i = (int64_t)gridDim.x + blockIdx.x + (int64_t)threadIdx.x * gridDim.x; i < HPF_NPART;
              i += (int64_t)kPotThreads * gridDim.x)
             w_part[i] = 0.0;
-    for (int64_t v = b * kPotThreads + threadIdx.x; v < nm; v += (int64_t)gridDim.x * kPotThreads) {
-        double phi[K];
-        double tot = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const unsigned long long n = counts[k * nm + v];
-            over |= n >= (1ull << 62);
-            phi[k] = (double)n * m.c_norm;
-            tot += phi[k];
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            counts[k * nm + v] = 0ull;
-        const double delta = tot - 1.0;
-        double inter = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double mix = 0.0;
-#pragma unroll
-            for (int kk = 0; kk < K; ++kk)
-                mix += p.A[k * K + kk] * phi[kk];
-            V[k * nm + v] = (float)(mix + p.inv_kappa * delta);
-            inter += phi[k] * mix;
-        }
-        wsum += 0.5 * inter + 0.5 * p.inv_kappa * delta * delta;
-    }
+    for (int64_t v = b * kPotThreads + threadIdx.x; v < nm; v += (int64_t)gridDim.x * kPotThreads)
+        wsum += potential_point<K>(counts, V, nm, v, m.c_norm, p, over);
     if (over)
         raise_flag(HPF_FLAG_OVERFLOW);
     if (w_part) {
@@ -92,19 +101,11 @@ hpf_status_t launch_field_potential(uint64_t* counts, const MeshK& m, int K, con
 
 constexpr int kGradX = 64, kGradY = 4;
 
-// One thread per mesh point: a 64 x 4 block covers a patch of an xy plane,
-// so the +-x neighbours are in the same or adjacent cache lines and the +-y
-// and +-z rows are re-read from L2 by neighbouring blocks.
-__global__ __launch_bounds__(kGradX * kGradY) void k_field_gradient(const float* __restrict__ V,
-                                                                    MeshK m, int K,
-                                                                    float4* __restrict__ G)
+// Centred gradient at mesh point (x, y, z), all species: G = (gx, gy, gz, V).
+__device__ __forceinline__ void gradient_point(const float* __restrict__ V, const MeshK& m, int K, int x, int y,
+                                               int z, float4* __restrict__ G)
 {
-    const int x = blockIdx.x * kGradX + threadIdx.x;
-    const int y = blockIdx.y * kGradY + threadIdx.y;
-    const int z = blockIdx.z;
     const int Mx = m.M[0], My = m.M[1], Mz = m.M[2];
-    if (x >= Mx || y >= My)
-        return;
     const int xp = next_wrap(x, Mx), xm = prev_wrap(x, Mx);
     const int64_t row = ((int64_t)z * My + y) * Mx;
     const int64_t rowyp = ((int64_t)z * My + next_wrap(y, My)) * Mx;
@@ -121,6 +122,20 @@ __global__ __launch_bounds__(kGradX * kGradY) void k_field_gradient(const float*
         g.w = Vk[row + x];
         G[k * m.nm + row + x] = g;
     }
+}
+
+// One thread per mesh point: a 64 x 4 block covers a patch of an xy plane,
+// so the +-x neighbours are in the same or adjacent cache lines and the +-y
+// and +-z rows are re-read from L2 by neighbouring blocks.
+__global__ __launch_bounds__(kGradX * kGradY) void k_field_gradient(const float* __restrict__ V,
+                                                                    MeshK m, int K,
+                                                                    float4* __restrict__ G)
+{
+    const int x = blockIdx.x * kGradX + threadIdx.x;
+    const int y = blockIdx.y * kGradY + threadIdx.y;
+    if (x >= m.M[0] || y >= m.M[1])
+        return;
+    gradient_point(V, m, K, x, y, blockIdx.z, G);
 }
 
 hpf_status_t launch_field_gradient(const float* V, const MeshK& m, int K, float* G, hipStream_t s)

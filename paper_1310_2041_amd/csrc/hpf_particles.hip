@@ -188,18 +188,23 @@ struct KinAcc {
         py += mass * vy;
         pz += mass * vz;
     }
-    __device__ __forceinline__ void store(double* part, int64_t slot, double* scratch)
+    // rows of `stride` slots: KE, Px, Py, Pz
+    __device__ __forceinline__ void store_rows(double* part, int64_t stride, int64_t slot, double* scratch)
     {
         const double a = block_sum(ke, scratch);
         const double b = block_sum(px, scratch);
         const double c = block_sum(py, scratch);
         const double d = block_sum(pz, scratch);
         if (threadIdx.x == 0) {
-            part[0 * HPF_NPART + slot] = a;
-            part[1 * HPF_NPART + slot] = b;
-            part[2 * HPF_NPART + slot] = c;
-            part[3 * HPF_NPART + slot] = d;
+            part[0 * stride + slot] = a;
+            part[1 * stride + slot] = b;
+            part[2 * stride + slot] = c;
+            part[3 * stride + slot] = d;
         }
+    }
+    __device__ __forceinline__ void store(double* part, int64_t slot, double* scratch)
+    {
+        store_rows(part, HPF_NPART, slot, scratch);
     }
 };
 
@@ -305,10 +310,43 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__
         acc.store(kin_part, w.block, scratch);
 }
 
-// Fused pass over the beads: field force + bond forces at x_n, second half
+// One bead of the fused pass: field force + bond forces at x_n, second half
 // kick of step n (kinetic-energy partials at v_n), first half kick and drift
-// of step n + 1. Positions go to R_next so that bond partners are always read
-// at x_n.
+// of step n + 1, written to R_next.
+template <bool kR0Zero>
+__device__ __forceinline__ void advance_bead(int64_t i, const float4* __restrict__ R, float4* __restrict__ R_next,
+                                             float4* __restrict__ Vel, const uint8_t* __restrict__ T,
+                                             int64_t N, const MeshK& m, int K, const float4* __restrict__ G,
+                                             const int32_t* __restrict__ bonds, int D, float k, float r0,
+                                             const BoxK& box, const float* __restrict__ inv_mass, float dt,
+                                             float hdt, float4* __restrict__ F_out, KinAcc& acc, double& e,
+                                             bool& bad_bead, bool& bad_bond, bool& nonfinite)
+{
+    float4 r = R[i];
+    float3 ff;
+    bad_bead |= !field_force(r, T[i], m, K, G, ff);
+    float ei;
+    const float3 fb = bond_sum<kR0Zero>(i, r, R, N, bonds, D, k, r0, box, ei, bad_bond);
+    float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
+    f.x += fb.x;
+    f.y += fb.y;
+    f.z += fb.z;
+    e += 0.5 * (double)ei;
+    if (F_out)
+        F_out[i] = f;
+    const float im = inv_mass ? inv_mass[i] : 1.0f;
+    float4 v = Vel[i];
+    kick(v, f, im, hdt);                 // v_n
+    acc.add(v, im);
+    kick(v, f, im, hdt);                 // v_{n+1/2}
+    drift(r, v, dt, box);                // x_{n+1}
+    nonfinite |= !(finite4(r) && finite4(v));
+    Vel[i] = v;
+    R_next[i] = r;
+}
+
+// Fused pass over the beads. Positions go to R_next so that bond partners
+// are always read at x_n.
 template <bool kR0Zero>
 __global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict__ R,
                                                        float4* __restrict__ R_next,
@@ -331,27 +369,8 @@ __global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict_
     double e = 0.0;
     bool bad_bead = false, bad_bond = false, nonfinite = false;
     FOR_BEADS(w, i) {
-        float4 r = R[i];
-        float3 ff;
-        bad_bead |= !field_force(r, T[i], m, K, G, ff);
-        float ei;
-        const float3 fb = bond_sum<kR0Zero>(i, r, R, N, bonds, D, k, r0, box, ei, bad_bond);
-        float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
-        f.x += fb.x;
-        f.y += fb.y;
-        f.z += fb.z;
-        e += 0.5 * (double)ei;
-        if (F_out)
-            F_out[i] = f;
-        const float im = inv_mass ? inv_mass[i] : 1.0f;
-        float4 v = Vel[i];
-        kick(v, f, im, hdt);                 // v_n
-        acc.add(v, im);
-        kick(v, f, im, hdt);                 // v_{n+1/2}
-        drift(r, v, dt, box);                // x_{n+1}
-        nonfinite |= !(finite4(r) && finite4(v));
-        Vel[i] = v;
-        R_next[i] = r;
+        advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box, inv_mass, dt, hdt, F_out,
+                              acc, e, bad_bead, bad_bond, nonfinite);
     }
     if (bad_bead)
         raise_flag(HPF_FLAG_BAD_BEAD);

@@ -80,12 +80,13 @@ __device__ __forceinline__ void lds_add_u64(unsigned long long* p, unsigned long
 // binned are staged and appended to the stray list.
 constexpr int kScBatch = 4;
 
-__global__ __launch_bounds__(kTcThreads) void k_scatter_bricks(const float4* __restrict__ R,
-                                                               const uint8_t* __restrict__ T, int K,
-                                                               TileK tk,
-                                                               const uint32_t* __restrict__ cell_start,
-                                                               unsigned long long* __restrict__ partials,
-                                                               uint32_t* __restrict__ strays)
+// Deposit of the beads listed in `brick` (cell_start of this system, i.e.
+// already offset for batched systems) into an LDS box, stored to `out`.
+__device__ __forceinline__ void scatter_brick_body(const float4* __restrict__ R, const uint8_t* __restrict__ T,
+                                                   int K, const TileK& tk,
+                                                   const uint32_t* __restrict__ cell_start, int64_t brick,
+                                                   unsigned long long* __restrict__ out,
+                                                   uint32_t* __restrict__ strays)
 {
     extern __shared__ unsigned long long smem[];
     __shared__ uint32_t stray_buf[kStrayStage];
@@ -93,7 +94,6 @@ __global__ __launch_bounds__(kTcThreads) void k_scatter_bricks(const float4* __r
     const int tid = threadIdx.x;
     const int B = tk.B, h = tk.h, P = tk.P;
     const int Mx = tk.m.M[0], My = tk.m.M[1], Mz = tk.m.M[2];
-    const int64_t brick = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(brick % tk.nb[0]);
     const int by = (int)((brick / tk.nb[0]) % tk.nb[1]);
     const int bz = (int)(brick / ((int64_t)tk.nb[0] * tk.nb[1]));
@@ -107,7 +107,6 @@ __global__ __launch_bounds__(kTcThreads) void k_scatter_bricks(const float4* __r
     if (tid == 0)
         stray_n = 0;
     __syncthreads();
-
     const uint32_t B3 = (uint32_t)(B * B * B);
     const uint32_t first = cell_start[(uint32_t)brick * B3];
     const uint32_t last = cell_start[(uint32_t)(brick + 1) * B3];
@@ -172,9 +171,20 @@ __global__ __launch_bounds__(kTcThreads) void k_scatter_bricks(const float4* __r
     __syncthreads();
     for (uint32_t i = tid; i < nst; i += kTcThreads)
         strays[1 + stray_base + i] = stray_buf[i];
-    unsigned long long* out = partials + brick * (int64_t)nbox;
     for (int e = tid; e < nbox; e += kTcThreads)
         out[e] = box[e];
+}
+
+__global__ __launch_bounds__(kTcThreads) void k_scatter_bricks(const float4* __restrict__ R,
+                                                               const uint8_t* __restrict__ T, int K,
+                                                               TileK tk,
+                                                               const uint32_t* __restrict__ cell_start,
+                                                               unsigned long long* __restrict__ partials,
+                                                               uint32_t* __restrict__ strays)
+{
+    const int64_t brick = xcd_block(blockIdx.x, gridDim.x);
+    const int P = tk.P;
+    scatter_brick_body(R, T, K, tk, cell_start, brick, partials + brick * (int64_t)K * P * P * P, strays);
 }
 
 // Pass 2: one thread per mesh point sums the partial boxes that cover it and
@@ -223,14 +233,13 @@ __device__ __forceinline__ Cover covering(int v, int B, int h, int nb, int M)
 // One workgroup per brick: the cover lists of the brick's coordinates along
 // each axis are built once in LDS, then each thread sums the partial boxes for
 // its points (consecutive threads -> consecutive x -> coalesced reads).
-__global__ __launch_bounds__(256) void k_scatter_sum(const unsigned long long* __restrict__ partials,
-                                                     TileK tk, int K,
-                                                     unsigned long long* __restrict__ counts)
+__device__ __forceinline__ void scatter_sum_body(const unsigned long long* __restrict__ partials,
+                                                 const TileK& tk, int K, int64_t brick,
+                                                 unsigned long long* __restrict__ counts)
 {
     __shared__ Cover cov[3][kTcMaxB];
     const int tid = threadIdx.x;
     const int B = tk.B, h = tk.h, P = tk.P, P3 = P * P * P;
-    const int64_t brick = xcd_block(blockIdx.x, gridDim.x);
     const int bxyz[3] = {(int)(brick % tk.nb[0]), (int)((brick / tk.nb[0]) % tk.nb[1]),
                          (int)(brick / ((int64_t)tk.nb[0] * tk.nb[1]))};
     int o[3];
@@ -265,9 +274,45 @@ __global__ __launch_bounds__(256) void k_scatter_sum(const unsigned long long* _
     }
 }
 
+__global__ __launch_bounds__(256) void k_scatter_sum(const unsigned long long* __restrict__ partials,
+                                                     TileK tk, int K,
+                                                     unsigned long long* __restrict__ counts)
+{
+    scatter_sum_body(partials, tk, K, xcd_block(blockIdx.x, gridDim.x), counts);
+}
+
 __device__ __forceinline__ void atomic_add_u64_agent(unsigned long long* p, unsigned long long v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Eight global u64 atomics of one bead; false if it cannot be binned.
+__device__ __forceinline__ bool deposit_global(const float4& r, int t, int K, const MeshK& m,
+                                               unsigned long long* __restrict__ counts)
+{
+    BeadCell b;
+    if (!(bead_cell(r, m, b) && t < K))
+        return false;
+    const int32_t x0 = b.c[0], x1 = next_wrap(x0, m.M[0]);
+    const int32_t y0 = b.c[1], y1 = next_wrap(y0, m.M[1]);
+    const int32_t z0 = b.c[2], z1 = next_wrap(z0, m.M[2]);
+    const uint64_t wx0 = kOne - b.q[0], wx1 = b.q[0];
+    const uint64_t wy0 = kOne - b.q[1], wy1 = b.q[1];
+    const uint64_t wz0 = kOne - b.q[2], wz1 = b.q[2];
+    unsigned long long* nk = counts + (int64_t)t * m.nm;
+    const int64_t r00 = ((int64_t)z0 * m.M[1] + y0) * m.M[0];
+    const int64_t r10 = ((int64_t)z0 * m.M[1] + y1) * m.M[0];
+    const int64_t r01 = ((int64_t)z1 * m.M[1] + y0) * m.M[0];
+    const int64_t r11 = ((int64_t)z1 * m.M[1] + y1) * m.M[0];
+    atomic_add_u64_agent(nk + r00 + x0, wx0 * wy0 * wz0);
+    atomic_add_u64_agent(nk + r00 + x1, wx1 * wy0 * wz0);
+    atomic_add_u64_agent(nk + r10 + x0, wx0 * wy1 * wz0);
+    atomic_add_u64_agent(nk + r10 + x1, wx1 * wy1 * wz0);
+    atomic_add_u64_agent(nk + r01 + x0, wx0 * wy0 * wz1);
+    atomic_add_u64_agent(nk + r01 + x1, wx1 * wy0 * wz1);
+    atomic_add_u64_agent(nk + r11 + x0, wx0 * wy1 * wz1);
+    atomic_add_u64_agent(nk + r11 + x1, wx1 * wy1 * wz1);
+    return true;
 }
 
 // Global-atomic deposit of the stray beads and of the beads the sort could not
@@ -286,32 +331,7 @@ __global__ __launch_bounds__(kTcThreads) void k_scatter_strays(const float4* __r
     for (int64_t j = (int64_t)blockIdx.x * kTcThreads + threadIdx.x; j < total;
          j += (int64_t)gridDim.x * kTcThreads) {
         const int64_t p = j < nstray ? (int64_t)strays[1 + j] : tail0 + (j - nstray);
-        const float4 r = R[p];
-        const int t = T[p];
-        BeadCell b;
-        if (!(bead_cell(r, m, b) && t < K)) {
-            bad = true;
-            continue;
-        }
-        const int32_t x0 = b.c[0], x1 = next_wrap(x0, m.M[0]);
-        const int32_t y0 = b.c[1], y1 = next_wrap(y0, m.M[1]);
-        const int32_t z0 = b.c[2], z1 = next_wrap(z0, m.M[2]);
-        const uint64_t wx0 = kOne - b.q[0], wx1 = b.q[0];
-        const uint64_t wy0 = kOne - b.q[1], wy1 = b.q[1];
-        const uint64_t wz0 = kOne - b.q[2], wz1 = b.q[2];
-        unsigned long long* nk = counts + (int64_t)t * m.nm;
-        const int64_t r00 = ((int64_t)z0 * m.M[1] + y0) * m.M[0];
-        const int64_t r10 = ((int64_t)z0 * m.M[1] + y1) * m.M[0];
-        const int64_t r01 = ((int64_t)z1 * m.M[1] + y0) * m.M[0];
-        const int64_t r11 = ((int64_t)z1 * m.M[1] + y1) * m.M[0];
-        atomic_add_u64_agent(nk + r00 + x0, wx0 * wy0 * wz0);
-        atomic_add_u64_agent(nk + r00 + x1, wx1 * wy0 * wz0);
-        atomic_add_u64_agent(nk + r10 + x0, wx0 * wy1 * wz0);
-        atomic_add_u64_agent(nk + r10 + x1, wx1 * wy1 * wz0);
-        atomic_add_u64_agent(nk + r01 + x0, wx0 * wy0 * wz1);
-        atomic_add_u64_agent(nk + r01 + x1, wx1 * wy0 * wz1);
-        atomic_add_u64_agent(nk + r11 + x0, wx0 * wy1 * wz1);
-        atomic_add_u64_agent(nk + r11 + x1, wx1 * wy1 * wz1);
+        bad |= !deposit_global(R[p], T[p], K, m, counts);
     }
     if (bad)
         raise_flag(HPF_FLAG_BAD_BEAD);

@@ -41,26 +41,6 @@ __global__ __launch_bounds__(kSortThreads) void k_copy_u32(const uint32_t* __res
         b[i] = a[i];
 }
 
-// Runs of equal keys inside a wavefront: beads arrive nearly in cell order,
-// so neighbouring lanes usually share a key. Returns the lane mask of run
-// heads; *len = length of the run this lane heads (heads only), *head = the
-// head lane of this lane's run.
-__device__ __forceinline__ void wave_runs(uint32_t key, bool active, int* head, int* len)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t prev = __shfl_up(key, 1, kWave);
-    const bool is_head = active && (lane == 0 || prev != key);
-    const uint64_t heads = __ballot(is_head);
-    const uint64_t act = __ballot(active);
-    // head of my run: highest head lane <= lane
-    const uint64_t below = heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1));
-    *head = below ? 63 - __builtin_clzll(below) : lane;
-    // run length: up to the next head or the last active lane
-    const uint64_t above = heads & ~((2ull << lane) - 1 | (lane == 63 ? ~0ull : 0ull));
-    const int next = above ? __builtin_ctzll(above) : 64 - __builtin_clzll(act);
-    *len = next - lane;
-}
-
 __global__ __launch_bounds__(kSortThreads) void k_sort_keys(const float4* __restrict__ R, int64_t N,
                                                             SortK sk, uint32_t* __restrict__ keys,
                                                             uint32_t* __restrict__ hist)

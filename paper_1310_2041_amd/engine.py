@@ -196,3 +196,147 @@ class HpfState:
         """(R, Vel, T, tag, bonds) as numpy arrays, in current storage order."""
         return (self.R.cpu().numpy(), self.Vel.cpu().numpy(), self.T.cpu().numpy(),
                 self.tag.cpu().numpy(), self.bonds.cpu().numpy())
+
+
+# ------------------------------------------------------------------ batches
+
+class BatchState:
+    """Many replicas advanced together through the batched entry points.
+
+    Replicas are concatenated in the given order: beads (global bond indices
+    and tags), and meshes. Each replica keeps its own box, mesh and chi; K,
+    bond parameters and dt are shared.
+    """
+
+    def __init__(self, systems, sort_every=10, brick=8, halo=1, bead_chunk=4096,
+                 mesh_chunk=16384, device="cuda"):
+        dev = torch.device(device)
+        s0 = systems[0]
+        self.K = int(s0.K)
+        self.D = int(s0.bonds.shape[0])
+        self.n_rep = len(systems)
+        offs = np.cumsum([0] + [s.N for s in systems])
+        self.offsets = offs
+        self.Ntot = int(offs[-1])
+        R = np.concatenate([s.R for s in systems])
+        V = np.concatenate([s.V for s in systems])
+        T = np.concatenate([s.T for s in systems])
+        tag = np.arange(self.Ntot, dtype=np.int32)
+        bonds = np.concatenate([np.where(s.bonds >= 0, s.bonds + o, -1).astype(np.int32)
+                                for s, o in zip(systems, offs[:-1])], axis=1)
+
+        def up(a, dtype):
+            return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dtype).contiguous()
+
+        self.R = [up(R, torch.float32), torch.empty((self.Ntot, 4), dtype=torch.float32, device=dev)]
+        self.Vel = [up(V, torch.float32), torch.empty((self.Ntot, 4), dtype=torch.float32, device=dev)]
+        self.T = [up(T, torch.uint8), torch.empty(self.Ntot, dtype=torch.uint8, device=dev)]
+        self.tag = [up(tag, torch.int32), torch.empty(self.Ntot, dtype=torch.int32, device=dev)]
+        self.bonds = [up(bonds, torch.int32), torch.empty_like(up(bonds, torch.int32))]
+        self.nm = [int(np.prod(s.M)) for s in systems]
+        nm_tot = sum(self.nm)
+        self.counts = torch.zeros(self.K * nm_tot, dtype=torch.int64, device=dev)
+        self.V = torch.empty(self.K * nm_tot, dtype=torch.float32, device=dev)
+        self.G = torch.empty(self.K * nm_tot * 4, dtype=torch.float32, device=dev)
+        reps = []
+        for s, o in zip(systems, offs[:-1]):
+            r = hpf.Replica()
+            r.bead_offset = int(o)
+            r.n_beads = s.N
+            r.L[:] = [float(x) for x in s.L]
+            r.M[:] = [int(x) for x in s.M]
+            r.kT = float(s.kT)
+            r.inv_kappa = float(s.inv_kappa)
+            for a in range(self.K):
+                for b in range(self.K):
+                    r.chi[a * self.K + b] = float(s.chi[a][b])
+            reps.append(r)
+        self.reps = reps
+        cfg = hpf.BatchConfig()
+        cfg.K, cfg.D = self.K, self.D
+        cfg.k_bond, cfg.r0, cfg.dt = float(s0.k_bond), float(s0.r0), float(s0.dt)
+        cfg.brick, cfg.halo, cfg.sort_every = brick, halo, sort_every
+        cfg.bead_chunk, cfg.mesh_chunk = bead_chunk, mesh_chunk
+        self.cfg = cfg
+        ws = hpf.hpf_batch_workspace_bytes(reps, cfg)
+        if ws == 0:
+            raise ValueError("batch sizes not supported (mesh edges must be >= brick + 5)")
+        self.work = torch.empty(ws, dtype=torch.uint8, device=dev)
+        bufs = hpf.BatchBuffers()
+        for i in range(2):
+            bufs.R[i] = self.R[i].data_ptr()
+            bufs.Vel[i] = self.Vel[i].data_ptr()
+            bufs.T[i] = self.T[i].data_ptr()
+            bufs.tag[i] = self.tag[i].data_ptr()
+            bufs.bonds[i] = self.bonds[i].data_ptr() if self.D else None
+        bufs.counts = self.counts.data_ptr()
+        bufs.V = self.V.data_ptr()
+        bufs.G = self.G.data_ptr()
+        self.bufs = bufs
+        self.handle = hpf.hpf_batch_create(reps, cfg, bufs, self.work)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            hpf.hpf_batch_destroy(h)
+            self.handle = None
+
+    def start(self, stream=None):
+        hpf.hpf_batch_start(self.handle, stream)
+
+    def step(self, n=1, report_last=True, stream=None):
+        hpf.hpf_batch_step(self.handle, n, report_last, stream)
+
+    def tune(self, trial_steps=3, stream=None):
+        cfg, ms = hpf.hpf_batch_tune(self.handle, trial_steps, stream)
+        self.cfg = cfg
+        return {"halo": cfg.halo, "bead_chunk": cfg.bead_chunk, "mesh_chunk": cfg.mesh_chunk}, ms
+
+    def _current(self, name):
+        ptr = hpf.hpf_batch_current(self.handle)[name]
+        for t in getattr(self, name):
+            if t.data_ptr() == ptr:
+                return t
+        raise RuntimeError("unknown current buffer")
+
+    def energies(self) -> np.ndarray:
+        """[n_rep, 8] = KE, E_bond, W, E_tot, Px, Py, Pz, 0 of the last reporting step."""
+        ptr = hpf.hpf_batch_current(self.handle)["energies"]
+        off = ptr - self.work.data_ptr()
+        e = self.work[off:off + 64 * self.n_rep].view(torch.float64).reshape(self.n_rep, 8)
+        return e.cpu().numpy()
+
+    def replica_beads(self, r):
+        """(R, Vel, T, tag - offset, bonds - offset) of replica r, in storage order."""
+        a, b = int(self.offsets[r]), int(self.offsets[r + 1])
+        R = self._current("R")[a:b].cpu().numpy()
+        V = self._current("Vel")[a:b].cpu().numpy()
+        T = self._current("T")[a:b].cpu().numpy()
+        tag = self._current("tag")[a:b].cpu().numpy() - a
+        bonds = self._current("bonds")[:, a:b].cpu().numpy()
+        bonds = np.where(bonds >= 0, bonds - a, -1)
+        return R, V, T, tag, bonds
+
+
+class Graph:
+    """A HIP graph of whatever library calls `fn` enqueues on a private stream."""
+
+    def __init__(self, fn):
+        self.stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(self.stream):
+            hpf.hpf_graph_begin(self.stream)
+            try:
+                fn()
+            finally:
+                self.handle = hpf.hpf_graph_end(self.stream)
+
+    def launch(self):
+        hpf.hpf_graph_launch(self.handle, self.stream)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            torch.cuda.synchronize()
+            hpf.hpf_graph_destroy(h)
+            self.handle = None

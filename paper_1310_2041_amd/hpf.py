@@ -49,6 +49,27 @@ class Field(C.Structure):
                 ("inv_kappa", C.c_double), ("chi", C.c_double * (HPF_MAX_TYPES * HPF_MAX_TYPES))]
 
 
+class Replica(C.Structure):
+    """hpf_replica_t"""
+    _fields_ = [("bead_offset", C.c_int64), ("n_beads", C.c_int64), ("L", C.c_float * 3),
+                ("M", C.c_int32 * 3), ("kT", C.c_double), ("inv_kappa", C.c_double),
+                ("chi", C.c_double * (HPF_MAX_TYPES * HPF_MAX_TYPES))]
+
+
+class BatchConfig(C.Structure):
+    """hpf_batch_config_t"""
+    _fields_ = [("K", C.c_int32), ("D", C.c_int32), ("k_bond", C.c_float), ("r0", C.c_float),
+                ("dt", C.c_float), ("brick", C.c_int32), ("halo", C.c_int32),
+                ("sort_every", C.c_int32), ("bead_chunk", C.c_int32), ("mesh_chunk", C.c_int32)]
+
+
+class BatchBuffers(C.Structure):
+    """hpf_batch_buffers_t"""
+    _fields_ = [("R", C.c_void_p * 2), ("Vel", C.c_void_p * 2), ("T", C.c_void_p * 2),
+                ("tag", C.c_void_p * 2), ("bonds", C.c_void_p * 2), ("counts", C.c_void_p),
+                ("V", C.c_void_p), ("G", C.c_void_p)]
+
+
 _lib = None
 _P = C.c_void_p
 
@@ -74,6 +95,23 @@ _SIGNATURES = {
     "hpf_sort_by_cell": ([C.POINTER(Mesh), C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
                           _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int32),
     "hpf_get_device_status": ([C.POINTER(C.c_uint32), C.c_int32, _P], C.c_int32),
+    "hpf_batch_workspace_bytes": ([C.POINTER(Replica), C.c_int32, C.POINTER(BatchConfig)],
+                                  C.c_size_t),
+    "hpf_batch_create": ([C.POINTER(Replica), C.c_int32, C.POINTER(BatchConfig),
+                          C.POINTER(BatchBuffers), _P, C.c_size_t, C.POINTER(C.c_void_p)],
+                         C.c_int32),
+    "hpf_batch_start": ([_P, _P], C.c_int32),
+    "hpf_batch_step": ([_P, C.c_int32, C.c_int32, _P], C.c_int32),
+    "hpf_batch_current": ([_P, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                           C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                           C.POINTER(C.c_void_p)], C.c_int32),
+    "hpf_batch_tune": ([_P, C.c_int32, _P, C.POINTER(BatchConfig), C.POINTER(C.c_float),
+                        C.POINTER(C.c_int32)], C.c_int32),
+    "hpf_batch_destroy": ([_P], C.c_int32),
+    "hpf_graph_begin": ([_P], C.c_int32),
+    "hpf_graph_end": ([_P, C.POINTER(C.c_void_p)], C.c_int32),
+    "hpf_graph_launch": ([_P, _P], C.c_int32),
+    "hpf_graph_destroy": ([_P], C.c_int32),
 }
 
 
@@ -327,3 +365,65 @@ def hpf_get_device_status(clear: bool = True, stream=None) -> int:
     _check("hpf_get_device_status",
            lib().hpf_get_device_status(C.byref(flags), int(bool(clear)), _stream(stream)))
     return int(flags.value)
+
+
+# ------------------------------------------------------------ batch / graph
+
+def hpf_batch_workspace_bytes(reps, cfg: BatchConfig) -> int:
+    arr = (Replica * len(reps))(*reps)
+    return int(lib().hpf_batch_workspace_bytes(arr, len(reps), C.byref(cfg)))
+
+
+def hpf_batch_create(reps, cfg: BatchConfig, bufs: BatchBuffers, work) -> C.c_void_p:
+    arr = (Replica * len(reps))(*reps)
+    h = C.c_void_p()
+    w = _dev(work, "work", torch.uint8)
+    _check("hpf_batch_create", lib().hpf_batch_create(arr, len(reps), C.byref(cfg), C.byref(bufs), w,
+                                                      work.numel(), C.byref(h)))
+    return h
+
+
+def hpf_batch_start(h, stream=None):
+    _check("hpf_batch_start", lib().hpf_batch_start(h, _stream(stream)))
+
+
+def hpf_batch_step(h, n_steps: int, report_last: bool = True, stream=None):
+    _check("hpf_batch_step", lib().hpf_batch_step(h, int(n_steps), int(bool(report_last)),
+                                                  _stream(stream)))
+
+
+def hpf_batch_current(h) -> dict:
+    ptrs = [C.c_void_p() for _ in range(6)]
+    _check("hpf_batch_current", lib().hpf_batch_current(h, *[C.byref(p) for p in ptrs]))
+    return dict(zip(["R", "Vel", "T", "tag", "bonds", "energies"], [p.value for p in ptrs]))
+
+
+def hpf_batch_tune(h, trial_steps: int, stream=None):
+    cfg = BatchConfig()
+    ms = (C.c_float * 16)()
+    n = C.c_int32()
+    _check("hpf_batch_tune", lib().hpf_batch_tune(h, int(trial_steps), _stream(stream),
+                                                  C.byref(cfg), ms, C.byref(n)))
+    return cfg, [ms[i] for i in range(n.value)]
+
+
+def hpf_batch_destroy(h):
+    _check("hpf_batch_destroy", lib().hpf_batch_destroy(h))
+
+
+def hpf_graph_begin(stream):
+    _check("hpf_graph_begin", lib().hpf_graph_begin(_stream(stream)))
+
+
+def hpf_graph_end(stream) -> C.c_void_p:
+    g = C.c_void_p()
+    _check("hpf_graph_end", lib().hpf_graph_end(_stream(stream), C.byref(g)))
+    return g
+
+
+def hpf_graph_launch(g, stream=None):
+    _check("hpf_graph_launch", lib().hpf_graph_launch(g, _stream(stream)))
+
+
+def hpf_graph_destroy(g):
+    _check("hpf_graph_destroy", lib().hpf_graph_destroy(g))

@@ -1,0 +1,49 @@
+"""Short fused-step run used as the target of rocprofv3 counter passes.
+
+python -m paper_1310_2041_amd.profile_step [--config c3] [--steps 12]
+
+Runs the workload's start, the first half step and `steps` fused steps
+(sorting every 10, reporting energies every step), then a plain 1 GiB device
+copy whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters
+(bytes per reported KiB).
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+COPY_BYTES = 1 << 30
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--steps", type=int, default=12)
+    args = ap.parse_args()
+    import torch
+
+    from paper_1310_2041_amd import engine
+    from synth import workloads as wl
+
+    s = wl.build(wl.SPECS[args.config])
+    st = engine.HpfState.from_system(s)
+    del s
+    st.start(sort=True)
+    st.prime()
+    for k in range(args.steps):
+        st.step_fused(report=True, sort=k % 10 == 0)
+    torch.cuda.synchronize()
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("profile_step done", flush=True)
+
+
+if __name__ == "__main__":
+    main()
