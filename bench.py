@@ -205,12 +205,9 @@ ROCPROF_KERNELS = {
 def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of
     `workload`, or None when there is none or the kernel sources changed since."""
-    from paper_1310_2041_amd.profile_summary import source_hash
-    path = os.path.join(ROOT, "profiles", f"{workload}_step.json")
-    if not os.path.exists(path):
-        return None
-    d = json.load(open(path))
-    if d.get("source_hash") != source_hash():
+    from paper_1310_2041_amd.profile_summary import read_record, source_hash
+    d = read_record(os.path.join(ROOT, "profiles", f"{workload}_step.md"))
+    if d is None or d.get("source_hash") != source_hash():
         return None
     tot, found = 0.0, False
     for k in ROCPROF_KERNELS.get(kernel, []):

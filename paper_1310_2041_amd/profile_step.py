@@ -1,11 +1,13 @@
 """Short fused-step run used as the target of rocprofv3 counter passes.
 
-python -m paper_1310_2041_amd.profile_step [--config c3] [--steps 12]
+python -m paper_1310_2041_amd.profile_step [--config c3|c4] [--steps 12]
 
-Runs the workload's start, the first half step and `steps` fused steps
-(sorting every 10, reporting energies every step), then a plain 1 GiB device
-copy whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters
-(bytes per reported KiB).
+c1..c3: the workload's start, the first half step and `steps` fused steps
+(sorting every 10, reporting energies every step).
+c4: the 64-replica A10B10 sweep stepped `steps` times through the batched
+entry points (sorting every 10, energies on the last step).
+Both end with a plain 1 GiB device copy whose FETCH_SIZE / WRITE_SIZE
+readings calibrate the counters (bytes per reported KiB).
 """
 from __future__ import annotations
 
@@ -30,13 +32,20 @@ def main():
     from paper_1310_2041_amd import engine
     from synth import workloads as wl
 
-    s = wl.build(wl.SPECS[args.config])
-    st = engine.HpfState.from_system(s)
-    del s
-    st.start(sort=True)
-    st.prime()
-    for k in range(args.steps):
-        st.step_fused(report=True, sort=k % 10 == 0)
+    if args.config == "c4":
+        systems = [wl.build_replica(sp, r) for r, sp in enumerate(wl.replica_specs())]
+        b = engine.BatchState(systems, sort_every=10)
+        del systems
+        b.start()
+        b.step(args.steps, report_last=True)
+    else:
+        s = wl.build(wl.SPECS[args.config])
+        st = engine.HpfState.from_system(s)
+        del s
+        st.start(sort=True)
+        st.prime()
+        for k in range(args.steps):
+            st.step_fused(report=True, sort=k % 10 == 0)
     torch.cuda.synchronize()
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)

@@ -1,14 +1,15 @@
 """Summarise rocprofv3 output of the hPF-MD step into profiles/.
 
 python -m paper_1310_2041_amd.profile_summary --stats DIR --fetch DIR --write DIR
-       --command "..." --out profiles/NAME.md [--json profiles/NAME.json]
+       --command "..." --pmc-command "..." --out profiles/NAME.md
 
 --stats  directory of a `--kernel-trace --stats --output-format csv` run
 --fetch / --write  directories of `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
          `python -m paper_1310_2041_amd.profile_step` (which ends with a 1 GiB copy)
-The JSON records, per kernel, the average duration and the HBM bytes per launch
-(counter KiB scaled by the copy calibration), plus a hash of the kernel sources
-so that stale traffic is not reported after a kernel changes.
+The summary ends with a fenced JSON record holding, per kernel, the average
+duration and the HBM bytes per launch (counter KiB scaled by the copy
+calibration), plus a hash of the kernel sources so that stale traffic is not
+reported after a kernel changes; `read_record` parses it back.
 """
 from __future__ import annotations
 
@@ -50,19 +51,37 @@ def kernel_stats(d: str) -> dict:
     return out
 
 
-def counter(d: str, name: str) -> dict:
+def counter(d: str, name: str):
+    """Per-kernel average of counter `name` per dispatch, and (kernel, value) of the
+    run's last dispatch, which the profiled program makes the calibration copy."""
     path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not path:
         raise SystemExit(f"no counter_collection.csv under {d}")
-    agg = collections.defaultdict(float)
-    n = collections.defaultdict(set)
+    per = collections.defaultdict(float)
+    kname = {}
     for r in csv.DictReader(open(path[0])):
         if r["Counter_Name"] != name:
             continue
-        k = _short(r["Kernel_Name"])
-        agg[k] += float(r["Counter_Value"])
-        n[k].add(r["Dispatch_Id"])
-    return {k: agg[k] / len(n[k]) for k in agg}
+        i = int(r["Dispatch_Id"])
+        per[i] += float(r["Counter_Value"])
+        kname[i] = _short(r["Kernel_Name"])
+    agg = collections.defaultdict(list)
+    for i, v in per.items():
+        agg[kname[i]].append(v)
+    last = max(per)
+    return {k: sum(v) / len(v) for k, v in agg.items()}, (kname[last], per[last])
+
+
+def read_record(path: str):
+    """The JSON record at the end of a summary written by this module, or None."""
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    i = txt.rfind("```json\n")
+    if i < 0:
+        return None
+    j = txt.find("```", i + 8)
+    return json.loads(txt[i + 8:j])
 
 
 def main():
@@ -73,17 +92,14 @@ def main():
     ap.add_argument("--command", required=True)
     ap.add_argument("--pmc-command", required=True)
     ap.add_argument("--out", required=True)
-    ap.add_argument("--json")
     args = ap.parse_args()
     stats = kernel_stats(args.stats)
-    fetch = counter(args.fetch, "FETCH_SIZE")
-    write = counter(args.write, "WRITE_SIZE")
-    copy = [k for k in fetch if "copyBuffer" in k or "copy" in k.lower()]
-    if not copy:
-        raise SystemExit("no calibration copy kernel in the counter runs")
-    ck = copy[0]
-    f_scale = COPY_BYTES / (fetch[ck] * 1024.0)
-    w_scale = COPY_BYTES / (write[ck] * 1024.0)
+    fetch, (ck, f_copy) = counter(args.fetch, "FETCH_SIZE")
+    write, (wk, w_copy) = counter(args.write, "WRITE_SIZE")
+    if "copy" not in ck.lower() or wk != ck:
+        raise SystemExit(f"last dispatch is {ck} / {wk}, not the calibration copy")
+    f_scale = COPY_BYTES / (f_copy * 1024.0)
+    w_scale = COPY_BYTES / (w_copy * 1024.0)
     rows = []
     for k, st in sorted(stats.items(), key=lambda kv: -kv[1]["total_us"]):
         rb = fetch.get(k)
@@ -104,12 +120,12 @@ def main():
         fm = f"{r['fetch_bytes'] / 1e6:.1f}" if r["fetch_bytes"] is not None else "-"
         wm = f"{r['write_bytes'] / 1e6:.1f}" if r["write_bytes"] is not None else "-"
         lines.append(f"| {r['kernel']} | {r['calls']} | {r['avg_us']:.2f} | {r['pct']:.1f} | {fm} | {wm} |")
+    rec = {"source_hash": source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "kernels": {r["kernel"]: {"avg_us": round(r["avg_us"], 3),
+                                     "fetch_bytes": r["fetch_bytes"], "write_bytes": r["write_bytes"]}
+                       for r in rows}}
+    lines += ["", "Machine-readable record:", "", "```json", json.dumps(rec), "```"]
     open(args.out, "w").write("\n".join(lines) + "\n")
-    if args.json:
-        json.dump({"source_hash": source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
-                   "kernels": {r["kernel"]: {"avg_us": r["avg_us"], "fetch_bytes": r["fetch_bytes"],
-                                             "write_bytes": r["write_bytes"]} for r in rows}},
-                  open(args.json, "w"), indent=1)
     print("\n".join(lines))
 
 
