@@ -90,15 +90,15 @@ def timed_step_fused(st, hpf, engine, tm, sort):
     tm.wrap("field_potential", hpf.hpf_field_potential, st.counts, st.mesh, st.field, st.V,
             st.part[engine.ROW_W])
     tm.wrap("field_gradient", hpf.hpf_field_gradient, st.V, st.mesh, st.K, st.G)
-    tm.wrap("advance", hpf.hpf_advance, st.R, st.R2, st.Vel, st.T, st.mesh, st.K, st.G, st.bonds,
-            st.k_bond, st.r0, st.box, st.dt, e_part=st.part[engine.ROW_EB],
-            kin_part=st.part[engine.ROW_KE:engine.ROW_KE + 4])
-    st.R, st.R2 = st.R2, st.R
+    tm.wrap("advance", st.advance, True)
     tm.wrap("reduce", hpf.hpf_reduce_partials, st.part, engine.N_ROWS, st.energy)
     st.steps_done += 1
 
 
-def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True):
+def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, graph=True):
+    """Warm up, time `steps` steps, then (instrument) time each call over one graph's worth
+    of eager steps. With `graph`, the timed steps replay a HIP graph of two sort periods:
+    every buffer swap of the step then returns to its start, so the graph can be looped."""
     import torch
 
     from paper_1310_2041_amd import engine, hpf
@@ -112,29 +112,50 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True):
     if fused:
         st.prime()
     step = st.step_fused if fused else st.step
+
+    def one(report=True):
+        step(report=report, sort=sort_every > 0 and st.steps_done % sort_every == 0)
+
     for _ in range(warmup):
-        step(report=True, sort=sort_every > 0 and st.steps_done % sort_every == 0)
+        one()
     torch.cuda.synchronize()
-    tm = Timers(torch)
+    period = 2 * sort_every if sort_every > 0 else 20
+    use_graph = graph and fused and steps % period == 0
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t0.record()
-    for _ in range(steps):
-        do_sort = sort_every > 0 and st.steps_done % sort_every == 0
-        if instrument:
-            (timed_step_fused if fused else timed_step)(st, hpf, engine, tm, do_sort)
-        else:
-            step(report=True, sort=do_sort)
-    t1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
+    if use_graph:
+        g = engine.Graph(lambda: [one() for _ in range(period)])
+        g.launch()                                   # untimed first replay
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        t0.record(g.stream)
+        for _ in range(steps // period):
+            g.launch()
+        t1.record(g.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        del g
+    else:
+        wall0 = time.perf_counter()
+        t0.record()
+        for _ in range(steps):
+            one()
+        t1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1)
+    tm = Timers(torch)
+    if instrument:
+        for _ in range(period):
+            do_sort = sort_every > 0 and st.steps_done % sort_every == 0
+            (timed_step_fused if fused else timed_step)(st, hpf, engine, tm, do_sort)
+        torch.cuda.synchronize()
     flags = hpf.hpf_get_device_status()
     e = st.energies()
     return {"spec": spec, "N": st.N, "K": st.K, "nm": st.nm, "D": st.bonds.shape[0],
             "ms_total": ms, "wall_s": wall, "kernels": tm.summary() if instrument else {},
-            "flags": flags, "energies": e}
+            "flags": flags, "energies": e, "graph": use_graph,
+            "advance_kernel": "cells" if st.uses_cells_advance() else "plain"}
 
 
 def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
@@ -194,7 +215,8 @@ def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
 
 # rocprofv3 kernel names behind each timed call of the step
 ROCPROF_KERNELS = {
-    "advance": ["hpf::k_advance<true>", "hpf::k_advance<false>"],
+    "advance": ["hpf::k_advance<true>", "hpf::k_advance<false>", "hpf::k_advance_cells<true>",
+                "hpf::k_advance_cells<false>"],
     "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum",
                         "hpf::k_scatter_strays"],
     "field_potential": ["hpf::k_field_potential<%d>" % k for k in range(1, 9)],
@@ -250,6 +272,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batched sweep")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every call from Python instead of replaying HIP graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hPF-MD path here runs on a single MI355X "
@@ -263,7 +287,8 @@ def main():
     torch.cuda.set_device(0)
 
     fused = args.mode == "fused"
-    r = run_workload(args.config, args.steps, args.warmup, args.sort_every, fused=fused)
+    r = run_workload(args.config, args.steps, args.warmup, args.sort_every, fused=fused,
+                     graph=not args.eager)
     ms_step = r["ms_total"] / args.steps
     value = r["N"] * args.steps / (r["ms_total"] * 1e-3)
     kern = r["kernels"]
@@ -294,7 +319,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": r["spec"].name, "beads": r["N"], "species": r["K"],
                    "mesh": [r["spec"].M] * 3, "box": r["spec"].L, "sort_every": args.sort_every,
-                   "energy_report_every": 1, "step": args.mode, "parallelism": "single-gpu"},
+                   "energy_report_every": 1, "step": args.mode, "advance": r["advance_kernel"],
+                   "launch": "hip_graph" if r["graph"] else "eager", "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "algorithmic_bytes": dom_bytes,
@@ -304,7 +330,7 @@ def main():
     }
     if args.also and args.also != args.config:
         r2 = run_workload(args.also, args.steps, args.warmup, args.sort_every, instrument=False,
-                          fused=fused)
+                          fused=fused, graph=not args.eager)
         out["also"] = {"workload": r2["spec"].name, "beads": r2["N"],
                        "value": r2["N"] * args.steps / (r2["ms_total"] * 1e-3),
                        "ms_per_step": r2["ms_total"] / args.steps,

@@ -264,6 +264,33 @@ hpf_status_t hpf_advance(const float* R, float* R_next, float* Vel, const uint8_
                          float dt, float* F_out, double* e_part, double* kin_part,
                          void* stream);
 
+/* ---------------------------------------------------------------------------
+ * hpf_advance_cells -- hpf_advance for beads in hpf_sort_by_cell order, with
+ * the same per-bead results bit for bit (forces eq. 6 and eq. 7, the Verlet
+ * halves of the Integration methods section). One workgroup takes the beads
+ * that one B^3 brick of cells listed at the last sort and first stages the
+ * brick's gradient box -- (B + 1 + 2*halo)^3 mesh points per species,
+ * starting halo points below the brick, periodic -- in LDS; beads that have
+ * since moved more than `halo` cells out of their brick, and beads the sort
+ * could not bin, read the mesh from memory instead.
+ *
+ * Arguments as in hpf_advance, plus:
+ * cell_start  uint32[NK + 2] device, from the hpf_sort_by_cell call with the
+ *             same mesh and B that produced the current bead order (the beads
+ *             may have moved since; their storage order must not have).
+ * B           brick edge 3..8 (0 selects 8); halo 0..2 cells, halo < B.
+ *             K * (B + 1 + 2*halo)^3 * 16 bytes must fit in 160 KiB of LDS.
+ * The energy partials are grouped by workgroup, so their sums may differ from
+ * hpf_advance's in the last FP64 bits; every bead state is identical.
+ * Returns HPF_EINVAL for bad arguments (nothing enqueued).
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_advance_cells(const float* R, float* R_next, float* Vel, const uint8_t* T,
+                               int64_t N, const hpf_mesh_t* mesh, int32_t K, const float* G,
+                               const int32_t* bonds, int32_t D, float k, float r0,
+                               const float* box, const float* inv_mass, float dt,
+                               const uint32_t* cell_start, int32_t B, int32_t halo,
+                               float* F_out, double* e_part, double* kin_part, void* stream);
+
 /* Deterministic FP64 reduction of partial-sum buffers: out[c] = sum of
  * part[c*HPF_NPART .. (c+1)*HPF_NPART) in a fixed tree order, c < ncomp.
  * part and out are device pointers; ncomp in [1, 8]. */
@@ -271,22 +298,26 @@ hpf_status_t hpf_reduce_partials(const double* part, int32_t ncomp, double* out,
                                  void* stream);
 
 /* ---------------------------------------------------------------------------
- * hpf_sort_by_cell -- put beads in canonical cell order (the paper reorders
- * particle data for cache hits and bins beads into a cell list; Algorithm 1
- * Kernel 1). The key of a bead is its cell in brick-major order: bricks of
- * B^3 cells, bricks numbered x fastest, cells x fastest inside a brick,
- *   key = ((bz*NBy + by)*NBx + bx) * B^3 + (lz*B + ly)*B + lx,  NB_d = ceil(M_d/B).
- * Beads that cannot be binned get key NK = NBx*NBy*NBz*B^3 and go last.
- * Output order: ascending (key, tag). Positions, velocities, types and tags
- * are permuted into the *_out arrays and the bond table is permuted and its
- * entries renumbered to the new storage indices.
+ * hpf_sort_by_cell -- put beads in canonical cell-list order (the paper
+ * reorders particle data for cache hits and bins beads into a cell list;
+ * Algorithm 1 Kernel 1). The key of a bead is the brick of B^3 cells that
+ * holds its cell, bricks numbered x fastest:
+ *   key = (bz*NBy + by)*NBx + bx,  b_d = c_d / B,  NB_d = ceil(M_d / B).
+ * Beads that cannot be binned get key NK = NBx*NBy*NBz and go last.
+ * Output order: ascending (key, tag), so every brick's beads are one
+ * contiguous range and, inside it, the beads of a chain (consecutive tags)
+ * are neighbours. Positions, velocities, types and tags are permuted into the
+ * *_out arrays and the bond table is permuted and its entries renumbered to
+ * the new storage indices. A brick holding more than 8192 beads keeps an
+ * arbitrary order inside and sets HPF_FLAG_SORT_ORDER.
  *
  * B            brick edge in cells, 1..16 (0 selects 8).
  * *_in / *_out device arrays of N rows (Vel/tag/bonds may be NULL together
  *              with their outputs; D may be 0); in and out must not alias.
  * cell_start   nullable uint32[NK + 2] device: cell_start[k] = index of the
- *              first bead with key >= k (so cell_start[NK] = number of
- *              binned beads, cell_start[NK+1] = N).
+ *              first bead with key >= k, i.e. brick k's beads are
+ *              [cell_start[k], cell_start[k+1]); cell_start[NK] = number of
+ *              binned beads, cell_start[NK+1] = N.
  * work         device workspace of at least hpf_sort_workspace_bytes()
  *              bytes (HPF_ESPACE otherwise).
  * ------------------------------------------------------------------------- */

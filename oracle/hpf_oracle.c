@@ -389,13 +389,9 @@ int or_sort_perm(const double* R, const int32_t* tag, int64_t N, const or_mesh_t
         int32_t c[3];
         uint32_t w[3][2];
         uint32_t key = 0xFFFFFFFFu;
-        if (!bead_cell(R, i, m, c, w)) {
-            uint32_t brick = ((uint32_t)(c[2] / B) * (uint32_t)nb[1] + (uint32_t)(c[1] / B)) *
-                                 (uint32_t)nb[0] + (uint32_t)(c[0] / B);
-            uint32_t local = ((uint32_t)(c[2] % B) * (uint32_t)B + (uint32_t)(c[1] % B)) *
-                                 (uint32_t)B + (uint32_t)(c[0] % B);
-            key = brick * (uint32_t)(B * B * B) + local;
-        }
+        if (!bead_cell(R, i, m, c, w))
+            key = ((uint32_t)(c[2] / B) * (uint32_t)nb[1] + (uint32_t)(c[1] / B)) * (uint32_t)nb[0] +
+                  (uint32_t)(c[0] / B);
         it[i].key = key;
         it[i].tag = tag[i];
         it[i].idx = i;

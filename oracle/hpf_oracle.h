@@ -102,9 +102,12 @@ int64_t or_forces(const double* R, const uint8_t* T, int64_t N, const or_params_
 int or_run(double* R, double* V, const uint8_t* T, const double* inv_mass, int64_t N,
            const or_params_t* p, double dt, int32_t n_steps, double* energies);
 
-/* a0: cell-sort permutation. key = brick-major cell index with bricks of
- * B^3 cells; perm receives the bead order sorted by (key, tag). keys
- * (nullable) receives each bead's key in the input order. */
+/* a0: cell-list order (the paper reorders particles for cache hits and bins
+ * them into cells, Algorithm 1 Kernel 1). key = index of the brick of B^3
+ * cells holding the bead's cell, bricks numbered x fastest; beads that
+ * cannot be binned get key 0xFFFFFFFF. perm receives the bead order sorted
+ * by (key, tag): every brick's beads are one contiguous range, in tag order.
+ * keys (nullable) receives each bead's key in the input order. */
 int or_sort_perm(const double* R, const int32_t* tag, int64_t N, const or_mesh_t* m,
                  int32_t B, int64_t* perm, uint32_t* keys);
 

@@ -125,7 +125,7 @@ static bool scatter_cells_setup(int64_t N, const hpf_mesh_t* mesh, int32_t K, in
     const int P = B + 1 + 2 * halo;
     if (scatter_cells_smem(K, P) > 160 * 1024)
         return false;
-    int64_t nk = (int64_t)B * B * B, nt = 1;
+    int64_t nk = 1, nt = 1;
     for (int d = 0; d < 3; ++d) {
         tk->nb[d] = (mesh->M[d] + B - 1) / B;
         nk *= tk->nb[d];
@@ -257,6 +257,49 @@ hpf_status_t hpf_advance(const float* R, float* R_next, float* Vel, const uint8_
     }
     return launch_advance(R, R_next, Vel, T, N, mesh_k(mesh), K, G, bonds, D, k, r0, b, inv_mass, dt, F_out,
                           e_part, kin_part, as_stream(stream));
+}
+
+hpf_status_t hpf_advance_cells(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
+                               const hpf_mesh_t* mesh, int32_t K, const float* G, const int32_t* bonds, int32_t D,
+                               float k, float r0, const float* box, const float* inv_mass, float dt,
+                               const uint32_t* cell_start, int32_t B, int32_t halo, float* F_out, double* e_part,
+                               double* kin_part, void* stream)
+{
+    if (N < 0 || N > 0x7fffffffLL || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES || D < 0 ||
+        D > HPF_MAX_BONDS || !box_ok(box) || !std::isfinite(k) || !std::isfinite(r0) || !(dt > 0.0f) ||
+        !std::isfinite(dt))
+        return HPF_EINVAL;
+    if (B == 0)
+        B = 8;
+    if (B < 3 || B > kTcMaxB || halo < 0 || halo > kTcMaxHalo || halo >= B)
+        return HPF_EINVAL;
+    const int P = B + 1 + 2 * halo;
+    if (advance_cells_smem(K, P) > 160 * 1024)
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !R_next || !Vel || !T || !G || !cell_start || (D > 0 && !bonds) || R == R_next))
+        return HPF_EINVAL;
+    TileK tk;
+    int64_t nk = 1, nt = 1;
+    for (int d = 0; d < 3; ++d) {
+        tk.nb[d] = (mesh->M[d] + B - 1) / B;
+        nk *= tk.nb[d];
+        nt *= tk.nb[d];
+    }
+    if (nk > 0xfffffff0LL)
+        return HPF_EINVAL;
+    tk.m = mesh_k(mesh);
+    tk.B = B;
+    tk.h = halo;
+    tk.P = P;
+    tk.NK = (uint32_t)nk;
+    tk.ntiles = nt;
+    BoxK b;
+    for (int d = 0; d < 3; ++d) {
+        b.L[d] = box[d];
+        b.halfL[d] = 0.5f * box[d];
+    }
+    return launch_advance_cells(R, R_next, Vel, T, N, tk, K, G, bonds, D, k, r0, b, inv_mass, dt, cell_start,
+                                F_out, e_part, kin_part, as_stream(stream));
 }
 
 hpf_status_t hpf_reduce_partials(const double* part, int32_t ncomp, double* out, void* stream)

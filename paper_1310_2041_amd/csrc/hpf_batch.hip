@@ -8,7 +8,8 @@
 // the concatenated key space sorts every replica inside its own bead range,
 // and the single-system sort kernels are reused unchanged. Every other phase
 // walks a host-built work list of (replica, range) items, one workgroup per
-// item, and calls the same device functions as the single-system kernels, so
+// item, with each XCD taking one contiguous run of items (so neighbouring
+// ranges of a replica share that XCD's L2), and calls the same device functions as the single-system kernels, so
 // each replica's beads follow exactly the trajectory they would follow alone.
 #include <algorithm>
 #include <vector>
@@ -60,7 +61,8 @@ __global__ __launch_bounds__(kBThreads) void k_batch_keys(const RepK* __restrict
                                                           uint32_t* __restrict__ keys,
                                                           uint32_t* __restrict__ hist)
 {
-    const ItemK it = items[blockIdx.x];
+    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
+    const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
     const int lane = threadIdx.x & (kWave - 1);
     for (int64_t base = it.begin; base < it.end; base += kBThreads) {
@@ -70,13 +72,12 @@ __global__ __launch_bounds__(kBThreads) void k_batch_keys(const RepK* __restrict
         if (active) {
             BeadCell b;
             if (bead_cell(R[i], rp.m, b))
-                key = rp.key_base + brick_key(b.c[0], b.c[1], b.c[2], B, rp.nb);
+                key = rp.key_base + brick_of(b.c[0], b.c[1], b.c[2], B, rp.nb);
             keys[i] = key;
         }
-        int head, len;
-        wave_runs(key, active, &head, &len);
-        if (active && head == lane)
-            atomicAdd(hist + key, (uint32_t)len);
+        const uint64_t grp = wave_key_group(key, active);
+        if (active && __builtin_ctzll(grp) == lane)
+            atomicAdd(hist + key, (uint32_t)__builtin_popcountll(grp));
     }
 }
 
@@ -91,7 +92,8 @@ __global__ __launch_bounds__(kTcThreads) void k_batch_scatter_bricks(const RepK*
                                                                      unsigned long long* __restrict__ partials,
                                                                      uint32_t* __restrict__ strays)
 {
-    const ItemK it = items[blockIdx.x];
+    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
+    const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
     const TileK tk = tile_of(rp, B, h);
     const int P = tk.P;
@@ -105,7 +107,8 @@ __global__ __launch_bounds__(256) void k_batch_scatter_sum(const RepK* __restric
                                                            const unsigned long long* __restrict__ partials,
                                                            unsigned long long* __restrict__ counts)
 {
-    const ItemK it = items[blockIdx.x];
+    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
+    const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
     const TileK tk = tile_of(rp, B, h);
     const int P = tk.P;
@@ -164,7 +167,8 @@ __global__ __launch_bounds__(kPotThreads) void k_batch_potential(const RepK* __r
                                                                  double* __restrict__ w_part)
 {
     __shared__ double scratch[kPotThreads / kWave];
-    const ItemK it = items[blockIdx.x];
+    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
+    const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
     double wsum = 0.0;
     bool over = false;
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(kPotThreads) void k_batch_potential(const RepK* __r
     if (w_part) {
         const double s = block_sum(wsum, scratch);
         if (threadIdx.x == 0)
-            w_part[blockIdx.x] = s * rp.p.rho0_dV;
+            w_part[li] = s * rp.p.rho0_dV;
     }
 }
 
@@ -187,7 +191,8 @@ __global__ __launch_bounds__(256) void k_batch_gradient(const RepK* __restrict__
                                                         const float* __restrict__ V,
                                                         float4* __restrict__ G)
 {
-    const ItemK it = items[blockIdx.x];
+    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
+    const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
     const int Mx = rp.m.M[0], My = rp.m.M[1];
     const int z = (int)it.begin;
@@ -211,7 +216,8 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
                                                              double* __restrict__ kin_part, int nslot)
 {
     __shared__ double scratch[kPThreads / kWave];
-    const ItemK it = items[blockIdx.x];
+    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
+    const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
     const float4* Gr = G + (int64_t)K * rp.moff;
     const float hdt = 0.5f * dt;
@@ -230,10 +236,10 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
     if (e_part) {
         const double s = block_sum(e, scratch);
         if (threadIdx.x == 0)
-            e_part[blockIdx.x] = s;
+            e_part[li] = s;
     }
     if (kin_part)
-        acc.store_rows(kin_part, nslot, blockIdx.x, scratch);
+        acc.store_rows(kin_part, nslot, li, scratch);
 }
 
 // per replica: energies {KE, E_bond, W, E_tot, Px, Py, Pz, 0} from the item
@@ -299,7 +305,8 @@ __global__ __launch_bounds__(kPThreads) void k_batch_prime(const RepK* __restric
                                                            double* __restrict__ kin_part, int nslot)
 {
     __shared__ double scratch[kPThreads / kWave];
-    const ItemK it = items[blockIdx.x];
+    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
+    const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
     const float4* Gr = G + (int64_t)K * rp.moff;
     const float hdt = 0.5f * dt;
@@ -334,10 +341,10 @@ __global__ __launch_bounds__(kPThreads) void k_batch_prime(const RepK* __restric
     if (e_part) {
         const double s = block_sum(e, scratch);
         if (threadIdx.x == 0)
-            e_part[blockIdx.x] = s;
+            e_part[li] = s;
     }
     if (kin_part)
-        acc.store_rows(kin_part, nslot, blockIdx.x, scratch);
+        acc.store_rows(kin_part, nslot, li, scratch);
 }
 
 constexpr int kMinBeadChunk = 512;
@@ -369,7 +376,7 @@ static bool batch_layout(const hpf_replica_t* reps, int nrep, const hpf_batch_co
         if (q.n_beads < 0 || q.bead_offset != expect_off)
             return false;
         expect_off += q.n_beads;
-        int64_t nk = (int64_t)B * B * B, nbr = 1, nm = 1;
+        int64_t nk = 1, nbr = 1, nm = 1;
         for (int d = 0; d < 3; ++d) {
             if (!(q.L[d] > 0.0f) || q.M[d] < B + 1 + 2 * kTcMaxHalo || q.M[d] > 4096)
                 return false;
@@ -504,8 +511,8 @@ static hpf_status_t batch_sort(hpf_batch* b, hipStream_t s)
         hipLaunchKernelGGL(k_copy_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, cursor, nscan);
         hipLaunchKernelGGL(k_sort_place, dim3(grid_of(N)), dim3(kSortThreads), 0, s, keys, N,
                            b->buf.tag[o], cursor, perm, ptag);
-        hipLaunchKernelGGL(k_sort_segments, dim3(grid_of(nscan - 1)), dim3(kSortThreads), 0, s, start,
-                           nscan - 1, ptag, perm);
+        hipLaunchKernelGGL(k_sort_bricks, dim3((unsigned)std::min<int64_t>(nscan - 1, 1 << 20)),
+                           dim3(kBrickSortThreads), 0, s, start, nscan - 1, ptag, perm);
         hipLaunchKernelGGL(k_sort_permute, dim3(grid_of(N)), dim3(kSortThreads), 0, s, perm, N,
                            reinterpret_cast<const float4*>(b->buf.R[b->rcur]),
                            reinterpret_cast<const float4*>(b->buf.Vel[o]), b->buf.T[o], b->buf.tag[o],
@@ -675,7 +682,7 @@ hpf_status_t hpf_batch_create(const hpf_replica_t* reps, int32_t n_rep, const hp
         rk.moff = moff;
         rk.key_base = key_base;
         rk.nbricks = (int64_t)rk.nb[0] * rk.nb[1] * rk.nb[2];
-        rk.NK = (uint32_t)(rk.nbricks * B * B * B);
+        rk.NK = (uint32_t)rk.nbricks;
         rk.brick_off = brick_off;
         key_base += rk.NK + 1;
         moff += rk.m.nm;

@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "hpf.h"
 
 namespace hpf {
@@ -180,6 +184,26 @@ __device__ __forceinline__ void wave_runs(uint32_t key, bool active, int* head, 
     *len = next - lane;
 }
 
+// Lanes of a wavefront grouped by equal key, whatever their positions: one
+// pass per distinct key among the active lanes (a uniform loop). Returns the
+// mask of active lanes holding this lane's key (0 for inactive lanes); its
+// lowest set bit is the group's leader, popcount its size, and the bits below
+// this lane give its rank in the group.
+__device__ __forceinline__ uint64_t wave_key_group(uint32_t key, bool active)
+{
+    uint64_t remaining = __ballot(active);
+    uint64_t mine = 0;
+    while (remaining) {
+        const int leader = __builtin_ctzll(remaining);
+        const uint32_t k = __shfl(key, leader, kWave);
+        const uint64_t m = __ballot(active && key == k);
+        if (active && key == k)
+            mine = m;
+        remaining &= ~m;
+    }
+    return mine;
+}
+
 // Minimum-image separation x_j - x_i along one axis of a periodic box for
 // coordinates inside [0, L). When the raw difference exceeds half a box the
 // wrapped coordinate is formed first (x_j - L or x_i - L is exact by Sterbenz's
@@ -209,6 +233,31 @@ __device__ __forceinline__ float wrap_coord(float x, float L)
     if (r >= L)
         r = 0.0f;
     return r;
+}
+
+// Workgroups of `fn` (with `threads` threads and `smem` bytes of dynamic LDS)
+// that the current device holds at once: blocks per CU from the occupancy
+// calculator (registers and LDS) times the CU count. Cached per device and
+// shape; 0 if the runtime cannot tell.
+inline int64_t resident_blocks(const void* fn, int threads, size_t smem)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, int, size_t>, int64_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0;
+    const auto key = std::make_tuple(dev, fn, threads, smem);
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = cache.find(key);
+    if (it != cache.end())
+        return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, smem) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int64_t n = (int64_t)per_cu * cus;
+    cache[key] = n;
+    return n;
 }
 
 }  // namespace hpf

@@ -7,6 +7,8 @@
 // (cell-sorted beads then share that XCD's L2 for mesh and partner reads).
 // The separate kernels and the fused one call the same device functions in
 // the same order, so they produce bitwise identical results.
+#include <algorithm>
+
 #include "hpf_common.hpp"
 
 namespace hpf {
@@ -57,7 +59,7 @@ __device__ __forceinline__ void clear_unused_slots(double* part, int rows)
         return;
     for (int r = 0; r < rows; ++r)
         for (int64_t i = (int64_t)gridDim.x + blockIdx.x + (int64_t)threadIdx.x * gridDim.x; i < HPF_NPART;
-             i += (int64_t)kPThreads * gridDim.x)
+             i += (int64_t)blockDim.x * gridDim.x)
             part[r * HPF_NPART + i] = 0.0;
 }
 
@@ -68,42 +70,27 @@ struct BoxK {
 
 // ------------------------------------------------------- device functions --
 
-// Field force on one bead: -sum_a (W_a / 2^48) G_t(c + a), separable
-// trilinear interpolation with the exact FP32 dyadic 1-D weights.
-__device__ __forceinline__ bool field_force(const float4& r, int t, const MeshK& m, int K,
-                                            const float4* __restrict__ G, float3& f)
+// Trilinear interpolation of the gradient at a bead from the 8 corner values
+// g[a], a = x + 2y + 4z, with the exact FP32 dyadic 1-D weights (separable
+// form of -sum_a (W_a / 2^48) G(c + a)).
+__device__ __forceinline__ float3 interp8(const BeadCell& b, const float4 (&g)[8])
 {
-    BeadCell b;
-    f = make_float3(0.0f, 0.0f, 0.0f);
-    if (!(bead_cell(r, m, b) && t < K))
-        return false;
-    const float4* Gk = G + t * m.nm;
-    const int32_t Mx = m.M[0], My = m.M[1], Mz = m.M[2];
-    const int32_t x0 = b.c[0], x1 = next_wrap(x0, Mx);
-    const int32_t y0 = b.c[1], y1 = next_wrap(y0, My);
-    const int32_t z0 = b.c[2], z1 = next_wrap(z0, Mz);
-    const int64_t r00 = ((int64_t)z0 * My + y0) * Mx, r10 = ((int64_t)z0 * My + y1) * Mx;
-    const int64_t r01 = ((int64_t)z1 * My + y0) * Mx, r11 = ((int64_t)z1 * My + y1) * Mx;
-    const float4 g000 = Gk[r00 + x0], g100 = Gk[r00 + x1];
-    const float4 g010 = Gk[r10 + x0], g110 = Gk[r10 + x1];
-    const float4 g001 = Gk[r01 + x0], g101 = Gk[r01 + x1];
-    const float4 g011 = Gk[r11 + x0], g111 = Gk[r11 + x1];
     const float ax1 = (float)b.q[0] * kInvOne, ax0 = (float)(kOne - b.q[0]) * kInvOne;
     const float ay1 = (float)b.q[1] * kInvOne, ay0 = (float)(kOne - b.q[1]) * kInvOne;
     const float az1 = (float)b.q[2] * kInvOne, az0 = (float)(kOne - b.q[2]) * kInvOne;
-    float3 e00, e10, e01, e11, f0, f1;
-    e00.x = ax0 * g000.x + ax1 * g100.x;
-    e00.y = ax0 * g000.y + ax1 * g100.y;
-    e00.z = ax0 * g000.z + ax1 * g100.z;
-    e10.x = ax0 * g010.x + ax1 * g110.x;
-    e10.y = ax0 * g010.y + ax1 * g110.y;
-    e10.z = ax0 * g010.z + ax1 * g110.z;
-    e01.x = ax0 * g001.x + ax1 * g101.x;
-    e01.y = ax0 * g001.y + ax1 * g101.y;
-    e01.z = ax0 * g001.z + ax1 * g101.z;
-    e11.x = ax0 * g011.x + ax1 * g111.x;
-    e11.y = ax0 * g011.y + ax1 * g111.y;
-    e11.z = ax0 * g011.z + ax1 * g111.z;
+    float3 e00, e10, e01, e11, f0, f1, f;
+    e00.x = ax0 * g[0].x + ax1 * g[1].x;
+    e00.y = ax0 * g[0].y + ax1 * g[1].y;
+    e00.z = ax0 * g[0].z + ax1 * g[1].z;
+    e10.x = ax0 * g[2].x + ax1 * g[3].x;
+    e10.y = ax0 * g[2].y + ax1 * g[3].y;
+    e10.z = ax0 * g[2].z + ax1 * g[3].z;
+    e01.x = ax0 * g[4].x + ax1 * g[5].x;
+    e01.y = ax0 * g[4].y + ax1 * g[5].y;
+    e01.z = ax0 * g[4].z + ax1 * g[5].z;
+    e11.x = ax0 * g[6].x + ax1 * g[7].x;
+    e11.y = ax0 * g[6].y + ax1 * g[7].y;
+    e11.z = ax0 * g[6].z + ax1 * g[7].z;
     f0.x = ay0 * e00.x + ay1 * e10.x;
     f0.y = ay0 * e00.y + ay1 * e10.y;
     f0.z = ay0 * e00.z + ay1 * e10.z;
@@ -113,6 +100,84 @@ __device__ __forceinline__ bool field_force(const float4& r, int t, const MeshK&
     f.x = -(az0 * f0.x + az1 * f1.x);
     f.y = -(az0 * f0.y + az1 * f1.y);
     f.z = -(az0 * f0.z + az1 * f1.z);
+    return f;
+}
+
+// The 8 corner values of cell b from species t's gradient mesh in memory.
+__device__ __forceinline__ void corners_global(const BeadCell& b, int t, const MeshK& m,
+                                               const float4* __restrict__ G, float4 (&g)[8])
+{
+    const float4* Gk = G + t * m.nm;
+    const int32_t Mx = m.M[0], My = m.M[1], Mz = m.M[2];
+    const int32_t x0 = b.c[0], x1 = next_wrap(x0, Mx);
+    const int32_t y0 = b.c[1], y1 = next_wrap(y0, My);
+    const int32_t z0 = b.c[2], z1 = next_wrap(z0, Mz);
+    const int64_t r00 = ((int64_t)z0 * My + y0) * Mx, r10 = ((int64_t)z0 * My + y1) * Mx;
+    const int64_t r01 = ((int64_t)z1 * My + y0) * Mx, r11 = ((int64_t)z1 * My + y1) * Mx;
+    g[0] = Gk[r00 + x0];
+    g[1] = Gk[r00 + x1];
+    g[2] = Gk[r10 + x0];
+    g[3] = Gk[r10 + x1];
+    g[4] = Gk[r01 + x0];
+    g[5] = Gk[r01 + x1];
+    g[6] = Gk[r11 + x0];
+    g[7] = Gk[r11 + x1];
+}
+
+// Field force on one bead (eq. 6). False (and zero force) for a bead that
+// cannot be binned or has a type >= K.
+__device__ __forceinline__ bool field_force(const float4& r, int t, const MeshK& m, int K,
+                                            const float4* __restrict__ G, float3& f)
+{
+    BeadCell b;
+    f = make_float3(0.0f, 0.0f, 0.0f);
+    if (!(bead_cell(r, m, b) && t < K))
+        return false;
+    float4 g[8];
+    corners_global(b, t, m, G, g);
+    f = interp8(b, g);
+    return true;
+}
+
+// A brick's gradient box in LDS: mesh points [o - h, o - h + P) per axis
+// (periodic; o = the brick's first cell), all K species, x fastest.
+struct GBox {
+    const float4* lds;
+    int32_t o[3];
+    int32_t h, P;
+};
+
+// Field force as field_force, with the corners read from the brick's LDS box
+// when the bead's cell lies within it, else from memory. Same values, same
+// arithmetic: the result is bitwise that of field_force.
+__device__ __forceinline__ bool field_force_box(const float4& r, int t, const MeshK& m, int K,
+                                                const float4* __restrict__ G, const GBox& gb, float3& f)
+{
+    BeadCell b;
+    f = make_float3(0.0f, 0.0f, 0.0f);
+    if (!(bead_cell(r, m, b) && t < K))
+        return false;
+    const int P = gb.P;
+    const int lx = periodic_delta(b.c[0], gb.o[0], m.M[0]) + gb.h;
+    const int ly = periodic_delta(b.c[1], gb.o[1], m.M[1]) + gb.h;
+    const int lz = periodic_delta(b.c[2], gb.o[2], m.M[2]) + gb.h;
+    float4 g[8];
+    if (gb.lds && (unsigned)lx <= (unsigned)(P - 2) && (unsigned)ly <= (unsigned)(P - 2) &&
+        (unsigned)lz <= (unsigned)(P - 2)) {
+        const int P2 = P * P;
+        const float4* c0 = gb.lds + (t * P + lz) * P2 + ly * P + lx;
+        g[0] = c0[0];
+        g[1] = c0[1];
+        g[2] = c0[P];
+        g[3] = c0[P + 1];
+        g[4] = c0[P2];
+        g[5] = c0[P2 + 1];
+        g[6] = c0[P2 + P];
+        g[7] = c0[P2 + P + 1];
+    } else {
+        corners_global(b, t, m, G, g);
+    }
+    f = interp8(b, g);
     return true;
 }
 
@@ -313,18 +378,23 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__
 // One bead of the fused pass: field force + bond forces at x_n, second half
 // kick of step n (kinetic-energy partials at v_n), first half kick and drift
 // of step n + 1, written to R_next.
-template <bool kR0Zero>
+// With kBox the corners come from the brick box `gb` where they can.
+template <bool kR0Zero, bool kBox = false>
 __device__ __forceinline__ void advance_bead(int64_t i, const float4* __restrict__ R, float4* __restrict__ R_next,
                                              float4* __restrict__ Vel, const uint8_t* __restrict__ T,
                                              int64_t N, const MeshK& m, int K, const float4* __restrict__ G,
                                              const int32_t* __restrict__ bonds, int D, float k, float r0,
                                              const BoxK& box, const float* __restrict__ inv_mass, float dt,
                                              float hdt, float4* __restrict__ F_out, KinAcc& acc, double& e,
-                                             bool& bad_bead, bool& bad_bond, bool& nonfinite)
+                                             bool& bad_bead, bool& bad_bond, bool& nonfinite,
+                                             const GBox* gb = nullptr)
 {
     float4 r = R[i];
     float3 ff;
-    bad_bead |= !field_force(r, T[i], m, K, G, ff);
+    if (kBox)
+        bad_bead |= !field_force_box(r, T[i], m, K, G, *gb, ff);
+    else
+        bad_bead |= !field_force(r, T[i], m, K, G, ff);
     float ei;
     const float3 fb = bond_sum<kR0Zero>(i, r, R, N, bonds, D, k, r0, box, ei, bad_bond);
     float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
@@ -385,6 +455,114 @@ __global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict_
     }
     if (kin_part)
         acc.store(kin_part, w.block, scratch);
+}
+
+// Fused pass over cell-sorted beads, one brick of the sort at a time. The
+// beads a brick listed at the last sort (one contiguous range) are processed
+// by one workgroup after it has staged the brick's gradient box, P = B + 1 +
+// 2h points per axis and species, in LDS; a bead that has since moved more
+// than h cells out of the brick, or that the sort could not bin (the range
+// after the last brick), reads its corners from memory. Each bead's update is
+// bitwise that of k_advance. Bricks are walked like beads in bead_walk: the
+// bricks are cut into one contiguous run per XCD, and that XCD's workgroups
+// take the bricks of its run in turn. A workgroup's partial-sum slot is its
+// launch index.
+constexpr int kAThreads = 512;
+
+struct BrickWalk {
+    int64_t end, first, stride;
+};
+
+__device__ __forceinline__ BrickWalk brick_walk(int64_t n)
+{
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t ng = nb < 8 ? nb : 8;
+    const int64_t g = b % ng, idx = b / ng;
+    const int64_t per_group = nb / ng + (g < nb % ng ? 1 : 0);
+    BrickWalk w;
+    w.first = n * g / ng + idx;
+    w.end = n * (g + 1) / ng;
+    w.stride = per_group;
+    return w;
+}
+
+template <bool kR0Zero>
+__global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __restrict__ R,
+                                                             float4* __restrict__ R_next,
+                                                             float4* __restrict__ Vel,
+                                                             const uint8_t* __restrict__ T, int64_t N,
+                                                             TileK tk, int K, const float4* __restrict__ G,
+                                                             const int32_t* __restrict__ bonds, int D,
+                                                             float k, float r0, BoxK box,
+                                                             const float* __restrict__ inv_mass, float dt,
+                                                             const uint32_t* __restrict__ cell_start,
+                                                             float4* __restrict__ F_out,
+                                                             double* __restrict__ e_part,
+                                                             double* __restrict__ kin_part)
+{
+    extern __shared__ float4 gsm[];
+    __shared__ double scratch[kAThreads / kWave];
+    clear_unused_slots(e_part, 1);
+    clear_unused_slots(kin_part, 4);
+    const MeshK& m = tk.m;
+    const int B = tk.B, P = tk.P, h = tk.h;
+    const int P2 = P * P, P3 = P2 * P;
+    const int nbox = K * P3;
+    const BrickWalk w = brick_walk(tk.ntiles + 1);
+    const float hdt = 0.5f * dt;
+    KinAcc acc;
+    double e = 0.0;
+    bool bad_bead = false, bad_bond = false, nonfinite = false;
+    for (int64_t item = w.first; item < w.end; item += w.stride) {
+        GBox gb;
+        gb.lds = nullptr;
+        gb.h = h;
+        gb.P = P;
+        int64_t first, last;
+        if (item < tk.ntiles) {
+            const int bx = (int)(item % tk.nb[0]);
+            const int by = (int)((item / tk.nb[0]) % tk.nb[1]);
+            const int bz = (int)(item / ((int64_t)tk.nb[0] * tk.nb[1]));
+            gb.o[0] = bx * B;
+            gb.o[1] = by * B;
+            gb.o[2] = bz * B;
+            __syncthreads();                          // the previous brick's box reads are done
+            for (int q = threadIdx.x; q < nbox; q += kAThreads) {
+                const int t = q / P3, rem = q - t * P3;
+                const int lz = rem / P2, rem2 = rem - lz * P2;
+                const int ly = rem2 / P, lx = rem2 - ly * P;
+                const int gx = wrap_idx(gb.o[0] - h + lx, m.M[0]);
+                const int gy = wrap_idx(gb.o[1] - h + ly, m.M[1]);
+                const int gz = wrap_idx(gb.o[2] - h + lz, m.M[2]);
+                gsm[q] = G[(int64_t)t * m.nm + ((int64_t)gz * m.M[1] + gy) * m.M[0] + gx];
+            }
+            __syncthreads();
+            gb.lds = gsm;
+            first = cell_start[item];
+            last = cell_start[item + 1];
+        } else {
+            gb.o[0] = gb.o[1] = gb.o[2] = 0;
+            first = cell_start[tk.NK];
+            last = N;
+        }
+        last = min(last, N);
+        for (int64_t i = first + threadIdx.x; i < last; i += kAThreads)
+            advance_bead<kR0Zero, true>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box, inv_mass, dt, hdt,
+                                        F_out, acc, e, bad_bead, bad_bond, nonfinite, &gb);
+    }
+    if (bad_bead)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+    if (bad_bond)
+        raise_flag(HPF_FLAG_BAD_BOND);
+    if (nonfinite)
+        raise_flag(HPF_FLAG_NONFINITE);
+    if (e_part) {
+        const double s = block_sum(e, scratch);
+        if (threadIdx.x == 0)
+            e_part[blockIdx.x] = s;
+    }
+    if (kin_part)
+        acc.store(kin_part, blockIdx.x, scratch);
 }
 
 // ---------------------------------------------------------------- launches --
@@ -463,6 +641,44 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
     else
         hipLaunchKernelGGL(k_advance<false>, g, bl, 0, s, Rp, Rn, Vp, T, N, m, K, Gp, bonds, D, k, r0,
                            box, inv_mass, dt, Fo, e_part, kin_part);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+static size_t advance_cells_smem(int K, int P) { return sizeof(float4) * (size_t)K * P * P * P; }
+
+hpf_status_t launch_advance_cells(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
+                                  const TileK& tk, int K, const float* G, const int32_t* bonds, int D, float k,
+                                  float r0, const BoxK& box, const float* inv_mass, float dt,
+                                  const uint32_t* cell_start, float* F_out, double* e_part, double* kin_part,
+                                  hipStream_t s)
+{
+    if (N == 0 && !e_part && !kin_part)
+        return HPF_OK;
+    const size_t smem = advance_cells_smem(K, tk.P);
+    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_cells<true>)
+                                : reinterpret_cast<const void*>(k_advance_cells<false>);
+    if (smem > 65536 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+        return HPF_EINVAL;
+    // one resident wave of workgroups walks all bricks (no late stragglers)
+    int64_t nb = resident_blocks(fn, kAThreads, smem);
+    if (nb < 1)
+        nb = 512;
+    nb = std::min<int64_t>(nb, tk.ntiles + 1);
+    if ((e_part || kin_part) && nb > HPF_NPART)
+        nb = HPF_NPART;
+    const dim3 g((unsigned)nb), bl(kAThreads);
+    auto* Rp = reinterpret_cast<const float4*>(R);
+    auto* Rn = reinterpret_cast<float4*>(R_next);
+    auto* Vp = reinterpret_cast<float4*>(Vel);
+    auto* Gp = reinterpret_cast<const float4*>(G);
+    auto* Fo = reinterpret_cast<float4*>(F_out);
+    if (r0 == 0.0f)
+        hipLaunchKernelGGL(k_advance_cells<true>, g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0,
+                           box, inv_mass, dt, cell_start, Fo, e_part, kin_part);
+    else
+        hipLaunchKernelGGL(k_advance_cells<false>, g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0,
+                           box, inv_mass, dt, cell_start, Fo, e_part, kin_part);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 

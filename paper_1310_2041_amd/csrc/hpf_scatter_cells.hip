@@ -33,18 +33,15 @@ struct TileK {
     int32_t B;          // brick edge (tile of owned mesh points)
     int32_t h;          // drift halo in cells
     int32_t nb[3];      // bricks per axis
-    uint32_t NK;        // number of cell keys
+    uint32_t NK;        // number of sort keys (bricks); key NK = beads that cannot be binned
     int32_t P;          // B + 1 + 2h: mesh points per axis of a brick's deposit box
     int64_t ntiles;
 };
 
-__device__ __forceinline__ uint32_t brick_key(int cx, int cy, int cz, int B, const int nb[3])
+// Sort key of a cell: the index of its brick of B^3 cells, x fastest.
+__device__ __forceinline__ uint32_t brick_of(int cx, int cy, int cz, int B, const int nb[3])
 {
-    const uint32_t brick = ((uint32_t)(cz / B) * (uint32_t)nb[1] + (uint32_t)(cy / B)) * (uint32_t)nb[0] +
-                           (uint32_t)(cx / B);
-    const uint32_t local = ((uint32_t)(cz % B) * (uint32_t)B + (uint32_t)(cy % B)) * (uint32_t)B +
-                           (uint32_t)(cx % B);
-    return brick * (uint32_t)(B * B * B) + local;
+    return ((uint32_t)(cz / B) * (uint32_t)nb[1] + (uint32_t)(cy / B)) * (uint32_t)nb[0] + (uint32_t)(cx / B);
 }
 
 __device__ __forceinline__ int wrap_idx(int c, int M)
@@ -107,9 +104,8 @@ __device__ __forceinline__ void scatter_brick_body(const float4* __restrict__ R,
     if (tid == 0)
         stray_n = 0;
     __syncthreads();
-    const uint32_t B3 = (uint32_t)(B * B * B);
-    const uint32_t first = cell_start[(uint32_t)brick * B3];
-    const uint32_t last = cell_start[(uint32_t)(brick + 1) * B3];
+    const uint32_t first = cell_start[brick];
+    const uint32_t last = cell_start[brick + 1];
     for (uint32_t j0 = first; j0 < last; j0 += kTcThreads * kScBatch) {
         float4 rj[kScBatch];
         int tj[kScBatch];

@@ -1,10 +1,13 @@
 // Canonical cell ordering of the beads (the paper reorders particle data for
 // cache hits and bins beads into a cell list, Algorithm 1 Kernel 1).
 //
-// Counting sort on a brick-major cell key: histogram (u32 atomics), an
-// exclusive scan over all keys, placement with per-key cursors, then each
-// key's segment is sorted by tag so the result -- ascending (key, tag) -- is
-// independent of the atomic placement order. Finally the bead arrays are
+// The key of a bead is the brick of B^3 cells holding its cell. Counting sort
+// on that key: histogram (u32 atomics), an exclusive scan over all keys,
+// placement with per-key cursors, then each key's segment is sorted by tag in
+// LDS, so the result -- ascending (brick, tag) -- is independent of the
+// atomic placement order. Inside a brick the beads then lie in tag order, so
+// the beads of one chain (consecutive tags) stay next to each other and most
+// bond partners are neighbours in memory. Finally the bead arrays are
 // gathered into the output buffers and the bond table is permuted and
 // renumbered through the inverse permutation.
 #include "hpf_common.hpp"
@@ -15,7 +18,7 @@ struct SortK {
     MeshK m;
     int32_t B;
     int32_t nb[3];
-    uint32_t NK;        // number of cell keys; key NK = "cannot be binned"
+    uint32_t NK;        // number of keys (bricks); key NK = "cannot be binned"
 };
 
 constexpr int kSortThreads = 256;
@@ -24,7 +27,8 @@ constexpr int kScanTile = kSortThreads * kScanPer;   // entries per scan block
 constexpr int kScanTopThreads = 1024;
 constexpr int kScanTopPer = 8;
 constexpr int kMaxScanTiles = kScanTopThreads * kScanTopPer;
-constexpr int kSegSortMax = 256;                       // longest segment sorted by tag
+constexpr int kBrickSortThreads = 512;
+constexpr int kBrickSortMax = 8192;                    // longest segment sorted by tag (64 KB LDS)
 
 __global__ __launch_bounds__(kSortThreads) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v)
 {
@@ -50,21 +54,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_keys(const float4* __rest
     uint32_t key = sk.NK;
     if (active) {
         BeadCell b;
-        if (bead_cell(R[i], sk.m, b)) {
-            const int B = sk.B;
-            const uint32_t brick = ((uint32_t)(b.c[2] / B) * (uint32_t)sk.nb[1] + (uint32_t)(b.c[1] / B)) *
-                                       (uint32_t)sk.nb[0] + (uint32_t)(b.c[0] / B);
-            const uint32_t local = ((uint32_t)(b.c[2] % B) * (uint32_t)B + (uint32_t)(b.c[1] % B)) *
-                                       (uint32_t)B + (uint32_t)(b.c[0] % B);
-            key = brick * (uint32_t)(B * B * B) + local;
-        }
+        if (bead_cell(R[i], sk.m, b))
+            key = brick_of(b.c[0], b.c[1], b.c[2], sk.B, sk.nb);
         keys[i] = key;
     }
-    int head, len;
-    wave_runs(key, active, &head, &len);
+    // one atomic per distinct key of the wavefront
+    const uint64_t grp = wave_key_group(key, active);
     const int lane = threadIdx.x & (kWave - 1);
-    if (active && head == lane)
-        atomicAdd(hist + key, (uint32_t)len);
+    if (active && __builtin_ctzll(grp) == lane)
+        atomicAdd(hist + key, (uint32_t)__builtin_popcountll(grp));
 }
 
 // Per-tile exclusive scan in place; tile totals to tile_sums.
@@ -121,8 +119,8 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_add(uint32_t* __restrict_
         a[i] += tile_sums[i / kScanTile];
 }
 
-// Placement: each run of equal keys in a wavefront reserves its slots with
-// one atomic; tags travel with the permutation so the in-cell sort reads
+// Placement: each group of equal keys in a wavefront reserves its slots with
+// one atomic; tags travel with the permutation so the in-brick sort reads
 // them contiguously.
 __global__ __launch_bounds__(kSortThreads) void k_sort_place(const uint32_t* __restrict__ keys, int64_t N,
                                                              const int32_t* __restrict__ tag,
@@ -133,55 +131,141 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_place(const uint32_t* __r
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
     const bool active = i < N;
     const uint32_t key = active ? keys[i] : 0xffffffffu;
-    int head, len;
-    wave_runs(key, active, &head, &len);
+    const uint64_t grp = wave_key_group(key, active);
     const int lane = threadIdx.x & (kWave - 1);
+    const int leader = active ? __builtin_ctzll(grp) : lane;
     uint32_t base = 0;
-    if (active && head == lane)
-        base = atomicAdd(cursor + key, (uint32_t)len);
-    base = __shfl(base, head, kWave);
+    if (active && leader == lane)
+        base = atomicAdd(cursor + key, (uint32_t)__builtin_popcountll(grp));
+    base = __shfl(base, leader, kWave);
     if (active) {
-        const uint32_t pos = base + (uint32_t)(lane - head);
+        const uint32_t pos = base + (uint32_t)__builtin_popcountll(grp & ((1ull << lane) - 1));
         perm[pos] = (int32_t)i;
         ptag[pos] = tag ? tag[i] : (int32_t)i;
     }
 }
 
 // Sort every key's segment of (perm, ptag) by tag (by input index when there
-// are no tags); insertion sort over contiguous entries, segments are a few
-// beads long. Longer segments keep their placement order and raise a flag.
-__global__ __launch_bounds__(kSortThreads) void k_sort_segments(const uint32_t* __restrict__ start,
-                                                                int64_t nseg,
-                                                                int32_t* __restrict__ ptag,
-                                                                int32_t* __restrict__ perm)
+// are no tags): one workgroup per segment runs a bitonic sort of (tag, perm)
+// pairs, padded to a power of two (at least one element per thread) with
+// entries that sort last. Element e = r * 512 + t lives in register row r of
+// thread t: compare-exchange partners at distance j >= 512 are in the same
+// thread, at j < 64 in the same wavefront (lane shuffles), and only
+// 64 <= j < 512 go through LDS. Tags compare as signed integers; they are
+// unique, so perm breaks no ties. A segment longer than kBrickSortMax keeps
+// its placement order and raises HPF_FLAG_SORT_ORDER.
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m)
 {
-    const int64_t k = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
-    if (k >= nseg)
-        return;
-    const uint32_t a = start[k], b = start[k + 1];
-    const uint32_t len = b - a;
-    if (len <= 1)
-        return;
-    if (len > (uint32_t)kSegSortMax) {
-        raise_flag(HPF_FLAG_SORT_ORDER);
-        return;
-    }
-    bool sorted = true;
-    for (uint32_t i = a + 1; i < b; ++i)
-        sorted &= ptag[i - 1] <= ptag[i];
-    if (sorted)
-        return;
-    for (uint32_t i = a + 1; i < b; ++i) {
-        const int32_t pi = perm[i];
-        const int32_t ti = ptag[i];
-        uint32_t j = i;
-        while (j > a && ptag[j - 1] > ti) {
-            perm[j] = perm[j - 1];
-            ptag[j] = ptag[j - 1];
-            --j;
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, kWave);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// compare-exchange of register rows r and r + D (D = j / 512) for r with bit D clear
+template <int D, int ROWS>
+__device__ __forceinline__ void bitonic_rows(unsigned long long (&v)[ROWS], uint32_t t, uint32_t k)
+{
+    if constexpr (D < ROWS) {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            if ((r & D) == 0) {
+                const uint32_t e = (uint32_t)r * kBrickSortThreads + t;
+                const unsigned long long x = v[r], y = v[r | D];
+                const bool sw = (x > y) == ((e & k) == 0);
+                v[r] = sw ? y : x;
+                v[r | D] = sw ? x : y;
+            }
         }
-        perm[j] = pi;
-        ptag[j] = ti;
+    }
+}
+
+// Bitonic sort of one segment of n <= ROWS * 512 entries starting at a.
+template <int ROWS>
+__device__ __forceinline__ void sort_segment(uint32_t a, uint32_t n, int32_t* __restrict__ ptag,
+                                             int32_t* __restrict__ perm, unsigned long long* sh)
+{
+    const uint32_t t = threadIdx.x;
+    constexpr uint32_t np = (uint32_t)ROWS * kBrickSortThreads;
+    unsigned long long v[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const uint32_t e = (uint32_t)r * kBrickSortThreads + t;
+        v[r] = e < n ? ((unsigned long long)((uint32_t)ptag[a + e] ^ 0x80000000u) << 32) | (uint32_t)perm[a + e]
+                     : ~0ull;
+    }
+    for (uint32_t k = 2; k <= np; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            if (j >= (uint32_t)kBrickSortThreads) {
+                const uint32_t d = j / kBrickSortThreads;
+                if (d == 1)
+                    bitonic_rows<1, ROWS>(v, t, k);
+                else if (d == 2)
+                    bitonic_rows<2, ROWS>(v, t, k);
+                else if (d == 4)
+                    bitonic_rows<4, ROWS>(v, t, k);
+                else
+                    bitonic_rows<8, ROWS>(v, t, k);
+            } else if (j >= (uint32_t)kWave) {
+                __syncthreads();                       // earlier reads of sh are done
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r)
+                    sh[r * kBrickSortThreads + t] = v[r];
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    const uint32_t e = (uint32_t)r * kBrickSortThreads + t, p = e ^ j;
+                    const unsigned long long x = v[r], y = sh[p];
+                    const bool keep_min = (e < p) == ((e & k) == 0);
+                    v[r] = keep_min == (x < y) ? x : y;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    const uint32_t e = (uint32_t)r * kBrickSortThreads + t;
+                    const unsigned long long x = v[r], y = shfl_xor_u64(x, (int)j);
+                    const bool keep_min = (t & j) == 0 ? ((e & k) == 0) : ((e & k) != 0);
+                    v[r] = keep_min == (x < y) ? x : y;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const uint32_t e = (uint32_t)r * kBrickSortThreads + t;
+        if (e < n) {
+            ptag[a + e] = (int32_t)((uint32_t)(v[r] >> 32) ^ 0x80000000u);
+            perm[a + e] = (int32_t)(uint32_t)v[r];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBrickSortThreads, 4) void k_sort_bricks(const uint32_t* __restrict__ start,
+                                                                   int64_t nseg, int32_t* __restrict__ ptag,
+                                                                   int32_t* __restrict__ perm)
+{
+    __shared__ unsigned long long sh[kBrickSortMax];
+    for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        const uint32_t a = start[seg], b = start[seg + 1];
+        const uint32_t n = b - a;
+        if (n <= 1)
+            continue;
+        if (n > (uint32_t)kBrickSortMax) {
+            if (threadIdx.x == 0)
+                raise_flag(HPF_FLAG_SORT_ORDER);
+            continue;
+        }
+        if (n <= 512)
+            sort_segment<1>(a, n, ptag, perm, sh);
+        else if (n <= 1024)
+            sort_segment<2>(a, n, ptag, perm, sh);
+        else if (n <= 2048)
+            sort_segment<4>(a, n, ptag, perm, sh);
+        else if (n <= 4096)
+            sort_segment<8>(a, n, ptag, perm, sh);
+        else
+            sort_segment<16>(a, n, ptag, perm, sh);
+        __syncthreads();                               // sh is free for the next segment
     }
 }
 
@@ -241,7 +325,7 @@ bool sort_layout(int64_t N, const int32_t M[3], int B, SortK* sk_out, size_t* by
         B = 8;
     if (B < 1 || B > 16 || N < 0 || N > 0x7ffffff0LL)
         return false;
-    int64_t nk = (int64_t)B * B * B;
+    int64_t nk = 1;
     int32_t nb[3];
     for (int d = 0; d < 3; ++d) {
         nb[d] = (M[d] + B - 1) / B;
@@ -301,8 +385,8 @@ hpf_status_t launch_sort(const SortK& sk, int64_t N, const float* R_in, const fl
         hipLaunchKernelGGL(k_copy_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, cursor, nscan);
         hipLaunchKernelGGL(k_sort_place, dim3(grid_for(N)), dim3(kSortThreads), 0, s, keys, N,
                            tag_in, cursor, perm, ptag);
-        hipLaunchKernelGGL(k_sort_segments, dim3(grid_for(nscan - 1)), dim3(kSortThreads), 0, s,
-                           start, nscan - 1, ptag, perm);
+        hipLaunchKernelGGL(k_sort_bricks, dim3((unsigned)std::min<int64_t>(nscan - 1, 1 << 20)),
+                           dim3(kBrickSortThreads), 0, s, start, nscan - 1, ptag, perm);
         hipLaunchKernelGGL(k_sort_permute, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, N,
                            reinterpret_cast<const float4*>(R_in), reinterpret_cast<const float4*>(V_in),
                            T_in, tag_in, reinterpret_cast<float4*>(R_out),

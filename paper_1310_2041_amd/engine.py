@@ -28,7 +28,7 @@ class HpfState:
     """One periodic system on the GPU: beads, bond table, mesh buffers."""
 
     def __init__(self, R, Vel, T, tag, bonds, L, M, K, kT, inv_kappa, chi, k_bond, r0, dt,
-                 device="cuda", sort_brick=8, halo=1):
+                 device="cuda", sort_brick=8, halo=1, advance_halo=1, advance="plain"):
         dev = torch.device(device)
         self.N = int(R.shape[0])
         self.K = int(K)
@@ -41,6 +41,10 @@ class HpfState:
         self.box = self.L
         self.B = int(sort_brick)
         self.halo = int(halo)
+        self.advance_halo = int(advance_halo)
+        # "plain": hpf_advance (the faster on gfx950 in brick order); "cells": hpf_advance_cells
+        # whenever the beads are cell-sorted
+        self.advance_mode = advance
         self.sorted = False      # storage order comes from hpf_sort_by_cell
         nm = self.mesh.M[0] * self.mesh.M[1] * self.mesh.M[2]
         self.nm = nm
@@ -157,14 +161,29 @@ class HpfState:
         hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V,
                                 self.part[ROW_W] if report else None, stream)
         hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
-        hpf.hpf_advance(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G,
-                        self.bonds if self.bonds.shape[0] else None, self.k_bond, self.r0, self.box,
-                        self.dt, e_part=self.part[ROW_EB] if report else None,
-                        kin_part=self.part[ROW_KE:ROW_KE + 4] if report else None, stream=stream)
-        self.R, self.R2 = self.R2, self.R
+        self.advance(report, stream)
         if report:
             hpf.hpf_reduce_partials(self.part, N_ROWS, self.energy, stream)
         self.steps_done += 1
+
+    def uses_cells_advance(self) -> bool:
+        return (self.advance_mode == "cells" and self.sorted and
+                hpf.advance_cells_fits(self.K, self.B, self.advance_halo))
+
+    def advance(self, report=False, stream=None):
+        """Fused forces + Verlet pass, x_n -> x_n+1 (the brick-box variant when cell-sorted)."""
+        bonds = self.bonds if self.bonds.shape[0] else None
+        e_part = self.part[ROW_EB] if report else None
+        kin_part = self.part[ROW_KE:ROW_KE + 4] if report else None
+        if self.uses_cells_advance():
+            hpf.hpf_advance_cells(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
+                                  self.k_bond, self.r0, self.box, self.dt, self.cell_start, self.B,
+                                  self.advance_halo, e_part=e_part, kin_part=kin_part, stream=stream)
+        else:
+            hpf.hpf_advance(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
+                            self.k_bond, self.r0, self.box, self.dt, e_part=e_part,
+                            kin_part=kin_part, stream=stream)
+        self.R, self.R2 = self.R2, self.R
 
     def run_fused(self, n_steps, report_every=0, sort_every=10, stream=None):
         out = []

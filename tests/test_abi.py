@@ -89,11 +89,24 @@ def test_invalid_arguments_rejected_on_host(hpf):
                               t_out, None, None, None, dummy, 1 << 30, None) == EINVAL
     assert L.hpf_sort_workspace_bytes(10, C.byref(m), 17) == 0
     assert L.hpf_get_device_status(None, 0, None) == EINVAL
+    # hpf_advance_cells: brick, halo, LDS size, missing cell list, aliasing
+    r_n, v, g, cs = (C.c_void_p(0x1000 * k) for k in (6, 7, 8, 9))
+
+    def adv(K=2, B=8, halo=1, cell_start=cs, R_next=r_n):
+        return L.hpf_advance_cells(r_in, R_next, v, t_in, 10, C.byref(m), K, g, None, 0, 100.0, 0.0,
+                                   box, None, 0.03, cell_start, B, halo, None, None, None, None)
+    assert adv(B=9) == EINVAL
+    assert adv(B=2) == EINVAL
+    assert adv(halo=3) == EINVAL
+    assert adv(B=3, halo=3) == EINVAL
+    assert adv(K=8, halo=1) == EINVAL                # 8 x 11^3 x 16 B > 160 KiB of LDS
+    assert adv(cell_start=None) == EINVAL
+    assert adv(R_next=r_in) == EINVAL
 
 
 def test_sort_workspace_size(hpf):
     m = hpf.hpf_mesh_make(149.4, 128, 10_000_000)
     n = hpf.hpf_sort_workspace_bytes(10_000_000, m, 8)
     nk = hpf.sort_key_count(m, 8)
-    assert nk == 128 ** 3
+    assert nk == 16 ** 3                      # one key per brick of 8^3 cells
     assert n >= 3 * 4 * 10_000_000 + 2 * 4 * (nk + 2)

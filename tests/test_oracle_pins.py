@@ -318,7 +318,7 @@ def test_verlet_kinematics_and_wrap(oracle_mod):
 
 # ---------------------------------------------------------------- a0 -------
 
-def test_sort_permutation_orders_by_brick_key_then_tag(oracle_mod):
+def test_sort_permutation_orders_by_brick_then_tag(oracle_mod):
     s = wl.small_system(300, 10, (13.1, 9.7, 21.0), (13, 10, 21), seed=9)
     sp, _ = wl.permuted(s)
     B = 4
@@ -333,5 +333,4 @@ def test_sort_permutation_orders_by_brick_key_then_tag(oracle_mod):
     for i in range(0, sp.N, 37):
         c = [bf.cell_weights(float(sp.R[i, d]), sp.L[d], sp.M[d])[0] for d in range(3)]
         brick = ((c[2] // B) * nb[1] + c[1] // B) * nb[0] + c[0] // B
-        local = ((c[2] % B) * B + c[1] % B) * B + c[0] % B
-        assert keys[i] == brick * B ** 3 + local
+        assert keys[i] == brick
