@@ -30,6 +30,9 @@ def algorithmic_bytes(name: str, N: int, K: int, nm: int, D: int) -> float:
     return {
         "verlet_half1": 80.0 * N,                   # R, Vel read+write; F read
         "density_scatter": 17.0 * N + 8.0 * K * nm,  # R, T read; counts written once
+        # counts of the positions the fused pass deposited, written once (the partial
+        # boxes between the two passes are this design's own traffic)
+        "density_finish": 8.0 * K * nm,
         "field_potential": 20.0 * K * nm,            # counts read + cleared; V written
         "field_gradient": 20.0 * K * nm,             # V read; G written
         "force_gather": 33.0 * N + 16.0 * K * nm,    # R, T read; F written; G read once
@@ -86,7 +89,7 @@ def timed_step(st, hpf, engine, tm, sort):
 def timed_step_fused(st, hpf, engine, tm, sort):
     if sort:
         tm.wrap("sort_by_cell", st.sort)
-    tm.wrap("density_scatter", st.scatter)
+    tm.wrap("density_finish" if st.density_pending else "density_scatter", st.density)
     tm.wrap("field_potential", hpf.hpf_field_potential, st.counts, st.mesh, st.field, st.V,
             st.part[engine.ROW_W])
     tm.wrap("field_gradient", hpf.hpf_field_gradient, st.V, st.mesh, st.K, st.G)
@@ -95,7 +98,8 @@ def timed_step_fused(st, hpf, engine, tm, sort):
     st.steps_done += 1
 
 
-def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, graph=True):
+def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, graph=True, halo=2,
+                 advance="scatter"):
     """Warm up, time `steps` steps, then (instrument) time each call over one graph's worth
     of eager steps. With `graph`, the timed steps replay a HIP graph of two sort periods:
     every buffer swap of the step then returns to its start, so the graph can be looped."""
@@ -106,7 +110,7 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
 
     spec = wl.SPECS[cfg]
     s = wl.build(spec)
-    st = engine.HpfState.from_system(s)
+    st = engine.HpfState.from_system(s, halo=halo, advance=advance)
     del s
     st.start(sort=True)
     if fused:
@@ -155,7 +159,8 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
     return {"spec": spec, "N": st.N, "K": st.K, "nm": st.nm, "D": st.bonds.shape[0],
             "ms_total": ms, "wall_s": wall, "kernels": tm.summary() if instrument else {},
             "flags": flags, "energies": e, "graph": use_graph,
-            "advance_kernel": "cells" if st.uses_cells_advance() else "plain"}
+            "advance_kernel": ("scatter" if st.uses_scatter_advance() else
+                               "cells" if st.uses_cells_advance() else "plain")}
 
 
 def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
@@ -216,9 +221,11 @@ def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
 # rocprofv3 kernel names behind each timed call of the step
 ROCPROF_KERNELS = {
     "advance": ["hpf::k_advance<true>", "hpf::k_advance<false>", "hpf::k_advance_cells<true>",
-                "hpf::k_advance_cells<false>"],
-    "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum",
+                "hpf::k_advance_cells<false>", "hpf::k_advance_scatter<true>",
+                "hpf::k_advance_scatter<false>"],
+    "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum<false>",
                         "hpf::k_scatter_strays"],
+    "density_finish": ["hpf::k_scatter_sum<true>"],
     "field_potential": ["hpf::k_field_potential<%d>" % k for k in range(1, 9)],
     "field_gradient": ["hpf::k_field_gradient"],
 }
@@ -266,12 +273,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--also", default="c2", help="second workload reported under 'also' ('' = none)")
-    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--sort-every", type=int, default=20)
     ap.add_argument("--mode", default="fused", choices=["fused", "api"],
                     help="fused: hpf_advance; api: the six separate calls")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batched sweep")
+    ap.add_argument("--halo", type=int, default=2, help="drift halo (cells) of the brick deposit boxes")
+    ap.add_argument("--advance", default="scatter", choices=["scatter", "plain", "cells"],
+                    help="fused pass on cell-sorted beads (scatter: with the density deposit)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every call from Python instead of replaying HIP graphs")
     args = ap.parse_args()
@@ -288,7 +298,7 @@ def main():
 
     fused = args.mode == "fused"
     r = run_workload(args.config, args.steps, args.warmup, args.sort_every, fused=fused,
-                     graph=not args.eager)
+                     graph=not args.eager, halo=args.halo, advance=args.advance)
     ms_step = r["ms_total"] / args.steps
     value = r["N"] * args.steps / (r["ms_total"] * 1e-3)
     kern = r["kernels"]
@@ -320,6 +330,7 @@ def main():
         "config": {"workload": r["spec"].name, "beads": r["N"], "species": r["K"],
                    "mesh": [r["spec"].M] * 3, "box": r["spec"].L, "sort_every": args.sort_every,
                    "energy_report_every": 1, "step": args.mode, "advance": r["advance_kernel"],
+                   "halo": args.halo,
                    "launch": "hip_graph" if r["graph"] else "eager", "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -330,7 +341,7 @@ def main():
     }
     if args.also and args.also != args.config:
         r2 = run_workload(args.also, args.steps, args.warmup, args.sort_every, instrument=False,
-                          fused=fused, graph=not args.eager)
+                          fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance)
         out["also"] = {"workload": r2["spec"].name, "beads": r2["N"],
                        "value": r2["N"] * args.steps / (r2["ms_total"] * 1e-3),
                        "ms_per_step": r2["ms_total"] / args.steps,

@@ -291,6 +291,47 @@ hpf_status_t hpf_advance_cells(const float* R, float* R_next, float* Vel, const 
                                const uint32_t* cell_start, int32_t B, int32_t halo,
                                float* F_out, double* e_part, double* kin_part, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * hpf_advance_scatter -- hpf_advance (bit for bit the same bead updates) that
+ * also deposits the new positions x_{n+1} for the next step's density (the
+ * assignment of the MD-SCF section, Algorithm 1 Kernel 2), so the next step
+ * need not read the beads again for it. One workgroup takes the beads one
+ * brick listed at the last sort, advances them and adds the fixed-point
+ * weights of their new positions to the brick's LDS deposit box, which is
+ * stored to the brick's partial buffer in `work` (the layout that
+ * hpf_density_scatter_cells uses). New positions more than `halo` cells out
+ * of their brick, and beads the sort could not bin, are added to `counts`
+ * with global atomics. hpf_density_finish_cells then adds the partial boxes
+ * to `counts`; the result equals hpf_density_scatter(R_next) bit for bit.
+ *
+ * Arguments as in hpf_advance, plus:
+ * cell_start, B, halo  as in hpf_density_scatter_cells (same limits).
+ * counts  uint64[K][M^3] device, ADDED to; it must hold zeros (or counts to be
+ *         kept) on entry. hpf_field_potential leaves it zeroed.
+ * work    device workspace of at least hpf_scatter_workspace_bytes(N, mesh,
+ *         K, B, halo) bytes (HPF_ESPACE otherwise); its partial boxes are
+ *         overwritten and must not be touched before hpf_density_finish_cells.
+ * The energy partials are grouped by workgroup (as in hpf_advance_cells).
+ * Positions that cannot be binned set HPF_FLAG_BAD_BEAD.
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_advance_scatter(const float* R, float* R_next, float* Vel, const uint8_t* T,
+                                 int64_t N, const hpf_mesh_t* mesh, int32_t K, const float* G,
+                                 const int32_t* bonds, int32_t D, float k, float r0,
+                                 const float* box, const float* inv_mass, float dt,
+                                 const uint32_t* cell_start, int32_t B, int32_t halo,
+                                 uint64_t* counts, void* work, size_t work_bytes, float* F_out,
+                                 double* e_part, double* kin_part, void* stream);
+
+/* hpf_density_finish_cells -- counts += the sum of the partial deposit boxes
+ * that hpf_advance_scatter left in `work` (same N, mesh, K, B, halo), i.e.
+ * the second pass of hpf_density_scatter_cells in accumulate form. After it,
+ * `counts` holds the exact density counts of the positions that
+ * hpf_advance_scatter produced, whatever the bead order in between (a
+ * hpf_sort_by_cell call between the two does not change them). */
+hpf_status_t hpf_density_finish_cells(uint64_t* counts, int64_t N, const hpf_mesh_t* mesh,
+                                      int32_t K, int32_t B, int32_t halo, const void* work,
+                                      size_t work_bytes, void* stream);
+
 /* Deterministic FP64 reduction of partial-sum buffers: out[c] = sum of
  * part[c*HPF_NPART .. (c+1)*HPF_NPART) in a fixed tree order, c < ncomp.
  * part and out are device pointers; ncomp in [1, 8]. */

@@ -302,6 +302,55 @@ hpf_status_t hpf_advance_cells(const float* R, float* R_next, float* Vel, const 
                                 F_out, e_part, kin_part, as_stream(stream));
 }
 
+static bool advance_args_ok(int64_t N, const hpf_mesh_t* mesh, int32_t K, int32_t D, float k, float r0,
+                            const float* box, float dt)
+{
+    return N >= 0 && N <= 0x7fffffffLL && mesh_ok(mesh) && K >= 1 && K <= HPF_MAX_TYPES && D >= 0 &&
+           D <= HPF_MAX_BONDS && box_ok(box) && std::isfinite(k) && std::isfinite(r0) && dt > 0.0f &&
+           std::isfinite(dt);
+}
+
+hpf_status_t hpf_advance_scatter(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
+                                 const hpf_mesh_t* mesh, int32_t K, const float* G, const int32_t* bonds,
+                                 int32_t D, float k, float r0, const float* box, const float* inv_mass, float dt,
+                                 const uint32_t* cell_start, int32_t B, int32_t halo, uint64_t* counts, void* work,
+                                 size_t work_bytes, float* F_out, double* e_part, double* kin_part, void* stream)
+{
+    TileK tk;
+    size_t sb = 0, tb = 0;
+    if (!advance_args_ok(N, mesh, K, D, k, r0, box, dt) || !counts || !cell_start ||
+        !scatter_cells_setup(N, mesh, K, B, halo, &tk, &sb, &tb))
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !R_next || !Vel || !T || !G || (D > 0 && !bonds) || R == R_next))
+        return HPF_EINVAL;
+    if (!work || work_bytes < tb)
+        return HPF_ESPACE;
+    BoxK b;
+    for (int d = 0; d < 3; ++d) {
+        b.L[d] = box[d];
+        b.halfL[d] = 0.5f * box[d];
+    }
+    char* w = static_cast<char*>(work);
+    return launch_advance_scatter(R, R_next, Vel, T, N, tk, K, G, bonds, D, k, r0, b, inv_mass, dt, cell_start,
+                                  reinterpret_cast<unsigned long long*>(w + sb),
+                                  reinterpret_cast<unsigned long long*>(counts), F_out, e_part, kin_part,
+                                  as_stream(stream));
+}
+
+hpf_status_t hpf_density_finish_cells(uint64_t* counts, int64_t N, const hpf_mesh_t* mesh, int32_t K, int32_t B,
+                                      int32_t halo, const void* work, size_t work_bytes, void* stream)
+{
+    TileK tk;
+    size_t sb = 0, tb = 0;
+    if (!counts || !scatter_cells_setup(N, mesh, K, B, halo, &tk, &sb, &tb))
+        return HPF_EINVAL;
+    if (!work || work_bytes < tb)
+        return HPF_ESPACE;
+    const char* w = static_cast<const char*>(work);
+    return launch_scatter_finish(reinterpret_cast<const unsigned long long*>(w + sb), tk, K,
+                                 reinterpret_cast<unsigned long long*>(counts), as_stream(stream));
+}
+
 hpf_status_t hpf_reduce_partials(const double* part, int32_t ncomp, double* out, void* stream)
 {
     if (!part || !out || ncomp < 1 || ncomp > 8)

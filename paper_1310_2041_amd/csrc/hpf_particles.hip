@@ -380,7 +380,7 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__
 // of step n + 1, written to R_next.
 // With kBox the corners come from the brick box `gb` where they can.
 template <bool kR0Zero, bool kBox = false>
-__device__ __forceinline__ void advance_bead(int64_t i, const float4* __restrict__ R, float4* __restrict__ R_next,
+__device__ __forceinline__ float4 advance_bead(int64_t i, const float4* __restrict__ R, float4* __restrict__ R_next,
                                              float4* __restrict__ Vel, const uint8_t* __restrict__ T,
                                              int64_t N, const MeshK& m, int K, const float4* __restrict__ G,
                                              const int32_t* __restrict__ bonds, int D, float k, float r0,
@@ -413,6 +413,7 @@ __device__ __forceinline__ void advance_bead(int64_t i, const float4* __restrict
     nonfinite |= !(finite4(r) && finite4(v));
     Vel[i] = v;
     R_next[i] = r;
+    return r;
 }
 
 // Fused pass over the beads. Positions go to R_next so that bond partners
@@ -565,6 +566,99 @@ __global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __res
         acc.store(kin_part, blockIdx.x, scratch);
 }
 
+// The fused pass plus the density deposit of the new positions, one brick of
+// the last sort at a time (bricks walked as in k_advance_cells). Each bead is
+// advanced exactly as in k_advance; its new position x_{n+1} is deposited into
+// the brick's LDS box (the deposit box of the cell scatter, P = B + 1 + 2h
+// points per axis), which is stored to the brick's partial buffer when the
+// brick is done. New positions outside the box, and every bead the sort could
+// not bin, are added to `counts` with global atomics; the partial sum pass
+// (k_scatter_sum<true>) then completes the counts of x_{n+1}.
+constexpr int kASThreads = 256;
+
+template <bool kR0Zero>
+__global__ __launch_bounds__(kASThreads, 5) void k_advance_scatter(const float4* __restrict__ R,
+                                                                float4* __restrict__ R_next,
+                                                                float4* __restrict__ Vel,
+                                                                const uint8_t* __restrict__ T, int64_t N,
+                                                                TileK tk, int K, const float4* __restrict__ G,
+                                                                const int32_t* __restrict__ bonds, int D,
+                                                                float k, float r0, BoxK box,
+                                                                const float* __restrict__ inv_mass, float dt,
+                                                                const uint32_t* __restrict__ cell_start,
+                                                                unsigned long long* __restrict__ partials,
+                                                                unsigned long long* __restrict__ counts,
+                                                                float4* __restrict__ F_out,
+                                                                double* __restrict__ e_part,
+                                                                double* __restrict__ kin_part)
+{
+    extern __shared__ unsigned long long dbox[];
+    __shared__ double scratch[kASThreads / kWave];
+    clear_unused_slots(e_part, 1);
+    clear_unused_slots(kin_part, 4);
+    const MeshK& m = tk.m;
+    const int B = tk.B, P = tk.P, h = tk.h;
+    const int P3 = P * P * P;
+    const int nbox = K * P3;
+    const BrickWalk w = brick_walk(tk.ntiles + 1);
+    const float hdt = 0.5f * dt;
+    KinAcc acc;
+    double e = 0.0;
+    bool bad_bead = false, bad_bond = false, nonfinite = false;
+    for (int64_t item = w.first; item < w.end; item += w.stride) {
+        if (item < tk.ntiles) {
+            const int bx = (int)(item % tk.nb[0]);
+            const int by = (int)((item / tk.nb[0]) % tk.nb[1]);
+            const int bz = (int)(item / ((int64_t)tk.nb[0] * tk.nb[1]));
+            const int x0 = bx * B, y0 = by * B, z0 = bz * B;
+            const int ox = min(B, m.M[0] - x0), oy = min(B, m.M[1] - y0), oz = min(B, m.M[2] - z0);
+            __syncthreads();                          // the previous brick's box is stored
+            for (int q = threadIdx.x; q < nbox; q += kASThreads)
+                dbox[q] = 0ull;
+            __syncthreads();
+            const int64_t first = cell_start[item];
+            const int64_t last = min((int64_t)cell_start[item + 1], N);
+            for (int64_t i = first + threadIdx.x; i < last; i += kASThreads) {
+                const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box,
+                                                        inv_mass, dt, hdt, F_out, acc, e, bad_bead, bad_bond,
+                                                        nonfinite);
+                const int t = T[i];
+                BeadCell b;
+                int lx, ly, lz;
+                if (bead_cell(rn, m, b) && t < K && brick_box_cell(b, m, x0, y0, z0, ox, oy, oz, h, lx, ly, lz))
+                    box_deposit(dbox, P, t, lx, ly, lz, b);
+                else
+                    bad_bead |= !deposit_global(rn, t, K, m, counts);
+            }
+            __syncthreads();
+            unsigned long long* out = partials + item * (int64_t)nbox;
+            for (int q = threadIdx.x; q < nbox; q += kASThreads)
+                out[q] = dbox[q];
+        } else {
+            const int64_t first = cell_start[tk.NK];
+            for (int64_t i = first + threadIdx.x; i < N; i += kASThreads) {
+                const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box,
+                                                        inv_mass, dt, hdt, F_out, acc, e, bad_bead, bad_bond,
+                                                        nonfinite);
+                bad_bead |= !deposit_global(rn, T[i], K, m, counts);
+            }
+        }
+    }
+    if (bad_bead)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+    if (bad_bond)
+        raise_flag(HPF_FLAG_BAD_BOND);
+    if (nonfinite)
+        raise_flag(HPF_FLAG_NONFINITE);
+    if (e_part) {
+        const double s = block_sum(e, scratch);
+        if (threadIdx.x == 0)
+            e_part[blockIdx.x] = s;
+    }
+    if (kin_part)
+        acc.store(kin_part, blockIdx.x, scratch);
+}
+
 // ---------------------------------------------------------------- launches --
 
 static int64_t bead_blocks(int64_t N, int64_t cap)
@@ -679,6 +773,47 @@ hpf_status_t launch_advance_cells(const float* R, float* R_next, float* Vel, con
     else
         hipLaunchKernelGGL(k_advance_cells<false>, g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0,
                            box, inv_mass, dt, cell_start, Fo, e_part, kin_part);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
+                                    const TileK& tk, int K, const float* G, const int32_t* bonds, int D, float k,
+                                    float r0, const BoxK& box, const float* inv_mass, float dt,
+                                    const uint32_t* cell_start, unsigned long long* partials,
+                                    unsigned long long* counts, float* F_out, double* e_part, double* kin_part,
+                                    hipStream_t s)
+{
+    const size_t smem = sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P;
+    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_scatter<true>)
+                                : reinterpret_cast<const void*>(k_advance_scatter<false>);
+    if (smem > 65536 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+        return HPF_EINVAL;
+    int64_t nb = resident_blocks(fn, kASThreads, smem);
+    if (nb < 1)
+        nb = 1024;
+    nb = std::min<int64_t>(nb, tk.ntiles + 1);
+    if ((e_part || kin_part) && nb > HPF_NPART)
+        nb = HPF_NPART;
+    const dim3 g((unsigned)nb), bl(kASThreads);
+    auto* Rp = reinterpret_cast<const float4*>(R);
+    auto* Rn = reinterpret_cast<float4*>(R_next);
+    auto* Vp = reinterpret_cast<float4*>(Vel);
+    auto* Gp = reinterpret_cast<const float4*>(G);
+    auto* Fo = reinterpret_cast<float4*>(F_out);
+    if (r0 == 0.0f)
+        hipLaunchKernelGGL(k_advance_scatter<true>, g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0,
+                           box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
+    else
+        hipLaunchKernelGGL(k_advance_scatter<false>, g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k,
+                           r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+hpf_status_t launch_scatter_finish(const unsigned long long* partials, const TileK& tk, int K,
+                                   unsigned long long* counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter_sum<true>, dim3((unsigned)tk.ntiles), dim3(256), 0, s, partials, tk, K, counts);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 

@@ -67,6 +67,43 @@ __device__ __forceinline__ void lds_add_u64(unsigned long long* p, unsigned long
 }
 
 
+// Cell of bead b relative to the deposit box of the brick whose first cell is
+// (x0, y0, z0) and whose width is (ox, oy, oz) cells: true, with the local
+// cell (lx, ly, lz), when the bead's 8 corners lie in the part of the box that
+// the sum pass reads (box points [0, o + 2h] per axis).
+__device__ __forceinline__ bool brick_box_cell(const BeadCell& b, const MeshK& m, int x0, int y0, int z0, int ox,
+                                               int oy, int oz, int h, int& lx, int& ly, int& lz)
+{
+    lx = periodic_delta(b.c[0], x0, m.M[0]) + h;
+    ly = periodic_delta(b.c[1], y0, m.M[1]) + h;
+    lz = periodic_delta(b.c[2], z0, m.M[2]) + h;
+    return lx >= 0 && lx <= ox - 1 + 2 * h && ly >= 0 && ly <= oy - 1 + 2 * h && lz >= 0 && lz <= oz - 1 + 2 * h;
+}
+
+// Adds one bead's 8 fixed-point corner weights to species t of an LDS box of
+// P^3 points at local cell (lx, ly, lz). The corner weights come from two
+// products: with w0 = 2^S - w1 per axis, W(0, ., .) = 2^S W_yz - W(1, ., .),
+// and likewise along y and z.
+__device__ __forceinline__ void box_deposit(unsigned long long* box, int P, int t, int lx, int ly, int lz,
+                                            const BeadCell& b)
+{
+    const int P2 = P * P;
+    const uint64_t yz11 = (uint64_t)b.q[1] * b.q[2];
+    const uint64_t yz01 = ((uint64_t)b.q[2] << HPF_FIX_BITS) - yz11;   // wy0 wz1
+    const uint64_t yz10 = ((uint64_t)b.q[1] << HPF_FIX_BITS) - yz11;   // wy1 wz0
+    const uint64_t yz00 = ((uint64_t)kOne << HPF_FIX_BITS) - yz11 - yz01 - yz10;
+    unsigned long long* c0 = box + t * P2 * P + (lz * P + ly) * P + lx;
+    const uint64_t q0 = b.q[0];
+    lds_add_u64(c0, (yz00 << HPF_FIX_BITS) - yz00 * q0);
+    lds_add_u64(c0 + 1, yz00 * q0);
+    lds_add_u64(c0 + P, (yz10 << HPF_FIX_BITS) - yz10 * q0);
+    lds_add_u64(c0 + P + 1, yz10 * q0);
+    lds_add_u64(c0 + P2, (yz01 << HPF_FIX_BITS) - yz01 * q0);
+    lds_add_u64(c0 + P2 + 1, yz01 * q0);
+    lds_add_u64(c0 + P2 + P, (yz11 << HPF_FIX_BITS) - yz11 * q0);
+    lds_add_u64(c0 + P2 + P + 1, yz11 * q0);
+}
+
 // Pass 1: one workgroup per brick deposits the beads listed in that brick --
 // one contiguous range of the cell-sorted arrays -- into an LDS box of
 // P = B + 1 + 2h mesh points per axis starting h points below the brick (a
@@ -124,16 +161,9 @@ __device__ __forceinline__ void scatter_brick_body(const float4* __restrict__ R,
                 continue;
             const int t = tj[u];
             BeadCell b;
+            int lx, ly, lz;
             const bool ok = bead_cell(rj[u], tk.m, b) && t < K;
-            // current cell relative to the box origin (x0 - h, ...), periodic
-            int lx = 0, ly = 0, lz = 0;
-            if (ok) {
-                lx = periodic_delta(b.c[0], x0, Mx) + h;
-                ly = periodic_delta(b.c[1], y0, My) + h;
-                lz = periodic_delta(b.c[2], z0, Mz) + h;
-            }
-            if (!ok || lx < 0 || lx > ox - 1 + 2 * h || ly < 0 || ly > oy - 1 + 2 * h || lz < 0 ||
-                lz > oz - 1 + 2 * h) {
+            if (!ok || !brick_box_cell(b, tk.m, x0, y0, z0, ox, oy, oz, h, lx, ly, lz)) {
                 const uint32_t slot = atomicAdd(&stray_n, 1u);
                 if (slot < (uint32_t)kStrayStage)
                     stray_buf[slot] = p;
@@ -141,22 +171,7 @@ __device__ __forceinline__ void scatter_brick_body(const float4* __restrict__ R,
                     strays[1 + atomicAdd(strays, 1u)] = p;       // stage full: direct append
                 continue;
             }
-            // corner weights from two products: with w0 = 2^S - w1 per axis,
-            // W(0, ., .) = 2^S W_yz - W(1, ., .), and likewise along y and z
-            const uint64_t yz11 = (uint64_t)b.q[1] * b.q[2];
-            const uint64_t yz01 = ((uint64_t)b.q[2] << HPF_FIX_BITS) - yz11;   // wy0 wz1
-            const uint64_t yz10 = ((uint64_t)b.q[1] << HPF_FIX_BITS) - yz11;   // wy1 wz0
-            const uint64_t yz00 = ((uint64_t)kOne << HPF_FIX_BITS) - yz11 - yz01 - yz10;
-            unsigned long long* c0 = box + t * P3 + (lz * P + ly) * P + lx;
-            const uint64_t q0 = b.q[0];
-            lds_add_u64(c0, (yz00 << HPF_FIX_BITS) - yz00 * q0);
-            lds_add_u64(c0 + 1, yz00 * q0);
-            lds_add_u64(c0 + P, (yz10 << HPF_FIX_BITS) - yz10 * q0);
-            lds_add_u64(c0 + P + 1, yz10 * q0);
-            lds_add_u64(c0 + P2, (yz01 << HPF_FIX_BITS) - yz01 * q0);
-            lds_add_u64(c0 + P2 + 1, yz01 * q0);
-            lds_add_u64(c0 + P2 + P, (yz11 << HPF_FIX_BITS) - yz11 * q0);
-            lds_add_u64(c0 + P2 + P + 1, yz11 * q0);
+            box_deposit(box, P, t, lx, ly, lz, b);
         }
     }
     __syncthreads();
@@ -229,6 +244,8 @@ __device__ __forceinline__ Cover covering(int v, int B, int h, int nb, int M)
 // One workgroup per brick: the cover lists of the brick's coordinates along
 // each axis are built once in LDS, then each thread sums the partial boxes for
 // its points (consecutive threads -> consecutive x -> coalesced reads).
+// With kAdd the sums are added to the counts instead of stored.
+template <bool kAdd = false>
 __device__ __forceinline__ void scatter_sum_body(const unsigned long long* __restrict__ partials,
                                                  const TileK& tk, int K, int64_t brick,
                                                  unsigned long long* __restrict__ counts)
@@ -265,16 +282,20 @@ __device__ __forceinline__ void scatter_sum_body(const unsigned long long* __res
                     for (int c = 0; c < cx.n; ++c)
                         sum += partials[((row + cx.brick[c]) * K + k) * P3 + loc + cx.local[c]];
                 }
-            counts[(int64_t)k * tk.m.nm + dst] = sum;
+            if (kAdd)
+                counts[(int64_t)k * tk.m.nm + dst] += sum;
+            else
+                counts[(int64_t)k * tk.m.nm + dst] = sum;
         }
     }
 }
 
+template <bool kAdd>
 __global__ __launch_bounds__(256) void k_scatter_sum(const unsigned long long* __restrict__ partials,
                                                      TileK tk, int K,
                                                      unsigned long long* __restrict__ counts)
 {
-    scatter_sum_body(partials, tk, K, xcd_block(blockIdx.x, gridDim.x), counts);
+    scatter_sum_body<kAdd>(partials, tk, K, xcd_block(blockIdx.x, gridDim.x), counts);
 }
 
 __device__ __forceinline__ void atomic_add_u64_agent(unsigned long long* p, unsigned long long v)
@@ -361,7 +382,7 @@ hpf_status_t launch_scatter_cells(const float* R, const uint8_t* T, int64_t N, c
     hipLaunchKernelGGL(k_zero_u32_one, dim3(1), dim3(1), 0, s, strays);
     hipLaunchKernelGGL(k_scatter_bricks, dim3((unsigned)tk.ntiles), dim3(kTcThreads), smem, s, Rp, T, K, tk,
                        cell_start, partials, strays);
-    hipLaunchKernelGGL(k_scatter_sum, dim3((unsigned)tk.ntiles), dim3(256), 0, s, partials, tk, K, c);
+    hipLaunchKernelGGL(k_scatter_sum<false>, dim3((unsigned)tk.ntiles), dim3(256), 0, s, partials, tk, K, c);
     hipLaunchKernelGGL(k_scatter_strays, dim3(512), dim3(kTcThreads), 0, s, Rp, T, N, K, tk.m, tk.NK,
                        cell_start, strays, c);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;

@@ -28,7 +28,7 @@ class HpfState:
     """One periodic system on the GPU: beads, bond table, mesh buffers."""
 
     def __init__(self, R, Vel, T, tag, bonds, L, M, K, kT, inv_kappa, chi, k_bond, r0, dt,
-                 device="cuda", sort_brick=8, halo=1, advance_halo=1, advance="plain"):
+                 device="cuda", sort_brick=8, halo=1, advance_halo=1, advance="scatter"):
         dev = torch.device(device)
         self.N = int(R.shape[0])
         self.K = int(K)
@@ -42,9 +42,11 @@ class HpfState:
         self.B = int(sort_brick)
         self.halo = int(halo)
         self.advance_halo = int(advance_halo)
-        # "plain": hpf_advance (the faster on gfx950 in brick order); "cells": hpf_advance_cells
-        # whenever the beads are cell-sorted
+        # How the fused step advances cell-sorted beads: "scatter" = hpf_advance_scatter (also
+        # deposits x_n+1, so the next step only finishes the density), "plain" = hpf_advance,
+        # "cells" = hpf_advance_cells. Unsorted beads always take hpf_advance.
         self.advance_mode = advance
+        self.density_pending = False   # partial boxes + counts hold the deposit of the current R
         self.sorted = False      # storage order comes from hpf_sort_by_cell
         nm = self.mesh.M[0] * self.mesh.M[1] * self.mesh.M[2]
         self.nm = nm
@@ -103,6 +105,7 @@ class HpfState:
 
     def scatter(self, stream=None):
         """Density counts: cell-list owner tiles when sorted, else the generic scatter."""
+        self.density_pending = False
         if self.sorted and self.cells_ok:
             hpf.hpf_density_scatter_cells(self.R, self.T, self.mesh, self.K, self.cell_start, self.B,
                                           self.halo, self.counts, self.scatter_work, stream)
@@ -126,6 +129,7 @@ class HpfState:
         self.bond_forces(report, stream)
 
     def step(self, report=False, sort=False, stream=None):
+        self.density_pending = False
         hpf.verlet_step(self.R, self.Vel, self.F, self.dt, self.box, 1, stream=stream)
         if sort:
             self.sort(stream)
@@ -138,6 +142,7 @@ class HpfState:
 
     def start(self, sort=True, stream=None):
         """Initial sort and force evaluation, with energies of the initial state."""
+        self.density_pending = False
         if sort:
             self.sort(stream)
         self.forces(report=True, stream=stream)
@@ -149,6 +154,7 @@ class HpfState:
 
     def prime(self, stream=None):
         """First half step after start(): (x_0, v_0, F_0) -> (x_1, v_1/2)."""
+        self.density_pending = False
         hpf.verlet_step(self.R, self.Vel, self.F, self.dt, self.box, 1, stream=stream)
 
     def step_fused(self, report=False, sort=False, stream=None):
@@ -157,7 +163,7 @@ class HpfState:
         Bitwise equal to step() followed by the next step's first half step."""
         if sort:
             self.sort(stream)
-        self.scatter(stream)
+        self.density(stream)
         hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V,
                                 self.part[ROW_W] if report else None, stream)
         hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
@@ -166,16 +172,38 @@ class HpfState:
             hpf.hpf_reduce_partials(self.part, N_ROWS, self.energy, stream)
         self.steps_done += 1
 
+    def density(self, stream=None):
+        """Counts of the current positions: finish the deposit the last fused pass made, or
+        scatter from scratch."""
+        if self.density_pending:
+            hpf.hpf_density_finish_cells(self.counts, self.N, self.mesh, self.K, self.B, self.halo,
+                                         self.scatter_work, stream)
+            self.density_pending = False
+        else:
+            self.scatter(stream)
+
     def uses_cells_advance(self) -> bool:
         return (self.advance_mode == "cells" and self.sorted and
                 hpf.advance_cells_fits(self.K, self.B, self.advance_halo))
 
+    def uses_scatter_advance(self) -> bool:
+        return self.advance_mode == "scatter" and self.sorted and self.cells_ok
+
     def advance(self, report=False, stream=None):
-        """Fused forces + Verlet pass, x_n -> x_n+1 (the brick-box variant when cell-sorted)."""
+        """Fused forces + Verlet pass, x_n -> x_n+1 (with the density deposit of x_n+1, or the
+        brick-box variant, when cell-sorted). Counts must be zero on entry (the potential pass
+        leaves them so)."""
         bonds = self.bonds if self.bonds.shape[0] else None
         e_part = self.part[ROW_EB] if report else None
         kin_part = self.part[ROW_KE:ROW_KE + 4] if report else None
-        if self.uses_cells_advance():
+        self.density_pending = False
+        if self.uses_scatter_advance():
+            hpf.hpf_advance_scatter(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
+                                    self.k_bond, self.r0, self.box, self.dt, self.cell_start, self.B,
+                                    self.halo, self.counts, self.scatter_work, e_part=e_part,
+                                    kin_part=kin_part, stream=stream)
+            self.density_pending = True
+        elif self.uses_cells_advance():
             hpf.hpf_advance_cells(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
                                   self.k_bond, self.r0, self.box, self.dt, self.cell_start, self.B,
                                   self.advance_halo, e_part=e_part, kin_part=kin_part, stream=stream)

@@ -94,6 +94,11 @@ _SIGNATURES = {
     "hpf_advance_cells": ([_P, _P, _P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, C.c_int32,
                            C.c_float, C.c_float, _P, _P, C.c_float, _P, C.c_int32, C.c_int32, _P, _P,
                            _P, _P], C.c_int32),
+    "hpf_advance_scatter": ([_P, _P, _P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, C.c_int32,
+                             C.c_float, C.c_float, _P, _P, C.c_float, _P, C.c_int32, C.c_int32, _P, _P,
+                             C.c_size_t, _P, _P, _P, _P], C.c_int32),
+    "hpf_density_finish_cells": ([_P, C.c_int64, C.POINTER(Mesh), C.c_int32, C.c_int32, C.c_int32,
+                                  _P, C.c_size_t, _P], C.c_int32),
     "hpf_sort_workspace_bytes": ([C.c_int64, C.POINTER(Mesh), C.c_int32], C.c_size_t),
     "hpf_sort_by_cell": ([C.POINTER(Mesh), C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
                           _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int32),
@@ -339,6 +344,46 @@ def hpf_advance_cells(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float,
     if kin_part is not None and kin_part.numel() < 4 * HPF_NPART:
         raise ValueError("kin_part needs 4 * HPF_NPART slots")
     _check("hpf_advance_cells", lib().hpf_advance_cells(*args, _stream(stream)))
+
+
+def hpf_advance_scatter(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float, r0: float, box,
+                        dt: float, cell_start, B: int, halo: int, counts, work, inv_mass=None,
+                        F_out=None, e_part=None, kin_part=None, stream=None):
+    N = R.shape[0]
+    D = bonds.shape[0] if bonds is not None else 0
+    args = [
+        _dev(R, "R", torch.float32, (N, 4)),
+        _dev(R_next, "R_next", torch.float32, (N, 4)),
+        _dev(Vel, "Vel", torch.float32, (N, 4)),
+        _dev(T, "T", torch.uint8, (N,)),
+        N, C.byref(mesh), int(K),
+        _dev(G, "G", torch.float32, (K, _nm(mesh), 4)),
+        _dev(bonds, "bonds", torch.int32, (D, N), allow_none=True) if D else None,
+        int(D), float(k), float(r0), _box(box),
+        _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True),
+        float(dt),
+        _dev(cell_start, "cell_start", torch.int32, (sort_key_count(mesh, B) + 2,)),
+        int(B), int(halo),
+        _dev(counts, "counts", torch.int64, (K, _nm(mesh))),
+        _dev(work, "work", torch.uint8), work.numel(),
+        _dev(F_out, "F_out", torch.float32, (N, 4), allow_none=True),
+        _dev(e_part, "e_part", torch.float64, None, allow_none=True),
+        _dev(kin_part, "kin_part", torch.float64, None, allow_none=True),
+    ]
+    if e_part is not None and e_part.numel() < HPF_NPART:
+        raise ValueError("e_part needs HPF_NPART slots")
+    if kin_part is not None and kin_part.numel() < 4 * HPF_NPART:
+        raise ValueError("kin_part needs 4 * HPF_NPART slots")
+    _check("hpf_advance_scatter", lib().hpf_advance_scatter(*args, _stream(stream)))
+
+
+def hpf_density_finish_cells(counts, N: int, mesh: Mesh, K: int, B: int, halo: int, work,
+                             stream=None):
+    c = _dev(counts, "counts", torch.int64, (K, _nm(mesh)))
+    w = _dev(work, "work", torch.uint8)
+    _check("hpf_density_finish_cells",
+           lib().hpf_density_finish_cells(c, int(N), C.byref(mesh), int(K), int(B), int(halo), w,
+                                          work.numel(), _stream(stream)))
 
 
 def advance_cells_fits(K: int, B: int = 8, halo: int = 1) -> bool:

@@ -102,6 +102,23 @@ def test_invalid_arguments_rejected_on_host(hpf):
     assert adv(K=8, halo=1) == EINVAL                # 8 x 11^3 x 16 B > 160 KiB of LDS
     assert adv(cell_start=None) == EINVAL
     assert adv(R_next=r_in) == EINVAL
+    # hpf_advance_scatter / hpf_density_finish_cells: mesh limits, counts, workspace
+    cnt, wk = C.c_void_p(0x10000), C.c_void_p(0x20000)
+    m16 = hpf.hpf_mesh_make(16.0, 16, 100)
+    need = L.hpf_scatter_workspace_bytes(10, C.byref(m16), 2, 8, 1)
+    assert need > 0
+
+    def advs(mesh=m16, counts=cnt, work=wk, nbytes=need, B=8, halo=1):
+        return L.hpf_advance_scatter(r_in, r_n, v, t_in, 10, C.byref(mesh), 2, g, None, 0, 100.0, 0.0,
+                                     box, None, 0.03, cs, B, halo, counts, work, nbytes, None, None, None,
+                                     None)
+    assert advs(mesh=m) == EINVAL                     # M = 10 < B + 1 + 2 halo
+    assert advs(counts=None) == EINVAL
+    assert advs(halo=3) == EINVAL
+    assert advs(nbytes=need - 1) == -3
+    assert advs(work=None) == -3
+    assert L.hpf_density_finish_cells(None, 10, C.byref(m16), 2, 8, 1, wk, need, None) == EINVAL
+    assert L.hpf_density_finish_cells(cnt, 10, C.byref(m16), 2, 8, 1, wk, need - 1, None) == -3
 
 
 def test_sort_workspace_size(hpf):

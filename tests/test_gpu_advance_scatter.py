@@ -1,0 +1,120 @@
+"""GPU: the fused pass with the density deposit of the new positions.
+
+hpf_advance_scatter must move every bead exactly as hpf_advance does, and after
+hpf_density_finish_cells the counts must equal the oracle's density of the new
+positions bit for bit: beads that stay in their brick box (LDS deposit),
+beads that left it (global atomics), beads the sort could not bin, and with a
+re-sort between the two calls.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from gpu_util import counts_np, dev, host  # noqa: E402
+from paper_1310_2041_amd import engine, hpf  # noqa: E402
+from synth import workloads as wl  # noqa: E402
+from test_gpu_advance_cells import drifted, field_of  # noqa: E402
+
+
+def advance_pair(st, halo):
+    """(R_next, Vel) of hpf_advance and of hpf_advance_scatter, and the finished counts."""
+    bonds = st.bonds if st.bonds.shape[0] else None
+    Rn_a, V_a = torch.empty_like(st.R), st.Vel.clone()
+    hpf.hpf_advance(st.R, Rn_a, V_a, st.T, st.mesh, st.K, st.G, bonds, st.k_bond, st.r0, st.box,
+                    st.dt)
+    Rn_b, V_b = torch.empty_like(st.R), st.Vel.clone()
+    st.counts.zero_()
+    st.scatter_work.fill_(0xA5)                      # stale partial boxes must be overwritten
+    hpf.hpf_advance_scatter(st.R, Rn_b, V_b, st.T, st.mesh, st.K, st.G, bonds, st.k_bond, st.r0,
+                            st.box, st.dt, st.cell_start, st.B, halo, st.counts, st.scatter_work)
+    return (Rn_a, V_a), (Rn_b, V_b)
+
+
+CASES = [
+    ("c1", lambda: wl.build(wl.SPECS["c1"]), 8, 1),
+    ("noncubic_k3", lambda: wl.small_system(300, 12, (21.3, 17.9, 25.2), (20, 17, 24), K=3,
+                                            n_solvent=4000, seed=61), 4, 2),
+    ("halo0", lambda: wl.small_system(300, 12, 16.0, 15, seed=62), 8, 0),
+    ("b3", lambda: wl.small_system(200, 10, 12.0, 11, seed=63), 3, 1),
+]
+
+
+@pytest.mark.parametrize("name,make,B,halo", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("sigma", [0.0, 0.6, 3.0])
+def test_advance_scatter_beads_and_counts(name, make, B, halo, sigma):
+    s, _ = wl.permuted(make(), seed=4)
+    st = engine.HpfState.from_system(s, sort_brick=B, halo=halo)
+    assert st.cells_ok
+    st.sort()
+    if sigma:
+        h_cell = float(np.float32(s.L[0])) / st.mesh.M[0]
+        st.R.copy_(dev(drifted(host(st.R), s.L, sigma, h_cell, seed=int(10 * sigma) + B),
+                       torch.float32))
+    field_of(st)
+    (Ra, Va), (Rb, Vb) = advance_pair(st, halo)
+    assert torch.equal(Ra.view(torch.int32), Rb.view(torch.int32))
+    assert torch.equal(Va.view(torch.int32), Vb.view(torch.int32))
+    hpf.hpf_density_finish_cells(st.counts, st.N, st.mesh, st.K, B, halo, st.scatter_work)
+    want, sk = oracle.density(host(Rb), host(st.T), s.L, s.M, s.K)
+    assert sk == 0
+    assert np.array_equal(counts_np(st.counts, st.K, tuple(st.mesh.M)), want)
+    assert hpf.hpf_get_device_status() == 0
+
+
+def test_advance_scatter_then_sort_then_finish():
+    """A re-sort between the deposit and the finishing pass leaves the counts exact."""
+    s = wl.build(wl.SPECS["c1"])
+    st = engine.HpfState.from_system(s)
+    st.sort()
+    field_of(st)
+    _, (Rb, Vb) = advance_pair(st, st.halo)
+    st.R.copy_(Rb)
+    st.Vel.copy_(Vb)
+    st.sort()                                        # permutes beads; partial boxes stay valid
+    hpf.hpf_density_finish_cells(st.counts, st.N, st.mesh, st.K, st.B, st.halo, st.scatter_work)
+    want, _ = oracle.density(host(st.R), host(st.T), s.L, s.M, s.K)
+    assert np.array_equal(counts_np(st.counts, st.K, tuple(st.mesh.M)), want)
+
+
+def test_advance_scatter_unbinnable_beads():
+    s = wl.small_system(100, 10, 12.0, 12, seed=64)
+    s.R[5, 0] = np.nan                               # cannot be binned at sort time
+    st = engine.HpfState.from_system(s)
+    st.sort()
+    field_of(st)
+    hpf.hpf_get_device_status(clear=True)
+    (Ra, Va), (Rb, Vb) = advance_pair(st, 1)
+    assert torch.equal(Ra.view(torch.int32), Rb.view(torch.int32))
+    assert hpf.hpf_get_device_status(clear=True) & hpf.HPF_FLAG_BAD_BEAD
+    hpf.hpf_density_finish_cells(st.counts, st.N, st.mesh, st.K, st.B, st.halo, st.scatter_work)
+    want, sk = oracle.density(host(Rb), host(st.T), s.L, s.M, s.K)
+    assert sk == 3                 # the NaN bead and, through their bonds, its two chain partners
+    assert np.array_equal(counts_np(st.counts, st.K, tuple(st.mesh.M)), want)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_engine_fused_deposit_matches_plain_steps(cfg):
+    """Stepping with the fused deposit equals stepping with hpf_advance + a fresh scatter:
+    beads and W bit for bit (the counts are), KE and E_bond to FP64 regrouping."""
+    s = wl.build(wl.SPECS[cfg])
+    a = engine.HpfState.from_system(s, advance="plain")
+    b = engine.HpfState.from_system(s, advance="scatter")
+    for st in (a, b):
+        st.start(sort=True)
+        st.prime()
+    ea = a.run_fused(23, report_every=1, sort_every=10)
+    eb = b.run_fused(23, report_every=1, sort_every=10)
+    assert b.uses_scatter_advance() and b.density_pending
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
+    for x, y in zip(ea, eb):
+        assert x["W"] == y["W"]
+        for key in ("KE", "E_bond"):
+            assert y[key] == pytest.approx(x[key], rel=1e-12)
+    assert hpf.hpf_get_device_status() == 0
