@@ -349,12 +349,17 @@ hpf_status_t hpf_reduce_partials(const double* part, int32_t ncomp, double* out,
  * contiguous range and, inside it, the beads of a chain (consecutive tags)
  * are neighbours. Positions, velocities, types and tags are permuted into the
  * *_out arrays and the bond table is permuted and its entries renumbered to
- * the new storage indices. A brick holding more than 8192 beads keeps an
- * arbitrary order inside and sets HPF_FLAG_SORT_ORDER.
+ * the new storage indices. The order comes from a stable counting sort of
+ * the beads taken in tag order, so it does not depend on the input order.
  *
- * B            brick edge in cells, 1..16 (0 selects 8).
+ * B            brick edge in cells, 1..16 (0 selects 8); NK + 1 must not
+ *              exceed 36864 keys (HPF_EINVAL otherwise).
  * *_in / *_out device arrays of N rows (Vel/tag/bonds may be NULL together
  *              with their outputs; D may be 0); in and out must not alias.
+ * tag_in       a permutation of [0, N) (the beads' original indices); NULL
+ *              uses the input index. A tag outside [0, N) or a repeated tag
+ *              sets HPF_FLAG_SORT_ORDER; the output is then not a valid
+ *              permutation (every index written stays inside [0, N)).
  * cell_start   nullable uint32[NK + 2] device: cell_start[k] = index of the
  *              first bead with key >= k, i.e. brick k's beads are
  *              [cell_start[k], cell_start[k+1]); cell_start[NK] = number of

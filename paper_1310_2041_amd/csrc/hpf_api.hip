@@ -362,10 +362,10 @@ size_t hpf_sort_workspace_bytes(int64_t N, const hpf_mesh_t* mesh, int32_t B)
 {
     if (!mesh_ok(mesh))
         return 0;
-    size_t bytes = 0, off[7];
-    if (!sort_layout(N, mesh->M, B, nullptr, &bytes, off))
+    SortPlan plan;
+    if (!sort_layout(N, mesh->M, B, nullptr, &plan))
         return 0;
-    return bytes;
+    return plan.bytes;
 }
 
 hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N, const float* R_in,
@@ -384,14 +384,14 @@ hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N, cons
                   (tag_in && tag_in == tag_out) || (D > 0 && bonds_in == bonds_out)))
         return HPF_EINVAL;
     SortK sk;
-    size_t bytes = 0, off[7];
-    if (!sort_layout(N, mesh->M, B, &sk, &bytes, off))
+    SortPlan plan;
+    if (!sort_layout(N, mesh->M, B, &sk, &plan))
         return HPF_EINVAL;
-    if (!work || work_bytes < bytes)
+    if (!work || work_bytes < plan.bytes)
         return HPF_ESPACE;
     sk.m = mesh_k(mesh);
-    return launch_sort(sk, N, R_in, Vel_in, T_in, tag_in, bonds_in, D, R_out, Vel_out, T_out, tag_out,
-                       bonds_out, cell_start, static_cast<char*>(work), off, as_stream(stream));
+    return launch_sort(sk, plan, N, R_in, Vel_in, T_in, tag_in, bonds_in, D, R_out, Vel_out, T_out, tag_out,
+                       bonds_out, cell_start, static_cast<char*>(work), as_stream(stream));
 }
 
 hpf_status_t hpf_get_device_status(uint32_t* flags, int32_t clear, void* stream)

@@ -53,34 +53,6 @@ __device__ __forceinline__ TileK tile_of(const RepK& r, int B, int h)
     return t;
 }
 
-// ---------------------------------------------------------------- sort keys
-
-__global__ __launch_bounds__(kBThreads) void k_batch_keys(const RepK* __restrict__ reps,
-                                                          const ItemK* __restrict__ items, int B,
-                                                          const float4* __restrict__ R,
-                                                          uint32_t* __restrict__ keys,
-                                                          uint32_t* __restrict__ hist)
-{
-    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
-    const ItemK it = items[li];
-    const RepK& rp = reps[it.rep];
-    const int lane = threadIdx.x & (kWave - 1);
-    for (int64_t base = it.begin; base < it.end; base += kBThreads) {
-        const int64_t i = base + threadIdx.x;
-        const bool active = i < it.end;
-        uint32_t key = rp.key_base + rp.NK;
-        if (active) {
-            BeadCell b;
-            if (bead_cell(R[i], rp.m, b))
-                key = rp.key_base + brick_of(b.c[0], b.c[1], b.c[2], B, rp.nb);
-            keys[i] = key;
-        }
-        const uint64_t grp = wave_key_group(key, active);
-        if (active && __builtin_ctzll(grp) == lane)
-            atomicAdd(hist + key, (uint32_t)__builtin_popcountll(grp));
-    }
-}
-
 // ------------------------------------------------------------- cell scatter
 
 __global__ __launch_bounds__(kTcThreads) void k_batch_scatter_bricks(const RepK* __restrict__ reps,
@@ -128,6 +100,21 @@ __device__ __forceinline__ int find_rep(const RepK* reps, int nrep, int64_t p)
     }
     return lo;
 }
+
+// Sort key of bead i of the batch: its replica's key base plus its brick (or
+// the replica's "cannot be binned" key).
+struct RepKeyer {
+    const RepK* reps;
+    int nrep;
+    int B;
+    const float4* R;
+    __device__ __forceinline__ uint32_t operator()(int32_t i) const
+    {
+        const RepK& rp = reps[find_rep(reps, nrep, i)];
+        BeadCell b;
+        return rp.key_base + (bead_cell(R[i], rp.m, b) ? brick_of(b.c[0], b.c[1], b.c[2], B, rp.nb) : rp.NK);
+    }
+};
 
 // Strays of all replicas (global indices in one list) and each replica's
 // beads that the sort could not bin, with global atomics.
@@ -357,8 +344,9 @@ struct BatchLayout {
     uint32_t NKT = 0;                    // keys of all replicas, invalid buckets included
     int64_t max_bead_items = 0, max_mesh_items = 0, max_planes = 0;
     size_t off_reps, off_bead_items, off_brick_items, off_mesh_items, off_plane_items, off_bead_ioff,
-        off_mesh_ioff, off_keys, off_perm, off_inv, off_start, off_cursor, off_tiles, off_ptag, off_strays,
-        off_partials, off_wpart, off_epart, off_kpart, off_energy, total;
+        off_mesh_ioff, off_sort, off_start, off_strays, off_partials, off_wpart, off_epart, off_kpart, off_energy,
+        total;
+    SortPlan sort;
 };
 
 static bool batch_layout(const hpf_replica_t* reps, int nrep, const hpf_batch_config_t* cfg, BatchLayout* L)
@@ -393,12 +381,11 @@ static bool batch_layout(const hpf_replica_t* reps, int nrep, const hpf_batch_co
         L->max_planes += q.M[2];
     }
     L->Ntot = expect_off;
-    if (L->Ntot > 0x7ffffff0LL || nkt + 2 > (int64_t)kMaxScanTiles * kScanTile)
+    if (L->Ntot > 0x7ffffff0LL || !sort_plan(L->Ntot, nkt, &L->sort))
         return false;
     L->NKT = (uint32_t)nkt;
     const int64_t N1 = L->Ntot > 0 ? L->Ntot : 1;
     const int64_t nscan = nkt + 1;
-    const int64_t ntiles = (nscan + kScanTile - 1) / kScanTile;
     size_t o = 0;
     L->off_reps = o; o += al256(sizeof(RepK) * nrep);
     L->off_bead_items = o; o += al256(sizeof(ItemK) * (L->max_bead_items + 1));
@@ -407,13 +394,8 @@ static bool batch_layout(const hpf_replica_t* reps, int nrep, const hpf_batch_co
     L->off_plane_items = o; o += al256(sizeof(ItemK) * (L->max_planes + 1));
     L->off_bead_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
     L->off_mesh_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
-    L->off_keys = o; o += al256(sizeof(uint32_t) * N1);
-    L->off_perm = o; o += al256(sizeof(int32_t) * N1);
-    L->off_inv = o; o += al256(sizeof(int32_t) * N1);
+    L->off_sort = o; o += al256(L->sort.bytes);
     L->off_start = o; o += al256(sizeof(uint32_t) * (nscan + 1));
-    L->off_cursor = o; o += al256(sizeof(uint32_t) * (nscan + 1));
-    L->off_tiles = o; o += al256(sizeof(uint32_t) * (ntiles + 1));
-    L->off_ptag = o; o += al256(sizeof(int32_t) * N1);
     L->off_strays = o; o += al256(sizeof(uint32_t) * (N1 + 64));
     L->off_partials = o; o += al256(sizeof(unsigned long long) * L->bricks_tot * cfg->K * Pmax * Pmax * Pmax);
     L->off_wpart = o; o += al256(sizeof(double) * (L->max_mesh_items + 1));
@@ -485,46 +467,17 @@ static hpf_status_t batch_build_items(hpf_batch* b)
 static hpf_status_t batch_sort(hpf_batch* b, hipStream_t s)
 {
     const BatchLayout& L = b->L;
-    const int64_t N = L.Ntot;
     const int o = b->scur, n = 1 - b->scur;
-    uint32_t* keys = b->at<uint32_t>(L.off_keys);
-    int32_t* perm = b->at<int32_t>(L.off_perm);
-    int32_t* inv = b->at<int32_t>(L.off_inv);
-    uint32_t* start = b->at<uint32_t>(L.off_start);
-    uint32_t* cursor = b->at<uint32_t>(L.off_cursor);
-    uint32_t* tiles = b->at<uint32_t>(L.off_tiles);
-    int32_t* ptag = b->at<int32_t>(L.off_ptag);
-    const int64_t nscan = (int64_t)L.NKT + 1;
-    const int64_t ntiles = (nscan + kScanTile - 1) / kScanTile;
-    const unsigned gfill = (unsigned)std::min<int64_t>((nscan + kSortThreads - 1) / kSortThreads, 4096);
-    auto grid_of = [](int64_t n) { return (unsigned)((n + kSortThreads - 1) / kSortThreads); };
-    const int B = b->cfg.brick;
-    hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, nscan, 0u);
-    if (b->n_bead_items > 0)
-        hipLaunchKernelGGL(k_batch_keys, dim3((unsigned)b->n_bead_items), dim3(kBThreads), 0, s,
-                           b->at<RepK>(L.off_reps), b->at<ItemK>(L.off_bead_items), B,
-                           reinterpret_cast<const float4*>(b->buf.R[b->rcur]), keys, start);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, start, nscan, tiles);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, s, tiles, (int)ntiles);
-    hipLaunchKernelGGL(k_scan_add, dim3(grid_of(nscan)), dim3(kSortThreads), 0, s, start, nscan, tiles);
-    if (N > 0) {
-        hipLaunchKernelGGL(k_copy_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, cursor, nscan);
-        hipLaunchKernelGGL(k_sort_place, dim3(grid_of(N)), dim3(kSortThreads), 0, s, keys, N,
-                           b->buf.tag[o], cursor, perm, ptag);
-        hipLaunchKernelGGL(k_sort_bricks, dim3((unsigned)std::min<int64_t>(nscan - 1, 1 << 20)),
-                           dim3(kBrickSortThreads), 0, s, start, nscan - 1, ptag, perm);
-        hipLaunchKernelGGL(k_sort_permute, dim3(grid_of(N)), dim3(kSortThreads), 0, s, perm, N,
-                           reinterpret_cast<const float4*>(b->buf.R[b->rcur]),
-                           reinterpret_cast<const float4*>(b->buf.Vel[o]), b->buf.T[o], b->buf.tag[o],
-                           reinterpret_cast<float4*>(b->buf.R[1 - b->rcur]),
-                           reinterpret_cast<float4*>(b->buf.Vel[n]), b->buf.T[n], b->buf.tag[n], inv);
-        if (b->cfg.D > 0)
-            hipLaunchKernelGGL(k_sort_bonds, dim3(grid_of(N)), dim3(kSortThreads), 0, s, perm, inv, N,
-                               b->buf.bonds[o], b->cfg.D, b->buf.bonds[n]);
-    }
+    RepKeyer keyer{b->at<RepK>(L.off_reps), b->nrep, b->cfg.brick,
+                   reinterpret_cast<const float4*>(b->buf.R[b->rcur])};
+    const hpf_status_t st =
+        run_sort(L.sort, keyer, L.Ntot, b->buf.R[b->rcur], b->buf.Vel[o], b->buf.T[o], b->buf.tag[o],
+                 b->cfg.D > 0 ? b->buf.bonds[o] : nullptr, b->cfg.D, b->buf.R[1 - b->rcur], b->buf.Vel[n],
+                 b->buf.T[n], b->buf.tag[n], b->cfg.D > 0 ? b->buf.bonds[n] : nullptr, b->at<uint32_t>(L.off_start),
+                 b->work + L.off_sort, s);
     b->rcur = 1 - b->rcur;
     b->scur = n;
-    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+    return st;
 }
 
 static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)

@@ -1,15 +1,28 @@
-// Canonical cell ordering of the beads (the paper reorders particle data for
+// Canonical cell-list order of the beads (the paper reorders particle data for
 // cache hits and bins beads into a cell list, Algorithm 1 Kernel 1).
 //
-// The key of a bead is the brick of B^3 cells holding its cell. Counting sort
-// on that key: histogram (u32 atomics), an exclusive scan over all keys,
-// placement with per-key cursors, then each key's segment is sorted by tag in
-// LDS, so the result -- ascending (brick, tag) -- is independent of the
-// atomic placement order. Inside a brick the beads then lie in tag order, so
-// the beads of one chain (consecutive tags) stay next to each other and most
-// bond partners are neighbours in memory. Finally the bead arrays are
-// gathered into the output buffers and the bond table is permuted and
-// renumbered through the inverse permutation.
+// The key of a bead is the brick of B^3 cells holding its cell (one more key
+// for beads that cannot be binned); the order is ascending (key, tag), where
+// the tags are a permutation of [0, N) (the beads' original indices). Inside
+// a brick the beads of a chain (consecutive tags) then stay neighbours, so
+// most bond partners are adjacent in memory. The order is produced by a
+// stable counting sort of the beads taken in tag order, so beads of one key
+// come out in tag order with no sorting inside a key:
+//   1. idx[tag[i]] = i;
+//   2. the tag sequence is cut into chunks of S tags; per chunk each bead's
+//      key is formed and a key histogram is counted in LDS and stored as one
+//      row of a chunk x key table;
+//   3. a column-wise exclusive scan of that table, taken in key-major order,
+//      gives every (chunk, key) pair its first output slot, and the key
+//      starts (cell_start);
+//   4. per chunk the beads are placed in tag order: the lanes of a wavefront
+//      that share a key take consecutive slots, and the wavefronts of a
+//      workgroup take turns.
+// No step needs a global atomic, and the result does not depend on the input
+// order. Finally the bead arrays are gathered into the output buffers and the
+// bond table is permuted and renumbered through the inverse permutation.
+#include <algorithm>
+
 #include "hpf_common.hpp"
 
 namespace hpf {
@@ -18,7 +31,7 @@ struct SortK {
     MeshK m;
     int32_t B;
     int32_t nb[3];
-    uint32_t NK;        // number of keys (bricks); key NK = "cannot be binned"
+    uint32_t NK;        // number of bricks; key NK = "cannot be binned"
 };
 
 constexpr int kSortThreads = 256;
@@ -27,8 +40,13 @@ constexpr int kScanTile = kSortThreads * kScanPer;   // entries per scan block
 constexpr int kScanTopThreads = 1024;
 constexpr int kScanTopPer = 8;
 constexpr int kMaxScanTiles = kScanTopThreads * kScanTopPer;
-constexpr int kBrickSortThreads = 512;
-constexpr int kBrickSortMax = 8192;                    // longest segment sorted by tag (64 KB LDS)
+constexpr int kChunkThreads = 256;                    // histogram / placement workgroups
+constexpr int kPlaceRegs = 16;                        // 256-tag blocks a thread holds at once
+constexpr int64_t kMinChunk = (int64_t)kChunkThreads * kPlaceRegs;   // 4096 tags
+constexpr int kColBlock = 64;                         // chunks per column-scan block
+constexpr int64_t kMaxSortKeys = 36864;               // one chunk's histogram in LDS (144 KiB)
+constexpr int64_t kMaxTable = 64LL << 20;             // chunk x key table entries
+constexpr uint32_t kNoKey = 0xffffffffu;              // a tag that names no bead
 
 __global__ __launch_bounds__(kSortThreads) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v)
 {
@@ -37,33 +55,7 @@ __global__ __launch_bounds__(kSortThreads) void k_fill_u32(uint32_t* __restrict_
         p[i] = v;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_copy_u32(const uint32_t* __restrict__ a,
-                                                           uint32_t* __restrict__ b, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kSortThreads)
-        b[i] = a[i];
-}
-
-__global__ __launch_bounds__(kSortThreads) void k_sort_keys(const float4* __restrict__ R, int64_t N,
-                                                            SortK sk, uint32_t* __restrict__ keys,
-                                                            uint32_t* __restrict__ hist)
-{
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
-    const bool active = i < N;
-    uint32_t key = sk.NK;
-    if (active) {
-        BeadCell b;
-        if (bead_cell(R[i], sk.m, b))
-            key = brick_of(b.c[0], b.c[1], b.c[2], sk.B, sk.nb);
-        keys[i] = key;
-    }
-    // one atomic per distinct key of the wavefront
-    const uint64_t grp = wave_key_group(key, active);
-    const int lane = threadIdx.x & (kWave - 1);
-    if (active && __builtin_ctzll(grp) == lane)
-        atomicAdd(hist + key, (uint32_t)__builtin_popcountll(grp));
-}
+// ------------------------------------------------------------ scan (u32) --
 
 // Per-tile exclusive scan in place; tile totals to tile_sums.
 __global__ __launch_bounds__(kSortThreads) void k_scan_tiles(uint32_t* __restrict__ a, int64_t n,
@@ -119,155 +111,180 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_add(uint32_t* __restrict_
         a[i] += tile_sums[i / kScanTile];
 }
 
-// Placement: each group of equal keys in a wavefront reserves its slots with
-// one atomic; tags travel with the permutation so the in-brick sort reads
-// them contiguously.
-__global__ __launch_bounds__(kSortThreads) void k_sort_place(const uint32_t* __restrict__ keys, int64_t N,
-                                                             const int32_t* __restrict__ tag,
-                                                             uint32_t* __restrict__ cursor,
-                                                             int32_t* __restrict__ perm,
-                                                             int32_t* __restrict__ ptag)
+// ------------------------------------------------------ 1. tag -> index --
+
+__global__ __launch_bounds__(kSortThreads) void k_tag_index(const int32_t* __restrict__ tag, int64_t N,
+                                                            int32_t* __restrict__ idx)
 {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
-    const bool active = i < N;
-    const uint32_t key = active ? keys[i] : 0xffffffffu;
-    const uint64_t grp = wave_key_group(key, active);
+    if (i >= N)
+        return;
+    const int32_t t = tag ? tag[i] : (int32_t)i;
+    if (t < 0 || t >= N)
+        raise_flag(HPF_FLAG_SORT_ORDER);
+    else
+        idx[t] = (int32_t)i;
+}
+
+// --------------------------------------------- 2. keys and chunk histograms --
+
+// Sort key of bead i of one system.
+struct CellKeyer {
+    SortK sk;
+    const float4* R;
+    __device__ __forceinline__ uint32_t operator()(int32_t i) const
+    {
+        BeadCell b;
+        return bead_cell(R[i], sk.m, b) ? brick_of(b.c[0], b.c[1], b.c[2], sk.B, sk.nb) : sk.NK;
+    }
+};
+
+template <class Keyer>
+__global__ __launch_bounds__(kChunkThreads) void k_sort_hist(Keyer keyer, const int32_t* __restrict__ idx,
+                                                             int64_t N, int64_t S, uint32_t nkeys,
+                                                             uint32_t* __restrict__ key_t,
+                                                             uint32_t* __restrict__ table)
+{
+    extern __shared__ uint32_t hist[];
+    const int64_t c = blockIdx.x;
+    for (uint32_t k = threadIdx.x; k < nkeys; k += kChunkThreads)
+        hist[k] = 0u;
+    __syncthreads();
+    const int64_t t0 = c * S, t1 = min(N, t0 + S);
     const int lane = threadIdx.x & (kWave - 1);
-    const int leader = active ? __builtin_ctzll(grp) : lane;
-    uint32_t base = 0;
-    if (active && leader == lane)
-        base = atomicAdd(cursor + key, (uint32_t)__builtin_popcountll(grp));
-    base = __shfl(base, leader, kWave);
-    if (active) {
-        const uint32_t pos = base + (uint32_t)__builtin_popcountll(grp & ((1ull << lane) - 1));
-        perm[pos] = (int32_t)i;
-        ptag[pos] = tag ? tag[i] : (int32_t)i;
+    bool missing = false;
+    for (int64_t base = t0; base < t1; base += kChunkThreads) {
+        const int64_t t = base + threadIdx.x;
+        uint32_t key = kNoKey;
+        if (t < t1) {
+            const int32_t i = idx[t];
+            if (i >= 0)
+                key = keyer(i);
+            else
+                missing = true;
+            key_t[t] = key;
+        }
+        const bool act = key != kNoKey;
+        const uint64_t grp = wave_key_group(key, act);
+        if (act && __builtin_ctzll(grp) == lane)
+            atomicAdd(hist + key, (uint32_t)__builtin_popcountll(grp));
+    }
+    if (missing)
+        raise_flag(HPF_FLAG_SORT_ORDER);
+    __syncthreads();
+    uint32_t* row = table + c * (int64_t)nkeys;
+    for (uint32_t k = threadIdx.x; k < nkeys; k += kChunkThreads)
+        row[k] = hist[k];
+}
+
+// ------------------------------------------------ 3. column-wise scan --
+
+// part[cb][k] = sum of table[c][k] over the chunks c of column block cb
+__global__ __launch_bounds__(kSortThreads) void k_col_partial(const uint32_t* __restrict__ table, int64_t nchunks,
+                                                              uint32_t nkeys, uint32_t* __restrict__ part)
+{
+    const uint32_t k = blockIdx.x * kSortThreads + threadIdx.x;
+    if (k >= nkeys)
+        return;
+    const int64_t c0 = (int64_t)blockIdx.y * kColBlock, c1 = min(nchunks, c0 + kColBlock);
+    uint32_t s = 0;
+    for (int64_t c = c0; c < c1; ++c)
+        s += table[c * nkeys + k];
+    part[(int64_t)blockIdx.y * nkeys + k] = s;
+}
+
+// part[cb][k] -> exclusive prefix over cb; tot[k] = key total
+__global__ __launch_bounds__(kSortThreads) void k_col_prefix(uint32_t* __restrict__ part, int64_t ncb,
+                                                             uint32_t nkeys, uint32_t* __restrict__ tot)
+{
+    const uint32_t k = blockIdx.x * kSortThreads + threadIdx.x;
+    if (k >= nkeys)
+        return;
+    uint32_t run = 0;
+    for (int64_t cb = 0; cb < ncb; ++cb) {
+        const uint32_t v = part[cb * nkeys + k];
+        part[cb * nkeys + k] = run;
+        run += v;
+    }
+    tot[k] = run;
+}
+
+// table[c][k] -> first output slot of chunk c's beads with key k
+__global__ __launch_bounds__(kSortThreads) void k_col_apply(uint32_t* __restrict__ table,
+                                                            const uint32_t* __restrict__ part,
+                                                            const uint32_t* __restrict__ start, int64_t nchunks,
+                                                            uint32_t nkeys)
+{
+    const uint32_t k = blockIdx.x * kSortThreads + threadIdx.x;
+    if (k >= nkeys)
+        return;
+    const int64_t c0 = (int64_t)blockIdx.y * kColBlock, c1 = min(nchunks, c0 + kColBlock);
+    uint32_t run = start[k] + part[(int64_t)blockIdx.y * nkeys + k];
+    for (int64_t c = c0; c < c1; ++c) {
+        const uint32_t v = table[c * nkeys + k];
+        table[c * nkeys + k] = run;
+        run += v;
     }
 }
 
-// Sort every key's segment of (perm, ptag) by tag (by input index when there
-// are no tags): one workgroup per segment runs a bitonic sort of (tag, perm)
-// pairs, padded to a power of two (at least one element per thread) with
-// entries that sort last. Element e = r * 512 + t lives in register row r of
-// thread t: compare-exchange partners at distance j >= 512 are in the same
-// thread, at j < 64 in the same wavefront (lane shuffles), and only
-// 64 <= j < 512 go through LDS. Tags compare as signed integers; they are
-// unique, so perm breaks no ties. A segment longer than kBrickSortMax keeps
-// its placement order and raises HPF_FLAG_SORT_ORDER.
+// ------------------------------------------------------ 4. placement --
 
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m)
+__global__ __launch_bounds__(kChunkThreads) void k_sort_place(const uint32_t* __restrict__ key_t,
+                                                              const int32_t* __restrict__ idx, int64_t N, int64_t S,
+                                                              uint32_t nkeys, const uint32_t* __restrict__ table,
+                                                              int32_t* __restrict__ perm)
 {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, kWave);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, kWave);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-// compare-exchange of register rows r and r + D (D = j / 512) for r with bit D clear
-template <int D, int ROWS>
-__device__ __forceinline__ void bitonic_rows(unsigned long long (&v)[ROWS], uint32_t t, uint32_t k)
-{
-    if constexpr (D < ROWS) {
+    extern __shared__ uint32_t next[];
+    const int64_t c = blockIdx.x;
+    const uint32_t* row = table + c * (int64_t)nkeys;
+    for (uint32_t k = threadIdx.x; k < nkeys; k += kChunkThreads)
+        next[k] = row[k];
+    __syncthreads();
+    const int64_t t0 = c * S, t1 = min(N, t0 + S);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (int64_t g0 = t0; g0 < t1; g0 += kMinChunk) {
+        uint32_t key[kPlaceRegs];
+        int32_t src[kPlaceRegs];
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            if ((r & D) == 0) {
-                const uint32_t e = (uint32_t)r * kBrickSortThreads + t;
-                const unsigned long long x = v[r], y = v[r | D];
-                const bool sw = (x > y) == ((e & k) == 0);
-                v[r] = sw ? y : x;
-                v[r | D] = sw ? x : y;
+        for (int b = 0; b < kPlaceRegs; ++b) {
+            const int64_t t = g0 + (int64_t)b * kChunkThreads + threadIdx.x;
+            key[b] = kNoKey;
+            src[b] = 0;
+            if (t < t1) {
+                key[b] = key_t[t];
+                src[b] = idx[t];
             }
         }
-    }
-}
-
-// Bitonic sort of one segment of n <= ROWS * 512 entries starting at a.
-template <int ROWS>
-__device__ __forceinline__ void sort_segment(uint32_t a, uint32_t n, int32_t* __restrict__ ptag,
-                                             int32_t* __restrict__ perm, unsigned long long* sh)
-{
-    const uint32_t t = threadIdx.x;
-    constexpr uint32_t np = (uint32_t)ROWS * kBrickSortThreads;
-    unsigned long long v[ROWS];
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const uint32_t e = (uint32_t)r * kBrickSortThreads + t;
-        v[r] = e < n ? ((unsigned long long)((uint32_t)ptag[a + e] ^ 0x80000000u) << 32) | (uint32_t)perm[a + e]
-                     : ~0ull;
-    }
-    for (uint32_t k = 2; k <= np; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            if (j >= (uint32_t)kBrickSortThreads) {
-                const uint32_t d = j / kBrickSortThreads;
-                if (d == 1)
-                    bitonic_rows<1, ROWS>(v, t, k);
-                else if (d == 2)
-                    bitonic_rows<2, ROWS>(v, t, k);
-                else if (d == 4)
-                    bitonic_rows<4, ROWS>(v, t, k);
-                else
-                    bitonic_rows<8, ROWS>(v, t, k);
-            } else if (j >= (uint32_t)kWave) {
-                __syncthreads();                       // earlier reads of sh are done
-#pragma unroll
-                for (int r = 0; r < ROWS; ++r)
-                    sh[r * kBrickSortThreads + t] = v[r];
+        for (int b = 0; b < kPlaceRegs; ++b) {
+            for (int w = 0; w < kChunkThreads / kWave; ++w) {
+                if (wave == w) {
+                    const bool act = key[b] != kNoKey;
+                    const uint64_t grp = wave_key_group(key[b], act);
+                    const int leader = act ? __builtin_ctzll(grp) : lane;
+                    uint32_t base = 0;
+                    if (act && leader == lane) {
+                        base = next[key[b]];
+                        next[key[b]] = base + (uint32_t)__builtin_popcountll(grp);
+                    }
+                    base = __shfl(base, leader, kWave);
+                    if (act)
+                        perm[base + (uint32_t)__builtin_popcountll(grp & ((1ull << lane) - 1))] = src[b];
+                }
                 __syncthreads();
-#pragma unroll
-                for (int r = 0; r < ROWS; ++r) {
-                    const uint32_t e = (uint32_t)r * kBrickSortThreads + t, p = e ^ j;
-                    const unsigned long long x = v[r], y = sh[p];
-                    const bool keep_min = (e < p) == ((e & k) == 0);
-                    v[r] = keep_min == (x < y) ? x : y;
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < ROWS; ++r) {
-                    const uint32_t e = (uint32_t)r * kBrickSortThreads + t;
-                    const unsigned long long x = v[r], y = shfl_xor_u64(x, (int)j);
-                    const bool keep_min = (t & j) == 0 ? ((e & k) == 0) : ((e & k) != 0);
-                    v[r] = keep_min == (x < y) ? x : y;
-                }
             }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const uint32_t e = (uint32_t)r * kBrickSortThreads + t;
-        if (e < n) {
-            ptag[a + e] = (int32_t)((uint32_t)(v[r] >> 32) ^ 0x80000000u);
-            perm[a + e] = (int32_t)(uint32_t)v[r];
         }
     }
 }
 
-__global__ __launch_bounds__(kBrickSortThreads, 4) void k_sort_bricks(const uint32_t* __restrict__ start,
-                                                                   int64_t nseg, int32_t* __restrict__ ptag,
-                                                                   int32_t* __restrict__ perm)
+__global__ __launch_bounds__(kSortThreads) void k_iota(int32_t* __restrict__ p, int64_t n)
 {
-    __shared__ unsigned long long sh[kBrickSortMax];
-    for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-        const uint32_t a = start[seg], b = start[seg + 1];
-        const uint32_t n = b - a;
-        if (n <= 1)
-            continue;
-        if (n > (uint32_t)kBrickSortMax) {
-            if (threadIdx.x == 0)
-                raise_flag(HPF_FLAG_SORT_ORDER);
-            continue;
-        }
-        if (n <= 512)
-            sort_segment<1>(a, n, ptag, perm, sh);
-        else if (n <= 1024)
-            sort_segment<2>(a, n, ptag, perm, sh);
-        else if (n <= 2048)
-            sort_segment<4>(a, n, ptag, perm, sh);
-        else if (n <= 4096)
-            sort_segment<8>(a, n, ptag, perm, sh);
-        else
-            sort_segment<16>(a, n, ptag, perm, sh);
-        __syncthreads();                               // sh is free for the next segment
-    }
+    const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    if (i < n)
+        p[i] = (int32_t)i;
 }
+
+// ------------------------------------------------ gather and bond table --
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_permute(const int32_t* __restrict__ perm, int64_t N,
                                                                const float4* __restrict__ R_in,
@@ -316,14 +333,53 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_bonds(const int32_t* __re
         raise_flag(HPF_FLAG_BAD_BOND);
 }
 
+// ------------------------------------------------------------------ host --
+
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-bool sort_layout(int64_t N, const int32_t M[3], int B, SortK* sk_out, size_t* bytes,
-                 size_t off[7])
+// Sizes and workspace layout of one sort of N beads over nkeys keys.
+struct SortPlan {
+    int64_t N = 0;
+    uint32_t nkeys = 0;
+    int64_t S = 0, nchunks = 0, ncb = 0, nscan = 0, ntiles = 0;
+    size_t off_key = 0, off_perm = 0, off_idx = 0, off_table = 0, off_part = 0, off_tiles = 0, off_start = 0;
+    size_t bytes = 0;
+};
+
+bool sort_plan(int64_t N, int64_t nkeys, SortPlan* p)
+{
+    if (N < 0 || N > 0x7ffffff0LL || nkeys < 1 || nkeys > kMaxSortKeys)
+        return false;
+    int64_t S = kMinChunk;
+    while (((N + S - 1) / S) * nkeys > kMaxTable)
+        S *= 2;
+    p->N = N;
+    p->nkeys = (uint32_t)nkeys;
+    p->S = S;
+    p->nchunks = std::max<int64_t>(1, (N + S - 1) / S);
+    p->ncb = (p->nchunks + kColBlock - 1) / kColBlock;
+    p->nscan = nkeys + 1;
+    p->ntiles = (p->nscan + kScanTile - 1) / kScanTile;
+    if (p->ntiles > kMaxScanTiles)
+        return false;
+    const size_t N1 = (size_t)(N > 0 ? N : 1);
+    size_t o = 0;
+    p->off_key = o; o += align_up(sizeof(uint32_t) * N1);
+    p->off_perm = o; o += align_up(sizeof(int32_t) * N1);
+    p->off_idx = o; o += align_up(sizeof(int32_t) * N1);          // tag index, then inverse permutation
+    p->off_table = o; o += align_up(sizeof(uint32_t) * (size_t)p->nchunks * (size_t)nkeys);
+    p->off_part = o; o += align_up(sizeof(uint32_t) * (size_t)p->ncb * (size_t)nkeys);
+    p->off_tiles = o; o += align_up(sizeof(uint32_t) * (size_t)(p->ntiles + 1));
+    p->off_start = o; o += align_up(sizeof(uint32_t) * (size_t)(p->nscan + 1));
+    p->bytes = o;
+    return true;
+}
+
+bool sort_layout(int64_t N, const int32_t M[3], int B, SortK* sk_out, SortPlan* plan)
 {
     if (B == 0)
         B = 8;
-    if (B < 1 || B > 16 || N < 0 || N > 0x7ffffff0LL)
+    if (B < 1 || B > 16)
         return false;
     int64_t nk = 1;
     int32_t nb[3];
@@ -331,9 +387,7 @@ bool sort_layout(int64_t N, const int32_t M[3], int B, SortK* sk_out, size_t* by
         nb[d] = (M[d] + B - 1) / B;
         nk *= nb[d];
     }
-    const int64_t nscan = nk + 2;
-    const int64_t ntiles = (nscan + kScanTile - 1) / kScanTile;
-    if (ntiles > kMaxScanTiles)
+    if (!sort_plan(N, nk + 1, plan))
         return false;
     if (sk_out) {
         sk_out->B = B;
@@ -341,61 +395,75 @@ bool sort_layout(int64_t N, const int32_t M[3], int B, SortK* sk_out, size_t* by
             sk_out->nb[d] = nb[d];
         sk_out->NK = (uint32_t)nk;
     }
-    size_t o = 0;
-    off[0] = o; o += align_up(sizeof(uint32_t) * (size_t)(N > 0 ? N : 1));    // keys
-    off[1] = o; o += align_up(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));     // perm
-    off[2] = o; o += align_up(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));     // inv
-    off[3] = o; o += align_up(sizeof(uint32_t) * (size_t)nscan);              // start
-    off[4] = o; o += align_up(sizeof(uint32_t) * (size_t)nscan);              // cursor
-    off[5] = o; o += align_up(sizeof(uint32_t) * (size_t)ntiles);             // tile sums
-    off[6] = o; o += align_up(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));     // tags in perm order
-    *bytes = o;
     return true;
 }
 
 static unsigned grid_for(int64_t n) { return (unsigned)((n + kSortThreads - 1) / kSortThreads); }
 
-hpf_status_t launch_sort(const SortK& sk, int64_t N, const float* R_in, const float* V_in,
-                         const uint8_t* T_in, const int32_t* tag_in, const int32_t* bonds_in, int D,
-                         float* R_out, float* V_out, uint8_t* T_out, int32_t* tag_out,
-                         int32_t* bonds_out, uint32_t* cell_start, char* work, const size_t off[7],
-                         hipStream_t s)
+// The four steps and the gather for any key function; `start` receives the
+// key starts (nkeys + 1 entries, the last = number of placed beads).
+template <class Keyer>
+hpf_status_t run_sort(const SortPlan& pl, Keyer keyer, int64_t N, const float* R_in, const float* V_in,
+                      const uint8_t* T_in, const int32_t* tag_in, const int32_t* bonds_in, int D, float* R_out,
+                      float* V_out, uint8_t* T_out, int32_t* tag_out, int32_t* bonds_out, uint32_t* start,
+                      char* work, hipStream_t s)
 {
-    uint32_t* keys = reinterpret_cast<uint32_t*>(work + off[0]);
-    int32_t* perm = reinterpret_cast<int32_t*>(work + off[1]);
-    int32_t* inv = reinterpret_cast<int32_t*>(work + off[2]);
-    uint32_t* start = cell_start ? cell_start : reinterpret_cast<uint32_t*>(work + off[3]);
-    uint32_t* cursor = reinterpret_cast<uint32_t*>(work + off[4]);
-    uint32_t* tiles = reinterpret_cast<uint32_t*>(work + off[5]);
-    int32_t* ptag = reinterpret_cast<int32_t*>(work + off[6]);
-    const int64_t nscan = (int64_t)sk.NK + 2;
-    const int64_t ntiles = (nscan + kScanTile - 1) / kScanTile;
-    const unsigned gfill = (unsigned)std::min<int64_t>(grid_for(nscan), 4096);
-
-    hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, nscan, 0u);
-    if (N > 0)
-        hipLaunchKernelGGL(k_sort_keys, dim3(grid_for(N)), dim3(kSortThreads), 0, s,
-                           reinterpret_cast<const float4*>(R_in), N, sk, keys, start);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, start, nscan,
-                       tiles);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, s, tiles, (int)ntiles);
-    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(nscan)), dim3(kSortThreads), 0, s, start, nscan,
-                       tiles);
+    uint32_t* key_t = reinterpret_cast<uint32_t*>(work + pl.off_key);
+    int32_t* perm = reinterpret_cast<int32_t*>(work + pl.off_perm);
+    int32_t* idx = reinterpret_cast<int32_t*>(work + pl.off_idx);
+    uint32_t* table = reinterpret_cast<uint32_t*>(work + pl.off_table);
+    uint32_t* part = reinterpret_cast<uint32_t*>(work + pl.off_part);
+    uint32_t* tiles = reinterpret_cast<uint32_t*>(work + pl.off_tiles);
+    const uint32_t nk = pl.nkeys;
+    const size_t smem = sizeof(uint32_t) * nk;
+    if (smem > 65536 &&
+        (hipFuncSetAttribute(reinterpret_cast<const void*>(k_sort_hist<Keyer>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess ||
+         hipFuncSetAttribute(reinterpret_cast<const void*>(k_sort_place), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)smem) != hipSuccess))
+        return HPF_EINVAL;
+    const unsigned gfill = (unsigned)std::min<int64_t>(grid_for(pl.nscan), 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, pl.nscan, 0u);
     if (N > 0) {
-        hipLaunchKernelGGL(k_copy_u32, dim3(gfill), dim3(kSortThreads), 0, s, start, cursor, nscan);
-        hipLaunchKernelGGL(k_sort_place, dim3(grid_for(N)), dim3(kSortThreads), 0, s, keys, N,
-                           tag_in, cursor, perm, ptag);
-        hipLaunchKernelGGL(k_sort_bricks, dim3((unsigned)std::min<int64_t>(nscan - 1, 1 << 20)),
-                           dim3(kBrickSortThreads), 0, s, start, nscan - 1, ptag, perm);
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(grid_for(N), 4096)), dim3(kSortThreads), 0, s,
+                           reinterpret_cast<uint32_t*>(idx), N, 0xffffffffu);
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, N);
+        hipLaunchKernelGGL(k_tag_index, dim3(grid_for(N)), dim3(kSortThreads), 0, s, tag_in, N, idx);
+        hipLaunchKernelGGL(k_sort_hist<Keyer>, dim3((unsigned)pl.nchunks), dim3(kChunkThreads), smem, s, keyer, idx,
+                           N, pl.S, nk, key_t, table);
+        const dim3 gcol((nk + kSortThreads - 1) / kSortThreads, (unsigned)pl.ncb);
+        hipLaunchKernelGGL(k_col_partial, gcol, dim3(kSortThreads), 0, s, table, pl.nchunks, nk, part);
+        hipLaunchKernelGGL(k_col_prefix, dim3((nk + kSortThreads - 1) / kSortThreads), dim3(kSortThreads), 0, s,
+                           part, pl.ncb, nk, start);
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)pl.ntiles), dim3(kSortThreads), 0, s, start, pl.nscan, tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, s, tiles, (int)pl.ntiles);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(pl.nscan)), dim3(kSortThreads), 0, s, start, pl.nscan, tiles);
+    if (N > 0) {
+        const dim3 gcol((nk + kSortThreads - 1) / kSortThreads, (unsigned)pl.ncb);
+        hipLaunchKernelGGL(k_col_apply, gcol, dim3(kSortThreads), 0, s, table, part, start, pl.nchunks, nk);
+        hipLaunchKernelGGL(k_sort_place, dim3((unsigned)pl.nchunks), dim3(kChunkThreads), smem, s, key_t, idx, N,
+                           pl.S, nk, table, perm);
         hipLaunchKernelGGL(k_sort_permute, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, N,
-                           reinterpret_cast<const float4*>(R_in), reinterpret_cast<const float4*>(V_in),
-                           T_in, tag_in, reinterpret_cast<float4*>(R_out),
-                           reinterpret_cast<float4*>(V_out), T_out, tag_out, inv);
+                           reinterpret_cast<const float4*>(R_in), reinterpret_cast<const float4*>(V_in), T_in,
+                           tag_in, reinterpret_cast<float4*>(R_out), reinterpret_cast<float4*>(V_out), T_out,
+                           tag_out, idx);
         if (D > 0 && bonds_in)
-            hipLaunchKernelGGL(k_sort_bonds, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, inv,
-                               N, bonds_in, D, bonds_out);
+            hipLaunchKernelGGL(k_sort_bonds, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, idx, N, bonds_in,
+                               D, bonds_out);
     }
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+hpf_status_t launch_sort(const SortK& sk, const SortPlan& pl, int64_t N, const float* R_in, const float* V_in,
+                         const uint8_t* T_in, const int32_t* tag_in, const int32_t* bonds_in, int D, float* R_out,
+                         float* V_out, uint8_t* T_out, int32_t* tag_out, int32_t* bonds_out, uint32_t* cell_start,
+                         char* work, hipStream_t s)
+{
+    CellKeyer keyer{sk, reinterpret_cast<const float4*>(R_in)};
+    uint32_t* start = cell_start ? cell_start : reinterpret_cast<uint32_t*>(work + pl.off_start);
+    return run_sort(pl, keyer, N, R_in, V_in, T_in, tag_in, bonds_in, D, R_out, V_out, T_out, tag_out, bonds_out,
+                    start, work, s);
 }
 
 }  // namespace hpf
