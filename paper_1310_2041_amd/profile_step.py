@@ -1,9 +1,10 @@
 """Short fused-step run used as the target of rocprofv3 counter passes.
 
-python -m paper_1310_2041_amd.profile_step [--config c3|c4] [--steps 12]
+python -m paper_1310_2041_amd.profile_step [--config c3|c4] [--steps 12] [--halo 2] [--sort-every 20]
 
 c1..c3: the workload's start, the first half step and `steps` fused steps
-(sorting every 10, reporting energies every step).
+(reporting energies every step) in the benchmark's configuration (deposit
+halo, sort interval, fused pass with the density deposit).
 c4: the 64-replica A10B10 sweep stepped `steps` times through the batched
 entry points (sorting every 10, energies on the last step).
 Both end with a plain 1 GiB device copy whose FETCH_SIZE / WRITE_SIZE
@@ -26,6 +27,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", default="c3")
     ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--halo", type=int, default=2)
+    ap.add_argument("--sort-every", type=int, default=20)
     args = ap.parse_args()
     import torch
 
@@ -40,12 +43,12 @@ def main():
         b.step(args.steps, report_last=True)
     else:
         s = wl.build(wl.SPECS[args.config])
-        st = engine.HpfState.from_system(s)
+        st = engine.HpfState.from_system(s, halo=args.halo)
         del s
         st.start(sort=True)
         st.prime()
         for k in range(args.steps):
-            st.step_fused(report=True, sort=k % 10 == 0)
+            st.step_fused(report=True, sort=k % args.sort_every == 0)
     torch.cuda.synchronize()
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
