@@ -577,7 +577,7 @@ __global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __res
 constexpr int kASThreads = 256;
 
 template <bool kR0Zero>
-__global__ __launch_bounds__(kASThreads, 5) void k_advance_scatter(const float4* __restrict__ R,
+__global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __restrict__ R,
                                                                 float4* __restrict__ R_next,
                                                                 float4* __restrict__ Vel,
                                                                 const uint8_t* __restrict__ T, int64_t N,

@@ -241,6 +241,8 @@ __device__ __forceinline__ Cover covering(int v, int B, int h, int nb, int M)
     return c;
 }
 
+constexpr int kSumFast = 8;       // covering boxes of a point summed with all loads in flight
+
 // One workgroup per brick: the cover lists of the brick's coordinates along
 // each axis are built once in LDS, then each thread sums the partial boxes for
 // its points (consecutive threads -> consecutive x -> coalesced reads).
@@ -273,6 +275,35 @@ __device__ __forceinline__ void scatter_sum_body(const unsigned long long* __res
         const Cover& cy = cov[1][iy];
         const Cover& cz = cov[2][iz];
         const int64_t dst = ((int64_t)(bxyz[2] * B + iz) * My + (bxyz[1] * B + iy)) * Mx + bxyz[0] * B + ix;
+        const int ncov = cx.n * cy.n * cz.n;
+        if (ncov <= kSumFast) {
+            // the usual case (at most two boxes per axis): all box offsets first, then
+            // every load of the point issued together
+            int64_t off[kSumFast];
+            int j = 0;
+            for (int a = 0; a < cz.n; ++a)
+                for (int b2 = 0; b2 < cy.n; ++b2) {
+                    const int64_t row = ((int64_t)cz.brick[a] * tk.nb[1] + cy.brick[b2]) * tk.nb[0];
+                    const int loc = (cz.local[a] * P + cy.local[b2]) * P;
+                    for (int c = 0; c < cx.n; ++c)
+                        off[j++] = (row + cx.brick[c]) * K * P3 + loc + cx.local[c];
+                }
+            for (int k = 0; k < K; ++k) {
+                unsigned long long v[kSumFast];
+#pragma unroll
+                for (int q = 0; q < kSumFast; ++q)
+                    v[q] = q < ncov ? partials[off[q] + (int64_t)k * P3] : 0ull;
+                unsigned long long sum = 0;
+#pragma unroll
+                for (int q = 0; q < kSumFast; ++q)
+                    sum += v[q];
+                if (kAdd)
+                    counts[(int64_t)k * tk.m.nm + dst] += sum;
+                else
+                    counts[(int64_t)k * tk.m.nm + dst] = sum;
+            }
+            continue;
+        }
         for (int k = 0; k < K; ++k) {
             unsigned long long sum = 0;
             for (int a = 0; a < cz.n; ++a)
