@@ -13,6 +13,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
+import oracle  # noqa: E402
 from paper_1310_2041_amd import engine, hpf  # noqa: E402
 from synth import workloads as wl  # noqa: E402
 
@@ -117,3 +118,29 @@ def test_batch_rejects_small_meshes():
     s = wl.small_system(20, 10, 10.0, 10, seed=1)
     with pytest.raises(ValueError):
         engine.BatchState([s])
+
+
+@pytest.mark.slow
+def test_full_size_64_replica_sweep_sampled():
+    """The 64-replica sweep at full size (6.8M beads) in the benchmark's launch shape (one
+    batch, 20 steps per HIP graph): the step-0 energies of sampled replicas match the oracle,
+    and after a replay replicas 0, 31 and 63 equal their single-system runs bit for bit."""
+    systems = [wl.build_replica(sp, r) for r, sp in enumerate(wl.replica_specs())]
+    b = engine.BatchState(systems, sort_every=10)
+    b.start()
+    E0 = b.energies()
+    for r in (0, 31, 63):
+        _, _, Eo = oracle.run(systems[r], 0)
+        assert E0[r, 0] == pytest.approx(Eo[0, 0], rel=1e-12)        # KE
+        assert E0[r, 1] == pytest.approx(Eo[0, 1], rel=1e-6)         # E_bond (FP32 terms)
+        assert E0[r, 2] == pytest.approx(Eo[0, 2], rel=1e-9)         # W
+    torch.cuda.synchronize()
+    g = engine.Graph(lambda: b.step(20, report_last=True))
+    g.launch()
+    torch.cuda.synchronize()
+    for r in (0, 31, 63):
+        st, _ = _single(systems[r], 20, 10)
+        for x, y in zip(b.replica_beads(r), st.host_beads()):
+            assert np.array_equal(x, y), f"replica {r}"
+    assert hpf.hpf_get_device_status() == 0
+    del g

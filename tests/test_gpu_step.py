@@ -75,6 +75,47 @@ def test_full_size_10m_blend_counts_and_forces():
     assert eb <= 1e-5
 
 
+@pytest.mark.slow
+def test_full_size_100m_three_species_sampled():
+    """The 100M-bead amphiphile/solvent system at full size (K = 3, 256^3 mesh, 32768
+    bricks, so the sort's key histogram takes the large-LDS path): counts bit-exact over
+    the whole mesh after the cell sort and cell scatter; field and bond forces of 200,000
+    sampled beads within 1e-5 (relative max-norm) of the oracle's."""
+    s = wl.build(wl.SPECS["c5"])
+    st = engine.HpfState.from_system(s)
+    st.sort()
+    assert st.cells_ok
+    st.scatter()
+    counts = counts_np(st.counts, s.K, s.M)
+    c_or, sk = oracle.density(s.R, s.T, s.L, s.M, s.K)
+    assert sk == 0
+    assert np.array_equal(counts, c_or)
+    del counts
+    hpf.hpf_field_potential(st.counts, st.mesh, st.field, st.V, None)
+    hpf.hpf_field_gradient(st.V, st.mesh, st.K, st.G)
+    F = torch.zeros_like(st.R)
+    hpf.hpf_force_gather(st.R, st.T, st.mesh, st.K, st.G, F)
+    tag = host(st.tag)
+    Ff = by_tag(host(F)[:, :3], tag, s.N)
+    F.zero_()
+    hpf.bond_forces(st.R, st.bonds, st.k_bond, st.r0, st.box, F)
+    Fb = by_tag(host(F)[:, :3], tag, s.N)
+    assert hpf.hpf_get_device_status() == 0
+    del st, F
+    V_or, _ = oracle.potential(c_or, s.L, s.M, s.N, s.kT, s.inv_kappa, s.chi)
+    del c_or
+    G_or = oracle.gradient(V_or, s.L, s.M)
+    del V_or
+    pick = np.sort(np.random.default_rng(5).choice(s.N, 200_000, replace=False))
+    Ff_or = oracle.gather(s.R[pick], s.T[pick], s.L, s.M, G_or)
+    del G_or
+    Fb_or, _ = oracle.bonds(s.R, s.bonds, s.k_bond, s.r0, s.L)
+    ef, eb = rel_max(Ff[pick], Ff_or), rel_max(Fb[pick], Fb_or[pick])
+    print(f"c5 sample: field rel max-norm {ef:.3e}, bond {eb:.3e}")
+    assert ef <= 1e-5
+    assert eb <= 1e-5
+
+
 def _gpu_energy_trace(s, n, sort_every=10):
     st = engine.HpfState.from_system(s)
     st.start(sort=True)
