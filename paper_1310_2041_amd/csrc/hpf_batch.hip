@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kTcThreads) void k_batch_scatter_bricks(const RepK*
                        partials + (rp.brick_off + it.begin) * (int64_t)K * P * P * P, strays);
 }
 
-__global__ __launch_bounds__(256) void k_batch_scatter_sum(const RepK* __restrict__ reps,
+__global__ __launch_bounds__(kSumThreads) void k_batch_scatter_sum(const RepK* __restrict__ reps,
                                                            const ItemK* __restrict__ items, int B, int h,
                                                            int K,
                                                            const unsigned long long* __restrict__ partials,
@@ -499,7 +499,7 @@ static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)
     hipLaunchKernelGGL(k_zero_u32_one, dim3(1), dim3(1), 0, s, strays);
     hipLaunchKernelGGL(k_batch_scatter_bricks, dim3((unsigned)b->n_brick_items), dim3(kTcThreads), smem, s, reps,
                        b->at<ItemK>(L.off_brick_items), B, h, K, R, T, cs, partials, strays);
-    hipLaunchKernelGGL(k_batch_scatter_sum, dim3((unsigned)b->n_brick_items), dim3(256), 0, s, reps,
+    hipLaunchKernelGGL(k_batch_scatter_sum, dim3((unsigned)b->n_brick_items), sum_block(b->n_brick_items), 0, s, reps,
                        b->at<ItemK>(L.off_brick_items), B, h, K, partials, counts);
     hipLaunchKernelGGL(k_batch_scatter_strays, dim3(256), dim3(kTcThreads), 0, s, reps, b->nrep, K, R, T, cs,
                        strays, counts);

@@ -574,9 +574,11 @@ __global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __res
 // brick is done. New positions outside the box, and every bead the sort could
 // not bin, are added to `counts` with global atomics; the partial sum pass
 // (k_scatter_sum<true>) then completes the counts of x_{n+1}.
-constexpr int kASThreads = 256;
+// Workgroup size: 256 threads, or 512 when there are few bricks (fewer than
+// kASFewBricks), so that a small mesh still fills the chip with waves.
+constexpr int kASFewBricks = 2048;
 
-template <bool kR0Zero>
+template <bool kR0Zero, int kASThreads>
 __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __restrict__ R,
                                                                 float4* __restrict__ R_next,
                                                                 float4* __restrict__ Vel,
@@ -776,6 +778,36 @@ hpf_status_t launch_advance_cells(const float* R, float* R_next, float* Vel, con
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
+template <int kThreads>
+static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float4* Vp, const uint8_t* T, int64_t N,
+                                             const TileK& tk, int K, const float4* Gp, const int32_t* bonds, int D,
+                                             float k, float r0, const BoxK& box, const float* inv_mass, float dt,
+                                             const uint32_t* cell_start, unsigned long long* partials,
+                                             unsigned long long* counts, float4* Fo, double* e_part,
+                                             double* kin_part, hipStream_t s)
+{
+    const size_t smem = sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P;
+    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_scatter<true, kThreads>)
+                                : reinterpret_cast<const void*>(k_advance_scatter<false, kThreads>);
+    if (smem > 65536 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+        return HPF_EINVAL;
+    int64_t nb = resident_blocks(fn, kThreads, smem);
+    if (nb < 1)
+        nb = 1024;
+    nb = std::min<int64_t>(nb, tk.ntiles + 1);
+    if ((e_part || kin_part) && nb > HPF_NPART)
+        nb = HPF_NPART;
+    const dim3 g((unsigned)nb), bl(kThreads);
+    if (r0 == 0.0f)
+        hipLaunchKernelGGL((k_advance_scatter<true, kThreads>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D,
+                           k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
+    else
+        hipLaunchKernelGGL((k_advance_scatter<false, kThreads>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds,
+                           D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
 hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
                                     const TileK& tk, int K, const float* G, const int32_t* bonds, int D, float k,
                                     float r0, const BoxK& box, const float* inv_mass, float dt,
@@ -783,37 +815,23 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
                                     unsigned long long* counts, float* F_out, double* e_part, double* kin_part,
                                     hipStream_t s)
 {
-    const size_t smem = sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P;
-    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_scatter<true>)
-                                : reinterpret_cast<const void*>(k_advance_scatter<false>);
-    if (smem > 65536 &&
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
-        return HPF_EINVAL;
-    int64_t nb = resident_blocks(fn, kASThreads, smem);
-    if (nb < 1)
-        nb = 1024;
-    nb = std::min<int64_t>(nb, tk.ntiles + 1);
-    if ((e_part || kin_part) && nb > HPF_NPART)
-        nb = HPF_NPART;
-    const dim3 g((unsigned)nb), bl(kASThreads);
     auto* Rp = reinterpret_cast<const float4*>(R);
     auto* Rn = reinterpret_cast<float4*>(R_next);
     auto* Vp = reinterpret_cast<float4*>(Vel);
     auto* Gp = reinterpret_cast<const float4*>(G);
     auto* Fo = reinterpret_cast<float4*>(F_out);
-    if (r0 == 0.0f)
-        hipLaunchKernelGGL(k_advance_scatter<true>, g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0,
-                           box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
-    else
-        hipLaunchKernelGGL(k_advance_scatter<false>, g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k,
-                           r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
-    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+    if (tk.ntiles < kASFewBricks)
+        return launch_advance_scatter_t<512>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
+                                             cell_start, partials, counts, Fo, e_part, kin_part, s);
+    return launch_advance_scatter_t<256>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt, cell_start,
+                                         partials, counts, Fo, e_part, kin_part, s);
 }
 
 hpf_status_t launch_scatter_finish(const unsigned long long* partials, const TileK& tk, int K,
                                    unsigned long long* counts, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scatter_sum<true>, dim3((unsigned)tk.ntiles), dim3(256), 0, s, partials, tk, K, counts);
+    hipLaunchKernelGGL(k_scatter_sum<true>, dim3((unsigned)tk.ntiles), sum_block(tk.ntiles), 0, s, partials, tk, K,
+                       counts);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 

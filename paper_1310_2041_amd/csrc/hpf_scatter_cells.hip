@@ -269,7 +269,7 @@ __device__ __forceinline__ void scatter_sum_body(const unsigned long long* __res
     __syncthreads();
     const int npts = o[0] * o[1] * o[2];
     const int Mx = tk.m.M[0], My = tk.m.M[1];
-    for (int e = tid; e < npts; e += 256) {
+    for (int e = tid; e < npts; e += (int)blockDim.x) {
         const int ix = e % o[0], r1 = e / o[0], iy = r1 % o[1], iz = r1 / o[1];
         const Cover& cx = cov[0][ix];
         const Cover& cy = cov[1][iy];
@@ -321,8 +321,16 @@ __device__ __forceinline__ void scatter_sum_body(const unsigned long long* __res
     }
 }
 
+// Up to one thread per point of the brick (B^3 <= 512): launched with 512
+// threads when there are few bricks (a small mesh must still fill the chip),
+// else with 256.
+constexpr int kSumThreads = 512;
+constexpr int64_t kSumFewBricks = 2048;
+
+static dim3 sum_block(int64_t ntiles) { return dim3(ntiles < kSumFewBricks ? kSumThreads : kSumThreads / 2); }
+
 template <bool kAdd>
-__global__ __launch_bounds__(256) void k_scatter_sum(const unsigned long long* __restrict__ partials,
+__global__ __launch_bounds__(kSumThreads) void k_scatter_sum(const unsigned long long* __restrict__ partials,
                                                      TileK tk, int K,
                                                      unsigned long long* __restrict__ counts)
 {
@@ -413,7 +421,8 @@ hpf_status_t launch_scatter_cells(const float* R, const uint8_t* T, int64_t N, c
     hipLaunchKernelGGL(k_zero_u32_one, dim3(1), dim3(1), 0, s, strays);
     hipLaunchKernelGGL(k_scatter_bricks, dim3((unsigned)tk.ntiles), dim3(kTcThreads), smem, s, Rp, T, K, tk,
                        cell_start, partials, strays);
-    hipLaunchKernelGGL(k_scatter_sum<false>, dim3((unsigned)tk.ntiles), dim3(256), 0, s, partials, tk, K, c);
+    hipLaunchKernelGGL(k_scatter_sum<false>, dim3((unsigned)tk.ntiles), sum_block(tk.ntiles), 0, s, partials, tk, K,
+                       c);
     hipLaunchKernelGGL(k_scatter_strays, dim3(512), dim3(kTcThreads), 0, s, Rp, T, N, K, tk.m, tk.NK,
                        cell_start, strays, c);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
