@@ -410,6 +410,9 @@ typedef struct hpf_batch_config {
     int32_t sort_every;      /* re-sort every n steps (0: never after start) */
     int32_t bead_chunk;      /* beads per work item, >= 512 */
     int32_t mesh_chunk;      /* mesh points per potential work item, >= 2048 */
+    int32_t fuse_deposit;    /* 1: each step's fused pass also deposits the new positions
+                                (as hpf_advance_scatter), so the next step only finishes
+                                the density; 0: a separate cell scatter every step */
 } hpf_batch_config_t;
 
 typedef struct hpf_batch_buffers {
@@ -443,11 +446,12 @@ hpf_status_t hpf_batch_step(hpf_batch_t* batch, int32_t n_steps, int32_t report_
  * double[n_rep][8] = {KE, E_bond, W, E_tot, Px, Py, Pz, 0}. Any may be NULL. */
 hpf_status_t hpf_batch_current(const hpf_batch_t* batch, float** R, float** Vel, uint8_t** T,
                                int32_t** tag, int32_t** bonds, double** energies);
-/* Autotuner: times trial_steps steps for each candidate (halo in {1,2},
- * bead_chunk in {1024..8192}, mesh_chunk in {4096,16384}) on the live
- * system, keeps the fastest and returns it in *chosen; trial_ms (nullable,
- * >= 16 floats) receives the per-step times, *n_trials their count. The
- * trials advance the simulation. Synchronises the stream. */
+/* Autotuner: times trial_steps steps for each candidate on the live system --
+ * halo in {1,2} x mesh_chunk in {4096,16384}, with the fused deposit and with
+ * a separate scatter (the latter also over bead_chunk in {1024..8192}) --
+ * keeps the fastest and returns it in *chosen; trial_ms (nullable, >= 20
+ * floats) receives the per-step times, *n_trials their count. The trials
+ * advance the simulation. Synchronises the stream. */
 hpf_status_t hpf_batch_tune(hpf_batch_t* batch, int32_t trial_steps, void* stream,
                             hpf_batch_config_t* chosen, float* trial_ms, int32_t* n_trials);
 hpf_status_t hpf_batch_destroy(hpf_batch_t* batch);

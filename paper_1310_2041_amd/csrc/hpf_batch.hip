@@ -37,6 +37,7 @@ struct ItemK {
 };
 
 constexpr int kBThreads = 256;
+constexpr int kASThreadsBatch = 256;
 
 __device__ __forceinline__ TileK tile_of(const RepK& r, int B, int h)
 {
@@ -73,6 +74,7 @@ __global__ __launch_bounds__(kTcThreads) void k_batch_scatter_bricks(const RepK*
                        partials + (rp.brick_off + it.begin) * (int64_t)K * P * P * P, strays);
 }
 
+template <bool kAdd>
 __global__ __launch_bounds__(kSumThreads) void k_batch_scatter_sum(const RepK* __restrict__ reps,
                                                            const ItemK* __restrict__ items, int B, int h,
                                                            int K,
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(kSumThreads) void k_batch_scatter_sum(const RepK* _
     const RepK& rp = reps[it.rep];
     const TileK tk = tile_of(rp, B, h);
     const int P = tk.P;
-    scatter_sum_body(partials + rp.brick_off * (int64_t)K * P * P * P, tk, K, it.begin,
+    scatter_sum_body<kAdd>(partials + rp.brick_off * (int64_t)K * P * P * P, tk, K, it.begin,
                      counts + (int64_t)K * rp.moff);
 }
 
@@ -229,6 +231,83 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
         acc.store_rows(kin_part, nslot, li, scratch);
 }
 
+// The fused pass with the density deposit of the new positions (as
+// k_advance_scatter), one workgroup per (replica, brick) item of the last
+// sort; a replica's last item (brick == NK) holds the beads the sort could
+// not bin, deposited with global atomics. The energy partials go to the
+// item's slot.
+template <bool kR0Zero>
+__global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
+    const RepK* __restrict__ reps, const ItemK* __restrict__ items, int B, int h, int K,
+    const float4* __restrict__ R, float4* __restrict__ R_next, float4* __restrict__ Vel,
+    const uint8_t* __restrict__ T, int64_t Ntot, const float4* __restrict__ G, const int32_t* __restrict__ bonds,
+    int D, float k, float r0, float dt, const uint32_t* __restrict__ cell_start,
+    unsigned long long* __restrict__ partials, unsigned long long* __restrict__ counts,
+    double* __restrict__ e_part, double* __restrict__ kin_part, int nslot)
+{
+    extern __shared__ unsigned long long dbox[];
+    __shared__ double scratch[kASThreadsBatch / kWave];
+    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
+    const ItemK it = items[li];
+    const RepK& rp = reps[it.rep];
+    const MeshK& m = rp.m;
+    const float4* Gr = G + (int64_t)K * rp.moff;
+    unsigned long long* cr = counts + (int64_t)K * rp.moff;
+    const int P = B + 1 + 2 * h, P3 = P * P * P, nbox = K * P3;
+    const int64_t brick = it.begin;
+    const float hdt = 0.5f * dt;
+    KinAcc acc;
+    double e = 0.0;
+    bool bad_bead = false, bad_bond = false, nonfinite = false;
+    const uint32_t* cs = cell_start + rp.key_base;
+    if (brick < rp.NK) {
+        const int bx = (int)(brick % rp.nb[0]);
+        const int by = (int)((brick / rp.nb[0]) % rp.nb[1]);
+        const int bz = (int)(brick / ((int64_t)rp.nb[0] * rp.nb[1]));
+        const int x0 = bx * B, y0 = by * B, z0 = bz * B;
+        const int ox = min(B, m.M[0] - x0), oy = min(B, m.M[1] - y0), oz = min(B, m.M[2] - z0);
+        for (int q = threadIdx.x; q < nbox; q += kASThreadsBatch)
+            dbox[q] = 0ull;
+        __syncthreads();
+        const int64_t first = cs[brick], last = min((int64_t)cs[brick + 1], Ntot);
+        for (int64_t i = first + threadIdx.x; i < last; i += kASThreadsBatch) {
+            const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k, r0, rp.box,
+                                                    nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond, nonfinite);
+            const int t = T[i];
+            BeadCell bc;
+            int lx, ly, lz;
+            if (bead_cell(rn, m, bc) && t < K && brick_box_cell(bc, m, x0, y0, z0, ox, oy, oz, h, lx, ly, lz))
+                box_deposit(dbox, P, t, lx, ly, lz, bc);
+            else
+                bad_bead |= !deposit_global(rn, t, K, m, cr);
+        }
+        __syncthreads();
+        unsigned long long* out = partials + (rp.brick_off + brick) * (int64_t)nbox;
+        for (int q = threadIdx.x; q < nbox; q += kASThreadsBatch)
+            out[q] = dbox[q];
+    } else {
+        const int64_t first = cs[rp.NK], last = min((int64_t)cs[rp.NK + 1], Ntot);
+        for (int64_t i = first + threadIdx.x; i < last; i += kASThreadsBatch) {
+            const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k, r0, rp.box,
+                                                    nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond, nonfinite);
+            bad_bead |= !deposit_global(rn, T[i], K, m, cr);
+        }
+    }
+    if (bad_bead)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+    if (bad_bond)
+        raise_flag(HPF_FLAG_BAD_BOND);
+    if (nonfinite)
+        raise_flag(HPF_FLAG_NONFINITE);
+    if (e_part) {
+        const double s = block_sum(e, scratch);
+        if (threadIdx.x == 0)
+            e_part[li] = s;
+    }
+    if (kin_part)
+        acc.store_rows(kin_part, nslot, li, scratch);
+}
+
 // per replica: energies {KE, E_bond, W, E_tot, Px, Py, Pz, 0} from the item
 // partials, each summed in item order by one lane
 __global__ __launch_bounds__(64) void k_batch_reduce(const int64_t* __restrict__ bead_items,
@@ -343,8 +422,9 @@ struct BatchLayout {
     int64_t Ntot = 0, nm_tot = 0, bricks_tot = 0;
     uint32_t NKT = 0;                    // keys of all replicas, invalid buckets included
     int64_t max_bead_items = 0, max_mesh_items = 0, max_planes = 0;
-    size_t off_reps, off_bead_items, off_brick_items, off_mesh_items, off_plane_items, off_bead_ioff,
-        off_mesh_ioff, off_sort, off_start, off_strays, off_partials, off_wpart, off_epart, off_kpart, off_energy,
+    int64_t nslot = 0;                   // energy partial slots (one per bead or fused item)
+    size_t off_reps, off_bead_items, off_brick_items, off_adv_items, off_mesh_items, off_plane_items, off_bead_ioff,
+        off_adv_ioff, off_mesh_ioff, off_sort, off_start, off_strays, off_partials, off_wpart, off_epart, off_kpart, off_energy,
         total;
     SortPlan sort;
 };
@@ -390,17 +470,20 @@ static bool batch_layout(const hpf_replica_t* reps, int nrep, const hpf_batch_co
     L->off_reps = o; o += al256(sizeof(RepK) * nrep);
     L->off_bead_items = o; o += al256(sizeof(ItemK) * (L->max_bead_items + 1));
     L->off_brick_items = o; o += al256(sizeof(ItemK) * (L->bricks_tot + 1));
+    L->off_adv_items = o; o += al256(sizeof(ItemK) * (L->bricks_tot + nrep + 1));
     L->off_mesh_items = o; o += al256(sizeof(ItemK) * (L->max_mesh_items + 1));
     L->off_plane_items = o; o += al256(sizeof(ItemK) * (L->max_planes + 1));
     L->off_bead_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
+    L->off_adv_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
     L->off_mesh_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
     L->off_sort = o; o += al256(L->sort.bytes);
     L->off_start = o; o += al256(sizeof(uint32_t) * (nscan + 1));
     L->off_strays = o; o += al256(sizeof(uint32_t) * (N1 + 64));
     L->off_partials = o; o += al256(sizeof(unsigned long long) * L->bricks_tot * cfg->K * Pmax * Pmax * Pmax);
     L->off_wpart = o; o += al256(sizeof(double) * (L->max_mesh_items + 1));
-    L->off_epart = o; o += al256(sizeof(double) * (L->max_bead_items + 1));
-    L->off_kpart = o; o += al256(sizeof(double) * 4 * (L->max_bead_items + 1));
+    L->nslot = std::max<int64_t>(L->max_bead_items, L->bricks_tot + nrep) + 1;
+    L->off_epart = o; o += al256(sizeof(double) * L->nslot);
+    L->off_kpart = o; o += al256(sizeof(double) * 4 * L->nslot);
     L->off_energy = o; o += al256(sizeof(double) * 8 * nrep);
     L->total = o;
     return true;
@@ -419,7 +502,8 @@ struct hpf_batch {
     int rcur = 0;        // current position buffer
     int scur = 0;        // current velocity / type / tag / bond buffer
     int64_t steps_done = 0;
-    int64_t n_bead_items = 0, n_brick_items = 0, n_mesh_items = 0, n_planes = 0;
+    int64_t n_bead_items = 0, n_brick_items = 0, n_adv_items = 0, n_mesh_items = 0, n_planes = 0;
+    bool pending = false;  // partial boxes + counts hold the deposit of the current positions
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(work + off); }
 };
 
@@ -428,8 +512,8 @@ namespace hpf {
 static hpf_status_t batch_build_items(hpf_batch* b)
 {
     const hpf_batch_config_t& c = b->cfg;
-    std::vector<ItemK> bead, brick, mesh, plane;
-    std::vector<int64_t> bead_off(b->nrep + 1), mesh_off(b->nrep + 1);
+    std::vector<ItemK> bead, brick, adv, mesh, plane;
+    std::vector<int64_t> bead_off(b->nrep + 1), adv_off(b->nrep + 1), mesh_off(b->nrep + 1);
     for (int r = 0; r < b->nrep; ++r) {
         const RepK& rp = b->reps[r];
         bead_off[r] = (int64_t)bead.size();
@@ -440,22 +524,30 @@ static hpf_status_t batch_build_items(hpf_batch* b)
             mesh.push_back({r, 0, s, std::min<int64_t>(rp.m.nm, s + c.mesh_chunk)});
         for (int64_t k = 0; k < rp.nbricks; ++k)
             brick.push_back({r, 0, k, k + 1});
+        adv_off[r] = (int64_t)adv.size();
+        for (int64_t k = 0; k <= rp.nbricks; ++k)          // the last item: beads that were not binned
+            adv.push_back({r, 0, k, k + 1});
         for (int z = 0; z < rp.m.M[2]; ++z)
             plane.push_back({r, 0, z, z + 1});
     }
     bead_off[b->nrep] = (int64_t)bead.size();
+    adv_off[b->nrep] = (int64_t)adv.size();
     mesh_off[b->nrep] = (int64_t)mesh.size();
     if ((int64_t)bead.size() > b->L.max_bead_items || (int64_t)mesh.size() > b->L.max_mesh_items)
         return HPF_EINVAL;
     b->n_bead_items = (int64_t)bead.size();
     b->n_brick_items = (int64_t)brick.size();
+    b->n_adv_items = (int64_t)adv.size();
     b->n_mesh_items = (int64_t)mesh.size();
+    b->pending = false;                 // launch shapes may change the deposit boxes
     b->n_planes = (int64_t)plane.size();
     auto up = [&](size_t off, const void* src, size_t bytes) {
         return bytes == 0 || hipMemcpy(b->work + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
     };
     if (!up(b->L.off_bead_items, bead.data(), sizeof(ItemK) * bead.size()) ||
         !up(b->L.off_brick_items, brick.data(), sizeof(ItemK) * brick.size()) ||
+        !up(b->L.off_adv_items, adv.data(), sizeof(ItemK) * adv.size()) ||
+        !up(b->L.off_adv_ioff, adv_off.data(), sizeof(int64_t) * adv_off.size()) ||
         !up(b->L.off_mesh_items, mesh.data(), sizeof(ItemK) * mesh.size()) ||
         !up(b->L.off_plane_items, plane.data(), sizeof(ItemK) * plane.size()) ||
         !up(b->L.off_bead_ioff, bead_off.data(), sizeof(int64_t) * bead_off.size()) ||
@@ -492,17 +584,24 @@ static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)
     const uint32_t* cs = b->at<uint32_t>(L.off_start);
     const auto* R = reinterpret_cast<const float4*>(b->buf.R[b->rcur]);
     const uint8_t* T = b->buf.T[b->scur];
-    const size_t smem = scatter_cells_smem(K, P);
-    if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_scatter_bricks),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
-        return HPF_EINVAL;
-    hipLaunchKernelGGL(k_zero_u32_one, dim3(1), dim3(1), 0, s, strays);
-    hipLaunchKernelGGL(k_batch_scatter_bricks, dim3((unsigned)b->n_brick_items), dim3(kTcThreads), smem, s, reps,
-                       b->at<ItemK>(L.off_brick_items), B, h, K, R, T, cs, partials, strays);
-    hipLaunchKernelGGL(k_batch_scatter_sum, dim3((unsigned)b->n_brick_items), sum_block(b->n_brick_items), 0, s, reps,
-                       b->at<ItemK>(L.off_brick_items), B, h, K, partials, counts);
-    hipLaunchKernelGGL(k_batch_scatter_strays, dim3(256), dim3(kTcThreads), 0, s, reps, b->nrep, K, R, T, cs,
-                       strays, counts);
+    if (b->pending) {
+        // the last fused pass deposited the current positions: add its boxes to the counts
+        hipLaunchKernelGGL(k_batch_scatter_sum<true>, dim3((unsigned)b->n_brick_items), sum_block(b->n_brick_items),
+                           0, s, reps, b->at<ItemK>(L.off_brick_items), B, h, K, partials, counts);
+        b->pending = false;
+    } else {
+        const size_t smem = scatter_cells_smem(K, P);
+        if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_scatter_bricks),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+            return HPF_EINVAL;
+        hipLaunchKernelGGL(k_zero_u32_one, dim3(1), dim3(1), 0, s, strays);
+        hipLaunchKernelGGL(k_batch_scatter_bricks, dim3((unsigned)b->n_brick_items), dim3(kTcThreads), smem, s, reps,
+                           b->at<ItemK>(L.off_brick_items), B, h, K, R, T, cs, partials, strays);
+        hipLaunchKernelGGL(k_batch_scatter_sum<false>, dim3((unsigned)b->n_brick_items), sum_block(b->n_brick_items),
+                           0, s, reps, b->at<ItemK>(L.off_brick_items), B, h, K, partials, counts);
+        hipLaunchKernelGGL(k_batch_scatter_strays, dim3(256), dim3(kTcThreads), 0, s, reps, b->nrep, K, R, T, cs,
+                           strays, counts);
+    }
     double* w = report ? b->at<double>(L.off_wpart) : nullptr;
     const dim3 gm((unsigned)b->n_mesh_items), bm(kPotThreads);
     const ItemK* mi = b->at<ItemK>(L.off_mesh_items);
@@ -537,8 +636,32 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
     const auto* G = reinterpret_cast<const float4*>(b->buf.G);
     double* e = report ? b->at<double>(L.off_epart) : nullptr;
     double* kp = report ? b->at<double>(L.off_kpart) : nullptr;
-    const int nslot = (int)(L.max_bead_items + 1);
-    if (b->n_bead_items > 0) {
+    const int nslot = (int)L.nslot;
+    const bool fused = !prime && c.fuse_deposit;
+    b->pending = false;
+    if (fused) {
+        const int P = c.brick + 1 + 2 * c.halo;
+        const size_t smem = sizeof(unsigned long long) * (size_t)c.K * P * P * P;
+        const void* fn = c.r0 == 0.0f ? reinterpret_cast<const void*>(k_batch_advance_scatter<true>)
+                                      : reinterpret_cast<const void*>(k_batch_advance_scatter<false>);
+        if (smem > 65536 &&
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+            return HPF_EINVAL;
+        const dim3 ga((unsigned)b->n_adv_items), ba(kASThreadsBatch);
+        const ItemK* adv = b->at<ItemK>(L.off_adv_items);
+        const uint32_t* cs = b->at<uint32_t>(L.off_start);
+        auto* partials = b->at<unsigned long long>(L.off_partials);
+        auto* counts = reinterpret_cast<unsigned long long*>(b->buf.counts);
+        if (c.r0 == 0.0f)
+            hipLaunchKernelGGL(k_batch_advance_scatter<true>, ga, ba, smem, s, reps, adv, c.brick, c.halo, c.K, R, Rn,
+                               Vel, T, L.Ntot, G, bonds, c.D, c.k_bond, c.r0, c.dt, cs, partials, counts, e, kp,
+                               nslot);
+        else
+            hipLaunchKernelGGL(k_batch_advance_scatter<false>, ga, ba, smem, s, reps, adv, c.brick, c.halo, c.K, R,
+                               Rn, Vel, T, L.Ntot, G, bonds, c.D, c.k_bond, c.r0, c.dt, cs, partials, counts, e, kp,
+                               nslot);
+        b->pending = true;
+    } else if (b->n_bead_items > 0) {
         if (prime) {
             if (c.r0 == 0.0f)
                 hipLaunchKernelGGL(k_batch_prime<true>, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot, G,
@@ -557,9 +680,9 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
     }
     b->rcur = 1 - b->rcur;
     if (report)
-        hipLaunchKernelGGL(k_batch_reduce, dim3(b->nrep), dim3(64), 0, s, b->at<int64_t>(L.off_bead_ioff),
-                           b->at<int64_t>(L.off_mesh_ioff), b->at<double>(L.off_wpart), e, kp, nslot,
-                           b->at<double>(L.off_energy));
+        hipLaunchKernelGGL(k_batch_reduce, dim3(b->nrep), dim3(64), 0, s,
+                           b->at<int64_t>(fused ? L.off_adv_ioff : L.off_bead_ioff), b->at<int64_t>(L.off_mesh_ioff),
+                           b->at<double>(L.off_wpart), e, kp, nslot, b->at<double>(L.off_energy));
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
@@ -590,7 +713,7 @@ hpf_status_t hpf_batch_create(const hpf_replica_t* reps, int32_t n_rep, const hp
     if (c.brick == 0)
         c.brick = 8;
     if (c.halo < 0 || c.halo > kTcMaxHalo || c.halo >= c.brick || !(c.dt > 0.0f) || c.sort_every < 0 ||
-        c.bead_chunk < kMinBeadChunk || c.mesh_chunk < kMinMeshChunk)
+        c.bead_chunk < kMinBeadChunk || c.mesh_chunk < kMinMeshChunk || c.fuse_deposit < 0 || c.fuse_deposit > 1)
         return HPF_EINVAL;
     for (int i = 0; i < 2; ++i)
         if (L.Ntot > 0 && (!bufs->R[i] || !bufs->Vel[i] || !bufs->T[i] || !bufs->tag[i] ||
@@ -728,43 +851,54 @@ hpf_status_t hpf_batch_tune(hpf_batch_t* b, int32_t trial_steps, void* stream, h
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return HPF_EHIP;
+    std::vector<hpf_batch_config_t> cands;
+    for (int hb : halo_opts) {
+        if (hb >= b->cfg.brick)
+            continue;
+        for (int mc : mesh_opts) {
+            hpf_batch_config_t c = b->cfg;
+            c.halo = hb;
+            c.mesh_chunk = mc;
+            c.fuse_deposit = 1;                 // bead chunks do not apply to the fused pass
+            cands.push_back(c);
+            c.fuse_deposit = 0;
+            for (int bc : bead_opts) {
+                c.bead_chunk = bc;
+                cands.push_back(c);
+            }
+        }
+    }
     hpf_batch_config_t best = b->cfg;
     float best_ms = 1e30f;
     int t = 0;
     hpf_status_t st = HPF_OK;
-    for (int hb : halo_opts)
-        for (int bc : bead_opts)
-            for (int mc : mesh_opts) {
-                if (hb >= b->cfg.brick)
-                    continue;
-                b->cfg.halo = hb;
-                b->cfg.bead_chunk = bc;
-                b->cfg.mesh_chunk = mc;
-                if ((st = batch_build_items(b)) != HPF_OK)
-                    goto done;
-                if ((st = hpf_batch_step(b, 1, 0, stream)) != HPF_OK)      // warm-up
-                    goto done;
-                if (hipEventRecord(e0, s) != hipSuccess) {
-                    st = HPF_EHIP;
-                    goto done;
-                }
-                if ((st = hpf_batch_step(b, trial_steps, 0, stream)) != HPF_OK)
-                    goto done;
-                float ms = 0.0f;
-                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                    st = HPF_EHIP;
-                    goto done;
-                }
-                ms /= trial_steps;
-                if (trial_ms)
-                    trial_ms[t] = ms;
-                ++t;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = b->cfg;
-                }
-            }
+    for (const hpf_batch_config_t& c : cands) {
+        b->cfg = c;
+        if ((st = batch_build_items(b)) != HPF_OK)
+            goto done;
+        if ((st = hpf_batch_step(b, 1, 0, stream)) != HPF_OK)      // warm-up
+            goto done;
+        if (hipEventRecord(e0, s) != hipSuccess) {
+            st = HPF_EHIP;
+            goto done;
+        }
+        if ((st = hpf_batch_step(b, trial_steps, 0, stream)) != HPF_OK)
+            goto done;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = HPF_EHIP;
+            goto done;
+        }
+        ms /= trial_steps;
+        if (trial_ms)
+            trial_ms[t] = ms;
+        ++t;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = b->cfg;
+        }
+    }
 done:
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -256,7 +256,7 @@ class BatchState:
     """
 
     def __init__(self, systems, sort_every=10, brick=8, halo=1, bead_chunk=4096,
-                 mesh_chunk=16384, device="cuda"):
+                 mesh_chunk=16384, fuse_deposit=True, device="cuda"):
         dev = torch.device(device)
         s0 = systems[0]
         self.K = int(s0.K)
@@ -304,6 +304,7 @@ class BatchState:
         cfg.k_bond, cfg.r0, cfg.dt = float(s0.k_bond), float(s0.r0), float(s0.dt)
         cfg.brick, cfg.halo, cfg.sort_every = brick, halo, sort_every
         cfg.bead_chunk, cfg.mesh_chunk = bead_chunk, mesh_chunk
+        cfg.fuse_deposit = int(fuse_deposit)
         self.cfg = cfg
         ws = hpf.hpf_batch_workspace_bytes(reps, cfg)
         if ws == 0:
@@ -337,7 +338,8 @@ class BatchState:
     def tune(self, trial_steps=3, stream=None):
         cfg, ms = hpf.hpf_batch_tune(self.handle, trial_steps, stream)
         self.cfg = cfg
-        return {"halo": cfg.halo, "bead_chunk": cfg.bead_chunk, "mesh_chunk": cfg.mesh_chunk}, ms
+        return {"halo": cfg.halo, "bead_chunk": cfg.bead_chunk, "mesh_chunk": cfg.mesh_chunk,
+                "fuse_deposit": cfg.fuse_deposit}, ms
 
     def _current(self, name):
         ptr = hpf.hpf_batch_current(self.handle)[name]

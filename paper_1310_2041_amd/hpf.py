@@ -60,7 +60,8 @@ class BatchConfig(C.Structure):
     """hpf_batch_config_t"""
     _fields_ = [("K", C.c_int32), ("D", C.c_int32), ("k_bond", C.c_float), ("r0", C.c_float),
                 ("dt", C.c_float), ("brick", C.c_int32), ("halo", C.c_int32),
-                ("sort_every", C.c_int32), ("bead_chunk", C.c_int32), ("mesh_chunk", C.c_int32)]
+                ("sort_every", C.c_int32), ("bead_chunk", C.c_int32), ("mesh_chunk", C.c_int32),
+                ("fuse_deposit", C.c_int32)]
 
 
 class BatchBuffers(C.Structure):
@@ -483,7 +484,7 @@ def hpf_batch_current(h) -> dict:
 
 def hpf_batch_tune(h, trial_steps: int, stream=None):
     cfg = BatchConfig()
-    ms = (C.c_float * 16)()
+    ms = (C.c_float * 32)()
     n = C.c_int32()
     _check("hpf_batch_tune", lib().hpf_batch_tune(h, int(trial_steps), _stream(stream),
                                                   C.byref(cfg), ms, C.byref(n)))

@@ -36,12 +36,13 @@ def _single(s, steps, sort_every):
     return st, e[-1]
 
 
+@pytest.mark.parametrize("fuse", [True, False])
 @pytest.mark.parametrize("bead_chunk,mesh_chunk,halo", [(512, 2048, 1), (4096, 16384, 2)])
-def test_batch_matches_single_systems_bitwise(bead_chunk, mesh_chunk, halo):
+def test_batch_matches_single_systems_bitwise(bead_chunk, mesh_chunk, halo, fuse):
     systems = _replicas()
     steps, sort_every = 12, 5
     b = engine.BatchState(systems, sort_every=sort_every, halo=halo, bead_chunk=bead_chunk,
-                          mesh_chunk=mesh_chunk)
+                          mesh_chunk=mesh_chunk, fuse_deposit=fuse)
     b.start()
     b.step(steps, report_last=True)
     E = b.energies()
@@ -106,8 +107,8 @@ def test_batch_tune_keeps_trajectories():
     a.start()
     b.start()
     chosen, times = a.tune(trial_steps=2)
-    assert len(times) == 16 and all(t > 0 for t in times)
-    assert chosen["halo"] in (1, 2) and chosen["bead_chunk"] in (1024, 2048, 4096, 8192)
+    assert len(times) == 20 and all(t > 0 for t in times)
+    assert chosen["halo"] in (1, 2) and chosen["fuse_deposit"] in (0, 1)
     b.step(len(times) * 3, report_last=False)
     for r in range(len(systems)):
         for x, y in zip(a.replica_beads(r), b.replica_beads(r)):
