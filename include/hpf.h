@@ -61,8 +61,8 @@ typedef int32_t hpf_status_t;
 #define HPF_FLAG_OVERFLOW 0x2u   /* a mesh count reached 2^62 (risk of u64 wrap) */
 #define HPF_FLAG_NONFINITE 0x4u  /* verlet_step produced a non-finite coordinate */
 #define HPF_FLAG_BAD_BOND 0x8u   /* a bond-table entry was outside [-1, N) */
-#define HPF_FLAG_SORT_ORDER 0x10u /* a cell held more beads than the in-cell tag sort
-                                     handles; that cell's beads kept placement order */
+#define HPF_FLAG_SORT_ORDER 0x10u /* hpf_sort_by_cell got tags that are not a permutation
+                                     of [0, N); its output is not a valid permutation */
 
 /* Periodic box and density mesh.
  *  L      box edge lengths, > 0.

@@ -378,7 +378,7 @@ hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N, cons
         return HPF_EINVAL;
     if (N > 0 && (!R_in || !T_in || !R_out || !T_out))
         return HPF_EINVAL;
-    if (!Vel_in != !Vel_out || !tag_in != !tag_out || (D > 0 && (!bonds_in || !bonds_out)))
+    if (!Vel_in != !Vel_out || !tag_in != !tag_out || (N > 0 && D > 0 && (!bonds_in || !bonds_out)))
         return HPF_EINVAL;
     if (N > 0 && (R_in == R_out || (Vel_in && Vel_in == Vel_out) || T_in == T_out ||
                   (tag_in && tag_in == tag_out) || (D > 0 && bonds_in == bonds_out)))

@@ -164,26 +164,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
     return r;
 }
 
-// Runs of equal keys inside a wavefront: beads arrive nearly in cell order,
-// so neighbouring lanes usually share a key. Returns the lane mask of run
-// heads; *len = length of the run this lane heads (heads only), *head = the
-// head lane of this lane's run.
-__device__ __forceinline__ void wave_runs(uint32_t key, bool active, int* head, int* len)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t prev = __shfl_up(key, 1, kWave);
-    const bool is_head = active && (lane == 0 || prev != key);
-    const uint64_t heads = __ballot(is_head);
-    const uint64_t act = __ballot(active);
-    // head of my run: highest head lane <= lane
-    const uint64_t below = heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1));
-    *head = below ? 63 - __builtin_clzll(below) : lane;
-    // run length: up to the next head or the last active lane
-    const uint64_t above = heads & ~((2ull << lane) - 1 | (lane == 63 ? ~0ull : 0ull));
-    const int next = above ? __builtin_ctzll(above) : 64 - __builtin_clzll(act);
-    *len = next - lane;
-}
-
 // Lanes of a wavefront grouped by equal key, whatever their positions: one
 // pass per distinct key among the active lanes (a uniform loop). Returns the
 // mask of active lanes holding this lane's key (0 for inactive lanes); its

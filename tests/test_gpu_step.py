@@ -218,3 +218,26 @@ def test_c2_1000_step_mean_energies():
         if rel > tol:
             bad.append(key)
     assert not bad
+
+
+@pytest.mark.parametrize("advance", ["scatter", "plain", "cells"])
+def test_empty_system_through_every_pass(advance):
+    """N = 0: the sort, the fused passes, the finishing pass and the reductions run on an
+    empty system (including inside a graph) and leave zero counts, zero energies and no flag."""
+    z4 = np.zeros((0, 4), np.float32)
+    chi = np.array([[0.0, 1.0], [1.0, 0.0]])
+    st = engine.HpfState(z4, z4, np.zeros(0, np.uint8), np.zeros(0, np.int32), np.zeros((2, 0), np.int32),
+                         12.0, 12, 2, 1.0, 10.0, chi, 100.0, 0.0, 0.03, advance=advance)
+    hpf.hpf_get_device_status(clear=True)
+    st.start(sort=True)
+    st.prime()
+    for i in range(4):
+        st.step_fused(report=True, sort=i % 2 == 0)
+    g = engine.Graph(lambda: [st.step_fused(report=True, sort=j == 0) for j in range(2)])
+    g.launch()
+    torch.cuda.synchronize()
+    e = st.energies()
+    assert e["KE"] == 0.0 and e["E_bond"] == 0.0 and e["W"] == 0.0
+    assert not host(st.counts).any()
+    assert hpf.hpf_get_device_status() == 0
+    del g
