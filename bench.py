@@ -33,6 +33,9 @@ def algorithmic_bytes(name: str, N: int, K: int, nm: int, D: int) -> float:
         # counts of the positions the fused pass deposited, written once (the partial
         # boxes between the two passes are this design's own traffic)
         "density_finish": 8.0 * K * nm,
+        # counts of the deposited positions read and cleared, V written (the partial boxes
+        # are this design's own traffic)
+        "finish_potential": 20.0 * K * nm,
         "field_potential": 20.0 * K * nm,            # counts read + cleared; V written
         "field_gradient": 20.0 * K * nm,             # V read; G written
         "force_gather": 33.0 * N + 16.0 * K * nm,    # R, T read; F written; G read once
@@ -89,9 +92,12 @@ def timed_step(st, hpf, engine, tm, sort):
 def timed_step_fused(st, hpf, engine, tm, sort):
     if sort:
         tm.wrap("sort_by_cell", st.sort)
-    tm.wrap("density_finish" if st.density_pending else "density_scatter", st.density)
-    tm.wrap("field_potential", hpf.hpf_field_potential, st.counts, st.mesh, st.field, st.V,
-            st.part[engine.ROW_W])
+    if st.density_pending:
+        tm.wrap("finish_potential", st.potential, True)
+    else:
+        tm.wrap("density_scatter", st.scatter)
+        tm.wrap("field_potential", hpf.hpf_field_potential, st.counts, st.mesh, st.field, st.V,
+                st.part[engine.ROW_W])
     tm.wrap("field_gradient", hpf.hpf_field_gradient, st.V, st.mesh, st.K, st.G)
     tm.wrap("advance", st.advance, True)
     tm.wrap("reduce", hpf.hpf_reduce_partials, st.part, engine.N_ROWS, st.energy)
@@ -226,9 +232,22 @@ ROCPROF_KERNELS = {
     "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum<false>",
                         "hpf::k_scatter_strays"],
     "density_finish": ["hpf::k_scatter_sum<true>"],
+    "finish_potential": ["hpf::k_finish_potential<%d>" % k for k in range(1, 9)],
     "field_potential": ["hpf::k_field_potential<%d>" % k for k in range(1, 9)],
     "field_gradient": ["hpf::k_field_gradient"],
 }
+
+
+def step_bandwidth(r, sort_every, ms_step):
+    """Algorithmic bytes of one whole step (every call once, the sort amortised over its
+    interval) over the measured step time, against the HBM peak."""
+    N, K, nm, D = r["N"], r["K"], r["nm"], r["D"]
+    b = sum(algorithmic_bytes(name, N, K, nm, D) for name in r["kernels"] if name != "sort_by_cell")
+    if sort_every > 0:
+        b += 150.0 * N / sort_every
+    gbs = b / (ms_step * 1e-3) / 1e9
+    return {"alg_bytes": b, "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "note": "all calls of a step; sort at its algorithmic 150 B/bead every sort_every steps"}
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -337,6 +356,7 @@ def main():
                      "algorithmic_bytes": dom_bytes,
                      "traffic": measured_traffic(r["spec"].name, dom)},
         "kernels": per_kernel,
+        "step_bandwidth": step_bandwidth(r, args.sort_every, ms_step),
         "device_flags": r["flags"],
     }
     if args.also and args.also != args.config:

@@ -332,6 +332,19 @@ hpf_status_t hpf_density_finish_cells(uint64_t* counts, int64_t N, const hpf_mes
                                       int32_t K, int32_t B, int32_t halo, const void* work,
                                       size_t work_bytes, void* stream);
 
+/* hpf_field_potential_cells -- hpf_density_finish_cells followed by
+ * hpf_field_potential in one pass over the mesh (eq. (4) with the counts of
+ * the positions hpf_advance_scatter deposited): each point's partial boxes
+ * are added to the counts it holds, the counts are cleared and V written.
+ * V is bitwise that of the two calls; w_part (nullable, double[HPF_NPART])
+ * receives the field-energy partials, grouped per workgroup, so their sum may
+ * differ from hpf_field_potential's in the last bits. N, mesh, B, halo and
+ * work as in hpf_advance_scatter; K = field->K. */
+hpf_status_t hpf_field_potential_cells(uint64_t* counts, int64_t N, const hpf_mesh_t* mesh,
+                                       const hpf_field_t* field, int32_t B, int32_t halo,
+                                       const void* work, size_t work_bytes, float* V,
+                                       double* w_part, void* stream);
+
 /* Deterministic FP64 reduction of partial-sum buffers: out[c] = sum of
  * part[c*HPF_NPART .. (c+1)*HPF_NPART) in a fixed tree order, c < ncomp.
  * part and out are device pointers; ncomp in [1, 8]. */

@@ -168,25 +168,52 @@ hpf_status_t hpf_density_scatter_cells(const float* R, const uint8_t* T, int64_t
                                 reinterpret_cast<unsigned long long*>(w + sb), as_stream(stream));
 }
 
+// Field coefficients A = kT chi, 1/kappa and the energy scale; false for non-finite input.
+static bool pot_params(const hpf_mesh_t* mesh, const hpf_field_t* field, PotK* p)
+{
+    const int K = field->K;
+    *p = PotK{};
+    for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b) {
+            const double c = field->chi[a * K + b];
+            if (!std::isfinite(c))
+                return false;
+            p->A[a * K + b] = field->kT * c;
+        }
+    if (!std::isfinite(field->kT) || !std::isfinite(field->inv_kappa))
+        return false;
+    p->inv_kappa = field->inv_kappa;
+    p->rho0_dV = mesh->c_norm > 0.0 ? 1.0 / (mesh->c_norm * 281474976710656.0) : 0.0;
+    return true;
+}
+
 hpf_status_t hpf_field_potential(uint64_t* counts, const hpf_mesh_t* mesh, const hpf_field_t* field,
                                  float* V, double* w_part, void* stream)
 {
     if (!counts || !V || !mesh_ok(mesh) || !field || field->K < 1 || field->K > HPF_MAX_TYPES)
         return HPF_EINVAL;
-    const int K = field->K;
-    PotK p{};
-    for (int a = 0; a < K; ++a)
-        for (int b = 0; b < K; ++b) {
-            const double c = field->chi[a * K + b];
-            if (!std::isfinite(c))
-                return HPF_EINVAL;
-            p.A[a * K + b] = field->kT * c;
-        }
-    if (!std::isfinite(field->kT) || !std::isfinite(field->inv_kappa))
+    PotK p;
+    if (!pot_params(mesh, field, &p))
         return HPF_EINVAL;
-    p.inv_kappa = field->inv_kappa;
-    p.rho0_dV = mesh->c_norm > 0.0 ? 1.0 / (mesh->c_norm * 281474976710656.0) : 0.0;
-    return launch_field_potential(counts, mesh_k(mesh), K, p, V, w_part, as_stream(stream));
+    return launch_field_potential(counts, mesh_k(mesh), field->K, p, V, w_part, as_stream(stream));
+}
+
+hpf_status_t hpf_field_potential_cells(uint64_t* counts, int64_t N, const hpf_mesh_t* mesh,
+                                       const hpf_field_t* field, int32_t B, int32_t halo, const void* work,
+                                       size_t work_bytes, float* V, double* w_part, void* stream)
+{
+    if (!counts || !V || !mesh_ok(mesh) || !field || field->K < 1 || field->K > HPF_MAX_TYPES)
+        return HPF_EINVAL;
+    TileK tk;
+    size_t sb = 0, tb = 0;
+    PotK p;
+    if (!scatter_cells_setup(N, mesh, field->K, B, halo, &tk, &sb, &tb) || !pot_params(mesh, field, &p))
+        return HPF_EINVAL;
+    if (!work || work_bytes < tb)
+        return HPF_ESPACE;
+    const char* w = static_cast<const char*>(work);
+    return launch_finish_potential(reinterpret_cast<const unsigned long long*>(w + sb), tk, field->K, p, counts, V,
+                                   w_part, as_stream(stream));
 }
 
 hpf_status_t hpf_field_gradient(const float* V, const hpf_mesh_t* mesh, int32_t K, float* G, void* stream)

@@ -81,6 +81,27 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks)
     return base + idx;
 }
 
+// Work split of a persistent grid over n items (bricks): the items are cut
+// into one contiguous run per XCD (workgroup b runs on XCD b % 8), and that
+// XCD's workgroups take the items of its run in turn, so the items in flight
+// at any moment are neighbours.
+struct BrickWalk {
+    int64_t end, first, stride;
+};
+
+__device__ __forceinline__ BrickWalk brick_walk(int64_t n)
+{
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t ng = nb < 8 ? nb : 8;
+    const int64_t g = b % ng, idx = b / ng;
+    const int64_t per_group = nb / ng + (g < nb % ng ? 1 : 0);
+    BrickWalk w;
+    w.first = n * g / ng + idx;
+    w.end = n * (g + 1) / ng;
+    w.stride = per_group;
+    return w;
+}
+
 // Fixed-order wave64 sum (butterfly), identical result in every lane.
 __device__ __forceinline__ double wave_sum(double v)
 {

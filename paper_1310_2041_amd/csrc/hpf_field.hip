@@ -2,6 +2,8 @@
 // counts, and its centred periodic gradient (Algorithm 1 Kernel 3, read as a
 // centred difference at the mesh point). Both are streaming, HBM-bound
 // passes over the mesh.
+#include <algorithm>
+
 #include "hpf_common.hpp"
 
 namespace hpf {
@@ -18,23 +20,19 @@ constexpr int kPotThreads = 256;
 // V_K = sum_K' A_KK' phi_K' + inv_kappa (sum phi - 1) stored as FP32, counts
 // cleared for the next scatter. Returns the point's field-energy term
 // (without the rho0 dV factor).
+// The same from counts n[K] already in registers (V written, nothing cleared).
 template <int K>
-__device__ __forceinline__ double potential_point(unsigned long long* __restrict__ counts,
-                                                  float* __restrict__ V, int64_t nm, int64_t q,
-                                                  double c_norm, const PotK& p, bool& over)
+__device__ __forceinline__ double potential_values(const unsigned long long (&n)[K], float* __restrict__ V,
+                                                   int64_t nm, int64_t q, double c_norm, const PotK& p, bool& over)
 {
     double phi[K];
     double tot = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const unsigned long long n = counts[k * nm + q];
-        over |= n >= (1ull << 62);
-        phi[k] = (double)n * c_norm;
+        over |= n[k] >= (1ull << 62);
+        phi[k] = (double)n[k] * c_norm;
         tot += phi[k];
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        counts[k * nm + q] = 0ull;
     const double delta = tot - 1.0;
     double inter = 0.0;
 #pragma unroll
@@ -47,6 +45,21 @@ __device__ __forceinline__ double potential_point(unsigned long long* __restrict
         inter += phi[k] * mix;
     }
     return 0.5 * inter + 0.5 * p.inv_kappa * delta * delta;
+}
+
+template <int K>
+__device__ __forceinline__ double potential_point(unsigned long long* __restrict__ counts,
+                                                  float* __restrict__ V, int64_t nm, int64_t q,
+                                                  double c_norm, const PotK& p, bool& over)
+{
+    unsigned long long n[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        n[k] = counts[k * nm + q];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        counts[k * nm + q] = 0ull;
+    return potential_values<K>(n, V, nm, q, c_norm, p, over);
 }
 
 // One thread per mesh point (grid-stride); optional FP64 field-energy partials.
@@ -97,6 +110,133 @@ hpf_status_t launch_field_potential(uint64_t* counts, const MeshK& m, int K, con
     default: return HPF_EINVAL;
     }
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+// The density finish fused with the potential: for each brick of points (a
+// persistent brick walk), the partial deposit boxes covering a point are
+// summed (as in the cell scatter's sum pass) and added to the counts already
+// held there (the beads that left their box), the counts are cleared, and V
+// and the field-energy term follow as in k_field_potential. V and the counts
+// it starts from are bitwise those of the finish + potential pair.
+constexpr int kFPThreads = 256;
+
+template <int K>
+__global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned long long* __restrict__ partials,
+                                                                 TileK tk, PotK p,
+                                                                 unsigned long long* __restrict__ counts,
+                                                                 float* __restrict__ V, double* __restrict__ w_part)
+{
+    __shared__ Cover cov[3][kTcMaxB];
+    __shared__ double scratch[kFPThreads / kWave];
+    const MeshK& m = tk.m;
+    const int64_t nm = m.nm;
+    if (w_part)                                    // slots beyond this grid read as zero
+        for (int64_t i = (int64_t)gridDim.x + blockIdx.x + (int64_t)threadIdx.x * gridDim.x; i < HPF_NPART;
+             i += (int64_t)kFPThreads * gridDim.x)
+            w_part[i] = 0.0;
+    const int tid = threadIdx.x;
+    const int B = tk.B, h = tk.h, P = tk.P, P3 = P * P * P;
+    const int Mx = m.M[0], My = m.M[1];
+    const BrickWalk w = brick_walk(tk.ntiles);
+    double wsum = 0.0;
+    bool over = false;
+    for (int64_t brick = w.first; brick < w.end; brick += w.stride) {
+        const int bxyz[3] = {(int)(brick % tk.nb[0]), (int)((brick / tk.nb[0]) % tk.nb[1]),
+                             (int)(brick / ((int64_t)tk.nb[0] * tk.nb[1]))};
+        int o[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            o[d] = min(B, m.M[d] - bxyz[d] * B);
+        __syncthreads();                              // the previous brick's cover lists are read
+        if (tid < 3 * B) {
+            const int d = tid / B, i = tid % B;
+            if (i < o[d])
+                cov[d][i] = covering(bxyz[d] * B + i, B, h, tk.nb[d], m.M[d]);
+        }
+        __syncthreads();
+        const int npts = o[0] * o[1] * o[2];
+        for (int e = tid; e < npts; e += kFPThreads) {
+            const int ix = e % o[0], r1 = e / o[0], iy = r1 % o[1], iz = r1 / o[1];
+            const Cover& cx = cov[0][ix];
+            const Cover& cy = cov[1][iy];
+            const Cover& cz = cov[2][iz];
+            const int64_t dst = ((int64_t)(bxyz[2] * B + iz) * My + (bxyz[1] * B + iy)) * Mx + bxyz[0] * B + ix;
+            unsigned long long n[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                n[k] = counts[(int64_t)k * nm + dst];
+            const int ncov = cx.n * cy.n * cz.n;
+            int64_t off[kSumFast];
+            int j = 0;
+            for (int a = 0; a < cz.n; ++a)
+                for (int b2 = 0; b2 < cy.n; ++b2) {
+                    const int64_t row = ((int64_t)cz.brick[a] * tk.nb[1] + cy.brick[b2]) * tk.nb[0];
+                    const int loc = (cz.local[a] * P + cy.local[b2]) * P;
+                    for (int c = 0; c < cx.n; ++c) {
+                        const int64_t o = (row + cx.brick[c]) * K * P3 + loc + cx.local[c];
+                        if (ncov <= kSumFast) {
+                            off[j++] = o;                 // the usual case: loads issued together below
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < K; ++k)
+                                n[k] += partials[o + (int64_t)k * P3];
+                        }
+                    }
+                }
+            if (ncov <= kSumFast) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    unsigned long long v[kSumFast];
+#pragma unroll
+                    for (int q = 0; q < kSumFast; ++q)
+                        v[q] = q < ncov ? partials[off[q] + (int64_t)k * P3] : 0ull;
+#pragma unroll
+                    for (int q = 0; q < kSumFast; ++q)
+                        n[k] += v[q];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                counts[(int64_t)k * nm + dst] = 0ull;
+            wsum += potential_values<K>(n, V, nm, dst, m.c_norm, p, over);
+        }
+    }
+    if (over)
+        raise_flag(HPF_FLAG_OVERFLOW);
+    if (w_part) {
+        const double s = block_sum(wsum, scratch);
+        if (threadIdx.x == 0)
+            w_part[blockIdx.x] = s * p.rho0_dV;
+    }
+}
+
+template <int K>
+static hpf_status_t launch_finish_potential_k(const unsigned long long* partials, const TileK& tk, const PotK& p,
+                                              unsigned long long* counts, float* V, double* w_part, hipStream_t s)
+{
+    // one brick per workgroup where the partial slots allow it (the dispatcher then
+    // balances uneven bricks), else bricks walked by HPF_NPART workgroups
+    const int64_t nb = std::min<int64_t>(tk.ntiles, HPF_NPART);
+    hipLaunchKernelGGL(k_finish_potential<K>, dim3((unsigned)nb), dim3(kFPThreads), 0, s, partials, tk, p, counts, V,
+                       w_part);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+hpf_status_t launch_finish_potential(const unsigned long long* partials, const TileK& tk, int K, const PotK& p,
+                                     uint64_t* counts, float* V, double* w_part, hipStream_t s)
+{
+    auto* c = reinterpret_cast<unsigned long long*>(counts);
+    switch (K) {
+    case 1: return launch_finish_potential_k<1>(partials, tk, p, c, V, w_part, s);
+    case 2: return launch_finish_potential_k<2>(partials, tk, p, c, V, w_part, s);
+    case 3: return launch_finish_potential_k<3>(partials, tk, p, c, V, w_part, s);
+    case 4: return launch_finish_potential_k<4>(partials, tk, p, c, V, w_part, s);
+    case 5: return launch_finish_potential_k<5>(partials, tk, p, c, V, w_part, s);
+    case 6: return launch_finish_potential_k<6>(partials, tk, p, c, V, w_part, s);
+    case 7: return launch_finish_potential_k<7>(partials, tk, p, c, V, w_part, s);
+    case 8: return launch_finish_potential_k<8>(partials, tk, p, c, V, w_part, s);
+    default: return HPF_EINVAL;
+    }
 }
 
 constexpr int kGradX = 64, kGradY = 4;

@@ -470,23 +470,6 @@ __global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict_
 // launch index.
 constexpr int kAThreads = 512;
 
-struct BrickWalk {
-    int64_t end, first, stride;
-};
-
-__device__ __forceinline__ BrickWalk brick_walk(int64_t n)
-{
-    const int64_t nb = gridDim.x, b = blockIdx.x;
-    const int64_t ng = nb < 8 ? nb : 8;
-    const int64_t g = b % ng, idx = b / ng;
-    const int64_t per_group = nb / ng + (g < nb % ng ? 1 : 0);
-    BrickWalk w;
-    w.first = n * g / ng + idx;
-    w.end = n * (g + 1) / ng;
-    w.stride = per_group;
-    return w;
-}
-
 template <bool kR0Zero>
 __global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __restrict__ R,
                                                              float4* __restrict__ R_next,

@@ -163,24 +163,24 @@ class HpfState:
         Bitwise equal to step() followed by the next step's first half step."""
         if sort:
             self.sort(stream)
-        self.density(stream)
-        hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V,
-                                self.part[ROW_W] if report else None, stream)
+        self.potential(report, stream)
         hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
         self.advance(report, stream)
         if report:
             hpf.hpf_reduce_partials(self.part, N_ROWS, self.energy, stream)
         self.steps_done += 1
 
-    def density(self, stream=None):
-        """Counts of the current positions: finish the deposit the last fused pass made, or
-        scatter from scratch."""
+    def potential(self, report=False, stream=None):
+        """Counts and potential of the current positions: finish the deposit the last fused
+        pass made and form V in one pass, or scatter from scratch and then form V."""
+        w = self.part[ROW_W] if report else None
         if self.density_pending:
-            hpf.hpf_density_finish_cells(self.counts, self.N, self.mesh, self.K, self.B, self.halo,
-                                         self.scatter_work, stream)
+            hpf.hpf_field_potential_cells(self.counts, self.N, self.mesh, self.field, self.B, self.halo,
+                                          self.scatter_work, self.V, w, stream)
             self.density_pending = False
         else:
             self.scatter(stream)
+            hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V, w, stream)
 
     def uses_cells_advance(self) -> bool:
         return (self.advance_mode == "cells" and self.sorted and

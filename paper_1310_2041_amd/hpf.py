@@ -100,6 +100,8 @@ _SIGNATURES = {
                              C.c_size_t, _P, _P, _P, _P], C.c_int32),
     "hpf_density_finish_cells": ([_P, C.c_int64, C.POINTER(Mesh), C.c_int32, C.c_int32, C.c_int32,
                                   _P, C.c_size_t, _P], C.c_int32),
+    "hpf_field_potential_cells": ([_P, C.c_int64, C.POINTER(Mesh), C.POINTER(Field), C.c_int32, C.c_int32,
+                                   _P, C.c_size_t, _P, _P, _P], C.c_int32),
     "hpf_sort_workspace_bytes": ([C.c_int64, C.POINTER(Mesh), C.c_int32], C.c_size_t),
     "hpf_sort_by_cell": ([C.POINTER(Mesh), C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
                           _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int32),
@@ -385,6 +387,20 @@ def hpf_density_finish_cells(counts, N: int, mesh: Mesh, K: int, B: int, halo: i
     _check("hpf_density_finish_cells",
            lib().hpf_density_finish_cells(c, int(N), C.byref(mesh), int(K), int(B), int(halo), w,
                                           work.numel(), _stream(stream)))
+
+
+def hpf_field_potential_cells(counts, N: int, mesh: Mesh, field: Field, B: int, halo: int, work, V,
+                              w_part=None, stream=None):
+    K = field.K
+    c = _dev(counts, "counts", torch.int64, (K, _nm(mesh)))
+    w = _dev(work, "work", torch.uint8)
+    v = _dev(V, "V", torch.float32, (K, _nm(mesh)))
+    wp = _dev(w_part, "w_part", torch.float64, None, allow_none=True)
+    if w_part is not None and w_part.numel() < HPF_NPART:
+        raise ValueError("w_part needs HPF_NPART slots")
+    _check("hpf_field_potential_cells",
+           lib().hpf_field_potential_cells(c, int(N), C.byref(mesh), C.byref(field), int(B), int(halo), w,
+                                           work.numel(), v, wp, _stream(stream)))
 
 
 def advance_cells_fits(K: int, B: int = 8, halo: int = 1) -> bool:

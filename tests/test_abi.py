@@ -119,6 +119,14 @@ def test_invalid_arguments_rejected_on_host(hpf):
     assert advs(work=None) == -3
     assert L.hpf_density_finish_cells(None, 10, C.byref(m16), 2, 8, 1, wk, need, None) == EINVAL
     assert L.hpf_density_finish_cells(cnt, 10, C.byref(m16), 2, 8, 1, wk, need - 1, None) == -3
+    f2 = hpf.make_field(2, 1.0, 10.0, [[0.0, 1.0], [1.0, 0.0]])
+    vv = C.c_void_p(0x30000)
+    assert L.hpf_field_potential_cells(None, 10, C.byref(m16), C.byref(f2), 8, 1, wk, need, vv, None,
+                                       None) == EINVAL
+    assert L.hpf_field_potential_cells(cnt, 10, C.byref(m), C.byref(f2), 8, 1, wk, need, vv, None,
+                                       None) == EINVAL                 # mesh too small for the boxes
+    assert L.hpf_field_potential_cells(cnt, 10, C.byref(m16), C.byref(f2), 8, 1, wk, need - 1, vv, None,
+                                       None) == -3
 
 
 def test_sort_workspace_size(hpf):
