@@ -295,7 +295,7 @@ def main():
     ap.add_argument("--sort-every", type=int, default=20)
     ap.add_argument("--mode", default="fused", choices=["fused", "api"],
                     help="fused: hpf_advance; api: the six separate calls")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batched sweep")
     ap.add_argument("--halo", type=int, default=2, help="drift halo (cells) of the brick deposit boxes")
