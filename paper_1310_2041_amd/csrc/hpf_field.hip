@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned 
              i += (int64_t)kFPThreads * gridDim.x)
             w_part[i] = 0.0;
     const int tid = threadIdx.x;
-    const int B = tk.B, h = tk.h, P = tk.P, P3 = P * P * P;
+    const int B = tk.B, P = tk.P, P3 = P * P * P;
     const int Mx = m.M[0], My = m.M[1];
     const BrickWalk w = brick_walk(tk.ntiles);
     double wsum = 0.0;
@@ -148,15 +148,11 @@ __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned 
         for (int d = 0; d < 3; ++d)
             o[d] = min(B, m.M[d] - bxyz[d] * B);
         __syncthreads();                              // the previous brick's cover lists are read
-        if (tid < 3 * B) {
-            const int d = tid / B, i = tid % B;
-            if (i < o[d])
-                cov[d][i] = covering(bxyz[d] * B + i, B, h, tk.nb[d], m.M[d]);
-        }
-        __syncthreads();
+        brick_covers(cov, tk, K, bxyz, o);
         const int npts = o[0] * o[1] * o[2];
         for (int e = tid; e < npts; e += kFPThreads) {
-            const int ix = e % o[0], r1 = e / o[0], iy = r1 % o[1], iz = r1 / o[1];
+            int ix, iy, iz;
+            brick_point(e, o, B, ix, iy, iz);
             const Cover& cx = cov[0][ix];
             const Cover& cy = cov[1][iy];
             const Cover& cz = cov[2][iz];
@@ -166,24 +162,15 @@ __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned 
             for (int k = 0; k < K; ++k)
                 n[k] = counts[(int64_t)k * nm + dst];
             const int ncov = cx.n * cy.n * cz.n;
-            int64_t off[kSumFast];
-            int j = 0;
-            for (int a = 0; a < cz.n; ++a)
-                for (int b2 = 0; b2 < cy.n; ++b2) {
-                    const int64_t row = ((int64_t)cz.brick[a] * tk.nb[1] + cy.brick[b2]) * tk.nb[0];
-                    const int loc = (cz.local[a] * P + cy.local[b2]) * P;
-                    for (int c = 0; c < cx.n; ++c) {
-                        const int64_t o = (row + cx.brick[c]) * K * P3 + loc + cx.local[c];
-                        if (ncov <= kSumFast) {
-                            off[j++] = o;                 // the usual case: loads issued together below
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < K; ++k)
-                                n[k] += partials[o + (int64_t)k * P3];
-                        }
-                    }
-                }
             if (ncov <= kSumFast) {
+                int64_t off[kSumFast];
+                int j = 0;
+                for (int a = 0; a < cz.n; ++a)
+                    for (int b2 = 0; b2 < cy.n; ++b2) {
+                        const int64_t zy = cz.off[a] + cy.off[b2];
+                        for (int c = 0; c < cx.n; ++c)
+                            off[j++] = zy + cx.off[c];
+                    }
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     unsigned long long v[kSumFast];
@@ -194,6 +181,14 @@ __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned 
                     for (int q = 0; q < kSumFast; ++q)
                         n[k] += v[q];
                 }
+            } else {
+                for (int a = 0; a < cz.n; ++a)
+                    for (int b2 = 0; b2 < cy.n; ++b2)
+                        for (int c = 0; c < cx.n; ++c) {
+#pragma unroll
+                            for (int k = 0; k < K; ++k)
+                                n[k] += partials[cz.off[a] + cy.off[b2] + cx.off[c] + (int64_t)k * P3];
+                        }
             }
 #pragma unroll
             for (int k = 0; k < K; ++k)

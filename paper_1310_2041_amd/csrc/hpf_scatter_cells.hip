@@ -207,6 +207,7 @@ struct Cover {
     int n;
     int brick[5];
     int local[5];
+    int64_t off[5];     // brick * (brick stride) + local * (point stride) along this axis
 };
 
 __device__ __forceinline__ Cover covering(int v, int B, int h, int nb, int M)
@@ -243,6 +244,46 @@ __device__ __forceinline__ Cover covering(int v, int B, int h, int nb, int M)
 
 constexpr int kSumFast = 8;       // covering boxes of a point summed with all loads in flight
 
+// Cover lists of one brick's coordinates along each axis, with the offsets of
+// the covering boxes' entries precomputed per axis (the offset of an entry in
+// the partial buffer is the sum of its three axis terms), so that a point's
+// covering entries cost three additions each. Call with all threads; ends
+// with a barrier.
+__device__ __forceinline__ void brick_covers(Cover (&cov)[3][kTcMaxB], const TileK& tk, int K, const int bxyz[3],
+                                             const int o[3])
+{
+    const int B = tk.B, h = tk.h, P = tk.P;
+    const int64_t P3K = (int64_t)K * P * P * P;
+    const int tid = threadIdx.x;
+    if (tid < 3 * B) {
+        const int d = tid / B, i = tid % B;
+        if (i < o[d]) {
+            Cover c = covering(bxyz[d] * B + i, B, h, tk.nb[d], tk.m.M[d]);
+            const int64_t bstride = d == 0 ? P3K : d == 1 ? tk.nb[0] * P3K : (int64_t)tk.nb[0] * tk.nb[1] * P3K;
+            const int lstride = d == 0 ? 1 : d == 1 ? P : P * P;
+            for (int j = 0; j < c.n; ++j)
+                c.off[j] = c.brick[j] * bstride + (int64_t)c.local[j] * lstride;
+            cov[d][i] = c;
+        }
+    }
+    __syncthreads();
+}
+
+// Local coordinates of point e of a brick of o[0] x o[1] x o[2] points (x fastest).
+__device__ __forceinline__ void brick_point(int e, const int o[3], int B, int& ix, int& iy, int& iz)
+{
+    if (B == 8 && o[0] == 8 && o[1] == 8) {
+        ix = e & 7;
+        iy = (e >> 3) & 7;
+        iz = e >> 6;
+    } else {
+        ix = e % o[0];
+        const int r1 = e / o[0];
+        iy = r1 % o[1];
+        iz = r1 / o[1];
+    }
+}
+
 // One workgroup per brick: the cover lists of the brick's coordinates along
 // each axis are built once in LDS, then each thread sums the partial boxes for
 // its points (consecutive threads -> consecutive x -> coalesced reads).
@@ -253,40 +294,34 @@ __device__ __forceinline__ void scatter_sum_body(const unsigned long long* __res
                                                  unsigned long long* __restrict__ counts)
 {
     __shared__ Cover cov[3][kTcMaxB];
-    const int tid = threadIdx.x;
-    const int B = tk.B, h = tk.h, P = tk.P, P3 = P * P * P;
+    const int B = tk.B, P = tk.P, P3 = P * P * P;
     const int bxyz[3] = {(int)(brick % tk.nb[0]), (int)((brick / tk.nb[0]) % tk.nb[1]),
                          (int)(brick / ((int64_t)tk.nb[0] * tk.nb[1]))};
     int o[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
         o[d] = min(B, tk.m.M[d] - bxyz[d] * B);
-    if (tid < 3 * B) {
-        const int d = tid / B, i = tid % B;
-        if (i < o[d])
-            cov[d][i] = covering(bxyz[d] * B + i, B, h, tk.nb[d], tk.m.M[d]);
-    }
-    __syncthreads();
+    brick_covers(cov, tk, K, bxyz, o);
     const int npts = o[0] * o[1] * o[2];
     const int Mx = tk.m.M[0], My = tk.m.M[1];
-    for (int e = tid; e < npts; e += (int)blockDim.x) {
-        const int ix = e % o[0], r1 = e / o[0], iy = r1 % o[1], iz = r1 / o[1];
+    for (int e = threadIdx.x; e < npts; e += (int)blockDim.x) {
+        int ix, iy, iz;
+        brick_point(e, o, B, ix, iy, iz);
         const Cover& cx = cov[0][ix];
         const Cover& cy = cov[1][iy];
         const Cover& cz = cov[2][iz];
         const int64_t dst = ((int64_t)(bxyz[2] * B + iz) * My + (bxyz[1] * B + iy)) * Mx + bxyz[0] * B + ix;
         const int ncov = cx.n * cy.n * cz.n;
         if (ncov <= kSumFast) {
-            // the usual case (at most two boxes per axis): all box offsets first, then
+            // the usual case (at most two boxes per axis): all entry offsets first, then
             // every load of the point issued together
             int64_t off[kSumFast];
             int j = 0;
             for (int a = 0; a < cz.n; ++a)
                 for (int b2 = 0; b2 < cy.n; ++b2) {
-                    const int64_t row = ((int64_t)cz.brick[a] * tk.nb[1] + cy.brick[b2]) * tk.nb[0];
-                    const int loc = (cz.local[a] * P + cy.local[b2]) * P;
+                    const int64_t zy = cz.off[a] + cy.off[b2];
                     for (int c = 0; c < cx.n; ++c)
-                        off[j++] = (row + cx.brick[c]) * K * P3 + loc + cx.local[c];
+                        off[j++] = zy + cx.off[c];
                 }
             for (int k = 0; k < K; ++k) {
                 unsigned long long v[kSumFast];
@@ -307,12 +342,9 @@ __device__ __forceinline__ void scatter_sum_body(const unsigned long long* __res
         for (int k = 0; k < K; ++k) {
             unsigned long long sum = 0;
             for (int a = 0; a < cz.n; ++a)
-                for (int b2 = 0; b2 < cy.n; ++b2) {
-                    const int64_t row = ((int64_t)cz.brick[a] * tk.nb[1] + cy.brick[b2]) * tk.nb[0];
-                    const int loc = (cz.local[a] * P + cy.local[b2]) * P;
+                for (int b2 = 0; b2 < cy.n; ++b2)
                     for (int c = 0; c < cx.n; ++c)
-                        sum += partials[((row + cx.brick[c]) * K + k) * P3 + loc + cx.local[c]];
-                }
+                        sum += partials[cz.off[a] + cy.off[b2] + cx.off[c] + (int64_t)k * P3];
             if (kAdd)
                 counts[(int64_t)k * tk.m.nm + dst] += sum;
             else
