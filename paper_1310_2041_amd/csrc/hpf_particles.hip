@@ -775,12 +775,9 @@ static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float
     if (smem > 65536 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
         return HPF_EINVAL;
-    int64_t nb = resident_blocks(fn, kThreads, smem);
-    if (nb < 1)
-        nb = 1024;
-    nb = std::min<int64_t>(nb, tk.ntiles + 1);
-    if ((e_part || kin_part) && nb > HPF_NPART)
-        nb = HPF_NPART;
+    // one brick per workgroup where the partial slots allow it, so the dispatcher balances
+    // uneven bricks; larger meshes walk their bricks with HPF_NPART workgroups
+    const int64_t nb = std::min<int64_t>(tk.ntiles + 1, HPF_NPART);
     const dim3 g((unsigned)nb), bl(kThreads);
     if (r0 == 0.0f)
         hipLaunchKernelGGL((k_advance_scatter<true, kThreads>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D,
