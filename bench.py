@@ -246,8 +246,17 @@ def step_bandwidth(r, sort_every, ms_step):
     if sort_every > 0:
         b += 150.0 * N / sort_every
     gbs = b / (ms_step * 1e-3) / 1e9
+    # the least any two-pass design must move per step: x, T read by the deposit (13 B), x, v,
+    # T read and x, v written by the force + integration pass (49 B), the bond-partner slots
+    # (8 B); per mesh point and species the counts written, read and cleared (24 B) and V
+    # written and read (8 B)
+    b_min = 70.0 * N + 32.0 * K * nm
+    gmin = b_min / (ms_step * 1e-3) / 1e9
     return {"alg_bytes": b, "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "note": "all calls of a step; sort at its algorithmic 150 B/bead every sort_every steps"}
+            "minimal_bytes": b_min, "minimal_achieved": round(gmin, 1),
+            "minimal_frac": round(gmin / HBM_PEAK_GBS, 4),
+            "note": "all calls of a step (sort at its algorithmic 150 B/bead every sort_every steps); "
+                    "minimal = 70 N + 32 K M^3, the bytes of a two-pass step"}
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -288,8 +297,8 @@ def cpu_baseline(cfg, n_steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--also", default="c2", help="second workload reported under 'also' ('' = none)")
     ap.add_argument("--sort-every", type=int, default=20)
