@@ -161,26 +161,11 @@ __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned 
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 n[k] = counts[(int64_t)k * nm + dst];
-            const int ncov = cx.n * cy.n * cz.n;
-            if (ncov <= kSumFast) {
-                int64_t off[kSumFast];
-                int j = 0;
-                for (int a = 0; a < cz.n; ++a)
-                    for (int b2 = 0; b2 < cy.n; ++b2) {
-                        const int64_t zy = cz.off[a] + cy.off[b2];
-                        for (int c = 0; c < cx.n; ++c)
-                            off[j++] = zy + cx.off[c];
-                    }
+            if (cover2_ok(cx, cy, cz)) {
+                const Cover2 c2 = cover2(cx, cy, cz);
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    unsigned long long v[kSumFast];
-#pragma unroll
-                    for (int q = 0; q < kSumFast; ++q)
-                        v[q] = q < ncov ? partials[off[q] + (int64_t)k * P3] : 0ull;
-#pragma unroll
-                    for (int q = 0; q < kSumFast; ++q)
-                        n[k] += v[q];
-                }
+                for (int k = 0; k < K; ++k)
+                    n[k] += cover2_sum(partials, c2, (int64_t)k * P3);
             } else {
                 for (int a = 0; a < cz.n; ++a)
                     for (int b2 = 0; b2 < cy.n; ++b2)

@@ -205,44 +205,92 @@ __global__ __launch_bounds__(kTcThreads) void k_scatter_bricks(const float4* __r
 // only next to the periodic seam when the last brick is narrower than h.
 struct Cover {
     int n;
-    int brick[5];
-    int local[5];
     int64_t off[5];     // brick * (brick stride) + local * (point stride) along this axis
 };
 
-__device__ __forceinline__ Cover covering(int v, int B, int h, int nb, int M)
+// Writes into c (in LDS) the boxes that cover coordinate v along one axis. A
+// brick reached twice through the periodic wrap (fewer than five bricks on the
+// axis) is listed once. Brick numbers are kept in registers (constant indices
+// only), so nothing of this goes to scratch memory.
+__device__ __forceinline__ void covering(Cover& c, int v, int B, int h, int nb, int M, int64_t bstride,
+                                         int lstride)
 {
-    Cover c;
-    c.n = 0;
+    int n = 0;
+    int seen[5];
     const int b0 = v / B;
 #pragma unroll
-    for (int db = -2; db <= 2; ++db) {
-        int b = b0 + db;
+    for (int q = 0; q < 5; ++q) {
+        int b = b0 + q - 2;
         if (b < 0)
             b += nb;
         else if (b >= nb)
             b -= nb;
-        if (b < 0 || b >= nb)
-            continue;                       // fewer than 3 bricks on this axis
+        bool ok = b >= 0 && b < nb;         // fewer than 3 bricks on this axis
+        seen[q] = ok ? b : -1 - q;
+#pragma unroll
+        for (int r = 0; r < q; ++r)
+            ok &= seen[r] != b;
         const int ob = min(B, M - b * B);
         int l = v - (b * B - h);
         if (l < 0)
             l += M;
         else if (l >= M)
             l -= M;
-        bool dup = false;
-        for (int i = 0; i < c.n; ++i)
-            dup |= c.brick[i] == b;
-        if (!dup && l <= ob + 2 * h) {
-            c.brick[c.n] = b;
-            c.local[c.n] = l;
-            ++c.n;
+        if (ok && l <= ob + 2 * h) {
+            c.off[n] = b * bstride + (int64_t)l * lstride;
+            ++n;
         }
+    }
+    c.n = n;
+}
+
+// The entries that cover one point when no axis has more than two covering
+// boxes (the usual case): the eight offsets and which of them exist. Built and
+// read with constant indices only, so it stays in registers.
+struct Cover2 {
+    int64_t e[8];
+    bool use[8];
+};
+
+__device__ __forceinline__ bool cover2_ok(const Cover& cx, const Cover& cy, const Cover& cz)
+{
+    return cx.n <= 2 && cy.n <= 2 && cz.n <= 2;
+}
+
+__device__ __forceinline__ Cover2 cover2(const Cover& cx, const Cover& cy, const Cover& cz)
+{
+    const bool hx = cx.n > 1, hy = cy.n > 1, hz = cz.n > 1;
+    const int64_t x[2] = {cx.off[0], hx ? cx.off[1] : cx.off[0]};
+    const int64_t y[2] = {cy.off[0], hy ? cy.off[1] : cy.off[0]};
+    const int64_t z[2] = {cz.off[0], hz ? cz.off[1] : cz.off[0]};
+    Cover2 c;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int a = q >> 2, b = (q >> 1) & 1, d = q & 1;
+        c.e[q] = z[a] + y[b] + x[d];
+        c.use[q] = (a == 0 || hz) && (b == 0 || hy) && (d == 0 || hx);
     }
     return c;
 }
 
-constexpr int kSumFast = 8;       // covering boxes of a point summed with all loads in flight
+// Sum of the covering entries of species block kb (= k * P^3); every load of
+// the point is issued before the additions.
+__device__ __forceinline__ unsigned long long cover2_sum(const unsigned long long* __restrict__ partials,
+                                                         const Cover2& c, int64_t kb)
+{
+    unsigned long long v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        v[q] = c.use[q] ? partials[c.e[q] + kb] : 0ull;
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        sum += v[q];
+    return sum;
+}
+
+// One of three values by axis, selected as values (the arguments are copies).
+__device__ __forceinline__ int pick3(int d, int a, int b, int c) { return d == 0 ? a : d == 1 ? b : c; }
 
 // Cover lists of one brick's coordinates along each axis, with the offsets of
 // the covering boxes' entries precomputed per axis (the offset of an entry in
@@ -256,14 +304,18 @@ __device__ __forceinline__ void brick_covers(Cover (&cov)[3][kTcMaxB], const Til
     const int64_t P3K = (int64_t)K * P * P * P;
     const int tid = threadIdx.x;
     if (tid < 3 * B) {
+        // the axis is chosen among values: a run-time index into the per-axis arrays
+        // (or a conditional over them, which selects an address) would place them in
+        // scratch memory
         const int d = tid / B, i = tid % B;
-        if (i < o[d]) {
-            Cover c = covering(bxyz[d] * B + i, B, h, tk.nb[d], tk.m.M[d]);
+        const int od = pick3(d, o[0], o[1], o[2]);
+        if (i < od) {
+            const int bd = pick3(d, bxyz[0], bxyz[1], bxyz[2]);
+            const int nbd = pick3(d, tk.nb[0], tk.nb[1], tk.nb[2]);
+            const int Md = pick3(d, tk.m.M[0], tk.m.M[1], tk.m.M[2]);
             const int64_t bstride = d == 0 ? P3K : d == 1 ? tk.nb[0] * P3K : (int64_t)tk.nb[0] * tk.nb[1] * P3K;
-            const int lstride = d == 0 ? 1 : d == 1 ? P : P * P;
-            for (int j = 0; j < c.n; ++j)
-                c.off[j] = c.brick[j] * bstride + (int64_t)c.local[j] * lstride;
-            cov[d][i] = c;
+            const int lstride = pick3(d, 1, P, P * P);
+            covering(cov[d][i], bd * B + i, B, h, nbd, Md, bstride, lstride);
         }
     }
     __syncthreads();
@@ -311,27 +363,10 @@ __device__ __forceinline__ void scatter_sum_body(const unsigned long long* __res
         const Cover& cy = cov[1][iy];
         const Cover& cz = cov[2][iz];
         const int64_t dst = ((int64_t)(bxyz[2] * B + iz) * My + (bxyz[1] * B + iy)) * Mx + bxyz[0] * B + ix;
-        const int ncov = cx.n * cy.n * cz.n;
-        if (ncov <= kSumFast) {
-            // the usual case (at most two boxes per axis): all entry offsets first, then
-            // every load of the point issued together
-            int64_t off[kSumFast];
-            int j = 0;
-            for (int a = 0; a < cz.n; ++a)
-                for (int b2 = 0; b2 < cy.n; ++b2) {
-                    const int64_t zy = cz.off[a] + cy.off[b2];
-                    for (int c = 0; c < cx.n; ++c)
-                        off[j++] = zy + cx.off[c];
-                }
+        if (cover2_ok(cx, cy, cz)) {
+            const Cover2 c2 = cover2(cx, cy, cz);
             for (int k = 0; k < K; ++k) {
-                unsigned long long v[kSumFast];
-#pragma unroll
-                for (int q = 0; q < kSumFast; ++q)
-                    v[q] = q < ncov ? partials[off[q] + (int64_t)k * P3] : 0ull;
-                unsigned long long sum = 0;
-#pragma unroll
-                for (int q = 0; q < kSumFast; ++q)
-                    sum += v[q];
+                const unsigned long long sum = cover2_sum(partials, c2, (int64_t)k * P3);
                 if (kAdd)
                     counts[(int64_t)k * tk.m.nm + dst] += sum;
                 else

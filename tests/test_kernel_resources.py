@@ -1,0 +1,69 @@
+"""CPU: no kernel of the built library uses scratch memory or spills VGPRs to it.
+
+Private (scratch) memory in these kernels has come from local arrays indexed
+at run time; every lane then writes them to memory, which once cost the batch
+box sum several times its useful HBM writes. The check reads the kernel
+descriptors of the gfx950 code object embedded in libhpf.so (built here from
+source) with the ROCm LLVM tools; it needs no GPU. (SGPR spills go to VGPR
+lanes, not to memory, and are not checked.)
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1310_2041_amd", "libhpf.so")
+LLVM = "/opt/rocm/llvm/bin"
+TARGET = "hipv4-amdgcn-amd-amdhsa--gfx950"
+
+
+def _tool(name):
+    p = os.path.join(LLVM, name)
+    return p if os.path.exists(p) else shutil.which(name)
+
+
+def kernel_metadata(tmp_path):
+    """{kernel symbol: {field: int}} from the code object's metadata note."""
+    objcopy, bundler, readelf = (_tool(t) for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-readelf"))
+    if not (objcopy and bundler and readelf):
+        pytest.skip("ROCm LLVM tools not found")
+    if not os.path.exists(LIB):
+        pytest.skip("libhpf.so not built")
+    fat, co = str(tmp_path / "fat.bin"), str(tmp_path / "dev.co")
+    subprocess.run([objcopy, "--dump-section", f".hip_fatbin={fat}", LIB, str(tmp_path / "copy.so")],
+                   check=True, capture_output=True)
+    subprocess.run([bundler, "--unbundle", "--type=o", f"--targets={TARGET}", f"--input={fat}",
+                    f"--output={co}"], check=True, capture_output=True)
+    notes = subprocess.run([readelf, "--notes", co], check=True, capture_output=True, text=True).stdout
+    out, cur = {}, None
+    for line in notes.splitlines():
+        m = re.match(r"\s*\.name:\s+(\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        m = re.match(r"\s*\.(private_segment_fixed_size|vgpr_spill_count|sgpr_spill_count|vgpr_count):\s+(\d+)",
+                     line)
+        if m and cur is not None:
+            cur[m.group(1)] = int(m.group(2))
+    return out
+
+
+def test_no_kernel_uses_scratch_or_spills(tmp_path):
+    md = kernel_metadata(tmp_path)
+    kernels = {k: v for k, v in md.items() if k.startswith("_ZN3hpf")}
+    assert len(kernels) > 30, "kernel metadata not found"
+    bad = {k: v for k, v in kernels.items()
+           if v.get("private_segment_fixed_size", 0) or v.get("vgpr_spill_count", 0)}
+    assert not bad, bad
+
+
+def test_fused_pass_register_budget(tmp_path):
+    """The fused advance + deposit runs at 4 waves per SIMD (at most 128 VGPRs)."""
+    md = kernel_metadata(tmp_path)
+    fused = {k: v for k, v in md.items() if "k_advance_scatter" in k}
+    assert fused
+    for k, v in fused.items():
+        assert v["vgpr_count"] <= 128, (k, v)
