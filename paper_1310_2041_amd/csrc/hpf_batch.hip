@@ -174,6 +174,39 @@ __global__ __launch_bounds__(kPotThreads) void k_batch_potential(const RepK* __r
     }
 }
 
+// The finish of the fused deposit and the potential in one pass, one
+// workgroup per brick item: the covering boxes are summed onto the counts held
+// at each point (the strays), V follows and the counts are cleared; the
+// workgroup's field-energy term goes to slot li.
+template <int K>
+__global__ __launch_bounds__(kFPThreads) void k_batch_finish_potential(const RepK* __restrict__ reps,
+                                                                       const ItemK* __restrict__ items, int B,
+                                                                       int h,
+                                                                       const unsigned long long* __restrict__ partials,
+                                                                       unsigned long long* __restrict__ counts,
+                                                                       float* __restrict__ V,
+                                                                       double* __restrict__ w_part)
+{
+    __shared__ Cover cov[3][kTcMaxB];
+    __shared__ double scratch[kFPThreads / kWave];
+    const int64_t li = xcd_block(blockIdx.x, gridDim.x);
+    const ItemK it = items[li];
+    const RepK& rp = reps[it.rep];
+    const TileK tk = tile_of(rp, B, h);
+    const int P = tk.P;
+    bool over = false;
+    const double wsum = finish_potential_brick<K>(cov, partials + rp.brick_off * (int64_t)K * P * P * P, tk, rp.p,
+                                                  counts + (int64_t)K * rp.moff, V + (int64_t)K * rp.moff,
+                                                  it.begin, over);
+    if (over)
+        raise_flag(HPF_FLAG_OVERFLOW);
+    if (w_part) {
+        const double s = block_sum(wsum, scratch);
+        if (threadIdx.x == 0)
+            w_part[li] = s * rp.p.rho0_dV;
+    }
+}
+
 // one workgroup per (replica, z plane)
 __global__ __launch_bounds__(256) void k_batch_gradient(const RepK* __restrict__ reps,
                                                         const ItemK* __restrict__ items, int K,
@@ -424,7 +457,7 @@ struct BatchLayout {
     int64_t max_bead_items = 0, max_mesh_items = 0, max_planes = 0;
     int64_t nslot = 0;                   // energy partial slots (one per bead or fused item)
     size_t off_reps, off_bead_items, off_brick_items, off_adv_items, off_mesh_items, off_plane_items, off_bead_ioff,
-        off_adv_ioff, off_mesh_ioff, off_sort, off_start, off_strays, off_partials, off_wpart, off_epart, off_kpart, off_energy,
+        off_adv_ioff, off_mesh_ioff, off_brick_ioff, off_sort, off_start, off_strays, off_partials, off_wpart, off_epart, off_kpart, off_energy,
         total;
     SortPlan sort;
 };
@@ -476,11 +509,12 @@ static bool batch_layout(const hpf_replica_t* reps, int nrep, const hpf_batch_co
     L->off_bead_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
     L->off_adv_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
     L->off_mesh_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
+    L->off_brick_ioff = o; o += al256(sizeof(int64_t) * (nrep + 1));
     L->off_sort = o; o += al256(L->sort.bytes);
     L->off_start = o; o += al256(sizeof(uint32_t) * (nscan + 1));
     L->off_strays = o; o += al256(sizeof(uint32_t) * (N1 + 64));
     L->off_partials = o; o += al256(sizeof(unsigned long long) * L->bricks_tot * cfg->K * Pmax * Pmax * Pmax);
-    L->off_wpart = o; o += al256(sizeof(double) * (L->max_mesh_items + 1));
+    L->off_wpart = o; o += al256(sizeof(double) * (std::max(L->max_mesh_items, L->bricks_tot) + 1));
     L->nslot = std::max<int64_t>(L->max_bead_items, L->bricks_tot + nrep) + 1;
     L->off_epart = o; o += al256(sizeof(double) * L->nslot);
     L->off_kpart = o; o += al256(sizeof(double) * 4 * L->nslot);
@@ -504,6 +538,7 @@ struct hpf_batch {
     int64_t steps_done = 0;
     int64_t n_bead_items = 0, n_brick_items = 0, n_adv_items = 0, n_mesh_items = 0, n_planes = 0;
     bool pending = false;  // partial boxes + counts hold the deposit of the current positions
+    bool w_bricks = false; // the last field pass left its W partials per brick item (else per mesh item)
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(work + off); }
 };
 
@@ -513,7 +548,8 @@ static hpf_status_t batch_build_items(hpf_batch* b)
 {
     const hpf_batch_config_t& c = b->cfg;
     std::vector<ItemK> bead, brick, adv, mesh, plane;
-    std::vector<int64_t> bead_off(b->nrep + 1), adv_off(b->nrep + 1), mesh_off(b->nrep + 1);
+    std::vector<int64_t> bead_off(b->nrep + 1), adv_off(b->nrep + 1), mesh_off(b->nrep + 1),
+        brick_off(b->nrep + 1);
     for (int r = 0; r < b->nrep; ++r) {
         const RepK& rp = b->reps[r];
         bead_off[r] = (int64_t)bead.size();
@@ -522,6 +558,7 @@ static hpf_status_t batch_build_items(hpf_batch* b)
         mesh_off[r] = (int64_t)mesh.size();
         for (int64_t s = 0; s < rp.m.nm; s += c.mesh_chunk)
             mesh.push_back({r, 0, s, std::min<int64_t>(rp.m.nm, s + c.mesh_chunk)});
+        brick_off[r] = (int64_t)brick.size();
         for (int64_t k = 0; k < rp.nbricks; ++k)
             brick.push_back({r, 0, k, k + 1});
         adv_off[r] = (int64_t)adv.size();
@@ -533,6 +570,7 @@ static hpf_status_t batch_build_items(hpf_batch* b)
     bead_off[b->nrep] = (int64_t)bead.size();
     adv_off[b->nrep] = (int64_t)adv.size();
     mesh_off[b->nrep] = (int64_t)mesh.size();
+    brick_off[b->nrep] = (int64_t)brick.size();
     if ((int64_t)bead.size() > b->L.max_bead_items || (int64_t)mesh.size() > b->L.max_mesh_items)
         return HPF_EINVAL;
     b->n_bead_items = (int64_t)bead.size();
@@ -551,7 +589,8 @@ static hpf_status_t batch_build_items(hpf_batch* b)
         !up(b->L.off_mesh_items, mesh.data(), sizeof(ItemK) * mesh.size()) ||
         !up(b->L.off_plane_items, plane.data(), sizeof(ItemK) * plane.size()) ||
         !up(b->L.off_bead_ioff, bead_off.data(), sizeof(int64_t) * bead_off.size()) ||
-        !up(b->L.off_mesh_ioff, mesh_off.data(), sizeof(int64_t) * mesh_off.size()))
+        !up(b->L.off_mesh_ioff, mesh_off.data(), sizeof(int64_t) * mesh_off.size()) ||
+        !up(b->L.off_brick_ioff, brick_off.data(), sizeof(int64_t) * brick_off.size()))
         return HPF_EHIP;
     return HPF_OK;
 }
@@ -572,6 +611,27 @@ static hpf_status_t batch_sort(hpf_batch* b, hipStream_t s)
     return st;
 }
 
+// The potential over the mesh items, from counts that are complete.
+static hpf_status_t batch_potential(hpf_batch* b, int K, unsigned long long* counts, double* w, hipStream_t s)
+{
+    const RepK* reps = b->at<RepK>(b->L.off_reps);
+    const dim3 gm((unsigned)b->n_mesh_items), bm(kPotThreads);
+    const ItemK* mi = b->at<ItemK>(b->L.off_mesh_items);
+    float* V = b->buf.V;
+    switch (K) {
+    case 1: hipLaunchKernelGGL(k_batch_potential<1>, gm, bm, 0, s, reps, mi, counts, V, w); break;
+    case 2: hipLaunchKernelGGL(k_batch_potential<2>, gm, bm, 0, s, reps, mi, counts, V, w); break;
+    case 3: hipLaunchKernelGGL(k_batch_potential<3>, gm, bm, 0, s, reps, mi, counts, V, w); break;
+    case 4: hipLaunchKernelGGL(k_batch_potential<4>, gm, bm, 0, s, reps, mi, counts, V, w); break;
+    case 5: hipLaunchKernelGGL(k_batch_potential<5>, gm, bm, 0, s, reps, mi, counts, V, w); break;
+    case 6: hipLaunchKernelGGL(k_batch_potential<6>, gm, bm, 0, s, reps, mi, counts, V, w); break;
+    case 7: hipLaunchKernelGGL(k_batch_potential<7>, gm, bm, 0, s, reps, mi, counts, V, w); break;
+    case 8: hipLaunchKernelGGL(k_batch_potential<8>, gm, bm, 0, s, reps, mi, counts, V, w); break;
+    default: return HPF_EINVAL;
+    }
+    return HPF_OK;
+}
+
 static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)
 {
     const BatchLayout& L = b->L;
@@ -584,11 +644,26 @@ static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)
     const uint32_t* cs = b->at<uint32_t>(L.off_start);
     const auto* R = reinterpret_cast<const float4*>(b->buf.R[b->rcur]);
     const uint8_t* T = b->buf.T[b->scur];
+    double* w = report ? b->at<double>(L.off_wpart) : nullptr;
     if (b->pending) {
-        // the last fused pass deposited the current positions: add its boxes to the counts
-        hipLaunchKernelGGL(k_batch_scatter_sum<true>, dim3((unsigned)b->n_brick_items), sum_block(b->n_brick_items),
-                           0, s, reps, b->at<ItemK>(L.off_brick_items), B, h, K, partials, counts);
+        // the last fused pass deposited the current positions: its boxes are added to the
+        // counts inside the potential pass
+        const dim3 gb((unsigned)b->n_brick_items), bb(kFPThreads);
+        const ItemK* bi = b->at<ItemK>(L.off_brick_items);
+        float* V = b->buf.V;
+        switch (K) {
+        case 1: hipLaunchKernelGGL(k_batch_finish_potential<1>, gb, bb, 0, s, reps, bi, B, h, partials, counts, V, w); break;
+        case 2: hipLaunchKernelGGL(k_batch_finish_potential<2>, gb, bb, 0, s, reps, bi, B, h, partials, counts, V, w); break;
+        case 3: hipLaunchKernelGGL(k_batch_finish_potential<3>, gb, bb, 0, s, reps, bi, B, h, partials, counts, V, w); break;
+        case 4: hipLaunchKernelGGL(k_batch_finish_potential<4>, gb, bb, 0, s, reps, bi, B, h, partials, counts, V, w); break;
+        case 5: hipLaunchKernelGGL(k_batch_finish_potential<5>, gb, bb, 0, s, reps, bi, B, h, partials, counts, V, w); break;
+        case 6: hipLaunchKernelGGL(k_batch_finish_potential<6>, gb, bb, 0, s, reps, bi, B, h, partials, counts, V, w); break;
+        case 7: hipLaunchKernelGGL(k_batch_finish_potential<7>, gb, bb, 0, s, reps, bi, B, h, partials, counts, V, w); break;
+        case 8: hipLaunchKernelGGL(k_batch_finish_potential<8>, gb, bb, 0, s, reps, bi, B, h, partials, counts, V, w); break;
+        default: return HPF_EINVAL;
+        }
         b->pending = false;
+        b->w_bricks = true;
     } else {
         const size_t smem = scatter_cells_smem(K, P);
         if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_scatter_bricks),
@@ -601,20 +676,9 @@ static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)
                            0, s, reps, b->at<ItemK>(L.off_brick_items), B, h, K, partials, counts);
         hipLaunchKernelGGL(k_batch_scatter_strays, dim3(256), dim3(kTcThreads), 0, s, reps, b->nrep, K, R, T, cs,
                            strays, counts);
-    }
-    double* w = report ? b->at<double>(L.off_wpart) : nullptr;
-    const dim3 gm((unsigned)b->n_mesh_items), bm(kPotThreads);
-    const ItemK* mi = b->at<ItemK>(L.off_mesh_items);
-    switch (K) {
-    case 1: hipLaunchKernelGGL(k_batch_potential<1>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
-    case 2: hipLaunchKernelGGL(k_batch_potential<2>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
-    case 3: hipLaunchKernelGGL(k_batch_potential<3>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
-    case 4: hipLaunchKernelGGL(k_batch_potential<4>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
-    case 5: hipLaunchKernelGGL(k_batch_potential<5>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
-    case 6: hipLaunchKernelGGL(k_batch_potential<6>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
-    case 7: hipLaunchKernelGGL(k_batch_potential<7>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
-    case 8: hipLaunchKernelGGL(k_batch_potential<8>, gm, bm, 0, s, reps, mi, counts, b->buf.V, w); break;
-    default: return HPF_EINVAL;
+        if (hpf_status_t st = batch_potential(b, K, counts, w, s))
+            return st;
+        b->w_bricks = false;
     }
     hipLaunchKernelGGL(k_batch_gradient, dim3((unsigned)b->n_planes), dim3(256), 0, s, reps,
                        b->at<ItemK>(L.off_plane_items), K, b->buf.V, reinterpret_cast<float4*>(b->buf.G));
@@ -681,7 +745,8 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
     b->rcur = 1 - b->rcur;
     if (report)
         hipLaunchKernelGGL(k_batch_reduce, dim3(b->nrep), dim3(64), 0, s,
-                           b->at<int64_t>(fused ? L.off_adv_ioff : L.off_bead_ioff), b->at<int64_t>(L.off_mesh_ioff),
+                           b->at<int64_t>(fused ? L.off_adv_ioff : L.off_bead_ioff),
+                           b->at<int64_t>(b->w_bricks ? L.off_brick_ioff : L.off_mesh_ioff),
                            b->at<double>(L.off_wpart), e, kp, nslot, b->at<double>(L.off_energy));
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }

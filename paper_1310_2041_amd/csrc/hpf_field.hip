@@ -120,6 +120,63 @@ hpf_status_t launch_field_potential(uint64_t* counts, const MeshK& m, int K, con
 // it starts from are bitwise those of the finish + potential pair.
 constexpr int kFPThreads = 256;
 
+// One brick of the fused finish + potential: all threads of the workgroup
+// call it; it begins with a barrier (the previous brick's cover lists may
+// still be read) and returns this thread's field-energy terms.
+template <int K>
+__device__ __forceinline__ double finish_potential_brick(Cover (&cov)[3][kTcMaxB],
+                                                         const unsigned long long* __restrict__ partials,
+                                                         const TileK& tk, const PotK& p,
+                                                         unsigned long long* __restrict__ counts,
+                                                         float* __restrict__ V, int64_t brick, bool& over)
+{
+    const MeshK& m = tk.m;
+    const int64_t nm = m.nm;
+    const int B = tk.B, P = tk.P, P3 = P * P * P;
+    const int Mx = m.M[0], My = m.M[1];
+    const int bxyz[3] = {(int)(brick % tk.nb[0]), (int)((brick / tk.nb[0]) % tk.nb[1]),
+                         (int)(brick / ((int64_t)tk.nb[0] * tk.nb[1]))};
+    int o[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        o[d] = min(B, m.M[d] - bxyz[d] * B);
+    __syncthreads();
+    brick_covers(cov, tk, K, bxyz, o);
+    const int npts = o[0] * o[1] * o[2];
+    double wsum = 0.0;
+    for (int e = threadIdx.x; e < npts; e += (int)blockDim.x) {
+        int ix, iy, iz;
+        brick_point(e, o, B, ix, iy, iz);
+        const Cover& cx = cov[0][ix];
+        const Cover& cy = cov[1][iy];
+        const Cover& cz = cov[2][iz];
+        const int64_t dst = ((int64_t)(bxyz[2] * B + iz) * My + (bxyz[1] * B + iy)) * Mx + bxyz[0] * B + ix;
+        unsigned long long n[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            n[k] = counts[(int64_t)k * nm + dst];
+        if (cover2_ok(cx, cy, cz)) {
+            const Cover2 c2 = cover2(cx, cy, cz);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                n[k] += cover2_sum(partials, c2, (int64_t)k * P3);
+        } else {
+            for (int a = 0; a < cz.n; ++a)
+                for (int b2 = 0; b2 < cy.n; ++b2)
+                    for (int c = 0; c < cx.n; ++c) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            n[k] += partials[cz.off[a] + cy.off[b2] + cx.off[c] + (int64_t)k * P3];
+                    }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            counts[(int64_t)k * nm + dst] = 0ull;
+        wsum += potential_values<K>(n, V, nm, dst, m.c_norm, p, over);
+    }
+    return wsum;
+}
+
 template <int K>
 __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned long long* __restrict__ partials,
                                                                  TileK tk, PotK p,
@@ -128,59 +185,15 @@ __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned 
 {
     __shared__ Cover cov[3][kTcMaxB];
     __shared__ double scratch[kFPThreads / kWave];
-    const MeshK& m = tk.m;
-    const int64_t nm = m.nm;
     if (w_part)                                    // slots beyond this grid read as zero
         for (int64_t i = (int64_t)gridDim.x + blockIdx.x + (int64_t)threadIdx.x * gridDim.x; i < HPF_NPART;
              i += (int64_t)kFPThreads * gridDim.x)
             w_part[i] = 0.0;
-    const int tid = threadIdx.x;
-    const int B = tk.B, P = tk.P, P3 = P * P * P;
-    const int Mx = m.M[0], My = m.M[1];
     const BrickWalk w = brick_walk(tk.ntiles);
     double wsum = 0.0;
     bool over = false;
-    for (int64_t brick = w.first; brick < w.end; brick += w.stride) {
-        const int bxyz[3] = {(int)(brick % tk.nb[0]), (int)((brick / tk.nb[0]) % tk.nb[1]),
-                             (int)(brick / ((int64_t)tk.nb[0] * tk.nb[1]))};
-        int o[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            o[d] = min(B, m.M[d] - bxyz[d] * B);
-        __syncthreads();                              // the previous brick's cover lists are read
-        brick_covers(cov, tk, K, bxyz, o);
-        const int npts = o[0] * o[1] * o[2];
-        for (int e = tid; e < npts; e += kFPThreads) {
-            int ix, iy, iz;
-            brick_point(e, o, B, ix, iy, iz);
-            const Cover& cx = cov[0][ix];
-            const Cover& cy = cov[1][iy];
-            const Cover& cz = cov[2][iz];
-            const int64_t dst = ((int64_t)(bxyz[2] * B + iz) * My + (bxyz[1] * B + iy)) * Mx + bxyz[0] * B + ix;
-            unsigned long long n[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                n[k] = counts[(int64_t)k * nm + dst];
-            if (cover2_ok(cx, cy, cz)) {
-                const Cover2 c2 = cover2(cx, cy, cz);
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    n[k] += cover2_sum(partials, c2, (int64_t)k * P3);
-            } else {
-                for (int a = 0; a < cz.n; ++a)
-                    for (int b2 = 0; b2 < cy.n; ++b2)
-                        for (int c = 0; c < cx.n; ++c) {
-#pragma unroll
-                            for (int k = 0; k < K; ++k)
-                                n[k] += partials[cz.off[a] + cy.off[b2] + cx.off[c] + (int64_t)k * P3];
-                        }
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                counts[(int64_t)k * nm + dst] = 0ull;
-            wsum += potential_values<K>(n, V, nm, dst, m.c_norm, p, over);
-        }
-    }
+    for (int64_t brick = w.first; brick < w.end; brick += w.stride)
+        wsum += finish_potential_brick<K>(cov, partials, tk, p, counts, V, brick, over);
     if (over)
         raise_flag(HPF_FLAG_OVERFLOW);
     if (w_part) {
