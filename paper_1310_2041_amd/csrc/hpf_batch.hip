@@ -112,7 +112,13 @@ struct RepKeyer {
     const float4* R;
     __device__ __forceinline__ uint32_t operator()(int32_t i) const
     {
-        const RepK& rp = reps[find_rep(reps, nrep, i)];
+        // Lanes of a wave nearly always hold beads of one replica: search once for the
+        // first active lane (a uniform search), and per lane only outside its range.
+        const int32_t i0 = __builtin_amdgcn_readfirstlane(i);
+        int r = find_rep(reps, nrep, i0);
+        if (!(i >= reps[r].bead_off && i < reps[r].bead_off + reps[r].N))
+            r = find_rep(reps, nrep, i);
+        const RepK& rp = reps[r];
         BeadCell b;
         return rp.key_base + (bead_cell(R[i], rp.m, b) ? brick_of(b.c[0], b.c[1], b.c[2], B, rp.nb) : rp.NK);
     }

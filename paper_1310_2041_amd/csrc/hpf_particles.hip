@@ -817,23 +817,34 @@ hpf_status_t launch_scatter_finish(const unsigned long long* partials, const Til
 
 // ------------------------------------------------------------- reduction ---
 
-// out[c] = sum of part[c][0..HPF_NPART) in a fixed order (one block per c).
-__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ part,
-                                                         double* __restrict__ out)
+// out[c] = sum of part[c][0..HPF_NPART) in a fixed order (one block per c):
+// each thread adds its slots j, j + 1024, ... (all loads issued first), then the
+// block sum.
+constexpr int kRedThreads = 1024;
+static_assert(HPF_NPART % kRedThreads == 0, "partial slots must fill the reduction block");
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* __restrict__ part,
+                                                                 double* __restrict__ out)
 {
-    __shared__ double scratch[256 / kWave];
+    __shared__ double scratch[kRedThreads / kWave];
     const double* p = part + (int64_t)blockIdx.x * HPF_NPART;
-    double v = 0.0;
-    for (int i = threadIdx.x; i < HPF_NPART; i += 256)
-        v += p[i];
-    const double s = block_sum(v, scratch);
+    constexpr int kPer = HPF_NPART / kRedThreads;
+    double v[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        v[j] = p[threadIdx.x + j * kRedThreads];
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        t += v[j];
+    const double s = block_sum(t, scratch);
     if (threadIdx.x == 0)
         out[blockIdx.x] = s;
 }
 
 hpf_status_t launch_reduce_partials(const double* part, int ncomp, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(ncomp), dim3(256), 0, s, part, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(ncomp), dim3(kRedThreads), 0, s, part, out);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
