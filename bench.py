@@ -228,7 +228,8 @@ def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
 ROCPROF_KERNELS = {
     "advance": ["hpf::k_advance<true>", "hpf::k_advance<false>", "hpf::k_advance_cells<true>",
                 "hpf::k_advance_cells<false>"] +
-               ["hpf::k_advance_scatter<%s, %d>" % (r0, n) for r0 in ("true", "false") for n in (256, 512)],
+               ["hpf::k_advance_scatter<%s, %d, %s>" % (r0, n, pipe) for r0 in ("true", "false") for n in (256, 512)
+                for pipe in ("true", "false")],
     "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum<false>",
                         "hpf::k_scatter_strays"],
     "density_finish": ["hpf::k_scatter_sum<true>"],

@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
 // sort; a replica's last item (brick == NK) holds the beads the sort could
 // not bin, deposited with global atomics. The energy partials go to the
 // item's slot.
-template <bool kR0Zero>
+template <bool kR0Zero, bool kPipe>
 __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
     const RepK* __restrict__ reps, const ItemK* __restrict__ items, int B, int h, int K,
     const float4* __restrict__ R, float4* __restrict__ R_next, float4* __restrict__ Vel,
@@ -309,16 +309,43 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
             dbox[q] = 0ull;
         __syncthreads();
         const int64_t first = cs[brick], last = min((int64_t)cs[brick + 1], Ntot);
-        for (int64_t i = first + threadIdx.x; i < last; i += kASThreadsBatch) {
-            const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k, r0, rp.box,
-                                                    nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond, nonfinite);
-            const int t = T[i];
-            BeadCell bc;
-            int lx, ly, lz;
-            if (bead_cell(rn, m, bc) && t < K && brick_box_cell(bc, m, x0, y0, z0, ox, oy, oz, h, lx, ly, lz))
-                box_deposit(dbox, P, t, lx, ly, lz, bc);
-            else
-                bad_bead |= !deposit_global(rn, t, K, m, cr);
+        if (kPipe) {
+            // software-pipelined as in k_advance_scatter (the table has at most kPreBonds rows)
+            int64_t i = first + threadIdx.x;
+            BeadIn cur;
+            if (i < last)
+                bead_fetch(cur, i, R, Vel, T, bonds, D, Ntot, nullptr);
+            for (; i < last; i += kASThreadsBatch) {
+                BeadLoads L;
+                bead_issue(L, cur, i, m, K, Gr, R, Ntot);
+                __builtin_amdgcn_sched_barrier(0);
+                BeadIn nxt;
+                bead_fetch(nxt, min(i + kASThreadsBatch, last - 1), R, Vel, T, bonds, D, Ntot, nullptr);
+                __builtin_amdgcn_sched_barrier(0);
+                const float4 rn = bead_finish<kR0Zero>(i, cur, L, R_next, Vel, Ntot, D, k, r0, rp.box, dt, hdt,
+                                                       nullptr, acc, e, bad_bead, bad_bond, nonfinite);
+                const int t = cur.t;
+                BeadCell bc;
+                int lx, ly, lz;
+                if (bead_cell(rn, m, bc) && t < K && brick_box_cell(bc, m, x0, y0, z0, ox, oy, oz, h, lx, ly, lz))
+                    box_deposit(dbox, P, t, lx, ly, lz, bc);
+                else
+                    bad_bead |= !deposit_global(rn, t, K, m, cr);
+                cur = nxt;
+            }
+        } else {
+            for (int64_t i = first + threadIdx.x; i < last; i += kASThreadsBatch) {
+                const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k, r0,
+                                                        rp.box, nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond,
+                                                        nonfinite);
+                const int t = T[i];
+                BeadCell bc;
+                int lx, ly, lz;
+                if (bead_cell(rn, m, bc) && t < K && brick_box_cell(bc, m, x0, y0, z0, ox, oy, oz, h, lx, ly, lz))
+                    box_deposit(dbox, P, t, lx, ly, lz, bc);
+                else
+                    bad_bead |= !deposit_global(rn, t, K, m, cr);
+            }
         }
         __syncthreads();
         unsigned long long* out = partials + (rp.brick_off + brick) * (int64_t)nbox;
@@ -712,24 +739,23 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
     if (fused) {
         const int P = c.brick + 1 + 2 * c.halo;
         const size_t smem = sizeof(unsigned long long) * (size_t)c.K * P * P * P;
-        const void* fn = c.r0 == 0.0f ? reinterpret_cast<const void*>(k_batch_advance_scatter<true>)
-                                      : reinterpret_cast<const void*>(k_batch_advance_scatter<false>);
-        if (smem > 65536 &&
-            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+        // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
+        using AdvFn = void (*)(const RepK*, const ItemK*, int, int, int, const float4*, float4*, float4*,
+                               const uint8_t*, int64_t, const float4*, const int32_t*, int, float, float, float,
+                               const uint32_t*, unsigned long long*, unsigned long long*, double*, double*, int);
+        const bool pipe = c.D <= kPreBonds;
+        const AdvFn fn = c.r0 == 0.0f ? (pipe ? k_batch_advance_scatter<true, true> : k_batch_advance_scatter<true, false>)
+                                      : (pipe ? k_batch_advance_scatter<false, true> : k_batch_advance_scatter<false, false>);
+        if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
             return HPF_EINVAL;
         const dim3 ga((unsigned)b->n_adv_items), ba(kASThreadsBatch);
         const ItemK* adv = b->at<ItemK>(L.off_adv_items);
         const uint32_t* cs = b->at<uint32_t>(L.off_start);
         auto* partials = b->at<unsigned long long>(L.off_partials);
         auto* counts = reinterpret_cast<unsigned long long*>(b->buf.counts);
-        if (c.r0 == 0.0f)
-            hipLaunchKernelGGL(k_batch_advance_scatter<true>, ga, ba, smem, s, reps, adv, c.brick, c.halo, c.K, R, Rn,
-                               Vel, T, L.Ntot, G, bonds, c.D, c.k_bond, c.r0, c.dt, cs, partials, counts, e, kp,
-                               nslot);
-        else
-            hipLaunchKernelGGL(k_batch_advance_scatter<false>, ga, ba, smem, s, reps, adv, c.brick, c.halo, c.K, R,
-                               Rn, Vel, T, L.Ntot, G, bonds, c.D, c.k_bond, c.r0, c.dt, cs, partials, counts, e, kp,
-                               nslot);
+        hipLaunchKernelGGL(fn, ga, ba, smem, s, reps, adv, c.brick, c.halo, c.K, R, Rn, Vel, T, L.Ntot, G, bonds,
+                           c.D, c.k_bond, c.r0, c.dt, cs, partials, counts, e, kp, nslot);
         b->pending = true;
     } else if (b->n_bead_items > 0) {
         if (prime) {

@@ -416,6 +416,125 @@ __device__ __forceinline__ float4 advance_bead(int64_t i, const float4* __restri
     return r;
 }
 
+// Software-pipelined form of advance_bead for bond tables of at most two rows.
+// A bead's own data (position, velocity, type, bond row, inverse mass) is
+// loaded one loop iteration ahead, and those loads are issued after the
+// current bead's corner and partner loads: vector memory operations retire in
+// issue order for the wait counter, so loads issued earlier would hold up the
+// wait for the corners. The arithmetic is that of advance_bead, in the same
+// order, so results are bitwise equal.
+constexpr int kPreBonds = 2;
+
+struct BeadIn {
+    float4 r, v;
+    float im;
+    int t;
+    int32_t j[kPreBonds];
+};
+
+__device__ __forceinline__ void bead_fetch(BeadIn& p, int64_t i, const float4* __restrict__ R,
+                                           const float4* __restrict__ Vel, const uint8_t* __restrict__ T,
+                                           const int32_t* __restrict__ bonds, int D, int64_t N,
+                                           const float* __restrict__ inv_mass)
+{
+    p.r = R[i];
+    p.v = Vel[i];
+    p.t = T[i];
+    p.im = inv_mass ? inv_mass[i] : 1.0f;
+#pragma unroll
+    for (int b = 0; b < kPreBonds; ++b)
+        p.j[b] = b < D ? bonds[(int64_t)b * N + i] : -1;
+}
+
+struct BeadLoads {
+    float4 g[8];
+    float4 xj[kPreBonds];
+    BeadCell b;
+    bool ok;
+};
+
+// Cell of the bead, its 8 corner loads (a bead that cannot be binned loads the
+// corners of cell 0 and gets no field force) and its partner loads (an index
+// outside [0, N) loads the bead itself; the bond is then skipped or flagged).
+__device__ __forceinline__ void bead_issue(BeadLoads& L, const BeadIn& p, int64_t i, const MeshK& m, int K,
+                                           const float4* __restrict__ G, const float4* __restrict__ R, int64_t N)
+{
+    L.ok = bead_cell(p.r, m, L.b) && p.t < K;
+    BeadCell c = L.b;
+    if (!L.ok)
+        c.c[0] = c.c[1] = c.c[2] = 0;
+    corners_global(c, L.ok ? p.t : 0, m, G, L.g);
+#pragma unroll
+    for (int b = 0; b < kPreBonds; ++b) {
+        const int32_t j = p.j[b];
+        L.xj[b] = R[(j >= 0 && j < N) ? (int64_t)j : i];
+    }
+}
+
+template <bool kR0Zero>
+__device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const BeadLoads& L,
+                                              float4* __restrict__ R_next, float4* __restrict__ Vel, int64_t N,
+                                              int D, float k, float r0, const BoxK& box, float dt, float hdt,
+                                              float4* __restrict__ F_out, KinAcc& acc, double& e, bool& bad_bead,
+                                              bool& bad_bond, bool& nonfinite)
+{
+    float4 r = p.r;
+    float3 ff = make_float3(0.0f, 0.0f, 0.0f);
+    if (L.ok)
+        ff = interp8(L.b, L.g);
+    bad_bead |= !L.ok;
+    // bond forces: the operations of bond_sum
+    const float two_k = 2.0f * k;
+    float3 fb = make_float3(0.0f, 0.0f, 0.0f);
+    float ei = 0.0f;
+#pragma unroll
+    for (int b = 0; b < kPreBonds; ++b) {
+        if (b >= D)
+            break;
+        const int32_t j = p.j[b];
+        if (j < 0)
+            continue;
+        if (j >= N) {
+            bad_bond = true;
+            continue;
+        }
+        const float4 xj = L.xj[b];
+        const float dx = min_image(xj.x, r.x, box.L[0], box.halfL[0]);
+        const float dy = min_image(xj.y, r.y, box.L[1], box.halfL[1]);
+        const float dz = min_image(xj.z, r.z, box.L[2], box.halfL[2]);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        float coef;
+        if (kR0Zero) {
+            coef = two_k;
+            ei += k * r2;
+        } else {
+            const float rr = sqrtf(r2);
+            const float dr = rr - r0;
+            coef = rr > 0.0f ? two_k * dr / rr : 0.0f;
+            ei += k * dr * dr;
+        }
+        fb.x += coef * dx;
+        fb.y += coef * dy;
+        fb.z += coef * dz;
+    }
+    float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
+    f.x += fb.x;
+    f.y += fb.y;
+    f.z += fb.z;
+    e += 0.5 * (double)ei;
+    if (F_out)
+        F_out[i] = f;
+    float4 v = p.v;
+    kick(v, f, p.im, hdt);               // v_n
+    acc.add(v, p.im);
+    kick(v, f, p.im, hdt);               // v_{n+1/2}
+    drift(r, v, dt, box);                // x_{n+1}
+    nonfinite |= !(finite4(r) && finite4(v));
+    Vel[i] = v;
+    R_next[i] = r;
+    return r;
+}
+
 // Fused pass over the beads. Positions go to R_next so that bond partners
 // are always read at x_n.
 template <bool kR0Zero>
@@ -561,7 +680,7 @@ __global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __res
 // kASFewBricks), so that a small mesh still fills the chip with waves.
 constexpr int kASFewBricks = 2048;
 
-template <bool kR0Zero, int kASThreads>
+template <bool kR0Zero, int kASThreads, bool kPipe>
 __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __restrict__ R,
                                                                 float4* __restrict__ R_next,
                                                                 float4* __restrict__ Vel,
@@ -603,17 +722,47 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
             __syncthreads();
             const int64_t first = cell_start[item];
             const int64_t last = min((int64_t)cell_start[item + 1], N);
-            for (int64_t i = first + threadIdx.x; i < last; i += kASThreads) {
-                const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box,
-                                                        inv_mass, dt, hdt, F_out, acc, e, bad_bead, bad_bond,
-                                                        nonfinite);
-                const int t = T[i];
-                BeadCell b;
-                int lx, ly, lz;
-                if (bead_cell(rn, m, b) && t < K && brick_box_cell(b, m, x0, y0, z0, ox, oy, oz, h, lx, ly, lz))
-                    box_deposit(dbox, P, t, lx, ly, lz, b);
-                else
-                    bad_bead |= !deposit_global(rn, t, K, m, counts);
+            if (kPipe) {
+                // (kPipe: the bond table has at most kPreBonds rows.) The next bead's own loads go out after this bead's corner and partner loads
+                // (the scheduling barriers keep that order) and stay in flight through its
+                // arithmetic; the last bead of a thread fetches a valid bead again
+                int64_t i = first + threadIdx.x;
+                BeadIn cur;
+                if (i < last)
+                    bead_fetch(cur, i, R, Vel, T, bonds, D, N, inv_mass);
+                for (; i < last; i += kASThreads) {
+                    BeadLoads L;
+                    bead_issue(L, cur, i, m, K, G, R, N);
+                    __builtin_amdgcn_sched_barrier(0);
+                    BeadIn nxt;
+                    bead_fetch(nxt, min(i + kASThreads, last - 1), R, Vel, T, bonds, D, N, inv_mass);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const float4 rn = bead_finish<kR0Zero>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt,
+                                                           F_out, acc, e, bad_bead, bad_bond, nonfinite);
+                    const int t = cur.t;
+                    BeadCell b;
+                    int lx, ly, lz;
+                    if (bead_cell(rn, m, b) && t < K &&
+                        brick_box_cell(b, m, x0, y0, z0, ox, oy, oz, h, lx, ly, lz))
+                        box_deposit(dbox, P, t, lx, ly, lz, b);
+                    else
+                        bad_bead |= !deposit_global(rn, t, K, m, counts);
+                    cur = nxt;
+                }
+            } else {
+                for (int64_t i = first + threadIdx.x; i < last; i += kASThreads) {
+                    const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0,
+                                                            box, inv_mass, dt, hdt, F_out, acc, e, bad_bead,
+                                                            bad_bond, nonfinite);
+                    const int t = T[i];
+                    BeadCell b;
+                    int lx, ly, lz;
+                    if (bead_cell(rn, m, b) && t < K &&
+                        brick_box_cell(b, m, x0, y0, z0, ox, oy, oz, h, lx, ly, lz))
+                        box_deposit(dbox, P, t, lx, ly, lz, b);
+                    else
+                        bad_bead |= !deposit_global(rn, t, K, m, counts);
+                }
             }
             __syncthreads();
             unsigned long long* out = partials + item * (int64_t)nbox;
@@ -761,7 +910,7 @@ hpf_status_t launch_advance_cells(const float* R, float* R_next, float* Vel, con
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
-template <int kThreads>
+template <int kThreads, bool kPipe>
 static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float4* Vp, const uint8_t* T, int64_t N,
                                              const TileK& tk, int K, const float4* Gp, const int32_t* bonds, int D,
                                              float k, float r0, const BoxK& box, const float* inv_mass, float dt,
@@ -770,8 +919,8 @@ static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float
                                              double* kin_part, hipStream_t s)
 {
     const size_t smem = sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P;
-    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_scatter<true, kThreads>)
-                                : reinterpret_cast<const void*>(k_advance_scatter<false, kThreads>);
+    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_scatter<true, kThreads, kPipe>)
+                                : reinterpret_cast<const void*>(k_advance_scatter<false, kThreads, kPipe>);
     if (smem > 65536 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
         return HPF_EINVAL;
@@ -780,11 +929,11 @@ static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float
     const int64_t nb = std::min<int64_t>(tk.ntiles + 1, HPF_NPART);
     const dim3 g((unsigned)nb), bl(kThreads);
     if (r0 == 0.0f)
-        hipLaunchKernelGGL((k_advance_scatter<true, kThreads>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D,
-                           k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
+        hipLaunchKernelGGL((k_advance_scatter<true, kThreads, kPipe>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp,
+                           bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
     else
-        hipLaunchKernelGGL((k_advance_scatter<false, kThreads>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds,
-                           D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
+        hipLaunchKernelGGL((k_advance_scatter<false, kThreads, kPipe>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp,
+                           bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
@@ -800,11 +949,19 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
     auto* Vp = reinterpret_cast<float4*>(Vel);
     auto* Gp = reinterpret_cast<const float4*>(G);
     auto* Fo = reinterpret_cast<float4*>(F_out);
-    if (tk.ntiles < kASFewBricks)
-        return launch_advance_scatter_t<512>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
-                                             cell_start, partials, counts, Fo, e_part, kin_part, s);
-    return launch_advance_scatter_t<256>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt, cell_start,
-                                         partials, counts, Fo, e_part, kin_part, s);
+    // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
+    const bool few = tk.ntiles < kASFewBricks, pipe = D <= kPreBonds;
+    if (few && pipe)
+        return launch_advance_scatter_t<512, true>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
+                                                   cell_start, partials, counts, Fo, e_part, kin_part, s);
+    if (few)
+        return launch_advance_scatter_t<512, false>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
+                                                    cell_start, partials, counts, Fo, e_part, kin_part, s);
+    if (pipe)
+        return launch_advance_scatter_t<256, true>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
+                                                   cell_start, partials, counts, Fo, e_part, kin_part, s);
+    return launch_advance_scatter_t<256, false>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
+                                                cell_start, partials, counts, Fo, e_part, kin_part, s);
 }
 
 hpf_status_t launch_scatter_finish(const unsigned long long* partials, const TileK& tk, int K,

@@ -143,3 +143,45 @@ def test_engine_fused_deposit_matches_plain_steps(cfg):
         for key in ("KE", "E_bond", "W"):
             assert y[key] == pytest.approx(x[key], rel=1e-12)
     assert hpf.hpf_get_device_status() == 0
+
+
+def _scatter_pass(st, bonds):
+    Rn, V = torch.empty_like(st.R), st.Vel.clone()
+    st.counts.zero_()
+    hpf.hpf_advance_scatter(st.R, Rn, V, st.T, st.mesh, st.K, st.G, bonds, st.k_bond, st.r0, st.box, st.dt,
+                            st.cell_start, st.B, st.halo, st.counts, st.scatter_work)
+    hpf.hpf_density_finish_cells(st.counts, st.N, st.mesh, st.K, st.B, st.halo, st.scatter_work)
+    return Rn, V, st.counts.clone()
+
+
+def test_advance_scatter_without_bond_table():
+    """No bond table (D = 0, null pointer): the fused pass equals hpf_advance bit for bit and
+    its deposit equals the oracle's density."""
+    s = wl.small_system(200, 10, 14.0, 14, seed=71)
+    st = engine.HpfState.from_system(s)
+    st.sort()
+    field_of(st)
+    Rn_a, V_a = torch.empty_like(st.R), st.Vel.clone()
+    hpf.hpf_advance(st.R, Rn_a, V_a, st.T, st.mesh, st.K, st.G, None, st.k_bond, st.r0, st.box, st.dt)
+    Rn_b, V_b, counts = _scatter_pass(st, None)
+    assert torch.equal(Rn_a.view(torch.int32), Rn_b.view(torch.int32))
+    assert torch.equal(V_a.view(torch.int32), V_b.view(torch.int32))
+    want, _ = oracle.density(host(Rn_b), host(st.T), s.L, s.M, s.K)
+    assert np.array_equal(counts_np(counts, st.K, tuple(st.mesh.M)), want)
+    assert hpf.hpf_get_device_status() == 0
+
+
+def test_advance_scatter_bond_rows_beyond_two():
+    """A bond table with a third row (all -1) takes the general bead loop; it must give the
+    same beads and counts as the two-row table (the software-pipelined loop)."""
+    s, _ = wl.permuted(wl.build(wl.SPECS["c1"]), seed=5)
+    st = engine.HpfState.from_system(s)
+    st.sort()
+    field_of(st)
+    b3 = torch.cat([st.bonds, torch.full((1, st.N), -1, dtype=torch.int32, device="cuda")]).contiguous()
+    Ra, Va, ca = _scatter_pass(st, st.bonds)
+    Rb, Vb, cb = _scatter_pass(st, b3)
+    assert torch.equal(Ra.view(torch.int32), Rb.view(torch.int32))
+    assert torch.equal(Va.view(torch.int32), Vb.view(torch.int32))
+    assert torch.equal(ca, cb)
+    assert hpf.hpf_get_device_status() == 0

@@ -61,9 +61,10 @@ def test_no_kernel_uses_scratch_or_spills(tmp_path):
 
 
 def test_fused_pass_register_budget(tmp_path):
-    """The fused advance + deposit runs at 4 waves per SIMD (at most 128 VGPRs)."""
+    """Each fused advance + deposit kernel keeps 4 waves per SIMD (at most 128 VGPRs of 512),
+    the software-pipelined ones included."""
     md = kernel_metadata(tmp_path)
-    fused = {k: v for k, v in md.items() if "k_advance_scatter" in k}
-    assert fused
+    fused = {k: v for k, v in md.items() if "advance_scatter" in k}
+    assert len(fused) >= 8
     for k, v in fused.items():
         assert v["vgpr_count"] <= 128, (k, v)
