@@ -675,9 +675,12 @@ __global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __res
 // points per axis), which is stored to the brick's partial buffer when the
 // brick is done. New positions outside the box, and every bead the sort could
 // not bin, are added to `counts` with global atomics; the partial sum pass
-// (k_scatter_sum<true>) then completes the counts of x_{n+1}.
+// (k_scatter_sum<true>, or the fused finish + potential) then completes the
+// counts of x_{n+1}.
 // Workgroup size: 256 threads, or 512 when there are few bricks (fewer than
 // kASFewBricks), so that a small mesh still fills the chip with waves.
+// kPipe selects the software-pipelined bead loop (bond tables of at most
+// kPreBonds rows); the plain loop serves wider tables.
 constexpr int kASFewBricks = 2048;
 
 template <bool kR0Zero, int kASThreads, bool kPipe>
@@ -723,9 +726,10 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
             const int64_t first = cell_start[item];
             const int64_t last = min((int64_t)cell_start[item + 1], N);
             if (kPipe) {
-                // (kPipe: the bond table has at most kPreBonds rows.) The next bead's own loads go out after this bead's corner and partner loads
-                // (the scheduling barriers keep that order) and stay in flight through its
-                // arithmetic; the last bead of a thread fetches a valid bead again
+                // Bond table of at most kPreBonds rows. The next bead's own loads go out
+                // after this bead's corner and partner loads (the scheduling barriers keep
+                // that order) and stay in flight through its arithmetic; a thread's last
+                // bead fetches a valid bead again.
                 int64_t i = first + threadIdx.x;
                 BeadIn cur;
                 if (i < last)
