@@ -42,7 +42,9 @@ constexpr int kScanTopPer = 8;
 constexpr int kMaxScanTiles = kScanTopThreads * kScanTopPer;
 constexpr int kChunkThreads = 256;                    // histogram / placement workgroups
 constexpr int kPlaceRegs = 16;                        // 256-tag blocks a thread holds at once
-constexpr int64_t kMinChunk = (int64_t)kChunkThreads * kPlaceRegs;   // 4096 tags
+constexpr int64_t kMinChunk = (int64_t)kChunkThreads * kPlaceRegs;   // 4096 tags (one placement round)
+constexpr int64_t kSmallChunk = kChunkThreads * 4;                    // 1024 tags
+constexpr int64_t kChunksWanted = 2048;     // chunks that keep the histogram and placement passes busy
 constexpr int kColBlock = 64;                         // chunks per column-scan block
 constexpr int64_t kMaxSortKeys = 36864;               // one chunk's histogram in LDS (144 KiB)
 constexpr int64_t kMaxTable = 64LL << 20;             // chunk x key table entries
@@ -245,6 +247,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_sort_place(const uint32_t* __
     for (int64_t g0 = t0; g0 < t1; g0 += kMinChunk) {
         uint32_t key[kPlaceRegs];
         int32_t src[kPlaceRegs];
+        // 256-tag blocks of this round that hold tags (fewer than kPlaceRegs for a short chunk)
+        const int nblk = (int)min((int64_t)kPlaceRegs, (t1 - g0 + kChunkThreads - 1) / kChunkThreads);
 #pragma unroll
         for (int b = 0; b < kPlaceRegs; ++b) {
             const int64_t t = g0 + (int64_t)b * kChunkThreads + threadIdx.x;
@@ -257,6 +261,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_sort_place(const uint32_t* __
         }
 #pragma unroll
         for (int b = 0; b < kPlaceRegs; ++b) {
+            if (b >= nblk)
+                break;
             for (int w = 0; w < kChunkThreads / kWave; ++w) {
                 if (wave == w) {
                     const bool act = key[b] != kNoKey;
@@ -350,7 +356,12 @@ bool sort_plan(int64_t N, int64_t nkeys, SortPlan* p)
 {
     if (N < 0 || N > 0x7ffffff0LL || nkeys < 1 || nkeys > kMaxSortKeys)
         return false;
+    // Chunks of 4096 tags (one placement round), or of 1024 when that leaves fewer
+    // than kChunksWanted chunks and the chunk x key table stays within 4 entries
+    // per bead; larger while the table exceeds kMaxTable.
     int64_t S = kMinChunk;
+    if ((N + S - 1) / S < kChunksWanted && ((N + kSmallChunk - 1) / kSmallChunk) * nkeys <= 4 * std::max<int64_t>(N, 1))
+        S = kSmallChunk;
     while (((N + S - 1) / S) * nkeys > kMaxTable)
         S *= 2;
     p->N = N;
