@@ -74,6 +74,9 @@ def lib():
         _lib.or_run.argtypes = [P, P, P, P, C.c_int64, C.POINTER(_Params), C.c_double,
                                 C.c_int32, P]
         _lib.or_run.restype = C.c_int
+        _lib.or_run_interval.argtypes = [P, P, P, P, C.c_int64, C.POINTER(_Params), C.c_double,
+                                         C.c_int32, C.c_int32, P]
+        _lib.or_run_interval.restype = C.c_int
         _lib.or_sort_perm.argtypes = [P, P, C.c_int64, C.POINTER(_Mesh), C.c_int32, P, P]
         _lib.or_sort_perm.restype = C.c_int
     return _lib
@@ -231,6 +234,26 @@ def run(sys, n_steps, R=None, V=None, inv_mass=None):
     E = np.zeros((n_steps + 1, 4))
     rc = lib().or_run(_p(Rd), _p(Vd), _p(T), None if im is None else _p(im), Rd.shape[0],
                       C.byref(p), float(sys.dt), int(n_steps), _p(E))
+    if rc:
+        raise MemoryError("oracle allocation failed")
+    return Rd, Vd, E
+
+
+def run_interval(sys, n_steps, field_every, R=None, V=None, inv_mass=None):
+    """run() with the density field rebuilt only every `field_every` force evaluations
+    (O11: the MD-SCF section's field-update interval); field_every = 1 is run()."""
+    m = mesh(sys.L, sys.M)
+    keep = []
+    p = _params(m, _sysdict(sys), sys.chi, sys.bonds, keep)
+    Rd = _pos(sys.R if R is None else R).copy()
+    Vd = _pos(sys.V if V is None else V).copy()
+    T = np.ascontiguousarray(sys.T, dtype=np.uint8)
+    im = None if inv_mass is None else np.ascontiguousarray(inv_mass, dtype=np.float64)
+    E = np.zeros((n_steps + 1, 4))
+    rc = lib().or_run_interval(_p(Rd), _p(Vd), _p(T), None if im is None else _p(im), Rd.shape[0],
+                               C.byref(p), float(sys.dt), int(n_steps), int(field_every), _p(E))
+    if rc == -2:
+        raise ValueError("field_every must be >= 1")
     if rc:
         raise MemoryError("oracle allocation failed")
     return Rd, Vd, E

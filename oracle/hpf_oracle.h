@@ -102,6 +102,15 @@ int64_t or_forces(const double* R, const uint8_t* T, int64_t N, const or_params_
 int or_run(double* R, double* V, const uint8_t* T, const double* inv_mass, int64_t N,
            const or_params_t* p, double dt, int32_t n_steps, double* energies);
 
+/* or_run with the density field rebuilt only at every field_every-th force
+ * evaluation (O11): evaluation s (0 at the start, s after step s) rebuilds
+ * n_K, V and G when s % field_every == 0; the others gather from the last G.
+ * energies as in or_run, W being that of the last rebuild. field_every = 1
+ * is or_run. Returns 0, -1 on allocation failure, -2 for field_every < 1. */
+int or_run_interval(double* R, double* V, const uint8_t* T, const double* inv_mass, int64_t N,
+                    const or_params_t* p, double dt, int32_t n_steps, int32_t field_every,
+                    double* energies);
+
 /* a0: cell-list order (the paper reorders particles for cache hits and bins
  * them into cells, Algorithm 1 Kernel 1). key = index of the brick of B^3
  * cells holding the bead's cell, bricks numbered x fastest; beads that

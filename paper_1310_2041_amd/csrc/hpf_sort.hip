@@ -261,8 +261,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_sort_place(const uint32_t* __
         }
 #pragma unroll
         for (int b = 0; b < kPlaceRegs; ++b) {
-            if (b >= nblk)
-                break;
+            if (b >= nblk)                           // uniform: the block holds no tags
+                continue;
             for (int w = 0; w < kChunkThreads / kWave; ++w) {
                 if (wave == w) {
                     const bool act = key[b] != kNoKey;

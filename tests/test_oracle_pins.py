@@ -334,3 +334,64 @@ def test_sort_permutation_orders_by_brick_then_tag(oracle_mod):
         c = [bf.cell_weights(float(sp.R[i, d]), sp.L[d], sp.M[d])[0] for d in range(3)]
         brick = ((c[2] // B) * nb[1] + c[1] // B) * nb[0] + c[0] // B
         assert keys[i] == brick
+
+
+# ---- O11: field-update interval (MD-SCF section; Fig. 5 refreshes the field every 300 steps)
+
+def test_run_interval_of_one_is_run(oracle_mod):
+    """A field rebuilt at every force evaluation is the plain run (or_run, a separate loop)."""
+    s = wl.small_system(30, 10, 10.0, 10, seed=81)
+    R1, V1, E1 = oracle_mod.run(s, 6)
+    R2, V2, E2 = oracle_mod.run_interval(s, 6, 1)
+    assert np.array_equal(R1, R2) and np.array_equal(V1, V2) and np.array_equal(E1, E2)
+
+
+def test_run_interval_without_field_is_run(oracle_mod):
+    """chi = 0 and 1/kappa = 0: V and its gradient vanish everywhere, so the rebuild schedule
+    cannot change the trajectory, and W = 0."""
+    s = wl.small_system(30, 10, 10.0, 10, seed=82, chi_ab=0.0, inv_kappa=0.0)
+    R1, V1, E1 = oracle_mod.run(s, 6)
+    for n in (2, 4, 7):
+        R2, V2, E2 = oracle_mod.run_interval(s, 6, n)
+        assert np.array_equal(R1, R2) and np.array_equal(V1, V2) and np.array_equal(E1, E2)
+        assert not E2[:, 2].any()
+
+
+def test_run_interval_schedule_from_pinned_pieces(oracle_mod):
+    """Interval 3 over 7 steps composed by hand from the separately pinned density, potential,
+    gradient, gather, bond and Verlet pieces: the field is rebuilt at evaluations 0, 3 and 6
+    only; the others gather from the last rebuild's gradient at the current positions, and
+    the reported W is the last rebuild's."""
+    s = wl.small_system(30, 10, 10.0, 10, seed=83)
+    n, steps = 3, 7
+
+    def field(R):
+        counts, _ = oracle_mod.density(R, s.T, s.L, s.M, s.K)
+        Vp, W = oracle_mod.potential(counts, s.L, s.M, s.N, s.kT, s.inv_kappa, s.chi)
+        return oracle_mod.gradient(Vp, s.L, s.M), W
+
+    def force(R, G):
+        Fb, Eb = oracle_mod.bonds(R, s.bonds, s.k_bond, s.r0, s.L)
+        return oracle_mod.gather(R, s.T, s.L, s.M, G) + Fb, Eb
+
+    R = s.R[:, :3].astype(np.float64)
+    V = s.V[:, :3].astype(np.float64)
+    G, W = field(R)
+    F, Eb = force(R, G)
+    Ws, Ebs, KEs = [W], [Eb], [0.5 * float((V * V).sum())]
+    for step in range(1, steps + 1):
+        R, V = oracle_mod.verlet_half1(R, V, F, s.dt, s.L)
+        if step % n == 0:
+            G, W = field(R)
+        F, Eb = force(R, G)
+        V, out = oracle_mod.verlet_half2(V, F, s.dt)
+        Ws.append(W)
+        Ebs.append(Eb)
+        KEs.append(out[0])
+    Ro, Vo, Eo = oracle_mod.run_interval(s, steps, n)
+    assert np.array_equal(Ro, R) and np.array_equal(Vo, V)
+    assert np.array_equal(Eo[:, 2], Ws) and np.array_equal(Eo[:, 1], Ebs)
+    np.testing.assert_allclose(Eo[:, 0], KEs, rtol=1e-14)
+    # the schedule matters: interval 3 differs from rebuilding every evaluation
+    R1, _, _ = oracle_mod.run(s, steps)
+    assert not np.array_equal(R1, Ro)
