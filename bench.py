@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -105,7 +106,7 @@ def timed_step_fused(st, hpf, engine, tm, sort):
 
 
 def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, graph=True, halo=2,
-                 advance="scatter"):
+                 advance="scatter", field_every=1):
     """Warm up, time `steps` steps, then (instrument) time each call over one graph's worth
     of eager steps. With `graph`, the timed steps replay a HIP graph of two sort periods:
     every buffer swap of the step then returns to its start, so the graph can be looped."""
@@ -116,7 +117,7 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
 
     spec = wl.SPECS[cfg]
     s = wl.build(spec)
-    st = engine.HpfState.from_system(s, halo=halo, advance=advance)
+    st = engine.HpfState.from_system(s, halo=halo, advance=advance, field_every=field_every)
     del s
     st.start(sort=True)
     if fused:
@@ -129,7 +130,8 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
     for _ in range(warmup):
         one()
     torch.cuda.synchronize()
-    period = 2 * sort_every if sort_every > 0 else 20
+    # the step pattern repeats after two sort intervals and after the field interval
+    period = math.lcm(2 * sort_every if sort_every > 0 else 20, field_every)
     use_graph = graph and fused and steps % period == 0
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -226,8 +228,8 @@ def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
 
 # rocprofv3 kernel names behind each timed call of the step
 ROCPROF_KERNELS = {
-    "advance": ["hpf::k_advance<true>", "hpf::k_advance<false>", "hpf::k_advance_cells<true>",
-                "hpf::k_advance_cells<false>"] +
+    "advance": ["hpf::k_advance<%s, %s>" % (r0, pipe) for r0 in ("true", "false") for pipe in ("true", "false")] +
+               ["hpf::k_advance_cells<true>", "hpf::k_advance_cells<false>"] +
                ["hpf::k_advance_scatter<%s, %d, %s>" % (r0, n, pipe) for r0 in ("true", "false") for n in (256, 512)
                 for pipe in ("true", "false")],
     "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum<false>",
@@ -313,6 +315,9 @@ def main():
                     help="fused pass on cell-sorted beads (scatter: with the density deposit)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every call from Python instead of replaying HIP graphs")
+    ap.add_argument("--field-interval", type=int, default=10,
+                    help="also time the workload with the density field rebuilt every n steps "
+                         "(the MD-SCF update interval; 0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hPF-MD path here runs on a single MI355X "
@@ -376,6 +381,15 @@ def main():
                        "value": r2["N"] * args.steps / (r2["ms_total"] * 1e-3),
                        "ms_per_step": r2["ms_total"] / args.steps,
                        "note": "working set fits the 256 MB Infinity Cache"}
+    if args.field_interval > 1 and fused:
+        r3 = run_workload(args.config, args.steps, args.warmup, args.sort_every, instrument=False,
+                          fused=True, graph=not args.eager, halo=args.halo, advance=args.advance,
+                          field_every=args.field_interval)
+        out["field_interval"] = {"workload": r3["spec"].name, "field_every": args.field_interval,
+                                 "value": r3["N"] * args.steps / (r3["ms_total"] * 1e-3),
+                                 "ms_per_step": r3["ms_total"] / args.steps,
+                                 "note": "density field rebuilt every field_every steps (MD-SCF); "
+                                         "value above rebuilds it every step"}
     if not args.no_batch:
         out["batched_sweep"] = run_batched_sweep()
     if not args.no_cpu_baseline:

@@ -537,7 +537,7 @@ __device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const 
 
 // Fused pass over the beads. Positions go to R_next so that bond partners
 // are always read at x_n.
-template <bool kR0Zero>
+template <bool kR0Zero, bool kPipe>
 __global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict__ R,
                                                        float4* __restrict__ R_next,
                                                        float4* __restrict__ Vel,
@@ -558,9 +558,30 @@ __global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict_
     KinAcc acc;
     double e = 0.0;
     bool bad_bead = false, bad_bond = false, nonfinite = false;
-    FOR_BEADS(w, i) {
-        advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box, inv_mass, dt, hdt, F_out,
-                              acc, e, bad_bead, bad_bond, nonfinite);
+    if (kPipe) {
+        // software-pipelined as in k_advance_scatter (bond table of at most kPreBonds
+        // rows): a thread's beads are i, i + stride, ... (one per chunk of its walk), and
+        // the next one's own loads stay in flight through this one's arithmetic
+        int64_t i = w.first + threadIdx.x;
+        BeadIn cur;
+        if (i < w.end)
+            bead_fetch(cur, i, R, Vel, T, bonds, D, N, inv_mass);
+        for (; i < w.end; i += w.stride) {
+            BeadLoads L;
+            bead_issue(L, cur, i, m, K, G, R, N);
+            __builtin_amdgcn_sched_barrier(0);
+            BeadIn nxt;
+            bead_fetch(nxt, i + w.stride < w.end ? i + w.stride : i, R, Vel, T, bonds, D, N, inv_mass);
+            __builtin_amdgcn_sched_barrier(0);
+            bead_finish<kR0Zero>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt, F_out, acc, e, bad_bead,
+                                 bad_bond, nonfinite);
+            cur = nxt;
+        }
+    } else {
+        FOR_BEADS(w, i) {
+            advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box, inv_mass, dt, hdt,
+                                  F_out, acc, e, bad_bead, bad_bond, nonfinite);
+        }
     }
     if (bad_bead)
         raise_flag(HPF_FLAG_BAD_BEAD);
@@ -867,12 +888,14 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
     auto* Vp = reinterpret_cast<float4*>(Vel);
     auto* Gp = reinterpret_cast<const float4*>(G);
     auto* Fo = reinterpret_cast<float4*>(F_out);
-    if (r0 == 0.0f)
-        hipLaunchKernelGGL(k_advance<true>, g, bl, 0, s, Rp, Rn, Vp, T, N, m, K, Gp, bonds, D, k, r0, box,
-                           inv_mass, dt, Fo, e_part, kin_part);
-    else
-        hipLaunchKernelGGL(k_advance<false>, g, bl, 0, s, Rp, Rn, Vp, T, N, m, K, Gp, bonds, D, k, r0,
-                           box, inv_mass, dt, Fo, e_part, kin_part);
+    // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
+    using AdvFn = void (*)(const float4*, float4*, float4*, const uint8_t*, int64_t, MeshK, int, const float4*,
+                           const int32_t*, int, float, float, BoxK, const float*, float, float4*, double*, double*);
+    const bool pipe = D <= kPreBonds;
+    const AdvFn fn = r0 == 0.0f ? (pipe ? k_advance<true, true> : k_advance<true, false>)
+                                : (pipe ? k_advance<false, true> : k_advance<false, false>);
+    hipLaunchKernelGGL(fn, g, bl, 0, s, Rp, Rn, Vp, T, N, m, K, Gp, bonds, D, k, r0, box, inv_mass, dt, Fo,
+                       e_part, kin_part);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 

@@ -28,7 +28,8 @@ class HpfState:
     """One periodic system on the GPU: beads, bond table, mesh buffers."""
 
     def __init__(self, R, Vel, T, tag, bonds, L, M, K, kT, inv_kappa, chi, k_bond, r0, dt,
-                 device="cuda", sort_brick=8, halo=1, advance_halo=1, advance="scatter"):
+                 device="cuda", sort_brick=8, halo=1, advance_halo=1, advance="scatter",
+                 field_every=1):
         dev = torch.device(device)
         self.N = int(R.shape[0])
         self.K = int(K)
@@ -46,6 +47,13 @@ class HpfState:
         # deposits x_n+1, so the next step only finishes the density), "plain" = hpf_advance,
         # "cells" = hpf_advance_cells. Unsorted beads always take hpf_advance.
         self.advance_mode = advance
+        # Field-update interval (MD-SCF section): the density field (counts, V, G) is rebuilt
+        # at force evaluations whose index is a multiple of field_every (evaluation 0 is
+        # start(), evaluation s comes after step s); the others gather from the last G, and
+        # the reported W is the last rebuild's.
+        if int(field_every) < 1:
+            raise ValueError("field_every must be >= 1")
+        self.field_every = int(field_every)
         self.density_pending = False   # partial boxes + counts hold the deposit of the current R
         self.sorted = False      # storage order comes from hpf_sort_by_cell
         nm = self.mesh.M[0] * self.mesh.M[1] * self.mesh.M[2]
@@ -112,20 +120,28 @@ class HpfState:
         else:
             hpf.hpf_density_scatter(self.R, self.T, self.mesh, self.K, self.counts, stream)
 
-    def field_forces(self, report=False, stream=None):
-        """F = field force (scatter, potential, gradient, gather)."""
-        self.scatter(stream)
-        hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V,
-                                self.part[ROW_W] if report else None, stream)
-        hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
+    def rebuilds_field(self, evaluation: int) -> bool:
+        """Whether force evaluation `evaluation` rebuilds the density field."""
+        return evaluation % self.field_every == 0
+
+    def field_forces(self, report=False, stream=None, rebuild=True):
+        """F = field force (scatter, potential, gradient, gather); without `rebuild`, only the
+        gather from the last gradient. W partials are kept whenever the interval exceeds one,
+        so that the steps until the next rebuild report the field energy in force."""
+        if rebuild:
+            self.scatter(stream)
+            hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V,
+                                    self.part[ROW_W] if (report or self.field_every > 1) else None,
+                                    stream)
+            hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
         hpf.hpf_force_gather(self.R, self.T, self.mesh, self.K, self.G, self.F, stream)
 
     def bond_forces(self, report=False, stream=None):
         hpf.bond_forces(self.R, self.bonds if self.bonds.shape[0] else None, self.k_bond, self.r0,
                         self.box, self.F, self.part[ROW_EB] if report else None, stream)
 
-    def forces(self, report=False, stream=None):
-        self.field_forces(report, stream)
+    def forces(self, report=False, stream=None, rebuild=True):
+        self.field_forces(report, stream, rebuild)
         self.bond_forces(report, stream)
 
     def step(self, report=False, sort=False, stream=None):
@@ -133,7 +149,7 @@ class HpfState:
         hpf.verlet_step(self.R, self.Vel, self.F, self.dt, self.box, 1, stream=stream)
         if sort:
             self.sort(stream)
-        self.forces(report, stream)
+        self.forces(report, stream, rebuild=self.rebuilds_field(self.steps_done + 1))
         hpf.verlet_step(None, self.Vel, self.F, self.dt, self.box, 2,
                         kin_part=self.part[ROW_KE:ROW_KE + 4] if report else None, stream=stream)
         if report:
@@ -163,9 +179,11 @@ class HpfState:
         Bitwise equal to step() followed by the next step's first half step."""
         if sort:
             self.sort(stream)
-        self.potential(report, stream)
-        hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
-        self.advance(report, stream)
+        # this step's force evaluation is number steps_done + 1 (start() was number 0)
+        if self.rebuilds_field(self.steps_done + 1):
+            self.potential(report or self.field_every > 1, stream)
+            hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
+        self.advance(report, stream, deposit=self.rebuilds_field(self.steps_done + 2))
         if report:
             hpf.hpf_reduce_partials(self.part, N_ROWS, self.energy, stream)
         self.steps_done += 1
@@ -189,15 +207,16 @@ class HpfState:
     def uses_scatter_advance(self) -> bool:
         return self.advance_mode == "scatter" and self.sorted and self.cells_ok
 
-    def advance(self, report=False, stream=None):
+    def advance(self, report=False, stream=None, deposit=True):
         """Fused forces + Verlet pass, x_n -> x_n+1 (with the density deposit of x_n+1, or the
         brick-box variant, when cell-sorted). Counts must be zero on entry (the potential pass
-        leaves them so)."""
+        leaves them so). Without `deposit` (the next step keeps the field) the plain pass runs
+        instead of the depositing one; the beads move the same either way."""
         bonds = self.bonds if self.bonds.shape[0] else None
         e_part = self.part[ROW_EB] if report else None
         kin_part = self.part[ROW_KE:ROW_KE + 4] if report else None
         self.density_pending = False
-        if self.uses_scatter_advance():
+        if deposit and self.uses_scatter_advance():
             hpf.hpf_advance_scatter(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
                                     self.k_bond, self.r0, self.box, self.dt, self.cell_start, self.B,
                                     self.halo, self.counts, self.scatter_work, e_part=e_part,
