@@ -388,6 +388,8 @@ def main():
         out["field_interval"] = {"workload": r3["spec"].name, "field_every": args.field_interval,
                                  "value": r3["N"] * args.steps / (r3["ms_total"] * 1e-3),
                                  "ms_per_step": r3["ms_total"] / args.steps,
+                                 "ke_per_bead_end": float(r3["energies"]["KE"]) / r3["N"],
+                                 "ke_per_bead_end_every_step": float(r["energies"]["KE"]) / r["N"],
                                  "note": "density field rebuilt every field_every steps (MD-SCF); "
                                          "value above rebuilds it every step"}
     if not args.no_batch:
