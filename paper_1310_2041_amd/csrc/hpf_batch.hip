@@ -37,7 +37,7 @@ struct ItemK {
 };
 
 constexpr int kBThreads = 256;
-constexpr int kASThreadsBatch = 256;
+constexpr int kASThreadsBatch = 512;
 
 __device__ __forceinline__ TileK tile_of(const RepK& r, int B, int h)
 {

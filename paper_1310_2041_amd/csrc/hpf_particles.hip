@@ -698,11 +698,12 @@ __global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __res
 // not bin, are added to `counts` with global atomics; the partial sum pass
 // (k_scatter_sum<true>, or the fused finish + potential) then completes the
 // counts of x_{n+1}.
-// Workgroup size: 256 threads, or 512 when there are few bricks (fewer than
-// kASFewBricks), so that a small mesh still fills the chip with waves.
+// Workgroup size: 512 threads (two workgroups of 8 waves per CU at 4 waves
+// per SIMD); with the software-pipelined loop this measured faster than 256
+// threads at every mesh size tried, and a small mesh still fills the chip.
 // kPipe selects the software-pipelined bead loop (bond tables of at most
 // kPreBonds rows); the plain loop serves wider tables.
-constexpr int kASFewBricks = 2048;
+constexpr int kASThreadsDefault = 512;
 
 template <bool kR0Zero, int kASThreads, bool kPipe>
 __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __restrict__ R,
@@ -977,18 +978,13 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
     auto* Gp = reinterpret_cast<const float4*>(G);
     auto* Fo = reinterpret_cast<float4*>(F_out);
     // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
-    const bool few = tk.ntiles < kASFewBricks, pipe = D <= kPreBonds;
-    if (few && pipe)
-        return launch_advance_scatter_t<512, true>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
-                                                   cell_start, partials, counts, Fo, e_part, kin_part, s);
-    if (few)
-        return launch_advance_scatter_t<512, false>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
-                                                    cell_start, partials, counts, Fo, e_part, kin_part, s);
-    if (pipe)
-        return launch_advance_scatter_t<256, true>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
-                                                   cell_start, partials, counts, Fo, e_part, kin_part, s);
-    return launch_advance_scatter_t<256, false>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt,
-                                                cell_start, partials, counts, Fo, e_part, kin_part, s);
+    if (D <= kPreBonds)
+        return launch_advance_scatter_t<kASThreadsDefault, true>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box,
+                                                                 inv_mass, dt, cell_start, partials, counts, Fo,
+                                                                 e_part, kin_part, s);
+    return launch_advance_scatter_t<kASThreadsDefault, false>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box,
+                                                              inv_mass, dt, cell_start, partials, counts, Fo,
+                                                              e_part, kin_part, s);
 }
 
 hpf_status_t launch_scatter_finish(const unsigned long long* partials, const TileK& tk, int K,
