@@ -148,3 +148,29 @@ def test_engine_cells_advance_matches_plain_over_steps():
     for key in ("KE", "E_bond", "W", "E_tot"):
         assert eb[-1][key] == pytest.approx(ea[-1][key], rel=1e-12)
     assert hpf.hpf_get_device_status() == 0
+
+
+def test_plain_pass_bond_table_widths():
+    """hpf_advance: a three-row bond table (third row all -1) takes the general bead loop and
+    must move beads exactly as the two-row table does (the software-pipelined loop); with no
+    table at all it must equal a table of -1 only."""
+    s = wl.build(wl.SPECS["c1"])
+    st = engine.HpfState.from_system(s)
+    st.sort()
+    field_of(st)
+    pad = torch.full((1, st.N), -1, dtype=torch.int32, device="cuda")
+
+    def run(bonds):
+        Rn, Vel = torch.empty_like(st.R), st.Vel.clone()
+        hpf.hpf_advance(st.R, Rn, Vel, st.T, st.mesh, st.K, st.G, bonds, st.k_bond, st.r0, st.box, st.dt)
+        return host(Rn), host(Vel)
+
+    two = run(st.bonds)
+    three = run(torch.cat([st.bonds, pad]).contiguous())
+    for x, y in zip(two, three):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    none = run(None)
+    empty = run(torch.full((2, st.N), -1, dtype=torch.int32, device="cuda"))
+    for x, y in zip(none, empty):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert hpf.hpf_get_device_status() == 0
