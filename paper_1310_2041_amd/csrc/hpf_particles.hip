@@ -28,13 +28,12 @@ struct BeadWalk {
     int64_t block;
 };
 
-__device__ __forceinline__ BeadWalk bead_walk(int64_t N)
+__device__ __forceinline__ BeadWalk bead_walk(int64_t N, int64_t chunk = kPThreads)
 {
     const int64_t nb = gridDim.x, b = blockIdx.x;
     const int64_t ng = nb < 8 ? nb : 8;             // groups = XCDs that received workgroups
     const int64_t g = b % ng, idx = b / ng;
     const int64_t per_group = nb / ng + (g < nb % ng ? 1 : 0);
-    const int64_t chunk = kPThreads;
     const int64_t nchunk = (N + chunk - 1) / chunk;
     const int64_t c0 = nchunk * g / ng, c1 = nchunk * (g + 1) / ng;
     BeadWalk w;
@@ -537,8 +536,12 @@ __device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const 
 
 // Fused pass over the beads. Positions go to R_next so that bond partners
 // are always read at x_n.
+// The software-pipelined form runs 512-thread workgroups over 512-bead chunks
+// (4% faster at 10M beads than 256); the general loop keeps kPThreads.
+constexpr int kAdvPipeThreads = 512;
+
 template <bool kR0Zero, bool kPipe>
-__global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict__ R,
+__global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float4* __restrict__ R,
                                                        float4* __restrict__ R_next,
                                                        float4* __restrict__ Vel,
                                                        const uint8_t* __restrict__ T, int64_t N,
@@ -550,8 +553,8 @@ __global__ __launch_bounds__(kPThreads) void k_advance(const float4* __restrict_
                                                        double* __restrict__ e_part,
                                                        double* __restrict__ kin_part)
 {
-    __shared__ double scratch[kPThreads / kWave];
-    const BeadWalk w = bead_walk(N);
+    __shared__ double scratch[kAdvPipeThreads / kWave];
+    const BeadWalk w = bead_walk(N, kPipe ? kAdvPipeThreads : kPThreads);
     clear_unused_slots(e_part, 1);
     clear_unused_slots(kin_part, 4);
     const float hdt = 0.5f * dt;
@@ -882,17 +885,19 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
 {
     if (N == 0 && !e_part && !kin_part)
         return HPF_OK;
-    const int64_t nb = bead_blocks(N, (e_part || kin_part) ? HPF_NPART : (1 << 20));
-    const dim3 g((unsigned)nb), bl(kPThreads);
+    // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
+    const bool pipe = D <= kPreBonds;
+    const int threads = pipe ? kAdvPipeThreads : kPThreads;
+    const int64_t cap = (e_part || kin_part) ? HPF_NPART : (1 << 20);
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((N + threads - 1) / threads, cap));
+    const dim3 g((unsigned)nb), bl(threads);
     auto* Rp = reinterpret_cast<const float4*>(R);
     auto* Rn = reinterpret_cast<float4*>(R_next);
     auto* Vp = reinterpret_cast<float4*>(Vel);
     auto* Gp = reinterpret_cast<const float4*>(G);
     auto* Fo = reinterpret_cast<float4*>(F_out);
-    // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
     using AdvFn = void (*)(const float4*, float4*, float4*, const uint8_t*, int64_t, MeshK, int, const float4*,
                            const int32_t*, int, float, float, BoxK, const float*, float, float4*, double*, double*);
-    const bool pipe = D <= kPreBonds;
     const AdvFn fn = r0 == 0.0f ? (pipe ? k_advance<true, true> : k_advance<true, false>)
                                 : (pipe ? k_advance<false, true> : k_advance<false, false>);
     hipLaunchKernelGGL(fn, g, bl, 0, s, Rp, Rn, Vp, T, N, m, K, Gp, bonds, D, k, r0, box, inv_mass, dt, Fo,

@@ -337,4 +337,5 @@ def test_per_bead_kernels_ragged_sizes(n_chains, chain_len):
     o2 = torch.zeros(4, dtype=torch.float64, device="cuda")
     hpf.hpf_reduce_partials(part1, 4, o1)
     hpf.hpf_reduce_partials(part2, 4, o2)
-    assert torch.equal(o1, o2)
+    # the fused pass groups its partials by 512-bead chunks, the separate call by 256
+    np.testing.assert_allclose(host(o2), host(o1), rtol=1e-12, atol=1e-9)

@@ -151,9 +151,9 @@ def test_determinism_bitwise():
 @pytest.mark.parametrize("cfg,steps,sort_every", [("c1", 30, 7), ("c2", 12, 5)])
 def test_fused_advance_equals_separate_calls_bitwise(cfg, steps, sort_every, advance):
     """The fused pass (hpf_advance, or hpf_advance_cells on cell-sorted beads) reproduces
-    gather + bonds + both half steps of the six calls bit for bit. hpf_advance also groups
-    its energy partials like the separate calls; hpf_advance_cells groups them by brick
-    walk, so its energies agree to FP64 rounding."""
+    gather + bonds + both half steps of the six calls bit for bit. Their energy partials are
+    grouped differently (512-bead chunks, or the brick walk, against the separate calls'
+    256-bead chunks), so energies agree to FP64 regrouping."""
     s = wl.build(wl.SPECS[cfg])
     a = engine.HpfState.from_system(s)
     a.start(sort=True)
@@ -168,14 +168,8 @@ def test_fused_advance_equals_separate_calls_bitwise(cfg, steps, sort_every, adv
         assert np.array_equal(x, y)
     for ea, eb in zip(Ea, Eb):
         for key in ("KE", "E_bond", "W"):
-            if advance == "plain":
-                assert ea[key] == eb[key]
-            else:
-                assert eb[key] == pytest.approx(ea[key], rel=1e-12)
-        if advance == "plain":
-            assert np.array_equal(ea["P"], eb["P"])
-        else:
-            np.testing.assert_allclose(eb["P"], ea["P"], rtol=1e-9, atol=1e-8)
+            assert eb[key] == pytest.approx(ea[key], rel=1e-12)
+        np.testing.assert_allclose(eb["P"], ea["P"], rtol=1e-9, atol=1e-8)
     assert hpf.hpf_get_device_status() == 0
 
 
