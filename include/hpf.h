@@ -445,7 +445,9 @@ typedef struct hpf_batch hpf_batch_t;   /* host object; owns no device memory */
 size_t hpf_batch_workspace_bytes(const hpf_replica_t* reps, int32_t n_rep,
                                  const hpf_batch_config_t* cfg);
 /* Build the replica table and work lists (synchronous host->device copies into
- * `work`). Buffers and workspace must outlive the batch and not move. */
+ * `work`). Buffers and workspace must outlive the batch and not move. The bond
+ * table bufs->bonds[0] is read back once (synchronously): a partner outside its
+ * own replica's bead range returns HPF_EINVAL. */
 hpf_status_t hpf_batch_create(const hpf_replica_t* reps, int32_t n_rep,
                               const hpf_batch_config_t* cfg, const hpf_batch_buffers_t* bufs,
                               void* work, size_t work_bytes, hpf_batch_t** out);
@@ -459,6 +461,13 @@ hpf_status_t hpf_batch_step(hpf_batch_t* batch, int32_t n_steps, int32_t report_
  * double[n_rep][8] = {KE, E_bond, W, E_tot, Px, Py, Pz, 0}. Any may be NULL. */
 hpf_status_t hpf_batch_current(const hpf_batch_t* batch, float** R, float** Vel, uint8_t** T,
                                int32_t** tag, int32_t** bonds, double** energies);
+/* Density counts of every replica at the current positions (the assignment of
+ * the MD-SCF section, as hpf_density_scatter computes it per system), e.g. for
+ * order parameters of a phase-diagram sweep. counts_out is uint64[K][sum_r M_r^3]
+ * device (replica r's block at K * (sum of the earlier replicas' M^3)), OVERWRITTEN;
+ * it must not be the batch's own counts buffer (HPF_EINVAL). The batch's state is
+ * not changed, so stepping continues as if the call had not been made. */
+hpf_status_t hpf_batch_density(hpf_batch_t* batch, uint64_t* counts_out, void* stream);
 /* Autotuner: times trial_steps steps for each candidate on the live system --
  * halo in {1,2} x mesh_chunk in {4096,16384}, with the fused deposit and with
  * a separate scatter (the latter also over bead_chunk in {1024..8192}) --

@@ -818,6 +818,23 @@ hpf_status_t hpf_batch_create(const hpf_replica_t* reps, int32_t n_rep, const hp
             return HPF_EINVAL;
     if (!bufs->counts || !bufs->V || !bufs->G)
         return HPF_EINVAL;
+    // every bond partner must lie in its own replica: a partner in another replica would
+    // couple two systems and take the wrong box's minimum image
+    if (c.D > 0 && L.Ntot > 0) {
+        std::vector<int32_t> tab((size_t)c.D * (size_t)L.Ntot);
+        if (hipMemcpy(tab.data(), bufs->bonds[0], sizeof(int32_t) * tab.size(), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return HPF_EHIP;
+        for (int r = 0; r < n_rep; ++r) {
+            const int64_t lo = reps[r].bead_offset, hi = lo + reps[r].n_beads;
+            for (int d = 0; d < c.D; ++d) {
+                const int32_t* row = tab.data() + (size_t)d * (size_t)L.Ntot;
+                for (int64_t i = lo; i < hi; ++i)
+                    if (row[i] != -1 && (row[i] < lo || row[i] >= hi))
+                        return HPF_EINVAL;
+            }
+        }
+    }
     hpf_batch* b = new (std::nothrow) hpf_batch;
     if (!b)
         return HPF_EINVAL;
@@ -914,6 +931,48 @@ hpf_status_t hpf_batch_step(hpf_batch_t* b, int32_t n_steps, int32_t report_last
         ++b->steps_done;
     }
     return HPF_OK;
+}
+
+hpf_status_t hpf_batch_density(hpf_batch_t* b, uint64_t* counts_out, void* stream)
+{
+    if (!b || !counts_out || counts_out == b->buf.counts)
+        return HPF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    const BatchLayout& L = b->L;
+    const int K = b->cfg.K, B = b->cfg.brick, h = b->cfg.halo;
+    const int P = B + 1 + 2 * h;
+    const RepK* reps = b->at<RepK>(L.off_reps);
+    const ItemK* bi = b->at<ItemK>(L.off_brick_items);
+    auto* out = reinterpret_cast<unsigned long long*>(counts_out);
+    auto* partials = b->at<unsigned long long>(L.off_partials);
+    if (b->n_brick_items == 0)
+        return HPF_OK;
+    if (b->pending) {
+        // the last fused pass deposited the current positions: its strays are in the
+        // batch's counts and its boxes in the partial buffer; neither is changed here
+        if (hipMemcpyAsync(out, b->buf.counts, sizeof(uint64_t) * (size_t)K * (size_t)L.nm_tot,
+                           hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return HPF_EHIP;
+        hipLaunchKernelGGL(k_batch_scatter_sum<true>, dim3((unsigned)b->n_brick_items), sum_block(b->n_brick_items),
+                           0, s, reps, bi, B, h, K, partials, out);
+    } else {
+        const size_t smem = scatter_cells_smem(K, P);
+        if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_scatter_bricks),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+            return HPF_EINVAL;
+        uint32_t* strays = b->at<uint32_t>(L.off_strays);
+        const auto* R = reinterpret_cast<const float4*>(b->buf.R[b->rcur]);
+        const uint8_t* T = b->buf.T[b->scur];
+        const uint32_t* cs = b->at<uint32_t>(L.off_start);
+        hipLaunchKernelGGL(k_zero_u32_one, dim3(1), dim3(1), 0, s, strays);
+        hipLaunchKernelGGL(k_batch_scatter_bricks, dim3((unsigned)b->n_brick_items), dim3(kTcThreads), smem, s, reps,
+                           bi, B, h, K, R, T, cs, partials, strays);
+        hipLaunchKernelGGL(k_batch_scatter_sum<false>, dim3((unsigned)b->n_brick_items), sum_block(b->n_brick_items),
+                           0, s, reps, bi, B, h, K, partials, out);
+        hipLaunchKernelGGL(k_batch_scatter_strays, dim3(256), dim3(kTcThreads), 0, s, reps, b->nrep, K, R, T, cs,
+                           strays, out);
+    }
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
 hpf_status_t hpf_batch_current(const hpf_batch_t* b, float** R, float** Vel, uint8_t** T, int32_t** tag,

@@ -55,6 +55,8 @@ class HpfState:
             raise ValueError("field_every must be >= 1")
         self.field_every = int(field_every)
         self.density_pending = False   # partial boxes + counts hold the deposit of the current R
+        # when True, the fused passes also store the total force at x_n into F (F_out)
+        self.keep_force = False
         self.sorted = False      # storage order comes from hpf_sort_by_cell
         nm = self.mesh.M[0] * self.mesh.M[1] * self.mesh.M[2]
         self.nm = nm
@@ -90,6 +92,21 @@ class HpfState:
         self.part = torch.zeros((N_ROWS, hpf.HPF_NPART), dtype=torch.float64, device=dev)
         self.energy = torch.zeros(8, dtype=torch.float64, device=dev)
         self.steps_done = 0
+
+    _SWAPPED = ("R", "R2", "Vel", "Vel2", "T", "T2", "tag", "tag2", "bonds", "bonds2")
+
+    def snapshot(self) -> dict:
+        """The host-side stepping state (which buffers are current, the step count, whether a
+        deposit is pending), so that a caller that replays captured steps can put the object
+        back in step with the device."""
+        d = {k: getattr(self, k) for k in self._SWAPPED}
+        d.update(steps_done=self.steps_done, density_pending=self.density_pending,
+                 sorted=self.sorted)
+        return d
+
+    def restore(self, d: dict):
+        for k, v in d.items():
+            setattr(self, k, v)
 
     @classmethod
     def from_system(cls, s, **kw):
@@ -215,20 +232,22 @@ class HpfState:
         bonds = self.bonds if self.bonds.shape[0] else None
         e_part = self.part[ROW_EB] if report else None
         kin_part = self.part[ROW_KE:ROW_KE + 4] if report else None
+        F_out = self.F if self.keep_force else None
         self.density_pending = False
         if deposit and self.uses_scatter_advance():
             hpf.hpf_advance_scatter(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
                                     self.k_bond, self.r0, self.box, self.dt, self.cell_start, self.B,
-                                    self.halo, self.counts, self.scatter_work, e_part=e_part,
+                                    self.halo, self.counts, self.scatter_work, F_out=F_out, e_part=e_part,
                                     kin_part=kin_part, stream=stream)
             self.density_pending = True
         elif self.uses_cells_advance():
             hpf.hpf_advance_cells(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
                                   self.k_bond, self.r0, self.box, self.dt, self.cell_start, self.B,
-                                  self.advance_halo, e_part=e_part, kin_part=kin_part, stream=stream)
+                                  self.advance_halo, F_out=F_out, e_part=e_part, kin_part=kin_part,
+                                  stream=stream)
         else:
             hpf.hpf_advance(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
-                            self.k_bond, self.r0, self.box, self.dt, e_part=e_part,
+                            self.k_bond, self.r0, self.box, self.dt, F_out=F_out, e_part=e_part,
                             kin_part=kin_part, stream=stream)
         self.R, self.R2 = self.R2, self.R
 
@@ -353,6 +372,13 @@ class BatchState:
 
     def step(self, n=1, report_last=True, stream=None):
         hpf.hpf_batch_step(self.handle, n, report_last, stream)
+
+    def density(self, stream=None):
+        """Density counts of every replica at the current positions, as a new int64 tensor
+        holding uint64 bits (replica r's [K][M_r^3] block follows replica r-1's)."""
+        out = torch.empty_like(self.counts)
+        hpf.hpf_batch_density(self.handle, out, stream)
+        return out
 
     def tune(self, trial_steps=3, stream=None):
         cfg, ms = hpf.hpf_batch_tune(self.handle, trial_steps, stream)

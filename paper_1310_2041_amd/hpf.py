@@ -116,6 +116,7 @@ _SIGNATURES = {
     "hpf_batch_current": ([_P, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                            C.POINTER(C.c_void_p)], C.c_int32),
+    "hpf_batch_density": ([_P, _P, _P], C.c_int32),
     "hpf_batch_tune": ([_P, C.c_int32, _P, C.POINTER(BatchConfig), C.POINTER(C.c_float),
                         C.POINTER(C.c_int32)], C.c_int32),
     "hpf_batch_destroy": ([_P], C.c_int32),
@@ -496,6 +497,11 @@ def hpf_batch_current(h) -> dict:
     ptrs = [C.c_void_p() for _ in range(6)]
     _check("hpf_batch_current", lib().hpf_batch_current(h, *[C.byref(p) for p in ptrs]))
     return dict(zip(["R", "Vel", "T", "tag", "bonds", "energies"], [p.value for p in ptrs]))
+
+
+def hpf_batch_density(h, counts_out, stream=None):
+    _check("hpf_batch_density", lib().hpf_batch_density(h, _dev(counts_out, "counts_out", _U64),
+                                                        _stream(stream)))
 
 
 def hpf_batch_tune(h, trial_steps: int, stream=None):

@@ -121,25 +121,92 @@ def test_batch_rejects_small_meshes():
         engine.BatchState([s])
 
 
+def _replica_counts(b, counts, r):
+    """Replica r's block of a batch counts tensor as uint64 [K, Mz, My, Mx]."""
+    off = b.K * sum(b.nm[:r])
+    M = tuple(b.reps[r].M)
+    blk = counts[off:off + b.K * b.nm[r]].cpu().numpy().view(np.uint64)
+    return blk.reshape(b.K, M[2], M[1], M[0])
+
+
+def _by_tag(arr, tag):
+    out = np.zeros_like(arr)
+    out[tag] = arr
+    return out
+
+
+def test_batch_density_matches_oracle():
+    """hpf_batch_density: every replica's counts at the current positions bit-exact against
+    the oracle, after the start (plain cell scatter) and after fused steps (the pending
+    deposit finished into the output), and the batch steps on unchanged."""
+    systems = _replicas()
+    b = engine.BatchState(systems, sort_every=5)
+    ref = engine.BatchState(systems, sort_every=5)
+    b.start()
+    ref.start()
+    for n in (0, 7):
+        if n:
+            b.step(n, report_last=True)
+            ref.step(n, report_last=True)
+        out = b.density()
+        for r, s in enumerate(systems):
+            R, _, T, tag, _ = b.replica_beads(r)
+            want, sk = oracle.density(_by_tag(R, tag), _by_tag(T, tag), s.L, s.M, s.K)
+            assert sk == 0
+            assert np.array_equal(_replica_counts(b, out, r), want), (n, r)
+    b.step(3, report_last=True)
+    ref.step(3, report_last=True)
+    for r in range(len(systems)):
+        for x, y in zip(b.replica_beads(r), ref.replica_beads(r)):
+            assert np.array_equal(x, y)
+    assert hpf.hpf_get_device_status() == 0
+
+
+def test_batch_rejects_bond_into_another_replica():
+    systems = _replicas()[:2]
+    systems[0].bonds[0, 3] = systems[0].N + 2        # a partner inside replica 1
+    with pytest.raises(hpf.HpfError):
+        engine.BatchState(systems)
+
+
 @pytest.mark.slow
 def test_full_size_64_replica_sweep_sampled():
     """The 64-replica sweep at full size (6.8M beads) in the benchmark's launch shape (one
-    batch, 20 steps per HIP graph): the step-0 energies of sampled replicas match the oracle,
-    and after a replay replicas 0, 31 and 63 equal their single-system runs bit for bit."""
+    batch, 20 steps per HIP graph). For replicas 0, 31 and 63: the counts at the current
+    positions bit-exact against the oracle after the start and after a replay (the pending
+    fused deposit), the step-0 forces (from the first half kick) within 1e-5 and the
+    step-0 energies of the oracle; after the replay each equals its single-system run bit
+    for bit."""
     systems = [wl.build_replica(sp, r) for r, sp in enumerate(wl.replica_specs())]
     b = engine.BatchState(systems, sort_every=10)
     b.start()
     E0 = b.energies()
+    out = b.density()
     for r in (0, 31, 63):
-        _, _, Eo = oracle.run(systems[r], 0)
+        s = systems[r]
+        _, _, Eo = oracle.run(s, 0)
         assert E0[r, 0] == pytest.approx(Eo[0, 0], rel=1e-12)        # KE
         assert E0[r, 1] == pytest.approx(Eo[0, 1], rel=1e-6)         # E_bond (FP32 terms)
         assert E0[r, 2] == pytest.approx(Eo[0, 2], rel=1e-9)         # W
+        R, V, T, tag, _ = b.replica_beads(r)
+        want, _ = oracle.density(_by_tag(R, tag), s.T, s.L, s.M, s.K)
+        assert np.array_equal(_replica_counts(b, out, r), want), r
+        # v_1/2 = v_0 + dt/2 F(x_0): the step-0 force from the batched kernels
+        Ff, Fb, _ = oracle.forces(s)
+        F_gpu = (_by_tag(V, tag)[:, :3].astype(np.float64) - s.V[:, :3]) / (0.5 * s.dt)
+        err = np.abs(F_gpu - (Ff + Fb)).max() / np.abs(Ff + Fb).max()
+        assert err <= 1e-5, (r, err)
+    del out
     torch.cuda.synchronize()
     g = engine.Graph(lambda: b.step(20, report_last=True))
     g.launch()
     torch.cuda.synchronize()
+    out = b.density()
     for r in (0, 31, 63):
+        R, _, T, tag, _ = b.replica_beads(r)
+        want, _ = oracle.density(_by_tag(R, tag), systems[r].T, systems[r].L, systems[r].M,
+                                 systems[r].K)
+        assert np.array_equal(_replica_counts(b, out, r), want), r
         st, _ = _single(systems[r], 20, 10)
         for x, y in zip(b.replica_beads(r), st.host_beads()):
             assert np.array_equal(x, y), f"replica {r}"

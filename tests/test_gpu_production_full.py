@@ -1,0 +1,147 @@
+"""GPU: the production step where its workgroups loop.
+
+The depositing fused pass (hpf_advance_scatter) and the fused finish + potential
+(hpf_field_potential_cells) launch at most HPF_NPART workgroups, so on a mesh of
+more than HPF_NPART bricks every workgroup walks several bricks; the plain
+fused pass (hpf_advance) carries each thread's prefetched bead across chunks
+once N exceeds HPF_NPART * 512 beads. These tests run both regimes against the
+FP64 oracle (density assignment of the MD-SCF section, eqs. (4), (6) and (7))
+and against the six separate calls, and check the cell sort's large-chunk
+paths against the oracle's permutation.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from gpu_util import by_tag, counts_np, host, rel_max  # noqa: E402
+from paper_1310_2041_amd import engine, hpf  # noqa: E402
+from synth import workloads as wl  # noqa: E402
+
+
+def many_brick_system():
+    """M = 136 and 8-cell bricks: 17^3 = 4913 bricks, more than HPF_NPART (4096) workgroups,
+    so every workgroup of the depositing pass and of the finish walks two bricks. K = 3,
+    20,000 chains of 12 beads plus 60,000 solvent beads (300,000 beads)."""
+    return wl.small_system(20000, 12, 149.6, 136, K=3, n_solvent=60000, seed=71)
+
+
+def test_depositing_step_where_workgroups_walk_bricks():
+    """Four production steps (sorting every other step) on 4913 bricks: each step's deposit
+    counts bit-exact, V within one FP32 rounding, W, E_bond and KE, and the total and field
+    forces at x_n within 1e-5 of the oracle; every bead equal bit for bit to the six calls."""
+    s = many_brick_system()
+    st = engine.HpfState.from_system(s, halo=2)
+    st.keep_force = True
+    nb = -(-st.mesh.M[0] // st.B) ** 3
+    assert nb + 1 > hpf.HPF_NPART
+    ref = engine.HpfState.from_system(s, halo=2)
+    st.start(sort=True)
+    ref.start(sort=True)
+    st.prime()
+    deposits_checked = 0
+    for step in range(4):
+        sort = step % 2 == 0
+        tag = host(st.tag)
+        x_n = by_tag(host(st.R), tag, s.N)
+        v_half = by_tag(host(st.Vel), tag, s.N)
+        if st.density_pending:
+            # the last pass deposited x_n: finish a copy of its counts
+            c = st.counts.clone()
+            hpf.hpf_density_finish_cells(c, st.N, st.mesh, st.K, st.B, st.halo, st.scatter_work)
+            want, sk = oracle.density(x_n, s.T, s.L, s.M, s.K)
+            assert sk == 0
+            assert np.array_equal(counts_np(c, s.K, s.M), want)
+            deposits_checked += 1
+            del c
+        st.step_fused(report=True, sort=sort)
+        ref.step(report=True, sort=sort)
+        # V of x_n from the fused finish + potential (or the plain scatter on the first step)
+        c_or, _ = oracle.density(x_n, s.T, s.L, s.M, s.K)
+        V_or, W_or = oracle.potential(c_or, s.L, s.M, s.N, s.kT, s.inv_kappa, s.chi)
+        V = host(st.V).reshape(V_or.shape).astype(np.float64)
+        assert (np.abs(V - V_or) <= 2.0 ** -23 * np.abs(V_or) + 1e-30).all()
+        Ff, Fb, e_or = oracle.forces(s, R=x_n)
+        e = st.energies()
+        assert e["W"] == pytest.approx(W_or, rel=1e-9)
+        assert e["W"] == pytest.approx(e_or["W"], rel=1e-9)
+        assert e["E_bond"] == pytest.approx(e_or["E_bond"], rel=1e-6)
+        # total force at x_n from the fused pass (F_out, in the storage order after the
+        # step's sort); field part = total - bond part
+        F = by_tag(host(st.F)[:, :3].astype(np.float64), host(st.tag), s.N)
+        assert rel_max(F, Ff + Fb) <= 1e-5
+        assert rel_max(F - Fb, Ff) <= 1e-5
+        # KE at v_n = v_{n-1/2} + dt/2 F(x_n)
+        v_n = v_half[:, :3].astype(np.float64) + 0.5 * s.dt * (Ff + Fb)
+        assert e["KE"] == pytest.approx(0.5 * (v_n ** 2).sum(), rel=1e-6)
+    assert deposits_checked == 3
+    ref.prime()
+    for x, y in zip(st.host_beads(), ref.host_beads()):
+        assert np.array_equal(x, y)
+    assert hpf.hpf_get_device_status() == 0
+
+
+@pytest.mark.slow
+def test_10m_blend_interval_fused_equals_six_calls_bitwise():
+    """The 10M-bead blend with the field rebuilt every 10 steps, 12 steps: the plain fused
+    pass (N > HPF_NPART * 512, so each thread carries its prefetched bead from chunk to
+    chunk), the depositing pass and the finish at 128^3 move every bead bit for bit as the
+    six separate calls do."""
+    s = wl.build(wl.SPECS["c3"])
+    a = engine.HpfState.from_system(s, field_every=10, halo=2)
+    b = engine.HpfState.from_system(s, field_every=10, halo=2)
+    del s
+    assert a.N > hpf.HPF_NPART * 512
+    a.start(sort=True)
+    Ea = a.run(12, report_every=1, sort_every=6)
+    a.prime()
+    b.start(sort=True)
+    b.prime()
+    Eb = b.run_fused(12, report_every=1, sort_every=6)
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
+    for ea, eb in zip(Ea, Eb):
+        for key in ("KE", "E_bond", "W"):
+            assert eb[key] == pytest.approx(ea[key], rel=1e-12)
+    assert hpf.hpf_get_device_status() == 0
+
+
+def _check_sort(s, B):
+    perm, keys = oracle.sort_perm(s.R, s.tag, s.L, s.M, B)
+    st = engine.HpfState.from_system(s, sort_brick=B)
+    hpf.hpf_get_device_status(clear=True)
+    st.sort()
+    R, Vel, T, tag, bonds = st.host_beads()
+    assert np.array_equal(tag, s.tag[perm])
+    assert np.array_equal(R, s.R[perm])
+    assert np.array_equal(Vel, s.V[perm])
+    assert np.array_equal(T, s.T[perm])
+    inv = np.empty(s.N, np.int64)
+    inv[perm] = np.arange(s.N)
+    b_old = s.bonds[:, perm]
+    assert np.array_equal(bonds, np.where(b_old >= 0, inv[np.maximum(b_old, 0)], -1))
+    nk = hpf.sort_key_count(st.mesh, B)
+    expect = np.searchsorted(np.sort(keys), np.arange(nk + 2), side="left")
+    expect[nk + 1] = s.N
+    assert np.array_equal(host(st.cell_start), expect)
+    assert hpf.hpf_get_device_status() == 0
+
+
+def test_sort_4096_tag_chunks_matches_oracle():
+    """4914 keys and 300,000 beads: the sort takes 4096-tag chunks (not the 1024-tag path of
+    small systems); permutation, renumbered bonds and cell_start against the oracle."""
+    s, _ = wl.permuted(many_brick_system(), seed=8)
+    _check_sort(s, 8)
+
+
+@pytest.mark.slow
+def test_sort_doubled_chunks_matches_oracle():
+    """35,938 keys (one-cell bricks on a 33^3 mesh) and 8.2M beads: the chunk x key table
+    would exceed its limit at 4096 tags, so the sort doubles its chunks to 8192 tags."""
+    s, _ = wl.permuted(wl.small_system(410000, 20, 33.0, 33, seed=72), seed=9)
+    _check_sort(s, 1)
