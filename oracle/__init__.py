@@ -22,7 +22,8 @@ _SRC = os.path.join(_HERE, "hpf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-          "-Wall", "-Wextra"]
+          "-Wall", "-Wextra", "-Wno-unknown-pragmas"]
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 
 def build(force: bool = True) -> str:
@@ -34,6 +35,18 @@ def build(force: bool = True) -> str:
     subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
     os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_omp(force: bool = True) -> str:
+    """The same source compiled with OpenMP into ``oracle/liboracle_omp.so``: used only to
+    time the oracle on all host cores (FP64 sums regrouped by thread; counts still exact)."""
+    if not force and os.path.exists(_LIB_OMP) and os.path.getmtime(_LIB_OMP) >= max(
+            os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "hpf_oracle.h"))):
+        return _LIB_OMP
+    tmp = _LIB_OMP + f".tmp{os.getpid()}"
+    subprocess.check_call(["gcc", *CFLAGS, "-fopenmp", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB_OMP)
+    return _LIB_OMP
 
 
 class _Mesh(C.Structure):
@@ -48,12 +61,28 @@ class _Params(C.Structure):
 
 
 _lib = None
+_lib_omp = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build(force=False))
+        _lib = _declare(C.CDLL(build(force=False)))
+    return _lib
+
+
+def lib_omp(threads: int):
+    """The OpenMP build (timing only), set to `threads` threads."""
+    global _lib_omp
+    if _lib_omp is None:
+        _lib_omp = _declare(C.CDLL(build_omp(force=False)))
+        _lib_omp.omp_set_num_threads.argtypes = [C.c_int]
+    _lib_omp.omp_set_num_threads(int(threads))
+    return _lib_omp
+
+
+def _declare(_lib):
+    if True:
         P = C.c_void_p
         _lib.or_mesh_init.argtypes = [C.POINTER(_Mesh), P, P]
         _lib.or_cell_weights.argtypes = [C.c_double, C.c_float, C.c_int32,
@@ -79,6 +108,13 @@ def lib():
         _lib.or_run_interval.restype = C.c_int
         _lib.or_sort_perm.argtypes = [P, P, C.c_int64, C.POINTER(_Mesh), C.c_int32, P, P]
         _lib.or_sort_perm.restype = C.c_int
+        _lib.or_philox4x32_10.argtypes = [P, P, P]
+        _lib.or_andersen.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_float, C.c_uint64,
+                                     C.c_int64, P]
+        _lib.or_andersen.restype = C.c_int64
+        _lib.or_run_nvt.argtypes = [P, P, P, P, P, C.c_int64, C.POINTER(_Params), C.c_double,
+                                    C.c_int32, C.c_int32, C.c_double, C.c_float, C.c_uint64, P]
+        _lib.or_run_nvt.restype = C.c_int
     return _lib
 
 
@@ -222,8 +258,10 @@ def forces(sys, R=None):
     return Ff, Fb, {"W": e2[0], "E_bond": e2[1], "skipped": int(rc)}
 
 
-def run(sys, n_steps, R=None, V=None, inv_mass=None):
-    """Velocity Verlet for n_steps; returns (R, V, energies[n_steps+1, 4] = KE, Eb, W, Etot)."""
+def run(sys, n_steps, R=None, V=None, inv_mass=None, threads=None):
+    """Velocity Verlet for n_steps; returns (R, V, energies[n_steps+1, 4] = KE, Eb, W, Etot).
+    With `threads`, the OpenMP build runs it on that many host threads (timing only: its FP64
+    sums are regrouped, so the energies may differ in the last bits)."""
     m = mesh(sys.L, sys.M)
     keep = []
     p = _params(m, _sysdict(sys), sys.chi, sys.bonds, keep)
@@ -232,8 +270,9 @@ def run(sys, n_steps, R=None, V=None, inv_mass=None):
     T = np.ascontiguousarray(sys.T, dtype=np.uint8)
     im = None if inv_mass is None else np.ascontiguousarray(inv_mass, dtype=np.float64)
     E = np.zeros((n_steps + 1, 4))
-    rc = lib().or_run(_p(Rd), _p(Vd), _p(T), None if im is None else _p(im), Rd.shape[0],
-                      C.byref(p), float(sys.dt), int(n_steps), _p(E))
+    L = lib() if threads is None else lib_omp(threads)
+    rc = L.or_run(_p(Rd), _p(Vd), _p(T), None if im is None else _p(im), Rd.shape[0],
+                  C.byref(p), float(sys.dt), int(n_steps), _p(E))
     if rc:
         raise MemoryError("oracle allocation failed")
     return Rd, Vd, E
@@ -269,3 +308,44 @@ def sort_perm(R, tag, L, M, B):
     if lib().or_sort_perm(_p(Rd), _p(tag), N, C.byref(m), int(B), _p(perm), _p(keys)):
         raise MemoryError("oracle allocation failed")
     return perm, keys
+
+
+def philox4x32_10(ctr, key):
+    """O12: the four 32-bit outputs of Philox4x32-10 for a counter (4 words) and key (2)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def andersen(V, tag, kT, p, seed, step, inv_mass=None):
+    """O13: velocities after the Andersen collisions of time level `step`; returns
+    (V [N, 3] float64, collision mask uint8 [N])."""
+    Vd = _pos(V).copy()
+    tg = np.ascontiguousarray(tag, dtype=np.int32)
+    im = None if inv_mass is None else np.ascontiguousarray(inv_mass, dtype=np.float64)
+    mask = np.zeros(Vd.shape[0], dtype=np.uint8)
+    lib().or_andersen(_p(Vd), _p(tg), None if im is None else _p(im), Vd.shape[0], float(kT),
+                      float(p), int(seed), int(step), _p(mask))
+    return Vd, mask
+
+
+def run_nvt(sys, n_steps, field_every, kT, p, seed, R=None, V=None, inv_mass=None):
+    """run_interval() with the Andersen thermostat after the second half kick of every step
+    (O13); p = collision probability per step. Returns (R, V, energies[n_steps+1, 4])."""
+    m = mesh(sys.L, sys.M)
+    keep = []
+    prm = _params(m, _sysdict(sys), sys.chi, sys.bonds, keep)
+    Rd = _pos(sys.R if R is None else R).copy()
+    Vd = _pos(sys.V if V is None else V).copy()
+    T = np.ascontiguousarray(sys.T, dtype=np.uint8)
+    tg = np.ascontiguousarray(sys.tag, dtype=np.int32)
+    im = None if inv_mass is None else np.ascontiguousarray(inv_mass, dtype=np.float64)
+    E = np.zeros((n_steps + 1, 4))
+    rc = lib().or_run_nvt(_p(Rd), _p(Vd), _p(T), _p(tg), None if im is None else _p(im), Rd.shape[0],
+                          C.byref(prm), float(sys.dt), int(n_steps), int(field_every), float(kT),
+                          float(p), int(seed), _p(E))
+    if rc:
+        raise MemoryError("oracle allocation failed")
+    return Rd, Vd, E

@@ -35,6 +35,14 @@
  *                       W = rho0 dV sum_v [ kT/2 sum_KK' chi phi_K phi_K'
  *                       + 1/(2 kappa) (sum_K phi_K - 1)^2 ], the functional
  *                       whose derivative by the bead count at v is V_K(v).
+ *   O12 generator       Philox4x32-10 (counter-based; or_philox4x32_10).
+ *   O13 Andersen        (or_andersen, or_run_nvt) the Integration methods
+ *                       section names the Andersen thermostat for NVT: after
+ *                       the second half kick of step s, each bead collides
+ *                       with probability p = (collision rate) dt and takes a
+ *                       new velocity from the Maxwell distribution at kT;
+ *                       the decision and the deviates come from O12 keyed on
+ *                       (tag, s), so they do not depend on the storage order.
  *   O11 field interval  (or_run_interval) the MD-SCF section keeps the stiff
  *                       bonded terms on the small time step but rebuilds the
  *                       soft density field only after many steps (the DPPC
@@ -45,6 +53,10 @@
  *                       rebuild at the current positions. Bonds are evaluated
  *                       every time. Reported W is that of the last rebuild
  *                       (reading: the field in force).
+ *
+ * Loops carry OpenMP pragmas that the parity build (no -fopenmp) ignores; a
+ * separately compiled OpenMP build serves only to time the oracle on all host
+ * cores (its density adds stay exact; its FP64 sums are regrouped by thread).
  *
  * Pins (what fixes each function independently of this file) are in the
  * CPU test suite: partition of unity, hand-derived single-bead weights,
@@ -109,6 +121,7 @@ int64_t or_density(const double* R, const uint8_t* T, int64_t N, const or_mesh_t
 {
     const int64_t nm = (int64_t)m->M[0] * m->M[1] * m->M[2];
     int64_t skipped = 0;
+#pragma omp parallel for reduction(+ : skipped) schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         int32_t c[3];
         uint32_t w[3][2];
@@ -124,6 +137,7 @@ int64_t or_density(const double* R, const uint8_t* T, int64_t N, const or_mesh_t
                     int32_t vy = (c[1] + ay) % m->M[1];
                     int32_t vz = (c[2] + az) % m->M[2];
                     uint64_t Wa = (uint64_t)w[0][ax] * w[1][ay] * w[2][az];
+#pragma omp atomic
                     nk[vertex_index(m, vx, vy, vz)] += Wa;
                 }
     }
@@ -138,6 +152,7 @@ void or_potential(const uint64_t* counts, const or_mesh_t* m, int64_t n_beads, i
     const double rho0 = (double)n_beads / vol;
     const double dV = vol / (double)nm;
     double w_sum = 0.0;
+#pragma omp parallel for reduction(+ : w_sum) schedule(static)
     for (int64_t v = 0; v < nm; ++v) {
         double phi[OR_MAX_TYPES];
         double total = 0.0;
@@ -167,6 +182,7 @@ void or_gradient(const double* V, const or_mesh_t* m, int32_t K, double* G)
     const double h[3] = {m->L[0] / Mx, m->L[1] / My, m->L[2] / Mz};
     for (int k = 0; k < K; ++k) {
         const double* Vk = V + k * nm;
+#pragma omp parallel for schedule(static)
         for (int32_t z = 0; z < Mz; ++z)
             for (int32_t y = 0; y < My; ++y)
                 for (int32_t x = 0; x < Mx; ++x) {
@@ -187,6 +203,7 @@ int64_t or_gather(const double* R, const uint8_t* T, int64_t N, const or_mesh_t*
 {
     const int64_t nm = (int64_t)m->M[0] * m->M[1] * m->M[2];
     int64_t skipped = 0;
+#pragma omp parallel for reduction(+ : skipped) schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         double f[3] = {0.0, 0.0, 0.0};
         int32_t c[3];
@@ -215,6 +232,7 @@ void or_bonds(const double* R, int64_t N, const int32_t* bonds, int32_t D, doubl
               double r0, const double L[3], double* F, double* E)
 {
     double e = 0.0;
+#pragma omp parallel for reduction(+ : e) schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         for (int32_t b = 0; b < D; ++b) {
             int32_t j = bonds[(int64_t)b * N + i];
@@ -254,6 +272,7 @@ static double wrap_coord(double x, double L)
 void or_verlet_half1(double* R, double* V, const double* F, const double* inv_mass,
                      int64_t N, double dt, const double L[3])
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         double im = inv_mass ? inv_mass[i] : 1.0;
         for (int a = 0; a < 3; ++a) {
@@ -266,21 +285,24 @@ void or_verlet_half1(double* R, double* V, const double* F, const double* inv_ma
 void or_verlet_half2(double* V, const double* F, const double* inv_mass, int64_t N,
                      double dt, double* out4)
 {
-    double ke = 0.0, p[3] = {0.0, 0.0, 0.0};
+    double ke = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+#pragma omp parallel for reduction(+ : ke, px, py, pz) schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         double im = inv_mass ? inv_mass[i] : 1.0;
         double mass = 1.0 / im;
         for (int a = 0; a < 3; ++a) {
             V[3 * i + a] += 0.5 * dt * F[3 * i + a] * im;
             ke += 0.5 * mass * V[3 * i + a] * V[3 * i + a];
-            p[a] += mass * V[3 * i + a];
         }
+        px += mass * V[3 * i + 0];
+        py += mass * V[3 * i + 1];
+        pz += mass * V[3 * i + 2];
     }
     if (out4) {
         out4[0] = ke;
-        out4[1] = p[0];
-        out4[2] = p[1];
-        out4[3] = p[2];
+        out4[1] = px;
+        out4[2] = py;
+        out4[3] = pz;
     }
 }
 
@@ -318,6 +340,7 @@ int64_t or_forces(const double* R, const uint8_t* T, int64_t N, const or_params_
 static double kinetic(const double* V, const double* inv_mass, int64_t N)
 {
     double ke = 0.0;
+#pragma omp parallel for reduction(+ : ke) schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         double mass = inv_mass ? 1.0 / inv_mass[i] : 1.0;
         for (int a = 0; a < 3; ++a)
@@ -342,6 +365,7 @@ int or_run(double* R, double* V, const uint8_t* T, const double* inv_mass, int64
     int rc = 0;
     if (or_forces(R, T, N, p, Ff, Fb, e2) < 0)
         rc = -1;
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < 3 * N; ++j)
         F[j] = Ff[j] + Fb[j];
     double ke = kinetic(V, inv_mass, N);
@@ -354,6 +378,7 @@ int or_run(double* R, double* V, const uint8_t* T, const double* inv_mass, int64
         or_verlet_half1(R, V, F, inv_mass, N, dt, p->mesh->L);
         if (or_forces(R, T, N, p, Ff, Fb, e2) < 0)
             rc = -1;
+#pragma omp parallel for schedule(static)
         for (int64_t j = 0; j < 3 * N; ++j)
             F[j] = Ff[j] + Fb[j];
         or_verlet_half2(V, F, inv_mass, N, dt, out4);
@@ -398,6 +423,7 @@ int or_run_interval(double* R, double* V, const uint8_t* T, const double* inv_ma
         double Eb = 0.0;
         memset(Fb, 0, sizeof(double) * (size_t)(3 * N));
         or_bonds(R, N, p->bonds, p->D, p->k_bond, p->r0, m->L, Fb, &Eb);
+#pragma omp parallel for schedule(static)
         for (int64_t j = 0; j < 3 * N; ++j)
             F[j] = Ff[j] + Fb[j];
         double ke;
@@ -408,6 +434,145 @@ int or_run_interval(double* R, double* V, const uint8_t* T, const double* inv_ma
         } else {
             ke = kinetic(V, inv_mass, N);
         }
+        double* e = energies + 4 * (int64_t)s;
+        e[0] = ke;
+        e[1] = Eb;
+        e[2] = W;
+        e[3] = ke + W + Eb;
+    }
+    free(counts);
+    free(Vf);
+    free(G);
+    free(Ff);
+    free(Fb);
+    free(F);
+    return rc;
+}
+
+/* O12: Philox4x32-10. Each round multiplies counter words 0 and 2 by the two
+ * round constants into 64-bit products; the new counter is (high word of the
+ * second product ^ word 1 ^ key 0, its low word, high word of the first
+ * product ^ word 3 ^ key 1, its low word). Between rounds the key advances by
+ * the two Weyl constants (golden ratio and sqrt(3) - 1, times 2^32). */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint64_t MUL0 = 0xD2511F53u, MUL1 = 0xCD9E8D57u;
+    const uint32_t WEYL0 = 0x9E3779B9u, WEYL1 = 0xBB67AE85u;
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += WEYL0;
+            k1 += WEYL1;
+        }
+        const uint64_t p0 = MUL0 * (uint64_t)c[0];
+        const uint64_t p1 = MUL1 * (uint64_t)c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        const uint32_t n3 = (uint32_t)p0;
+        c[0] = n0;
+        c[1] = n1;
+        c[2] = n2;
+        c[3] = n3;
+    }
+    for (int j = 0; j < 4; ++j)
+        out[j] = c[j];
+}
+
+static const double TWO_M24 = 1.0 / 16777216.0;     /* 2^-24 */
+
+/* O13: one bead's draw at (tag, step): collision decision and, if it collides,
+ * three standard normal deviates (Box-Muller, FP64). */
+static int andersen_draw(int32_t tag, int64_t step, uint64_t seed, uint32_t thr, double g[3])
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {(uint32_t)tag, (uint32_t)(uint64_t)step, (uint32_t)((uint64_t)step >> 32), 0u};
+    uint32_t r[4], r2[4];
+    or_philox4x32_10(ctr, key, r);
+    if ((r[0] >> 8) >= thr)
+        return 0;
+    ctr[3] = 1u;
+    or_philox4x32_10(ctr, key, r2);
+    const double pi = 3.14159265358979323846;
+    const double u1 = (double)((r[1] >> 8) + 1u) * TWO_M24;     /* (0, 1] */
+    const double u2 = (double)(r[2] >> 8) * TWO_M24;            /* [0, 1) */
+    const double u3 = (double)((r[3] >> 8) + 1u) * TWO_M24;
+    const double u4 = (double)(r2[0] >> 8) * TWO_M24;
+    const double rad1 = sqrt(-2.0 * log(u1));
+    const double rad2 = sqrt(-2.0 * log(u3));
+    g[0] = rad1 * cos(2.0 * pi * u2);
+    g[1] = rad1 * sin(2.0 * pi * u2);
+    g[2] = rad2 * cos(2.0 * pi * u4);
+    return 1;
+}
+
+/* Integer threshold of a collision probability p in [0, 1]: floor(p 2^24). */
+static uint32_t andersen_threshold(float p)
+{
+    if (!(p > 0.0f))
+        return 0u;
+    if (p >= 1.0f)
+        return 1u << 24;
+    return (uint32_t)floor((double)p * 16777216.0);
+}
+
+int64_t or_andersen(double* V, const int32_t* tag, const double* inv_mass, int64_t N, double kT,
+                    float p, uint64_t seed, int64_t step, uint8_t* mask)
+{
+    const uint32_t thr = andersen_threshold(p);
+    int64_t n = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double g[3];
+        const int hit = andersen_draw(tag[i], step, seed, thr, g);
+        if (mask)
+            mask[i] = (uint8_t)hit;
+        if (!hit)
+            continue;
+        const double sd = sqrt(kT * (inv_mass ? inv_mass[i] : 1.0));
+        for (int a = 0; a < 3; ++a)
+            V[3 * i + a] = sd * g[a];
+        ++n;
+    }
+    return n;
+}
+
+int or_run_nvt(double* R, double* V, const uint8_t* T, const int32_t* tag, const double* inv_mass,
+               int64_t N, const or_params_t* p, double dt, int32_t n_steps, int32_t field_every,
+               double kT, float p_coll, uint64_t seed, double* energies)
+{
+    if (field_every < 1)
+        return -2;
+    const or_mesh_t* m = p->mesh;
+    const int64_t nm = (int64_t)m->M[0] * m->M[1] * m->M[2];
+    uint64_t* counts = malloc(sizeof(uint64_t) * (size_t)(p->K * nm));
+    double* Vf = malloc(sizeof(double) * (size_t)(p->K * nm));
+    double* G = malloc(sizeof(double) * (size_t)(3 * p->K * nm));
+    double* Ff = malloc(sizeof(double) * (size_t)(3 * N + 1));
+    double* Fb = malloc(sizeof(double) * (size_t)(3 * N + 1));
+    double* F = malloc(sizeof(double) * (size_t)(3 * N + 1));
+    int rc = (counts && Vf && G && Ff && Fb && F) ? 0 : -1;
+    double W = 0.0;
+    for (int32_t s = 0; s <= n_steps && rc == 0; ++s) {
+        if (s > 0)
+            or_verlet_half1(R, V, F, inv_mass, N, dt, m->L);
+        if (s % field_every == 0) {
+            memset(counts, 0, sizeof(uint64_t) * (size_t)(p->K * nm));
+            or_density(R, T, N, m, p->K, counts);
+            or_potential(counts, m, N, p->K, p->kT, p->inv_kappa, p->chi, Vf, &W);
+            or_gradient(Vf, m, p->K, G);
+        }
+        or_gather(R, T, N, m, p->K, G, Ff);
+        double Eb = 0.0;
+        memset(Fb, 0, sizeof(double) * (size_t)(3 * N));
+        or_bonds(R, N, p->bonds, p->D, p->k_bond, p->r0, m->L, Fb, &Eb);
+        for (int64_t j = 0; j < 3 * N; ++j)
+            F[j] = Ff[j] + Fb[j];
+        if (s > 0) {
+            or_verlet_half2(V, F, inv_mass, N, dt, NULL);
+            or_andersen(V, tag, inv_mass, N, kT, p_coll, seed, s, NULL);
+        }
+        const double ke = kinetic(V, inv_mass, N);
         double* e = energies + 4 * (int64_t)s;
         e[0] = ke;
         e[1] = Eb;

@@ -111,6 +111,31 @@ int or_run_interval(double* R, double* V, const uint8_t* T, const double* inv_ma
                     const or_params_t* p, double dt, int32_t n_steps, int32_t field_every,
                     double* energies);
 
+/* O12 counter-based generator: Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11): a 4 x 32-bit counter
+ * and a 2 x 32-bit key give 4 x 32 random bits through ten rounds of two
+ * 32 x 32 -> 64-bit products with Weyl-sequence key updates. */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* O13 Andersen thermostat (Integration methods section: NVT by the Andersen
+ * thermostat). At time level `step` bead i (tag t_i) collides with the heat
+ * bath with probability p (= collision rate x dt): the 24-bit uniform
+ * integer (r0 >> 8) of Philox(ctr = (t_i, step_lo, step_hi, 0), key = seed)
+ * is compared with floor(p 2^24) in integers. A colliding bead gets
+ * v = sqrt(kT / m) (g0, g1, g2), g from Box-Muller on the 24-bit uniforms
+ * u = (r >> 8 [+ 1]) 2^-24 of r1, r2 (g0 = rad cos, g1 = rad sin) and of r3
+ * and word 0 of the counter (t_i, step_lo, step_hi, 1) (g2 = rad cos).
+ * Returns the number of collisions. mask (nullable) receives 1 per colliding bead. */
+int64_t or_andersen(double* V, const int32_t* tag, const double* inv_mass, int64_t N, double kT,
+                    float p, uint64_t seed, int64_t step, uint8_t* mask);
+
+/* or_run_interval with the Andersen thermostat applied after the second half
+ * kick of every step s (time level s), before that step's kinetic energy is
+ * taken. p = 0 is or_run_interval. */
+int or_run_nvt(double* R, double* V, const uint8_t* T, const int32_t* tag, const double* inv_mass,
+               int64_t N, const or_params_t* p, double dt, int32_t n_steps, int32_t field_every,
+               double kT, float p_coll, uint64_t seed, double* energies);
+
 /* a0: cell-list order (the paper reorders particles for cache hits and bins
  * them into cells, Algorithm 1 Kernel 1). key = index of the brick of B^3
  * cells holding the bead's cell, bricks numbered x fastest; beads that

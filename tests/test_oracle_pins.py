@@ -395,3 +395,110 @@ def test_run_interval_schedule_from_pinned_pieces(oracle_mod):
     # the schedule matters: interval 3 differs from rebuilding every evaluation
     R1, _, _ = oracle_mod.run(s, steps)
     assert not np.array_equal(R1, Ro)
+
+
+# ---- O12/O13: counter-based generator and Andersen thermostat (Integration methods section)
+
+def test_philox_known_answers(oracle_mod):
+    """Philox4x32-10 reproduces the generator's published known-answer vectors."""
+    n = 0
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(x, 16) for x in line.split()]
+        out = oracle_mod.philox4x32_10(w[0:4], w[4:6])
+        assert [int(x) for x in out] == w[6:10]
+        n += 1
+    assert n == 3
+
+
+def _thermo_system(n=200000, seed=3):
+    rng = np.random.default_rng(seed)
+    V = rng.standard_normal((n, 3))
+    tag = rng.permutation(n).astype(np.int32)
+    return V, tag
+
+
+def test_andersen_zero_rate_leaves_velocities(oracle_mod):
+    V, tag = _thermo_system(5000)
+    V2, mask = oracle_mod.andersen(V, tag, 1.0, 0.0, 77, 5)
+    assert not mask.any()
+    assert np.array_equal(V2, V)
+
+
+def test_andersen_collision_fraction_and_maxwell_statistics(oracle_mod):
+    """p = 0.3: the colliding fraction is p within its binomial error; the new velocities
+    are Maxwell at kT (mean 0, variance kT/m per component, normal quantiles, no
+    correlation between components), and beads that do not collide keep theirs."""
+    V, tag = _thermo_system()
+    n = V.shape[0]
+    kT = 2.5
+    V2, mask = oracle_mod.andersen(V, tag, kT, 0.3, 12345, 17)
+    hit = mask.astype(bool)
+    frac = hit.mean()
+    assert abs(frac - 0.3) <= 4.0 * np.sqrt(0.3 * 0.7 / n)
+    assert np.array_equal(V2[~hit], V[~hit])
+    g = V2[hit] / np.sqrt(kT)
+    m = g.size
+    assert abs(g.mean()) <= 4.0 / np.sqrt(m)
+    assert abs(g.var() - 1.0) <= 4.0 * np.sqrt(2.0 / m)
+    # fourth moment of a normal deviate is 3
+    assert abs((g ** 4).mean() - 3.0) <= 4.0 * np.sqrt(96.0 / m)
+    for a in range(3):
+        for b in range(a + 1, 3):
+            assert abs(np.mean(g[:, a] * g[:, b])) <= 4.0 / np.sqrt(g.shape[0])
+    # quantiles of the standard normal
+    from scipy import stats
+    assert stats.kstest(g.ravel(), "norm").pvalue > 1e-4
+
+
+def test_andersen_full_rate_and_mass_scaling(oracle_mod):
+    """p = 1 replaces every velocity; with inverse mass 4 the deviates are scaled by
+    sqrt(kT / m) = 2 sqrt(kT), bead for bead the same draws."""
+    V, tag = _thermo_system(20000)
+    V1, mask = oracle_mod.andersen(V, tag, 1.0, 1.0, 9, 3)
+    assert mask.all()
+    V4, _ = oracle_mod.andersen(V, tag, 1.0, 1.0, 9, 3, inv_mass=np.full(V.shape[0], 4.0))
+    np.testing.assert_allclose(V4, 2.0 * V1, rtol=0, atol=0)
+    assert abs(V1.var() - 1.0) <= 4.0 * np.sqrt(2.0 / V1.size)
+
+
+def test_andersen_draws_follow_tags_not_storage(oracle_mod):
+    """Draws are keyed on (tag, step): a permuted storage order permutes the result; another
+    step or seed gives uncorrelated draws."""
+    V, tag = _thermo_system(20000)
+    Va, ma = oracle_mod.andersen(V, tag, 1.0, 0.5, 4, 8)
+    perm = np.random.default_rng(1).permutation(V.shape[0])
+    Vb, mb = oracle_mod.andersen(V[perm], tag[perm], 1.0, 0.5, 4, 8)
+    assert np.array_equal(Vb, Va[perm]) and np.array_equal(mb, ma[perm])
+    Vc, _ = oracle_mod.andersen(V, tag, 1.0, 1.0, 4, 9)
+    Vd, _ = oracle_mod.andersen(V, tag, 1.0, 1.0, 5, 8)
+    Ve, _ = oracle_mod.andersen(V, tag, 1.0, 1.0, 4, 8)
+    for X in (Vc, Vd):
+        assert abs(np.corrcoef(X.ravel(), Ve.ravel())[0, 1]) <= 4.0 / np.sqrt(X.size)
+
+
+def test_run_nvt_without_collisions_is_run_interval(oracle_mod):
+    s = wl.small_system(60, 10, 9.0, 9, seed=11)
+    for n_f in (1, 3):
+        Ra, Va, Ea = oracle_mod.run_interval(s, 12, n_f)
+        Rb, Vb, Eb = oracle_mod.run_nvt(s, 12, n_f, 1.0, 0.0, 5)
+        assert np.array_equal(Ra, Rb) and np.array_equal(Va, Vb) and np.array_equal(Ea, Eb)
+
+
+def test_run_nvt_holds_the_bath_temperature(oracle_mod):
+    """Equipartition under the thermostat: with soft bonds (k = 10) and dt = 0.01, so that
+    velocity Verlet's own bias (of order (omega dt / 2)^2 for the stiffest bond mode) is
+    below 0.2 %, the mean kinetic energy after equilibration is 3/2 N kT within 2 % without
+    a field and within 3 % with one (the interpolated field force is not exactly
+    conservative). NVE from the same start stays far hotter."""
+    import dataclasses
+    base = wl.small_system(200, 10, 9.0, 9, seed=12)
+    soft = dataclasses.replace(base, k_bond=10.0, dt=0.01)
+    free = dataclasses.replace(soft, inv_kappa=0.0, chi=np.zeros((2, 2)))
+    for sysm, tol in ((free, 0.02), (soft, 0.03)):
+        _, _, E = oracle_mod.run_nvt(sysm, 1000, 1, 1.0, 0.1, 2024)
+        ke = E[500:, 0].mean() / sysm.N
+        assert abs(ke - 1.5) <= tol * 1.5, (tol, ke)
+    _, _, E0 = oracle_mod.run(base, 100)
+    assert E0[50:, 0].mean() / base.N > 10.0
