@@ -27,25 +27,42 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(name: str, N: int, K: int, nm: int, D: int) -> float:
-    """Bytes a kernel must move per launch (each array read / written once)."""
+    """Bytes a kernel must move per launch on the method's minimal data (FP32 x, v; uint8
+    types; 4-byte bond-partner slots; uint64 counts; FP32 V), each array read or written once.
+
+    The fused depositing pass "advance" does the gather, bonds and both Verlet halves and
+    deposits x_{n+1}: x, v, T read and x, v written (49 B per bead), the two bond-partner
+    slots (8 B), and per mesh point and species V read (4 B) and the count flush (8 B).
+    "finish_potential" reads and clears the counts (16 B) and writes V (4 B). Together
+    with the deposit read of x, T (13 B) that the fusion saves, these are the two-pass step
+    bytes 70 N + 32 K M^3. The gradient has no minimal-design bytes (the minimal pass reads
+    V at the corners instead); its entry, like those of the six separate calls, is at the
+    API level (their sum is 178 N + 56 K M^3)."""
     return {
-        "verlet_half1": 80.0 * N,                   # R, Vel read+write; F read
-        "density_scatter": 17.0 * N + 8.0 * K * nm,  # R, T read; counts written once
-        # counts of the positions the fused pass deposited, written once (the partial
-        # boxes between the two passes are this design's own traffic)
+        "verlet_half1": 60.0 * N,                   # x, v read + written; F read
+        "density_scatter": 13.0 * N + 8.0 * K * nm,  # x, T read; counts written once
         "density_finish": 8.0 * K * nm,
-        # counts of the deposited positions read and cleared, V written (the partial boxes
-        # are this design's own traffic)
         "finish_potential": 20.0 * K * nm,
         "field_potential": 20.0 * K * nm,            # counts read + cleared; V written
-        "field_gradient": 20.0 * K * nm,             # V read; G written
-        "force_gather": 33.0 * N + 16.0 * K * nm,    # R, T read; F written; G read once
-        "bond_forces": (48.0 + 4.0 * D) * N,         # R, bond table, F read; F written
-        "verlet_half2": 48.0 * N,                    # Vel read+write; F read
-        # R, Vel, T, bond table read; R_next, Vel written; G read once
-        "advance": (65.0 + 4.0 * D) * N + 16.0 * K * nm,
-        "reduce": 6 * 1024 * 8.0,
+        "field_gradient": 16.0 * K * nm,             # V read; gradient (3 x FP32) written
+        "force_gather": 25.0 * N + 12.0 * K * nm,    # x, T read; F written; gradient read
+        "bond_forces": 36.0 * N + 4.0 * D * N,       # x, bond table, F read; F written
+        "verlet_half2": 36.0 * N,                    # v read + written; F read
+        "advance": 57.0 * N + 12.0 * K * nm,
+        "reduce": 6 * 4096 * 8.0,
     }[name]
+
+
+def layout_bytes(name: str, N: int, K: int, nm: int, D: int, P: int, nbricks: int) -> float:
+    """Bytes the kernel moves by its data layout: float4 bead rows (16 B for x, v and F),
+    the (x, y, z, V) gradient mesh (16 B per point and species), and the partial deposit
+    boxes of K P^3 uint64 per brick that the depositing pass writes and the finish reads."""
+    box = 8.0 * K * P ** 3 * nbricks
+    return {
+        "advance": (65.0 + 4.0 * D) * N + 16.0 * K * nm + box,
+        "finish_potential": 20.0 * K * nm + box,
+        "field_gradient": 20.0 * K * nm,
+    }.get(name)
 
 
 class Timers:
@@ -105,11 +122,50 @@ def timed_step_fused(st, hpf, engine, tm, sort):
     st.steps_done += 1
 
 
+def replay_segments(st, one, steps, period, torch, engine, max_graphs=64):
+    """Time `steps` steps replayed from HIP graphs; None if no segment split fits.
+
+    One period of the step pattern returns every buffer swap to its start. It is cut into
+    segments of gcd(steps, period) steps, each captured as one graph; the timed region
+    replays the segments in order, steps / seg of them. The host-side stepping state is then
+    put back to where the replays left the device."""
+    seg = math.gcd(steps, period)
+    nseg = period // seg
+    if nseg > max_graphs:
+        return None
+    snaps, graphs = [], []
+    for _ in range(nseg):
+        snaps.append(st.snapshot())
+        graphs.append(engine.Graph(lambda: [one() for _ in range(seg)]))
+    # after capture the host state is one period ahead of the device (same buffers)
+    base = st.snapshot()
+    for g in graphs:                                 # untimed first replay of every segment
+        g.launch()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    n = steps // seg
+    stream = graphs[0].stream
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for j in range(n):
+        graphs[j % nseg].launch()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    done = snaps[n % nseg]
+    done = dict(done, steps_done=done["steps_done"] + (base["steps_done"] - snaps[0]["steps_done"]) *
+                (1 + n // nseg))
+    st.restore(done)
+    del graphs
+    return ms, wall, seg, nseg
+
+
 def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, graph=True, halo=2,
-                 advance="scatter", field_every=1):
-    """Warm up, time `steps` steps, then (instrument) time each call over one graph's worth
-    of eager steps. With `graph`, the timed steps replay a HIP graph of two sort periods:
-    every buffer swap of the step then returns to its start, so the graph can be looped."""
+                 advance="scatter", field_every=1, thermostat=0.0):
+    """Warm up, time `steps` steps, then (instrument) time each call over one period of
+    eager steps. With `graph`, the timed steps replay HIP graphs (replay_segments)."""
     import torch
 
     from paper_1310_2041_amd import engine, hpf
@@ -118,6 +174,8 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
     spec = wl.SPECS[cfg]
     s = wl.build(spec)
     st = engine.HpfState.from_system(s, halo=halo, advance=advance, field_every=field_every)
+    if thermostat > 0.0:
+        st.set_thermostat(thermostat, seed=13102041 + spec.index)
     del s
     st.start(sort=True)
     if fused:
@@ -131,23 +189,14 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
         one()
     torch.cuda.synchronize()
     # the step pattern repeats after two sort intervals and after the field interval
-    period = math.lcm(2 * sort_every if sort_every > 0 else 20, field_every)
-    use_graph = graph and fused and steps % period == 0
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    if use_graph:
-        g = engine.Graph(lambda: [one() for _ in range(period)])
-        g.launch()                                   # untimed first replay
-        torch.cuda.synchronize()
-        wall0 = time.perf_counter()
-        t0.record(g.stream)
-        for _ in range(steps // period):
-            g.launch()
-        t1.record(g.stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - wall0
-        del g
+    period = math.lcm(2 * sort_every if sort_every > 0 else 2, field_every)
+    rep = replay_segments(st, one, steps, period, torch, engine) if graph else None
+    if rep is not None:
+        ms, wall, seg, nseg = rep
+        launch = {"mode": "hip_graph", "steps_per_graph": seg, "graphs": nseg}
     else:
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
         t0.record()
         for _ in range(steps):
@@ -155,7 +204,8 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
         t1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1)
+        ms = t0.elapsed_time(t1)
+        launch = {"mode": "eager"}
     tm = Timers(torch)
     if instrument:
         for _ in range(period):
@@ -164,11 +214,14 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
         torch.cuda.synchronize()
     flags = hpf.hpf_get_device_status()
     e = st.energies()
+    nb = 1
+    for d in range(3):
+        nb *= -(-st.mesh.M[d] // st.B)
     return {"spec": spec, "N": st.N, "K": st.K, "nm": st.nm, "D": st.bonds.shape[0],
+            "P": st.B + 1 + 2 * st.halo, "nbricks": nb,
             "ms_total": ms, "wall_s": wall, "kernels": tm.summary() if instrument else {},
-            "flags": flags, "energies": e, "graph": use_graph,
-            "advance_kernel": ("scatter" if st.uses_scatter_advance() else
-                               "cells" if st.uses_cells_advance() else "plain")}
+            "flags": flags, "energies": e, "launch": launch,
+            "advance_kernel": "scatter" if st.uses_scatter_advance() else "plain"}
 
 
 def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
@@ -229,7 +282,6 @@ def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
 # rocprofv3 kernel names behind each timed call of the step
 ROCPROF_KERNELS = {
     "advance": ["hpf::k_advance<%s, %s>" % (r0, pipe) for r0 in ("true", "false") for pipe in ("true", "false")] +
-               ["hpf::k_advance_cells<true>", "hpf::k_advance_cells<false>"] +
                ["hpf::k_advance_scatter<%s, %d, %s>" % (r0, n, pipe) for r0 in ("true", "false") for n in (256, 512)
                 for pipe in ("true", "false")],
     "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum<false>",
@@ -241,25 +293,18 @@ ROCPROF_KERNELS = {
 }
 
 
-def step_bandwidth(r, sort_every, ms_step):
-    """Algorithmic bytes of one whole step (every call once, the sort amortised over its
-    interval) over the measured step time, against the HBM peak."""
-    N, K, nm, D = r["N"], r["K"], r["nm"], r["D"]
-    b = sum(algorithmic_bytes(name, N, K, nm, D) for name in r["kernels"] if name != "sort_by_cell")
-    if sort_every > 0:
-        b += 150.0 * N / sort_every
-    gbs = b / (ms_step * 1e-3) / 1e9
-    # the least any two-pass design must move per step: x, T read by the deposit (13 B), x, v,
-    # T read and x, v written by the force + integration pass (49 B), the bond-partner slots
-    # (8 B); per mesh point and species the counts written, read and cleared (24 B) and V
-    # written and read (8 B)
+def step_bandwidth(r, ms_step):
+    """The whole step against the HBM peak on the two-pass step bytes 70 N + 32 K M^3: the
+    least a design with one pass over the beads and one over the mesh must move (x, T read
+    by the deposit 13 B, x, v, T read and x, v written by the force + integration pass 49 B,
+    bond-partner slots 8 B per bead; per mesh point and species the counts written, read
+    and cleared 24 B and V written and read 8 B). The sort and the gradient are not in it."""
+    N, K, nm = r["N"], r["K"], r["nm"]
     b_min = 70.0 * N + 32.0 * K * nm
     gmin = b_min / (ms_step * 1e-3) / 1e9
-    return {"alg_bytes": b, "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "minimal_bytes": b_min, "minimal_achieved": round(gmin, 1),
-            "minimal_frac": round(gmin / HBM_PEAK_GBS, 4),
-            "note": "all calls of a step (sort at its algorithmic 150 B/bead every sort_every steps); "
-                    "minimal = 70 N + 32 K M^3, the bytes of a two-pass step"}
+    return {"bytes_per_step": b_min, "achieved": round(gmin, 1), "unit": "GB/s",
+            "peak": HBM_PEAK_GBS, "frac": round(gmin / HBM_PEAK_GBS, 4),
+            "note": "two-pass step bytes 70 N + 32 K M^3 over the whole measured step time"}
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -278,23 +323,80 @@ def measured_traffic(workload: str, kernel: str):
     return tot if found else None
 
 
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(cfg, n_steps):
-    """The FP64 oracle (single-threaded C) on a bounded sample of the workload."""
+    """The FP64 oracle on a bounded sample of the workload: one host thread (the parity
+    build), and all the threads this process may use (the same source built with OpenMP)."""
     import oracle
     from synth import workloads as wl
 
     s = wl.build(wl.SPECS[cfg])
-    t0 = time.perf_counter()
-    oracle.forces(s)
-    t_force = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.run(s, n_steps)
-    t_run = time.perf_counter() - t0
-    t_steps = max(t_run - t_force, 1e-9)      # run() evaluates the initial forces first
-    return {"value": s.N * n_steps / t_steps, "unit": "particle-steps/s", "cores": 1,
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
+
+    def timed(th):
+        t0 = time.perf_counter()
+        oracle.forces(s) if th is None else oracle.run(s, 0, threads=th)
+        t_force = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.run(s, n_steps, threads=th)
+        t_run = time.perf_counter() - t0
+        return max(t_run - t_force, 1e-9)      # run() evaluates the initial forces first
+
+    t1 = timed(None)
+    tn = timed(threads)
+    info = cpu_info()
+    return {"value": s.N * n_steps / tn, "unit": "particle-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{n_steps} velocity-Verlet steps of the full {s.N}-bead {cfg} workload "
-                      f"(FP64 C oracle, one thread; {t_steps:.1f} s)"}
+            "single_thread_value": s.N * n_steps / t1,
+            "cpu": info,
+            "sample": f"{n_steps} velocity-Verlet steps of the full {s.N}-bead {cfg} workload, FP64 C "
+                      f"oracle: {tn:.1f} s on {threads} threads (OpenMP build of the same source), "
+                      f"{t1:.1f} s on one thread; host {info['model']}, nproc {info['nproc']}"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_table(r):
+    kern = r["kernels"]
+    out = {}
+    for name, k in kern.items():
+        if name == "sort_by_cell":
+            out[name] = {"avg_us": round(k["avg_us"], 2), "launches": k["launches"]}
+            continue
+        b = algorithmic_bytes(name, r["N"], r["K"], r["nm"], r["D"])
+        out[name] = {"avg_us": round(k["avg_us"], 2), "alg_GBs": round(b / (k["avg_us"] * 1e-6) / 1e9, 1)}
+    return out
+
+
+def roofline(r, name):
+    avg_us = r["kernels"][name]["avg_us"]
+    b = algorithmic_bytes(name, r["N"], r["K"], r["nm"], r["D"])
+    lb = layout_bytes(name, r["N"], r["K"], r["nm"], r["D"], r["P"], r["nbricks"])
+    achieved = b / (avg_us * 1e-6) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(r["spec"].name, name),
+            "algorithmic_bytes": b, "avg_us": round(avg_us, 2),
+            "layout_bytes": lb,
+            "layout_frac": None if lb is None else round(lb / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "achieved = minimal algorithmic bytes per launch / average launch time (HIP events "
+                    "on the launch stream); layout_bytes = what this kernel's data layout moves "
+                    "(float4 bead rows, (x, y, z, V) gradient corners, partial deposit boxes); "
+                    "traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, calibrated"}
 
 
 def main():
@@ -310,14 +412,18 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batched sweep")
+    ap.add_argument("--c5-steps", type=int, default=40,
+                    help="steps of the 100M-bead three-species system reported under 'c5' (0 = skip)")
     ap.add_argument("--halo", type=int, default=2, help="drift halo (cells) of the brick deposit boxes")
-    ap.add_argument("--advance", default="scatter", choices=["scatter", "plain", "cells"],
+    ap.add_argument("--advance", default="scatter", choices=["scatter", "plain"],
                     help="fused pass on cell-sorted beads (scatter: with the density deposit)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every call from Python instead of replaying HIP graphs")
     ap.add_argument("--field-interval", type=int, default=10,
                     help="also time the workload with the density field rebuilt every n steps "
                          "(the MD-SCF update interval; 0 = skip)")
+    ap.add_argument("--thermostat", type=float, default=5.0,
+                    help="Andersen collision rate of the field-interval run (0 = NVE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hPF-MD path here runs on a single MI355X "
@@ -331,23 +437,13 @@ def main():
     torch.cuda.set_device(0)
 
     fused = args.mode == "fused"
+    log(f"{args.config}: {args.warmup} warm-up + {args.steps} timed steps")
     r = run_workload(args.config, args.steps, args.warmup, args.sort_every, fused=fused,
                      graph=not args.eager, halo=args.halo, advance=args.advance)
     ms_step = r["ms_total"] / args.steps
     value = r["N"] * args.steps / (r["ms_total"] * 1e-3)
-    kern = r["kernels"]
-    per_kernel = {}
-    for name, k in kern.items():
-        if name == "sort_by_cell":
-            continue
-        b = algorithmic_bytes(name, r["N"], r["K"], r["nm"], r["D"])
-        per_kernel[name] = {"avg_us": round(k["avg_us"], 2), "alg_GBs": round(b / (k["avg_us"] * 1e-6) / 1e9, 1)}
-    if "sort_by_cell" in kern:
-        per_kernel["sort_by_cell"] = {"avg_us": round(kern["sort_by_cell"]["avg_us"], 2),
-                                      "launches": kern["sort_by_cell"]["launches"]}
+    per_kernel = kernel_table(r)
     dom = max((n for n in per_kernel if n != "sort_by_cell"), key=lambda n: per_kernel[n]["avg_us"])
-    dom_bytes = algorithmic_bytes(dom, r["N"], r["K"], r["nm"], r["D"])
-    achieved = dom_bytes / (kern[dom]["avg_us"] * 1e-6) / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -364,37 +460,58 @@ def main():
         "config": {"workload": r["spec"].name, "beads": r["N"], "species": r["K"],
                    "mesh": [r["spec"].M] * 3, "box": r["spec"].L, "sort_every": args.sort_every,
                    "energy_report_every": 1, "step": args.mode, "advance": r["advance_kernel"],
-                   "halo": args.halo,
-                   "launch": "hip_graph" if r["graph"] else "eager", "parallelism": "single-gpu"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "algorithmic_bytes": dom_bytes,
-                     "traffic": measured_traffic(r["spec"].name, dom)},
+                   "halo": args.halo, "launch": r["launch"], "parallelism": "single-gpu"},
+        "roofline": roofline(r, dom),
+        "step_roofline": step_bandwidth(r, ms_step),
         "kernels": per_kernel,
-        "step_bandwidth": step_bandwidth(r, args.sort_every, ms_step),
         "device_flags": r["flags"],
     }
+    if "finish_potential" in r["kernels"]:
+        out["roofline_finish_potential"] = roofline(r, "finish_potential")
+    log(f"{args.config}: {ms_step:.4f} ms/step")
     if args.also and args.also != args.config:
         r2 = run_workload(args.also, args.steps, args.warmup, args.sort_every, instrument=False,
                           fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance)
+        ms2 = r2["ms_total"] / args.steps
         out["also"] = {"workload": r2["spec"].name, "beads": r2["N"],
                        "value": r2["N"] * args.steps / (r2["ms_total"] * 1e-3),
-                       "ms_per_step": r2["ms_total"] / args.steps,
+                       "ms_per_step": ms2, "launch": r2["launch"],
+                       "step_roofline": step_bandwidth(r2, ms2),
                        "note": "working set fits the 256 MB Infinity Cache"}
+        log(f"{args.also}: {ms2:.4f} ms/step")
     if args.field_interval > 1 and fused:
         r3 = run_workload(args.config, args.steps, args.warmup, args.sort_every, instrument=False,
                           fused=True, graph=not args.eager, halo=args.halo, advance=args.advance,
-                          field_every=args.field_interval)
+                          field_every=args.field_interval, thermostat=args.thermostat)
         out["field_interval"] = {"workload": r3["spec"].name, "field_every": args.field_interval,
+                                 "thermostat_rate": args.thermostat,
                                  "value": r3["N"] * args.steps / (r3["ms_total"] * 1e-3),
-                                 "ms_per_step": r3["ms_total"] / args.steps,
+                                 "ms_per_step": r3["ms_total"] / args.steps, "launch": r3["launch"],
                                  "ke_per_bead_end": float(r3["energies"]["KE"]) / r3["N"],
                                  "ke_per_bead_end_every_step": float(r["energies"]["KE"]) / r["N"],
-                                 "note": "density field rebuilt every field_every steps (MD-SCF); "
-                                         "value above rebuilds it every step"}
+                                 "note": "density field rebuilt every field_every steps (MD-SCF), "
+                                         "Andersen thermostat at kT = 1 with the given collision rate; "
+                                         "value above rebuilds it every step (NVE)"}
+        log(f"field interval {args.field_interval}: {r3['ms_total'] / args.steps:.4f} ms/step")
+    if args.c5_steps > 0:
+        log(f"c5: building the 100M-bead system, {min(args.warmup, 5)} warm-up + {args.c5_steps} steps")
+        r5 = run_workload("c5", args.c5_steps, min(args.warmup, 5), args.sort_every, instrument=True,
+                          fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance)
+        ms5 = r5["ms_total"] / args.c5_steps
+        out["c5"] = {"workload": r5["spec"].name, "beads": r5["N"], "species": r5["K"],
+                     "mesh": [r5["spec"].M] * 3, "steps": args.c5_steps,
+                     "value": r5["N"] / (ms5 * 1e-3), "ms_per_step": ms5, "launch": r5["launch"],
+                     "step_roofline": step_bandwidth(r5, ms5),
+                     "roofline": roofline(r5, max((n for n in r5["kernels"] if n != "sort_by_cell"),
+                                                  key=lambda n: r5["kernels"][n]["avg_us"])),
+                     "kernels": kernel_table(r5), "device_flags": r5["flags"]}
+        del r5
+        log(f"c5: {ms5:.4f} ms/step")
     if not args.no_batch:
+        log("64-replica batched sweep")
         out["batched_sweep"] = run_batched_sweep()
     if not args.no_cpu_baseline:
+        log(f"oracle on the host: {args.cpu_steps} steps of {args.config}")
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

@@ -92,6 +92,32 @@ typedef struct hpf_field {
     double chi[HPF_MAX_TYPES * HPF_MAX_TYPES];
 } hpf_field_t;
 
+/* Andersen thermostat (Integration methods section: NVT with the Andersen
+ * thermostat). At time level n each bead collides with the heat bath with
+ * probability p and then takes a new velocity from the Maxwell distribution at
+ * kT: v = sqrt(kT / m) (g0, g1, g2). The decision and the deviates come from the
+ * counter-based generator Philox4x32-10 (Salmon et al., SC'11) with key `seed`
+ * and counters (tag_i, n, 0) and (tag_i, n, 1): the bead collides when
+ * (r0 >> 8) < floor(p 2^24); g0, g1 are the Box-Muller pair of the 24-bit
+ * uniforms of r1 and r2 (((r1 >> 8) + 1) 2^-24 under the logarithm), g2 the
+ * cosine deviate of r3 and of word 0 of the second counter. Draws therefore
+ * depend only on (seed, tag, n), not on the storage order or launch shape.
+ *  p     collision probability per step (collision rate x dt), in [0, 1];
+ *        0 = no thermostat.
+ *  kT    bath temperature, > 0.
+ *  step  DEVICE pointer to the time level n (int64), read by the kernels when
+ *        they run, so that a captured graph sees the value the caller has
+ *        advanced in the meantime (the library never writes it).
+ *  tag   DEVICE int32[N], the beads' tags in their current storage order.
+ * A null thermostat pointer is no thermostat. Invalid values give HPF_EINVAL. */
+typedef struct hpf_thermostat {
+    float p;
+    float kT;
+    uint64_t seed;
+    const int64_t* step;
+    const int32_t* tag;
+} hpf_thermostat_t;
+
 /* Library ABI version (HPF_ABI_VERSION). */
 int32_t hpf_abi_version(void);
 
@@ -237,6 +263,14 @@ hpf_status_t verlet_step(float* R, float* Vel, const float* F, const float* inv_
                          int64_t N, float dt, const float* box, int32_t half,
                          double* kin_part, void* stream);
 
+/* hpf_andersen -- the Andersen collisions of time level *thermostat->step on
+ * every bead (see hpf_thermostat_t), to be applied after verlet_step(half = 2).
+ * Vel float[N][4] device, updated; inv_mass nullable float[N] (NULL = unit
+ * masses). kin_part nullable double[4][HPF_NPART]: partial sums of {KE, Px,
+ * Py, Pz} after the collisions (as verlet_step's). thermostat must not be NULL. */
+hpf_status_t hpf_andersen(float* Vel, const float* inv_mass, int64_t N,
+                          const hpf_thermostat_t* thermostat, double* kin_part, void* stream);
+
 /* ---------------------------------------------------------------------------
  * hpf_advance -- one fused pass over the beads that produces exactly the
  * results of this call sequence (bit for bit):
@@ -255,6 +289,10 @@ hpf_status_t verlet_step(float* R, float* Vel, const float* F, const float* inv_
  * F_out   nullable float[N][4] device: receives the total force at x_n.
  * e_part  nullable double[HPF_NPART]; kin_part nullable double[4][HPF_NPART]:
  *         as in bond_forces and verlet_step(half = 2).
+ * thermostat  nullable: with it, the Andersen collisions of time level
+ *         *thermostat->step act on v_n right after the second half kick, as
+ *         hpf_andersen after verlet_step(half = 2) would, and the kinetic-energy
+ *         partials are those of the velocities after the collisions.
  * Sets HPF_FLAG_BAD_BEAD / HPF_FLAG_BAD_BOND / HPF_FLAG_NONFINITE like the
  * separate calls.
  * ------------------------------------------------------------------------- */
@@ -262,34 +300,7 @@ hpf_status_t hpf_advance(const float* R, float* R_next, float* Vel, const uint8_
                          const hpf_mesh_t* mesh, int32_t K, const float* G, const int32_t* bonds,
                          int32_t D, float k, float r0, const float* box, const float* inv_mass,
                          float dt, float* F_out, double* e_part, double* kin_part,
-                         void* stream);
-
-/* ---------------------------------------------------------------------------
- * hpf_advance_cells -- hpf_advance for beads in hpf_sort_by_cell order, with
- * the same per-bead results bit for bit (forces eq. 6 and eq. 7, the Verlet
- * halves of the Integration methods section). One workgroup takes the beads
- * that one B^3 brick of cells listed at the last sort and first stages the
- * brick's gradient box -- (B + 1 + 2*halo)^3 mesh points per species,
- * starting halo points below the brick, periodic -- in LDS; beads that have
- * since moved more than `halo` cells out of their brick, and beads the sort
- * could not bin, read the mesh from memory instead.
- *
- * Arguments as in hpf_advance, plus:
- * cell_start  uint32[NK + 2] device, from the hpf_sort_by_cell call with the
- *             same mesh and B that produced the current bead order (the beads
- *             may have moved since; their storage order must not have).
- * B           brick edge 3..8 (0 selects 8); halo 0..2 cells, halo < B.
- *             K * (B + 1 + 2*halo)^3 * 16 bytes must fit in 160 KiB of LDS.
- * The energy partials are grouped by workgroup, so their sums may differ from
- * hpf_advance's in the last FP64 bits; every bead state is identical.
- * Returns HPF_EINVAL for bad arguments (nothing enqueued).
- * ------------------------------------------------------------------------- */
-hpf_status_t hpf_advance_cells(const float* R, float* R_next, float* Vel, const uint8_t* T,
-                               int64_t N, const hpf_mesh_t* mesh, int32_t K, const float* G,
-                               const int32_t* bonds, int32_t D, float k, float r0,
-                               const float* box, const float* inv_mass, float dt,
-                               const uint32_t* cell_start, int32_t B, int32_t halo,
-                               float* F_out, double* e_part, double* kin_part, void* stream);
+                         const hpf_thermostat_t* thermostat, void* stream);
 
 /* ---------------------------------------------------------------------------
  * hpf_advance_scatter -- hpf_advance (bit for bit the same bead updates) that
@@ -304,14 +315,15 @@ hpf_status_t hpf_advance_cells(const float* R, float* R_next, float* Vel, const 
  * with global atomics. hpf_density_finish_cells then adds the partial boxes
  * to `counts`; the result equals hpf_density_scatter(R_next) bit for bit.
  *
- * Arguments as in hpf_advance, plus:
+ * Arguments as in hpf_advance (thermostat included), plus:
  * cell_start, B, halo  as in hpf_density_scatter_cells (same limits).
  * counts  uint64[K][M^3] device, ADDED to; it must hold zeros (or counts to be
  *         kept) on entry. hpf_field_potential leaves it zeroed.
  * work    device workspace of at least hpf_scatter_workspace_bytes(N, mesh,
  *         K, B, halo) bytes (HPF_ESPACE otherwise); its partial boxes are
  *         overwritten and must not be touched before hpf_density_finish_cells.
- * The energy partials are grouped by workgroup (as in hpf_advance_cells).
+ * The energy partials are grouped by workgroup, so their sums may differ from
+ * hpf_advance's in the last FP64 bits; every bead state is identical.
  * Positions that cannot be binned set HPF_FLAG_BAD_BEAD.
  * ------------------------------------------------------------------------- */
 hpf_status_t hpf_advance_scatter(const float* R, float* R_next, float* Vel, const uint8_t* T,
@@ -320,7 +332,8 @@ hpf_status_t hpf_advance_scatter(const float* R, float* R_next, float* Vel, cons
                                  const float* box, const float* inv_mass, float dt,
                                  const uint32_t* cell_start, int32_t B, int32_t halo,
                                  uint64_t* counts, void* work, size_t work_bytes, float* F_out,
-                                 double* e_part, double* kin_part, void* stream);
+                                 double* e_part, double* kin_part,
+                                 const hpf_thermostat_t* thermostat, void* stream);
 
 /* hpf_density_finish_cells -- counts += the sum of the partial deposit boxes
  * that hpf_advance_scatter left in `work` (same N, mesh, K, B, halo), i.e.
@@ -426,6 +439,12 @@ typedef struct hpf_batch_config {
     int32_t fuse_deposit;    /* 1: each step's fused pass also deposits the new positions
                                 (as hpf_advance_scatter), so the next step only finishes
                                 the density; 0: a separate cell scatter every step */
+    float thermo_p;          /* Andersen collision probability per step (hpf_thermostat_t),
+                                0 = NVE; each replica's bath is at its own kT */
+    int32_t reserved;
+    uint64_t thermo_seed;    /* generator key of the thermostat; the batch keeps the time
+                                level on the device (1 at the first step after
+                                hpf_batch_start) and advances it every step */
 } hpf_batch_config_t;
 
 typedef struct hpf_batch_buffers {

@@ -56,6 +56,11 @@ static bool box_ok(const float* box)
 
 static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Kernel form of a thermostat description; false for invalid parameters. A null
+// description, or p = 0, is no thermostat (thr = 0).
+struct ThermoK;
+static bool thermo_k(const hpf_thermostat_t* t, int64_t N, ThermoK* out);
+
 }  // namespace hpf
 
 #include "hpf_scatter.hip"
@@ -63,6 +68,28 @@ static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 #include "hpf_field.hip"
 #include "hpf_particles.hip"
 #include "hpf_sort.hip"
+
+namespace hpf {
+
+static bool thermo_k(const hpf_thermostat_t* t, int64_t N, ThermoK* out)
+{
+    *out = ThermoK{0u, 0.0f, 0u, 0u, nullptr, nullptr};
+    if (!t || t->p == 0.0f)
+        return true;
+    if (!(t->p > 0.0f && t->p <= 1.0f) || !(t->kT > 0.0f) || !std::isfinite(t->kT) || !t->step ||
+        (N > 0 && !t->tag))
+        return false;
+    // floor(p 2^24): exact, p * 2^24 is exact in double for a float p
+    out->thr = t->p >= 1.0f ? (1u << 24) : (uint32_t)std::floor((double)t->p * 16777216.0);
+    out->kT = t->kT;
+    out->key0 = (uint32_t)t->seed;
+    out->key1 = (uint32_t)(t->seed >> 32);
+    out->step = t->step;
+    out->tag = t->tag;
+    return true;
+}
+
+}  // namespace hpf
 
 using namespace hpf;
 
@@ -269,8 +296,11 @@ hpf_status_t verlet_step(float* R, float* Vel, const float* F, const float* inv_
 hpf_status_t hpf_advance(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
                          const hpf_mesh_t* mesh, int32_t K, const float* G, const int32_t* bonds, int32_t D,
                          float k, float r0, const float* box, const float* inv_mass, float dt, float* F_out,
-                         double* e_part, double* kin_part, void* stream)
+                         double* e_part, double* kin_part, const hpf_thermostat_t* thermostat, void* stream)
 {
+    ThermoK th;
+    if (!thermo_k(thermostat, N, &th))
+        return HPF_EINVAL;
     if (N < 0 || N > 0x7fffffffLL || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES || D < 0 ||
         D > HPF_MAX_BONDS || !box_ok(box) || !std::isfinite(k) || !std::isfinite(r0) || !(dt > 0.0f) ||
         !std::isfinite(dt))
@@ -283,50 +313,7 @@ hpf_status_t hpf_advance(const float* R, float* R_next, float* Vel, const uint8_
         b.halfL[d] = 0.5f * box[d];
     }
     return launch_advance(R, R_next, Vel, T, N, mesh_k(mesh), K, G, bonds, D, k, r0, b, inv_mass, dt, F_out,
-                          e_part, kin_part, as_stream(stream));
-}
-
-hpf_status_t hpf_advance_cells(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
-                               const hpf_mesh_t* mesh, int32_t K, const float* G, const int32_t* bonds, int32_t D,
-                               float k, float r0, const float* box, const float* inv_mass, float dt,
-                               const uint32_t* cell_start, int32_t B, int32_t halo, float* F_out, double* e_part,
-                               double* kin_part, void* stream)
-{
-    if (N < 0 || N > 0x7fffffffLL || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES || D < 0 ||
-        D > HPF_MAX_BONDS || !box_ok(box) || !std::isfinite(k) || !std::isfinite(r0) || !(dt > 0.0f) ||
-        !std::isfinite(dt))
-        return HPF_EINVAL;
-    if (B == 0)
-        B = 8;
-    if (B < 3 || B > kTcMaxB || halo < 0 || halo > kTcMaxHalo || halo >= B)
-        return HPF_EINVAL;
-    const int P = B + 1 + 2 * halo;
-    if (advance_cells_smem(K, P) > 160 * 1024)
-        return HPF_EINVAL;
-    if (N > 0 && (!R || !R_next || !Vel || !T || !G || !cell_start || (D > 0 && !bonds) || R == R_next))
-        return HPF_EINVAL;
-    TileK tk;
-    int64_t nk = 1, nt = 1;
-    for (int d = 0; d < 3; ++d) {
-        tk.nb[d] = (mesh->M[d] + B - 1) / B;
-        nk *= tk.nb[d];
-        nt *= tk.nb[d];
-    }
-    if (nk > 0xfffffff0LL)
-        return HPF_EINVAL;
-    tk.m = mesh_k(mesh);
-    tk.B = B;
-    tk.h = halo;
-    tk.P = P;
-    tk.NK = (uint32_t)nk;
-    tk.ntiles = nt;
-    BoxK b;
-    for (int d = 0; d < 3; ++d) {
-        b.L[d] = box[d];
-        b.halfL[d] = 0.5f * box[d];
-    }
-    return launch_advance_cells(R, R_next, Vel, T, N, tk, K, G, bonds, D, k, r0, b, inv_mass, dt, cell_start,
-                                F_out, e_part, kin_part, as_stream(stream));
+                          e_part, kin_part, th, as_stream(stream));
 }
 
 static bool advance_args_ok(int64_t N, const hpf_mesh_t* mesh, int32_t K, int32_t D, float k, float r0,
@@ -341,10 +328,14 @@ hpf_status_t hpf_advance_scatter(const float* R, float* R_next, float* Vel, cons
                                  const hpf_mesh_t* mesh, int32_t K, const float* G, const int32_t* bonds,
                                  int32_t D, float k, float r0, const float* box, const float* inv_mass, float dt,
                                  const uint32_t* cell_start, int32_t B, int32_t halo, uint64_t* counts, void* work,
-                                 size_t work_bytes, float* F_out, double* e_part, double* kin_part, void* stream)
+                                 size_t work_bytes, float* F_out, double* e_part, double* kin_part,
+                                 const hpf_thermostat_t* thermostat, void* stream)
 {
     TileK tk;
+    ThermoK th;
     size_t sb = 0, tb = 0;
+    if (!thermo_k(thermostat, N, &th))
+        return HPF_EINVAL;
     if (!advance_args_ok(N, mesh, K, D, k, r0, box, dt) || !counts || !cell_start ||
         !scatter_cells_setup(N, mesh, K, B, halo, &tk, &sb, &tb))
         return HPF_EINVAL;
@@ -360,8 +351,17 @@ hpf_status_t hpf_advance_scatter(const float* R, float* R_next, float* Vel, cons
     char* w = static_cast<char*>(work);
     return launch_advance_scatter(R, R_next, Vel, T, N, tk, K, G, bonds, D, k, r0, b, inv_mass, dt, cell_start,
                                   reinterpret_cast<unsigned long long*>(w + sb),
-                                  reinterpret_cast<unsigned long long*>(counts), F_out, e_part, kin_part,
+                                  reinterpret_cast<unsigned long long*>(counts), F_out, e_part, kin_part, th,
                                   as_stream(stream));
+}
+
+hpf_status_t hpf_andersen(float* Vel, const float* inv_mass, int64_t N, const hpf_thermostat_t* thermostat,
+                          double* kin_part, void* stream)
+{
+    ThermoK th;
+    if (N < 0 || N > 0x7fffffffLL || !thermostat || !thermo_k(thermostat, N, &th) || (N > 0 && !Vel))
+        return HPF_EINVAL;
+    return launch_andersen(Vel, inv_mass, N, th, kin_part, as_stream(stream));
 }
 
 hpf_status_t hpf_density_finish_cells(uint64_t* counts, int64_t N, const hpf_mesh_t* mesh, int32_t K, int32_t B,

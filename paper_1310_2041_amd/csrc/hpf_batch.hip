@@ -12,9 +12,11 @@
 // ranges of a replica share that XCD's L2), and calls the same device functions as the single-system kernels, so
 // each replica's beads follow exactly the trajectory they would follow alone.
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "hpf_common.hpp"
+#include "hpf_thermo.hpp"
 
 namespace hpf {
 
@@ -28,6 +30,7 @@ struct RepK {
     int32_t nb[3];
     int64_t brick_off;     // first brick of the replica in the concatenated brick numbering
     int64_t nbricks;
+    float kT;              // the replica's temperature (its thermostat's bath)
 };
 
 struct ItemK {
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(256) void k_batch_gradient(const RepK* __restrict__
 
 // ------------------------------------------------------------------ advance
 
-template <bool kR0Zero>
+template <bool kR0Zero, bool kThermo>
 __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restrict__ reps,
                                                              const ItemK* __restrict__ items, int K,
                                                              const float4* __restrict__ R,
@@ -241,20 +244,22 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
                                                              const int32_t* __restrict__ bonds, int D, float k,
                                                              float r0, float dt,
                                                              double* __restrict__ e_part,
-                                                             double* __restrict__ kin_part, int nslot)
+                                                             double* __restrict__ kin_part, int nslot, ThermoK th)
 {
     __shared__ double scratch[kPThreads / kWave];
     const int64_t li = xcd_block(blockIdx.x, gridDim.x);
     const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
+    th.kT = rp.kT;
+    const uint64_t tstep = thermo_step(th);
     const float4* Gr = G + (int64_t)K * rp.moff;
     const float hdt = 0.5f * dt;
     KinAcc acc;
     double e = 0.0;
     bool bad_bead = false, bad_bond = false, nonfinite = false;
     for (int64_t i = it.begin + threadIdx.x; i < it.end; i += kPThreads)
-        advance_bead<kR0Zero>(i, R, R_next, Vel, T, Ntot, rp.m, K, Gr, bonds, D, k, r0, rp.box, nullptr,
-                              dt, hdt, nullptr, acc, e, bad_bead, bad_bond, nonfinite);
+        advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, Ntot, rp.m, K, Gr, bonds, D, k, r0, rp.box, nullptr,
+                              dt, hdt, nullptr, acc, e, bad_bead, bad_bond, nonfinite, th, tstep);
     if (bad_bead)
         raise_flag(HPF_FLAG_BAD_BEAD);
     if (bad_bond)
@@ -275,20 +280,22 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
 // sort; a replica's last item (brick == NK) holds the beads the sort could
 // not bin, deposited with global atomics. The energy partials go to the
 // item's slot.
-template <bool kR0Zero, bool kPipe>
+template <bool kR0Zero, bool kPipe, bool kThermo>
 __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
     const RepK* __restrict__ reps, const ItemK* __restrict__ items, int B, int h, int K,
     const float4* __restrict__ R, float4* __restrict__ R_next, float4* __restrict__ Vel,
     const uint8_t* __restrict__ T, int64_t Ntot, const float4* __restrict__ G, const int32_t* __restrict__ bonds,
     int D, float k, float r0, float dt, const uint32_t* __restrict__ cell_start,
     unsigned long long* __restrict__ partials, unsigned long long* __restrict__ counts,
-    double* __restrict__ e_part, double* __restrict__ kin_part, int nslot)
+    double* __restrict__ e_part, double* __restrict__ kin_part, int nslot, ThermoK th)
 {
     extern __shared__ unsigned long long dbox[];
     __shared__ double scratch[kASThreadsBatch / kWave];
     const int64_t li = xcd_block(blockIdx.x, gridDim.x);
     const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
+    th.kT = rp.kT;
+    const uint64_t tstep = thermo_step(th);
     const MeshK& m = rp.m;
     const float4* Gr = G + (int64_t)K * rp.moff;
     unsigned long long* cr = counts + (int64_t)K * rp.moff;
@@ -314,16 +321,18 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
             int64_t i = first + threadIdx.x;
             BeadIn cur;
             if (i < last)
-                bead_fetch(cur, i, R, Vel, T, bonds, D, Ntot, nullptr);
+                bead_fetch<kThermo>(cur, i, R, Vel, T, bonds, D, Ntot, nullptr, th);
             for (; i < last; i += kASThreadsBatch) {
                 BeadLoads L;
                 bead_issue(L, cur, i, m, K, Gr, R, Ntot);
                 __builtin_amdgcn_sched_barrier(0);
                 BeadIn nxt;
-                bead_fetch(nxt, min(i + kASThreadsBatch, last - 1), R, Vel, T, bonds, D, Ntot, nullptr);
+                bead_fetch<kThermo>(nxt, min(i + kASThreadsBatch, last - 1), R, Vel, T, bonds, D, Ntot, nullptr,
+                                    th);
                 __builtin_amdgcn_sched_barrier(0);
-                const float4 rn = bead_finish<kR0Zero>(i, cur, L, R_next, Vel, Ntot, D, k, r0, rp.box, dt, hdt,
-                                                       nullptr, acc, e, bad_bead, bad_bond, nonfinite);
+                const float4 rn = bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, Ntot, D, k, r0, rp.box, dt,
+                                                                hdt,
+                                                       nullptr, acc, e, bad_bead, bad_bond, nonfinite, th, tstep);
                 const int t = cur.t;
                 BeadCell bc;
                 int lx, ly, lz;
@@ -335,9 +344,9 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
             }
         } else {
             for (int64_t i = first + threadIdx.x; i < last; i += kASThreadsBatch) {
-                const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k, r0,
-                                                        rp.box, nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond,
-                                                        nonfinite);
+                const float4 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k,
+                                                                 r0, rp.box, nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond,
+                                                        nonfinite, th, tstep);
                 const int t = T[i];
                 BeadCell bc;
                 int lx, ly, lz;
@@ -354,8 +363,10 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
     } else {
         const int64_t first = cs[rp.NK], last = min((int64_t)cs[rp.NK + 1], Ntot);
         for (int64_t i = first + threadIdx.x; i < last; i += kASThreadsBatch) {
-            const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k, r0, rp.box,
-                                                    nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond, nonfinite);
+            const float4 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k, r0,
+                                                             rp.box,
+                                                    nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond, nonfinite,
+                                                    th, tstep);
             bad_bead |= !deposit_global(rn, T[i], K, m, cr);
         }
     }
@@ -422,6 +433,10 @@ __global__ __launch_bounds__(64) void k_batch_reduce(const int64_t* __restrict__
 // ======================================================================
 
 namespace hpf {
+
+// The batch's device time level (a kernel, so that captured graphs advance it).
+__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
+__global__ void k_add_i64(int64_t* p, int64_t v) { *p += v; }
 
 // prime: forces at x_0, energies with v_0, then the first half step
 template <bool kR0Zero>
@@ -491,7 +506,7 @@ struct BatchLayout {
     int64_t nslot = 0;                   // energy partial slots (one per bead or fused item)
     size_t off_reps, off_bead_items, off_brick_items, off_adv_items, off_mesh_items, off_plane_items, off_bead_ioff,
         off_adv_ioff, off_mesh_ioff, off_brick_ioff, off_sort, off_start, off_strays, off_partials, off_wpart, off_epart, off_kpart, off_energy,
-        total;
+        off_tstep, total;
     SortPlan sort;
 };
 
@@ -552,6 +567,7 @@ static bool batch_layout(const hpf_replica_t* reps, int nrep, const hpf_batch_co
     L->off_epart = o; o += al256(sizeof(double) * L->nslot);
     L->off_kpart = o; o += al256(sizeof(double) * 4 * L->nslot);
     L->off_energy = o; o += al256(sizeof(double) * 8 * nrep);
+    L->off_tstep = o; o += al256(sizeof(int64_t));
     L->total = o;
     return true;
 }
@@ -735,6 +751,16 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
     double* kp = report ? b->at<double>(L.off_kpart) : nullptr;
     const int nslot = (int)L.nslot;
     const bool fused = !prime && c.fuse_deposit;
+    // the thermostat acts in every step after the start (time levels 1, 2, ... on the device)
+    ThermoK th{0u, 0.0f, 0u, 0u, nullptr, nullptr};
+    int64_t* tstep = b->at<int64_t>(L.off_tstep);
+    if (!prime && c.thermo_p > 0.0f) {
+        th.thr = c.thermo_p >= 1.0f ? (1u << 24) : (uint32_t)std::floor((double)c.thermo_p * 16777216.0);
+        th.key0 = (uint32_t)c.thermo_seed;
+        th.key1 = (uint32_t)(c.thermo_seed >> 32);
+        th.step = tstep;
+        th.tag = b->buf.tag[b->scur];
+    }
     b->pending = false;
     if (fused) {
         const int P = c.brick + 1 + 2 * c.halo;
@@ -742,10 +768,19 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
         // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
         using AdvFn = void (*)(const RepK*, const ItemK*, int, int, int, const float4*, float4*, float4*,
                                const uint8_t*, int64_t, const float4*, const int32_t*, int, float, float, float,
-                               const uint32_t*, unsigned long long*, unsigned long long*, double*, double*, int);
+                               const uint32_t*, unsigned long long*, unsigned long long*, double*, double*, int,
+                               ThermoK);
         const bool pipe = c.D <= kPreBonds;
-        const AdvFn fn = c.r0 == 0.0f ? (pipe ? k_batch_advance_scatter<true, true> : k_batch_advance_scatter<true, false>)
-                                      : (pipe ? k_batch_advance_scatter<false, true> : k_batch_advance_scatter<false, false>);
+        const bool thermo = th.thr != 0;
+        const AdvFn fn =
+            thermo ? (c.r0 == 0.0f ? (pipe ? k_batch_advance_scatter<true, true, true>
+                                           : k_batch_advance_scatter<true, false, true>)
+                                   : (pipe ? k_batch_advance_scatter<false, true, true>
+                                           : k_batch_advance_scatter<false, false, true>))
+                   : (c.r0 == 0.0f ? (pipe ? k_batch_advance_scatter<true, true, false>
+                                           : k_batch_advance_scatter<true, false, false>)
+                                   : (pipe ? k_batch_advance_scatter<false, true, false>
+                                           : k_batch_advance_scatter<false, false, false>));
         if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
             return HPF_EINVAL;
@@ -755,7 +790,7 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
         auto* partials = b->at<unsigned long long>(L.off_partials);
         auto* counts = reinterpret_cast<unsigned long long*>(b->buf.counts);
         hipLaunchKernelGGL(fn, ga, ba, smem, s, reps, adv, c.brick, c.halo, c.K, R, Rn, Vel, T, L.Ntot, G, bonds,
-                           c.D, c.k_bond, c.r0, c.dt, cs, partials, counts, e, kp, nslot);
+                           c.D, c.k_bond, c.r0, c.dt, cs, partials, counts, e, kp, nslot, th);
         b->pending = true;
     } else if (b->n_bead_items > 0) {
         if (prime) {
@@ -766,14 +801,19 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
                 hipLaunchKernelGGL(k_batch_prime<false>, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot, G,
                                    bonds, c.D, c.k_bond, c.r0, c.dt, e, kp, nslot);
         } else {
-            if (c.r0 == 0.0f)
-                hipLaunchKernelGGL(k_batch_advance<true>, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot, G,
-                                   bonds, c.D, c.k_bond, c.r0, c.dt, e, kp, nslot);
-            else
-                hipLaunchKernelGGL(k_batch_advance<false>, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot,
-                                   G, bonds, c.D, c.k_bond, c.r0, c.dt, e, kp, nslot);
+            using BAdvFn = void (*)(const RepK*, const ItemK*, int, const float4*, float4*, float4*, const uint8_t*,
+                                    int64_t, const float4*, const int32_t*, int, float, float, float, double*,
+                                    double*, int, ThermoK);
+            const BAdvFn fa = th.thr ? (c.r0 == 0.0f ? k_batch_advance<true, true> : k_batch_advance<false, true>)
+                                     : (c.r0 == 0.0f ? k_batch_advance<true, false> : k_batch_advance<false, false>);
+            hipLaunchKernelGGL(fa, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot, G, bonds, c.D, c.k_bond,
+                               c.r0, c.dt, e, kp, nslot, th);
         }
     }
+    if (prime)
+        hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, tstep, (int64_t)1);
+    else if (th.thr)
+        hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, s, tstep, (int64_t)1);
     b->rcur = 1 - b->rcur;
     if (report)
         hipLaunchKernelGGL(k_batch_reduce, dim3(b->nrep), dim3(64), 0, s,
@@ -810,8 +850,13 @@ hpf_status_t hpf_batch_create(const hpf_replica_t* reps, int32_t n_rep, const hp
     if (c.brick == 0)
         c.brick = 8;
     if (c.halo < 0 || c.halo > kTcMaxHalo || c.halo >= c.brick || !(c.dt > 0.0f) || c.sort_every < 0 ||
-        c.bead_chunk < kMinBeadChunk || c.mesh_chunk < kMinMeshChunk || c.fuse_deposit < 0 || c.fuse_deposit > 1)
+        c.bead_chunk < kMinBeadChunk || c.mesh_chunk < kMinMeshChunk || c.fuse_deposit < 0 || c.fuse_deposit > 1 ||
+        !(c.thermo_p >= 0.0f && c.thermo_p <= 1.0f))
         return HPF_EINVAL;
+    if (c.thermo_p > 0.0f)
+        for (int r = 0; r < n_rep; ++r)
+            if (!(reps[r].kT > 0.0) || !std::isfinite(reps[r].kT))
+                return HPF_EINVAL;
     for (int i = 0; i < 2; ++i)
         if (L.Ntot > 0 && (!bufs->R[i] || !bufs->Vel[i] || !bufs->T[i] || !bufs->tag[i] ||
                            (c.D > 0 && !bufs->bonds[i])))
@@ -874,6 +919,7 @@ hpf_status_t hpf_batch_create(const hpf_replica_t* reps, int32_t n_rep, const hp
         rk.nbricks = (int64_t)rk.nb[0] * rk.nb[1] * rk.nb[2];
         rk.NK = (uint32_t)rk.nbricks;
         rk.brick_off = brick_off;
+        rk.kT = (float)q.kT;
         key_base += rk.NK + 1;
         moff += rk.m.nm;
         brick_off += rk.nbricks;

@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "hpf_common.hpp"
+#include "hpf_thermo.hpp"
 
 namespace hpf {
 
@@ -134,48 +135,6 @@ __device__ __forceinline__ bool field_force(const float4& r, int t, const MeshK&
         return false;
     float4 g[8];
     corners_global(b, t, m, G, g);
-    f = interp8(b, g);
-    return true;
-}
-
-// A brick's gradient box in LDS: mesh points [o - h, o - h + P) per axis
-// (periodic; o = the brick's first cell), all K species, x fastest.
-struct GBox {
-    const float4* lds;
-    int32_t o[3];
-    int32_t h, P;
-};
-
-// Field force as field_force, with the corners read from the brick's LDS box
-// when the bead's cell lies within it, else from memory. Same values, same
-// arithmetic: the result is bitwise that of field_force.
-__device__ __forceinline__ bool field_force_box(const float4& r, int t, const MeshK& m, int K,
-                                                const float4* __restrict__ G, const GBox& gb, float3& f)
-{
-    BeadCell b;
-    f = make_float3(0.0f, 0.0f, 0.0f);
-    if (!(bead_cell(r, m, b) && t < K))
-        return false;
-    const int P = gb.P;
-    const int lx = periodic_delta(b.c[0], gb.o[0], m.M[0]) + gb.h;
-    const int ly = periodic_delta(b.c[1], gb.o[1], m.M[1]) + gb.h;
-    const int lz = periodic_delta(b.c[2], gb.o[2], m.M[2]) + gb.h;
-    float4 g[8];
-    if (gb.lds && (unsigned)lx <= (unsigned)(P - 2) && (unsigned)ly <= (unsigned)(P - 2) &&
-        (unsigned)lz <= (unsigned)(P - 2)) {
-        const int P2 = P * P;
-        const float4* c0 = gb.lds + (t * P + lz) * P2 + ly * P + lx;
-        g[0] = c0[0];
-        g[1] = c0[1];
-        g[2] = c0[P];
-        g[3] = c0[P + 1];
-        g[4] = c0[P2];
-        g[5] = c0[P2 + 1];
-        g[6] = c0[P2 + P];
-        g[7] = c0[P2 + P + 1];
-    } else {
-        corners_global(b, t, m, G, g);
-    }
     f = interp8(b, g);
     return true;
 }
@@ -376,9 +335,9 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__
 
 // One bead of the fused pass: field force + bond forces at x_n, second half
 // kick of step n (kinetic-energy partials at v_n), first half kick and drift
-// of step n + 1, written to R_next.
-// With kBox the corners come from the brick box `gb` where they can.
-template <bool kR0Zero, bool kBox = false>
+// of step n + 1, written to R_next. With kThermo the Andersen collisions of th act
+// on v_n (a separate instantiation, so the NVE passes keep their register budget).
+template <bool kR0Zero, bool kThermo>
 __device__ __forceinline__ float4 advance_bead(int64_t i, const float4* __restrict__ R, float4* __restrict__ R_next,
                                              float4* __restrict__ Vel, const uint8_t* __restrict__ T,
                                              int64_t N, const MeshK& m, int K, const float4* __restrict__ G,
@@ -386,14 +345,11 @@ __device__ __forceinline__ float4 advance_bead(int64_t i, const float4* __restri
                                              const BoxK& box, const float* __restrict__ inv_mass, float dt,
                                              float hdt, float4* __restrict__ F_out, KinAcc& acc, double& e,
                                              bool& bad_bead, bool& bad_bond, bool& nonfinite,
-                                             const GBox* gb = nullptr)
+                                             const ThermoK& th, uint64_t tstep)
 {
     float4 r = R[i];
     float3 ff;
-    if (kBox)
-        bad_bead |= !field_force_box(r, T[i], m, K, G, *gb, ff);
-    else
-        bad_bead |= !field_force(r, T[i], m, K, G, ff);
+    bad_bead |= !field_force(r, T[i], m, K, G, ff);
     float ei;
     const float3 fb = bond_sum<kR0Zero>(i, r, R, N, bonds, D, k, r0, box, ei, bad_bond);
     float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
@@ -406,6 +362,8 @@ __device__ __forceinline__ float4 advance_bead(int64_t i, const float4* __restri
     const float im = inv_mass ? inv_mass[i] : 1.0f;
     float4 v = Vel[i];
     kick(v, f, im, hdt);                 // v_n
+    if (kThermo && th.thr)
+        andersen_collide(th, tstep, th.tag[i], im, v);
     acc.add(v, im);
     kick(v, f, im, hdt);                 // v_{n+1/2}
     drift(r, v, dt, box);                // x_{n+1}
@@ -428,18 +386,21 @@ struct BeadIn {
     float4 r, v;
     float im;
     int t;
+    int32_t tag;
     int32_t j[kPreBonds];
 };
 
+template <bool kThermo>
 __device__ __forceinline__ void bead_fetch(BeadIn& p, int64_t i, const float4* __restrict__ R,
                                            const float4* __restrict__ Vel, const uint8_t* __restrict__ T,
                                            const int32_t* __restrict__ bonds, int D, int64_t N,
-                                           const float* __restrict__ inv_mass)
+                                           const float* __restrict__ inv_mass, const ThermoK& th)
 {
     p.r = R[i];
     p.v = Vel[i];
     p.t = T[i];
     p.im = inv_mass ? inv_mass[i] : 1.0f;
+    p.tag = (kThermo && th.thr) ? th.tag[i] : 0;
 #pragma unroll
     for (int b = 0; b < kPreBonds; ++b)
         p.j[b] = b < D ? bonds[(int64_t)b * N + i] : -1;
@@ -470,12 +431,12 @@ __device__ __forceinline__ void bead_issue(BeadLoads& L, const BeadIn& p, int64_
     }
 }
 
-template <bool kR0Zero>
+template <bool kR0Zero, bool kThermo>
 __device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const BeadLoads& L,
                                               float4* __restrict__ R_next, float4* __restrict__ Vel, int64_t N,
                                               int D, float k, float r0, const BoxK& box, float dt, float hdt,
                                               float4* __restrict__ F_out, KinAcc& acc, double& e, bool& bad_bead,
-                                              bool& bad_bond, bool& nonfinite)
+                                              bool& bad_bond, bool& nonfinite, const ThermoK& th, uint64_t tstep)
 {
     float4 r = p.r;
     float3 ff = make_float3(0.0f, 0.0f, 0.0f);
@@ -525,6 +486,8 @@ __device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const 
         F_out[i] = f;
     float4 v = p.v;
     kick(v, f, p.im, hdt);               // v_n
+    if (kThermo && th.thr)
+        andersen_collide(th, tstep, p.tag, p.im, v);
     acc.add(v, p.im);
     kick(v, f, p.im, hdt);               // v_{n+1/2}
     drift(r, v, dt, box);                // x_{n+1}
@@ -540,7 +503,7 @@ __device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const 
 // (4% faster at 10M beads than 256); the general loop keeps kPThreads.
 constexpr int kAdvPipeThreads = 512;
 
-template <bool kR0Zero, bool kPipe>
+template <bool kR0Zero, bool kPipe, bool kThermo>
 __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float4* __restrict__ R,
                                                        float4* __restrict__ R_next,
                                                        float4* __restrict__ Vel,
@@ -551,9 +514,10 @@ __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float4* __res
                                                        const float* __restrict__ inv_mass, float dt,
                                                        float4* __restrict__ F_out,
                                                        double* __restrict__ e_part,
-                                                       double* __restrict__ kin_part)
+                                                       double* __restrict__ kin_part, ThermoK th)
 {
     __shared__ double scratch[kAdvPipeThreads / kWave];
+    const uint64_t tstep = thermo_step(th);
     const BeadWalk w = bead_walk(N, kPipe ? kAdvPipeThreads : kPThreads);
     clear_unused_slots(e_part, 1);
     clear_unused_slots(kin_part, 4);
@@ -568,22 +532,23 @@ __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float4* __res
         int64_t i = w.first + threadIdx.x;
         BeadIn cur;
         if (i < w.end)
-            bead_fetch(cur, i, R, Vel, T, bonds, D, N, inv_mass);
+            bead_fetch<kThermo>(cur, i, R, Vel, T, bonds, D, N, inv_mass, th);
         for (; i < w.end; i += w.stride) {
             BeadLoads L;
             bead_issue(L, cur, i, m, K, G, R, N);
             __builtin_amdgcn_sched_barrier(0);
             BeadIn nxt;
-            bead_fetch(nxt, i + w.stride < w.end ? i + w.stride : i, R, Vel, T, bonds, D, N, inv_mass);
+            bead_fetch<kThermo>(nxt, i + w.stride < w.end ? i + w.stride : i, R, Vel, T, bonds, D, N, inv_mass,
+                                th);
             __builtin_amdgcn_sched_barrier(0);
-            bead_finish<kR0Zero>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt, F_out, acc, e, bad_bead,
-                                 bad_bond, nonfinite);
+            bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt, F_out, acc, e,
+                                          bad_bead, bad_bond, nonfinite, th, tstep);
             cur = nxt;
         }
     } else {
         FOR_BEADS(w, i) {
-            advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box, inv_mass, dt, hdt,
-                                  F_out, acc, e, bad_bead, bad_bond, nonfinite);
+            advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box, inv_mass, dt,
+                                           hdt, F_out, acc, e, bad_bead, bad_bond, nonfinite, th, tstep);
         }
     }
     if (bad_bead)
@@ -601,99 +566,9 @@ __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float4* __res
         acc.store(kin_part, w.block, scratch);
 }
 
-// Fused pass over cell-sorted beads, one brick of the sort at a time. The
-// beads a brick listed at the last sort (one contiguous range) are processed
-// by one workgroup after it has staged the brick's gradient box, P = B + 1 +
-// 2h points per axis and species, in LDS; a bead that has since moved more
-// than h cells out of the brick, or that the sort could not bin (the range
-// after the last brick), reads its corners from memory. Each bead's update is
-// bitwise that of k_advance. Bricks are walked like beads in bead_walk: the
-// bricks are cut into one contiguous run per XCD, and that XCD's workgroups
-// take the bricks of its run in turn. A workgroup's partial-sum slot is its
-// launch index.
-constexpr int kAThreads = 512;
-
-template <bool kR0Zero>
-__global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __restrict__ R,
-                                                             float4* __restrict__ R_next,
-                                                             float4* __restrict__ Vel,
-                                                             const uint8_t* __restrict__ T, int64_t N,
-                                                             TileK tk, int K, const float4* __restrict__ G,
-                                                             const int32_t* __restrict__ bonds, int D,
-                                                             float k, float r0, BoxK box,
-                                                             const float* __restrict__ inv_mass, float dt,
-                                                             const uint32_t* __restrict__ cell_start,
-                                                             float4* __restrict__ F_out,
-                                                             double* __restrict__ e_part,
-                                                             double* __restrict__ kin_part)
-{
-    extern __shared__ float4 gsm[];
-    __shared__ double scratch[kAThreads / kWave];
-    clear_unused_slots(e_part, 1);
-    clear_unused_slots(kin_part, 4);
-    const MeshK& m = tk.m;
-    const int B = tk.B, P = tk.P, h = tk.h;
-    const int P2 = P * P, P3 = P2 * P;
-    const int nbox = K * P3;
-    const BrickWalk w = brick_walk(tk.ntiles + 1);
-    const float hdt = 0.5f * dt;
-    KinAcc acc;
-    double e = 0.0;
-    bool bad_bead = false, bad_bond = false, nonfinite = false;
-    for (int64_t item = w.first; item < w.end; item += w.stride) {
-        GBox gb;
-        gb.lds = nullptr;
-        gb.h = h;
-        gb.P = P;
-        int64_t first, last;
-        if (item < tk.ntiles) {
-            const int bx = (int)(item % tk.nb[0]);
-            const int by = (int)((item / tk.nb[0]) % tk.nb[1]);
-            const int bz = (int)(item / ((int64_t)tk.nb[0] * tk.nb[1]));
-            gb.o[0] = bx * B;
-            gb.o[1] = by * B;
-            gb.o[2] = bz * B;
-            __syncthreads();                          // the previous brick's box reads are done
-            for (int q = threadIdx.x; q < nbox; q += kAThreads) {
-                const int t = q / P3, rem = q - t * P3;
-                const int lz = rem / P2, rem2 = rem - lz * P2;
-                const int ly = rem2 / P, lx = rem2 - ly * P;
-                const int gx = wrap_idx(gb.o[0] - h + lx, m.M[0]);
-                const int gy = wrap_idx(gb.o[1] - h + ly, m.M[1]);
-                const int gz = wrap_idx(gb.o[2] - h + lz, m.M[2]);
-                gsm[q] = G[(int64_t)t * m.nm + ((int64_t)gz * m.M[1] + gy) * m.M[0] + gx];
-            }
-            __syncthreads();
-            gb.lds = gsm;
-            first = cell_start[item];
-            last = cell_start[item + 1];
-        } else {
-            gb.o[0] = gb.o[1] = gb.o[2] = 0;
-            first = cell_start[tk.NK];
-            last = N;
-        }
-        last = min(last, N);
-        for (int64_t i = first + threadIdx.x; i < last; i += kAThreads)
-            advance_bead<kR0Zero, true>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box, inv_mass, dt, hdt,
-                                        F_out, acc, e, bad_bead, bad_bond, nonfinite, &gb);
-    }
-    if (bad_bead)
-        raise_flag(HPF_FLAG_BAD_BEAD);
-    if (bad_bond)
-        raise_flag(HPF_FLAG_BAD_BOND);
-    if (nonfinite)
-        raise_flag(HPF_FLAG_NONFINITE);
-    if (e_part) {
-        const double s = block_sum(e, scratch);
-        if (threadIdx.x == 0)
-            e_part[blockIdx.x] = s;
-    }
-    if (kin_part)
-        acc.store(kin_part, blockIdx.x, scratch);
-}
-
 // The fused pass plus the density deposit of the new positions, one brick of
-// the last sort at a time (bricks walked as in k_advance_cells). Each bead is
+// the last sort at a time (bricks walked as the beads are in bead_walk: one
+// contiguous run of bricks per XCD, taken in turn by its workgroups). Each bead is
 // advanced exactly as in k_advance; its new position x_{n+1} is deposited into
 // the brick's LDS box (the deposit box of the cell scatter, P = B + 1 + 2h
 // points per axis), which is stored to the brick's partial buffer when the
@@ -708,7 +583,7 @@ __global__ __launch_bounds__(kAThreads) void k_advance_cells(const float4* __res
 // kPreBonds rows); the plain loop serves wider tables.
 constexpr int kASThreadsDefault = 512;
 
-template <bool kR0Zero, int kASThreads, bool kPipe>
+template <bool kR0Zero, int kASThreads, bool kPipe, bool kThermo>
 __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __restrict__ R,
                                                                 float4* __restrict__ R_next,
                                                                 float4* __restrict__ Vel,
@@ -722,9 +597,10 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
                                                                 unsigned long long* __restrict__ counts,
                                                                 float4* __restrict__ F_out,
                                                                 double* __restrict__ e_part,
-                                                                double* __restrict__ kin_part)
+                                                                double* __restrict__ kin_part, ThermoK th)
 {
     extern __shared__ unsigned long long dbox[];
+    const uint64_t tstep = thermo_step(th);
     __shared__ double scratch[kASThreads / kWave];
     clear_unused_slots(e_part, 1);
     clear_unused_slots(kin_part, 4);
@@ -758,16 +634,17 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
                 int64_t i = first + threadIdx.x;
                 BeadIn cur;
                 if (i < last)
-                    bead_fetch(cur, i, R, Vel, T, bonds, D, N, inv_mass);
+                    bead_fetch<kThermo>(cur, i, R, Vel, T, bonds, D, N, inv_mass, th);
                 for (; i < last; i += kASThreads) {
                     BeadLoads L;
                     bead_issue(L, cur, i, m, K, G, R, N);
                     __builtin_amdgcn_sched_barrier(0);
                     BeadIn nxt;
-                    bead_fetch(nxt, min(i + kASThreads, last - 1), R, Vel, T, bonds, D, N, inv_mass);
+                    bead_fetch<kThermo>(nxt, min(i + kASThreads, last - 1), R, Vel, T, bonds, D, N, inv_mass, th);
                     __builtin_amdgcn_sched_barrier(0);
-                    const float4 rn = bead_finish<kR0Zero>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt,
-                                                           F_out, acc, e, bad_bead, bad_bond, nonfinite);
+                    const float4 rn = bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt,
+                                                           F_out, acc, e, bad_bead, bad_bond, nonfinite, th,
+                                                           tstep);
                     const int t = cur.t;
                     BeadCell b;
                     int lx, ly, lz;
@@ -780,9 +657,9 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
                 }
             } else {
                 for (int64_t i = first + threadIdx.x; i < last; i += kASThreads) {
-                    const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0,
-                                                            box, inv_mass, dt, hdt, F_out, acc, e, bad_bead,
-                                                            bad_bond, nonfinite);
+                    const float4 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k,
+                                                            r0, box, inv_mass, dt, hdt, F_out, acc, e, bad_bead,
+                                                            bad_bond, nonfinite, th, tstep);
                     const int t = T[i];
                     BeadCell b;
                     int lx, ly, lz;
@@ -800,9 +677,9 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
         } else {
             const int64_t first = cell_start[tk.NK];
             for (int64_t i = first + threadIdx.x; i < N; i += kASThreads) {
-                const float4 rn = advance_bead<kR0Zero>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0, box,
-                                                        inv_mass, dt, hdt, F_out, acc, e, bad_bead, bad_bond,
-                                                        nonfinite);
+                const float4 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0,
+                                                        box, inv_mass, dt, hdt, F_out, acc, e, bad_bead, bad_bond,
+                                                        nonfinite, th, tstep);
                 bad_bead |= !deposit_global(rn, T[i], K, m, counts);
             }
         }
@@ -881,7 +758,7 @@ hpf_status_t launch_verlet(float* R, float* Vel, const float* F, const float* in
 hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
                             const MeshK& m, int K, const float* G, const int32_t* bonds, int D, float k,
                             float r0, const BoxK& box, const float* inv_mass, float dt, float* F_out,
-                            double* e_part, double* kin_part, hipStream_t s)
+                            double* e_part, double* kin_part, const ThermoK& th, hipStream_t s)
 {
     if (N == 0 && !e_part && !kin_part)
         return HPF_OK;
@@ -897,63 +774,30 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
     auto* Gp = reinterpret_cast<const float4*>(G);
     auto* Fo = reinterpret_cast<float4*>(F_out);
     using AdvFn = void (*)(const float4*, float4*, float4*, const uint8_t*, int64_t, MeshK, int, const float4*,
-                           const int32_t*, int, float, float, BoxK, const float*, float, float4*, double*, double*);
-    const AdvFn fn = r0 == 0.0f ? (pipe ? k_advance<true, true> : k_advance<true, false>)
-                                : (pipe ? k_advance<false, true> : k_advance<false, false>);
+                           const int32_t*, int, float, float, BoxK, const float*, float, float4*, double*, double*,
+                           ThermoK);
+    const bool thermo = th.thr != 0;
+    const AdvFn fn =
+        thermo ? (r0 == 0.0f ? (pipe ? k_advance<true, true, true> : k_advance<true, false, true>)
+                             : (pipe ? k_advance<false, true, true> : k_advance<false, false, true>))
+               : (r0 == 0.0f ? (pipe ? k_advance<true, true, false> : k_advance<true, false, false>)
+                             : (pipe ? k_advance<false, true, false> : k_advance<false, false, false>));
     hipLaunchKernelGGL(fn, g, bl, 0, s, Rp, Rn, Vp, T, N, m, K, Gp, bonds, D, k, r0, box, inv_mass, dt, Fo,
-                       e_part, kin_part);
+                       e_part, kin_part, th);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
-static size_t advance_cells_smem(int K, int P) { return sizeof(float4) * (size_t)K * P * P * P; }
-
-hpf_status_t launch_advance_cells(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
-                                  const TileK& tk, int K, const float* G, const int32_t* bonds, int D, float k,
-                                  float r0, const BoxK& box, const float* inv_mass, float dt,
-                                  const uint32_t* cell_start, float* F_out, double* e_part, double* kin_part,
-                                  hipStream_t s)
-{
-    if (N == 0 && !e_part && !kin_part)
-        return HPF_OK;
-    const size_t smem = advance_cells_smem(K, tk.P);
-    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_cells<true>)
-                                : reinterpret_cast<const void*>(k_advance_cells<false>);
-    if (smem > 65536 &&
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
-        return HPF_EINVAL;
-    // one resident wave of workgroups walks all bricks (no late stragglers)
-    int64_t nb = resident_blocks(fn, kAThreads, smem);
-    if (nb < 1)
-        nb = 512;
-    nb = std::min<int64_t>(nb, tk.ntiles + 1);
-    if ((e_part || kin_part) && nb > HPF_NPART)
-        nb = HPF_NPART;
-    const dim3 g((unsigned)nb), bl(kAThreads);
-    auto* Rp = reinterpret_cast<const float4*>(R);
-    auto* Rn = reinterpret_cast<float4*>(R_next);
-    auto* Vp = reinterpret_cast<float4*>(Vel);
-    auto* Gp = reinterpret_cast<const float4*>(G);
-    auto* Fo = reinterpret_cast<float4*>(F_out);
-    if (r0 == 0.0f)
-        hipLaunchKernelGGL(k_advance_cells<true>, g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0,
-                           box, inv_mass, dt, cell_start, Fo, e_part, kin_part);
-    else
-        hipLaunchKernelGGL(k_advance_cells<false>, g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0,
-                           box, inv_mass, dt, cell_start, Fo, e_part, kin_part);
-    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
-}
-
-template <int kThreads, bool kPipe>
+template <int kThreads, bool kPipe, bool kThermo>
 static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float4* Vp, const uint8_t* T, int64_t N,
                                              const TileK& tk, int K, const float4* Gp, const int32_t* bonds, int D,
                                              float k, float r0, const BoxK& box, const float* inv_mass, float dt,
                                              const uint32_t* cell_start, unsigned long long* partials,
                                              unsigned long long* counts, float4* Fo, double* e_part,
-                                             double* kin_part, hipStream_t s)
+                                             double* kin_part, const ThermoK& th, hipStream_t s)
 {
     const size_t smem = sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P;
-    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_scatter<true, kThreads, kPipe>)
-                                : reinterpret_cast<const void*>(k_advance_scatter<false, kThreads, kPipe>);
+    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_scatter<true, kThreads, kPipe, kThermo>)
+                                : reinterpret_cast<const void*>(k_advance_scatter<false, kThreads, kPipe, kThermo>);
     if (smem > 65536 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
         return HPF_EINVAL;
@@ -962,11 +806,13 @@ static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float
     const int64_t nb = std::min<int64_t>(tk.ntiles + 1, HPF_NPART);
     const dim3 g((unsigned)nb), bl(kThreads);
     if (r0 == 0.0f)
-        hipLaunchKernelGGL((k_advance_scatter<true, kThreads, kPipe>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp,
-                           bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
+        hipLaunchKernelGGL((k_advance_scatter<true, kThreads, kPipe, kThermo>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp,
+                           bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part,
+                           th);
     else
-        hipLaunchKernelGGL((k_advance_scatter<false, kThreads, kPipe>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp,
-                           bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part);
+        hipLaunchKernelGGL((k_advance_scatter<false, kThreads, kPipe, kThermo>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp,
+                           bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part,
+                           th);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
@@ -975,7 +821,7 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
                                     float r0, const BoxK& box, const float* inv_mass, float dt,
                                     const uint32_t* cell_start, unsigned long long* partials,
                                     unsigned long long* counts, float* F_out, double* e_part, double* kin_part,
-                                    hipStream_t s)
+                                    const ThermoK& th, hipStream_t s)
 {
     auto* Rp = reinterpret_cast<const float4*>(R);
     auto* Rn = reinterpret_cast<float4*>(R_next);
@@ -983,13 +829,45 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
     auto* Gp = reinterpret_cast<const float4*>(G);
     auto* Fo = reinterpret_cast<float4*>(F_out);
     // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
-    if (D <= kPreBonds)
-        return launch_advance_scatter_t<kASThreadsDefault, true>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box,
-                                                                 inv_mass, dt, cell_start, partials, counts, Fo,
-                                                                 e_part, kin_part, s);
-    return launch_advance_scatter_t<kASThreadsDefault, false>(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box,
-                                                              inv_mass, dt, cell_start, partials, counts, Fo,
-                                                              e_part, kin_part, s);
+    const bool pipe = D <= kPreBonds, thermo = th.thr != 0;
+    auto* launch = pipe ? (thermo ? launch_advance_scatter_t<kASThreadsDefault, true, true>
+                                  : launch_advance_scatter_t<kASThreadsDefault, true, false>)
+                        : (thermo ? launch_advance_scatter_t<kASThreadsDefault, false, true>
+                                  : launch_advance_scatter_t<kASThreadsDefault, false, false>);
+    return launch(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo,
+                  e_part, kin_part, th, s);
+}
+
+// Andersen collisions of time level *th.step on every bead (after the second half
+// kick), and optionally the kinetic-energy and momentum partials of the result.
+__global__ __launch_bounds__(kPThreads) void k_andersen(float4* __restrict__ Vel, const float* __restrict__ inv_mass,
+                                                        int64_t N, ThermoK th, double* __restrict__ kin_part)
+{
+    __shared__ double scratch[kPThreads / kWave];
+    const BeadWalk w = bead_walk(N);
+    clear_unused_slots(kin_part, 4);
+    const uint64_t tstep = thermo_step(th);
+    KinAcc acc;
+    FOR_BEADS(w, i) {
+        const float im = inv_mass ? inv_mass[i] : 1.0f;
+        float4 v = Vel[i];
+        if (th.thr && andersen_collide(th, tstep, th.tag[i], im, v))
+            Vel[i] = v;
+        acc.add(v, im);
+    }
+    if (kin_part)
+        acc.store(kin_part, w.block, scratch);
+}
+
+hpf_status_t launch_andersen(float* Vel, const float* inv_mass, int64_t N, const ThermoK& th, double* kin_part,
+                             hipStream_t s)
+{
+    if (N == 0 && !kin_part)
+        return HPF_OK;
+    const int64_t nb = bead_blocks(N, kin_part ? HPF_NPART : (1 << 20));
+    hipLaunchKernelGGL(k_andersen, dim3((unsigned)nb), dim3(kPThreads), 0, s, reinterpret_cast<float4*>(Vel),
+                       inv_mass, N, th, kin_part);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
 hpf_status_t launch_scatter_finish(const unsigned long long* partials, const TileK& tk, int K,

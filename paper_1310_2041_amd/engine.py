@@ -28,7 +28,7 @@ class HpfState:
     """One periodic system on the GPU: beads, bond table, mesh buffers."""
 
     def __init__(self, R, Vel, T, tag, bonds, L, M, K, kT, inv_kappa, chi, k_bond, r0, dt,
-                 device="cuda", sort_brick=8, halo=1, advance_halo=1, advance="scatter",
+                 device="cuda", sort_brick=8, halo=1, advance="scatter",
                  field_every=1):
         dev = torch.device(device)
         self.N = int(R.shape[0])
@@ -42,10 +42,9 @@ class HpfState:
         self.box = self.L
         self.B = int(sort_brick)
         self.halo = int(halo)
-        self.advance_halo = int(advance_halo)
         # How the fused step advances cell-sorted beads: "scatter" = hpf_advance_scatter (also
-        # deposits x_n+1, so the next step only finishes the density), "plain" = hpf_advance,
-        # "cells" = hpf_advance_cells. Unsorted beads always take hpf_advance.
+        # deposits x_n+1, so the next step only finishes the density), "plain" = hpf_advance.
+        # Unsorted beads always take hpf_advance.
         self.advance_mode = advance
         # Field-update interval (MD-SCF section): the density field (counts, V, G) is rebuilt
         # at force evaluations whose index is a multiple of field_every (evaluation 0 is
@@ -57,6 +56,9 @@ class HpfState:
         self.density_pending = False   # partial boxes + counts hold the deposit of the current R
         # when True, the fused passes also store the total force at x_n into F (F_out)
         self.keep_force = False
+        # Andersen thermostat (set_thermostat): (p, kT, seed) and the device time level
+        self.thermo = None
+        self.tstep = None
         self.sorted = False      # storage order comes from hpf_sort_by_cell
         nm = self.mesh.M[0] * self.mesh.M[1] * self.mesh.M[2]
         self.nm = nm
@@ -92,6 +94,27 @@ class HpfState:
         self.part = torch.zeros((N_ROWS, hpf.HPF_NPART), dtype=torch.float64, device=dev)
         self.energy = torch.zeros(8, dtype=torch.float64, device=dev)
         self.steps_done = 0
+
+    def set_thermostat(self, rate: float, kT: float | None = None, seed: int = 1):
+        """NVT with the Andersen thermostat (Integration methods section): every step each bead
+        collides with probability rate * dt and takes a Maxwell velocity at kT (the field's kT
+        by default). The time level of the collisions lives on the device and advances with
+        every step, so graph replays draw fresh numbers. rate = 0 returns to NVE."""
+        p = float(rate) * self.dt
+        if p == 0.0:
+            self.thermo = None
+            return
+        if not 0.0 < p <= 1.0:
+            raise ValueError("rate * dt must lie in (0, 1]")
+        self.thermo = (p, float(self.field.kT if kT is None else kT), int(seed))
+        self.tstep = torch.tensor([self.steps_done + 1], dtype=torch.int64, device=self.R.device)
+
+    def thermostat(self):
+        """The C thermostat description for the current storage order (None for NVE)."""
+        if self.thermo is None:
+            return None
+        p, kT, seed = self.thermo
+        return hpf.make_thermostat(p, kT, seed, self.tstep, self.tag)
 
     _SWAPPED = ("R", "R2", "Vel", "Vel2", "T", "T2", "tag", "tag2", "bonds", "bonds2")
 
@@ -167,11 +190,24 @@ class HpfState:
         if sort:
             self.sort(stream)
         self.forces(report, stream, rebuild=self.rebuilds_field(self.steps_done + 1))
+        kin = self.part[ROW_KE:ROW_KE + 4] if report else None
+        th = self.thermostat()
         hpf.verlet_step(None, self.Vel, self.F, self.dt, self.box, 2,
-                        kin_part=self.part[ROW_KE:ROW_KE + 4] if report else None, stream=stream)
+                        kin_part=kin if th is None else None, stream=stream)
+        if th is not None:
+            hpf.hpf_andersen(self.Vel, th, kin_part=kin, stream=stream)
+            self._advance_time_level(stream)
         if report:
             hpf.hpf_reduce_partials(self.part, N_ROWS, self.energy, stream)
         self.steps_done += 1
+
+    def _advance_time_level(self, stream=None):
+        if stream is None:
+            self.tstep.add_(1)
+        else:
+            with torch.cuda.stream(stream if isinstance(stream, torch.cuda.Stream) else
+                                   torch.cuda.ExternalStream(int(stream))):
+                self.tstep.add_(1)
 
     def start(self, sort=True, stream=None):
         """Initial sort and force evaluation, with energies of the initial state."""
@@ -217,38 +253,32 @@ class HpfState:
             self.scatter(stream)
             hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V, w, stream)
 
-    def uses_cells_advance(self) -> bool:
-        return (self.advance_mode == "cells" and self.sorted and
-                hpf.advance_cells_fits(self.K, self.B, self.advance_halo))
-
     def uses_scatter_advance(self) -> bool:
         return self.advance_mode == "scatter" and self.sorted and self.cells_ok
 
     def advance(self, report=False, stream=None, deposit=True):
-        """Fused forces + Verlet pass, x_n -> x_n+1 (with the density deposit of x_n+1, or the
-        brick-box variant, when cell-sorted). Counts must be zero on entry (the potential pass
+        """Fused forces + Verlet pass, x_n -> x_n+1 (with the density deposit of x_n+1 when
+        cell-sorted). Counts must be zero on entry (the potential pass
         leaves them so). Without `deposit` (the next step keeps the field) the plain pass runs
         instead of the depositing one; the beads move the same either way."""
         bonds = self.bonds if self.bonds.shape[0] else None
         e_part = self.part[ROW_EB] if report else None
         kin_part = self.part[ROW_KE:ROW_KE + 4] if report else None
         F_out = self.F if self.keep_force else None
+        th = self.thermostat()
         self.density_pending = False
         if deposit and self.uses_scatter_advance():
             hpf.hpf_advance_scatter(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
                                     self.k_bond, self.r0, self.box, self.dt, self.cell_start, self.B,
                                     self.halo, self.counts, self.scatter_work, F_out=F_out, e_part=e_part,
-                                    kin_part=kin_part, stream=stream)
+                                    kin_part=kin_part, thermostat=th, stream=stream)
             self.density_pending = True
-        elif self.uses_cells_advance():
-            hpf.hpf_advance_cells(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
-                                  self.k_bond, self.r0, self.box, self.dt, self.cell_start, self.B,
-                                  self.advance_halo, F_out=F_out, e_part=e_part, kin_part=kin_part,
-                                  stream=stream)
         else:
             hpf.hpf_advance(self.R, self.R2, self.Vel, self.T, self.mesh, self.K, self.G, bonds,
                             self.k_bond, self.r0, self.box, self.dt, F_out=F_out, e_part=e_part,
-                            kin_part=kin_part, stream=stream)
+                            kin_part=kin_part, thermostat=th, stream=stream)
+        if th is not None:
+            self._advance_time_level(stream)
         self.R, self.R2 = self.R2, self.R
 
     def run_fused(self, n_steps, report_every=0, sort_every=10, stream=None):
@@ -294,7 +324,8 @@ class BatchState:
     """
 
     def __init__(self, systems, sort_every=10, brick=8, halo=1, bead_chunk=4096,
-                 mesh_chunk=16384, fuse_deposit=True, device="cuda"):
+                 mesh_chunk=16384, fuse_deposit=True, device="cuda", thermostat_rate=0.0,
+                 thermostat_seed=1):
         dev = torch.device(device)
         s0 = systems[0]
         self.K = int(s0.K)
@@ -343,6 +374,9 @@ class BatchState:
         cfg.brick, cfg.halo, cfg.sort_every = brick, halo, sort_every
         cfg.bead_chunk, cfg.mesh_chunk = bead_chunk, mesh_chunk
         cfg.fuse_deposit = int(fuse_deposit)
+        # Andersen thermostat: collision probability per step, each replica at its own kT
+        cfg.thermo_p = float(thermostat_rate) * float(s0.dt)
+        cfg.thermo_seed = int(thermostat_seed)
         self.cfg = cfg
         ws = hpf.hpf_batch_workspace_bytes(reps, cfg)
         if ws == 0:

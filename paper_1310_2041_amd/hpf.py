@@ -61,7 +61,27 @@ class BatchConfig(C.Structure):
     _fields_ = [("K", C.c_int32), ("D", C.c_int32), ("k_bond", C.c_float), ("r0", C.c_float),
                 ("dt", C.c_float), ("brick", C.c_int32), ("halo", C.c_int32),
                 ("sort_every", C.c_int32), ("bead_chunk", C.c_int32), ("mesh_chunk", C.c_int32),
-                ("fuse_deposit", C.c_int32)]
+                ("fuse_deposit", C.c_int32), ("thermo_p", C.c_float), ("reserved", C.c_int32),
+                ("thermo_seed", C.c_uint64)]
+
+
+class Thermostat(C.Structure):
+    """hpf_thermostat_t (step and tag are device pointers)"""
+    _fields_ = [("p", C.c_float), ("kT", C.c_float), ("seed", C.c_uint64), ("step", C.c_void_p),
+                ("tag", C.c_void_p)]
+
+
+def make_thermostat(p: float, kT: float, seed: int, step, tag) -> Thermostat:
+    """Andersen thermostat description: collision probability p per step, bath kT, generator
+    key seed; step is a device int64 tensor of one element (the time level), tag the beads'
+    int32 tags in storage order."""
+    th = Thermostat()
+    th.p = float(p)
+    th.kT = float(kT)
+    th.seed = int(seed)
+    th.step = _dev(step, "step", torch.int64, (1,))
+    th.tag = _dev(tag, "tag", torch.int32, None)
+    return th
 
 
 class BatchBuffers(C.Structure):
@@ -91,13 +111,11 @@ _SIGNATURES = {
     "verlet_step": ([_P, _P, _P, _P, C.c_int64, C.c_float, _P, C.c_int32, _P, _P], C.c_int32),
     "hpf_reduce_partials": ([_P, C.c_int32, _P, _P], C.c_int32),
     "hpf_advance": ([_P, _P, _P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, C.c_int32,
-                     C.c_float, C.c_float, _P, _P, C.c_float, _P, _P, _P, _P], C.c_int32),
-    "hpf_advance_cells": ([_P, _P, _P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, C.c_int32,
-                           C.c_float, C.c_float, _P, _P, C.c_float, _P, C.c_int32, C.c_int32, _P, _P,
-                           _P, _P], C.c_int32),
+                     C.c_float, C.c_float, _P, _P, C.c_float, _P, _P, _P, _P, _P], C.c_int32),
+    "hpf_andersen": ([_P, _P, C.c_int64, _P, _P, _P], C.c_int32),
     "hpf_advance_scatter": ([_P, _P, _P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, C.c_int32,
                              C.c_float, C.c_float, _P, _P, C.c_float, _P, C.c_int32, C.c_int32, _P, _P,
-                             C.c_size_t, _P, _P, _P, _P], C.c_int32),
+                             C.c_size_t, _P, _P, _P, _P, _P], C.c_int32),
     "hpf_density_finish_cells": ([_P, C.c_int64, C.POINTER(Mesh), C.c_int32, C.c_int32, C.c_int32,
                                   _P, C.c_size_t, _P], C.c_int32),
     "hpf_field_potential_cells": ([_P, C.c_int64, C.POINTER(Mesh), C.POINTER(Field), C.c_int32, C.c_int32,
@@ -296,7 +314,8 @@ def verlet_step(R, Vel, F, dt: float, box, half: int, inv_mass=None, kin_part=No
 
 
 def hpf_advance(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float, r0: float, box,
-                dt: float, inv_mass=None, F_out=None, e_part=None, kin_part=None, stream=None):
+                dt: float, inv_mass=None, F_out=None, e_part=None, kin_part=None, thermostat=None,
+                stream=None):
     N = R.shape[0]
     D = bonds.shape[0] if bonds is not None else 0
     args = [
@@ -318,41 +337,26 @@ def hpf_advance(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float, r0: f
         raise ValueError("e_part needs HPF_NPART slots")
     if kin_part is not None and kin_part.numel() < 4 * HPF_NPART:
         raise ValueError("kin_part needs 4 * HPF_NPART slots")
-    _check("hpf_advance", lib().hpf_advance(*args, _stream(stream)))
+    _check("hpf_advance", lib().hpf_advance(*args, _thermo(thermostat), _stream(stream)))
 
 
-def hpf_advance_cells(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float, r0: float, box,
-                      dt: float, cell_start, B: int = 8, halo: int = 1, inv_mass=None, F_out=None,
-                      e_part=None, kin_part=None, stream=None):
-    N = R.shape[0]
-    D = bonds.shape[0] if bonds is not None else 0
-    args = [
-        _dev(R, "R", torch.float32, (N, 4)),
-        _dev(R_next, "R_next", torch.float32, (N, 4)),
-        _dev(Vel, "Vel", torch.float32, (N, 4)),
-        _dev(T, "T", torch.uint8, (N,)),
-        N, C.byref(mesh), int(K),
-        _dev(G, "G", torch.float32, (K, _nm(mesh), 4)),
-        _dev(bonds, "bonds", torch.int32, (D, N), allow_none=True) if D else None,
-        int(D), float(k), float(r0), _box(box),
-        _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True),
-        float(dt),
-        _dev(cell_start, "cell_start", torch.int32, (sort_key_count(mesh, B) + 2,)),
-        int(B), int(halo),
-        _dev(F_out, "F_out", torch.float32, (N, 4), allow_none=True),
-        _dev(e_part, "e_part", torch.float64, None, allow_none=True),
-        _dev(kin_part, "kin_part", torch.float64, None, allow_none=True),
-    ]
-    if e_part is not None and e_part.numel() < HPF_NPART:
-        raise ValueError("e_part needs HPF_NPART slots")
+def _thermo(th):
+    return None if th is None else C.byref(th)
+
+
+def hpf_andersen(Vel, thermostat: Thermostat, inv_mass=None, kin_part=None, stream=None):
+    N = Vel.shape[0]
     if kin_part is not None and kin_part.numel() < 4 * HPF_NPART:
         raise ValueError("kin_part needs 4 * HPF_NPART slots")
-    _check("hpf_advance_cells", lib().hpf_advance_cells(*args, _stream(stream)))
+    _check("hpf_andersen", lib().hpf_andersen(
+        _dev(Vel, "Vel", torch.float32, (N, 4)),
+        _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True), N, C.byref(thermostat),
+        _dev(kin_part, "kin_part", torch.float64, None, allow_none=True), _stream(stream)))
 
 
 def hpf_advance_scatter(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float, r0: float, box,
                         dt: float, cell_start, B: int, halo: int, counts, work, inv_mass=None,
-                        F_out=None, e_part=None, kin_part=None, stream=None):
+                        F_out=None, e_part=None, kin_part=None, thermostat=None, stream=None):
     N = R.shape[0]
     D = bonds.shape[0] if bonds is not None else 0
     args = [
@@ -378,7 +382,8 @@ def hpf_advance_scatter(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: floa
         raise ValueError("e_part needs HPF_NPART slots")
     if kin_part is not None and kin_part.numel() < 4 * HPF_NPART:
         raise ValueError("kin_part needs 4 * HPF_NPART slots")
-    _check("hpf_advance_scatter", lib().hpf_advance_scatter(*args, _stream(stream)))
+    _check("hpf_advance_scatter", lib().hpf_advance_scatter(*args, _thermo(thermostat),
+                                                            _stream(stream)))
 
 
 def hpf_density_finish_cells(counts, N: int, mesh: Mesh, K: int, B: int, halo: int, work,
@@ -402,12 +407,6 @@ def hpf_field_potential_cells(counts, N: int, mesh: Mesh, field: Field, B: int, 
     _check("hpf_field_potential_cells",
            lib().hpf_field_potential_cells(c, int(N), C.byref(mesh), C.byref(field), int(B), int(halo), w,
                                            work.numel(), v, wp, _stream(stream)))
-
-
-def advance_cells_fits(K: int, B: int = 8, halo: int = 1) -> bool:
-    """Whether the gradient box of hpf_advance_cells fits in 160 KiB of LDS."""
-    P = (B or 8) + 1 + 2 * halo
-    return K * P ** 3 * 16 <= 160 * 1024
 
 
 def hpf_reduce_partials(part, ncomp: int, out, stream=None):

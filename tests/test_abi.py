@@ -89,19 +89,7 @@ def test_invalid_arguments_rejected_on_host(hpf):
                               t_out, None, None, None, dummy, 1 << 30, None) == EINVAL
     assert L.hpf_sort_workspace_bytes(10, C.byref(m), 17) == 0
     assert L.hpf_get_device_status(None, 0, None) == EINVAL
-    # hpf_advance_cells: brick, halo, LDS size, missing cell list, aliasing
     r_n, v, g, cs = (C.c_void_p(0x1000 * k) for k in (6, 7, 8, 9))
-
-    def adv(K=2, B=8, halo=1, cell_start=cs, R_next=r_n):
-        return L.hpf_advance_cells(r_in, R_next, v, t_in, 10, C.byref(m), K, g, None, 0, 100.0, 0.0,
-                                   box, None, 0.03, cell_start, B, halo, None, None, None, None)
-    assert adv(B=9) == EINVAL
-    assert adv(B=2) == EINVAL
-    assert adv(halo=3) == EINVAL
-    assert adv(B=3, halo=3) == EINVAL
-    assert adv(K=8, halo=1) == EINVAL                # 8 x 11^3 x 16 B > 160 KiB of LDS
-    assert adv(cell_start=None) == EINVAL
-    assert adv(R_next=r_in) == EINVAL
     # hpf_advance_scatter / hpf_density_finish_cells: mesh limits, counts, workspace
     cnt, wk = C.c_void_p(0x10000), C.c_void_p(0x20000)
     m16 = hpf.hpf_mesh_make(16.0, 16, 100)
@@ -111,12 +99,23 @@ def test_invalid_arguments_rejected_on_host(hpf):
     def advs(mesh=m16, counts=cnt, work=wk, nbytes=need, B=8, halo=1):
         return L.hpf_advance_scatter(r_in, r_n, v, t_in, 10, C.byref(mesh), 2, g, None, 0, 100.0, 0.0,
                                      box, None, 0.03, cs, B, halo, counts, work, nbytes, None, None, None,
-                                     None)
+                                     None, None)
     assert advs(mesh=m) == EINVAL                     # M = 10 < B + 1 + 2 halo
     assert advs(counts=None) == EINVAL
     assert advs(halo=3) == EINVAL
     assert advs(nbytes=need - 1) == -3
     assert advs(work=None) == -3
+    # thermostat descriptions: probability outside [0, 1], no time level, no tags, kT <= 0
+    for p, kT, step, tag in ((1.5, 1.0, 8, 9), (-0.1, 1.0, 8, 9), (0.5, 1.0, None, 9),
+                             (0.5, 1.0, 8, None), (0.5, 0.0, 8, 9)):
+        th = hpf.Thermostat()
+        th.p, th.kT, th.seed = p, kT, 1
+        th.step = None if step is None else 0x1000 * step
+        th.tag = None if tag is None else 0x1000 * tag
+        assert L.hpf_andersen(v, None, 10, C.byref(th), None, None) == EINVAL
+        assert L.hpf_advance(r_in, r_n, v, t_in, 10, C.byref(m), 2, g, None, 0, 100.0, 0.0, box, None,
+                             0.03, None, None, None, C.byref(th), None) == EINVAL
+    assert L.hpf_andersen(v, None, 10, None, None, None) == EINVAL
     assert L.hpf_density_finish_cells(None, 10, C.byref(m16), 2, 8, 1, wk, need, None) == EINVAL
     assert L.hpf_density_finish_cells(cnt, 10, C.byref(m16), 2, 8, 1, wk, need - 1, None) == -3
     f2 = hpf.make_field(2, 1.0, 10.0, [[0.0, 1.0], [1.0, 0.0]])

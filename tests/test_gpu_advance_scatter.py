@@ -16,10 +16,9 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
-from gpu_util import counts_np, dev, host  # noqa: E402
+from gpu_util import counts_np, dev, drifted, field_of, host  # noqa: E402
 from paper_1310_2041_amd import engine, hpf  # noqa: E402
 from synth import workloads as wl  # noqa: E402
-from test_gpu_advance_cells import drifted, field_of  # noqa: E402
 
 
 def advance_pair(st, halo):

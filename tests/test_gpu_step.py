@@ -147,13 +147,13 @@ def test_determinism_bitwise():
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("advance", ["plain", "cells"])
+@pytest.mark.parametrize("advance", ["plain", "scatter"])
 @pytest.mark.parametrize("cfg,steps,sort_every", [("c1", 30, 7), ("c2", 12, 5)])
 def test_fused_advance_equals_separate_calls_bitwise(cfg, steps, sort_every, advance):
-    """The fused pass (hpf_advance, or hpf_advance_cells on cell-sorted beads) reproduces
-    gather + bonds + both half steps of the six calls bit for bit. Their energy partials are
-    grouped differently (512-bead chunks, or the brick walk, against the separate calls'
-    256-bead chunks), so energies agree to FP64 regrouping."""
+    """The fused pass (hpf_advance, or hpf_advance_scatter with the deposit on cell-sorted
+    beads) reproduces gather + bonds + both half steps of the six calls bit for bit. Their
+    energy partials are grouped differently (512-bead chunks, or the brick walk, against the
+    separate calls' 256-bead chunks), so energies agree to FP64 regrouping."""
     s = wl.build(wl.SPECS[cfg])
     a = engine.HpfState.from_system(s)
     a.start(sort=True)
@@ -163,7 +163,7 @@ def test_fused_advance_equals_separate_calls_bitwise(cfg, steps, sort_every, adv
     b.start(sort=True)
     b.prime()
     Eb = b.run_fused(steps, report_every=1, sort_every=sort_every)
-    assert b.uses_cells_advance() == (advance == "cells")
+    assert b.uses_scatter_advance() == (advance == "scatter")
     for x, y in zip(a.host_beads(), b.host_beads()):
         assert np.array_equal(x, y)
     for ea, eb in zip(Ea, Eb):
@@ -214,7 +214,7 @@ def test_c2_1000_step_mean_energies():
     assert not bad
 
 
-@pytest.mark.parametrize("advance", ["scatter", "plain", "cells"])
+@pytest.mark.parametrize("advance", ["scatter", "plain"])
 def test_empty_system_through_every_pass(advance):
     """N = 0: the sort, the fused passes, the finishing pass and the reductions run on an
     empty system (including inside a graph) and leave zero counts, zero energies and no flag."""

@@ -62,9 +62,11 @@ def test_no_kernel_uses_scratch_or_spills(tmp_path):
 
 def test_fused_pass_register_budget(tmp_path):
     """Each fused advance + deposit kernel keeps 4 waves per SIMD (at most 128 VGPRs of 512),
-    the software-pipelined ones included."""
+    the software-pipelined ones included; the variants with the Andersen thermostat (last
+    template argument true) keep at least 3 (at most 168 VGPRs)."""
     md = kernel_metadata(tmp_path)
     fused = {k: v for k, v in md.items() if "advance_scatter" in k}
-    assert len(fused) >= 8
+    assert len(fused) >= 16
     for k, v in fused.items():
-        assert v["vgpr_count"] <= 128, (k, v)
+        thermo = re.search(r"Lb([01])EEEv", k).group(1) == "1"
+        assert v["vgpr_count"] <= (168 if thermo else 128), (k, v)
