@@ -108,6 +108,8 @@ def _declare(_lib):
         _lib.or_run_interval.restype = C.c_int
         _lib.or_sort_perm.argtypes = [P, P, C.c_int64, C.POINTER(_Mesh), C.c_int32, P, P]
         _lib.or_sort_perm.restype = C.c_int
+        _lib.or_gather_staggered.argtypes = [P, P, C.c_int64, C.POINTER(_Mesh), C.c_int32, P, P, P]
+        _lib.or_gather_staggered.restype = C.c_int64
         _lib.or_philox4x32_10.argtypes = [P, P, P]
         _lib.or_andersen.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_float, C.c_uint64,
                                      C.c_int64, P]
@@ -349,3 +351,17 @@ def run_nvt(sys, n_steps, field_every, kT, p, seed, R=None, V=None, inv_mass=Non
     if rc:
         raise MemoryError("oracle allocation failed")
     return Rd, Vd, E
+
+
+def gather_staggered(R, T, L, M, Phi, A):
+    """O7P: the staggered nearest-vertex force (reading P of Algorithm 1 Kernels 3-4) of fields
+    Phi [K, Mz, My, Mx] with coefficients A [K, K]; returns F [N, 3]."""
+    m = mesh(L, M)
+    Rd = _pos(R)
+    Td = np.ascontiguousarray(T, dtype=np.uint8)
+    Pd = np.ascontiguousarray(Phi, dtype=np.float64)
+    K = Pd.shape[0]
+    Ad = np.ascontiguousarray(A, dtype=np.float64).reshape(K, K)
+    F = np.zeros((Rd.shape[0], 3))
+    lib().or_gather_staggered(_p(Rd), _p(Td), Rd.shape[0], C.byref(m), K, _p(Pd), _p(Ad), _p(F))
+    return F

@@ -27,6 +27,10 @@
  *   O7 gather           F_i = -sum_a (W_a / 2^3S) g_{T_i}(c_i + a): the field
  *                       force of eq. 6, interpolated with the same weights used
  *                       for the density (Algorithm 1 Kernel 4, reading).
+ *   O7P staggered       (or_gather_staggered) the paper-literal reading of
+ *                       Algorithm 1 Kernels 3-4: staggered backward and forward
+ *                       differences at the bead's nearest vertex, blended by the
+ *                       fraction ratios 1/2 -+ (u - n), no transverse weights.
  *   O8 bonds            U = k (r - r0)^2 (eq. 7, no factor 1/2); d = minimum
  *                       image of x_j - x_i; F_i += 2k (r - r0) d / r.
  *   O9 velocity Verlet  (Integration methods section) with unit mass by
@@ -221,6 +225,60 @@ int64_t or_gather(const double* R, const uint8_t* T, int64_t N, const or_mesh_t*
                         for (int d = 0; d < 3; ++d)
                             f[d] -= Wa * Gk[3 * v + d];
                     }
+        }
+        for (int d = 0; d < 3; ++d)
+            F[3 * i + d] = f[d];
+    }
+    return skipped;
+}
+
+/* O7P: nearest vertex and offset along one axis, from the O1-O2 quantities. */
+static void nearest_vertex(int32_t c, uint32_t q, int32_t M, int32_t* n, double* delta)
+{
+    const uint32_t half = OR_ONE / 2;
+    if (q < half) {
+        *n = c;
+        *delta = (double)q / (double)OR_ONE;
+    } else {
+        *n = (c + 1) % M;
+        *delta = ((double)q - (double)OR_ONE) / (double)OR_ONE;
+    }
+}
+
+int64_t or_gather_staggered(const double* R, const uint8_t* T, int64_t N, const or_mesh_t* m,
+                            int32_t K, const double* Phi, const double* A, double* F)
+{
+    const int64_t nm = (int64_t)m->M[0] * m->M[1] * m->M[2];
+    const double h[3] = {m->L[0] / m->M[0], m->L[1] / m->M[1], m->L[2] / m->M[2]};
+    int64_t skipped = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int32_t c[3];
+        uint32_t w[3][2];
+        double f[3] = {0.0, 0.0, 0.0};
+        if (T[i] >= K || bead_cell(R, i, m, c, w)) {
+            ++skipped;
+        } else {
+            int32_t n[3];
+            double delta[3];
+            for (int d = 0; d < 3; ++d)
+                nearest_vertex(c[d], w[d][1], m->M[d], &n[d], &delta[d]);
+            const int64_t v0 = vertex_index(m, n[0], n[1], n[2]);
+            for (int d = 0; d < 3; ++d) {
+                int32_t lo[3] = {n[0], n[1], n[2]}, hi[3] = {n[0], n[1], n[2]};
+                lo[d] = (n[d] + m->M[d] - 1) % m->M[d];
+                hi[d] = (n[d] + 1) % m->M[d];
+                const int64_t vlo = vertex_index(m, lo[0], lo[1], lo[2]);
+                const int64_t vhi = vertex_index(m, hi[0], hi[1], hi[2]);
+                const double xf1 = 0.5 - delta[d], xf2 = 0.5 + delta[d];
+                double sum = 0.0;
+                for (int kk = 0; kk < K; ++kk) {
+                    const double* P = Phi + kk * nm;
+                    const double g1 = P[v0] - P[vlo];       /* backward difference (Kernel 3) */
+                    const double g2 = P[vhi] - P[v0];       /* forward difference */
+                    sum += A[T[i] * K + kk] * (xf1 * g1 + xf2 * g2);
+                }
+                f[d] = -sum / h[d];
+            }
         }
         for (int d = 0; d < 3; ++d)
             F[3 * i + d] = f[d];

@@ -111,6 +111,21 @@ int or_run_interval(double* R, double* V, const uint8_t* T, const double* inv_ma
                     const or_params_t* p, double dt, int32_t n_steps, int32_t field_every,
                     double* energies);
 
+/* O7P staggered gather (reading P of Algorithm 1 Kernels 3-4): per axis d the
+ * bead's nearest vertex n_d (u_d = fl32(x_d s_d), quantised fraction q_d/2^S as
+ * in O2: n_d = c_d when q_d < 2^(S-1), else c_d + 1) and delta_d = u_d - n_d
+ * (quantised, in [-1/2, 1/2)); the backward and forward differences of each
+ * field Phi_K' at n along d (Kernel 3), blended with the fraction ratios
+ * 1/2 - delta_d and 1/2 + delta_d and summed with the coefficients
+ * A[T_i][K'] (Kernel 4):
+ *   F_i,d = -(1/h_d) sum_K' A[T_i][K'] ((1/2 - delta_d)(Phi_K'(n) - Phi_K'(n - e_d))
+ *                                     + (1/2 + delta_d)(Phi_K'(n + e_d) - Phi_K'(n))).
+ * With Phi = phi and A = kT chi + 1/kappa this is the paper's order; with Phi = V
+ * and A = identity it is the same force (eq. 6 is linear). Phi is [K][M^3];
+ * A is [K][K]. Returns the number of skipped beads (F = 0 for them). */
+int64_t or_gather_staggered(const double* R, const uint8_t* T, int64_t N, const or_mesh_t* m,
+                            int32_t K, const double* Phi, const double* A, double* F);
+
 /* O12 counter-based generator: Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
  * "Parallel random numbers: as easy as 1, 2, 3", SC'11): a 4 x 32-bit counter
  * and a 2 x 32-bit key give 4 x 32 random bits through ten rounds of two

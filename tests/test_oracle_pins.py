@@ -502,3 +502,78 @@ def test_run_nvt_holds_the_bath_temperature(oracle_mod):
         assert abs(ke - 1.5) <= tol * 1.5, (tol, ke)
     _, _, E0 = oracle_mod.run(base, 100)
     assert E0[50:, 0].mean() / base.N > 10.0
+
+
+# ---- O7P: the paper-literal staggered gather (reading P of Algorithm 1 Kernels 3-4)
+
+def _beads_away_from_seam(rng, n, L, M, margin=2.0):
+    h = L / M
+    R = np.zeros((n, 4), np.float32)
+    R[:, :3] = rng.uniform(margin * h, L - margin * h, (n, 3)).astype(np.float32)
+    return R
+
+
+def test_staggered_uniform_field_gives_no_force(oracle_mod):
+    rng = np.random.default_rng(1)
+    L, M = 16.0, 16
+    R = _beads_away_from_seam(rng, 500, L, M, margin=0.0)
+    T = rng.integers(0, 2, 500).astype(np.uint8)
+    Phi = np.full((2, M, M, M), 0.731)
+    A = np.array([[0.3, 1.7], [1.7, -0.4]])
+    F = oracle_mod.gather_staggered(R, T, L, M, Phi, A)
+    assert np.array_equal(F, np.zeros_like(F))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_staggered_quadratic_potential_gives_exact_linear_force(oracle_mod, axis):
+    """V = x_d^2 at the vertices: the blend of the backward and forward differences at the
+    nearest vertex, weighted 1/2 - delta and 1/2 + delta, is exactly -dV/dx_d = -2 x_d at the
+    (quantised) bead position, for beads whose stencil avoids the periodic seam; the other
+    components vanish. Swapped or shifted fraction ratios would not be exact."""
+    rng = np.random.default_rng(2 + axis)
+    L, M = 16.0, 16                      # h = 1: vertex coordinates are exact
+    R = _beads_away_from_seam(rng, 400, L, M)
+    T = np.zeros(400, np.uint8)
+    x = np.arange(M, dtype=np.float64)
+    shape = [1, 1, 1]
+    shape[2 - axis] = M
+    Phi = np.broadcast_to((x ** 2).reshape(shape), (M, M, M))[None].copy()
+    F = oracle_mod.gather_staggered(R, T, L, M, Phi, np.eye(1))
+    u = R[:, axis].astype(np.float64)
+    q = np.floor((u - np.floor(u)) * 65536.0)
+    xq = np.floor(u) + q / 65536.0           # the position the weights see
+    np.testing.assert_array_equal(F[:, axis], -2.0 * xq)
+    others = [d for d in range(3) if d != axis]
+    assert not F[:, others].any()
+
+
+def test_staggered_linear_potential_exact_and_midpoint_continuity(oracle_mod):
+    """V = a x (a = 0.25, h = 0.5): F = -a exactly; a bead exactly half-way between two
+    vertices takes the forward difference at the lower vertex, the same value as the backward
+    difference at the upper one."""
+    L, M, a = 8.0, 16, 0.25
+    h = L / M
+    x = np.arange(M) * h
+    Phi = np.broadcast_to((a * x).reshape(1, 1, M), (M, M, M))[None].copy()
+    R = np.array([[3.0 + 0.5 * h, 4.0, 4.0, 0.0], [3.1, 3.7, 4.9, 0.0]], np.float32)
+    F = oracle_mod.gather_staggered(R, np.zeros(2, np.uint8), L, M, Phi, np.eye(1))
+    np.testing.assert_array_equal(F[:, 0], [-a, -a])
+    assert not F[:, 1:].any()
+
+
+def test_staggered_paper_order_equals_potential_first(oracle_mod):
+    """Kernel 4's order (differences of phi per species, then kT chi + 1/kappa) equals the
+    differences of V with unit coefficients, to rounding (eq. 6 is linear)."""
+    s = wl.small_system(300, 10, 11.0, 11, K=3, n_solvent=2000, seed=31)
+    counts, _ = oracle_mod.density(s.R, s.T, s.L, s.M, s.K)
+    V, _ = oracle_mod.potential(counts, s.L, s.M, s.N, s.kT, s.inv_kappa, s.chi)
+    vol = float(np.prod(np.asarray(s.L, dtype=np.float32).astype(np.float64)))
+    nm = int(np.prod(s.M))
+    phi = counts.astype(np.float64) / (2.0 ** 48 * (s.N / vol) * (vol / nm))
+    A = s.kT * np.asarray(s.chi) + s.inv_kappa
+    Fp = oracle_mod.gather_staggered(s.R, s.T, s.L, s.M, phi, A)
+    Fv = oracle_mod.gather_staggered(s.R, s.T, s.L, s.M, V, np.eye(s.K))
+    assert np.abs(Fp - Fv).max() <= 1e-12 * np.abs(Fv).max()
+    # each bead feels only its own species' row of A
+    Fr = oracle_mod.gather_staggered(s.R, s.T, s.L, s.M, V, np.diag([1.0, 0.0, 0.0]))
+    assert not Fr[s.T != 0].any() and np.array_equal(Fr[s.T == 0], Fv[s.T == 0])
