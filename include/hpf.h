@@ -229,6 +229,28 @@ hpf_status_t hpf_force_gather(const float* R, const uint8_t* T, int64_t N,
                               void* stream);
 
 /* ---------------------------------------------------------------------------
+ * hpf_force_gather_staggered -- the field force of eq. (6) read literally from
+ * Algorithm 1: Kernel 3's staggered backward and forward differences, taken at
+ * the bead's nearest mesh point and blended with Kernel 4's fraction ratios.
+ * Per axis d, with u_d, c_d and q_d as in hpf_density_scatter: the nearest point
+ * is n_d = c_d when q_d < 2^15, else c_d + 1 (periodic), delta_d = (q_d or
+ * q_d - 2^16) / 2^16 in [-1/2, 1/2), and
+ *   F_i,d = -s_d [ (1/2 - delta_d)(V_T(n) - V_T(n - e_d))
+ *                + (1/2 + delta_d)(V_T(n + e_d) - V_T(n)) ],   T = T_i,
+ * the sum over species of Kernel 4 being contained in V (the equation is
+ * linear). No transverse interpolation; unlike hpf_force_gather this is not
+ * the transpose of the density assignment, so it does not conserve momentum
+ * exactly. It needs no gradient mesh.
+ *
+ * R float[N][4], T uint8[N], V float[K][M^3] device (hpf_field_potential).
+ * F float[N][4] device, OVERWRITTEN (w = 0). Skipped beads (see
+ * hpf_density_scatter) get F = 0.
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_force_gather_staggered(const float* R, const uint8_t* T, int64_t N,
+                                        const hpf_mesh_t* mesh, int32_t K, const float* V,
+                                        float* F, void* stream);
+
+/* ---------------------------------------------------------------------------
  * bond_forces -- harmonic bonds U = k (r - r0)^2 (eq. (7), no factor 1/2),
  * one thread per bead summing over its own bonds, so each bond is evaluated
  * from both ends (Bonded forces section). With d = minimum image of

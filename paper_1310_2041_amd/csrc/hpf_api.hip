@@ -262,6 +262,16 @@ hpf_status_t hpf_force_gather(const float* R, const uint8_t* T, int64_t N, const
     return launch_force_gather(R, T, N, mesh_k(mesh), K, G, F, as_stream(stream));
 }
 
+hpf_status_t hpf_force_gather_staggered(const float* R, const uint8_t* T, int64_t N, const hpf_mesh_t* mesh,
+                                        int32_t K, const float* V, float* F, void* stream)
+{
+    if (N < 0 || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES || !V)
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !T || !F))
+        return HPF_EINVAL;
+    return launch_force_gather_staggered(R, T, N, mesh_k(mesh), K, V, F, as_stream(stream));
+}
+
 hpf_status_t bond_forces(const float* R, int64_t N, const int32_t* bonds, int32_t D, float k, float r0,
                          const float* box, float* F, double* e_part, void* stream)
 {

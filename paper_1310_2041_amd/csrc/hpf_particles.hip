@@ -139,6 +139,51 @@ __device__ __forceinline__ bool field_force(const float4& r, int t, const MeshK&
     return true;
 }
 
+// Field force on one bead read paper-literally from Algorithm 1 Kernels 3-4:
+// along each axis the nearest vertex n (the cell's lower vertex when the
+// quantised fraction is below one half, else the upper one) and the offset
+// delta = u - n in [-1/2, 1/2); the backward difference V(n) - V(n - e) and the
+// forward difference V(n + e) - V(n) are blended with the fraction ratios
+// 1/2 - delta and 1/2 + delta (exact FP32 dyadics) and scaled by 1/h = s. V is
+// the potential of the bead's own species, so the chi sum of Kernel 4 is
+// already in it (eq. 6 is linear). False (and zero force) for a bead that
+// cannot be binned or has a type >= K.
+__device__ __forceinline__ bool field_force_staggered(const float4& r, int t, const MeshK& m, int K,
+                                                      const float* __restrict__ V, float3& f)
+{
+    BeadCell b;
+    f = make_float3(0.0f, 0.0f, 0.0f);
+    if (!(bead_cell(r, m, b) && t < K))
+        return false;
+    const float* Vk = V + t * m.nm;
+    int32_t n[3];
+    float xf1[3], xf2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int32_t half = (int32_t)(kOne / 2);
+        int32_t dq = (int32_t)b.q[d];
+        n[d] = b.c[d];
+        if (dq >= half) {
+            n[d] = next_wrap(b.c[d], m.M[d]);
+            dq -= (int32_t)kOne;
+        }
+        xf1[d] = (float)(half - dq) * kInvOne;
+        xf2[d] = (float)(half + dq) * kInvOne;
+    }
+    const int32_t Mx = m.M[0], My = m.M[1], Mz = m.M[2];
+    const int64_t row = ((int64_t)n[2] * My + n[1]) * Mx;
+    const float v0 = Vk[row + n[0]];
+    const float vxm = Vk[row + prev_wrap(n[0], Mx)], vxp = Vk[row + next_wrap(n[0], Mx)];
+    const float vym = Vk[((int64_t)n[2] * My + prev_wrap(n[1], My)) * Mx + n[0]];
+    const float vyp = Vk[((int64_t)n[2] * My + next_wrap(n[1], My)) * Mx + n[0]];
+    const float vzm = Vk[((int64_t)prev_wrap(n[2], Mz) * My + n[1]) * Mx + n[0]];
+    const float vzp = Vk[((int64_t)next_wrap(n[2], Mz) * My + n[1]) * Mx + n[0]];
+    f.x = -(xf1[0] * (v0 - vxm) + xf2[0] * (vxp - v0)) * m.s[0];
+    f.y = -(xf1[1] * (v0 - vym) + xf2[1] * (vyp - v0)) * m.s[1];
+    f.z = -(xf1[2] * (v0 - vzm) + xf2[2] * (vzp - v0)) * m.s[2];
+    return true;
+}
+
 // Sum of the harmonic bond forces on bead i over its table row, and its
 // bond energy k (r - r0)^2 summed over its bonds (FP32).
 template <bool kR0Zero>
@@ -244,6 +289,22 @@ __global__ __launch_bounds__(kPThreads) void k_force_gather(const float4* __rest
     FOR_BEADS(w, i) {
         float3 f;
         bad |= !field_force(R[i], T[i], m, K, G, f);
+        F[i] = make_float4(f.x, f.y, f.z, 0.0f);
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BEAD);
+}
+
+__global__ __launch_bounds__(kPThreads) void k_force_gather_staggered(const float4* __restrict__ R,
+                                                                      const uint8_t* __restrict__ T, int64_t N,
+                                                                      MeshK m, int K, const float* __restrict__ V,
+                                                                      float4* __restrict__ F)
+{
+    const BeadWalk w = bead_walk(N);
+    bool bad = false;
+    FOR_BEADS(w, i) {
+        float3 f;
+        bad |= !field_force_staggered(R[i], T[i], m, K, V, f);
         F[i] = make_float4(f.x, f.y, f.z, 0.0f);
     }
     if (bad)
@@ -717,6 +778,16 @@ hpf_status_t launch_force_gather(const float* R, const uint8_t* T, int64_t N, co
     hipLaunchKernelGGL(k_force_gather, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads),
                        0, s, reinterpret_cast<const float4*>(R), T, N, m, K,
                        reinterpret_cast<const float4*>(G), reinterpret_cast<float4*>(F));
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+hpf_status_t launch_force_gather_staggered(const float* R, const uint8_t* T, int64_t N, const MeshK& m, int K,
+                                           const float* V, float* F, hipStream_t s)
+{
+    if (N == 0)
+        return HPF_OK;
+    hipLaunchKernelGGL(k_force_gather_staggered, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads), 0, s,
+                       reinterpret_cast<const float4*>(R), T, N, m, K, V, reinterpret_cast<float4*>(F));
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 

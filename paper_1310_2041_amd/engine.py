@@ -29,7 +29,7 @@ class HpfState:
 
     def __init__(self, R, Vel, T, tag, bonds, L, M, K, kT, inv_kappa, chi, k_bond, r0, dt,
                  device="cuda", sort_brick=8, halo=1, advance="scatter",
-                 field_every=1):
+                 field_every=1, stencil="centred"):
         dev = torch.device(device)
         self.N = int(R.shape[0])
         self.K = int(K)
@@ -46,6 +46,14 @@ class HpfState:
         # deposits x_n+1, so the next step only finishes the density), "plain" = hpf_advance.
         # Unsorted beads always take hpf_advance.
         self.advance_mode = advance
+        # Force interpolation (Algorithm 1 Kernels 3-4): "centred" = centred differences at the
+        # mesh points gathered with the deposit's weights (hpf_field_gradient +
+        # hpf_force_gather, and the fused passes); "staggered" = the paper-literal backward /
+        # forward differences at the nearest mesh point (hpf_force_gather_staggered; the
+        # six-call step only).
+        if stencil not in ("centred", "staggered"):
+            raise ValueError("stencil must be 'centred' or 'staggered'")
+        self.stencil = stencil
         # Field-update interval (MD-SCF section): the density field (counts, V, G) is rebuilt
         # at force evaluations whose index is a multiple of field_every (evaluation 0 is
         # start(), evaluation s comes after step s); the others gather from the last G, and
@@ -173,8 +181,12 @@ class HpfState:
             hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V,
                                     self.part[ROW_W] if (report or self.field_every > 1) else None,
                                     stream)
-            hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
-        hpf.hpf_force_gather(self.R, self.T, self.mesh, self.K, self.G, self.F, stream)
+            if self.stencil == "centred":
+                hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
+        if self.stencil == "staggered":
+            hpf.hpf_force_gather_staggered(self.R, self.T, self.mesh, self.K, self.V, self.F, stream)
+        else:
+            hpf.hpf_force_gather(self.R, self.T, self.mesh, self.K, self.G, self.F, stream)
 
     def bond_forces(self, report=False, stream=None):
         hpf.bond_forces(self.R, self.bonds if self.bonds.shape[0] else None, self.k_bond, self.r0,
@@ -228,8 +240,11 @@ class HpfState:
 
     def step_fused(self, report=False, sort=False, stream=None):
         """(x_n, v_n-1/2) -> (x_n+1, v_n+1/2) with hpf_advance; energies of step n.
+        The fused passes interpolate with the centred stencil only.
 
         Bitwise equal to step() followed by the next step's first half step."""
+        if self.stencil != "centred":
+            raise ValueError("the fused passes use the centred stencil; step() runs the staggered one")
         if sort:
             self.sort(stream)
         # this step's force evaluation is number steps_done + 1 (start() was number 0)

@@ -106,6 +106,8 @@ _SIGNATURES = {
     "hpf_field_potential": ([_P, C.POINTER(Mesh), C.POINTER(Field), _P, _P, _P], C.c_int32),
     "hpf_field_gradient": ([_P, C.POINTER(Mesh), C.c_int32, _P, _P], C.c_int32),
     "hpf_force_gather": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, _P], C.c_int32),
+    "hpf_force_gather_staggered": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, _P],
+                                   C.c_int32),
     "bond_forces": ([_P, C.c_int64, _P, C.c_int32, C.c_float, C.c_float, _P, _P, _P, _P],
                     C.c_int32),
     "verlet_step": ([_P, _P, _P, _P, C.c_int64, C.c_float, _P, C.c_int32, _P, _P], C.c_int32),
@@ -285,6 +287,14 @@ def hpf_force_gather(R, T, mesh: Mesh, K: int, G, F, stream=None):
     f = _dev(F, "F", torch.float32, (N, 4))
     _check("hpf_force_gather",
            lib().hpf_force_gather(r, t, N, C.byref(mesh), K, g, f, _stream(stream)))
+
+
+def hpf_force_gather_staggered(R, T, mesh: Mesh, K: int, V, F, stream=None):
+    N = R.shape[0]
+    _check("hpf_force_gather_staggered", lib().hpf_force_gather_staggered(
+        _dev(R, "R", torch.float32, (N, 4)), _dev(T, "T", torch.uint8, (N,)), N, C.byref(mesh), int(K),
+        _dev(V, "V", torch.float32, (K, _nm(mesh))), _dev(F, "F", torch.float32, (N, 4)),
+        _stream(stream)))
 
 
 def bond_forces(R, bonds, k: float, r0: float, box, F, e_part=None, stream=None):
