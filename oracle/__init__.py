@@ -110,6 +110,7 @@ def _declare(_lib):
         _lib.or_sort_perm.restype = C.c_int
         _lib.or_gather_staggered.argtypes = [P, P, C.c_int64, C.POINTER(_Mesh), C.c_int32, P, P, P]
         _lib.or_gather_staggered.restype = C.c_int64
+        _lib.or_angles.argtypes = [P, C.c_int64, P, C.c_int32, C.c_int32, P, P, P, P, P, P]
         _lib.or_philox4x32_10.argtypes = [P, P, P]
         _lib.or_andersen.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_float, C.c_uint64,
                                      C.c_int64, P]
@@ -365,3 +366,21 @@ def gather_staggered(R, T, L, M, Phi, A):
     F = np.zeros((Rd.shape[0], 3))
     lib().or_gather_staggered(_p(Rd), _p(Td), Rd.shape[0], C.byref(m), K, _p(Pd), _p(Ad), _p(F))
     return F
+
+
+def angles(R, angle_table, k, theta0, form, L):
+    """O8A: angle forces F [N, 3] and energy of a per-bead angle table [3A, N] (rows partner,
+    partner, role + 2 type per slot); k, theta0, form are scalars (one type) or per-type
+    sequences; form 0 = k (theta - theta0)^2, 1 = k (cos theta - cos theta0)^2."""
+    Rd = _pos(R)
+    N = Rd.shape[0]
+    tab = np.ascontiguousarray(angle_table, dtype=np.int32)
+    A = tab.shape[0] // 3 if tab.size else 0
+    kk = np.atleast_1d(np.asarray(k, dtype=np.float64)).copy()
+    th = np.broadcast_to(np.asarray(theta0, dtype=np.float64), kk.shape).copy()
+    fm = np.broadcast_to(np.asarray(form, dtype=np.int32), kk.shape).copy()
+    F = np.zeros((N, 3))
+    E = C.c_double(0.0)
+    lib().or_angles(_p(Rd), N, _p(tab) if A else None, A, kk.size, _p(kk), _p(th), _p(fm),
+                    _p(_box(L)), _p(F), C.byref(E))
+    return F, E.value

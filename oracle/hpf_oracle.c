@@ -33,6 +33,10 @@
  *                       fraction ratios 1/2 -+ (u - n), no transverse weights.
  *   O8 bonds            U = k (r - r0)^2 (eq. 7, no factor 1/2); d = minimum
  *                       image of x_j - x_i; F_i += 2k (r - r0) d / r.
+ *   O8A angles          (or_angles) the two angle forms of the Bonded forces
+ *                       section, k (theta - theta0)^2 and k (cos theta -
+ *                       cos theta0)^2, theta at the middle bead; stored and
+ *                       evaluated per bead like the bonds (three times per angle).
  *   O9 velocity Verlet  (Integration methods section) with unit mass by
  *                       default and wrapping into the periodic box.
  *   O10 energies        KE = sum m v^2 / 2; E_bond = sum over bonds of U;
@@ -315,6 +319,80 @@ void or_bonds(const double* R, int64_t N, const int32_t* bonds, int32_t D, doubl
     }
     if (E)
         *E = 0.5 * e;                                     /* each bond seen twice */
+}
+
+/* O8A: minimum-image vector x_j - x_i. */
+static void min_image_vec(const double* R, int64_t i, int64_t j, const double L[3], double d[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        d[a] = R[3 * j + a] - R[3 * i + a];
+        d[a] -= L[a] * nearbyint(d[a] / L[a]);
+    }
+}
+
+/* O8A: energy and dU/dcos(theta) of one triplet from its two arm vectors. */
+static void angle_terms(const double a[3], const double b[3], double k, double theta0, int32_t form,
+                        double* U, double* dUdc, double* c_out, double* la, double* lb)
+{
+    const double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    const double nb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    const double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    const double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2], cz = a[0] * b[1] - a[1] * b[0];
+    const double cr = sqrt(cx * cx + cy * cy + cz * cz);
+    const double c = dot / (na * nb);
+    const double theta = atan2(cr, dot);
+    if (form == 0) {
+        double st = cr / (na * nb);
+        if (st < 1e-3)
+            st = 1e-3;
+        *U = k * (theta - theta0) * (theta - theta0);
+        *dUdc = -2.0 * k * (theta - theta0) / st;
+    } else {
+        const double c0 = cos(theta0);
+        *U = k * (c - c0) * (c - c0);
+        *dUdc = 2.0 * k * (c - c0);
+    }
+    *c_out = c;
+    *la = na;
+    *lb = nb;
+}
+
+void or_angles(const double* R, int64_t N, const int32_t* angles, int32_t A, int32_t ntypes,
+               const double* k, const double* theta0, const int32_t* form, const double L[3], double* F,
+               double* E)
+{
+    double e = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        for (int32_t r = 0; r < A; ++r) {
+            const int32_t p = angles[(3 * (int64_t)r + 0) * N + i];
+            const int32_t q = angles[(3 * (int64_t)r + 1) * N + i];
+            const int32_t code = angles[(3 * (int64_t)r + 2) * N + i];
+            const int32_t role = code & 1, type = code >> 1;
+            if (p < 0 || type >= ntypes)
+                continue;
+            /* the triplet (end1, middle, end2) and which member this bead is */
+            const int64_t mid = role == 1 ? i : p;
+            const int64_t e1 = role == 1 ? p : i;
+            const int64_t e2 = q;
+            double a[3], b[3], U, dUdc, c, la, lb;
+            min_image_vec(R, mid, e1, L, a);
+            min_image_vec(R, mid, e2, L, b);
+            angle_terms(a, b, k[type], theta0[type], form[type], &U, &dUdc, &c, &la, &lb);
+            /* dc/dx_e1 = (b^ - c a^) / |a|, dc/dx_e2 = (a^ - c b^) / |b|, dc/dx_mid = -(sum) */
+            double g1[3], g2[3];
+            for (int d = 0; d < 3; ++d) {
+                g1[d] = (b[d] / lb - c * a[d] / la) / la;
+                g2[d] = (a[d] / la - c * b[d] / lb) / lb;
+            }
+            for (int d = 0; d < 3; ++d) {
+                const double g = role == 1 ? -(g1[d] + g2[d]) : g1[d];
+                F[3 * i + d] -= dUdc * g;
+            }
+            e += U;
+        }
+    }
+    if (E)
+        *E = e / 3.0;                                     /* each angle seen three times */
 }
 
 static double wrap_coord(double x, double L)

@@ -73,6 +73,26 @@ int64_t or_gather(const double* R, const uint8_t* T, int64_t N, const or_mesh_t*
 void or_bonds(const double* R, int64_t N, const int32_t* bonds, int32_t D, double k,
               double r0, const double L[3], double* F, double* E);
 
+/* O8A angles (Bonded forces section): the angle theta at the middle bead j of
+ * a triplet (i, j, k) between the minimum-image vectors a = x_i - x_j and
+ * b = x_k - x_j, cos(theta) = a.b / (|a| |b|), theta = atan2(|a x b|, a.b).
+ *   form 0 (harmonic):  U = k (theta - theta0)^2
+ *   form 1 (cosine):    U = k (cos(theta) - cos(theta0))^2
+ * Stored as the bonds are, per bead: angles[(3a + 0) N + i] and
+ * angles[(3a + 1) N + i] are the other two members of the bead's a-th angle and
+ * code = angles[(3a + 2) N + i] = role + 2 type: role 1 if the bead is the
+ * middle, 0 if it is an end (the first partner then being the middle); type
+ * selects k[type], theta0[type], form[type] (type < ntypes). A first partner
+ * < 0 means no angle.
+ * Each angle is evaluated from each of its three members, every member taking
+ * its own force -dU/dx; *E (if non-NULL) receives the angle energy, each angle
+ * counted once. For the harmonic form dU/dcos = -2k (theta - theta0) / sin(theta),
+ * with sin(theta) floored at 1e-3 (reading: the force of an exactly straight
+ * triplet is otherwise undefined). F[N][3] is accumulated. */
+void or_angles(const double* R, int64_t N, const int32_t* angles, int32_t A, int32_t ntypes,
+               const double* k, const double* theta0, const int32_t* form, const double L[3], double* F,
+               double* E);
+
 /* O9: first half of velocity Verlet: v += dt/2 F/m; x += dt v; wrap to [0, L). */
 void or_verlet_half1(double* R, double* V, const double* F, const double* inv_mass,
                      int64_t N, double dt, const double L[3]);

@@ -577,3 +577,114 @@ def test_staggered_paper_order_equals_potential_first(oracle_mod):
     # each bead feels only its own species' row of A
     Fr = oracle_mod.gather_staggered(s.R, s.T, s.L, s.M, V, np.diag([1.0, 0.0, 0.0]))
     assert not Fr[s.T != 0].any() and np.array_equal(Fr[s.T == 0], Fv[s.T == 0])
+
+
+# ---- O8A: angle potentials (Bonded forces section)
+
+def _angle_table_for(triplets, N):
+    """Per-bead angle table [3A, N] (partner, partner, role) of a list of (end, middle, end)."""
+    rows = {}
+    for (i, j, k) in triplets:
+        for bead, entry in ((i, (j, k, 0)), (j, (i, k, 1)), (k, (j, i, 0))):
+            rows.setdefault(bead, []).append(entry)
+    A = max((len(v) for v in rows.values()), default=0)
+    tab = np.full((3 * A, N), -1, np.int32)
+    for bead, entries in rows.items():
+        for a, (p, q, role) in enumerate(entries):
+            tab[3 * a, bead], tab[3 * a + 1, bead], tab[3 * a + 2, bead] = p, q, role
+    tab[2::3][tab[0::3] < 0] = 0
+    return tab
+
+
+def test_angle_right_triplet_by_hand(oracle_mod):
+    """Ends at (1,0,0) and (0,1,0), middle at the origin: theta = pi/2. Cosine form with
+    theta0 = 2 pi / 3 (cos theta0 = -1/2), k = 3: U = 3 (0 + 1/2)^2 = 3/4; dU/dcos = 3, and
+    d cos/d x_end1 = (0,1,0), d cos/d x_end2 = (1,0,0), so F_end1 = (0,-3,0),
+    F_end2 = (-3,0,0), F_mid = (3,3,0): the ends are pushed apart, opening the angle.
+    Harmonic form with theta0 = pi/3: U = k (pi/6)^2, dU/dtheta = k pi / 3 and
+    |d theta / d x_end| = 1 / |a| = 1, so F_end1 = (0, k pi/3, 0) closes the angle."""
+    L = (10.0, 10.0, 10.0)
+    R = np.array([[6.0, 5.0, 5.0], [5.0, 5.0, 5.0], [5.0, 6.0, 5.0]])
+    tab = _angle_table_for([(0, 1, 2)], 3)
+    F, E = oracle_mod.angles(R, tab, 3.0, 2.0 * np.pi / 3.0, 1, L)
+    np.testing.assert_allclose(F, [[0.0, -3.0, 0.0], [3.0, 3.0, 0.0], [-3.0, 0.0, 0.0]], atol=1e-14)
+    assert E == pytest.approx(0.75, rel=1e-14)
+    k = 2.0
+    F, E = oracle_mod.angles(R, tab, k, np.pi / 3.0, 0, L)
+    np.testing.assert_allclose(F[0], [0.0, k * np.pi / 3.0, 0.0], atol=1e-13)
+    np.testing.assert_allclose(F[2], [k * np.pi / 3.0, 0.0, 0.0], atol=1e-13)
+    assert E == pytest.approx(k * (np.pi / 6.0) ** 2, rel=1e-14)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_angle_forces_are_minus_the_energy_gradient(oracle_mod, form):
+    """Random bent chains across the periodic seam: every force component equals the central
+    finite difference of the angle energy, and the forces sum to zero."""
+    rng = np.random.default_rng(7 + form)
+    L = (6.0, 7.0, 5.5)
+    n_chain, length = 12, 6
+    R = []
+    for c in range(n_chain):
+        x = rng.uniform(0, 1, 3) * np.asarray(L)
+        for b in range(length):
+            R.append(x.copy())
+            x = x + rng.normal(0, 0.6, 3)
+    R = np.mod(np.asarray(R), np.asarray(L))
+    N = len(R)
+    trip = [(c * length + b, c * length + b + 1, c * length + b + 2)
+            for c in range(n_chain) for b in range(length - 2)]
+    tab = _angle_table_for(trip, N)
+    k, th0 = 4.0, 1.9
+    F, E = oracle_mod.angles(R, tab, k, th0, form, L)
+    eps = 1e-6
+    Fd = np.zeros_like(F)
+    for i in range(N):
+        for d in range(3):
+            Rp, Rm = R.copy(), R.copy()
+            Rp[i, d] += eps
+            Rm[i, d] -= eps
+            Fd[i, d] = -(oracle_mod.angles(Rp, tab, k, th0, form, L)[1] -
+                         oracle_mod.angles(Rm, tab, k, th0, form, L)[1]) / (2 * eps)
+    assert np.abs(F - Fd).max() <= 1e-6 * np.abs(F).max()
+    assert np.abs(F.sum(0)).max() <= 1e-10 * np.abs(F).max()
+    # the energy is that of each angle once, whichever member evaluates it
+    th = []
+    for (i, j, kk) in trip:
+        a = R[i] - R[j]
+        b = R[kk] - R[j]
+        a -= np.asarray(L) * np.rint(a / np.asarray(L))
+        b -= np.asarray(L) * np.rint(b / np.asarray(L))
+        th.append(np.arccos(np.dot(a, b) / np.linalg.norm(a) / np.linalg.norm(b)))
+    th = np.asarray(th)
+    want = (k * (th - th0) ** 2).sum() if form == 0 else (k * (np.cos(th) - np.cos(th0)) ** 2).sum()
+    assert E == pytest.approx(want, rel=1e-9)
+
+
+def test_angle_energy_invariant_under_rotation(oracle_mod):
+    rng = np.random.default_rng(3)
+    R = rng.uniform(20, 30, (3, 3))
+    L = (100.0, 100.0, 100.0)
+    tab = _angle_table_for([(0, 1, 2)], 3)
+    q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    R2 = (R - 25.0) @ q.T + 50.0
+    for form in (0, 1):
+        F1, E1 = oracle_mod.angles(R, tab, 1.5, 2.0, form, L)
+        F2, E2 = oracle_mod.angles(R2, tab, 1.5, 2.0, form, L)
+        assert E2 == pytest.approx(E1, rel=1e-12)
+        np.testing.assert_allclose(F2, F1 @ q.T, atol=1e-12 * np.abs(F1).max())
+
+
+def test_angle_types_select_their_parameters(oracle_mod):
+    """A table holding a harmonic triplet (type 0) and a cosine triplet (type 1) gives the sum
+    of the two evaluated alone with their own parameters."""
+    rng = np.random.default_rng(9)
+    L = (20.0, 20.0, 20.0)
+    R = rng.uniform(5, 8, (6, 3))
+    both = _angle_table_for([(0, 1, 2), (3, 4, 5)], 6)
+    both[2::3][both[0::3] >= 0] += 2 * (np.arange(6) >= 3)[None, :].repeat(both.shape[0] // 3, 0)[
+        both[0::3] >= 0]
+    Fa, Ea = oracle_mod.angles(R, _angle_table_for([(0, 1, 2)], 6), 2.0, 1.1, 0, L)
+    Fb, Eb = oracle_mod.angles(R, _angle_table_for([(3, 4, 5)], 6), 5.0, 2.9, 1, L)
+    F, E = oracle_mod.angles(R, both, [2.0, 5.0], [1.1, 2.9], [0, 1], L)
+    np.testing.assert_allclose(F, Fa + Fb, rtol=0, atol=1e-14 * np.abs(F).max())
+    assert E == pytest.approx(Ea + Eb, rel=1e-14)
