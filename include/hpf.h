@@ -48,6 +48,8 @@ extern "C" {
 #define HPF_MAX_TYPES 8     /* K <= 8 species */
 #define HPF_NPART 4096      /* slots per component of an FP64 partial-sum buffer */
 #define HPF_MAX_BONDS 16    /* D <= 16 bond-table rows */
+#define HPF_MAX_ANGLES 16   /* A <= 16 angle slots per bead */
+#define HPF_MAX_ANGLE_TYPES 8
 
 typedef int32_t hpf_status_t;
 #define HPF_OK 0
@@ -271,6 +273,30 @@ hpf_status_t bond_forces(const float* R, int64_t N, const int32_t* bonds, int32_
                          void* stream);
 
 /* ---------------------------------------------------------------------------
+ * angle_forces -- the angle potentials of the Bonded forces section,
+ *   form 0:  U = k (theta - theta0)^2        form 1:  U = k (cos theta - cos theta0)^2
+ * with theta the angle at the middle bead j of a triplet (i, j, k) between the
+ * minimum-image vectors x_i - x_j and x_k - x_j. Stored like the bonds, per bead
+ * (the paper keeps angles in the bond-table form, marking whether the bead is
+ * the middle or an end, and evaluates each angle three times, once per member):
+ *   angles[(3a + 0) N + i], angles[(3a + 1) N + i]  the other two members of bead
+ *       i's a-th angle (-1 in the first = no angle);
+ *   angles[(3a + 2) N + i] = role + 2 type: role 1 if bead i is the middle (the
+ *       partners are the ends), 0 if it is an end (the first partner is then the
+ *       middle, the second the other end); type < ntypes selects the parameters.
+ * A in [0, HPF_MAX_ANGLES]; ntypes in [1, HPF_MAX_ANGLE_TYPES]; k, theta0 (radians)
+ * and form (0 or 1) are HOST arrays of ntypes entries. For the harmonic form
+ * dU/dcos = -2k (theta - theta0) / sin(theta), sin(theta) floored at 1e-3 (the
+ * direction of the force of an exactly straight triplet is undefined).
+ * F float[N][4] device, ACCUMULATED into. e_part nullable double[HPF_NPART]:
+ * partial sums of the angle energy, each angle once. Entries outside [-1, N) or
+ * with a type >= ntypes are skipped and set HPF_FLAG_BAD_BOND.
+ * ------------------------------------------------------------------------- */
+hpf_status_t angle_forces(const float* R, int64_t N, const int32_t* angles, int32_t A, int32_t ntypes,
+                          const float* k, const float* theta0, const int32_t* form, const float* box,
+                          float* F, double* e_part, void* stream);
+
+/* ---------------------------------------------------------------------------
  * verlet_step -- velocity Verlet (Integration methods section), split into
  * its two half steps around the force evaluation:
  *   half = 1:  v += dt/2 F/m;  x += dt v;  x wrapped into [0, L)
@@ -422,6 +448,16 @@ hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N,
                               float* R_out, float* Vel_out, uint8_t* T_out, int32_t* tag_out,
                               int32_t* bonds_out, uint32_t* cell_start, void* work,
                               size_t work_bytes, void* stream);
+
+/* hpf_sort_angles -- the per-bead angle table (angle_forces layout, int32[3A][N])
+ * in the order of the hpf_sort_by_cell call that last used `work` (same mesh, B
+ * and N, and `work` untouched since): rows are permuted with their beads, the
+ * partner rows renumbered to the new storage indices, the code rows kept.
+ * angles_out must not alias angles_in. Partners outside [-1, N) become -1 and
+ * set HPF_FLAG_BAD_BOND. */
+hpf_status_t hpf_sort_angles(const hpf_mesh_t* mesh, int32_t B, int64_t N, const int32_t* angles_in,
+                             int32_t A, int32_t* angles_out, const void* work, size_t work_bytes,
+                             void* stream);
 
 /* ===========================================================================
  * Batched replicas (a phase-diagram sweep): many independent systems of

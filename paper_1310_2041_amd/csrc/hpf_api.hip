@@ -288,6 +288,33 @@ hpf_status_t bond_forces(const float* R, int64_t N, const int32_t* bonds, int32_
     return launch_bond_forces(R, N, bonds, D, k, r0, b, F, e_part, as_stream(stream));
 }
 
+hpf_status_t angle_forces(const float* R, int64_t N, const int32_t* angles, int32_t A, int32_t ntypes,
+                          const float* k, const float* theta0, const int32_t* form, const float* box, float* F,
+                          double* e_part, void* stream)
+{
+    if (N < 0 || A < 0 || A > HPF_MAX_ANGLES || ntypes < 1 || ntypes > HPF_MAX_ANGLE_TYPES || !k || !theta0 ||
+        !form || !box_ok(box))
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !F || (A > 0 && !angles)))
+        return HPF_EINVAL;
+    AngleK ak{};
+    ak.ntypes = ntypes;
+    for (int t = 0; t < ntypes; ++t) {
+        if (!std::isfinite(k[t]) || !std::isfinite(theta0[t]) || (form[t] != 0 && form[t] != 1))
+            return HPF_EINVAL;
+        ak.k[t] = k[t];
+        ak.theta0[t] = theta0[t];
+        ak.cos0[t] = (float)std::cos((double)theta0[t]);
+        ak.form[t] = form[t];
+    }
+    BoxK b;
+    for (int d = 0; d < 3; ++d) {
+        b.L[d] = box[d];
+        b.halfL[d] = 0.5f * box[d];
+    }
+    return launch_angle_forces(R, N, angles, A, ak, b, F, e_part, as_stream(stream));
+}
+
 hpf_status_t verlet_step(float* R, float* Vel, const float* F, const float* inv_mass, int64_t N, float dt,
                          const float* box, int32_t half, double* kin_part, void* stream)
 {
@@ -429,6 +456,23 @@ hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N, cons
     sk.m = mesh_k(mesh);
     return launch_sort(sk, plan, N, R_in, Vel_in, T_in, tag_in, bonds_in, D, R_out, Vel_out, T_out, tag_out,
                        bonds_out, cell_start, static_cast<char*>(work), as_stream(stream));
+}
+
+hpf_status_t hpf_sort_angles(const hpf_mesh_t* mesh, int32_t B, int64_t N, const int32_t* angles_in, int32_t A,
+                             int32_t* angles_out, const void* work, size_t work_bytes, void* stream)
+{
+    if (!mesh_ok(mesh) || N < 0 || A < 0 || A > HPF_MAX_ANGLES)
+        return HPF_EINVAL;
+    if (N > 0 && A > 0 && (!angles_in || !angles_out || angles_in == angles_out))
+        return HPF_EINVAL;
+    SortK sk;
+    SortPlan plan;
+    if (!sort_layout(N, mesh->M, B, &sk, &plan))
+        return HPF_EINVAL;
+    if (!work || work_bytes < plan.bytes)
+        return HPF_ESPACE;
+    return launch_sort_angles(plan, N, angles_in, A, angles_out, static_cast<const char*>(work),
+                              as_stream(stream));
 }
 
 hpf_status_t hpf_get_device_status(uint32_t* flags, int32_t clear, void* stream)

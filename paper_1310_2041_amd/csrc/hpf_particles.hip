@@ -311,6 +311,110 @@ __global__ __launch_bounds__(kPThreads) void k_force_gather_staggered(const floa
         raise_flag(HPF_FLAG_BAD_BEAD);
 }
 
+// Angle parameters by type: U = k (theta - theta0)^2 (form 0) or
+// k (cos theta - cos theta0)^2 (form 1), Bonded forces section.
+struct AngleK {
+    int ntypes;
+    float k[8];
+    float theta0[8];
+    float cos0[8];
+    int form[8];
+};
+
+// Force on bead i from its angle-table rows (each angle is evaluated by each of
+// its three members, as the bonds are from both ends) and its share of their
+// energy (one third each). theta is the angle at the middle bead between the
+// minimum-image arms a = x_end1 - x_mid and b = x_end2 - x_mid;
+// theta = atan2(|a x b|, a.b); dcos/dx_end1 = (b^ - c a^) / |a|,
+// dcos/dx_end2 = (a^ - c b^) / |b|, dcos/dx_mid = -(their sum). For the harmonic
+// form dU/dcos = -2k (theta - theta0) / sin(theta), sin(theta) floored at 1e-3.
+__device__ __forceinline__ float3 angle_sum(int64_t i, const float4& xi, const float4* __restrict__ R, int64_t N,
+                                            const int32_t* __restrict__ angles, int A, const AngleK& ak,
+                                            const BoxK& box, double& ei, bool& bad)
+{
+    float3 f = make_float3(0.0f, 0.0f, 0.0f);
+    for (int r = 0; r < A; ++r) {
+        const int32_t p = angles[(3 * (int64_t)r + 0) * N + i];
+        const int32_t q = angles[(3 * (int64_t)r + 1) * N + i];
+        const int32_t code = angles[(3 * (int64_t)r + 2) * N + i];
+        if (p < 0)
+            continue;
+        const int role = code & 1, type = code >> 1;
+        if (p >= N || q < 0 || q >= N || type >= ak.ntypes) {
+            bad = true;
+            continue;
+        }
+        const float4 xp = R[p], xq = R[q];
+        // the middle bead and the two ends
+        const float4 xm = role ? xi : xp;
+        const float4 x1 = role ? xp : xi;
+        float a[3], b[3];
+        a[0] = min_image(x1.x, xm.x, box.L[0], box.halfL[0]);
+        a[1] = min_image(x1.y, xm.y, box.L[1], box.halfL[1]);
+        a[2] = min_image(x1.z, xm.z, box.L[2], box.halfL[2]);
+        b[0] = min_image(xq.x, xm.x, box.L[0], box.halfL[0]);
+        b[1] = min_image(xq.y, xm.y, box.L[1], box.halfL[1]);
+        b[2] = min_image(xq.z, xm.z, box.L[2], box.halfL[2]);
+        const float na = sqrtf(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        const float nb = sqrtf(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+        const float dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+        const float cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2], cz = a[0] * b[1] - a[1] * b[0];
+        const float cr = sqrtf(cx * cx + cy * cy + cz * cz);
+        const float c = dot / (na * nb);
+        float U, dUdc;
+        if (ak.form[type] == 0) {
+            const float th = atan2f(cr, dot) - ak.theta0[type];
+            const float st = fmaxf(cr / (na * nb), 1e-3f);
+            U = ak.k[type] * th * th;
+            dUdc = -2.0f * ak.k[type] * th / st;
+        } else {
+            const float dc = c - ak.cos0[type];
+            U = ak.k[type] * dc * dc;
+            dUdc = 2.0f * ak.k[type] * dc;
+        }
+        float g[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float g1 = (b[d] / nb - c * a[d] / na) / na;
+            const float g2 = (a[d] / na - c * b[d] / nb) / nb;
+            g[d] = role ? -(g1 + g2) : g1;
+        }
+        f.x -= dUdc * g[0];
+        f.y -= dUdc * g[1];
+        f.z -= dUdc * g[2];
+        ei += (double)U / 3.0;
+    }
+    return f;
+}
+
+// F_i += the angle forces on bead i; optional FP64 energy partials.
+__global__ __launch_bounds__(kPThreads) void k_angle_forces(const float4* __restrict__ R, int64_t N,
+                                                            const int32_t* __restrict__ angles, int A, AngleK ak,
+                                                            BoxK box, float4* __restrict__ F,
+                                                            double* __restrict__ e_part)
+{
+    __shared__ double scratch[kPThreads / kWave];
+    const BeadWalk w = bead_walk(N);
+    clear_unused_slots(e_part, 1);
+    double e = 0.0;
+    bool bad = false;
+    FOR_BEADS(w, i) {
+        const float3 fa = angle_sum(i, R[i], R, N, angles, A, ak, box, e, bad);
+        float4 f = F[i];
+        f.x += fa.x;
+        f.y += fa.y;
+        f.z += fa.z;
+        F[i] = f;
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BOND);
+    if (e_part) {
+        const double s = block_sum(e, scratch);
+        if (threadIdx.x == 0)
+            e_part[w.block] = s;
+    }
+}
+
 // F_i += sum_j 2k (r - r0) d / r over the bead's own table row; E partials
 // accumulate k (r - r0)^2 / 2 per bond end (each bond is seen from both ends).
 template <bool kR0Zero>
@@ -788,6 +892,17 @@ hpf_status_t launch_force_gather_staggered(const float* R, const uint8_t* T, int
         return HPF_OK;
     hipLaunchKernelGGL(k_force_gather_staggered, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads), 0, s,
                        reinterpret_cast<const float4*>(R), T, N, m, K, V, reinterpret_cast<float4*>(F));
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+hpf_status_t launch_angle_forces(const float* R, int64_t N, const int32_t* angles, int A, const AngleK& ak,
+                                 const BoxK& box, float* F, double* e_part, hipStream_t s)
+{
+    if (N == 0 && !e_part)
+        return HPF_OK;
+    const int64_t nb = bead_blocks(N, e_part ? HPF_NPART : (1 << 20));
+    hipLaunchKernelGGL(k_angle_forces, dim3((unsigned)nb), dim3(kPThreads), 0, s, reinterpret_cast<const float4*>(R),
+                       N, angles, A, ak, box, reinterpret_cast<float4*>(F), e_part);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 

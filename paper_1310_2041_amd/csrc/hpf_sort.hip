@@ -339,6 +339,34 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_bonds(const int32_t* __re
         raise_flag(HPF_FLAG_BAD_BOND);
 }
 
+// Per-bead angle table in the new order: partner rows (3a, 3a + 1) renumbered
+// like the bond table, code rows (3a + 2) moved with their bead unchanged.
+__global__ __launch_bounds__(kSortThreads) void k_sort_angles(const int32_t* __restrict__ perm,
+                                                              const int32_t* __restrict__ inv, int64_t N,
+                                                              const int32_t* __restrict__ ang_in, int A,
+                                                              int32_t* __restrict__ ang_out)
+{
+    const int64_t p = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
+    if (p >= N)
+        return;
+    const int32_t o = perm[p];
+    bool bad = false;
+    for (int r = 0; r < 3 * A; ++r) {
+        const int32_t j = ang_in[(int64_t)r * N + o];
+        int32_t nj = j;
+        if (r % 3 != 2) {
+            nj = -1;
+            if (j >= 0 && j < N)
+                nj = inv[j];
+            else if (j >= N || j < -1)
+                bad = true;
+        }
+        ang_out[(int64_t)r * N + p] = nj;
+    }
+    if (bad)
+        raise_flag(HPF_FLAG_BAD_BOND);
+}
+
 // ------------------------------------------------------------------ host --
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -475,6 +503,17 @@ hpf_status_t launch_sort(const SortK& sk, const SortPlan& pl, int64_t N, const f
     uint32_t* start = cell_start ? cell_start : reinterpret_cast<uint32_t*>(work + pl.off_start);
     return run_sort(pl, keyer, N, R_in, V_in, T_in, tag_in, bonds_in, D, R_out, V_out, T_out, tag_out, bonds_out,
                     start, work, s);
+}
+
+hpf_status_t launch_sort_angles(const SortPlan& pl, int64_t N, const int32_t* ang_in, int A, int32_t* ang_out,
+                                const char* work, hipStream_t s)
+{
+    if (N == 0 || A == 0)
+        return HPF_OK;
+    const int32_t* perm = reinterpret_cast<const int32_t*>(work + pl.off_perm);
+    const int32_t* inv = reinterpret_cast<const int32_t*>(work + pl.off_idx);
+    hipLaunchKernelGGL(k_sort_angles, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, inv, N, ang_in, A, ang_out);
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
 }  // namespace hpf

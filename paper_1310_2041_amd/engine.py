@@ -21,7 +21,8 @@ from . import hpf
 
 # rows of the partial-sum buffer
 ROW_W, ROW_EB, ROW_KE = 0, 1, 2      # KE, Px, Py, Pz occupy rows 2..5
-N_ROWS = 6
+ROW_EA = 6                           # angle energy
+N_ROWS = 7
 
 
 class HpfState:
@@ -29,7 +30,8 @@ class HpfState:
 
     def __init__(self, R, Vel, T, tag, bonds, L, M, K, kT, inv_kappa, chi, k_bond, r0, dt,
                  device="cuda", sort_brick=8, halo=1, advance="scatter",
-                 field_every=1, stencil="centred"):
+                 field_every=1, stencil="centred", angles=None, angle_k=(), angle_theta0=(),
+                 angle_form=()):
         dev = torch.device(device)
         self.N = int(R.shape[0])
         self.K = int(K)
@@ -81,6 +83,11 @@ class HpfState:
         self.bonds = up(bonds, torch.int32) if bonds is not None and len(bonds) else \
             torch.zeros((0, self.N), dtype=torch.int32, device=dev)
         self.F = torch.zeros((self.N, 4), dtype=torch.float32, device=dev)
+        # angles (Bonded forces section): per-bead table [3A, N] and per-type parameters; the
+        # six-call step evaluates them (the fused passes take bonds only)
+        self.angles = up(angles, torch.int32) if angles is not None and len(angles) else None
+        self.angles2 = torch.empty_like(self.angles) if self.angles is not None else None
+        self.angle_params = (tuple(angle_k), tuple(angle_theta0), tuple(angle_form))
         # ping-pong targets of the cell sort
         self.R2 = torch.empty_like(self.R)
         self.Vel2 = torch.empty_like(self.Vel)
@@ -141,6 +148,9 @@ class HpfState:
 
     @classmethod
     def from_system(cls, s, **kw):
+        if getattr(s, "angles", None) is not None:
+            kw = dict(dict(angles=s.angles, angle_k=s.angle_k, angle_theta0=s.angle_theta0,
+                           angle_form=s.angle_form), **kw)
         return cls(s.R, s.V, s.T, s.tag, s.bonds, s.L, s.M, s.K, s.kT, s.inv_kappa, s.chi,
                    s.k_bond, s.r0, s.dt, **kw)
 
@@ -157,6 +167,9 @@ class HpfState:
         self.T, self.T2 = self.T2, self.T
         self.tag, self.tag2 = self.tag2, self.tag
         self.bonds, self.bonds2 = self.bonds2, self.bonds
+        if self.angles is not None:
+            hpf.hpf_sort_angles(self.mesh, self.B, self.angles, self.angles2, self.work, stream)
+            self.angles, self.angles2 = self.angles2, self.angles
         self.sorted = True
 
     def scatter(self, stream=None):
@@ -192,9 +205,17 @@ class HpfState:
         hpf.bond_forces(self.R, self.bonds if self.bonds.shape[0] else None, self.k_bond, self.r0,
                         self.box, self.F, self.part[ROW_EB] if report else None, stream)
 
+    def angle_forces(self, report=False, stream=None):
+        if self.angles is None:
+            return
+        k, th, fm = self.angle_params
+        hpf.angle_forces(self.R, self.angles, k, th, fm, self.box, self.F,
+                         self.part[ROW_EA] if report else None, stream)
+
     def forces(self, report=False, stream=None, rebuild=True):
         self.field_forces(report, stream, rebuild)
         self.bond_forces(report, stream)
+        self.angle_forces(report, stream)
 
     def step(self, report=False, sort=False, stream=None):
         self.density_pending = False
@@ -243,8 +264,9 @@ class HpfState:
         The fused passes interpolate with the centred stencil only.
 
         Bitwise equal to step() followed by the next step's first half step."""
-        if self.stencil != "centred":
-            raise ValueError("the fused passes use the centred stencil; step() runs the staggered one")
+        if self.stencil != "centred" or self.angles is not None:
+            raise ValueError("the fused passes take the centred stencil and bonds only; "
+                             "step() runs the staggered stencil and angles")
         if sort:
             self.sort(stream)
         # this step's force evaluation is number steps_done + 1 (start() was number 0)
@@ -310,7 +332,9 @@ class HpfState:
         """{KE, E_bond, W, E_tot, P} of the last reporting step (synchronises)."""
         e = self.energy.cpu().numpy()
         ke, eb, w = e[ROW_KE], e[ROW_EB], e[ROW_W]
-        return {"KE": ke, "E_bond": eb, "W": w, "E_tot": ke + eb + w, "P": e[3:6].copy()}
+        ea = e[ROW_EA] if self.angles is not None else 0.0
+        return {"KE": ke, "E_bond": eb, "W": w, "E_angle": ea, "E_tot": ke + eb + w + ea,
+                "P": e[3:6].copy()}
 
     def run(self, n_steps, report_every=0, sort_every=10, stream=None):
         out = []

@@ -110,6 +110,10 @@ _SIGNATURES = {
                                    C.c_int32),
     "bond_forces": ([_P, C.c_int64, _P, C.c_int32, C.c_float, C.c_float, _P, _P, _P, _P],
                     C.c_int32),
+    "angle_forces": ([_P, C.c_int64, _P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
+                     C.c_int32),
+    "hpf_sort_angles": ([C.POINTER(Mesh), C.c_int32, C.c_int64, _P, C.c_int32, _P, _P, C.c_size_t, _P],
+                        C.c_int32),
     "verlet_step": ([_P, _P, _P, _P, C.c_int64, C.c_float, _P, C.c_int32, _P, _P], C.c_int32),
     "hpf_reduce_partials": ([_P, C.c_int32, _P, _P], C.c_int32),
     "hpf_advance": ([_P, _P, _P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, C.c_int32,
@@ -308,6 +312,34 @@ def bond_forces(R, bonds, k: float, r0: float, box, F, e_part=None, stream=None)
         raise ValueError("e_part needs HPF_NPART slots")
     _check("bond_forces", lib().bond_forces(r, N, b, D, float(k), float(r0), _box(box), f, e,
                                             _stream(stream)))
+
+
+def angle_forces(R, angles, k, theta0, form, box, F, e_part=None, stream=None):
+    """Angle forces (Bonded forces section) added to F; angles is the per-bead table [3A, N]
+    (None = no angles); k, theta0 (radians), form: one value per angle type."""
+    N = R.shape[0]
+    A = angles.shape[0] // 3 if angles is not None else 0
+    kk = [float(x) for x in (k if hasattr(k, "__len__") else (k,))]
+    nt = len(kk)
+    th = [float(x) for x in (theta0 if hasattr(theta0, "__len__") else (theta0,) * nt)]
+    fm = [int(x) for x in (form if hasattr(form, "__len__") else (form,) * nt)]
+    if e_part is not None and e_part.numel() < HPF_NPART:
+        raise ValueError("e_part needs HPF_NPART slots")
+    _check("angle_forces", lib().angle_forces(
+        _dev(R, "R", torch.float32, (N, 4)), N,
+        _dev(angles, "angles", torch.int32, (3 * A, N), allow_none=True) if A else None, A, nt,
+        (C.c_float * nt)(*kk), (C.c_float * nt)(*th), (C.c_int32 * nt)(*fm), _box(box),
+        _dev(F, "F", torch.float32, (N, 4)),
+        _dev(e_part, "e_part", torch.float64, None, allow_none=True), _stream(stream)))
+
+
+def hpf_sort_angles(mesh: Mesh, B: int, angles_in, angles_out, work, stream=None):
+    N = angles_in.shape[1]
+    A = angles_in.shape[0] // 3
+    _check("hpf_sort_angles", lib().hpf_sort_angles(
+        C.byref(mesh), int(B), N, _dev(angles_in, "angles_in", torch.int32, (3 * A, N)), A,
+        _dev(angles_out, "angles_out", torch.int32, (3 * A, N)), _dev(work, "work", torch.uint8),
+        work.numel(), _stream(stream)))
 
 
 def verlet_step(R, Vel, F, dt: float, box, half: int, inv_mass=None, kin_part=None, stream=None):

@@ -54,6 +54,12 @@ class System:
     r0: float
     dt: float
     meta: dict = field(default_factory=dict)
+    # angle table [3A, N] (partner, partner, role + 2 type per slot) and per-type
+    # parameters (k, theta0 in radians, form 0 = harmonic in theta, 1 = in cos theta)
+    angles: np.ndarray | None = None
+    angle_k: tuple = ()
+    angle_theta0: tuple = ()
+    angle_form: tuple = ()
 
     @property
     def N(self) -> int:
@@ -255,4 +261,106 @@ def permuted(sys: System, seed: int = 99) -> tuple:
     out = System(sys.name + "_perm", sys.R[perm].copy(), sys.V[perm].copy(), sys.T[perm].copy(),
                  sys.tag[perm].copy(), b_new, sys.L, sys.M, sys.K, sys.kT, sys.inv_kappa,
                  sys.chi, sys.k_bond, sys.r0, sys.dt, dict(sys.meta))
+    if sys.angles is not None:
+        a_old = sys.angles[:, perm]
+        idx_rows = (np.arange(a_old.shape[0]) % 3 != 2)[:, None]
+        out.angles = np.where(idx_rows, np.where(a_old >= 0, inv[np.maximum(a_old, 0)], -1),
+                              a_old).astype(np.int32)
+        out.angle_k, out.angle_theta0, out.angle_form = sys.angle_k, sys.angle_theta0, sys.angle_form
     return out, perm
+
+
+# ---------------------------------------------------------------------------
+# A five-species lipid-like system in water, standing in for the paper's own
+# MD-SCF workload (coarse-grained phospholipids in water, whose force-field
+# parameters are not available here): 12-bead two-tailed lipids
+#
+#     N - P - G1 - C - C - C - C          species: N = 0 (choline-like head),
+#             |                                    P = 1 (phosphate-like),
+#             G2 - C - C - C - C                   G = 2 (glycerol), C = 3 (tail),
+#                                                  W = 4 (water, single beads)
+#
+# drawn as branched random walks of bond length 0.97 from uniform random start
+# points, plus uniformly placed water, at bead density 3. Bonds are harmonic
+# (k = 100, r0 = 0.5, the paper's U = k (r - r0)^2); the glycerol bead G1 has
+# three partners, so the bond table has three rows. Angles: P-G1-G2 and
+# P-G1-C (type 0, harmonic in theta, theta0 = 120 degrees, k = 12) and the tail
+# angles G-C-C and C-C-C (type 1, harmonic in cos theta, theta0 = 180 degrees,
+# k = 12). The chi matrix (kT units) makes tails repel water and heads:
+# chi_CW = 7, chi_NC = chi_PC = 5, chi_GC = chi_GW = 3, chi_NG = chi_PG = 1.5,
+# chi_NP = 0.5, heads and water mutually 0. These values are chosen for the
+# benchmark's shape and are not the paper's.
+LIPID_BONDS = [(0, 1), (1, 2), (2, 3), (2, 4), (4, 5), (5, 6), (6, 7),
+               (3, 8), (8, 9), (9, 10), (10, 11)]
+LIPID_TYPES = [0, 1, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3]
+LIPID_ANGLES = [((1, 2, 3), 0), ((1, 2, 4), 0), ((2, 4, 5), 1), ((4, 5, 6), 1), ((5, 6, 7), 1),
+                ((2, 3, 8), 1), ((3, 8, 9), 1), ((8, 9, 10), 1), ((9, 10, 11), 1)]
+LIPID_CHI = {(0, 1): 0.5, (0, 2): 1.5, (1, 2): 1.5, (0, 3): 5.0, (1, 3): 5.0, (2, 3): 3.0,
+             (3, 4): 7.0, (2, 4): 3.0}
+
+
+def table_from_pairs(pairs, N: int) -> np.ndarray:
+    """Bond table [D, N] (paper's table form) from undirected pairs."""
+    nbr = [[] for _ in range(N)]
+    for i, j in pairs:
+        nbr[i].append(j)
+        nbr[j].append(i)
+    D = max((len(v) for v in nbr), default=0)
+    tab = np.full((D, N), -1, dtype=np.int32)
+    for i, v in enumerate(nbr):
+        tab[:len(v), i] = v
+    return tab
+
+
+def angle_table(triplets, N: int) -> np.ndarray:
+    """Per-bead angle table [3A, N] from (end, middle, end, type) tuples: each member gets a
+    slot (partner, partner, role + 2 type); role 1 = middle (partners are the ends), 0 = end
+    (first partner = middle, second = the other end)."""
+    slots = [[] for _ in range(N)]
+    for i, j, k, t in triplets:
+        slots[j].append((i, k, 1 + 2 * t))
+        slots[i].append((j, k, 2 * t))
+        slots[k].append((j, i, 2 * t))
+    A = max((len(v) for v in slots), default=0)
+    tab = np.full((3 * A, N), -1, dtype=np.int32)
+    tab[2::3] = 0
+    for b, v in enumerate(slots):
+        for a, (p, q, code) in enumerate(v):
+            tab[3 * a, b], tab[3 * a + 1, b], tab[3 * a + 2, b] = p, q, code
+    return tab
+
+
+def lipid_system(n_lipids: int, n_water: int, M: int | None = None, seed: int = BASE_SEED + 5,
+                 density: float = 3.0) -> System:
+    """The five-species lipid-in-water system above (n_lipids * 12 + n_water beads)."""
+    rng = np.random.default_rng(seed)
+    per = len(LIPID_TYPES)
+    nl = n_lipids * per
+    N = nl + n_water
+    L = (N / density) ** (1.0 / 3.0)
+    M = int(math.ceil(L)) if M is None else M
+    pos = np.empty((nl, 3))
+    step = rng.standard_normal((n_lipids, per, 3))
+    step *= 0.97 / np.linalg.norm(step, axis=2, keepdims=True)
+    start = rng.random((n_lipids, 3)) * L
+    lip = np.empty((n_lipids, per, 3))
+    lip[:, 0] = start
+    parent = {1: 0, 2: 1, 3: 2, 4: 2, 5: 4, 6: 5, 7: 6, 8: 3, 9: 8, 10: 9, 11: 10}
+    for b in range(1, per):
+        lip[:, b] = lip[:, parent[b]] + step[:, b]
+    pos[:] = lip.reshape(-1, 3)
+    if n_water:
+        pos = np.concatenate([pos, rng.random((n_water, 3)) * L])
+    T = np.empty(N, dtype=np.uint8)
+    T[:nl] = np.tile(np.asarray(LIPID_TYPES, dtype=np.uint8), n_lipids)
+    T[nl:] = 4
+    pairs = [(m * per + i, m * per + j) for m in range(n_lipids) for i, j in LIPID_BONDS]
+    trip = [(m * per + i, m * per + j, m * per + k, t) for m in range(n_lipids)
+            for (i, j, k), t in LIPID_ANGLES]
+    R = _pack4(wrap_f32(pos, L))
+    V = _pack4(maxwell(rng, N).astype(np.float32))
+    return System("lipid_k5", R, V, T, np.arange(N, dtype=np.int32), table_from_pairs(pairs, N),
+                  (L,) * 3, (M,) * 3, 5, 1.0, 10.0, chi_matrix(5, LIPID_CHI), 100.0, 0.5, 0.03,
+                  {"seed": seed, "n_lipids": n_lipids, "n_water": n_water},
+                  angles=angle_table(trip, N), angle_k=(12.0, 12.0),
+                  angle_theta0=(2.0 * math.pi / 3.0, math.pi), angle_form=(0, 1))
