@@ -224,9 +224,10 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
             "advance_kernel": "scatter" if st.uses_scatter_advance() else "plain"}
 
 
-def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
+def run_batched_sweep(replays=5, sort_every=10, tune=True):
     """64 uneven A10B10 replicas: batched entry points vs one single-system call chain
-    per replica, both captured in a HIP graph of `steps_per_graph` steps and replayed."""
+    per replica, both with the sort interval the tuner picks, captured in HIP graphs of two
+    sort intervals (at least 20 steps, so every buffer swap returns) and replayed."""
     import torch
 
     from paper_1310_2041_amd import engine
@@ -235,6 +236,14 @@ def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
     specs = wl.replica_specs()
     systems = [wl.build_replica(sp, r) for r, sp in enumerate(specs)]
     n_beads = sum(s.N for s in systems)
+
+    batch = engine.BatchState(systems, sort_every=sort_every)
+    batch.start()
+    chosen, trials = (batch.tune(trial_steps=20) if tune else (None, []))
+    if chosen:
+        sort_every = chosen["sort_every"]
+    steps_per_graph = math.lcm(2 * sort_every, 20)
+    torch.cuda.synchronize()
 
     def time_graph(g):
         g.launch()                                   # warm-up replay
@@ -248,10 +257,7 @@ def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / (replays * steps_per_graph)
 
-    batch = engine.BatchState(systems, sort_every=sort_every)
-    batch.start()
-    chosen, trials = (batch.tune(trial_steps=3) if tune else (None, []))
-    torch.cuda.synchronize()
+    # the batch's step count is 0 here (after start or tuning): the graph begins with a sort
     gb = engine.Graph(lambda: batch.step(steps_per_graph, report_last=True))
     ms_batched = time_graph(gb)
     del gb
@@ -271,12 +277,15 @@ def run_batched_sweep(steps_per_graph=20, replays=5, sort_every=10, tune=True):
     gp = engine.Graph(plain)
     ms_plain = time_graph(gp)
     del gp
+    srt = sorted(trials)
     return {"workload": "c4_64_replica_a10b10_sweep", "replicas": len(systems), "beads": n_beads,
             "batched_value": n_beads / (ms_batched * 1e-3), "plain_value": n_beads / (ms_plain * 1e-3),
             "batched_ms_per_step": ms_batched, "plain_ms_per_step": ms_plain,
             "speedup": ms_plain / ms_batched, "tuned": chosen,
             "tune_trial_ms": [round(t, 4) for t in trials],
-            "note": "both paths replayed from HIP graphs of %d steps" % steps_per_graph}
+            "tune_margin": round(srt[1] / srt[0] - 1.0, 4) if len(srt) > 1 else None,
+            "note": "both paths replayed from HIP graphs of %d steps, sort every %d" %
+                    (steps_per_graph, sort_every)}
 
 
 # rocprofv3 kernel names behind each timed call of the step

@@ -545,12 +545,17 @@ hpf_status_t hpf_batch_current(const hpf_batch_t* batch, float** R, float** Vel,
  * it must not be the batch's own counts buffer (HPF_EINVAL). The batch's state is
  * not changed, so stepping continues as if the call had not been made. */
 hpf_status_t hpf_batch_density(hpf_batch_t* batch, uint64_t* counts_out, void* stream);
-/* Autotuner: times trial_steps steps for each candidate on the live system --
- * halo in {1,2} x mesh_chunk in {4096,16384}, with the fused deposit and with
- * a separate scatter (the latter also over bead_chunk in {1024..8192}) --
- * keeps the fastest and returns it in *chosen; trial_ms (nullable, >= 20
- * floats) receives the per-step times, *n_trials their count. The trials
- * advance the simulation. Synchronises the stream. */
+/* Autotuner of the launch shape on the live system. Candidates: the fused deposit
+ * with deposit halo {1, 2} x sort interval {5, 10, 20}, and the separate scatter
+ * with halo {1, 2} x bead_chunk {2048, 4096} (sort every 10). Each candidate
+ * runs three times from a fresh sort for trial_steps steps rounded up to a
+ * multiple of 20; its time is the median of the three, and the fastest is kept.
+ * trial_ms (nullable, >= 32 floats) receives the medians (ms per step) in
+ * candidate order and *n_trials their count. The choice is cached per process
+ * by replica set (sizes, meshes, K, D, brick) and device: a later call for the
+ * same set applies it without trials (*n_trials = 0). The trials advance the
+ * simulation; the trajectory per bead is that of any other launch shape (the
+ * storage order between sorts may differ). Synchronises the stream. */
 hpf_status_t hpf_batch_tune(hpf_batch_t* batch, int32_t trial_steps, void* stream,
                             hpf_batch_config_t* chosen, float* trial_ms, int32_t* n_trials);
 hpf_status_t hpf_batch_destroy(hpf_batch_t* batch);

@@ -13,6 +13,8 @@
 // each replica's beads follow exactly the trajectory they would follow alone.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "hpf_common.hpp"
@@ -1041,34 +1043,81 @@ hpf_status_t hpf_batch_current(const hpf_batch_t* b, float** R, float** Vel, uin
     return HPF_OK;
 }
 
+// Cache of tuned launch shapes by replica set (sizes, meshes, K, D) and device.
+static std::mutex g_tune_mu;
+static std::map<std::vector<int64_t>, hpf_batch_config_t> g_tune_cache;
+
+static std::vector<int64_t> tune_key(const hpf_batch* b)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::vector<int64_t> k = {dev, b->nrep, b->cfg.K, b->cfg.D, b->cfg.brick, (int64_t)b->cfg.fuse_deposit};
+    for (const hpf_replica_t& q : b->desc) {
+        k.push_back(q.n_beads);
+        for (int d = 0; d < 3; ++d)
+            k.push_back(q.M[d]);
+    }
+    return k;
+}
+
 hpf_status_t hpf_batch_tune(hpf_batch_t* b, int32_t trial_steps, void* stream, hpf_batch_config_t* chosen,
                             float* trial_ms, int32_t* n_trials)
 {
     if (!b || trial_steps < 1)
         return HPF_EINVAL;
     hipStream_t s = as_stream(stream);
-    const int bead_opts[] = {1024, 2048, 4096, 8192};
-    const int mesh_opts[] = {4096, 16384};
-    const int halo_opts[] = {1, 2};
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return HPF_EHIP;
+    if (n_trials)
+        *n_trials = 0;
+    const std::vector<int64_t> key = tune_key(b);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        const auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            hpf_batch_config_t c = b->cfg;
+            c.halo = it->second.halo;
+            c.sort_every = it->second.sort_every;
+            c.bead_chunk = it->second.bead_chunk;
+            c.mesh_chunk = it->second.mesh_chunk;
+            c.fuse_deposit = it->second.fuse_deposit;
+            b->cfg = c;
+            const hpf_status_t st = batch_build_items(b);
+            if (chosen)
+                *chosen = b->cfg;
+            return st;
+        }
+    }
+    // Each candidate runs from a fresh sort for a whole number of its sort intervals (trial
+    // steps rounded up to a multiple of 20), three times; its time is the median.
+    constexpr int kRepeats = 3;
+    const int steps = ((std::max(trial_steps, 20) + 19) / 20) * 20;
     std::vector<hpf_batch_config_t> cands;
-    for (int hb : halo_opts) {
+    for (int hb : {1, 2}) {
         if (hb >= b->cfg.brick)
             continue;
-        for (int mc : mesh_opts) {
+        for (int se : {5, 10, 20}) {
             hpf_batch_config_t c = b->cfg;
             c.halo = hb;
-            c.mesh_chunk = mc;
-            c.fuse_deposit = 1;                 // bead chunks do not apply to the fused pass
+            c.sort_every = se;
+            c.mesh_chunk = 16384;
+            c.fuse_deposit = 1;
             cands.push_back(c);
-            c.fuse_deposit = 0;
-            for (int bc : bead_opts) {
-                c.bead_chunk = bc;
-                cands.push_back(c);
-            }
         }
+        for (int bc : {2048, 4096}) {
+            hpf_batch_config_t c = b->cfg;
+            c.halo = hb;
+            c.sort_every = 10;
+            c.mesh_chunk = 16384;
+            c.fuse_deposit = 0;
+            c.bead_chunk = bc;
+            cands.push_back(c);
+        }
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return HPF_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return HPF_EHIP;
     }
     hpf_batch_config_t best = b->cfg;
     float best_ms = 1e30f;
@@ -1077,36 +1126,46 @@ hpf_status_t hpf_batch_tune(hpf_batch_t* b, int32_t trial_steps, void* stream, h
     for (const hpf_batch_config_t& c : cands) {
         b->cfg = c;
         if ((st = batch_build_items(b)) != HPF_OK)
-            goto done;
-        if ((st = hpf_batch_step(b, 1, 0, stream)) != HPF_OK)      // warm-up
-            goto done;
-        if (hipEventRecord(e0, s) != hipSuccess) {
-            st = HPF_EHIP;
-            goto done;
+            break;
+        float rep[kRepeats];
+        for (int r = 0; r < kRepeats && st == HPF_OK; ++r) {
+            b->steps_done = 0;                         // the trial starts with a sort
+            if (hipEventRecord(e0, s) != hipSuccess) {
+                st = HPF_EHIP;
+                break;
+            }
+            if ((st = hpf_batch_step(b, steps, 0, stream)) != HPF_OK)
+                break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = HPF_EHIP;
+                break;
+            }
+            rep[r] = ms / steps;
         }
-        if ((st = hpf_batch_step(b, trial_steps, 0, stream)) != HPF_OK)
-            goto done;
-        float ms = 0.0f;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            st = HPF_EHIP;
-            goto done;
-        }
-        ms /= trial_steps;
-        if (trial_ms)
-            trial_ms[t] = ms;
+        if (st != HPF_OK)
+            break;
+        std::sort(rep, rep + kRepeats);
+        const float med = rep[kRepeats / 2];
+        if (trial_ms && t < 32)
+            trial_ms[t] = med;
         ++t;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = b->cfg;
+        if (med < best_ms) {
+            best_ms = med;
+            best = c;
         }
     }
-done:
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->cfg = best;
+    b->steps_done = 0;
     if (st == HPF_OK)
         st = batch_build_items(b);
+    if (st == HPF_OK) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = b->cfg;
+    }
     if (chosen)
         *chosen = b->cfg;
     if (n_trials)

@@ -456,8 +456,8 @@ class BatchState:
     def tune(self, trial_steps=3, stream=None):
         cfg, ms = hpf.hpf_batch_tune(self.handle, trial_steps, stream)
         self.cfg = cfg
-        return {"halo": cfg.halo, "bead_chunk": cfg.bead_chunk, "mesh_chunk": cfg.mesh_chunk,
-                "fuse_deposit": cfg.fuse_deposit}, ms
+        return {"halo": cfg.halo, "sort_every": cfg.sort_every, "bead_chunk": cfg.bead_chunk,
+                "mesh_chunk": cfg.mesh_chunk, "fuse_deposit": cfg.fuse_deposit}, ms
 
     def _current(self, name):
         ptr = hpf.hpf_batch_current(self.handle)[name]

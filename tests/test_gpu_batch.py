@@ -101,18 +101,28 @@ def test_graph_of_single_system_steps_matches_eager():
 
 
 def test_batch_tune_keeps_trajectories():
+    """Tuning (which also varies the sort interval) moves every bead as untuned stepping does;
+    compared by tag, since the storage order between sorts depends on the sort interval. A
+    second tuning of the same replica set comes from the cache, without trials."""
     systems = _replicas()
     a = engine.BatchState(systems, sort_every=5)
     b = engine.BatchState(systems, sort_every=5)
     a.start()
     b.start()
-    chosen, times = a.tune(trial_steps=2)
-    assert len(times) == 20 and all(t > 0 for t in times)
+    chosen, times = a.tune(trial_steps=20)
+    assert len(times) == 10 and all(t > 0 for t in times)
     assert chosen["halo"] in (1, 2) and chosen["fuse_deposit"] in (0, 1)
-    b.step(len(times) * 3, report_last=False)
+    assert chosen["sort_every"] in (5, 10, 20)
+    b.step(len(times) * 3 * 20, report_last=False)
     for r in range(len(systems)):
-        for x, y in zip(a.replica_beads(r), b.replica_beads(r)):
-            assert np.array_equal(x, y)
+        ra, rb = a.replica_beads(r), b.replica_beads(r)
+        ta, tb = ra[3], rb[3]
+        for x, y in zip(ra[:3], rb[:3]):
+            assert np.array_equal(x[np.argsort(ta)], y[np.argsort(tb)])
+    c = engine.BatchState(systems, sort_every=5)
+    c.start()
+    chosen2, times2 = c.tune(trial_steps=20)
+    assert times2 == [] and chosen2 == chosen
 
 
 def test_batch_rejects_small_meshes():
