@@ -190,8 +190,13 @@ def test_c2_1000_step_mean_energies():
 
     The reference is an ensemble of 8 oracle runs whose initial coordinates differ by
     about one FP32 rounding (tests/golden/make_mean_energies.py); chaos spreads their
-    means by sd. Each mean must lie within max(1e-4, 4 sd) of the ensemble mean,
-    relative: 1e-4 where the method's own spread allows it, its spread where not."""
+    means by sd (relative: KE 3.5e-5, E_bond 2.4e-5, W 3.6e-4, E_tot 2.3e-5). E_tot and
+    E_bond must lie within 1e-4 of the ensemble mean. KE and W must lie within
+    max(1e-4, 4 sd): for KE that is 1.4e-4, for W 1.4e-3, because the oracle's own
+    runs disagree by that much. The measured deviations are written to
+    gpurun_out/records/c2_mean_energies_1000_gpu.json when that folder can be made."""
+    import json
+    import os
     gold = _golden_means("c2_mean_energies_1000.txt")
     s = wl.build(wl.SPECS["c2"])
     st = engine.HpfState.from_system(s)
@@ -201,17 +206,29 @@ def test_c2_1000_step_mean_energies():
     trace = st.run_fused(1000, report_every=1, sort_every=10)
     E = np.array([[e["KE"], e["E_bond"], e["W"], e["E_tot"]] for e in trace])
     assert hpf.hpf_get_device_status() == 0
-    bad = []
+    flat = {"E_tot", "E_bond"}
+    record, bad = {}, []
     for i, key in enumerate(["KE", "E_bond", "W", "E_tot"]):
         ens, sd, _, want0 = gold[key]
         assert e0[key] == pytest.approx(want0, rel=1e-6)
         rel = abs(E[:, i].mean() - ens) / abs(ens)
-        tol = max(1e-4, 4.0 * sd / abs(ens))
+        tol = 1e-4 if key in flat else max(1e-4, 4.0 * sd / abs(ens))
+        record[key] = {"gpu_mean": float(E[:, i].mean()), "oracle_ensemble_mean": ens,
+                       "rel_deviation": rel, "ensemble_rel_sd": sd / abs(ens), "tolerance": tol}
         print(f"{key}: mean rel dev {rel:.2e} from the oracle ensemble (tolerance {tol:.1e}, "
               f"ensemble sd {sd / abs(ens):.1e})")
         if rel > tol:
             bad.append(key)
-    assert not bad
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out",
+                       "records")
+    try:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "c2_mean_energies_1000_gpu.json"), "w") as f:
+            json.dump({"workload": "c2_a20b20_diblock_1m", "steps": 1000, "sort_every": 10,
+                       "path": "fused depositing pass", "components": record}, f, indent=1)
+    except OSError:
+        pass
+    assert not bad, bad
 
 
 @pytest.mark.parametrize("advance", ["scatter", "plain"])
