@@ -199,11 +199,15 @@ hpf_status_t hpf_density_scatter_cells(const float* R, const uint8_t* T, int64_t
  *         + inv_kappa/2 (sum_K phi_K - 1)^2 ] (the functional whose
  *         derivative by the bead count at v is V_K(v)); reduce with
  *         hpf_reduce_partials(w_part, 1, ...).
+ * present nullable uint8[M^3] device: the composition list of every mesh point
+ *         (the MD-SCF section's list of the components present, here per point):
+ *         bit K is set when counts_K > 0 there. hpf_field_gradient uses it to
+ *         skip the species that are absent (dilute multi-component systems).
  * A count >= 2^62 sets HPF_FLAG_OVERFLOW.
  * ------------------------------------------------------------------------- */
 hpf_status_t hpf_field_potential(uint64_t* counts, const hpf_mesh_t* mesh,
                                  const hpf_field_t* field, float* V, double* w_part,
-                                 void* stream);
+                                 uint8_t* present, void* stream);
 
 /* ---------------------------------------------------------------------------
  * hpf_field_gradient -- mesh gradient of the potential (Algorithm 1
@@ -213,9 +217,15 @@ hpf_status_t hpf_field_potential(uint64_t* counts, const hpf_mesh_t* mesh,
  *
  * V  float[K][M^3] device.  G float[K][M^3][4] device, overwritten; the 4th
  * component carries V_K(v) itself.
+ * present  nullable uint8[M^3] device, the composition list that
+ *          hpf_field_potential wrote for the same counts: G_K(v) is then written
+ *          only where bit K of present[v] is set; the other entries keep their
+ *          previous values (they must be finite, e.g. zero at first). The force
+ *          gathers read G_K only at mesh points where a bead of species K has a
+ *          non-zero weight, all of which carry bit K, so forces are unchanged.
  * ------------------------------------------------------------------------- */
 hpf_status_t hpf_field_gradient(const float* V, const hpf_mesh_t* mesh, int32_t K,
-                                float* G, void* stream);
+                                float* G, const uint8_t* present, void* stream);
 
 /* ---------------------------------------------------------------------------
  * hpf_force_gather -- field force on every bead, eq. (6) (Algorithm 1
@@ -400,11 +410,12 @@ hpf_status_t hpf_density_finish_cells(uint64_t* counts, int64_t N, const hpf_mes
  * V is bitwise that of the two calls; w_part (nullable, double[HPF_NPART])
  * receives the field-energy partials, grouped per workgroup, so their sum may
  * differ from hpf_field_potential's in the last bits. N, mesh, B, halo and
- * work as in hpf_advance_scatter; K = field->K. */
+ * work as in hpf_advance_scatter; K = field->K; present (nullable) as in
+ * hpf_field_potential. */
 hpf_status_t hpf_field_potential_cells(uint64_t* counts, int64_t N, const hpf_mesh_t* mesh,
                                        const hpf_field_t* field, int32_t B, int32_t halo,
                                        const void* work, size_t work_bytes, float* V,
-                                       double* w_part, void* stream);
+                                       double* w_part, uint8_t* present, void* stream);
 
 /* Deterministic FP64 reduction of partial-sum buffers: out[c] = sum of
  * part[c*HPF_NPART .. (c+1)*HPF_NPART) in a fixed tree order, c < ncomp.

@@ -6,6 +6,7 @@
 // sources below, so the device status word needs no relocatable device code.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "hpf_common.hpp"
 
@@ -215,19 +216,20 @@ static bool pot_params(const hpf_mesh_t* mesh, const hpf_field_t* field, PotK* p
 }
 
 hpf_status_t hpf_field_potential(uint64_t* counts, const hpf_mesh_t* mesh, const hpf_field_t* field,
-                                 float* V, double* w_part, void* stream)
+                                 float* V, double* w_part, uint8_t* present, void* stream)
 {
     if (!counts || !V || !mesh_ok(mesh) || !field || field->K < 1 || field->K > HPF_MAX_TYPES)
         return HPF_EINVAL;
     PotK p;
     if (!pot_params(mesh, field, &p))
         return HPF_EINVAL;
-    return launch_field_potential(counts, mesh_k(mesh), field->K, p, V, w_part, as_stream(stream));
+    return launch_field_potential(counts, mesh_k(mesh), field->K, p, V, w_part, present, as_stream(stream));
 }
 
 hpf_status_t hpf_field_potential_cells(uint64_t* counts, int64_t N, const hpf_mesh_t* mesh,
                                        const hpf_field_t* field, int32_t B, int32_t halo, const void* work,
-                                       size_t work_bytes, float* V, double* w_part, void* stream)
+                                       size_t work_bytes, float* V, double* w_part, uint8_t* present,
+                                       void* stream)
 {
     if (!counts || !V || !mesh_ok(mesh) || !field || field->K < 1 || field->K > HPF_MAX_TYPES)
         return HPF_EINVAL;
@@ -240,16 +242,17 @@ hpf_status_t hpf_field_potential_cells(uint64_t* counts, int64_t N, const hpf_me
         return HPF_ESPACE;
     const char* w = static_cast<const char*>(work);
     return launch_finish_potential(reinterpret_cast<const unsigned long long*>(w + sb), tk, field->K, p, counts, V,
-                                   w_part, as_stream(stream));
+                                   w_part, present, as_stream(stream));
 }
 
-hpf_status_t hpf_field_gradient(const float* V, const hpf_mesh_t* mesh, int32_t K, float* G, void* stream)
+hpf_status_t hpf_field_gradient(const float* V, const hpf_mesh_t* mesh, int32_t K, float* G,
+                                const uint8_t* present, void* stream)
 {
     if (!V || !G || !mesh_ok(mesh) || K < 1 || K > HPF_MAX_TYPES)
         return HPF_EINVAL;
     if ((mesh->M[0] + 63) / 64 > 65535 || mesh->M[2] > 65535)
         return HPF_EINVAL;
-    return launch_field_gradient(V, mesh_k(mesh), K, G, as_stream(stream));
+    return launch_field_gradient(V, mesh_k(mesh), K, G, present, as_stream(stream));
 }
 
 hpf_status_t hpf_force_gather(const float* R, const uint8_t* T, int64_t N, const hpf_mesh_t* mesh,

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kPotThreads) void k_batch_potential(const RepK* __r
     unsigned long long* c = counts + (int64_t)K * rp.moff;
     float* v = V + (int64_t)K * rp.moff;
     for (int64_t q = it.begin + threadIdx.x; q < it.end; q += kPotThreads)
-        wsum += potential_point<K>(c, v, rp.m.nm, q, rp.m.c_norm, rp.p, over);
+        wsum += potential_point<K>(c, v, rp.m.nm, q, rp.m.c_norm, rp.p, over, nullptr);
     if (over)
         raise_flag(HPF_FLAG_OVERFLOW);
     if (w_part) {
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kFPThreads) void k_batch_finish_potential(const Rep
     bool over = false;
     const double wsum = finish_potential_brick<K>(cov, partials + rp.brick_off * (int64_t)K * P * P * P, tk, rp.p,
                                                   counts + (int64_t)K * rp.moff, V + (int64_t)K * rp.moff,
-                                                  it.begin, over);
+                                                  it.begin, over, nullptr);
     if (over)
         raise_flag(HPF_FLAG_OVERFLOW);
     if (w_part) {

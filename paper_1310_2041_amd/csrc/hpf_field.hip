@@ -47,10 +47,24 @@ __device__ __forceinline__ double potential_values(const unsigned long long (&n)
     return 0.5 * inter + 0.5 * p.inv_kappa * delta * delta;
 }
 
+// Composition list of a mesh point (the paper's list of the species with a
+// non-zero density there, used to shorten the species loop): bit k set when
+// species k has a non-zero count.
+template <int K>
+__device__ __forceinline__ uint8_t composition(const unsigned long long (&n)[K])
+{
+    uint32_t bits = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        bits |= (n[k] != 0ull ? 1u : 0u) << k;
+    return (uint8_t)bits;
+}
+
 template <int K>
 __device__ __forceinline__ double potential_point(unsigned long long* __restrict__ counts,
                                                   float* __restrict__ V, int64_t nm, int64_t q,
-                                                  double c_norm, const PotK& p, bool& over)
+                                                  double c_norm, const PotK& p, bool& over,
+                                                  uint8_t* __restrict__ present)
 {
     unsigned long long n[K];
 #pragma unroll
@@ -59,6 +73,8 @@ __device__ __forceinline__ double potential_point(unsigned long long* __restrict
 #pragma unroll
     for (int k = 0; k < K; ++k)
         counts[k * nm + q] = 0ull;
+    if (present)
+        present[q] = composition<K>(n);
     return potential_values<K>(n, V, nm, q, c_norm, p, over);
 }
 
@@ -67,7 +83,8 @@ template <int K>
 __global__ __launch_bounds__(kPotThreads) void k_field_potential(unsigned long long* __restrict__ counts,
                                                                  MeshK m, PotK p,
                                                                  float* __restrict__ V,
-                                                                 double* __restrict__ w_part)
+                                                                 double* __restrict__ w_part,
+                                                                 uint8_t* __restrict__ present)
 {
     __shared__ double scratch[kPotThreads / kWave];
     const int64_t nm = m.nm;
@@ -79,7 +96,7 @@ __global__ __launch_bounds__(kPotThreads) void k_field_potential(unsigned long l
              i += (int64_t)kPotThreads * gridDim.x)
             w_part[i] = 0.0;
     for (int64_t v = b * kPotThreads + threadIdx.x; v < nm; v += (int64_t)gridDim.x * kPotThreads)
-        wsum += potential_point<K>(counts, V, nm, v, m.c_norm, p, over);
+        wsum += potential_point<K>(counts, V, nm, v, m.c_norm, p, over, present);
     if (over)
         raise_flag(HPF_FLAG_OVERFLOW);
     if (w_part) {
@@ -90,7 +107,7 @@ __global__ __launch_bounds__(kPotThreads) void k_field_potential(unsigned long l
 }
 
 hpf_status_t launch_field_potential(uint64_t* counts, const MeshK& m, int K, const PotK& p,
-                                    float* V, double* w_part, hipStream_t s)
+                                    float* V, double* w_part, uint8_t* present, hipStream_t s)
 {
     int64_t nb = (m.nm + kPotThreads - 1) / kPotThreads;
     const int64_t cap = w_part ? HPF_NPART : 8192;
@@ -99,14 +116,14 @@ hpf_status_t launch_field_potential(uint64_t* counts, const MeshK& m, int K, con
     auto* c = reinterpret_cast<unsigned long long*>(counts);
     const dim3 g((unsigned)nb), bl(kPotThreads);
     switch (K) {
-    case 1: hipLaunchKernelGGL(k_field_potential<1>, g, bl, 0, s, c, m, p, V, w_part); break;
-    case 2: hipLaunchKernelGGL(k_field_potential<2>, g, bl, 0, s, c, m, p, V, w_part); break;
-    case 3: hipLaunchKernelGGL(k_field_potential<3>, g, bl, 0, s, c, m, p, V, w_part); break;
-    case 4: hipLaunchKernelGGL(k_field_potential<4>, g, bl, 0, s, c, m, p, V, w_part); break;
-    case 5: hipLaunchKernelGGL(k_field_potential<5>, g, bl, 0, s, c, m, p, V, w_part); break;
-    case 6: hipLaunchKernelGGL(k_field_potential<6>, g, bl, 0, s, c, m, p, V, w_part); break;
-    case 7: hipLaunchKernelGGL(k_field_potential<7>, g, bl, 0, s, c, m, p, V, w_part); break;
-    case 8: hipLaunchKernelGGL(k_field_potential<8>, g, bl, 0, s, c, m, p, V, w_part); break;
+    case 1: hipLaunchKernelGGL(k_field_potential<1>, g, bl, 0, s, c, m, p, V, w_part, present); break;
+    case 2: hipLaunchKernelGGL(k_field_potential<2>, g, bl, 0, s, c, m, p, V, w_part, present); break;
+    case 3: hipLaunchKernelGGL(k_field_potential<3>, g, bl, 0, s, c, m, p, V, w_part, present); break;
+    case 4: hipLaunchKernelGGL(k_field_potential<4>, g, bl, 0, s, c, m, p, V, w_part, present); break;
+    case 5: hipLaunchKernelGGL(k_field_potential<5>, g, bl, 0, s, c, m, p, V, w_part, present); break;
+    case 6: hipLaunchKernelGGL(k_field_potential<6>, g, bl, 0, s, c, m, p, V, w_part, present); break;
+    case 7: hipLaunchKernelGGL(k_field_potential<7>, g, bl, 0, s, c, m, p, V, w_part, present); break;
+    case 8: hipLaunchKernelGGL(k_field_potential<8>, g, bl, 0, s, c, m, p, V, w_part, present); break;
     default: return HPF_EINVAL;
     }
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
@@ -128,7 +145,8 @@ __device__ __forceinline__ double finish_potential_brick(Cover (&cov)[3][kTcMaxB
                                                          const unsigned long long* __restrict__ partials,
                                                          const TileK& tk, const PotK& p,
                                                          unsigned long long* __restrict__ counts,
-                                                         float* __restrict__ V, int64_t brick, bool& over)
+                                                         float* __restrict__ V, int64_t brick, bool& over,
+                                                         uint8_t* __restrict__ present)
 {
     const MeshK& m = tk.m;
     const int64_t nm = m.nm;
@@ -172,6 +190,8 @@ __device__ __forceinline__ double finish_potential_brick(Cover (&cov)[3][kTcMaxB
 #pragma unroll
         for (int k = 0; k < K; ++k)
             counts[(int64_t)k * nm + dst] = 0ull;
+        if (present)
+            present[dst] = composition<K>(n);
         wsum += potential_values<K>(n, V, nm, dst, m.c_norm, p, over);
     }
     return wsum;
@@ -181,7 +201,8 @@ template <int K>
 __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned long long* __restrict__ partials,
                                                                  TileK tk, PotK p,
                                                                  unsigned long long* __restrict__ counts,
-                                                                 float* __restrict__ V, double* __restrict__ w_part)
+                                                                 float* __restrict__ V, double* __restrict__ w_part,
+                                                                 uint8_t* __restrict__ present)
 {
     __shared__ Cover cov[3][kTcMaxB];
     __shared__ double scratch[kFPThreads / kWave];
@@ -193,7 +214,7 @@ __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned 
     double wsum = 0.0;
     bool over = false;
     for (int64_t brick = w.first; brick < w.end; brick += w.stride)
-        wsum += finish_potential_brick<K>(cov, partials, tk, p, counts, V, brick, over);
+        wsum += finish_potential_brick<K>(cov, partials, tk, p, counts, V, brick, over, present);
     if (over)
         raise_flag(HPF_FLAG_OVERFLOW);
     if (w_part) {
@@ -205,38 +226,42 @@ __global__ __launch_bounds__(kFPThreads) void k_finish_potential(const unsigned 
 
 template <int K>
 static hpf_status_t launch_finish_potential_k(const unsigned long long* partials, const TileK& tk, const PotK& p,
-                                              unsigned long long* counts, float* V, double* w_part, hipStream_t s)
+                                              unsigned long long* counts, float* V, double* w_part,
+                                              uint8_t* present, hipStream_t s)
 {
     // one brick per workgroup where the partial slots allow it (the dispatcher then
     // balances uneven bricks), else bricks walked by HPF_NPART workgroups
     const int64_t nb = std::min<int64_t>(tk.ntiles, HPF_NPART);
     hipLaunchKernelGGL(k_finish_potential<K>, dim3((unsigned)nb), dim3(kFPThreads), 0, s, partials, tk, p, counts, V,
-                       w_part);
+                       w_part, present);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
 hpf_status_t launch_finish_potential(const unsigned long long* partials, const TileK& tk, int K, const PotK& p,
-                                     uint64_t* counts, float* V, double* w_part, hipStream_t s)
+                                     uint64_t* counts, float* V, double* w_part, uint8_t* present, hipStream_t s)
 {
     auto* c = reinterpret_cast<unsigned long long*>(counts);
     switch (K) {
-    case 1: return launch_finish_potential_k<1>(partials, tk, p, c, V, w_part, s);
-    case 2: return launch_finish_potential_k<2>(partials, tk, p, c, V, w_part, s);
-    case 3: return launch_finish_potential_k<3>(partials, tk, p, c, V, w_part, s);
-    case 4: return launch_finish_potential_k<4>(partials, tk, p, c, V, w_part, s);
-    case 5: return launch_finish_potential_k<5>(partials, tk, p, c, V, w_part, s);
-    case 6: return launch_finish_potential_k<6>(partials, tk, p, c, V, w_part, s);
-    case 7: return launch_finish_potential_k<7>(partials, tk, p, c, V, w_part, s);
-    case 8: return launch_finish_potential_k<8>(partials, tk, p, c, V, w_part, s);
+    case 1: return launch_finish_potential_k<1>(partials, tk, p, c, V, w_part, present, s);
+    case 2: return launch_finish_potential_k<2>(partials, tk, p, c, V, w_part, present, s);
+    case 3: return launch_finish_potential_k<3>(partials, tk, p, c, V, w_part, present, s);
+    case 4: return launch_finish_potential_k<4>(partials, tk, p, c, V, w_part, present, s);
+    case 5: return launch_finish_potential_k<5>(partials, tk, p, c, V, w_part, present, s);
+    case 6: return launch_finish_potential_k<6>(partials, tk, p, c, V, w_part, present, s);
+    case 7: return launch_finish_potential_k<7>(partials, tk, p, c, V, w_part, present, s);
+    case 8: return launch_finish_potential_k<8>(partials, tk, p, c, V, w_part, present, s);
     default: return HPF_EINVAL;
     }
 }
 
 constexpr int kGradX = 64, kGradY = 4;
 
-// Centred gradient at mesh point (x, y, z), all species: G = (gx, gy, gz, V).
+// Centred gradient at mesh point (x, y, z): G = (gx, gy, gz, V) for the species whose
+// bit is set in `listed` (the point's composition list; all species with ~0). Entries of
+// species left out keep their previous values: a bead reads G of its own species only at
+// the corners that its weights reach, all of which hold a non-zero count of its species.
 __device__ __forceinline__ void gradient_point(const float* __restrict__ V, const MeshK& m, int K, int x, int y,
-                                               int z, float4* __restrict__ G)
+                                               int z, float4* __restrict__ G, uint32_t listed = ~0u)
 {
     const int Mx = m.M[0], My = m.M[1], Mz = m.M[2];
     const int xp = next_wrap(x, Mx), xm = prev_wrap(x, Mx);
@@ -247,6 +272,8 @@ __device__ __forceinline__ void gradient_point(const float* __restrict__ V, cons
     const int64_t rowzm = ((int64_t)prev_wrap(z, Mz) * My + y) * Mx;
     const float hx = 0.5f * m.s[0], hy = 0.5f * m.s[1], hz = 0.5f * m.s[2];
     for (int k = 0; k < K; ++k) {
+        if (!((listed >> k) & 1u))
+            continue;
         const float* Vk = V + k * m.nm;
         float4 g;
         g.x = (Vk[row + xp] - Vk[row + xm]) * hx;
@@ -262,20 +289,24 @@ __device__ __forceinline__ void gradient_point(const float* __restrict__ V, cons
 // and +-z rows are re-read from L2 by neighbouring blocks.
 __global__ __launch_bounds__(kGradX * kGradY) void k_field_gradient(const float* __restrict__ V,
                                                                     MeshK m, int K,
-                                                                    float4* __restrict__ G)
+                                                                    float4* __restrict__ G,
+                                                                    const uint8_t* __restrict__ present)
 {
     const int x = blockIdx.x * kGradX + threadIdx.x;
     const int y = blockIdx.y * kGradY + threadIdx.y;
     if (x >= m.M[0] || y >= m.M[1])
         return;
-    gradient_point(V, m, K, x, y, blockIdx.z, G);
+    const uint32_t listed =
+        present ? present[((int64_t)blockIdx.z * m.M[1] + y) * m.M[0] + x] : ~0u;
+    gradient_point(V, m, K, x, y, blockIdx.z, G, listed);
 }
 
-hpf_status_t launch_field_gradient(const float* V, const MeshK& m, int K, float* G, hipStream_t s)
+hpf_status_t launch_field_gradient(const float* V, const MeshK& m, int K, float* G, const uint8_t* present,
+                                   hipStream_t s)
 {
     const dim3 g((m.M[0] + kGradX - 1) / kGradX, (m.M[1] + kGradY - 1) / kGradY, m.M[2]);
     hipLaunchKernelGGL(k_field_gradient, g, dim3(kGradX, kGradY), 0, s, V, m, K,
-                       reinterpret_cast<float4*>(G));
+                       reinterpret_cast<float4*>(G), present);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 

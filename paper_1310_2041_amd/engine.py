@@ -31,7 +31,7 @@ class HpfState:
     def __init__(self, R, Vel, T, tag, bonds, L, M, K, kT, inv_kappa, chi, k_bond, r0, dt,
                  device="cuda", sort_brick=8, halo=1, advance="scatter",
                  field_every=1, stencil="centred", angles=None, angle_k=(), angle_theta0=(),
-                 angle_form=()):
+                 angle_form=(), composition_list=False):
         dev = torch.device(device)
         self.N = int(R.shape[0])
         self.K = int(K)
@@ -105,7 +105,12 @@ class HpfState:
         # mesh buffers; counts start at zero and are cleared by the potential pass
         self.counts = torch.zeros((self.K, nm), dtype=torch.int64, device=dev)
         self.V = torch.empty((self.K, nm), dtype=torch.float32, device=dev)
-        self.G = torch.empty((self.K, nm, 4), dtype=torch.float32, device=dev)
+        # Composition list (MD-SCF section): the potential pass records which species are
+        # present at each mesh point and the gradient pass skips the absent ones; G starts at
+        # zero so that entries never written stay finite.
+        self.present = torch.zeros(nm, dtype=torch.uint8, device=dev) if composition_list else None
+        self.G = (torch.zeros if composition_list else torch.empty)((self.K, nm, 4), dtype=torch.float32,
+                                                                    device=dev)
         self.part = torch.zeros((N_ROWS, hpf.HPF_NPART), dtype=torch.float64, device=dev)
         self.energy = torch.zeros(8, dtype=torch.float64, device=dev)
         self.steps_done = 0
@@ -193,9 +198,9 @@ class HpfState:
             self.scatter(stream)
             hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V,
                                     self.part[ROW_W] if (report or self.field_every > 1) else None,
-                                    stream)
+                                    stream, present=self.present)
             if self.stencil == "centred":
-                hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
+                hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream, present=self.present)
         if self.stencil == "staggered":
             hpf.hpf_force_gather_staggered(self.R, self.T, self.mesh, self.K, self.V, self.F, stream)
         else:
@@ -272,7 +277,7 @@ class HpfState:
         # this step's force evaluation is number steps_done + 1 (start() was number 0)
         if self.rebuilds_field(self.steps_done + 1):
             self.potential(report or self.field_every > 1, stream)
-            hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream)
+            hpf.hpf_field_gradient(self.V, self.mesh, self.K, self.G, stream, present=self.present)
         self.advance(report, stream, deposit=self.rebuilds_field(self.steps_done + 2))
         if report:
             hpf.hpf_reduce_partials(self.part, N_ROWS, self.energy, stream)
@@ -284,11 +289,11 @@ class HpfState:
         w = self.part[ROW_W] if report else None
         if self.density_pending:
             hpf.hpf_field_potential_cells(self.counts, self.N, self.mesh, self.field, self.B, self.halo,
-                                          self.scatter_work, self.V, w, stream)
+                                          self.scatter_work, self.V, w, stream, present=self.present)
             self.density_pending = False
         else:
             self.scatter(stream)
-            hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V, w, stream)
+            hpf.hpf_field_potential(self.counts, self.mesh, self.field, self.V, w, stream, present=self.present)
 
     def uses_scatter_advance(self) -> bool:
         return self.advance_mode == "scatter" and self.sorted and self.cells_ok

@@ -103,8 +103,8 @@ _SIGNATURES = {
                                     C.c_size_t),
     "hpf_density_scatter_cells": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, C.c_int32,
                                    C.c_int32, _P, _P, C.c_size_t, _P], C.c_int32),
-    "hpf_field_potential": ([_P, C.POINTER(Mesh), C.POINTER(Field), _P, _P, _P], C.c_int32),
-    "hpf_field_gradient": ([_P, C.POINTER(Mesh), C.c_int32, _P, _P], C.c_int32),
+    "hpf_field_potential": ([_P, C.POINTER(Mesh), C.POINTER(Field), _P, _P, _P, _P], C.c_int32),
+    "hpf_field_gradient": ([_P, C.POINTER(Mesh), C.c_int32, _P, _P, _P], C.c_int32),
     "hpf_force_gather": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, _P], C.c_int32),
     "hpf_force_gather_staggered": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, _P],
                                    C.c_int32),
@@ -125,7 +125,7 @@ _SIGNATURES = {
     "hpf_density_finish_cells": ([_P, C.c_int64, C.POINTER(Mesh), C.c_int32, C.c_int32, C.c_int32,
                                   _P, C.c_size_t, _P], C.c_int32),
     "hpf_field_potential_cells": ([_P, C.c_int64, C.POINTER(Mesh), C.POINTER(Field), C.c_int32, C.c_int32,
-                                   _P, C.c_size_t, _P, _P, _P], C.c_int32),
+                                   _P, C.c_size_t, _P, _P, _P, _P], C.c_int32),
     "hpf_sort_workspace_bytes": ([C.c_int64, C.POINTER(Mesh), C.c_int32], C.c_size_t),
     "hpf_sort_by_cell": ([C.POINTER(Mesh), C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
                           _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int32),
@@ -265,7 +265,7 @@ def hpf_density_scatter_cells(R, T, mesh: Mesh, K: int, cell_start, B: int, halo
                                            work.numel() * work.element_size(), _stream(stream)))
 
 
-def hpf_field_potential(counts, mesh: Mesh, field: Field, V, w_part=None, stream=None):
+def hpf_field_potential(counts, mesh: Mesh, field: Field, V, w_part=None, stream=None, present=None):
     nm, K = _nm(mesh), field.K
     c = _dev(counts, "counts", _U64, (K, nm))
     v = _dev(V, "V", torch.float32, (K, nm))
@@ -273,14 +273,17 @@ def hpf_field_potential(counts, mesh: Mesh, field: Field, V, w_part=None, stream
     if w_part is not None and w_part.numel() < HPF_NPART:
         raise ValueError("w_part needs HPF_NPART slots")
     _check("hpf_field_potential",
-           lib().hpf_field_potential(c, C.byref(mesh), C.byref(field), v, w, _stream(stream)))
+           lib().hpf_field_potential(c, C.byref(mesh), C.byref(field), v, w,
+                                     _dev(present, "present", torch.uint8, (nm,), allow_none=True),
+                                     _stream(stream)))
 
 
-def hpf_field_gradient(V, mesh: Mesh, K: int, G, stream=None):
+def hpf_field_gradient(V, mesh: Mesh, K: int, G, stream=None, present=None):
     nm = _nm(mesh)
     v = _dev(V, "V", torch.float32, (K, nm))
     g = _dev(G, "G", torch.float32, (K, nm, 4))
-    _check("hpf_field_gradient", lib().hpf_field_gradient(v, C.byref(mesh), K, g, _stream(stream)))
+    pr = _dev(present, "present", torch.uint8, (nm,), allow_none=True)
+    _check("hpf_field_gradient", lib().hpf_field_gradient(v, C.byref(mesh), K, g, pr, _stream(stream)))
 
 
 def hpf_force_gather(R, T, mesh: Mesh, K: int, G, F, stream=None):
@@ -438,7 +441,7 @@ def hpf_density_finish_cells(counts, N: int, mesh: Mesh, K: int, B: int, halo: i
 
 
 def hpf_field_potential_cells(counts, N: int, mesh: Mesh, field: Field, B: int, halo: int, work, V,
-                              w_part=None, stream=None):
+                              w_part=None, stream=None, present=None):
     K = field.K
     c = _dev(counts, "counts", torch.int64, (K, _nm(mesh)))
     w = _dev(work, "work", torch.uint8)
@@ -448,7 +451,9 @@ def hpf_field_potential_cells(counts, N: int, mesh: Mesh, field: Field, B: int, 
         raise ValueError("w_part needs HPF_NPART slots")
     _check("hpf_field_potential_cells",
            lib().hpf_field_potential_cells(c, int(N), C.byref(mesh), C.byref(field), int(B), int(halo), w,
-                                           work.numel(), v, wp, _stream(stream)))
+                                           work.numel(), v, wp,
+                                           _dev(present, "present", torch.uint8, (_nm(mesh),),
+                                                allow_none=True), _stream(stream)))
 
 
 def hpf_reduce_partials(part, ncomp: int, out, stream=None):

@@ -67,7 +67,7 @@ def test_invalid_arguments_rejected_on_host(hpf):
     assert L.hpf_density_scatter(dummy, dummy, 10, C.byref(bad), 2, dummy, None) == EINVAL
     f = hpf.make_field(2, 1.0, 10.0, [[0.0, 1.0], [1.0, 0.0]])
     f.K = 9
-    assert L.hpf_field_potential(dummy, C.byref(m), C.byref(f), dummy, None, None) == EINVAL
+    assert L.hpf_field_potential(dummy, C.byref(m), C.byref(f), dummy, None, None, None) == EINVAL
     box = (C.c_float * 3)(10, 10, 10)
     badbox = (C.c_float * 3)(10, -1, 10)
     assert L.bond_forces(dummy, 10, dummy, 17, 1.0, 0.0, box, dummy, None, None) == EINVAL
@@ -121,11 +121,11 @@ def test_invalid_arguments_rejected_on_host(hpf):
     f2 = hpf.make_field(2, 1.0, 10.0, [[0.0, 1.0], [1.0, 0.0]])
     vv = C.c_void_p(0x30000)
     assert L.hpf_field_potential_cells(None, 10, C.byref(m16), C.byref(f2), 8, 1, wk, need, vv, None,
-                                       None) == EINVAL
+                                       None, None) == EINVAL
     assert L.hpf_field_potential_cells(cnt, 10, C.byref(m), C.byref(f2), 8, 1, wk, need, vv, None,
-                                       None) == EINVAL                 # mesh too small for the boxes
+                                       None, None) == EINVAL                 # mesh too small for the boxes
     assert L.hpf_field_potential_cells(cnt, 10, C.byref(m16), C.byref(f2), 8, 1, wk, need - 1, vv, None,
-                                       None) == -3
+                                       None, None) == -3
 
 
 def test_sort_workspace_size(hpf):

@@ -1,0 +1,102 @@
+"""GPU: the composition list (MD-SCF section: the list of components present, used to
+shorten the species loop in multi-component systems), kept per mesh point by the
+potential pass and used by the gradient pass to skip absent species.
+
+The list must equal the oracle's counts > 0 bit for bit; the listed gradient entries
+must equal those of the unlisted pass bit for bit and the others keep their values;
+and whole runs with the list must move every bead exactly as runs without it."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from gpu_util import host  # noqa: E402
+from paper_1310_2041_amd import engine, hpf  # noqa: E402
+from synth import workloads as wl  # noqa: E402
+
+
+def dilute_lipids():
+    """K = 5: 2000 lipids (24,000 beads) in 216,000 waters: the head species are absent
+    from most mesh points."""
+    return wl.lipid_system(2000, 216000)
+
+
+def test_composition_list_and_listed_gradient():
+    s = dilute_lipids()
+    st = engine.HpfState.from_system(s, composition_list=True)
+    st.sort()
+    hpf.hpf_density_scatter(st.R, st.T, st.mesh, st.K, st.counts)
+    hpf.hpf_field_potential(st.counts, st.mesh, st.field, st.V, None, present=st.present)
+    c_or, _ = oracle.density(s.R, s.T, s.L, s.M, s.K)
+    want = np.zeros(c_or.shape[1:], np.uint8)
+    for k in range(s.K):
+        want |= ((c_or[k] > 0).astype(np.uint8) << k)
+    got = host(st.present).reshape(want.shape)
+    assert np.array_equal(got, want)
+    absent = 1.0 - np.mean([(c_or[k] > 0).mean() for k in range(s.K)])
+    print(f"absent (point, species) pairs: {absent:.2f}")
+    assert absent > 0.3
+    # the listed gradient: listed entries bitwise those of the full pass, the rest untouched
+    full = torch.empty_like(st.G)
+    hpf.hpf_field_gradient(st.V, st.mesh, st.K, full)
+    listed = torch.full_like(st.G, 3.0)
+    hpf.hpf_field_gradient(st.V, st.mesh, st.K, listed, present=st.present)
+    mask = np.stack([(want.ravel() >> k) & 1 for k in range(s.K)]).astype(bool)
+    a, b = host(full).view(np.uint32), host(listed).view(np.uint32)
+    assert np.array_equal(a[mask], b[mask])
+    assert (host(listed)[~mask] == 3.0).all()
+
+
+def test_runs_with_the_list_equal_runs_without():
+    """Ten six-call steps of the dilute lipid system (angles included) and twelve fused
+    steps of the 20,000-bead melt: bit for bit the same beads and energies."""
+    s = dilute_lipids()
+    a = engine.HpfState.from_system(s)
+    b = engine.HpfState.from_system(s, composition_list=True)
+    for st in (a, b):
+        st.start(sort=True)
+    Ea = a.run(10, report_every=1, sort_every=5)
+    Eb = b.run(10, report_every=1, sort_every=5)
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
+    for ea, eb in zip(Ea, Eb):
+        for key in ("KE", "E_bond", "W", "E_angle"):
+            assert ea[key] == eb[key]
+    c1 = wl.build(wl.SPECS["c1"])
+    a = engine.HpfState.from_system(c1)
+    b = engine.HpfState.from_system(c1, composition_list=True)
+    for st in (a, b):
+        st.start(sort=True)
+        st.prime()
+        st.run_fused(12, report_every=0, sort_every=4)
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
+    assert hpf.hpf_get_device_status() == 0
+
+
+def test_gradient_time_with_and_without_the_list():
+    """Measurement for the dilute five-species system at 1.2M beads: the gradient pass with
+    and without the composition list (printed; the benchmark reports the same comparison)."""
+    s = wl.lipid_system(10000, 1080000)
+    st = engine.HpfState.from_system(s, composition_list=True)
+    st.sort()
+    st.scatter()
+    hpf.hpf_field_potential(st.counts, st.mesh, st.field, st.V, None, present=st.present)
+    times = {}
+    for name, pr in (("all species", None), ("listed", st.present)):
+        for _ in range(3):
+            hpf.hpf_field_gradient(st.V, st.mesh, st.K, st.G, present=pr)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            hpf.hpf_field_gradient(st.V, st.mesh, st.K, st.G, present=pr)
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / 20 * 1e3
+    print("gradient pass, K = 5 dilute lipids, 1.2M beads, us:", times)
+    assert all(t > 0 for t in times.values())
