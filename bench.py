@@ -163,7 +163,7 @@ def replay_segments(st, one, steps, period, torch, engine, max_graphs=64):
 
 
 def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, graph=True, halo=2,
-                 advance="scatter", field_every=1, thermostat=0.0):
+                 advance="scatter", field_every=1, thermostat=0.0, brick=8):
     """Warm up, time `steps` steps, then (instrument) time each call over one period of
     eager steps. With `graph`, the timed steps replay HIP graphs (replay_segments)."""
     import torch
@@ -173,7 +173,8 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
 
     spec = wl.SPECS[cfg]
     s = wl.build(spec)
-    st = engine.HpfState.from_system(s, halo=halo, advance=advance, field_every=field_every)
+    st = engine.HpfState.from_system(s, halo=halo, advance=advance, field_every=field_every,
+                                     sort_brick=brick)
     if thermostat > 0.0:
         st.set_thermostat(thermostat, seed=13102041 + spec.index)
     del s
@@ -424,6 +425,7 @@ def main():
     ap.add_argument("--c5-steps", type=int, default=40,
                     help="steps of the 100M-bead three-species system reported under 'c5' (0 = skip)")
     ap.add_argument("--halo", type=int, default=2, help="drift halo (cells) of the brick deposit boxes")
+    ap.add_argument("--brick", type=int, default=8, help="sort brick edge in cells (3..16)")
     ap.add_argument("--advance", default="scatter", choices=["scatter", "plain"],
                     help="fused pass on cell-sorted beads (scatter: with the density deposit)")
     ap.add_argument("--eager", action="store_true",
@@ -448,7 +450,8 @@ def main():
     fused = args.mode == "fused"
     log(f"{args.config}: {args.warmup} warm-up + {args.steps} timed steps")
     r = run_workload(args.config, args.steps, args.warmup, args.sort_every, fused=fused,
-                     graph=not args.eager, halo=args.halo, advance=args.advance)
+                     graph=not args.eager, halo=args.halo, advance=args.advance,
+                     brick=args.brick)
     ms_step = r["ms_total"] / args.steps
     value = r["N"] * args.steps / (r["ms_total"] * 1e-3)
     per_kernel = kernel_table(r)
@@ -469,7 +472,8 @@ def main():
         "config": {"workload": r["spec"].name, "beads": r["N"], "species": r["K"],
                    "mesh": [r["spec"].M] * 3, "box": r["spec"].L, "sort_every": args.sort_every,
                    "energy_report_every": 1, "step": args.mode, "advance": r["advance_kernel"],
-                   "halo": args.halo, "launch": r["launch"], "parallelism": "single-gpu"},
+                   "halo": args.halo, "brick": args.brick, "launch": r["launch"],
+                   "parallelism": "single-gpu"},
         "roofline": roofline(r, dom),
         "step_roofline": step_bandwidth(r, ms_step),
         "kernels": per_kernel,
@@ -480,7 +484,8 @@ def main():
     log(f"{args.config}: {ms_step:.4f} ms/step")
     if args.also and args.also != args.config:
         r2 = run_workload(args.also, args.steps, args.warmup, args.sort_every, instrument=False,
-                          fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance)
+                          fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance,
+                     brick=args.brick)
         ms2 = r2["ms_total"] / args.steps
         out["also"] = {"workload": r2["spec"].name, "beads": r2["N"],
                        "value": r2["N"] * args.steps / (r2["ms_total"] * 1e-3),
@@ -491,7 +496,7 @@ def main():
     if args.field_interval > 1 and fused:
         r3 = run_workload(args.config, args.steps, args.warmup, args.sort_every, instrument=False,
                           fused=True, graph=not args.eager, halo=args.halo, advance=args.advance,
-                          field_every=args.field_interval, thermostat=args.thermostat)
+                          field_every=args.field_interval, thermostat=args.thermostat, brick=args.brick)
         out["field_interval"] = {"workload": r3["spec"].name, "field_every": args.field_interval,
                                  "thermostat_rate": args.thermostat,
                                  "value": r3["N"] * args.steps / (r3["ms_total"] * 1e-3),
@@ -505,7 +510,8 @@ def main():
     if args.c5_steps > 0:
         log(f"c5: building the 100M-bead system, {min(args.warmup, 5)} warm-up + {args.c5_steps} steps")
         r5 = run_workload("c5", args.c5_steps, min(args.warmup, 5), args.sort_every, instrument=True,
-                          fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance)
+                          fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance,
+                     brick=args.brick)
         ms5 = r5["ms_total"] / args.c5_steps
         out["c5"] = {"workload": r5["spec"].name, "beads": r5["N"], "species": r5["K"],
                      "mesh": [r5["spec"].M] * 3, "steps": args.c5_steps,

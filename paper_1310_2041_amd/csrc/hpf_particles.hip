@@ -747,6 +747,7 @@ __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float4* __res
 // kPipe selects the software-pipelined bead loop (bond tables of at most
 // kPreBonds rows); the plain loop serves wider tables.
 constexpr int kASThreadsDefault = 512;
+constexpr int kASThreadsWide = 768;
 
 template <bool kR0Zero, int kASThreads, bool kPipe, bool kThermo>
 __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __restrict__ R,
@@ -973,7 +974,7 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
-template <int kThreads, bool kPipe, bool kThermo>
+template <bool kR0Zero, int kThreads, bool kPipe, bool kThermo>
 static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float4* Vp, const uint8_t* T, int64_t N,
                                              const TileK& tk, int K, const float4* Gp, const int32_t* bonds, int D,
                                              float k, float r0, const BoxK& box, const float* inv_mass, float dt,
@@ -982,8 +983,7 @@ static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float
                                              double* kin_part, const ThermoK& th, hipStream_t s)
 {
     const size_t smem = sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P;
-    const void* fn = r0 == 0.0f ? reinterpret_cast<const void*>(k_advance_scatter<true, kThreads, kPipe, kThermo>)
-                                : reinterpret_cast<const void*>(k_advance_scatter<false, kThreads, kPipe, kThermo>);
+    const void* fn = reinterpret_cast<const void*>(k_advance_scatter<kR0Zero, kThreads, kPipe, kThermo>);
     if (smem > 65536 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
         return HPF_EINVAL;
@@ -991,14 +991,9 @@ static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float
     // uneven bricks; larger meshes walk their bricks with HPF_NPART workgroups
     const int64_t nb = std::min<int64_t>(tk.ntiles + 1, HPF_NPART);
     const dim3 g((unsigned)nb), bl(kThreads);
-    if (r0 == 0.0f)
-        hipLaunchKernelGGL((k_advance_scatter<true, kThreads, kPipe, kThermo>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp,
-                           bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part,
-                           th);
-    else
-        hipLaunchKernelGGL((k_advance_scatter<false, kThreads, kPipe, kThermo>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk, K, Gp,
-                           bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part,
-                           th);
+    hipLaunchKernelGGL((k_advance_scatter<kR0Zero, kThreads, kPipe, kThermo>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk,
+                       K, Gp, bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part,
+                       th);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
@@ -1015,11 +1010,29 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
     auto* Gp = reinterpret_cast<const float4*>(G);
     auto* Fo = reinterpret_cast<float4*>(F_out);
     // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
-    const bool pipe = D <= kPreBonds, thermo = th.thr != 0;
-    auto* launch = pipe ? (thermo ? launch_advance_scatter_t<kASThreadsDefault, true, true>
-                                  : launch_advance_scatter_t<kASThreadsDefault, true, false>)
-                        : (thermo ? launch_advance_scatter_t<kASThreadsDefault, false, true>
-                                  : launch_advance_scatter_t<kASThreadsDefault, false, false>);
+    const bool pipe = D <= kPreBonds, thermo = th.thr != 0, r0z = r0 == 0.0f;
+    // A deposit box of more than 80 KiB (16-cell bricks) leaves room for one workgroup per
+    // CU: with r0 = 0 and no thermostat the pass then takes 768 threads (3 waves per SIMD;
+    // 1024 threads would cap it at 128 VGPRs, which spills); the others keep 512.
+    const bool wide = r0z && !thermo && sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P > 80 * 1024;
+    using LaunchFn = hpf_status_t (*)(const float4*, float4*, float4*, const uint8_t*, int64_t, const TileK&, int,
+                                      const float4*, const int32_t*, int, float, float, const BoxK&, const float*,
+                                      float, const uint32_t*, unsigned long long*, unsigned long long*, float4*,
+                                      double*, double*, const ThermoK&, hipStream_t);
+    LaunchFn launch;
+    if (wide)
+        launch = pipe ? launch_advance_scatter_t<true, kASThreadsWide, true, false>
+                      : launch_advance_scatter_t<true, kASThreadsWide, false, false>;
+    else if (r0z)
+        launch = pipe ? (thermo ? launch_advance_scatter_t<true, kASThreadsDefault, true, true>
+                                : launch_advance_scatter_t<true, kASThreadsDefault, true, false>)
+                      : (thermo ? launch_advance_scatter_t<true, kASThreadsDefault, false, true>
+                                : launch_advance_scatter_t<true, kASThreadsDefault, false, false>);
+    else
+        launch = pipe ? (thermo ? launch_advance_scatter_t<false, kASThreadsDefault, true, true>
+                                : launch_advance_scatter_t<false, kASThreadsDefault, true, false>)
+                      : (thermo ? launch_advance_scatter_t<false, kASThreadsDefault, false, true>
+                                : launch_advance_scatter_t<false, kASThreadsDefault, false, false>);
     return launch(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo,
                   e_part, kin_part, th, s);
 }

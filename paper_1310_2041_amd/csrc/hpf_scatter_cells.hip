@@ -24,7 +24,7 @@
 namespace hpf {
 
 constexpr int kTcThreads = 256;
-constexpr int kTcMaxB = 8;
+constexpr int kTcMaxB = 16;
 constexpr int kTcMaxHalo = 2;
 constexpr int kStrayStage = 1024;   // strays a workgroup stages in LDS before appending
 

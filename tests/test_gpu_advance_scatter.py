@@ -41,6 +41,8 @@ CASES = [
                                             n_solvent=4000, seed=61), 4, 2),
     ("halo0", lambda: wl.small_system(300, 12, 16.0, 15, seed=62), 8, 0),
     ("b3", lambda: wl.small_system(200, 10, 12.0, 11, seed=63), 3, 1),
+    # 16-cell bricks: a 148 KiB deposit box, one 768-thread workgroup per CU
+    ("b16", lambda: wl.small_system(1500, 12, 26.1, (24, 23, 26), seed=64), 16, 2),
 ]
 
 
