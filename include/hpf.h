@@ -167,7 +167,7 @@ hpf_status_t hpf_density_scatter(const float* R, const uint8_t* T, int64_t N,
  *
  * cell_start  uint32[NK + 2] device, from the hpf_sort_by_cell call that
  *             produced the current storage order, with the same B.
- * B           brick edge 3..8 (0 selects 8); halo 0..2 cells, halo < B. Every
+ * B           brick edge 3..16 (0 selects 8); halo 0..2 cells, halo < B. Every
  *             M_d must be >= B + 1 + 2*halo, and K (B + 1 + 2 halo)^3 * 8 bytes
  *             must fit in 160 KiB of LDS (HPF_EINVAL otherwise).
  * counts      uint64[K][Mz][My][Mx] device, OVERWRITTEN (need not be zero).
