@@ -139,17 +139,18 @@ def replay_segments(st, one, steps, period, torch, engine, max_graphs=64):
         graphs.append(engine.Graph(lambda: [one() for _ in range(seg)]))
     # after capture the host state is one period ahead of the device (same buffers)
     base = st.snapshot()
+    # every segment replays on one stream, so that they run in order
+    stream = graphs[0].stream
     for g in graphs:                                 # untimed first replay of every segment
-        g.launch()
+        g.launch(stream)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     n = steps // seg
-    stream = graphs[0].stream
     wall0 = time.perf_counter()
     t0.record(stream)
     for j in range(n):
-        graphs[j % nseg].launch()
+        graphs[j % nseg].launch(stream)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0

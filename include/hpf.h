@@ -99,7 +99,7 @@ typedef struct hpf_field {
  * probability p and then takes a new velocity from the Maxwell distribution at
  * kT: v = sqrt(kT / m) (g0, g1, g2). The decision and the deviates come from the
  * counter-based generator Philox4x32-10 (Salmon et al., SC'11) with key `seed`
- * and counters (tag_i, n, 0) and (tag_i, n, 1): the bead collides when
+ * and counters (tag_i + tag_offset, n, 0) and (tag_i + tag_offset, n, 1): the bead collides when
  * (r0 >> 8) < floor(p 2^24); g0, g1 are the Box-Muller pair of the 24-bit
  * uniforms of r1 and r2 (((r1 >> 8) + 1) 2^-24 under the logarithm), g2 the
  * cosine deviate of r3 and of word 0 of the second counter. Draws therefore
@@ -111,6 +111,10 @@ typedef struct hpf_field {
  *        they run, so that a captured graph sees the value the caller has
  *        advanced in the meantime (the library never writes it).
  *  tag   DEVICE int32[N], the beads' tags in their current storage order.
+ *  tag_offset  added (mod 2^32) to every tag to form the generator's first
+ *        counter word. A batch of replicas numbers its tags globally, replica r
+ *        from its first bead on; a system run alone with tags 0..N_r-1 and
+ *        tag_offset = that first bead draws the same numbers as replica r.
  * A null thermostat pointer is no thermostat. Invalid values give HPF_EINVAL. */
 typedef struct hpf_thermostat {
     float p;
@@ -118,6 +122,7 @@ typedef struct hpf_thermostat {
     uint64_t seed;
     const int64_t* step;
     const int32_t* tag;
+    int64_t tag_offset;
 } hpf_thermostat_t;
 
 /* Library ABI version (HPF_ABI_VERSION). */

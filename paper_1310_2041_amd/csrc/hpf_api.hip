@@ -74,7 +74,7 @@ namespace hpf {
 
 static bool thermo_k(const hpf_thermostat_t* t, int64_t N, ThermoK* out)
 {
-    *out = ThermoK{0u, 0.0f, 0u, 0u, nullptr, nullptr};
+    *out = ThermoK{0u, 0.0f, 0u, 0u, nullptr, nullptr, 0u};
     if (!t || t->p == 0.0f)
         return true;
     if (!(t->p > 0.0f && t->p <= 1.0f) || !(t->kT > 0.0f) || !std::isfinite(t->kT) || !t->step ||
@@ -87,6 +87,7 @@ static bool thermo_k(const hpf_thermostat_t* t, int64_t N, ThermoK* out)
     out->key1 = (uint32_t)(t->seed >> 32);
     out->step = t->step;
     out->tag = t->tag;
+    out->tag_off = (uint32_t)t->tag_offset;
     return true;
 }
 

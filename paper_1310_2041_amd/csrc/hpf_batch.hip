@@ -754,7 +754,7 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
     const int nslot = (int)L.nslot;
     const bool fused = !prime && c.fuse_deposit;
     // the thermostat acts in every step after the start (time levels 1, 2, ... on the device)
-    ThermoK th{0u, 0.0f, 0u, 0u, nullptr, nullptr};
+    ThermoK th{0u, 0.0f, 0u, 0u, nullptr, nullptr, 0u};
     int64_t* tstep = b->at<int64_t>(L.off_tstep);
     if (!prime && c.thermo_p > 0.0f) {
         th.thr = c.thermo_p >= 1.0f ? (1u << 24) : (uint32_t)std::floor((double)c.thermo_p * 16777216.0);

@@ -17,6 +17,7 @@ struct ThermoK {
     uint32_t key0, key1;     // generator key (the seed)
     const int64_t* step;     // device: time level of the collisions
     const int32_t* tag;      // device: bead tags (the generator's per-bead counter word)
+    uint32_t tag_off;        // added to every tag in that counter word
 };
 
 // Ten Philox rounds: counter words 0 and 2 are multiplied by the round constants into
@@ -37,15 +38,15 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// The bead with tag `tag` at time level `step`: false if it does not collide; else true
-// with v.xyz replaced by sqrt(kT im) (g0, g1, g2), the three standard normal deviates of
+// The bead with tag `tag` (counter word tag + tag_off) at time level `step`: false if
+// it does not collide; else true with v.xyz replaced by sqrt(kT im) (g0, g1, g2), the three standard normal deviates of
 // two Box-Muller pairs on 24-bit uniforms (u = (r >> 8) 2^-24, shifted to (0, 1] where a
 // logarithm is taken): g0, g1 from words 1, 2 of counter (tag, step, 0) and g2 from its
 // word 3 and word 0 of counter (tag, step, 1).
 __device__ __forceinline__ bool andersen_collide(const ThermoK& th, uint64_t step, int32_t tag, float im,
                                                  float4& v)
 {
-    uint4 c = make_uint4((uint32_t)tag, (uint32_t)step, (uint32_t)(step >> 32), 0u);
+    uint4 c = make_uint4((uint32_t)tag + th.tag_off, (uint32_t)step, (uint32_t)(step >> 32), 0u);
     const uint4 r = philox4x32_10(c, th.key0, th.key1);
     if ((r.x >> 8) >= th.thr)
         return false;

@@ -63,6 +63,12 @@ class HpfState:
         if int(field_every) < 1:
             raise ValueError("field_every must be >= 1")
         self.field_every = int(field_every)
+        # The composition list leaves the gradient of an absent species stale at a mesh point.
+        # That is exact only when every bead gathers at the positions that built the counts
+        # (each corner it reaches with a non-zero weight then holds its own species), i.e. the
+        # field is rebuilt at every force evaluation and gathered with the deposit's weights.
+        if composition_list and (self.field_every != 1 or stencil != "centred"):
+            raise ValueError("composition_list needs field_every=1 and the centred stencil")
         self.density_pending = False   # partial boxes + counts hold the deposit of the current R
         # when True, the fused passes also store the total force at x_n into F (F_out)
         self.keep_force = False
@@ -115,26 +121,28 @@ class HpfState:
         self.energy = torch.zeros(8, dtype=torch.float64, device=dev)
         self.steps_done = 0
 
-    def set_thermostat(self, rate: float, kT: float | None = None, seed: int = 1):
+    def set_thermostat(self, rate: float, kT: float | None = None, seed: int = 1, tag_offset: int = 0):
         """NVT with the Andersen thermostat (Integration methods section): every step each bead
         collides with probability rate * dt and takes a Maxwell velocity at kT (the field's kT
         by default). The time level of the collisions lives on the device and advances with
-        every step, so graph replays draw fresh numbers. rate = 0 returns to NVE."""
+        every step, so graph replays draw fresh numbers. rate = 0 returns to NVE. tag_offset is
+        added to the tags in the generator's counter (a replica of a batch numbers its tags from
+        its first bead on)."""
         p = float(rate) * self.dt
         if p == 0.0:
             self.thermo = None
             return
         if not 0.0 < p <= 1.0:
             raise ValueError("rate * dt must lie in (0, 1]")
-        self.thermo = (p, float(self.field.kT if kT is None else kT), int(seed))
+        self.thermo = (p, float(self.field.kT if kT is None else kT), int(seed), int(tag_offset))
         self.tstep = torch.tensor([self.steps_done + 1], dtype=torch.int64, device=self.R.device)
 
     def thermostat(self):
         """The C thermostat description for the current storage order (None for NVE)."""
         if self.thermo is None:
             return None
-        p, kT, seed = self.thermo
-        return hpf.make_thermostat(p, kT, seed, self.tstep, self.tag)
+        p, kT, seed, tag_offset = self.thermo
+        return hpf.make_thermostat(p, kT, seed, self.tstep, self.tag, tag_offset)
 
     _SWAPPED = ("R", "R2", "Vel", "Vel2", "T", "T2", "tag", "tag2", "bonds", "bonds2")
 
@@ -503,8 +511,11 @@ class Graph:
             finally:
                 self.handle = hpf.hpf_graph_end(self.stream)
 
-    def launch(self):
-        hpf.hpf_graph_launch(self.handle, self.stream)
+    def launch(self, stream=None):
+        """Replay on this graph's own stream, or on `stream`. Replays of several graphs that
+        must run one after the other go to one stream: graphs replayed on different streams
+        are not ordered with respect to each other."""
+        hpf.hpf_graph_launch(self.handle, self.stream if stream is None else stream)
 
     def __del__(self):
         h = getattr(self, "handle", None)

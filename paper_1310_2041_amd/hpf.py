@@ -68,19 +68,20 @@ class BatchConfig(C.Structure):
 class Thermostat(C.Structure):
     """hpf_thermostat_t (step and tag are device pointers)"""
     _fields_ = [("p", C.c_float), ("kT", C.c_float), ("seed", C.c_uint64), ("step", C.c_void_p),
-                ("tag", C.c_void_p)]
+                ("tag", C.c_void_p), ("tag_offset", C.c_int64)]
 
 
-def make_thermostat(p: float, kT: float, seed: int, step, tag) -> Thermostat:
+def make_thermostat(p: float, kT: float, seed: int, step, tag, tag_offset: int = 0) -> Thermostat:
     """Andersen thermostat description: collision probability p per step, bath kT, generator
     key seed; step is a device int64 tensor of one element (the time level), tag the beads'
-    int32 tags in storage order."""
+    int32 tags in storage order; tag_offset is added to every tag in the generator's counter."""
     th = Thermostat()
     th.p = float(p)
     th.kT = float(kT)
     th.seed = int(seed)
     th.step = _dev(step, "step", torch.int64, (1,))
     th.tag = _dev(tag, "tag", torch.int32, None)
+    th.tag_offset = int(tag_offset)
     return th
 
 

@@ -306,3 +306,34 @@ def test_field_interval_fused_equals_six_calls_bitwise(n):
         for key in ("KE", "E_bond", "W"):
             assert eb[key] == pytest.approx(ea[key], rel=1e-12)
     assert hpf.hpf_get_device_status() == 0
+
+
+def test_graph_segments_replayed_in_order_match_eager():
+    """Two captured segments of three steps (each starting with a sort), replayed in turn on
+    one stream, move the beads as eager stepping does. Each segment flips the position and
+    velocity buffers, so only the pair returns them; the replays must run in order."""
+    import torch
+    s = wl.build(wl.SPECS["c1"])
+    a = engine.HpfState.from_system(s)
+    b = engine.HpfState.from_system(s)
+    for st in (a, b):
+        st.start(sort=True)
+        st.prime()
+    torch.cuda.synchronize()
+
+    def three():
+        for _ in range(3):
+            a.step_fused(report=False, sort=a.steps_done % 3 == 0)
+
+    segs = [engine.Graph(three), engine.Graph(three)]
+    stream = segs[0].stream
+    for _ in range(2):
+        for g in segs:
+            g.launch(stream)
+    torch.cuda.synchronize()
+    b.run_fused(12, report_every=0, sort_every=3)
+    torch.cuda.synchronize()
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
+    assert hpf.hpf_get_device_status() == 0
+    del segs

@@ -108,8 +108,9 @@ def test_thermostat_graph_replays_draw_fresh_numbers():
 
 
 def test_batch_thermostat_matches_single_systems():
-    """A batch with the thermostat moves every replica as its single-system run with the same
-    tags (the batch's tags are global: replica r's are offset by its first bead)."""
+    """A batch with the thermostat moves every replica as its single-system run. The batch's
+    tags are global (replica r's start at its first bead); the single system keeps the tags
+    0..N_r-1 that its sort needs and offsets them in the generator's counter instead."""
     specs = [(40, 10, 13.3, 13, 0.0), (150, 10, 17.1, 16, 0.7), (60, 20, 15.5, 14, 2.0)]
     systems = [wl.small_system(nc, cl, L, M, seed=200 + i, chi_ab=chi)
                for i, (nc, cl, L, M, chi) in enumerate(specs)]
@@ -118,15 +119,14 @@ def test_batch_thermostat_matches_single_systems():
     b.step(12, report_last=True)
     off = 0
     for r, s in enumerate(systems):
-        st = engine.HpfState(s.R, s.V, s.T, s.tag + off, s.bonds, s.L, s.M, s.K, s.kT, s.inv_kappa,
-                             s.chi, s.k_bond, s.r0, s.dt)
-        st.set_thermostat(4.0, seed=11)
+        st = engine.HpfState.from_system(s)
+        st.set_thermostat(4.0, seed=11, tag_offset=off)
         st.start(sort=True)
         st.prime()
         st.run_fused(12, report_every=0, sort_every=5)
         R, V, T, tag, bonds = st.host_beads()
         bR, bV, bT, btag, bbonds = b.replica_beads(r)
         assert np.array_equal(bR, R) and np.array_equal(bV, V)
-        assert np.array_equal(btag, tag - off)
+        assert np.array_equal(btag, tag)
         off += s.N
     assert hpf.hpf_get_device_status() == 0
