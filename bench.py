@@ -54,12 +54,12 @@ def algorithmic_bytes(name: str, N: int, K: int, nm: int, D: int) -> float:
 
 
 def layout_bytes(name: str, N: int, K: int, nm: int, D: int, P: int, nbricks: int) -> float:
-    """Bytes the kernel moves by its data layout: float4 bead rows (16 B for x, v and F),
-    the (x, y, z, V) gradient mesh (16 B per point and species), and the partial deposit
+    """Bytes the kernel moves by its data layout: 12-byte bead rows (x, v), the (x, y, z, V)
+    gradient mesh (16 B per point and species, read in place of V), and the partial deposit
     boxes of K P^3 uint64 per brick that the depositing pass writes and the finish reads."""
     box = 8.0 * K * P ** 3 * nbricks
     return {
-        "advance": (65.0 + 4.0 * D) * N + 16.0 * K * nm + box,
+        "advance": (49.0 + 4.0 * D) * N + 16.0 * K * nm + box,
         "finish_potential": 20.0 * K * nm + box,
         "field_gradient": 20.0 * K * nm,
     }.get(name)
@@ -292,9 +292,10 @@ def run_batched_sweep(replays=5, sort_every=10, tune=True):
 
 # rocprofv3 kernel names behind each timed call of the step
 ROCPROF_KERNELS = {
-    "advance": ["hpf::k_advance<%s, %s>" % (r0, pipe) for r0 in ("true", "false") for pipe in ("true", "false")] +
-               ["hpf::k_advance_scatter<%s, %d, %s>" % (r0, n, pipe) for r0 in ("true", "false") for n in (256, 512)
-                for pipe in ("true", "false")],
+    "advance": ["hpf::k_advance<%s, %s, %s>" % (r0, pipe, th) for r0 in ("true", "false")
+                for pipe in ("true", "false") for th in ("true", "false")] +
+               ["hpf::k_advance_scatter<%s, %d, %s, %s>" % (r0, n, pipe, th) for r0 in ("true", "false")
+                for n in (512, 768) for pipe in ("true", "false") for th in ("true", "false")],
     "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum<false>",
                         "hpf::k_scatter_strays"],
     "density_finish": ["hpf::k_scatter_sum<true>"],
@@ -406,7 +407,7 @@ def roofline(r, name):
             "layout_frac": None if lb is None else round(lb / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             "note": "achieved = minimal algorithmic bytes per launch / average launch time (HIP events "
                     "on the launch stream); layout_bytes = what this kernel's data layout moves "
-                    "(float4 bead rows, (x, y, z, V) gradient corners, partial deposit boxes); "
+                    "(12-byte bead rows, (x, y, z, V) gradient corners, partial deposit boxes); "
                     "traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, calibrated"}
 
 

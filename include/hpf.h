@@ -18,9 +18,9 @@
  *    Every call only enqueues work on it and returns; results are valid once
  *    the stream has reached that point.
  *  - Bead arrays are structure-of-arrays, one row per bead, in storage order
- *    i = 0..N-1: positions R, velocities Vel and forces F are float[N][4]
- *    with (x, y, z, w); w is written as 0 and otherwise ignored. Types T are
- *    uint8[N] in [0, K).
+ *    i = 0..N-1: positions R, velocities Vel and forces F are float[N][3]
+ *    (x, y, z; 12 bytes per bead, no padding). Types T are uint8[N] in
+ *    [0, K).
  *  - Mesh arrays are [K][Mz][My][Mx] with x fastest. A mesh point is a cell
  *    corner; the mesh is periodic, so there are as many points as cells.
  *  - Return value: HPF_OK, or a negative hpf_status_t for errors detected on
@@ -147,7 +147,7 @@ hpf_status_t hpf_mesh_make(const float* L, const int32_t* M, int64_t n_beads,
  * product W_a of its three 1-D weights; the eight W_a sum to 2^48.
  *   counts[T_i][c + a] += W_a        (uint64, exact, order independent)
  *
- * R       float[N][4] device; T uint8[N] device; N >= 0.
+ * R       float[N][3] device; T uint8[N] device; N >= 0.
  * mesh    host; K in [1, HPF_MAX_TYPES].
  * counts  uint64[K][Mz][My][Mx] device, ACCUMULATED into (zero it first, or
  *         let hpf_field_potential clear it after reading).
@@ -237,8 +237,8 @@ hpf_status_t hpf_field_gradient(const float* V, const hpf_mesh_t* mesh, int32_t 
  * Kernel 4, read as interpolation with the density-assignment weights):
  *   F_i = - sum_a (W_a(i) / 2^48) G_{T_i}(c_i + a)
  *
- * R float[N][4], T uint8[N], G float[K][M^3][4] device.
- * F float[N][4] device, OVERWRITTEN (w = 0). Skipped beads (see
+ * R float[N][3], T uint8[N], G float[K][M^3][4] device.
+ * F float[N][3] device, OVERWRITTEN. Skipped beads (see
  * hpf_density_scatter) get F = 0.
  * ------------------------------------------------------------------------- */
 hpf_status_t hpf_force_gather(const float* R, const uint8_t* T, int64_t N,
@@ -259,8 +259,8 @@ hpf_status_t hpf_force_gather(const float* R, const uint8_t* T, int64_t N,
  * the transpose of the density assignment, so it does not conserve momentum
  * exactly. It needs no gradient mesh.
  *
- * R float[N][4], T uint8[N], V float[K][M^3] device (hpf_field_potential).
- * F float[N][4] device, OVERWRITTEN (w = 0). Skipped beads (see
+ * R float[N][3], T uint8[N], V float[K][M^3] device (hpf_field_potential).
+ * F float[N][3] device, OVERWRITTEN. Skipped beads (see
  * hpf_density_scatter) get F = 0.
  * ------------------------------------------------------------------------- */
 hpf_status_t hpf_force_gather_staggered(const float* R, const uint8_t* T, int64_t N,
@@ -279,7 +279,7 @@ hpf_status_t hpf_force_gather_staggered(const float* R, const uint8_t* T, int64_
  *        D in [0, HPF_MAX_BONDS]. Entries outside [-1, N) are skipped and set
  *        HPF_FLAG_BAD_BOND.
  * box    host float[3], the periodic box edges.
- * F      float[N][4] device, ACCUMULATED into (x, y, z).
+ * F      float[N][3] device, ACCUMULATED into.
  * e_part nullable double[HPF_NPART] device: partial sums of the bond energy
  *        sum over bonds of k (r - r0)^2.
  * ------------------------------------------------------------------------- */
@@ -303,7 +303,7 @@ hpf_status_t bond_forces(const float* R, int64_t N, const int32_t* bonds, int32_
  * and form (0 or 1) are HOST arrays of ntypes entries. For the harmonic form
  * dU/dcos = -2k (theta - theta0) / sin(theta), sin(theta) floored at 1e-3 (the
  * direction of the force of an exactly straight triplet is undefined).
- * F float[N][4] device, ACCUMULATED into. e_part nullable double[HPF_NPART]:
+ * F float[N][3] device, ACCUMULATED into. e_part nullable double[HPF_NPART]:
  * partial sums of the angle energy, each angle once. Entries outside [-1, N) or
  * with a type >= ntypes are skipped and set HPF_FLAG_BAD_BOND.
  * ------------------------------------------------------------------------- */
@@ -328,7 +328,7 @@ hpf_status_t verlet_step(float* R, float* Vel, const float* F, const float* inv_
 
 /* hpf_andersen -- the Andersen collisions of time level *thermostat->step on
  * every bead (see hpf_thermostat_t), to be applied after verlet_step(half = 2).
- * Vel float[N][4] device, updated; inv_mass nullable float[N] (NULL = unit
+ * Vel float[N][3] device, updated; inv_mass nullable float[N] (NULL = unit
  * masses). kin_part nullable double[4][HPF_NPART]: partial sums of {KE, Px,
  * Py, Pz} after the collisions (as verlet_step's). thermostat must not be NULL. */
 hpf_status_t hpf_andersen(float* Vel, const float* inv_mass, int64_t N,
@@ -343,13 +343,13 @@ hpf_status_t hpf_andersen(float* Vel, const float* inv_mass, int64_t N,
  * half kick of step n (kinetic-energy and momentum partials at v_n) and the
  * first half kick and drift of step n + 1 (Integration methods section).
  *
- * R       float[N][4] device, x_n, read only (bond partners are read here).
- * R_next  float[N][4] device, receives x_{n+1} wrapped into the box; must not
+ * R       float[N][3] device, x_n, read only (bond partners are read here).
+ * R_next  float[N][3] device, receives x_{n+1} wrapped into the box; must not
  *         alias R.
- * Vel     float[N][4] device, v_{n-1/2} in, v_{n+1/2} out.
+ * Vel     float[N][3] device, v_{n-1/2} in, v_{n+1/2} out.
  * G       float[K][M^3][4] device, the gradient mesh of x_n.
  * bonds, D, k, r0, box, inv_mass, dt: as in bond_forces / verlet_step.
- * F_out   nullable float[N][4] device: receives the total force at x_n.
+ * F_out   nullable float[N][3] device: receives the total force at x_n.
  * e_part  nullable double[HPF_NPART]; kin_part nullable double[4][HPF_NPART]:
  *         as in bond_forces and verlet_step(half = 2).
  * thermostat  nullable: with it, the Andersen collisions of time level
@@ -522,7 +522,7 @@ typedef struct hpf_batch_config {
 } hpf_batch_config_t;
 
 typedef struct hpf_batch_buffers {
-    float* R[2];             /* float[N_total][4] each */
+    float* R[2];             /* float[N_total][3] each */
     float* Vel[2];
     uint8_t* T[2];
     int32_t* tag[2];

@@ -64,7 +64,7 @@ __device__ __forceinline__ TileK tile_of(const RepK& r, int B, int h)
 __global__ __launch_bounds__(kTcThreads) void k_batch_scatter_bricks(const RepK* __restrict__ reps,
                                                                      const ItemK* __restrict__ items,
                                                                      int B, int h, int K,
-                                                                     const float4* __restrict__ R,
+                                                                     const float3* __restrict__ R,
                                                                      const uint8_t* __restrict__ T,
                                                                      const uint32_t* __restrict__ cell_start,
                                                                      unsigned long long* __restrict__ partials,
@@ -114,7 +114,7 @@ struct RepKeyer {
     const RepK* reps;
     int nrep;
     int B;
-    const float4* R;
+    const float3* R;
     __device__ __forceinline__ uint32_t operator()(int32_t i) const
     {
         // Lanes of a wave nearly always hold beads of one replica: search once for the
@@ -132,7 +132,7 @@ struct RepKeyer {
 // Strays of all replicas (global indices in one list) and each replica's
 // beads that the sort could not bin, with global atomics.
 __global__ __launch_bounds__(kTcThreads) void k_batch_scatter_strays(const RepK* __restrict__ reps, int nrep,
-                                                                     int K, const float4* __restrict__ R,
+                                                                     int K, const float3* __restrict__ R,
                                                                      const uint8_t* __restrict__ T,
                                                                      const uint32_t* __restrict__ cell_start,
                                                                      const uint32_t* __restrict__ strays,
@@ -238,9 +238,9 @@ __global__ __launch_bounds__(256) void k_batch_gradient(const RepK* __restrict__
 template <bool kR0Zero, bool kThermo>
 __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restrict__ reps,
                                                              const ItemK* __restrict__ items, int K,
-                                                             const float4* __restrict__ R,
-                                                             float4* __restrict__ R_next,
-                                                             float4* __restrict__ Vel,
+                                                             const float3* __restrict__ R,
+                                                             float3* __restrict__ R_next,
+                                                             float3* __restrict__ Vel,
                                                              const uint8_t* __restrict__ T, int64_t Ntot,
                                                              const float4* __restrict__ G,
                                                              const int32_t* __restrict__ bonds, int D, float k,
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
 template <bool kR0Zero, bool kPipe, bool kThermo>
 __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
     const RepK* __restrict__ reps, const ItemK* __restrict__ items, int B, int h, int K,
-    const float4* __restrict__ R, float4* __restrict__ R_next, float4* __restrict__ Vel,
+    const float3* __restrict__ R, float3* __restrict__ R_next, float3* __restrict__ Vel,
     const uint8_t* __restrict__ T, int64_t Ntot, const float4* __restrict__ G, const int32_t* __restrict__ bonds,
     int D, float k, float r0, float dt, const uint32_t* __restrict__ cell_start,
     unsigned long long* __restrict__ partials, unsigned long long* __restrict__ counts,
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
                 bead_fetch<kThermo>(nxt, min(i + kASThreadsBatch, last - 1), R, Vel, T, bonds, D, Ntot, nullptr,
                                     th);
                 __builtin_amdgcn_sched_barrier(0);
-                const float4 rn = bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, Ntot, D, k, r0, rp.box, dt,
+                const float3 rn = bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, Ntot, D, k, r0, rp.box, dt,
                                                                 hdt,
                                                        nullptr, acc, e, bad_bead, bad_bond, nonfinite, th, tstep);
                 const int t = cur.t;
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
             }
         } else {
             for (int64_t i = first + threadIdx.x; i < last; i += kASThreadsBatch) {
-                const float4 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k,
+                const float3 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k,
                                                                  r0, rp.box, nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond,
                                                         nonfinite, th, tstep);
                 const int t = T[i];
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
     } else {
         const int64_t first = cs[rp.NK], last = min((int64_t)cs[rp.NK + 1], Ntot);
         for (int64_t i = first + threadIdx.x; i < last; i += kASThreadsBatch) {
-            const float4 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k, r0,
+            const float3 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, Ntot, m, K, Gr, bonds, D, k, r0,
                                                              rp.box,
                                                     nullptr, dt, hdt, nullptr, acc, e, bad_bead, bad_bond, nonfinite,
                                                     th, tstep);
@@ -444,9 +444,9 @@ __global__ void k_add_i64(int64_t* p, int64_t v) { *p += v; }
 template <bool kR0Zero>
 __global__ __launch_bounds__(kPThreads) void k_batch_prime(const RepK* __restrict__ reps,
                                                            const ItemK* __restrict__ items, int K,
-                                                           const float4* __restrict__ R,
-                                                           float4* __restrict__ R_next,
-                                                           float4* __restrict__ Vel,
+                                                           const float3* __restrict__ R,
+                                                           float3* __restrict__ R_next,
+                                                           float3* __restrict__ Vel,
                                                            const uint8_t* __restrict__ T, int64_t Ntot,
                                                            const float4* __restrict__ G,
                                                            const int32_t* __restrict__ bonds, int D, float k,
@@ -463,21 +463,21 @@ __global__ __launch_bounds__(kPThreads) void k_batch_prime(const RepK* __restric
     double e = 0.0;
     bool bad_bead = false, bad_bond = false, nonfinite = false;
     for (int64_t i = it.begin + threadIdx.x; i < it.end; i += kPThreads) {
-        float4 r = R[i];
+        float3 r = R[i];
         float3 ff;
         bad_bead |= !field_force(r, T[i], rp.m, K, Gr, ff);
         float ei;
         const float3 fb = bond_sum<kR0Zero>(i, r, R, Ntot, bonds, D, k, r0, rp.box, ei, bad_bond);
-        float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
+        float3 f = make_float3(ff.x, ff.y, ff.z);
         f.x += fb.x;
         f.y += fb.y;
         f.z += fb.z;
         e += 0.5 * (double)ei;
-        float4 v = Vel[i];
+        float3 v = Vel[i];
         acc.add(v, 1.0f);
         kick(v, f, 1.0f, hdt);
         drift(r, v, dt, rp.box);
-        nonfinite |= !(finite4(r) && finite4(v));
+        nonfinite |= !(finite3(r) && finite3(v));
         Vel[i] = v;
         R_next[i] = r;
     }
@@ -651,7 +651,7 @@ static hpf_status_t batch_sort(hpf_batch* b, hipStream_t s)
     const BatchLayout& L = b->L;
     const int o = b->scur, n = 1 - b->scur;
     RepKeyer keyer{b->at<RepK>(L.off_reps), b->nrep, b->cfg.brick,
-                   reinterpret_cast<const float4*>(b->buf.R[b->rcur])};
+                   reinterpret_cast<const float3*>(b->buf.R[b->rcur])};
     const hpf_status_t st =
         run_sort(L.sort, keyer, L.Ntot, b->buf.R[b->rcur], b->buf.Vel[o], b->buf.T[o], b->buf.tag[o],
                  b->cfg.D > 0 ? b->buf.bonds[o] : nullptr, b->cfg.D, b->buf.R[1 - b->rcur], b->buf.Vel[n],
@@ -693,7 +693,7 @@ static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)
     uint32_t* strays = b->at<uint32_t>(L.off_strays);
     auto* partials = b->at<unsigned long long>(L.off_partials);
     const uint32_t* cs = b->at<uint32_t>(L.off_start);
-    const auto* R = reinterpret_cast<const float4*>(b->buf.R[b->rcur]);
+    const auto* R = reinterpret_cast<const float3*>(b->buf.R[b->rcur]);
     const uint8_t* T = b->buf.T[b->scur];
     double* w = report ? b->at<double>(L.off_wpart) : nullptr;
     if (b->pending) {
@@ -743,9 +743,9 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
     const dim3 g((unsigned)b->n_bead_items), bl(kPThreads);
     const RepK* reps = b->at<RepK>(L.off_reps);
     const ItemK* items = b->at<ItemK>(L.off_bead_items);
-    const auto* R = reinterpret_cast<const float4*>(b->buf.R[b->rcur]);
-    auto* Rn = reinterpret_cast<float4*>(b->buf.R[1 - b->rcur]);
-    auto* Vel = reinterpret_cast<float4*>(b->buf.Vel[b->scur]);
+    const auto* R = reinterpret_cast<const float3*>(b->buf.R[b->rcur]);
+    auto* Rn = reinterpret_cast<float3*>(b->buf.R[1 - b->rcur]);
+    auto* Vel = reinterpret_cast<float3*>(b->buf.Vel[b->scur]);
     const uint8_t* T = b->buf.T[b->scur];
     const int32_t* bonds = c.D > 0 ? b->buf.bonds[b->scur] : nullptr;
     const auto* G = reinterpret_cast<const float4*>(b->buf.G);
@@ -768,7 +768,7 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
         const int P = c.brick + 1 + 2 * c.halo;
         const size_t smem = sizeof(unsigned long long) * (size_t)c.K * P * P * P;
         // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
-        using AdvFn = void (*)(const RepK*, const ItemK*, int, int, int, const float4*, float4*, float4*,
+        using AdvFn = void (*)(const RepK*, const ItemK*, int, int, int, const float3*, float3*, float3*,
                                const uint8_t*, int64_t, const float4*, const int32_t*, int, float, float, float,
                                const uint32_t*, unsigned long long*, unsigned long long*, double*, double*, int,
                                ThermoK);
@@ -803,7 +803,7 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
                 hipLaunchKernelGGL(k_batch_prime<false>, g, bl, 0, s, reps, items, c.K, R, Rn, Vel, T, L.Ntot, G,
                                    bonds, c.D, c.k_bond, c.r0, c.dt, e, kp, nslot);
         } else {
-            using BAdvFn = void (*)(const RepK*, const ItemK*, int, const float4*, float4*, float4*, const uint8_t*,
+            using BAdvFn = void (*)(const RepK*, const ItemK*, int, const float3*, float3*, float3*, const uint8_t*,
                                     int64_t, const float4*, const int32_t*, int, float, float, float, double*,
                                     double*, int, ThermoK);
             const BAdvFn fa = th.thr ? (c.r0 == 0.0f ? k_batch_advance<true, true> : k_batch_advance<false, true>)
@@ -1009,7 +1009,7 @@ hpf_status_t hpf_batch_density(hpf_batch_t* b, uint64_t* counts_out, void* strea
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
             return HPF_EINVAL;
         uint32_t* strays = b->at<uint32_t>(L.off_strays);
-        const auto* R = reinterpret_cast<const float4*>(b->buf.R[b->rcur]);
+        const auto* R = reinterpret_cast<const float3*>(b->buf.R[b->rcur]);
         const uint8_t* T = b->buf.T[b->scur];
         const uint32_t* cs = b->at<uint32_t>(L.off_start);
         hipLaunchKernelGGL(k_zero_u32_one, dim3(1), dim3(1), 0, s, strays);

@@ -59,7 +59,7 @@ struct BeadCell {
     uint32_t q[3];
 };
 
-__device__ __forceinline__ bool bead_cell(const float4& r, const MeshK& m, BeadCell& b)
+__device__ __forceinline__ bool bead_cell(const float3& r, const MeshK& m, BeadCell& b)
 {
     bool ok = cell_coord(r.x, m.s[0], m.M[0], b.c[0], b.q[0]);
     ok = cell_coord(r.y, m.s[1], m.M[1], b.c[1], b.q[1]) && ok;

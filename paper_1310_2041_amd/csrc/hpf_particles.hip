@@ -126,7 +126,7 @@ __device__ __forceinline__ void corners_global(const BeadCell& b, int t, const M
 
 // Field force on one bead (eq. 6). False (and zero force) for a bead that
 // cannot be binned or has a type >= K.
-__device__ __forceinline__ bool field_force(const float4& r, int t, const MeshK& m, int K,
+__device__ __forceinline__ bool field_force(const float3& r, int t, const MeshK& m, int K,
                                             const float4* __restrict__ G, float3& f)
 {
     BeadCell b;
@@ -148,7 +148,7 @@ __device__ __forceinline__ bool field_force(const float4& r, int t, const MeshK&
 // the potential of the bead's own species, so the chi sum of Kernel 4 is
 // already in it (eq. 6 is linear). False (and zero force) for a bead that
 // cannot be binned or has a type >= K.
-__device__ __forceinline__ bool field_force_staggered(const float4& r, int t, const MeshK& m, int K,
+__device__ __forceinline__ bool field_force_staggered(const float3& r, int t, const MeshK& m, int K,
                                                       const float* __restrict__ V, float3& f)
 {
     BeadCell b;
@@ -187,7 +187,7 @@ __device__ __forceinline__ bool field_force_staggered(const float4& r, int t, co
 // Sum of the harmonic bond forces on bead i over its table row, and its
 // bond energy k (r - r0)^2 summed over its bonds (FP32).
 template <bool kR0Zero>
-__device__ __forceinline__ float3 bond_sum(int64_t i, const float4& xi, const float4* __restrict__ R,
+__device__ __forceinline__ float3 bond_sum(int64_t i, const float3& xi, const float3* __restrict__ R,
                                            int64_t N, const int32_t* __restrict__ bonds, int D, float k,
                                            float r0, const BoxK& box, float& ei, bool& bad)
 {
@@ -202,7 +202,7 @@ __device__ __forceinline__ float3 bond_sum(int64_t i, const float4& xi, const fl
             bad = true;
             continue;
         }
-        const float4 xj = R[j];
+        const float3 xj = R[j];
         const float dx = min_image(xj.x, xi.x, box.L[0], box.halfL[0]);
         const float dy = min_image(xj.y, xi.y, box.L[1], box.halfL[1]);
         const float dz = min_image(xj.z, xi.z, box.L[2], box.halfL[2]);
@@ -224,30 +224,28 @@ __device__ __forceinline__ float3 bond_sum(int64_t i, const float4& xi, const fl
     return f;
 }
 
-__device__ __forceinline__ void kick(float4& v, const float4& f, float im, float hdt)
+__device__ __forceinline__ void kick(float3& v, const float3& f, float im, float hdt)
 {
     v.x += hdt * (f.x * im);
     v.y += hdt * (f.y * im);
     v.z += hdt * (f.z * im);
-    v.w = 0.0f;
 }
 
-__device__ __forceinline__ void drift(float4& r, const float4& v, float dt, const BoxK& box)
+__device__ __forceinline__ void drift(float3& r, const float3& v, float dt, const BoxK& box)
 {
     r.x = wrap_coord(r.x + dt * v.x, box.L[0]);
     r.y = wrap_coord(r.y + dt * v.y, box.L[1]);
     r.z = wrap_coord(r.z + dt * v.z, box.L[2]);
-    r.w = 0.0f;
 }
 
-__device__ __forceinline__ bool finite4(const float4& a)
+__device__ __forceinline__ bool finite3(const float3& a)
 {
     return isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
 }
 
 struct KinAcc {
     double ke = 0.0, px = 0.0, py = 0.0, pz = 0.0;
-    __device__ __forceinline__ void add(const float4& v, float im)
+    __device__ __forceinline__ void add(const float3& v, float im)
     {
         const double mass = 1.0 / (double)im;
         const double vx = v.x, vy = v.y, vz = v.z;
@@ -278,34 +276,34 @@ struct KinAcc {
 
 // ---------------------------------------------------------------- kernels --
 
-__global__ __launch_bounds__(kPThreads) void k_force_gather(const float4* __restrict__ R,
+__global__ __launch_bounds__(kPThreads) void k_force_gather(const float3* __restrict__ R,
                                                             const uint8_t* __restrict__ T,
                                                             int64_t N, MeshK m, int K,
                                                             const float4* __restrict__ G,
-                                                            float4* __restrict__ F)
+                                                            float3* __restrict__ F)
 {
     const BeadWalk w = bead_walk(N);
     bool bad = false;
     FOR_BEADS(w, i) {
         float3 f;
         bad |= !field_force(R[i], T[i], m, K, G, f);
-        F[i] = make_float4(f.x, f.y, f.z, 0.0f);
+        F[i] = make_float3(f.x, f.y, f.z);
     }
     if (bad)
         raise_flag(HPF_FLAG_BAD_BEAD);
 }
 
-__global__ __launch_bounds__(kPThreads) void k_force_gather_staggered(const float4* __restrict__ R,
+__global__ __launch_bounds__(kPThreads) void k_force_gather_staggered(const float3* __restrict__ R,
                                                                       const uint8_t* __restrict__ T, int64_t N,
                                                                       MeshK m, int K, const float* __restrict__ V,
-                                                                      float4* __restrict__ F)
+                                                                      float3* __restrict__ F)
 {
     const BeadWalk w = bead_walk(N);
     bool bad = false;
     FOR_BEADS(w, i) {
         float3 f;
         bad |= !field_force_staggered(R[i], T[i], m, K, V, f);
-        F[i] = make_float4(f.x, f.y, f.z, 0.0f);
+        F[i] = make_float3(f.x, f.y, f.z);
     }
     if (bad)
         raise_flag(HPF_FLAG_BAD_BEAD);
@@ -328,7 +326,7 @@ struct AngleK {
 // theta = atan2(|a x b|, a.b); dcos/dx_end1 = (b^ - c a^) / |a|,
 // dcos/dx_end2 = (a^ - c b^) / |b|, dcos/dx_mid = -(their sum). For the harmonic
 // form dU/dcos = -2k (theta - theta0) / sin(theta), sin(theta) floored at 1e-3.
-__device__ __forceinline__ float3 angle_sum(int64_t i, const float4& xi, const float4* __restrict__ R, int64_t N,
+__device__ __forceinline__ float3 angle_sum(int64_t i, const float3& xi, const float3* __restrict__ R, int64_t N,
                                             const int32_t* __restrict__ angles, int A, const AngleK& ak,
                                             const BoxK& box, double& ei, bool& bad)
 {
@@ -344,10 +342,10 @@ __device__ __forceinline__ float3 angle_sum(int64_t i, const float4& xi, const f
             bad = true;
             continue;
         }
-        const float4 xp = R[p], xq = R[q];
+        const float3 xp = R[p], xq = R[q];
         // the middle bead and the two ends
-        const float4 xm = role ? xi : xp;
-        const float4 x1 = role ? xp : xi;
+        const float3 xm = role ? xi : xp;
+        const float3 x1 = role ? xp : xi;
         float a[3], b[3];
         a[0] = min_image(x1.x, xm.x, box.L[0], box.halfL[0]);
         a[1] = min_image(x1.y, xm.y, box.L[1], box.halfL[1]);
@@ -388,9 +386,9 @@ __device__ __forceinline__ float3 angle_sum(int64_t i, const float4& xi, const f
 }
 
 // F_i += the angle forces on bead i; optional FP64 energy partials.
-__global__ __launch_bounds__(kPThreads) void k_angle_forces(const float4* __restrict__ R, int64_t N,
+__global__ __launch_bounds__(kPThreads) void k_angle_forces(const float3* __restrict__ R, int64_t N,
                                                             const int32_t* __restrict__ angles, int A, AngleK ak,
-                                                            BoxK box, float4* __restrict__ F,
+                                                            BoxK box, float3* __restrict__ F,
                                                             double* __restrict__ e_part)
 {
     __shared__ double scratch[kPThreads / kWave];
@@ -400,7 +398,7 @@ __global__ __launch_bounds__(kPThreads) void k_angle_forces(const float4* __rest
     bool bad = false;
     FOR_BEADS(w, i) {
         const float3 fa = angle_sum(i, R[i], R, N, angles, A, ak, box, e, bad);
-        float4 f = F[i];
+        float3 f = F[i];
         f.x += fa.x;
         f.y += fa.y;
         f.z += fa.z;
@@ -418,10 +416,10 @@ __global__ __launch_bounds__(kPThreads) void k_angle_forces(const float4* __rest
 // F_i += sum_j 2k (r - r0) d / r over the bead's own table row; E partials
 // accumulate k (r - r0)^2 / 2 per bond end (each bond is seen from both ends).
 template <bool kR0Zero>
-__global__ __launch_bounds__(kPThreads) void k_bond_forces(const float4* __restrict__ R, int64_t N,
+__global__ __launch_bounds__(kPThreads) void k_bond_forces(const float3* __restrict__ R, int64_t N,
                                                            const int32_t* __restrict__ bonds, int D,
                                                            float k, float r0, BoxK box,
-                                                           float4* __restrict__ F,
+                                                           float3* __restrict__ F,
                                                            double* __restrict__ e_part)
 {
     __shared__ double scratch[kPThreads / kWave];
@@ -430,10 +428,10 @@ __global__ __launch_bounds__(kPThreads) void k_bond_forces(const float4* __restr
     double e = 0.0;
     bool bad = false;
     FOR_BEADS(w, i) {
-        const float4 xi = R[i];
+        const float3 xi = R[i];
         float ei;
         const float3 fb = bond_sum<kR0Zero>(i, xi, R, N, bonds, D, k, r0, box, ei, bad);
-        float4 f = F[i];
+        float3 f = F[i];
         f.x += fb.x;
         f.y += fb.y;
         f.z += fb.z;
@@ -449,9 +447,9 @@ __global__ __launch_bounds__(kPThreads) void k_bond_forces(const float4* __restr
     }
 }
 
-__global__ __launch_bounds__(kPThreads) void k_verlet_half1(float4* __restrict__ R,
-                                                            float4* __restrict__ Vel,
-                                                            const float4* __restrict__ F,
+__global__ __launch_bounds__(kPThreads) void k_verlet_half1(float3* __restrict__ R,
+                                                            float3* __restrict__ Vel,
+                                                            const float3* __restrict__ F,
                                                             const float* __restrict__ inv_mass,
                                                             int64_t N, float dt, BoxK box)
 {
@@ -460,11 +458,11 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half1(float4* __restrict__
     bool bad = false;
     FOR_BEADS(w, i) {
         const float im = inv_mass ? inv_mass[i] : 1.0f;
-        float4 v = Vel[i];
-        float4 r = R[i];
+        float3 v = Vel[i];
+        float3 r = R[i];
         kick(v, F[i], im, hdt);
         drift(r, v, dt, box);
-        bad |= !(finite4(r) && finite4(v));
+        bad |= !(finite3(r) && finite3(v));
         Vel[i] = v;
         R[i] = r;
     }
@@ -472,8 +470,8 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half1(float4* __restrict__
         raise_flag(HPF_FLAG_NONFINITE);
 }
 
-__global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__ Vel,
-                                                            const float4* __restrict__ F,
+__global__ __launch_bounds__(kPThreads) void k_verlet_half2(float3* __restrict__ Vel,
+                                                            const float3* __restrict__ F,
                                                             const float* __restrict__ inv_mass,
                                                             int64_t N, float dt,
                                                             double* __restrict__ kin_part)
@@ -486,9 +484,9 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__
     bool bad = false;
     FOR_BEADS(w, i) {
         const float im = inv_mass ? inv_mass[i] : 1.0f;
-        float4 v = Vel[i];
+        float3 v = Vel[i];
         kick(v, F[i], im, hdt);
-        bad |= !finite4(v);
+        bad |= !finite3(v);
         Vel[i] = v;
         acc.add(v, im);
     }
@@ -503,21 +501,21 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half2(float4* __restrict__
 // of step n + 1, written to R_next. With kThermo the Andersen collisions of th act
 // on v_n (a separate instantiation, so the NVE passes keep their register budget).
 template <bool kR0Zero, bool kThermo>
-__device__ __forceinline__ float4 advance_bead(int64_t i, const float4* __restrict__ R, float4* __restrict__ R_next,
-                                             float4* __restrict__ Vel, const uint8_t* __restrict__ T,
+__device__ __forceinline__ float3 advance_bead(int64_t i, const float3* __restrict__ R, float3* __restrict__ R_next,
+                                             float3* __restrict__ Vel, const uint8_t* __restrict__ T,
                                              int64_t N, const MeshK& m, int K, const float4* __restrict__ G,
                                              const int32_t* __restrict__ bonds, int D, float k, float r0,
                                              const BoxK& box, const float* __restrict__ inv_mass, float dt,
-                                             float hdt, float4* __restrict__ F_out, KinAcc& acc, double& e,
+                                             float hdt, float3* __restrict__ F_out, KinAcc& acc, double& e,
                                              bool& bad_bead, bool& bad_bond, bool& nonfinite,
                                              const ThermoK& th, uint64_t tstep)
 {
-    float4 r = R[i];
+    float3 r = R[i];
     float3 ff;
     bad_bead |= !field_force(r, T[i], m, K, G, ff);
     float ei;
     const float3 fb = bond_sum<kR0Zero>(i, r, R, N, bonds, D, k, r0, box, ei, bad_bond);
-    float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
+    float3 f = make_float3(ff.x, ff.y, ff.z);
     f.x += fb.x;
     f.y += fb.y;
     f.z += fb.z;
@@ -525,14 +523,14 @@ __device__ __forceinline__ float4 advance_bead(int64_t i, const float4* __restri
     if (F_out)
         F_out[i] = f;
     const float im = inv_mass ? inv_mass[i] : 1.0f;
-    float4 v = Vel[i];
+    float3 v = Vel[i];
     kick(v, f, im, hdt);                 // v_n
     if (kThermo && th.thr)
         andersen_collide(th, tstep, th.tag[i], im, v);
     acc.add(v, im);
     kick(v, f, im, hdt);                 // v_{n+1/2}
     drift(r, v, dt, box);                // x_{n+1}
-    nonfinite |= !(finite4(r) && finite4(v));
+    nonfinite |= !(finite3(r) && finite3(v));
     Vel[i] = v;
     R_next[i] = r;
     return r;
@@ -548,7 +546,7 @@ __device__ __forceinline__ float4 advance_bead(int64_t i, const float4* __restri
 constexpr int kPreBonds = 2;
 
 struct BeadIn {
-    float4 r, v;
+    float3 r, v;
     float im;
     int t;
     int32_t tag;
@@ -556,8 +554,8 @@ struct BeadIn {
 };
 
 template <bool kThermo>
-__device__ __forceinline__ void bead_fetch(BeadIn& p, int64_t i, const float4* __restrict__ R,
-                                           const float4* __restrict__ Vel, const uint8_t* __restrict__ T,
+__device__ __forceinline__ void bead_fetch(BeadIn& p, int64_t i, const float3* __restrict__ R,
+                                           const float3* __restrict__ Vel, const uint8_t* __restrict__ T,
                                            const int32_t* __restrict__ bonds, int D, int64_t N,
                                            const float* __restrict__ inv_mass, const ThermoK& th)
 {
@@ -573,7 +571,7 @@ __device__ __forceinline__ void bead_fetch(BeadIn& p, int64_t i, const float4* _
 
 struct BeadLoads {
     float4 g[8];
-    float4 xj[kPreBonds];
+    float3 xj[kPreBonds];
     BeadCell b;
     bool ok;
 };
@@ -582,7 +580,7 @@ struct BeadLoads {
 // corners of cell 0 and gets no field force) and its partner loads (an index
 // outside [0, N) loads the bead itself; the bond is then skipped or flagged).
 __device__ __forceinline__ void bead_issue(BeadLoads& L, const BeadIn& p, int64_t i, const MeshK& m, int K,
-                                           const float4* __restrict__ G, const float4* __restrict__ R, int64_t N)
+                                           const float4* __restrict__ G, const float3* __restrict__ R, int64_t N)
 {
     L.ok = bead_cell(p.r, m, L.b) && p.t < K;
     BeadCell c = L.b;
@@ -597,13 +595,13 @@ __device__ __forceinline__ void bead_issue(BeadLoads& L, const BeadIn& p, int64_
 }
 
 template <bool kR0Zero, bool kThermo>
-__device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const BeadLoads& L,
-                                              float4* __restrict__ R_next, float4* __restrict__ Vel, int64_t N,
+__device__ __forceinline__ float3 bead_finish(int64_t i, const BeadIn& p, const BeadLoads& L,
+                                              float3* __restrict__ R_next, float3* __restrict__ Vel, int64_t N,
                                               int D, float k, float r0, const BoxK& box, float dt, float hdt,
-                                              float4* __restrict__ F_out, KinAcc& acc, double& e, bool& bad_bead,
+                                              float3* __restrict__ F_out, KinAcc& acc, double& e, bool& bad_bead,
                                               bool& bad_bond, bool& nonfinite, const ThermoK& th, uint64_t tstep)
 {
-    float4 r = p.r;
+    float3 r = p.r;
     float3 ff = make_float3(0.0f, 0.0f, 0.0f);
     if (L.ok)
         ff = interp8(L.b, L.g);
@@ -623,7 +621,7 @@ __device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const 
             bad_bond = true;
             continue;
         }
-        const float4 xj = L.xj[b];
+        const float3 xj = L.xj[b];
         const float dx = min_image(xj.x, r.x, box.L[0], box.halfL[0]);
         const float dy = min_image(xj.y, r.y, box.L[1], box.halfL[1]);
         const float dz = min_image(xj.z, r.z, box.L[2], box.halfL[2]);
@@ -642,21 +640,21 @@ __device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const 
         fb.y += coef * dy;
         fb.z += coef * dz;
     }
-    float4 f = make_float4(ff.x, ff.y, ff.z, 0.0f);
+    float3 f = make_float3(ff.x, ff.y, ff.z);
     f.x += fb.x;
     f.y += fb.y;
     f.z += fb.z;
     e += 0.5 * (double)ei;
     if (F_out)
         F_out[i] = f;
-    float4 v = p.v;
+    float3 v = p.v;
     kick(v, f, p.im, hdt);               // v_n
     if (kThermo && th.thr)
         andersen_collide(th, tstep, p.tag, p.im, v);
     acc.add(v, p.im);
     kick(v, f, p.im, hdt);               // v_{n+1/2}
     drift(r, v, dt, box);                // x_{n+1}
-    nonfinite |= !(finite4(r) && finite4(v));
+    nonfinite |= !(finite3(r) && finite3(v));
     Vel[i] = v;
     R_next[i] = r;
     return r;
@@ -669,15 +667,15 @@ __device__ __forceinline__ float4 bead_finish(int64_t i, const BeadIn& p, const 
 constexpr int kAdvPipeThreads = 512;
 
 template <bool kR0Zero, bool kPipe, bool kThermo>
-__global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float4* __restrict__ R,
-                                                       float4* __restrict__ R_next,
-                                                       float4* __restrict__ Vel,
+__global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float3* __restrict__ R,
+                                                       float3* __restrict__ R_next,
+                                                       float3* __restrict__ Vel,
                                                        const uint8_t* __restrict__ T, int64_t N,
                                                        MeshK m, int K, const float4* __restrict__ G,
                                                        const int32_t* __restrict__ bonds, int D,
                                                        float k, float r0, BoxK box,
                                                        const float* __restrict__ inv_mass, float dt,
-                                                       float4* __restrict__ F_out,
+                                                       float3* __restrict__ F_out,
                                                        double* __restrict__ e_part,
                                                        double* __restrict__ kin_part, ThermoK th)
 {
@@ -750,9 +748,9 @@ constexpr int kASThreadsDefault = 512;
 constexpr int kASThreadsWide = 768;
 
 template <bool kR0Zero, int kASThreads, bool kPipe, bool kThermo>
-__global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __restrict__ R,
-                                                                float4* __restrict__ R_next,
-                                                                float4* __restrict__ Vel,
+__global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float3* __restrict__ R,
+                                                                float3* __restrict__ R_next,
+                                                                float3* __restrict__ Vel,
                                                                 const uint8_t* __restrict__ T, int64_t N,
                                                                 TileK tk, int K, const float4* __restrict__ G,
                                                                 const int32_t* __restrict__ bonds, int D,
@@ -761,7 +759,7 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
                                                                 const uint32_t* __restrict__ cell_start,
                                                                 unsigned long long* __restrict__ partials,
                                                                 unsigned long long* __restrict__ counts,
-                                                                float4* __restrict__ F_out,
+                                                                float3* __restrict__ F_out,
                                                                 double* __restrict__ e_part,
                                                                 double* __restrict__ kin_part, ThermoK th)
 {
@@ -808,7 +806,7 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
                     BeadIn nxt;
                     bead_fetch<kThermo>(nxt, min(i + kASThreads, last - 1), R, Vel, T, bonds, D, N, inv_mass, th);
                     __builtin_amdgcn_sched_barrier(0);
-                    const float4 rn = bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt,
+                    const float3 rn = bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt,
                                                            F_out, acc, e, bad_bead, bad_bond, nonfinite, th,
                                                            tstep);
                     const int t = cur.t;
@@ -823,7 +821,7 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
                 }
             } else {
                 for (int64_t i = first + threadIdx.x; i < last; i += kASThreads) {
-                    const float4 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k,
+                    const float3 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k,
                                                             r0, box, inv_mass, dt, hdt, F_out, acc, e, bad_bead,
                                                             bad_bond, nonfinite, th, tstep);
                     const int t = T[i];
@@ -843,7 +841,7 @@ __global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float4* __
         } else {
             const int64_t first = cell_start[tk.NK];
             for (int64_t i = first + threadIdx.x; i < N; i += kASThreads) {
-                const float4 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0,
+                const float3 rn = advance_bead<kR0Zero, kThermo>(i, R, R_next, Vel, T, N, m, K, G, bonds, D, k, r0,
                                                         box, inv_mass, dt, hdt, F_out, acc, e, bad_bead, bad_bond,
                                                         nonfinite, th, tstep);
                 bad_bead |= !deposit_global(rn, T[i], K, m, counts);
@@ -881,8 +879,8 @@ hpf_status_t launch_force_gather(const float* R, const uint8_t* T, int64_t N, co
     if (N == 0)
         return HPF_OK;
     hipLaunchKernelGGL(k_force_gather, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads),
-                       0, s, reinterpret_cast<const float4*>(R), T, N, m, K,
-                       reinterpret_cast<const float4*>(G), reinterpret_cast<float4*>(F));
+                       0, s, reinterpret_cast<const float3*>(R), T, N, m, K,
+                       reinterpret_cast<const float4*>(G), reinterpret_cast<float3*>(F));
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
@@ -892,7 +890,7 @@ hpf_status_t launch_force_gather_staggered(const float* R, const uint8_t* T, int
     if (N == 0)
         return HPF_OK;
     hipLaunchKernelGGL(k_force_gather_staggered, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads), 0, s,
-                       reinterpret_cast<const float4*>(R), T, N, m, K, V, reinterpret_cast<float4*>(F));
+                       reinterpret_cast<const float3*>(R), T, N, m, K, V, reinterpret_cast<float3*>(F));
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
@@ -902,8 +900,8 @@ hpf_status_t launch_angle_forces(const float* R, int64_t N, const int32_t* angle
     if (N == 0 && !e_part)
         return HPF_OK;
     const int64_t nb = bead_blocks(N, e_part ? HPF_NPART : (1 << 20));
-    hipLaunchKernelGGL(k_angle_forces, dim3((unsigned)nb), dim3(kPThreads), 0, s, reinterpret_cast<const float4*>(R),
-                       N, angles, A, ak, box, reinterpret_cast<float4*>(F), e_part);
+    hipLaunchKernelGGL(k_angle_forces, dim3((unsigned)nb), dim3(kPThreads), 0, s, reinterpret_cast<const float3*>(R),
+                       N, angles, A, ak, box, reinterpret_cast<float3*>(F), e_part);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
@@ -914,8 +912,8 @@ hpf_status_t launch_bond_forces(const float* R, int64_t N, const int32_t* bonds,
         return HPF_OK;
     const int64_t nb = bead_blocks(N, e_part ? HPF_NPART : (1 << 20));
     const dim3 g((unsigned)nb), bl(kPThreads);
-    auto* Rp = reinterpret_cast<const float4*>(R);
-    auto* Fp = reinterpret_cast<float4*>(F);
+    auto* Rp = reinterpret_cast<const float3*>(R);
+    auto* Fp = reinterpret_cast<float3*>(F);
     if (r0 == 0.0f)
         hipLaunchKernelGGL(k_bond_forces<true>, g, bl, 0, s, Rp, N, bonds, D, k, r0, box, Fp, e_part);
     else
@@ -928,9 +926,9 @@ hpf_status_t launch_verlet(float* R, float* Vel, const float* F, const float* in
 {
     if (N == 0 && !(half == 2 && kin_part))
         return HPF_OK;
-    auto* Rp = reinterpret_cast<float4*>(R);
-    auto* Vp = reinterpret_cast<float4*>(Vel);
-    auto* Fp = reinterpret_cast<const float4*>(F);
+    auto* Rp = reinterpret_cast<float3*>(R);
+    auto* Vp = reinterpret_cast<float3*>(Vel);
+    auto* Fp = reinterpret_cast<const float3*>(F);
     if (half == 1) {
         hipLaunchKernelGGL(k_verlet_half1, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads),
                            0, s, Rp, Vp, Fp, inv_mass, N, dt, box);
@@ -955,13 +953,13 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
     const int64_t cap = (e_part || kin_part) ? HPF_NPART : (1 << 20);
     const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((N + threads - 1) / threads, cap));
     const dim3 g((unsigned)nb), bl(threads);
-    auto* Rp = reinterpret_cast<const float4*>(R);
-    auto* Rn = reinterpret_cast<float4*>(R_next);
-    auto* Vp = reinterpret_cast<float4*>(Vel);
+    auto* Rp = reinterpret_cast<const float3*>(R);
+    auto* Rn = reinterpret_cast<float3*>(R_next);
+    auto* Vp = reinterpret_cast<float3*>(Vel);
     auto* Gp = reinterpret_cast<const float4*>(G);
-    auto* Fo = reinterpret_cast<float4*>(F_out);
-    using AdvFn = void (*)(const float4*, float4*, float4*, const uint8_t*, int64_t, MeshK, int, const float4*,
-                           const int32_t*, int, float, float, BoxK, const float*, float, float4*, double*, double*,
+    auto* Fo = reinterpret_cast<float3*>(F_out);
+    using AdvFn = void (*)(const float3*, float3*, float3*, const uint8_t*, int64_t, MeshK, int, const float4*,
+                           const int32_t*, int, float, float, BoxK, const float*, float, float3*, double*, double*,
                            ThermoK);
     const bool thermo = th.thr != 0;
     const AdvFn fn =
@@ -975,11 +973,11 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
 }
 
 template <bool kR0Zero, int kThreads, bool kPipe, bool kThermo>
-static hpf_status_t launch_advance_scatter_t(const float4* Rp, float4* Rn, float4* Vp, const uint8_t* T, int64_t N,
+static hpf_status_t launch_advance_scatter_t(const float3* Rp, float3* Rn, float3* Vp, const uint8_t* T, int64_t N,
                                              const TileK& tk, int K, const float4* Gp, const int32_t* bonds, int D,
                                              float k, float r0, const BoxK& box, const float* inv_mass, float dt,
                                              const uint32_t* cell_start, unsigned long long* partials,
-                                             unsigned long long* counts, float4* Fo, double* e_part,
+                                             unsigned long long* counts, float3* Fo, double* e_part,
                                              double* kin_part, const ThermoK& th, hipStream_t s)
 {
     const size_t smem = sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P;
@@ -1004,20 +1002,20 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
                                     unsigned long long* counts, float* F_out, double* e_part, double* kin_part,
                                     const ThermoK& th, hipStream_t s)
 {
-    auto* Rp = reinterpret_cast<const float4*>(R);
-    auto* Rn = reinterpret_cast<float4*>(R_next);
-    auto* Vp = reinterpret_cast<float4*>(Vel);
+    auto* Rp = reinterpret_cast<const float3*>(R);
+    auto* Rn = reinterpret_cast<float3*>(R_next);
+    auto* Vp = reinterpret_cast<float3*>(Vel);
     auto* Gp = reinterpret_cast<const float4*>(G);
-    auto* Fo = reinterpret_cast<float4*>(F_out);
+    auto* Fo = reinterpret_cast<float3*>(F_out);
     // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
     const bool pipe = D <= kPreBonds, thermo = th.thr != 0, r0z = r0 == 0.0f;
     // A deposit box of more than 80 KiB (16-cell bricks) leaves room for one workgroup per
     // CU: with r0 = 0 and no thermostat the pass then takes 768 threads (3 waves per SIMD;
     // 1024 threads would cap it at 128 VGPRs, which spills); the others keep 512.
     const bool wide = r0z && !thermo && sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P > 80 * 1024;
-    using LaunchFn = hpf_status_t (*)(const float4*, float4*, float4*, const uint8_t*, int64_t, const TileK&, int,
+    using LaunchFn = hpf_status_t (*)(const float3*, float3*, float3*, const uint8_t*, int64_t, const TileK&, int,
                                       const float4*, const int32_t*, int, float, float, const BoxK&, const float*,
-                                      float, const uint32_t*, unsigned long long*, unsigned long long*, float4*,
+                                      float, const uint32_t*, unsigned long long*, unsigned long long*, float3*,
                                       double*, double*, const ThermoK&, hipStream_t);
     LaunchFn launch;
     if (wide)
@@ -1039,7 +1037,7 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
 
 // Andersen collisions of time level *th.step on every bead (after the second half
 // kick), and optionally the kinetic-energy and momentum partials of the result.
-__global__ __launch_bounds__(kPThreads) void k_andersen(float4* __restrict__ Vel, const float* __restrict__ inv_mass,
+__global__ __launch_bounds__(kPThreads) void k_andersen(float3* __restrict__ Vel, const float* __restrict__ inv_mass,
                                                         int64_t N, ThermoK th, double* __restrict__ kin_part)
 {
     __shared__ double scratch[kPThreads / kWave];
@@ -1049,7 +1047,7 @@ __global__ __launch_bounds__(kPThreads) void k_andersen(float4* __restrict__ Vel
     KinAcc acc;
     FOR_BEADS(w, i) {
         const float im = inv_mass ? inv_mass[i] : 1.0f;
-        float4 v = Vel[i];
+        float3 v = Vel[i];
         if (th.thr && andersen_collide(th, tstep, th.tag[i], im, v))
             Vel[i] = v;
         acc.add(v, im);
@@ -1064,7 +1062,7 @@ hpf_status_t launch_andersen(float* Vel, const float* inv_mass, int64_t N, const
     if (N == 0 && !kin_part)
         return HPF_OK;
     const int64_t nb = bead_blocks(N, kin_part ? HPF_NPART : (1 << 20));
-    hipLaunchKernelGGL(k_andersen, dim3((unsigned)nb), dim3(kPThreads), 0, s, reinterpret_cast<float4*>(Vel),
+    hipLaunchKernelGGL(k_andersen, dim3((unsigned)nb), dim3(kPThreads), 0, s, reinterpret_cast<float3*>(Vel),
                        inv_mass, N, th, kin_part);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }

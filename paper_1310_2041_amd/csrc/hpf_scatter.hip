@@ -31,7 +31,7 @@ __device__ __forceinline__ void atomic_add_lds_u64(unsigned long long* p, unsign
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__global__ __launch_bounds__(kScThreads) void k_density_scatter(const float4* __restrict__ R,
+__global__ __launch_bounds__(kScThreads) void k_density_scatter(const float3* __restrict__ R,
                                                                 const uint8_t* __restrict__ T,
                                                                 int64_t N, MeshK m, int K,
                                                                 unsigned long long* __restrict__ counts)
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kScThreads) void k_density_scatter(const float4* __
         const int64_t i = base + (int64_t)j * kScThreads + tid;
         ty[j] = -1;
         if (i < N) {
-            const float4 r = R[i];
+            const float3 r = R[i];
             const int t = T[i];
             BeadCell b;
             if (bead_cell(r, m, b) && t < K) {
@@ -222,7 +222,7 @@ hpf_status_t launch_density_scatter(const float* R, const uint8_t* T, int64_t N,
     if (nb > 0x7fffffff)
         return HPF_EINVAL;
     hipLaunchKernelGGL(k_density_scatter, dim3((unsigned)nb), dim3(kScThreads), 0, s,
-                       reinterpret_cast<const float4*>(R), T, N, m, K,
+                       reinterpret_cast<const float3*>(R), T, N, m, K,
                        reinterpret_cast<unsigned long long*>(counts));
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }

@@ -116,7 +116,7 @@ constexpr int kScBatch = 4;
 
 // Deposit of the beads listed in `brick` (cell_start of this system, i.e.
 // already offset for batched systems) into an LDS box, stored to `out`.
-__device__ __forceinline__ void scatter_brick_body(const float4* __restrict__ R, const uint8_t* __restrict__ T,
+__device__ __forceinline__ void scatter_brick_body(const float3* __restrict__ R, const uint8_t* __restrict__ T,
                                                    int K, const TileK& tk,
                                                    const uint32_t* __restrict__ cell_start, int64_t brick,
                                                    unsigned long long* __restrict__ out,
@@ -144,7 +144,7 @@ __device__ __forceinline__ void scatter_brick_body(const float4* __restrict__ R,
     const uint32_t first = cell_start[brick];
     const uint32_t last = cell_start[brick + 1];
     for (uint32_t j0 = first; j0 < last; j0 += kTcThreads * kScBatch) {
-        float4 rj[kScBatch];
+        float3 rj[kScBatch];
         int tj[kScBatch];
         const uint32_t jb = j0 + tid * kScBatch;
 #pragma unroll
@@ -186,7 +186,7 @@ __device__ __forceinline__ void scatter_brick_body(const float4* __restrict__ R,
         out[e] = box[e];
 }
 
-__global__ __launch_bounds__(kTcThreads) void k_scatter_bricks(const float4* __restrict__ R,
+__global__ __launch_bounds__(kTcThreads) void k_scatter_bricks(const float3* __restrict__ R,
                                                                const uint8_t* __restrict__ T, int K,
                                                                TileK tk,
                                                                const uint32_t* __restrict__ cell_start,
@@ -410,7 +410,7 @@ __device__ __forceinline__ void atomic_add_u64_agent(unsigned long long* p, unsi
 }
 
 // Eight global u64 atomics of one bead; false if it cannot be binned.
-__device__ __forceinline__ bool deposit_global(const float4& r, int t, int K, const MeshK& m,
+__device__ __forceinline__ bool deposit_global(const float3& r, int t, int K, const MeshK& m,
                                                unsigned long long* __restrict__ counts)
 {
     BeadCell b;
@@ -440,7 +440,7 @@ __device__ __forceinline__ bool deposit_global(const float4& r, int t, int K, co
 
 // Global-atomic deposit of the stray beads and of the beads the sort could not
 // bin (storage indices [cell_start[NK], N)).
-__global__ __launch_bounds__(kTcThreads) void k_scatter_strays(const float4* __restrict__ R,
+__global__ __launch_bounds__(kTcThreads) void k_scatter_strays(const float3* __restrict__ R,
                                                                const uint8_t* __restrict__ T, int64_t N,
                                                                int K, MeshK m, uint32_t NK,
                                                                const uint32_t* __restrict__ cell_start,
@@ -477,7 +477,7 @@ hpf_status_t launch_scatter_cells(const float* R, const uint8_t* T, int64_t N, c
                                   unsigned long long* partials, hipStream_t s)
 {
     auto* c = reinterpret_cast<unsigned long long*>(counts);
-    auto* Rp = reinterpret_cast<const float4*>(R);
+    auto* Rp = reinterpret_cast<const float3*>(R);
     const size_t smem = scatter_cells_smem(K, tk.P);
     if (smem > 65536) {
         // gfx950 has 160 KiB of LDS per CU; opt in above the 64 KiB default

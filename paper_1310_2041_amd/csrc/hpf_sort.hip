@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tag_index(const int32_t* __res
 // Sort key of bead i of one system.
 struct CellKeyer {
     SortK sk;
-    const float4* R;
+    const float3* R;
     __device__ __forceinline__ uint32_t operator()(int32_t i) const
     {
         BeadCell b;
@@ -293,12 +293,12 @@ __global__ __launch_bounds__(kSortThreads) void k_iota(int32_t* __restrict__ p, 
 // ------------------------------------------------ gather and bond table --
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_permute(const int32_t* __restrict__ perm, int64_t N,
-                                                               const float4* __restrict__ R_in,
-                                                               const float4* __restrict__ V_in,
+                                                               const float3* __restrict__ R_in,
+                                                               const float3* __restrict__ V_in,
                                                                const uint8_t* __restrict__ T_in,
                                                                const int32_t* __restrict__ tag_in,
-                                                               float4* __restrict__ R_out,
-                                                               float4* __restrict__ V_out,
+                                                               float3* __restrict__ R_out,
+                                                               float3* __restrict__ V_out,
                                                                uint8_t* __restrict__ T_out,
                                                                int32_t* __restrict__ tag_out,
                                                                int32_t* __restrict__ inv)
@@ -484,8 +484,8 @@ hpf_status_t run_sort(const SortPlan& pl, Keyer keyer, int64_t N, const float* R
         hipLaunchKernelGGL(k_sort_place, dim3((unsigned)pl.nchunks), dim3(kChunkThreads), smem, s, key_t, idx, N,
                            pl.S, nk, table, perm);
         hipLaunchKernelGGL(k_sort_permute, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, N,
-                           reinterpret_cast<const float4*>(R_in), reinterpret_cast<const float4*>(V_in), T_in,
-                           tag_in, reinterpret_cast<float4*>(R_out), reinterpret_cast<float4*>(V_out), T_out,
+                           reinterpret_cast<const float3*>(R_in), reinterpret_cast<const float3*>(V_in), T_in,
+                           tag_in, reinterpret_cast<float3*>(R_out), reinterpret_cast<float3*>(V_out), T_out,
                            tag_out, idx);
         if (D > 0 && bonds_in)
             hipLaunchKernelGGL(k_sort_bonds, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, idx, N, bonds_in,
@@ -499,7 +499,7 @@ hpf_status_t launch_sort(const SortK& sk, const SortPlan& pl, int64_t N, const f
                          float* V_out, uint8_t* T_out, int32_t* tag_out, int32_t* bonds_out, uint32_t* cell_start,
                          char* work, hipStream_t s)
 {
-    CellKeyer keyer{sk, reinterpret_cast<const float4*>(R_in)};
+    CellKeyer keyer{sk, reinterpret_cast<const float3*>(R_in)};
     uint32_t* start = cell_start ? cell_start : reinterpret_cast<uint32_t*>(work + pl.off_start);
     return run_sort(pl, keyer, N, R_in, V_in, T_in, tag_in, bonds_in, D, R_out, V_out, T_out, tag_out, bonds_out,
                     start, work, s);

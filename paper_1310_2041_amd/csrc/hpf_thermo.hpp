@@ -44,7 +44,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // logarithm is taken): g0, g1 from words 1, 2 of counter (tag, step, 0) and g2 from its
 // word 3 and word 0 of counter (tag, step, 1).
 __device__ __forceinline__ bool andersen_collide(const ThermoK& th, uint64_t step, int32_t tag, float im,
-                                                 float4& v)
+                                                 float3& v)
 {
     uint4 c = make_uint4((uint32_t)tag + th.tag_off, (uint32_t)step, (uint32_t)(step >> 32), 0u);
     const uint4 r = philox4x32_10(c, th.key0, th.key1);
@@ -65,7 +65,6 @@ __device__ __forceinline__ bool andersen_collide(const ThermoK& th, uint64_t ste
     v.x = sd * (rad1 * c1);
     v.y = sd * (rad1 * s1);
     v.z = sd * (rad2 * cosf(two_pi * u4));
-    v.w = 0.0f;
     return true;
 }
 

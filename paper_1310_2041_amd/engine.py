@@ -82,13 +82,14 @@ class HpfState:
         def up(a, dtype):
             return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dtype).contiguous()
 
-        self.R = up(R, torch.float32)
-        self.Vel = up(Vel, torch.float32)
+        # bead rows are (x, y, z), 12 bytes; (N, 4) host arrays give their first three columns
+        self.R = up(np.asarray(R)[:, :3], torch.float32)
+        self.Vel = up(np.asarray(Vel)[:, :3], torch.float32)
         self.T = up(T, torch.uint8)
         self.tag = up(tag, torch.int32)
         self.bonds = up(bonds, torch.int32) if bonds is not None and len(bonds) else \
             torch.zeros((0, self.N), dtype=torch.int32, device=dev)
-        self.F = torch.zeros((self.N, 4), dtype=torch.float32, device=dev)
+        self.F = torch.zeros((self.N, 3), dtype=torch.float32, device=dev)
         # angles (Bonded forces section): per-bead table [3A, N] and per-type parameters; the
         # six-call step evaluates them (the fused passes take bonds only)
         self.angles = up(angles, torch.int32) if angles is not None and len(angles) else None
@@ -396,8 +397,8 @@ class BatchState:
         def up(a, dtype):
             return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dtype).contiguous()
 
-        self.R = [up(R, torch.float32), torch.empty((self.Ntot, 4), dtype=torch.float32, device=dev)]
-        self.Vel = [up(V, torch.float32), torch.empty((self.Ntot, 4), dtype=torch.float32, device=dev)]
+        self.R = [up(R[:, :3], torch.float32), torch.empty((self.Ntot, 3), dtype=torch.float32, device=dev)]
+        self.Vel = [up(V[:, :3], torch.float32), torch.empty((self.Ntot, 3), dtype=torch.float32, device=dev)]
         self.T = [up(T, torch.uint8), torch.empty(self.Ntot, dtype=torch.uint8, device=dev)]
         self.tag = [up(tag, torch.int32), torch.empty(self.Ntot, dtype=torch.int32, device=dev)]
         self.bonds = [up(bonds, torch.int32), torch.empty_like(up(bonds, torch.int32))]

@@ -241,7 +241,7 @@ def _box(mesh_or_box):
 
 def hpf_density_scatter(R, T, mesh: Mesh, K: int, counts, stream=None):
     N = R.shape[0]
-    r = _dev(R, "R", torch.float32, (N, 4))
+    r = _dev(R, "R", torch.float32, (N, 3))
     t = _dev(T, "T", torch.uint8, (N,))
     c = _dev(counts, "counts", _U64, (K, _nm(mesh)))
     _check("hpf_density_scatter",
@@ -256,7 +256,7 @@ def hpf_scatter_workspace_bytes(N: int, mesh: Mesh, K: int, B: int = 8, halo: in
 def hpf_density_scatter_cells(R, T, mesh: Mesh, K: int, cell_start, B: int, halo: int, counts, work,
                               stream=None):
     N = R.shape[0]
-    r = _dev(R, "R", torch.float32, (N, 4))
+    r = _dev(R, "R", torch.float32, (N, 3))
     t = _dev(T, "T", torch.uint8, (N,))
     cs = _dev(cell_start, "cell_start", torch.int32, (sort_key_count(mesh, B) + 2,))
     c = _dev(counts, "counts", _U64, (K, _nm(mesh)))
@@ -289,10 +289,10 @@ def hpf_field_gradient(V, mesh: Mesh, K: int, G, stream=None, present=None):
 
 def hpf_force_gather(R, T, mesh: Mesh, K: int, G, F, stream=None):
     N, nm = R.shape[0], _nm(mesh)
-    r = _dev(R, "R", torch.float32, (N, 4))
+    r = _dev(R, "R", torch.float32, (N, 3))
     t = _dev(T, "T", torch.uint8, (N,))
     g = _dev(G, "G", torch.float32, (K, nm, 4))
-    f = _dev(F, "F", torch.float32, (N, 4))
+    f = _dev(F, "F", torch.float32, (N, 3))
     _check("hpf_force_gather",
            lib().hpf_force_gather(r, t, N, C.byref(mesh), K, g, f, _stream(stream)))
 
@@ -300,17 +300,17 @@ def hpf_force_gather(R, T, mesh: Mesh, K: int, G, F, stream=None):
 def hpf_force_gather_staggered(R, T, mesh: Mesh, K: int, V, F, stream=None):
     N = R.shape[0]
     _check("hpf_force_gather_staggered", lib().hpf_force_gather_staggered(
-        _dev(R, "R", torch.float32, (N, 4)), _dev(T, "T", torch.uint8, (N,)), N, C.byref(mesh), int(K),
-        _dev(V, "V", torch.float32, (K, _nm(mesh))), _dev(F, "F", torch.float32, (N, 4)),
+        _dev(R, "R", torch.float32, (N, 3)), _dev(T, "T", torch.uint8, (N,)), N, C.byref(mesh), int(K),
+        _dev(V, "V", torch.float32, (K, _nm(mesh))), _dev(F, "F", torch.float32, (N, 3)),
         _stream(stream)))
 
 
 def bond_forces(R, bonds, k: float, r0: float, box, F, e_part=None, stream=None):
     N = R.shape[0]
     D = bonds.shape[0] if bonds is not None else 0
-    r = _dev(R, "R", torch.float32, (N, 4))
+    r = _dev(R, "R", torch.float32, (N, 3))
     b = _dev(bonds, "bonds", torch.int32, (D, N), allow_none=True) if D else None
-    f = _dev(F, "F", torch.float32, (N, 4))
+    f = _dev(F, "F", torch.float32, (N, 3))
     e = _dev(e_part, "e_part", torch.float64, None, allow_none=True)
     if e_part is not None and e_part.numel() < HPF_NPART:
         raise ValueError("e_part needs HPF_NPART slots")
@@ -330,10 +330,10 @@ def angle_forces(R, angles, k, theta0, form, box, F, e_part=None, stream=None):
     if e_part is not None and e_part.numel() < HPF_NPART:
         raise ValueError("e_part needs HPF_NPART slots")
     _check("angle_forces", lib().angle_forces(
-        _dev(R, "R", torch.float32, (N, 4)), N,
+        _dev(R, "R", torch.float32, (N, 3)), N,
         _dev(angles, "angles", torch.int32, (3 * A, N), allow_none=True) if A else None, A, nt,
         (C.c_float * nt)(*kk), (C.c_float * nt)(*th), (C.c_int32 * nt)(*fm), _box(box),
-        _dev(F, "F", torch.float32, (N, 4)),
+        _dev(F, "F", torch.float32, (N, 3)),
         _dev(e_part, "e_part", torch.float64, None, allow_none=True), _stream(stream)))
 
 
@@ -348,9 +348,9 @@ def hpf_sort_angles(mesh: Mesh, B: int, angles_in, angles_out, work, stream=None
 
 def verlet_step(R, Vel, F, dt: float, box, half: int, inv_mass=None, kin_part=None, stream=None):
     N = Vel.shape[0]
-    r = _dev(R, "R", torch.float32, (N, 4), allow_none=(half == 2))
-    v = _dev(Vel, "Vel", torch.float32, (N, 4))
-    f = _dev(F, "F", torch.float32, (N, 4))
+    r = _dev(R, "R", torch.float32, (N, 3), allow_none=(half == 2))
+    v = _dev(Vel, "Vel", torch.float32, (N, 3))
+    f = _dev(F, "F", torch.float32, (N, 3))
     im = _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True)
     kp = _dev(kin_part, "kin_part", torch.float64, None, allow_none=True)
     if kin_part is not None and kin_part.numel() < 4 * HPF_NPART:
@@ -365,9 +365,9 @@ def hpf_advance(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float, r0: f
     N = R.shape[0]
     D = bonds.shape[0] if bonds is not None else 0
     args = [
-        _dev(R, "R", torch.float32, (N, 4)),
-        _dev(R_next, "R_next", torch.float32, (N, 4)),
-        _dev(Vel, "Vel", torch.float32, (N, 4)),
+        _dev(R, "R", torch.float32, (N, 3)),
+        _dev(R_next, "R_next", torch.float32, (N, 3)),
+        _dev(Vel, "Vel", torch.float32, (N, 3)),
         _dev(T, "T", torch.uint8, (N,)),
         N, C.byref(mesh), int(K),
         _dev(G, "G", torch.float32, (K, _nm(mesh), 4)),
@@ -375,7 +375,7 @@ def hpf_advance(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float, r0: f
         int(D), float(k), float(r0), _box(box),
         _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True),
         float(dt),
-        _dev(F_out, "F_out", torch.float32, (N, 4), allow_none=True),
+        _dev(F_out, "F_out", torch.float32, (N, 3), allow_none=True),
         _dev(e_part, "e_part", torch.float64, None, allow_none=True),
         _dev(kin_part, "kin_part", torch.float64, None, allow_none=True),
     ]
@@ -395,7 +395,7 @@ def hpf_andersen(Vel, thermostat: Thermostat, inv_mass=None, kin_part=None, stre
     if kin_part is not None and kin_part.numel() < 4 * HPF_NPART:
         raise ValueError("kin_part needs 4 * HPF_NPART slots")
     _check("hpf_andersen", lib().hpf_andersen(
-        _dev(Vel, "Vel", torch.float32, (N, 4)),
+        _dev(Vel, "Vel", torch.float32, (N, 3)),
         _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True), N, C.byref(thermostat),
         _dev(kin_part, "kin_part", torch.float64, None, allow_none=True), _stream(stream)))
 
@@ -406,9 +406,9 @@ def hpf_advance_scatter(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: floa
     N = R.shape[0]
     D = bonds.shape[0] if bonds is not None else 0
     args = [
-        _dev(R, "R", torch.float32, (N, 4)),
-        _dev(R_next, "R_next", torch.float32, (N, 4)),
-        _dev(Vel, "Vel", torch.float32, (N, 4)),
+        _dev(R, "R", torch.float32, (N, 3)),
+        _dev(R_next, "R_next", torch.float32, (N, 3)),
+        _dev(Vel, "Vel", torch.float32, (N, 3)),
         _dev(T, "T", torch.uint8, (N,)),
         N, C.byref(mesh), int(K),
         _dev(G, "G", torch.float32, (K, _nm(mesh), 4)),
@@ -420,7 +420,7 @@ def hpf_advance_scatter(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: floa
         int(B), int(halo),
         _dev(counts, "counts", torch.int64, (K, _nm(mesh))),
         _dev(work, "work", torch.uint8), work.numel(),
-        _dev(F_out, "F_out", torch.float32, (N, 4), allow_none=True),
+        _dev(F_out, "F_out", torch.float32, (N, 3), allow_none=True),
         _dev(e_part, "e_part", torch.float64, None, allow_none=True),
         _dev(kin_part, "kin_part", torch.float64, None, allow_none=True),
     ]
@@ -486,14 +486,14 @@ def hpf_sort_by_cell(mesh: Mesh, B: int, R_in, Vel_in, T_in, tag_in, bonds_in, R
     N = R_in.shape[0]
     D = bonds_in.shape[0] if bonds_in is not None else 0
     args = [
-        _dev(R_in, "R_in", torch.float32, (N, 4)),
-        _dev(Vel_in, "Vel_in", torch.float32, (N, 4), allow_none=True),
+        _dev(R_in, "R_in", torch.float32, (N, 3)),
+        _dev(Vel_in, "Vel_in", torch.float32, (N, 3), allow_none=True),
         _dev(T_in, "T_in", torch.uint8, (N,)),
         _dev(tag_in, "tag_in", torch.int32, (N,), allow_none=True),
         _dev(bonds_in, "bonds_in", torch.int32, (D, N), allow_none=True) if D else None,
         int(D),
-        _dev(R_out, "R_out", torch.float32, (N, 4)),
-        _dev(Vel_out, "Vel_out", torch.float32, (N, 4), allow_none=True),
+        _dev(R_out, "R_out", torch.float32, (N, 3)),
+        _dev(Vel_out, "Vel_out", torch.float32, (N, 3), allow_none=True),
         _dev(T_out, "T_out", torch.uint8, (N,)),
         _dev(tag_out, "tag_out", torch.int32, (N,), allow_none=True),
         _dev(bonds_out, "bonds_out", torch.int32, (D, N), allow_none=True) if D else None,

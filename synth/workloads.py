@@ -39,8 +39,8 @@ BASE_SEED = 13102041
 @dataclass
 class System:
     name: str
-    R: np.ndarray          # float32 [N, 4]  (x, y, z, 0)
-    V: np.ndarray          # float32 [N, 4]  (vx, vy, vz, 0)
+    R: np.ndarray          # float32 [N, 3]  (x, y, z)
+    V: np.ndarray          # float32 [N, 3]  (vx, vy, vz)
     T: np.ndarray          # uint8   [N]
     tag: np.ndarray        # int32   [N]
     bonds: np.ndarray      # int32   [2, N]  (-1 = none)
@@ -152,10 +152,8 @@ def chain_bonds(n_chains: int, chain_len: int, n_total: int, first: int = 0) -> 
     return b
 
 
-def _pack4(xyz: np.ndarray) -> np.ndarray:
-    out = np.zeros((xyz.shape[0], 4), dtype=np.float32)
-    out[:, :3] = xyz
-    return out
+def _rows3(xyz: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
 
 
 def build(spec: Spec, seed: int | None = None) -> System:
@@ -176,8 +174,8 @@ def build(spec: Spec, seed: int | None = None) -> System:
     if spec.n_solvent:
         pos = np.concatenate([pos, rng.random((spec.n_solvent, 3)) * spec.L])
         T[n_chain_beads:] = 2
-    R = _pack4(wrap_f32(pos, spec.L))
-    V = _pack4(maxwell(rng, N).astype(np.float32))
+    R = _rows3(wrap_f32(pos, spec.L))
+    V = _rows3(maxwell(rng, N).astype(np.float32))
     bonds = chain_bonds(spec.n_chains, spec.chain_len, N)
     return System(spec.name, R, V, T, np.arange(N, dtype=np.int32), bonds,
                   (spec.L,) * 3, (spec.M,) * 3, spec.K, spec.kT, spec.inv_kappa,
@@ -242,8 +240,8 @@ def small_system(n_chains: int, chain_len: int, L, M, K: int = 2, seed: int = 7,
         for b in range(K):
             if a != b:
                 chi[a, b] = chi_ab * (1.0 + 0.25 * ((a + b) % 3))
-    R = _pack4(wrap_f32(pos, Lt))
-    V = _pack4(maxwell(rng, N).astype(np.float32))
+    R = _rows3(wrap_f32(pos, Lt))
+    V = _rows3(maxwell(rng, N).astype(np.float32))
     return System("small", R, V, T, np.arange(N, dtype=np.int32),
                   chain_bonds(n_chains, chain_len, N), Lt, Mt, K, 1.0, inv_kappa,
                   chi, 100.0, 0.0, 0.03, {"seed": seed})
@@ -357,8 +355,8 @@ def lipid_system(n_lipids: int, n_water: int, M: int | None = None, seed: int = 
     pairs = [(m * per + i, m * per + j) for m in range(n_lipids) for i, j in LIPID_BONDS]
     trip = [(m * per + i, m * per + j, m * per + k, t) for m in range(n_lipids)
             for (i, j, k), t in LIPID_ANGLES]
-    R = _pack4(wrap_f32(pos, L))
-    V = _pack4(maxwell(rng, N).astype(np.float32))
+    R = _rows3(wrap_f32(pos, L))
+    V = _rows3(maxwell(rng, N).astype(np.float32))
     return System("lipid_k5", R, V, T, np.arange(N, dtype=np.int32), table_from_pairs(pairs, N),
                   (L,) * 3, (M,) * 3, 5, 1.0, 10.0, chi_matrix(5, LIPID_CHI), 100.0, 0.5, 0.03,
                   {"seed": seed, "n_lipids": n_lipids, "n_water": n_water},

@@ -31,7 +31,7 @@ def _oracle_angles(s, R=None):
 def test_angle_forces_match_oracle():
     s = lipids()
     R = dev(s.R, torch.float32)
-    F = torch.zeros((s.N, 4), dtype=torch.float32, device="cuda")
+    F = torch.zeros((s.N, 3), dtype=torch.float32, device="cuda")
     part = torch.zeros(hpf.HPF_NPART, dtype=torch.float64, device="cuda")
     hpf.angle_forces(R, dev(s.angles, torch.int32), s.angle_k, s.angle_theta0, s.angle_form, s.L, F,
                      e_part=part)
@@ -56,11 +56,11 @@ def test_single_angle_form_on_chains(form):
     pos = np.stack([start + 0.9 * d1 / np.linalg.norm(d1, axis=1, keepdims=True), start,
                     start + 1.1 * d2 / np.linalg.norm(d2, axis=1, keepdims=True)], 1).reshape(-1, 3)
     N = pos.shape[0]
-    R = np.zeros((N, 4), np.float32)
+    R = np.zeros((N, 3), np.float32)
     R[:, :3] = wl.wrap_f32(pos, L)
     tab = wl.angle_table([(3 * c, 3 * c + 1, 3 * c + 2, 0) for c in range(n_ch)], N)
     k, th0 = 7.5, 1.8
-    F = torch.zeros((N, 4), dtype=torch.float32, device="cuda")
+    F = torch.zeros((N, 3), dtype=torch.float32, device="cuda")
     hpf.angle_forces(dev(R, torch.float32), dev(tab, torch.int32), k, th0, form, (L, L, L), F)
     Fo, _ = oracle.angles(R, tab, k, th0, form, (L, L, L))
     err = rel_max(host(F)[:, :3], Fo)

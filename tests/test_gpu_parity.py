@@ -22,11 +22,8 @@ from synth import workloads as wl  # noqa: E402
 I64 = torch.int64
 
 
-def _pos4(xyz):
-    xyz = np.asarray(xyz, dtype=np.float32).reshape(-1, 3)
-    out = np.zeros((len(xyz), 4), np.float32)
-    out[:, :3] = xyz
-    return out
+def _pos3(xyz):
+    return np.ascontiguousarray(np.asarray(xyz, dtype=np.float32).reshape(-1, 3))
 
 
 def gpu_counts(R, T, L, M, K):
@@ -61,7 +58,7 @@ def test_scatter_counts_bit_exact(name, s):
 def test_scatter_ragged_sizes(n):
     rng = np.random.default_rng(n)
     L, M = (6.7, 5.3, 9.1), (7, 5, 10)
-    R = _pos4(rng.random((n, 3)) * np.array(L))
+    R = _pos3(rng.random((n, 3)) * np.array(L))
     T = rng.integers(0, 2, n).astype(np.uint8)
     c_or, _ = oracle.density(R, T, L, M, 2)
     assert np.array_equal(gpu_counts(R, T, L, M, 2), c_or)
@@ -71,14 +68,14 @@ def test_scatter_edge_positions_and_bad_beads():
     L, M = 8.0, 8
     Lf = np.float32(L)
     xs = [0.0, np.nextafter(Lf, np.float32(0)), -1e-7, -0.3, 7.999, 8.0, 11.5, -9.25, 1e-38]
-    R = _pos4([[x, y, z] for x in xs for y in xs[:4] for z in xs[4:]])
+    R = _pos3([[x, y, z] for x in xs for y in xs[:4] for z in xs[4:]])
     T = (np.arange(len(R)) % 2).astype(np.uint8)
     c_or, sk = oracle.density(R, T, L, M, 2)
     assert sk == 0
     hpf.hpf_get_device_status(clear=True)
     assert np.array_equal(gpu_counts(R, T, L, M, 2), c_or)
     assert hpf.hpf_get_device_status() == 0
-    bad = _pos4([[1.0, 1.0, 1.0], [np.nan, 1, 1], [1, np.inf, 1], [1e30, 1, 1], [2, 2, 2]])
+    bad = _pos3([[1.0, 1.0, 1.0], [np.nan, 1, 1], [1, np.inf, 1], [1e30, 1, 1], [2, 2, 2]])
     Tb = np.array([0, 0, 0, 0, 7], np.uint8)
     c_or, sk = oracle.density(bad, Tb, L, M, 2)
     assert sk == 4
@@ -90,7 +87,7 @@ def test_scatter_spread_chunk_falls_back_exactly():
     """Beads scattered over the whole box (no locality) take the global-atomic path."""
     rng = np.random.default_rng(5)
     L, M = 64.0, 64
-    R = _pos4(rng.random((50000, 3)) * L)
+    R = _pos3(rng.random((50000, 3)) * L)
     T = rng.integers(0, 3, 50000).astype(np.uint8)
     c_or, _ = oracle.density(R, T, L, M, 3)
     assert np.array_equal(gpu_counts(R, T, L, M, 3), c_or)
@@ -157,12 +154,11 @@ def test_gather_matches_oracle(name, s):
     G = rng.standard_normal((s.K, nm, 4)).astype(np.float32)
     F_or = oracle.gather(s.R, s.T, s.L, s.M, G[..., :3].reshape(s.K, *s.M[::-1], 3).astype(np.float64))
     mesh = hpf.hpf_mesh_make(s.L, s.M, s.N)
-    F = torch.full((s.N, 4), 7.0, dtype=torch.float32, device="cuda")
+    F = torch.full((s.N, 3), 7.0, dtype=torch.float32, device="cuda")
     hpf.hpf_force_gather(dev(s.R, torch.float32), dev(s.T, torch.uint8), mesh, s.K,
                          dev(G, torch.float32), F)
     Fg = host(F)
     assert rel_max(Fg[:, :3], F_or) <= 1e-6
-    assert np.all(Fg[:, 3] == 0.0)
 
 
 # ------------------------------------------------------------------ bonds --
@@ -171,7 +167,7 @@ def test_gather_matches_oracle(name, s):
 def test_bonds_match_oracle(r0):
     s = wl.small_system(300, 20, 9.7, 9, seed=21)
     F_or, E_or = oracle.bonds(s.R, s.bonds, s.k_bond, r0, s.L)
-    F0 = np.random.default_rng(1).standard_normal((s.N, 4)).astype(np.float32)
+    F0 = np.random.default_rng(1).standard_normal((s.N, 3)).astype(np.float32)
     F = dev(F0, torch.float32)
     part = torch.zeros(hpf.HPF_NPART, dtype=torch.float64, device="cuda")
     out = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -189,12 +185,12 @@ def test_bonds_across_the_seam_of_a_large_box():
     n = 2000
     xi = rng.random((n, 3)) * 0.8
     xj = np.mod(xi - 0.3 - rng.random((n, 3)) * 0.6, L)
-    R = _pos4(np.concatenate([xi, xj]))
+    R = _pos3(np.concatenate([xi, xj]))
     bonds = np.full((1, 2 * n), -1, np.int32)
     bonds[0, :n] = np.arange(n, 2 * n)
     bonds[0, n:] = np.arange(n)
     F_or, _ = oracle.bonds(R, bonds, 100.0, 0.0, L)
-    F = torch.zeros((2 * n, 4), dtype=torch.float32, device="cuda")
+    F = torch.zeros((2 * n, 3), dtype=torch.float32, device="cuda")
     hpf.bond_forces(dev(R, torch.float32), dev(bonds, torch.int32), 100.0, 0.0, L, F)
     assert rel_max(host(F)[:, :3], F_or) <= 1e-6
 
@@ -204,8 +200,7 @@ def test_bonds_across_the_seam_of_a_large_box():
 def test_verlet_halves_match_oracle():
     s = wl.small_system(100, 10, 7.0, 7, seed=31)
     rng = np.random.default_rng(2)
-    F0 = (rng.standard_normal((s.N, 4)) * 50).astype(np.float32)
-    F0[:, 3] = 0
+    F0 = (rng.standard_normal((s.N, 3)) * 50).astype(np.float32)
     R1o, V1o = oracle.verlet_half1(s.R, s.V, F0[:, :3], 0.03, s.L)
     R, Vel, F = dev(s.R, torch.float32), dev(s.V, torch.float32), dev(F0, torch.float32)
     hpf.verlet_step(R, Vel, F, 0.03, s.L, 1)
@@ -226,9 +221,9 @@ def test_verlet_halves_match_oracle():
 
 
 def test_verlet_nonfinite_flag():
-    R = dev(_pos4([[1.0, 1.0, 1.0]]), torch.float32)
-    Vel = dev(_pos4([[np.inf, 0.0, 0.0]]), torch.float32)
-    F = torch.zeros((1, 4), dtype=torch.float32, device="cuda")
+    R = dev(_pos3([[1.0, 1.0, 1.0]]), torch.float32)
+    Vel = dev(_pos3([[np.inf, 0.0, 0.0]]), torch.float32)
+    F = torch.zeros((1, 3), dtype=torch.float32, device="cuda")
     hpf.hpf_get_device_status(clear=True)
     hpf.verlet_step(R, Vel, F, 0.03, 5.0, 1)
     assert hpf.hpf_get_device_status() & hpf.HPF_FLAG_NONFINITE
@@ -317,7 +312,7 @@ def test_per_bead_kernels_ragged_sizes(n_chains, chain_len):
     mesh = hpf.hpf_mesh_make(s.L, s.M, s.N)
     R, T, Gd = dev(s.R, torch.float32), dev(s.T, torch.uint8), dev(G, torch.float32)
     bonds = dev(s.bonds, torch.int32)
-    F = torch.zeros((s.N, 4), dtype=torch.float32, device="cuda")
+    F = torch.zeros((s.N, 3), dtype=torch.float32, device="cuda")
     hpf.hpf_force_gather(R, T, mesh, 2, Gd, F)
     assert rel_max(host(F)[:, :3], F_or) <= 1e-6
     hpf.bond_forces(R, bonds, s.k_bond, s.r0, s.L, F)

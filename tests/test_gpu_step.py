@@ -235,7 +235,7 @@ def test_c2_1000_step_mean_energies():
 def test_empty_system_through_every_pass(advance):
     """N = 0: the sort, the fused passes, the finishing pass and the reductions run on an
     empty system (including inside a graph) and leave zero counts, zero energies and no flag."""
-    z4 = np.zeros((0, 4), np.float32)
+    z4 = np.zeros((0, 3), np.float32)
     chi = np.array([[0.0, 1.0], [1.0, 0.0]])
     st = engine.HpfState(z4, z4, np.zeros(0, np.uint8), np.zeros(0, np.int32), np.zeros((2, 0), np.int32),
                          12.0, 12, 2, 1.0, 10.0, chi, 100.0, 0.0, 0.03, advance=advance)
