@@ -56,6 +56,10 @@ typedef int32_t hpf_status_t;
 #define HPF_EINVAL (-1)     /* an argument is invalid (null pointer, bad size or mesh) */
 #define HPF_EHIP (-2)       /* the HIP runtime reported an error while enqueueing */
 #define HPF_ESPACE (-3)     /* a caller-provided workspace is too small */
+#define HPF_ETOOBIG (-4)    /* the problem needs more than HPF_STATIC_SCRATCH_BYTES */
+
+/* Size of the fixed device scratch of hpf_density_scatter_cells_static. */
+#define HPF_STATIC_SCRATCH_BYTES (32u << 20)
 
 /* Sticky device status bits (hpf_get_device_status). */
 #define HPF_FLAG_BAD_BEAD 0x1u   /* a bead with a non-finite or out-of-range position
@@ -188,6 +192,28 @@ hpf_status_t hpf_density_scatter_cells(const float* R, const uint8_t* T, int64_t
                                        const uint32_t* cell_start, int32_t B, int32_t halo,
                                        uint64_t* counts, void* work, size_t work_bytes,
                                        void* stream);
+
+/* ---------------------------------------------------------------------------
+ * hpf_density_scatter_cells_static -- hpf_density_scatter_cells for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same counts, from the same
+ * kernels, with no workspace argument. The stray list and partial boxes live in
+ * a fixed device array of HPF_STATIC_SCRATCH_BYTES (32 MiB) that each GPU holds
+ * while the library is loaded; the call allocates nothing.
+ *
+ * Arguments are those of hpf_density_scatter_cells without work/work_bytes.
+ * Returns HPF_ETOOBIG, with nothing enqueued, when
+ * hpf_scatter_workspace_bytes(N, mesh, K, B, halo) exceeds
+ * HPF_STATIC_SCRATCH_BYTES (for example 1M beads on a 64^3 mesh with K = 2,
+ * B = 8, halo = 2 needs 22 MB; 10M beads on 128^3 need 184 MB and are refused).
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * behind (each launch clears what must start at zero): calls that overlap in
+ * time on one GPU, from any streams or threads, race and must not be made.
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_density_scatter_cells_static(const float* R, const uint8_t* T, int64_t N,
+                                              const hpf_mesh_t* mesh, int32_t K,
+                                              const uint32_t* cell_start, int32_t B, int32_t halo,
+                                              uint64_t* counts, void* stream);
 
 /* ---------------------------------------------------------------------------
  * hpf_field_potential -- external potential of eq. (4) at every mesh point.

@@ -91,6 +91,34 @@ static bool thermo_k(const hpf_thermostat_t* t, int64_t N, ThermoK* out)
     return true;
 }
 
+// Device scratch of hpf_density_scatter_cells_static (its stray list and partial
+// boxes) for callers that cannot allocate: a fixed array that every device holds
+// while the library is loaded. In host code its name stands for a host-side shadow,
+// not a device address; only its per-device address from hipGetSymbolAddress is
+// passed to kernels.
+static __device__ __align__(256) unsigned char scratch[HPF_STATIC_SCRATCH_BYTES];
+
+// The device address of `scratch` on the current device, looked up on the first call
+// made with that device current and kept per device.
+static hpf_status_t static_scratch(char** out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return HPF_EHIP;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return HPF_EHIP;
+        addr[dev] = p;
+    }
+    *out = static_cast<char*>(addr[dev]);
+    return HPF_OK;
+}
+
 }  // namespace hpf
 
 using namespace hpf;
@@ -106,6 +134,7 @@ const char* hpf_status_string(hpf_status_t status)
     case HPF_EINVAL: return "invalid argument";
     case HPF_EHIP: return "HIP runtime error";
     case HPF_ESPACE: return "workspace too small";
+    case HPF_ETOOBIG: return "problem exceeds the library's fixed device scratch (HPF_STATIC_SCRATCH_BYTES)";
     default: return "unknown status";
     }
 }
@@ -178,6 +207,28 @@ size_t hpf_scatter_workspace_bytes(int64_t N, const hpf_mesh_t* mesh, int32_t K,
     TileK tk;
     size_t sb = 0, tb = 0;
     return scatter_cells_setup(N, mesh, K, B, halo, &tk, &sb, &tb) ? tb : 0;
+}
+
+hpf_status_t hpf_density_scatter_cells_static(const float* R, const uint8_t* T, int64_t N, const hpf_mesh_t* mesh,
+                                              int32_t K, const uint32_t* cell_start, int32_t B, int32_t halo,
+                                              uint64_t* counts, void* stream)
+{
+    TileK tk;
+    size_t sb = 0, tb = 0;
+    if (!counts || !cell_start || !scatter_cells_setup(N, mesh, K, B, halo, &tk, &sb, &tb))
+        return HPF_EINVAL;
+    if (N > 0 && (!R || !T))
+        return HPF_EINVAL;
+    if (tb > (size_t)HPF_STATIC_SCRATCH_BYTES)
+        return HPF_ETOOBIG;
+    char* w = nullptr;
+    const hpf_status_t st = static_scratch(&w);
+    if (st != HPF_OK)
+        return st;
+    // the stray counter at the head of the list is cleared by a kernel of the launch,
+    // and every brick overwrites its whole partial box
+    return launch_scatter_cells(R, T, N, tk, K, cell_start, counts, reinterpret_cast<uint32_t*>(w),
+                                reinterpret_cast<unsigned long long*>(w + sb), as_stream(stream));
 }
 
 hpf_status_t hpf_density_scatter_cells(const float* R, const uint8_t* T, int64_t N, const hpf_mesh_t* mesh,

@@ -30,6 +30,9 @@ HPF_FLAG_NONFINITE = 0x4
 HPF_FLAG_BAD_BOND = 0x8
 HPF_FLAG_SORT_ORDER = 0x10
 
+HPF_ETOOBIG = -4
+HPF_STATIC_SCRATCH_BYTES = 32 << 20
+
 
 class HpfError(RuntimeError):
     def __init__(self, fn: str, status: int, text: str):
@@ -104,6 +107,8 @@ _SIGNATURES = {
                                     C.c_size_t),
     "hpf_density_scatter_cells": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, C.c_int32,
                                    C.c_int32, _P, _P, C.c_size_t, _P], C.c_int32),
+    "hpf_density_scatter_cells_static": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, C.c_int32,
+                                          C.c_int32, _P, _P], C.c_int32),
     "hpf_field_potential": ([_P, C.POINTER(Mesh), C.POINTER(Field), _P, _P, _P, _P], C.c_int32),
     "hpf_field_gradient": ([_P, C.POINTER(Mesh), C.c_int32, _P, _P, _P], C.c_int32),
     "hpf_force_gather": ([_P, _P, C.c_int64, C.POINTER(Mesh), C.c_int32, _P, _P, _P], C.c_int32),
@@ -264,6 +269,18 @@ def hpf_density_scatter_cells(R, T, mesh: Mesh, K: int, cell_start, B: int, halo
     _check("hpf_density_scatter_cells",
            lib().hpf_density_scatter_cells(r, t, N, C.byref(mesh), K, cs, int(B), int(halo), c, w,
                                            work.numel() * work.element_size(), _stream(stream)))
+
+
+def hpf_density_scatter_cells_static(R, T, mesh: Mesh, K: int, cell_start, B: int, halo: int, counts,
+                                     stream=None):
+    N = R.shape[0]
+    r = _dev(R, "R", torch.float32, (N, 3))
+    t = _dev(T, "T", torch.uint8, (N,))
+    cs = _dev(cell_start, "cell_start", torch.int32, (sort_key_count(mesh, B) + 2,))
+    c = _dev(counts, "counts", _U64, (K, _nm(mesh)))
+    _check("hpf_density_scatter_cells_static",
+           lib().hpf_density_scatter_cells_static(r, t, N, C.byref(mesh), K, cs, int(B), int(halo), c,
+                                                  _stream(stream)))
 
 
 def hpf_field_potential(counts, mesh: Mesh, field: Field, V, w_part=None, stream=None, present=None):

@@ -134,3 +134,19 @@ def test_sort_workspace_size(hpf):
     nk = hpf.sort_key_count(m, 8)
     assert nk == 16 ** 3                      # one key per brick of 8^3 cells
     assert n >= 3 * 4 * 10_000_000 + 2 * 4 * (nk + 2)
+
+
+def test_static_scatter_refuses_problems_beyond_its_scratch(hpf):
+    """hpf_density_scatter_cells_static holds its scratch in a fixed 32 MiB device array:
+    10M beads on a 128^3 mesh need 184 MB and are refused on the host (HPF_ETOOBIG)
+    before anything is enqueued; bad arguments still give HPF_EINVAL."""
+    L = hpf.lib()
+    m = hpf.hpf_mesh_make(149.4, 128, 10_000_000)
+    need = L.hpf_scatter_workspace_bytes(10_000_000, C.byref(m), 2, 8, 2)
+    assert need > hpf.HPF_STATIC_SCRATCH_BYTES == 32 << 20
+    dummy = C.c_void_p(0x1000)         # never dereferenced: checks fail first
+    assert L.hpf_density_scatter_cells_static(dummy, dummy, 10_000_000, C.byref(m), 2, dummy, 8, 2,
+                                              dummy, None) == hpf.HPF_ETOOBIG
+    assert L.hpf_density_scatter_cells_static(dummy, dummy, 10_000_000, C.byref(m), 2, None, 8, 2,
+                                              dummy, None) == -1
+    assert L.hpf_status_string(hpf.HPF_ETOOBIG).startswith(b"problem exceeds")
