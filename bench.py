@@ -54,14 +54,14 @@ def algorithmic_bytes(name: str, N: int, K: int, nm: int, D: int) -> float:
 
 
 def layout_bytes(name: str, N: int, K: int, nm: int, D: int, P: int, nbricks: int) -> float:
-    """Bytes the kernel moves by its data layout: 12-byte bead rows (x, v), the (x, y, z, V)
-    gradient mesh (16 B per point and species, read in place of V), and the partial deposit
-    boxes of K P^3 uint64 per brick that the depositing pass writes and the finish reads."""
+    """Bytes the kernel moves by its data layout: 12-byte bead rows (x, v), the gradient mesh
+    (12 B per point and species, read in place of V), and the partial deposit boxes of
+    K P^3 uint64 per brick that the depositing pass writes and the finish reads."""
     box = 8.0 * K * P ** 3 * nbricks
     return {
-        "advance": (49.0 + 4.0 * D) * N + 16.0 * K * nm + box,
+        "advance": (49.0 + 4.0 * D) * N + 12.0 * K * nm + box,
         "finish_potential": 20.0 * K * nm + box,
-        "field_gradient": 20.0 * K * nm,
+        "field_gradient": 16.0 * K * nm,
     }.get(name)
 
 
@@ -164,7 +164,7 @@ def replay_segments(st, one, steps, period, torch, engine, max_graphs=64):
 
 
 def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, graph=True, halo=2,
-                 advance="scatter", field_every=1, thermostat=0.0, brick=8):
+                 advance="scatter", field_every=1, thermostat=0.0, brick=0):
     """Warm up, time `steps` steps, then (instrument) time each call over one period of
     eager steps. With `graph`, the timed steps replay HIP graphs (replay_segments)."""
     import torch
@@ -220,7 +220,7 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
     for d in range(3):
         nb *= -(-st.mesh.M[d] // st.B)
     return {"spec": spec, "N": st.N, "K": st.K, "nm": st.nm, "D": st.bonds.shape[0],
-            "P": st.B + 1 + 2 * st.halo, "nbricks": nb,
+            "B": st.B, "P": st.B + 1 + 2 * st.halo, "nbricks": nb,
             "ms_total": ms, "wall_s": wall, "kernels": tm.summary() if instrument else {},
             "flags": flags, "energies": e, "launch": launch,
             "advance_kernel": "scatter" if st.uses_scatter_advance() else "plain"}
@@ -407,7 +407,7 @@ def roofline(r, name):
             "layout_frac": None if lb is None else round(lb / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             "note": "achieved = minimal algorithmic bytes per launch / average launch time (HIP events "
                     "on the launch stream); layout_bytes = what this kernel's data layout moves "
-                    "(12-byte bead rows, (x, y, z, V) gradient corners, partial deposit boxes); "
+                    "(12-byte bead rows and gradient corners, partial deposit boxes); "
                     "traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, calibrated"}
 
 
@@ -427,7 +427,8 @@ def main():
     ap.add_argument("--c5-steps", type=int, default=40,
                     help="steps of the 100M-bead three-species system reported under 'c5' (0 = skip)")
     ap.add_argument("--halo", type=int, default=2, help="drift halo (cells) of the brick deposit boxes")
-    ap.add_argument("--brick", type=int, default=8, help="sort brick edge in cells (3..16)")
+    ap.add_argument("--brick", type=int, default=0,
+                    help="sort brick edge in cells (3..16); 0 = the engine's choice for the mesh")
     ap.add_argument("--advance", default="scatter", choices=["scatter", "plain"],
                     help="fused pass on cell-sorted beads (scatter: with the density deposit)")
     ap.add_argument("--eager", action="store_true",
@@ -474,7 +475,7 @@ def main():
         "config": {"workload": r["spec"].name, "beads": r["N"], "species": r["K"],
                    "mesh": [r["spec"].M] * 3, "box": r["spec"].L, "sort_every": args.sort_every,
                    "energy_report_every": 1, "step": args.mode, "advance": r["advance_kernel"],
-                   "halo": args.halo, "brick": args.brick, "launch": r["launch"],
+                   "halo": args.halo, "brick": r["B"], "launch": r["launch"],
                    "parallelism": "single-gpu"},
         "roofline": roofline(r, dom),
         "step_roofline": step_bandwidth(r, ms_step),
@@ -489,7 +490,7 @@ def main():
                           fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance,
                      brick=args.brick)
         ms2 = r2["ms_total"] / args.steps
-        out["also"] = {"workload": r2["spec"].name, "beads": r2["N"],
+        out["also"] = {"workload": r2["spec"].name, "beads": r2["N"], "brick": r2["B"],
                        "value": r2["N"] * args.steps / (r2["ms_total"] * 1e-3),
                        "ms_per_step": ms2, "launch": r2["launch"],
                        "step_roofline": step_bandwidth(r2, ms2),
@@ -515,7 +516,7 @@ def main():
                           fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance,
                      brick=args.brick)
         ms5 = r5["ms_total"] / args.c5_steps
-        out["c5"] = {"workload": r5["spec"].name, "beads": r5["N"], "species": r5["K"],
+        out["c5"] = {"workload": r5["spec"].name, "beads": r5["N"], "species": r5["K"], "brick": r5["B"],
                      "mesh": [r5["spec"].M] * 3, "steps": args.c5_steps,
                      "value": r5["N"] / (ms5 * 1e-3), "ms_per_step": ms5, "launch": r5["launch"],
                      "step_roofline": step_bandwidth(r5, ms5),

@@ -243,11 +243,10 @@ hpf_status_t hpf_field_potential(uint64_t* counts, const hpf_mesh_t* mesh,
 /* ---------------------------------------------------------------------------
  * hpf_field_gradient -- mesh gradient of the potential (Algorithm 1
  * Kernel 3, read as a centred periodic difference at the mesh point):
- *   G_K(v) = ( (V_K(v+e_x) - V_K(v-e_x)) / (2 h_x), ... y, ... z, V_K(v) )
+ *   G_K(v) = ( (V_K(v+e_x) - V_K(v-e_x)) / (2 h_x), ... y, ... z )
  * with 1/(2 h_d) = s_d / 2.
  *
- * V  float[K][M^3] device.  G float[K][M^3][4] device, overwritten; the 4th
- * component carries V_K(v) itself.
+ * V  float[K][M^3] device.  G float[K][M^3][3] device, overwritten.
  * present  nullable uint8[M^3] device, the composition list that
  *          hpf_field_potential wrote for the same counts: G_K(v) is then written
  *          only where bit K of present[v] is set; the other entries keep their
@@ -263,7 +262,7 @@ hpf_status_t hpf_field_gradient(const float* V, const hpf_mesh_t* mesh, int32_t 
  * Kernel 4, read as interpolation with the density-assignment weights):
  *   F_i = - sum_a (W_a(i) / 2^48) G_{T_i}(c_i + a)
  *
- * R float[N][3], T uint8[N], G float[K][M^3][4] device.
+ * R float[N][3], T uint8[N], G float[K][M^3][3] device.
  * F float[N][3] device, OVERWRITTEN. Skipped beads (see
  * hpf_density_scatter) get F = 0.
  * ------------------------------------------------------------------------- */
@@ -373,7 +372,7 @@ hpf_status_t hpf_andersen(float* Vel, const float* inv_mass, int64_t N,
  * R_next  float[N][3] device, receives x_{n+1} wrapped into the box; must not
  *         alias R.
  * Vel     float[N][3] device, v_{n-1/2} in, v_{n+1/2} out.
- * G       float[K][M^3][4] device, the gradient mesh of x_n.
+ * G       float[K][M^3][3] device, the gradient mesh of x_n.
  * bonds, D, k, r0, box, inv_mass, dt: as in bond_forces / verlet_step.
  * F_out   nullable float[N][3] device: receives the total force at x_n.
  * e_part  nullable double[HPF_NPART]; kin_part nullable double[4][HPF_NPART]:
@@ -555,7 +554,7 @@ typedef struct hpf_batch_buffers {
     int32_t* bonds[2];       /* int32[D][N_total] each (NULL when D = 0) */
     uint64_t* counts;        /* sum_r K M_r^3 */
     float* V;                /* sum_r K M_r^3 */
-    float* G;                /* sum_r K M_r^3 * 4 */
+    float* G;                /* sum_r K M_r^3 * 3 */
 } hpf_batch_buffers_t;
 
 typedef struct hpf_batch hpf_batch_t;   /* host object; owns no device memory */

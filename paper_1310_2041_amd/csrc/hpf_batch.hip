@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kFPThreads) void k_batch_finish_potential(const Rep
 __global__ __launch_bounds__(256) void k_batch_gradient(const RepK* __restrict__ reps,
                                                         const ItemK* __restrict__ items, int K,
                                                         const float* __restrict__ V,
-                                                        float4* __restrict__ G)
+                                                        float3* __restrict__ G)
 {
     const int64_t li = xcd_block(blockIdx.x, gridDim.x);
     const ItemK it = items[li];
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
                                                              float3* __restrict__ R_next,
                                                              float3* __restrict__ Vel,
                                                              const uint8_t* __restrict__ T, int64_t Ntot,
-                                                             const float4* __restrict__ G,
+                                                             const float3* __restrict__ G,
                                                              const int32_t* __restrict__ bonds, int D, float k,
                                                              float r0, float dt,
                                                              double* __restrict__ e_part,
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
     const RepK& rp = reps[it.rep];
     th.kT = rp.kT;
     const uint64_t tstep = thermo_step(th);
-    const float4* Gr = G + (int64_t)K * rp.moff;
+    const float3* Gr = G + (int64_t)K * rp.moff;
     const float hdt = 0.5f * dt;
     KinAcc acc;
     double e = 0.0;
@@ -286,7 +286,7 @@ template <bool kR0Zero, bool kPipe, bool kThermo>
 __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
     const RepK* __restrict__ reps, const ItemK* __restrict__ items, int B, int h, int K,
     const float3* __restrict__ R, float3* __restrict__ R_next, float3* __restrict__ Vel,
-    const uint8_t* __restrict__ T, int64_t Ntot, const float4* __restrict__ G, const int32_t* __restrict__ bonds,
+    const uint8_t* __restrict__ T, int64_t Ntot, const float3* __restrict__ G, const int32_t* __restrict__ bonds,
     int D, float k, float r0, float dt, const uint32_t* __restrict__ cell_start,
     unsigned long long* __restrict__ partials, unsigned long long* __restrict__ counts,
     double* __restrict__ e_part, double* __restrict__ kin_part, int nslot, ThermoK th)
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
     th.kT = rp.kT;
     const uint64_t tstep = thermo_step(th);
     const MeshK& m = rp.m;
-    const float4* Gr = G + (int64_t)K * rp.moff;
+    const float3* Gr = G + (int64_t)K * rp.moff;
     unsigned long long* cr = counts + (int64_t)K * rp.moff;
     const int P = B + 1 + 2 * h, P3 = P * P * P, nbox = K * P3;
     const int64_t brick = it.begin;
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kPThreads) void k_batch_prime(const RepK* __restric
                                                            float3* __restrict__ R_next,
                                                            float3* __restrict__ Vel,
                                                            const uint8_t* __restrict__ T, int64_t Ntot,
-                                                           const float4* __restrict__ G,
+                                                           const float3* __restrict__ G,
                                                            const int32_t* __restrict__ bonds, int D, float k,
                                                            float r0, float dt, double* __restrict__ e_part,
                                                            double* __restrict__ kin_part, int nslot)
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(kPThreads) void k_batch_prime(const RepK* __restric
     const int64_t li = xcd_block(blockIdx.x, gridDim.x);
     const ItemK it = items[li];
     const RepK& rp = reps[it.rep];
-    const float4* Gr = G + (int64_t)K * rp.moff;
+    const float3* Gr = G + (int64_t)K * rp.moff;
     const float hdt = 0.5f * dt;
     KinAcc acc;
     double e = 0.0;
@@ -732,7 +732,7 @@ static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)
         b->w_bricks = false;
     }
     hipLaunchKernelGGL(k_batch_gradient, dim3((unsigned)b->n_planes), dim3(256), 0, s, reps,
-                       b->at<ItemK>(L.off_plane_items), K, b->buf.V, reinterpret_cast<float4*>(b->buf.G));
+                       b->at<ItemK>(L.off_plane_items), K, b->buf.V, reinterpret_cast<float3*>(b->buf.G));
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
@@ -748,7 +748,7 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
     auto* Vel = reinterpret_cast<float3*>(b->buf.Vel[b->scur]);
     const uint8_t* T = b->buf.T[b->scur];
     const int32_t* bonds = c.D > 0 ? b->buf.bonds[b->scur] : nullptr;
-    const auto* G = reinterpret_cast<const float4*>(b->buf.G);
+    const auto* G = reinterpret_cast<const float3*>(b->buf.G);
     double* e = report ? b->at<double>(L.off_epart) : nullptr;
     double* kp = report ? b->at<double>(L.off_kpart) : nullptr;
     const int nslot = (int)L.nslot;
@@ -769,7 +769,7 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
         const size_t smem = sizeof(unsigned long long) * (size_t)c.K * P * P * P;
         // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
         using AdvFn = void (*)(const RepK*, const ItemK*, int, int, int, const float3*, float3*, float3*,
-                               const uint8_t*, int64_t, const float4*, const int32_t*, int, float, float, float,
+                               const uint8_t*, int64_t, const float3*, const int32_t*, int, float, float, float,
                                const uint32_t*, unsigned long long*, unsigned long long*, double*, double*, int,
                                ThermoK);
         const bool pipe = c.D <= kPreBonds;
@@ -804,7 +804,7 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
                                    bonds, c.D, c.k_bond, c.r0, c.dt, e, kp, nslot);
         } else {
             using BAdvFn = void (*)(const RepK*, const ItemK*, int, const float3*, float3*, float3*, const uint8_t*,
-                                    int64_t, const float4*, const int32_t*, int, float, float, float, double*,
+                                    int64_t, const float3*, const int32_t*, int, float, float, float, double*,
                                     double*, int, ThermoK);
             const BAdvFn fa = th.thr ? (c.r0 == 0.0f ? k_batch_advance<true, true> : k_batch_advance<false, true>)
                                      : (c.r0 == 0.0f ? k_batch_advance<true, false> : k_batch_advance<false, false>);

@@ -256,12 +256,12 @@ hpf_status_t launch_finish_potential(const unsigned long long* partials, const T
 
 constexpr int kGradX = 64, kGradY = 4;
 
-// Centred gradient at mesh point (x, y, z): G = (gx, gy, gz, V) for the species whose
+// Centred gradient at mesh point (x, y, z): G = (gx, gy, gz) for the species whose
 // bit is set in `listed` (the point's composition list; all species with ~0). Entries of
 // species left out keep their previous values: a bead reads G of its own species only at
 // the corners that its weights reach, all of which hold a non-zero count of its species.
 __device__ __forceinline__ void gradient_point(const float* __restrict__ V, const MeshK& m, int K, int x, int y,
-                                               int z, float4* __restrict__ G, uint32_t listed = ~0u)
+                                               int z, float3* __restrict__ G, uint32_t listed = ~0u)
 {
     const int Mx = m.M[0], My = m.M[1], Mz = m.M[2];
     const int xp = next_wrap(x, Mx), xm = prev_wrap(x, Mx);
@@ -275,11 +275,10 @@ __device__ __forceinline__ void gradient_point(const float* __restrict__ V, cons
         if (!((listed >> k) & 1u))
             continue;
         const float* Vk = V + k * m.nm;
-        float4 g;
+        float3 g;
         g.x = (Vk[row + xp] - Vk[row + xm]) * hx;
         g.y = (Vk[rowyp + x] - Vk[rowym + x]) * hy;
         g.z = (Vk[rowzp + x] - Vk[rowzm + x]) * hz;
-        g.w = Vk[row + x];
         G[k * m.nm + row + x] = g;
     }
 }
@@ -289,7 +288,7 @@ __device__ __forceinline__ void gradient_point(const float* __restrict__ V, cons
 // and +-z rows are re-read from L2 by neighbouring blocks.
 __global__ __launch_bounds__(kGradX * kGradY) void k_field_gradient(const float* __restrict__ V,
                                                                     MeshK m, int K,
-                                                                    float4* __restrict__ G,
+                                                                    float3* __restrict__ G,
                                                                     const uint8_t* __restrict__ present)
 {
     const int x = blockIdx.x * kGradX + threadIdx.x;
@@ -306,7 +305,7 @@ hpf_status_t launch_field_gradient(const float* V, const MeshK& m, int K, float*
 {
     const dim3 g((m.M[0] + kGradX - 1) / kGradX, (m.M[1] + kGradY - 1) / kGradY, m.M[2]);
     hipLaunchKernelGGL(k_field_gradient, g, dim3(kGradX, kGradY), 0, s, V, m, K,
-                       reinterpret_cast<float4*>(G), present);
+                       reinterpret_cast<float3*>(G), present);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 

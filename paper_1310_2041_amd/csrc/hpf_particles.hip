@@ -73,7 +73,7 @@ struct BoxK {
 // Trilinear interpolation of the gradient at a bead from the 8 corner values
 // g[a], a = x + 2y + 4z, with the exact FP32 dyadic 1-D weights (separable
 // form of -sum_a (W_a / 2^48) G(c + a)).
-__device__ __forceinline__ float3 interp8(const BeadCell& b, const float4 (&g)[8])
+__device__ __forceinline__ float3 interp8(const BeadCell& b, const float3 (&g)[8])
 {
     const float ax1 = (float)b.q[0] * kInvOne, ax0 = (float)(kOne - b.q[0]) * kInvOne;
     const float ay1 = (float)b.q[1] * kInvOne, ay0 = (float)(kOne - b.q[1]) * kInvOne;
@@ -105,9 +105,9 @@ __device__ __forceinline__ float3 interp8(const BeadCell& b, const float4 (&g)[8
 
 // The 8 corner values of cell b from species t's gradient mesh in memory.
 __device__ __forceinline__ void corners_global(const BeadCell& b, int t, const MeshK& m,
-                                               const float4* __restrict__ G, float4 (&g)[8])
+                                               const float3* __restrict__ G, float3 (&g)[8])
 {
-    const float4* Gk = G + t * m.nm;
+    const float3* Gk = G + t * m.nm;
     const int32_t Mx = m.M[0], My = m.M[1], Mz = m.M[2];
     const int32_t x0 = b.c[0], x1 = next_wrap(x0, Mx);
     const int32_t y0 = b.c[1], y1 = next_wrap(y0, My);
@@ -127,13 +127,13 @@ __device__ __forceinline__ void corners_global(const BeadCell& b, int t, const M
 // Field force on one bead (eq. 6). False (and zero force) for a bead that
 // cannot be binned or has a type >= K.
 __device__ __forceinline__ bool field_force(const float3& r, int t, const MeshK& m, int K,
-                                            const float4* __restrict__ G, float3& f)
+                                            const float3* __restrict__ G, float3& f)
 {
     BeadCell b;
     f = make_float3(0.0f, 0.0f, 0.0f);
     if (!(bead_cell(r, m, b) && t < K))
         return false;
-    float4 g[8];
+    float3 g[8];
     corners_global(b, t, m, G, g);
     f = interp8(b, g);
     return true;
@@ -279,7 +279,7 @@ struct KinAcc {
 __global__ __launch_bounds__(kPThreads) void k_force_gather(const float3* __restrict__ R,
                                                             const uint8_t* __restrict__ T,
                                                             int64_t N, MeshK m, int K,
-                                                            const float4* __restrict__ G,
+                                                            const float3* __restrict__ G,
                                                             float3* __restrict__ F)
 {
     const BeadWalk w = bead_walk(N);
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(kPThreads) void k_verlet_half2(float3* __restrict__
 template <bool kR0Zero, bool kThermo>
 __device__ __forceinline__ float3 advance_bead(int64_t i, const float3* __restrict__ R, float3* __restrict__ R_next,
                                              float3* __restrict__ Vel, const uint8_t* __restrict__ T,
-                                             int64_t N, const MeshK& m, int K, const float4* __restrict__ G,
+                                             int64_t N, const MeshK& m, int K, const float3* __restrict__ G,
                                              const int32_t* __restrict__ bonds, int D, float k, float r0,
                                              const BoxK& box, const float* __restrict__ inv_mass, float dt,
                                              float hdt, float3* __restrict__ F_out, KinAcc& acc, double& e,
@@ -570,7 +570,7 @@ __device__ __forceinline__ void bead_fetch(BeadIn& p, int64_t i, const float3* _
 }
 
 struct BeadLoads {
-    float4 g[8];
+    float3 g[8];
     float3 xj[kPreBonds];
     BeadCell b;
     bool ok;
@@ -580,7 +580,7 @@ struct BeadLoads {
 // corners of cell 0 and gets no field force) and its partner loads (an index
 // outside [0, N) loads the bead itself; the bond is then skipped or flagged).
 __device__ __forceinline__ void bead_issue(BeadLoads& L, const BeadIn& p, int64_t i, const MeshK& m, int K,
-                                           const float4* __restrict__ G, const float3* __restrict__ R, int64_t N)
+                                           const float3* __restrict__ G, const float3* __restrict__ R, int64_t N)
 {
     L.ok = bead_cell(p.r, m, L.b) && p.t < K;
     BeadCell c = L.b;
@@ -671,7 +671,7 @@ __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float3* __res
                                                        float3* __restrict__ R_next,
                                                        float3* __restrict__ Vel,
                                                        const uint8_t* __restrict__ T, int64_t N,
-                                                       MeshK m, int K, const float4* __restrict__ G,
+                                                       MeshK m, int K, const float3* __restrict__ G,
                                                        const int32_t* __restrict__ bonds, int D,
                                                        float k, float r0, BoxK box,
                                                        const float* __restrict__ inv_mass, float dt,
@@ -748,11 +748,17 @@ constexpr int kASThreadsDefault = 512;
 constexpr int kASThreadsWide = 768;
 
 template <bool kR0Zero, int kASThreads, bool kPipe, bool kThermo>
-__global__ __launch_bounds__(kASThreads) void k_advance_scatter(const float3* __restrict__ R,
+// The second bound is waves per SIMD. The production form (512 threads, r0 = 0, no
+// thermostat) keeps two workgroups per CU, 4 waves per SIMD (at most 128 VGPRs, which it
+// fits without spilling); the others take 3 (at most 168), as does a 768-thread workgroup,
+// which runs alone on its CU next to its large deposit box.
+__global__ __launch_bounds__(kASThreads, kASThreads == kASThreadsDefault && kR0Zero && !kThermo ? 4 : 3) void
+k_advance_scatter(
+    const float3* __restrict__ R,
                                                                 float3* __restrict__ R_next,
                                                                 float3* __restrict__ Vel,
                                                                 const uint8_t* __restrict__ T, int64_t N,
-                                                                TileK tk, int K, const float4* __restrict__ G,
+                                                                TileK tk, int K, const float3* __restrict__ G,
                                                                 const int32_t* __restrict__ bonds, int D,
                                                                 float k, float r0, BoxK box,
                                                                 const float* __restrict__ inv_mass, float dt,
@@ -880,7 +886,7 @@ hpf_status_t launch_force_gather(const float* R, const uint8_t* T, int64_t N, co
         return HPF_OK;
     hipLaunchKernelGGL(k_force_gather, dim3((unsigned)bead_blocks(N, 1 << 20)), dim3(kPThreads),
                        0, s, reinterpret_cast<const float3*>(R), T, N, m, K,
-                       reinterpret_cast<const float4*>(G), reinterpret_cast<float3*>(F));
+                       reinterpret_cast<const float3*>(G), reinterpret_cast<float3*>(F));
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
@@ -956,9 +962,9 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
     auto* Rp = reinterpret_cast<const float3*>(R);
     auto* Rn = reinterpret_cast<float3*>(R_next);
     auto* Vp = reinterpret_cast<float3*>(Vel);
-    auto* Gp = reinterpret_cast<const float4*>(G);
+    auto* Gp = reinterpret_cast<const float3*>(G);
     auto* Fo = reinterpret_cast<float3*>(F_out);
-    using AdvFn = void (*)(const float3*, float3*, float3*, const uint8_t*, int64_t, MeshK, int, const float4*,
+    using AdvFn = void (*)(const float3*, float3*, float3*, const uint8_t*, int64_t, MeshK, int, const float3*,
                            const int32_t*, int, float, float, BoxK, const float*, float, float3*, double*, double*,
                            ThermoK);
     const bool thermo = th.thr != 0;
@@ -974,7 +980,7 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
 
 template <bool kR0Zero, int kThreads, bool kPipe, bool kThermo>
 static hpf_status_t launch_advance_scatter_t(const float3* Rp, float3* Rn, float3* Vp, const uint8_t* T, int64_t N,
-                                             const TileK& tk, int K, const float4* Gp, const int32_t* bonds, int D,
+                                             const TileK& tk, int K, const float3* Gp, const int32_t* bonds, int D,
                                              float k, float r0, const BoxK& box, const float* inv_mass, float dt,
                                              const uint32_t* cell_start, unsigned long long* partials,
                                              unsigned long long* counts, float3* Fo, double* e_part,
@@ -1005,7 +1011,7 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
     auto* Rp = reinterpret_cast<const float3*>(R);
     auto* Rn = reinterpret_cast<float3*>(R_next);
     auto* Vp = reinterpret_cast<float3*>(Vel);
-    auto* Gp = reinterpret_cast<const float4*>(G);
+    auto* Gp = reinterpret_cast<const float3*>(G);
     auto* Fo = reinterpret_cast<float3*>(F_out);
     // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
     const bool pipe = D <= kPreBonds, thermo = th.thr != 0, r0z = r0 == 0.0f;
@@ -1014,7 +1020,7 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
     // 1024 threads would cap it at 128 VGPRs, which spills); the others keep 512.
     const bool wide = r0z && !thermo && sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P > 80 * 1024;
     using LaunchFn = hpf_status_t (*)(const float3*, float3*, float3*, const uint8_t*, int64_t, const TileK&, int,
-                                      const float4*, const int32_t*, int, float, float, const BoxK&, const float*,
+                                      const float3*, const int32_t*, int, float, float, const BoxK&, const float*,
                                       float, const uint32_t*, unsigned long long*, unsigned long long*, float3*,
                                       double*, double*, const ThermoK&, hipStream_t);
     LaunchFn launch;

@@ -25,11 +25,29 @@ ROW_EA = 6                           # angle energy
 N_ROWS = 7
 
 
+LDS_BYTES = 160 * 1024
+
+
+def auto_brick(M, K: int, halo: int) -> int:
+    """Sort brick edge for the fused depositing pass: 16 cells when the mesh holds at least
+    512 such bricks (two per CU) and their deposit box of K (17 + 2 halo)^3 uint64 fits in
+    LDS, else 8. Larger bricks halve the partial-box traffic (the box overhang is a smaller
+    share of the brick); on small meshes they would leave CUs idle."""
+    B = 16
+    P = B + 1 + 2 * halo
+    nb = 1
+    for d in range(3):
+        nb *= -(-int(M[d]) // B)
+    if nb >= 512 and K * P ** 3 * 8 <= LDS_BYTES and all(int(m) >= P for m in M):
+        return B
+    return 8
+
+
 class HpfState:
     """One periodic system on the GPU: beads, bond table, mesh buffers."""
 
     def __init__(self, R, Vel, T, tag, bonds, L, M, K, kT, inv_kappa, chi, k_bond, r0, dt,
-                 device="cuda", sort_brick=8, halo=1, advance="scatter",
+                 device="cuda", sort_brick=0, halo=1, advance="scatter",
                  field_every=1, stencil="centred", angles=None, angle_k=(), angle_theta0=(),
                  angle_form=(), composition_list=False):
         dev = torch.device(device)
@@ -42,7 +60,8 @@ class HpfState:
         self.mesh = hpf.hpf_mesh_make(self.L, M, self.N)
         self.field = hpf.make_field(self.K, kT, inv_kappa, chi)
         self.box = self.L
-        self.B = int(sort_brick)
+        # 0 = auto_brick(): 16-cell bricks on large meshes, else 8
+        self.B = int(sort_brick) or auto_brick(self.mesh.M, self.K, int(halo))
         self.halo = int(halo)
         # How the fused step advances cell-sorted beads: "scatter" = hpf_advance_scatter (also
         # deposits x_n+1, so the next step only finishes the density), "plain" = hpf_advance.
@@ -116,7 +135,7 @@ class HpfState:
         # present at each mesh point and the gradient pass skips the absent ones; G starts at
         # zero so that entries never written stay finite.
         self.present = torch.zeros(nm, dtype=torch.uint8, device=dev) if composition_list else None
-        self.G = (torch.zeros if composition_list else torch.empty)((self.K, nm, 4), dtype=torch.float32,
+        self.G = (torch.zeros if composition_list else torch.empty)((self.K, nm, 3), dtype=torch.float32,
                                                                     device=dev)
         self.part = torch.zeros((N_ROWS, hpf.HPF_NPART), dtype=torch.float64, device=dev)
         self.energy = torch.zeros(8, dtype=torch.float64, device=dev)
@@ -406,7 +425,7 @@ class BatchState:
         nm_tot = sum(self.nm)
         self.counts = torch.zeros(self.K * nm_tot, dtype=torch.int64, device=dev)
         self.V = torch.empty(self.K * nm_tot, dtype=torch.float32, device=dev)
-        self.G = torch.empty(self.K * nm_tot * 4, dtype=torch.float32, device=dev)
+        self.G = torch.empty(self.K * nm_tot * 3, dtype=torch.float32, device=dev)
         reps = []
         for s, o in zip(systems, offs[:-1]):
             r = hpf.Replica()

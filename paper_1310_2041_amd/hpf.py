@@ -299,7 +299,7 @@ def hpf_field_potential(counts, mesh: Mesh, field: Field, V, w_part=None, stream
 def hpf_field_gradient(V, mesh: Mesh, K: int, G, stream=None, present=None):
     nm = _nm(mesh)
     v = _dev(V, "V", torch.float32, (K, nm))
-    g = _dev(G, "G", torch.float32, (K, nm, 4))
+    g = _dev(G, "G", torch.float32, (K, nm, 3))
     pr = _dev(present, "present", torch.uint8, (nm,), allow_none=True)
     _check("hpf_field_gradient", lib().hpf_field_gradient(v, C.byref(mesh), K, g, pr, _stream(stream)))
 
@@ -308,7 +308,7 @@ def hpf_force_gather(R, T, mesh: Mesh, K: int, G, F, stream=None):
     N, nm = R.shape[0], _nm(mesh)
     r = _dev(R, "R", torch.float32, (N, 3))
     t = _dev(T, "T", torch.uint8, (N,))
-    g = _dev(G, "G", torch.float32, (K, nm, 4))
+    g = _dev(G, "G", torch.float32, (K, nm, 3))
     f = _dev(F, "F", torch.float32, (N, 3))
     _check("hpf_force_gather",
            lib().hpf_force_gather(r, t, N, C.byref(mesh), K, g, f, _stream(stream)))
@@ -387,7 +387,7 @@ def hpf_advance(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: float, r0: f
         _dev(Vel, "Vel", torch.float32, (N, 3)),
         _dev(T, "T", torch.uint8, (N,)),
         N, C.byref(mesh), int(K),
-        _dev(G, "G", torch.float32, (K, _nm(mesh), 4)),
+        _dev(G, "G", torch.float32, (K, _nm(mesh), 3)),
         _dev(bonds, "bonds", torch.int32, (D, N), allow_none=True) if D else None,
         int(D), float(k), float(r0), _box(box),
         _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True),
@@ -428,7 +428,7 @@ def hpf_advance_scatter(R, R_next, Vel, T, mesh: Mesh, K: int, G, bonds, k: floa
         _dev(Vel, "Vel", torch.float32, (N, 3)),
         _dev(T, "T", torch.uint8, (N,)),
         N, C.byref(mesh), int(K),
-        _dev(G, "G", torch.float32, (K, _nm(mesh), 4)),
+        _dev(G, "G", torch.float32, (K, _nm(mesh), 3)),
         _dev(bonds, "bonds", torch.int32, (D, N), allow_none=True) if D else None,
         int(D), float(k), float(r0), _box(box),
         _dev(inv_mass, "inv_mass", torch.float32, (N,), allow_none=True),

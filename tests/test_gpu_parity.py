@@ -137,12 +137,11 @@ def test_gradient_matches_oracle(L, M, K):
     G_or = oracle.gradient(V.astype(np.float64), L, M)
     mesh = hpf.hpf_mesh_make(L, M, 1000)
     nm = int(np.prod(M))
-    G = torch.empty((K, nm, 4), dtype=torch.float32, device="cuda")
+    G = torch.empty((K, nm, 3), dtype=torch.float32, device="cuda")
     hpf.hpf_field_gradient(dev(V.reshape(K, nm), torch.float32), mesh, K, G)
-    Gg = host(G).reshape(K, M[2], M[1], M[0], 4)
-    assert rel_max(Gg[..., :3], G_or) <= 1e-6
-    assert np.all(np.abs(Gg[..., :3] - G_or) <= 4e-7 * np.abs(G_or) + 1e-6 * np.abs(G_or).max())
-    assert np.array_equal(Gg[..., 3], V)
+    Gg = host(G).reshape(K, M[2], M[1], M[0], 3)
+    assert rel_max(Gg, G_or) <= 1e-6
+    assert np.all(np.abs(Gg - G_or) <= 4e-7 * np.abs(G_or) + 1e-6 * np.abs(G_or).max())
 
 
 # ----------------------------------------------------------------- gather --
@@ -151,8 +150,8 @@ def test_gradient_matches_oracle(L, M, K):
 def test_gather_matches_oracle(name, s):
     rng = np.random.default_rng(3)
     nm = int(np.prod(s.M))
-    G = rng.standard_normal((s.K, nm, 4)).astype(np.float32)
-    F_or = oracle.gather(s.R, s.T, s.L, s.M, G[..., :3].reshape(s.K, *s.M[::-1], 3).astype(np.float64))
+    G = rng.standard_normal((s.K, nm, 3)).astype(np.float32)
+    F_or = oracle.gather(s.R, s.T, s.L, s.M, G.reshape(s.K, *s.M[::-1], 3).astype(np.float64))
     mesh = hpf.hpf_mesh_make(s.L, s.M, s.N)
     F = torch.full((s.N, 3), 7.0, dtype=torch.float32, device="cuda")
     hpf.hpf_force_gather(dev(s.R, torch.float32), dev(s.T, torch.uint8), mesh, s.K,
@@ -306,8 +305,8 @@ def test_per_bead_kernels_ragged_sizes(n_chains, chain_len):
     s = wl.small_system(n_chains, chain_len, 9.0, 9, seed=n_chains + chain_len)
     rng = np.random.default_rng(1)
     nm = 9 ** 3
-    G = rng.standard_normal((2, nm, 4)).astype(np.float32)
-    F_or = oracle.gather(s.R, s.T, s.L, s.M, G[..., :3].reshape(2, 9, 9, 9, 3).astype(np.float64))
+    G = rng.standard_normal((2, nm, 3)).astype(np.float32)
+    F_or = oracle.gather(s.R, s.T, s.L, s.M, G.reshape(2, 9, 9, 9, 3).astype(np.float64))
     Fb_or, _ = oracle.bonds(s.R, s.bonds, s.k_bond, s.r0, s.L)
     mesh = hpf.hpf_mesh_make(s.L, s.M, s.N)
     R, T, Gd = dev(s.R, torch.float32), dev(s.T, torch.uint8), dev(G, torch.float32)
