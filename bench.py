@@ -226,6 +226,53 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
             "advance_kernel": "scatter" if st.uses_scatter_advance() else "plain"}
 
 
+def run_composition(steps=40, sort_every=20):
+    """The composition list (MD-SCF section) on a dilute five-species system: 10,000 lipids
+    (12 beads, species 0-3) in 1,080,000 waters (species 4), 1.2M beads. Whole steps (the
+    six calls with angles, sorted every `sort_every`, replayed from a HIP graph) and the
+    gradient pass alone, each with and without the list. The beads move identically either
+    way; the list only skips the gradient of species absent from a mesh point."""
+    import torch
+
+    from paper_1310_2041_amd import engine, hpf
+    from synth import workloads as wl
+
+    s = wl.lipid_system(10000, 1080000)
+    out = {"workload": "lipid_k5_dilute_1.2m", "beads": s.N, "species": s.K, "mesh": list(s.M)}
+    for name, listed in (("all_species", False), ("listed", True)):
+        st = engine.HpfState.from_system(s, composition_list=listed)
+        st.start(sort=True)
+
+        def seg():
+            for _ in range(steps):
+                st.step(report=True, sort=sort_every > 0 and st.steps_done % sort_every == 0)
+
+        g = engine.Graph(seg)
+        g.launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(g.stream)
+        g.launch()
+        e1.record(g.stream)
+        torch.cuda.synchronize()
+        step_ms = e0.elapsed_time(e1) / steps
+        del g
+        e0.record()
+        for _ in range(20):
+            hpf.hpf_field_gradient(st.V, st.mesh, st.K, st.G, present=st.present)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_step": step_ms, "gradient_us": e0.elapsed_time(e1) / 20 * 1e3}
+        if listed:
+            pr = st.present.cpu().numpy()
+            out["absent_point_species_fraction"] = float(
+                1.0 - sum(((pr >> k) & 1).mean() for k in range(s.K)) / s.K)
+        del st
+    out["note"] = ("six-call steps with angles (the fused passes take bonds only), graph-replayed; "
+                   "gradient_us: the gradient pass alone")
+    return out
+
+
 def run_batched_sweep(replays=5, sort_every=10, tune=True):
     """64 uneven A10B10 replicas: batched entry points vs one single-system call chain
     per replica, both with the sort interval the tuner picks, captured in HIP graphs of two
@@ -424,6 +471,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batched sweep")
+    ap.add_argument("--no-composition", action="store_true",
+                    help="skip the composition-list comparison on the dilute five-species system")
     ap.add_argument("--c5-steps", type=int, default=40,
                     help="steps of the 100M-bead three-species system reported under 'c5' (0 = skip)")
     ap.add_argument("--halo", type=int, default=2, help="drift halo (cells) of the brick deposit boxes")
@@ -525,6 +574,9 @@ def main():
                      "kernels": kernel_table(r5), "device_flags": r5["flags"]}
         del r5
         log(f"c5: {ms5:.4f} ms/step")
+    if not args.no_composition:
+        log("composition list: dilute five-species system")
+        out["composition_list"] = run_composition()
     if not args.no_batch:
         log("64-replica batched sweep")
         out["batched_sweep"] = run_batched_sweep()

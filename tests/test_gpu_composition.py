@@ -81,7 +81,8 @@ def test_runs_with_the_list_equal_runs_without():
 
 def test_gradient_time_with_and_without_the_list():
     """Measurement for the dilute five-species system at 1.2M beads: the gradient pass with
-    and without the composition list (printed; the benchmark reports the same comparison)."""
+    and without the composition list (printed; bench.py reports it with whole steps under
+    "composition_list")."""
     s = wl.lipid_system(10000, 1080000)
     st = engine.HpfState.from_system(s, composition_list=True)
     st.sort()
