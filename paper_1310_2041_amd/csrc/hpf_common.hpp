@@ -67,6 +67,34 @@ __device__ __forceinline__ bool bead_cell(const float3& r, const MeshK& m, BeadC
     return ok;
 }
 
+// Streaming accesses: data that a pass reads or writes once (its own bead rows, the
+// bond table, the stored deposit boxes) go through the caches with the nontemporal
+// hint, so that their lines are the first evicted and the gradient mesh and the bond
+// partners, which are read many times, stay in L2.
+__device__ __forceinline__ float3 load_stream(const float3* p)
+{
+    const float* q = reinterpret_cast<const float*>(p);
+    return make_float3(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1),
+                       __builtin_nontemporal_load(q + 2));
+}
+__device__ __forceinline__ void store_stream(float3* p, const float3& v)
+{
+    float* q = reinterpret_cast<float*>(p);
+    __builtin_nontemporal_store(v.x, q);
+    __builtin_nontemporal_store(v.y, q + 1);
+    __builtin_nontemporal_store(v.z, q + 2);
+}
+template <class T>
+__device__ __forceinline__ T load_stream(const T* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ __forceinline__ void store_stream(T* p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 __device__ __forceinline__ int32_t next_wrap(int32_t c, int32_t M) { return c + 1 == M ? 0 : c + 1; }
 __device__ __forceinline__ int32_t prev_wrap(int32_t c, int32_t M) { return c == 0 ? M - 1 : c - 1; }
 

@@ -559,14 +559,14 @@ __device__ __forceinline__ void bead_fetch(BeadIn& p, int64_t i, const float3* _
                                            const int32_t* __restrict__ bonds, int D, int64_t N,
                                            const float* __restrict__ inv_mass, const ThermoK& th)
 {
-    p.r = R[i];
-    p.v = Vel[i];
-    p.t = T[i];
+    p.r = R[i];                       // also read as bond partners: cached
+    p.v = load_stream(Vel + i);
+    p.t = load_stream(T + i);
     p.im = inv_mass ? inv_mass[i] : 1.0f;
     p.tag = (kThermo && th.thr) ? th.tag[i] : 0;
 #pragma unroll
     for (int b = 0; b < kPreBonds; ++b)
-        p.j[b] = b < D ? bonds[(int64_t)b * N + i] : -1;
+        p.j[b] = b < D ? load_stream(bonds + (int64_t)b * N + i) : -1;
 }
 
 struct BeadLoads {
@@ -655,8 +655,8 @@ __device__ __forceinline__ float3 bead_finish(int64_t i, const BeadIn& p, const 
     kick(v, f, p.im, hdt);               // v_{n+1/2}
     drift(r, v, dt, box);                // x_{n+1}
     nonfinite |= !(finite3(r) && finite3(v));
-    Vel[i] = v;
-    R_next[i] = r;
+    store_stream(Vel + i, v);
+    store_stream(R_next + i, r);
     return r;
 }
 
@@ -843,7 +843,7 @@ k_advance_scatter(
             __syncthreads();
             unsigned long long* out = partials + item * (int64_t)nbox;
             for (int q = threadIdx.x; q < nbox; q += kASThreads)
-                out[q] = dbox[q];
+                store_stream(out + q, dbox[q]);
         } else {
             const int64_t first = cell_start[tk.NK];
             for (int64_t i = first + threadIdx.x; i < N; i += kASThreads) {

@@ -16,7 +16,9 @@ import re
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhpf.so")
+# HPF_LIBRARY names another build of the same library (for comparing builds); the
+# in-tree one is the default.
+LIB_PATH = os.environ.get("HPF_LIBRARY") or os.path.join(_HERE, "libhpf.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "hpf.h")
 
 HPF_FIX_BITS = 16
