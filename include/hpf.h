@@ -490,12 +490,39 @@ hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N,
                               int32_t* bonds_out, uint32_t* cell_start, void* work,
                               size_t work_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * hpf_resort_by_cell -- the order and outputs of hpf_sort_by_cell, for beads
+ * that are in the order an earlier hpf_sort_by_cell / hpf_resort_by_cell with
+ * the same mesh and B produced (positions may have moved since; the storage
+ * order must not have changed). That sort's key starts come in as
+ * cell_start_in. Between sorts most beads keep their brick, so the order is
+ * built per brick rather than over the whole tag sequence: the beads that keep
+ * their brick stay in tag order, the others are sorted by tag per new brick,
+ * and the two lists are merged by tag. The work is a few passes in storage
+ * order whatever the number of bricks.
+ *
+ * Arguments as hpf_sort_by_cell, plus:
+ * cell_start_in   uint32[NK + 2] device, the earlier sort's key starts.
+ * cell_start_out  uint32[NK + 2] device, the new key starts (must not alias
+ *                 cell_start_in).
+ * work            as for hpf_sort_by_cell (hpf_sort_workspace_bytes).
+ * If the input is not in an earlier sort's order (a key range out of tag
+ * order), HPF_FLAG_SORT_ORDER is set and the output, while a set of valid
+ * indices, is not the sorted order.
+ * ------------------------------------------------------------------------- */
+hpf_status_t hpf_resort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N, const float* R_in,
+                                const float* Vel_in, const uint8_t* T_in, const int32_t* tag_in,
+                                const int32_t* bonds_in, int32_t D, float* R_out, float* Vel_out,
+                                uint8_t* T_out, int32_t* tag_out, int32_t* bonds_out,
+                                const uint32_t* cell_start_in, uint32_t* cell_start_out, void* work,
+                                size_t work_bytes, void* stream);
+
 /* hpf_sort_angles -- the per-bead angle table (angle_forces layout, int32[3A][N])
- * in the order of the hpf_sort_by_cell call that last used `work` (same mesh, B
- * and N, and `work` untouched since): rows are permuted with their beads, the
- * partner rows renumbered to the new storage indices, the code rows kept.
- * angles_out must not alias angles_in. Partners outside [-1, N) become -1 and
- * set HPF_FLAG_BAD_BOND. */
+ * in the order of the hpf_sort_by_cell or hpf_resort_by_cell call that last used
+ * `work` (same mesh, B and N, and `work` untouched since): rows are permuted with
+ * their beads, the partner rows renumbered to the new storage indices, the code
+ * rows kept. angles_out must not alias angles_in. Partners outside [-1, N) become
+ * -1 and set HPF_FLAG_BAD_BOND. */
 hpf_status_t hpf_sort_angles(const hpf_mesh_t* mesh, int32_t B, int64_t N, const int32_t* angles_in,
                              int32_t A, int32_t* angles_out, const void* work, size_t work_bytes,
                              void* stream);

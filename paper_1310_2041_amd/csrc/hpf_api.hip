@@ -513,6 +513,33 @@ hpf_status_t hpf_sort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N, cons
                        bonds_out, cell_start, static_cast<char*>(work), as_stream(stream));
 }
 
+hpf_status_t hpf_resort_by_cell(const hpf_mesh_t* mesh, int32_t B, int64_t N, const float* R_in,
+                                const float* Vel_in, const uint8_t* T_in, const int32_t* tag_in,
+                                const int32_t* bonds_in, int32_t D, float* R_out, float* Vel_out, uint8_t* T_out,
+                                int32_t* tag_out, int32_t* bonds_out, const uint32_t* cell_start_in,
+                                uint32_t* cell_start_out, void* work, size_t work_bytes, void* stream)
+{
+    if (!mesh_ok(mesh) || N < 0 || D < 0 || D > HPF_MAX_BONDS || !cell_start_in || !cell_start_out ||
+        cell_start_in == cell_start_out)
+        return HPF_EINVAL;
+    if (N > 0 && (!R_in || !T_in || !R_out || !T_out))
+        return HPF_EINVAL;
+    if (!Vel_in != !Vel_out || !tag_in != !tag_out || (N > 0 && D > 0 && (!bonds_in || !bonds_out)))
+        return HPF_EINVAL;
+    if (N > 0 && (R_in == R_out || (Vel_in && Vel_in == Vel_out) || T_in == T_out ||
+                  (tag_in && tag_in == tag_out) || (D > 0 && bonds_in == bonds_out)))
+        return HPF_EINVAL;
+    SortK sk;
+    SortPlan plan;
+    if (!sort_layout(N, mesh->M, B, &sk, &plan))
+        return HPF_EINVAL;
+    if (!work || work_bytes < plan.bytes)
+        return HPF_ESPACE;
+    sk.m = mesh_k(mesh);
+    return launch_resort(sk, plan, N, R_in, Vel_in, T_in, tag_in, bonds_in, D, R_out, Vel_out, T_out, tag_out,
+                         bonds_out, cell_start_in, cell_start_out, static_cast<char*>(work), as_stream(stream));
+}
+
 hpf_status_t hpf_sort_angles(const hpf_mesh_t* mesh, int32_t B, int64_t N, const int32_t* angles_in, int32_t A,
                              int32_t* angles_out, const void* work, size_t work_bytes, void* stream)
 {

@@ -367,6 +367,223 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_angles(const int32_t* __r
         raise_flag(HPF_FLAG_BAD_BOND);
 }
 
+// ------------------------------------------- re-sort from a previous order --
+//
+// Between sorts most beads stay in their brick. When the input is in the order an
+// earlier sort produced (ascending (key, tag) for the positions of that time) and
+// that sort's key starts are given, the new order is built per key instead of over
+// the whole tag sequence:
+//   1. per old key range, in storage order (coalesced): every bead's new key; the
+//      beads that keep their key ("stayers") are compacted in place, still in tag
+//      order; the others ("movers") are counted per new key;
+//   2. one scan gives the new key starts and each key's slot range for its movers;
+//   3. every mover is appended (tag, index) to its new key's slots;
+//   4. per new key: its movers are sorted by tag, and the stayers and the movers
+//      are merged by tag: an element's position is its rank in its own list plus
+//      the number of elements of the other list with a smaller tag (a binary
+//      search).
+// The result equals the stable counting sort's exactly: (key, tag) order.
+constexpr int kResortThreads = 256;
+constexpr int kPlaceThreads = 512;
+constexpr int kMoverCap = 4096;          // movers of one key sorted in LDS (32 KiB)
+
+__device__ __forceinline__ int32_t tag_of(const int32_t* __restrict__ tag, int64_t i)
+{
+    return tag ? tag[i] : (int32_t)i;
+}
+
+template <class Keyer>
+__global__ __launch_bounds__(kResortThreads) void k_resort_keys(Keyer keyer, const int32_t* __restrict__ tag,
+                                                                const uint32_t* __restrict__ cs_old, int64_t N,
+                                                                uint32_t* __restrict__ keyp,
+                                                                int32_t* __restrict__ stayidx,
+                                                                uint32_t* __restrict__ cnt_stay,
+                                                                uint32_t* __restrict__ cnt_move)
+{
+    __shared__ uint32_t sh[kResortThreads / kWave + 1];
+    const uint32_t k = blockIdx.x;
+    const int64_t a = min((int64_t)cs_old[k], N), b = min((int64_t)cs_old[k + 1], N);
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t run = 0;
+    bool bad = false;
+    for (int64_t base = a; base < b; base += kResortThreads) {
+        const int64_t i = base + threadIdx.x;
+        uint32_t key = kNoKey;
+        if (i < b) {
+            key = keyer((int32_t)i);
+            keyp[i] = key;
+            // the precondition: every old key range in ascending tag order
+            bad |= i > a && tag_of(tag, i) <= tag_of(tag, i - 1);
+        }
+        const bool stay = key == k;
+        uint32_t total;
+        const uint32_t r = block_excl_scan<kResortThreads>(stay ? 1u : 0u, sh, &total);
+        if (stay)
+            stayidx[a + run + r] = (int32_t)i;
+        run += total;
+        const bool mv = i < b && !stay;
+        const uint64_t grp = wave_key_group(key, mv);
+        if (mv && __builtin_ctzll(grp) == lane)
+            atomicAdd(cnt_move + key, (uint32_t)__builtin_popcountll(grp));
+    }
+    if (threadIdx.x == 0)
+        cnt_stay[k] = run;
+    if (bad)
+        raise_flag(HPF_FLAG_SORT_ORDER);
+}
+
+// One block: new key starts (stayers + movers per key, exclusive scan; the last entry
+// the total) and the movers' slot offsets (exclusive scan of the mover counts); the
+// slot fill counters are cleared.
+constexpr int kResortScanThreads = 1024;
+
+__global__ __launch_bounds__(kResortScanThreads) void k_resort_scan(const uint32_t* __restrict__ cnt_stay,
+                                                                    const uint32_t* __restrict__ cnt_move,
+                                                                    uint32_t nkeys, uint32_t* __restrict__ start,
+                                                                    uint32_t* __restrict__ moff,
+                                                                    uint32_t* __restrict__ fill)
+{
+    __shared__ uint32_t sh[kResortScanThreads / kWave + 1];
+    const uint32_t per = (nkeys + kResortScanThreads - 1) / kResortScanThreads;
+    const uint32_t k0 = min(nkeys, threadIdx.x * per), k1 = min(nkeys, k0 + per);
+    uint32_t st = 0, mv = 0;
+    for (uint32_t k = k0; k < k1; ++k) {
+        st += cnt_stay[k] + cnt_move[k];
+        mv += cnt_move[k];
+    }
+    uint32_t tot_st, tot_mv;
+    uint32_t run_st = block_excl_scan<kResortScanThreads>(st, sh, &tot_st);
+    uint32_t run_mv = block_excl_scan<kResortScanThreads>(mv, sh, &tot_mv);
+    for (uint32_t k = k0; k < k1; ++k) {
+        start[k] = run_st;
+        moff[k] = run_mv;
+        fill[k] = 0u;
+        run_st += cnt_stay[k] + cnt_move[k];
+        run_mv += cnt_move[k];
+    }
+    if (threadIdx.x == 0) {
+        start[nkeys] = tot_st;
+        moff[nkeys] = tot_mv;
+    }
+}
+
+// Movers appended to their new key's slots as (tag << 32 | index); their order inside
+// a key's slots is arbitrary (sorted in the placement).
+__global__ __launch_bounds__(kResortThreads) void k_resort_movers(const int32_t* __restrict__ tag,
+                                                                  const uint32_t* __restrict__ cs_old, int64_t N,
+                                                                  const uint32_t* __restrict__ keyp,
+                                                                  const uint32_t* __restrict__ moff,
+                                                                  uint32_t* __restrict__ fill,
+                                                                  unsigned long long* __restrict__ movers)
+{
+    const uint32_t k = blockIdx.x;
+    const int64_t a = min((int64_t)cs_old[k], N), b = min((int64_t)cs_old[k + 1], N);
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int64_t base = a; base < b; base += kResortThreads) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t key = i < b ? keyp[i] : kNoKey;
+        const bool mv = i < b && key != k;
+        const uint64_t grp = wave_key_group(key, mv);
+        const int leader = mv ? __builtin_ctzll(grp) : lane;
+        uint32_t slot = 0;
+        if (mv && leader == lane)
+            slot = atomicAdd(fill + key, (uint32_t)__builtin_popcountll(grp));
+        slot = __shfl(slot, leader, kWave);
+        if (mv) {
+            slot += (uint32_t)__builtin_popcountll(grp & ((1ull << lane) - 1));
+            movers[(int64_t)moff[key] + slot] =
+                ((unsigned long long)(uint32_t)tag_of(tag, i) << 32) | (unsigned long long)(uint32_t)i;
+        }
+    }
+}
+
+// Ascending sort of v[0, n) padded with +inf to p (a power of two): a bitonic network
+// whose comparators all put the smaller value first (the first step of every merge
+// compares mirrored positions), so the padding never moves forward. All threads call.
+template <class Load, class Store>
+__device__ __forceinline__ void sort_padded(int64_t n, int64_t p, Load load, Store store)
+{
+    for (int64_t size = 2; size <= p; size <<= 1) {
+        for (int64_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int64_t q = threadIdx.x; q < p / 2; q += blockDim.x) {
+                // the q-th comparator of this step: elements i < j
+                const int64_t blk = q / stride, off = q % stride;
+                int64_t i = blk * 2 * stride + off, j = i + stride;
+                if (stride == (size >> 1))
+                    j = (i / size) * size + size - 1 - (i % size);   // mirrored partner
+                if (j < n) {
+                    const unsigned long long a = load(i), c = load(j);
+                    if (c < a) {
+                        store(i, c);
+                        store(j, a);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Per new key: movers sorted by tag (in LDS when they fit, else in place in their
+// slots), then stayers and movers merged by tag into the key's output range.
+__global__ __launch_bounds__(kPlaceThreads) void k_resort_place(const int32_t* __restrict__ tag,
+                                                                const uint32_t* __restrict__ cs_old, int64_t N,
+                                                                const int32_t* __restrict__ stayidx,
+                                                                const uint32_t* __restrict__ cnt_stay,
+                                                                const uint32_t* __restrict__ cnt_move,
+                                                                const uint32_t* __restrict__ moff,
+                                                                const uint32_t* __restrict__ start,
+                                                                unsigned long long* __restrict__ movers,
+                                                                int32_t* __restrict__ perm)
+{
+    __shared__ unsigned long long smv[kMoverCap];
+    const uint32_t k = blockIdx.x;
+    const int64_t nmv = cnt_move[k], ns = cnt_stay[k];
+    const int64_t base = start[k];
+    unsigned long long* mv = movers + moff[k];
+    const int32_t* st = stayidx + min((int64_t)cs_old[k], N);
+    int64_t p2 = 1;
+    while (p2 < nmv)
+        p2 <<= 1;
+    const bool in_lds = nmv <= kMoverCap;
+    if (in_lds) {
+        for (int64_t q = threadIdx.x; q < nmv; q += kPlaceThreads)
+            smv[q] = mv[q];
+        __syncthreads();
+        sort_padded(nmv, p2, [&](int64_t q) { return smv[q]; }, [&](int64_t q, unsigned long long v) { smv[q] = v; });
+    } else {
+        sort_padded(nmv, p2, [&](int64_t q) { return mv[q]; }, [&](int64_t q, unsigned long long v) { mv[q] = v; });
+    }
+    // movers: rank among movers + stayers with a smaller tag
+    for (int64_t q = threadIdx.x; q < nmv; q += kPlaceThreads) {
+        const unsigned long long e = in_lds ? smv[q] : mv[q];
+        const int32_t t = (int32_t)(e >> 32);
+        int64_t lo = 0, hi = ns;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (tag_of(tag, st[mid]) < t)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        perm[base + q + lo] = (int32_t)(uint32_t)e;
+    }
+    // stayers: rank among stayers + movers with a smaller tag
+    for (int64_t q = threadIdx.x; q < ns; q += kPlaceThreads) {
+        const int32_t i = st[q];
+        const unsigned long long t = (unsigned long long)(uint32_t)tag_of(tag, i) << 32;
+        int64_t lo = 0, hi = nmv;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((in_lds ? smv[mid] : mv[mid]) < t)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        perm[base + q + lo] = i;
+    }
+}
+
 // ------------------------------------------------------------------ host --
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -377,6 +594,8 @@ struct SortPlan {
     uint32_t nkeys = 0;
     int64_t S = 0, nchunks = 0, ncb = 0, nscan = 0, ntiles = 0;
     size_t off_key = 0, off_perm = 0, off_idx = 0, off_table = 0, off_part = 0, off_tiles = 0, off_start = 0;
+    // re-sort from a previous order: compacted stayers, movers, per-key counts and offsets
+    size_t off_stay = 0, off_movers = 0, off_cstay = 0, off_cmove = 0, off_fill = 0, off_moff = 0;
     size_t bytes = 0;
 };
 
@@ -410,6 +629,12 @@ bool sort_plan(int64_t N, int64_t nkeys, SortPlan* p)
     p->off_part = o; o += align_up(sizeof(uint32_t) * (size_t)p->ncb * (size_t)nkeys);
     p->off_tiles = o; o += align_up(sizeof(uint32_t) * (size_t)(p->ntiles + 1));
     p->off_start = o; o += align_up(sizeof(uint32_t) * (size_t)(p->nscan + 1));
+    p->off_stay = o; o += align_up(sizeof(int32_t) * N1);
+    p->off_movers = o; o += align_up(sizeof(uint64_t) * N1);
+    p->off_cstay = o; o += align_up(sizeof(uint32_t) * (size_t)nkeys);
+    p->off_cmove = o; o += align_up(sizeof(uint32_t) * (size_t)nkeys);
+    p->off_fill = o; o += align_up(sizeof(uint32_t) * (size_t)nkeys);
+    p->off_moff = o; o += align_up(sizeof(uint32_t) * (size_t)(nkeys + 1));
     p->bytes = o;
     return true;
 }
@@ -503,6 +728,50 @@ hpf_status_t launch_sort(const SortK& sk, const SortPlan& pl, int64_t N, const f
     uint32_t* start = cell_start ? cell_start : reinterpret_cast<uint32_t*>(work + pl.off_start);
     return run_sort(pl, keyer, N, R_in, V_in, T_in, tag_in, bonds_in, D, R_out, V_out, T_out, tag_out, bonds_out,
                     start, work, s);
+}
+
+// The re-sort (steps 1-4 above), then the gather and the bond renumbering of run_sort.
+hpf_status_t launch_resort(const SortK& sk, const SortPlan& pl, int64_t N, const float* R_in, const float* V_in,
+                           const uint8_t* T_in, const int32_t* tag_in, const int32_t* bonds_in, int D, float* R_out,
+                           float* V_out, uint8_t* T_out, int32_t* tag_out, int32_t* bonds_out,
+                           const uint32_t* cs_old, uint32_t* cs_new, char* work, hipStream_t s)
+{
+    CellKeyer keyer{sk, reinterpret_cast<const float3*>(R_in)};
+    const uint32_t nk = pl.nkeys;
+    auto* keyp = reinterpret_cast<uint32_t*>(work + pl.off_key);
+    auto* perm = reinterpret_cast<int32_t*>(work + pl.off_perm);
+    auto* inv = reinterpret_cast<int32_t*>(work + pl.off_idx);
+    auto* stay = reinterpret_cast<int32_t*>(work + pl.off_stay);
+    auto* movers = reinterpret_cast<unsigned long long*>(work + pl.off_movers);
+    auto* cstay = reinterpret_cast<uint32_t*>(work + pl.off_cstay);
+    auto* cmove = reinterpret_cast<uint32_t*>(work + pl.off_cmove);
+    auto* fill = reinterpret_cast<uint32_t*>(work + pl.off_fill);
+    auto* moff = reinterpret_cast<uint32_t*>(work + pl.off_moff);
+    const unsigned gfill = (unsigned)std::min<int64_t>(grid_for(nk), 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(kSortThreads), 0, s, cmove, (int64_t)nk, 0u);
+    if (N > 0) {
+        // every output slot holds a valid index even if the input breaks the precondition
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, N);
+        hipLaunchKernelGGL(k_resort_keys<CellKeyer>, dim3(nk), dim3(kResortThreads), 0, s, keyer, tag_in, cs_old, N,
+                           keyp, stay, cstay, cmove);
+    } else {
+        hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(kSortThreads), 0, s, cstay, (int64_t)nk, 0u);
+    }
+    hipLaunchKernelGGL(k_resort_scan, dim3(1), dim3(kResortScanThreads), 0, s, cstay, cmove, nk, cs_new, moff, fill);
+    if (N > 0) {
+        hipLaunchKernelGGL(k_resort_movers, dim3(nk), dim3(kResortThreads), 0, s, tag_in, cs_old, N, keyp, moff, fill,
+                           movers);
+        hipLaunchKernelGGL(k_resort_place, dim3(nk), dim3(kPlaceThreads), 0, s, tag_in, cs_old, N, stay, cstay, cmove,
+                           moff, cs_new, movers, perm);
+        hipLaunchKernelGGL(k_sort_permute, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, N,
+                           reinterpret_cast<const float3*>(R_in), reinterpret_cast<const float3*>(V_in), T_in,
+                           tag_in, reinterpret_cast<float3*>(R_out), reinterpret_cast<float3*>(V_out), T_out,
+                           tag_out, inv);
+        if (D > 0 && bonds_in)
+            hipLaunchKernelGGL(k_sort_bonds, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, inv, N, bonds_in,
+                               D, bonds_out);
+    }
+    return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
 hpf_status_t launch_sort_angles(const SortPlan& pl, int64_t N, const int32_t* ang_in, int A, int32_t* ang_out,

@@ -26,6 +26,7 @@ N_ROWS = 7
 
 
 LDS_BYTES = 160 * 1024
+RESORT_MIN_BRICKS = 8192
 
 
 def auto_brick(M, K: int, halo: int) -> int:
@@ -124,6 +125,12 @@ class HpfState:
                                 dtype=torch.uint8, device=dev)
         self.cell_start = torch.empty(hpf.sort_key_count(self.mesh, self.B) + 2,
                                       dtype=torch.int32, device=dev)
+        self.cell_start2 = torch.empty_like(self.cell_start)
+        # Re-sort from the previous sort's order (hpf_resort_by_cell) once sorted. Its passes
+        # run one workgroup per brick, so it pays on meshes of many bricks (10^8 beads in
+        # 32,768 bricks: 7 ms against 40 ms for the full sort); with a few hundred large
+        # bricks the full sort is faster (0.48 against 0.84 ms for 10^7 beads in 512).
+        self.resort = hpf.sort_key_count(self.mesh, self.B) >= RESORT_MIN_BRICKS
         # the cell-list scatter needs every mesh edge >= B + 1 + 2*halo (0 bytes = unsupported)
         ws = hpf.hpf_scatter_workspace_bytes(self.N, self.mesh, self.K, self.B, self.halo)
         self.cells_ok = ws > 0
@@ -164,7 +171,8 @@ class HpfState:
         p, kT, seed, tag_offset = self.thermo
         return hpf.make_thermostat(p, kT, seed, self.tstep, self.tag, tag_offset)
 
-    _SWAPPED = ("R", "R2", "Vel", "Vel2", "T", "T2", "tag", "tag2", "bonds", "bonds2")
+    _SWAPPED = ("R", "R2", "Vel", "Vel2", "T", "T2", "tag", "tag2", "bonds", "bonds2", "cell_start",
+                "cell_start2", "angles", "angles2")
 
     def snapshot(self) -> dict:
         """The host-side stepping state (which buffers are current, the step count, whether a
@@ -190,11 +198,20 @@ class HpfState:
     # ---------------------------------------------------------------- pieces
 
     def sort(self, stream=None):
+        """Canonical (brick, tag) order. From the order of an earlier sort the incremental
+        re-sort builds the same order brick by brick; otherwise the full counting sort."""
         D = self.bonds.shape[0]
-        hpf.hpf_sort_by_cell(self.mesh, self.B, self.R, self.Vel, self.T, self.tag,
-                             self.bonds if D else None, self.R2, self.Vel2, self.T2, self.tag2,
-                             self.bonds2 if D else None, self.work, cell_start=self.cell_start,
-                             stream=stream)
+        if self.sorted and self.resort:
+            hpf.hpf_resort_by_cell(self.mesh, self.B, self.R, self.Vel, self.T, self.tag,
+                                   self.bonds if D else None, self.R2, self.Vel2, self.T2, self.tag2,
+                                   self.bonds2 if D else None, self.work, self.cell_start, self.cell_start2,
+                                   stream=stream)
+            self.cell_start, self.cell_start2 = self.cell_start2, self.cell_start
+        else:
+            hpf.hpf_sort_by_cell(self.mesh, self.B, self.R, self.Vel, self.T, self.tag,
+                                 self.bonds if D else None, self.R2, self.Vel2, self.T2, self.tag2,
+                                 self.bonds2 if D else None, self.work, cell_start=self.cell_start,
+                                 stream=stream)
         self.R, self.R2 = self.R2, self.R
         self.Vel, self.Vel2 = self.Vel2, self.Vel
         self.T, self.T2 = self.T2, self.T

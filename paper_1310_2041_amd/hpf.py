@@ -137,6 +137,8 @@ _SIGNATURES = {
     "hpf_sort_workspace_bytes": ([C.c_int64, C.POINTER(Mesh), C.c_int32], C.c_size_t),
     "hpf_sort_by_cell": ([C.POINTER(Mesh), C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
                           _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int32),
+    "hpf_resort_by_cell": ([C.POINTER(Mesh), C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
+                            _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int32),
     "hpf_get_device_status": ([C.POINTER(C.c_uint32), C.c_int32, _P], C.c_int32),
     "hpf_batch_workspace_bytes": ([C.POINTER(Replica), C.c_int32, C.POINTER(BatchConfig)],
                                   C.c_size_t),
@@ -498,6 +500,31 @@ def sort_key_count(mesh: Mesh, B: int = 8) -> int:
     for d in range(3):
         n *= (mesh.M[d] + B - 1) // B
     return n
+
+
+def hpf_resort_by_cell(mesh: Mesh, B: int, R_in, Vel_in, T_in, tag_in, bonds_in, R_out, Vel_out,
+                       T_out, tag_out, bonds_out, work, cell_start_in, cell_start_out, stream=None):
+    N = R_in.shape[0]
+    D = bonds_in.shape[0] if bonds_in is not None else 0
+    nk = sort_key_count(mesh, B)
+    args = [
+        _dev(R_in, "R_in", torch.float32, (N, 3)),
+        _dev(Vel_in, "Vel_in", torch.float32, (N, 3), allow_none=True),
+        _dev(T_in, "T_in", torch.uint8, (N,)),
+        _dev(tag_in, "tag_in", torch.int32, (N,), allow_none=True),
+        _dev(bonds_in, "bonds_in", torch.int32, (D, N), allow_none=True) if D else None,
+        int(D),
+        _dev(R_out, "R_out", torch.float32, (N, 3)),
+        _dev(Vel_out, "Vel_out", torch.float32, (N, 3), allow_none=True),
+        _dev(T_out, "T_out", torch.uint8, (N,)),
+        _dev(tag_out, "tag_out", torch.int32, (N,), allow_none=True),
+        _dev(bonds_out, "bonds_out", torch.int32, (D, N), allow_none=True) if D else None,
+        _dev(cell_start_in, "cell_start_in", torch.int32, (nk + 2,)),
+        _dev(cell_start_out, "cell_start_out", torch.int32, (nk + 2,)),
+    ]
+    w = _dev(work, "work", torch.uint8)
+    _check("hpf_resort_by_cell",
+           lib().hpf_resort_by_cell(C.byref(mesh), int(B), N, *args, w, work.numel(), _stream(stream)))
 
 
 def hpf_sort_by_cell(mesh: Mesh, B: int, R_in, Vel_in, T_in, tag_in, bonds_in, R_out, Vel_out,
