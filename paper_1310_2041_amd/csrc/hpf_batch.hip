@@ -281,8 +281,8 @@ __global__ __launch_bounds__(kPThreads) void k_batch_advance(const RepK* __restr
 // k_advance_scatter), one workgroup per (replica, brick) item of the last
 // sort; a replica's last item (brick == NK) holds the beads the sort could
 // not bin, deposited with global atomics. The energy partials go to the
-// item's slot.
-template <bool kR0Zero, bool kPipe, bool kThermo>
+// item's slot. kNT as in k_advance_scatter, chosen on the bytes of the whole batch.
+template <bool kR0Zero, bool kPipe, bool kThermo, bool kNT>
 __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
     const RepK* __restrict__ reps, const ItemK* __restrict__ items, int B, int h, int K,
     const float3* __restrict__ R, float3* __restrict__ R_next, float3* __restrict__ Vel,
@@ -323,16 +323,16 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
             int64_t i = first + threadIdx.x;
             BeadIn cur;
             if (i < last)
-                bead_fetch<kThermo>(cur, i, R, Vel, T, bonds, D, Ntot, nullptr, th);
+                bead_fetch<kThermo, kNT>(cur, i, R, Vel, T, bonds, D, Ntot, nullptr, th);
             for (; i < last; i += kASThreadsBatch) {
                 BeadLoads L;
                 bead_issue(L, cur, i, m, K, Gr, R, Ntot);
                 __builtin_amdgcn_sched_barrier(0);
                 BeadIn nxt;
-                bead_fetch<kThermo>(nxt, min(i + kASThreadsBatch, last - 1), R, Vel, T, bonds, D, Ntot, nullptr,
+                bead_fetch<kThermo, kNT>(nxt, min(i + kASThreadsBatch, last - 1), R, Vel, T, bonds, D, Ntot, nullptr,
                                     th);
                 __builtin_amdgcn_sched_barrier(0);
-                const float3 rn = bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, Ntot, D, k, r0, rp.box, dt,
+                const float3 rn = bead_finish<kR0Zero, kThermo, kNT>(i, cur, L, R_next, Vel, Ntot, D, k, r0, rp.box, dt,
                                                                 hdt,
                                                        nullptr, acc, e, bad_bead, bad_bond, nonfinite, th, tstep);
                 const int t = cur.t;
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
         __syncthreads();
         unsigned long long* out = partials + (rp.brick_off + brick) * (int64_t)nbox;
         for (int q = threadIdx.x; q < nbox; q += kASThreadsBatch)
-            out[q] = dbox[q];
+            store_hint<kNT>(out + q, dbox[q]);
     } else {
         const int64_t first = cs[rp.NK], last = min((int64_t)cs[rp.NK + 1], Ntot);
         for (int64_t i = first + threadIdx.x; i < last; i += kASThreadsBatch) {
@@ -736,6 +736,19 @@ static hpf_status_t batch_fields(hpf_batch* b, bool report, hipStream_t s)
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
+using BatchAdvFn = void (*)(const RepK*, const ItemK*, int, int, int, const float3*, float3*, float3*,
+                            const uint8_t*, int64_t, const float3*, const int32_t*, int, float, float, float,
+                            const uint32_t*, unsigned long long*, unsigned long long*, double*, double*, int, ThermoK);
+
+template <bool kPipe, bool kNT>
+static BatchAdvFn batch_advance_fn(bool thermo, bool r0z)
+{
+    return thermo ? (r0z ? k_batch_advance_scatter<true, kPipe, true, kNT>
+                         : k_batch_advance_scatter<false, kPipe, true, kNT>)
+                  : (r0z ? k_batch_advance_scatter<true, kPipe, false, kNT>
+                         : k_batch_advance_scatter<false, kPipe, false, kNT>);
+}
+
 static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipStream_t s)
 {
     const BatchLayout& L = b->L;
@@ -768,21 +781,14 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
         const int P = c.brick + 1 + 2 * c.halo;
         const size_t smem = sizeof(unsigned long long) * (size_t)c.K * P * P * P;
         // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
-        using AdvFn = void (*)(const RepK*, const ItemK*, int, int, int, const float3*, float3*, float3*,
-                               const uint8_t*, int64_t, const float3*, const int32_t*, int, float, float, float,
-                               const uint32_t*, unsigned long long*, unsigned long long*, double*, double*, int,
-                               ThermoK);
         const bool pipe = c.D <= kPreBonds;
-        const bool thermo = th.thr != 0;
-        const AdvFn fn =
-            thermo ? (c.r0 == 0.0f ? (pipe ? k_batch_advance_scatter<true, true, true>
-                                           : k_batch_advance_scatter<true, false, true>)
-                                   : (pipe ? k_batch_advance_scatter<false, true, true>
-                                           : k_batch_advance_scatter<false, false, true>))
-                   : (c.r0 == 0.0f ? (pipe ? k_batch_advance_scatter<true, true, false>
-                                           : k_batch_advance_scatter<true, false, false>)
-                                   : (pipe ? k_batch_advance_scatter<false, true, false>
-                                           : k_batch_advance_scatter<false, false, false>));
+        const bool thermo = th.thr != 0, r0z = c.r0 == 0.0f;
+        const int64_t bytes = L.Ntot * (49 + 4 * (int64_t)std::min(c.D, kPreBonds)) + L.nm_tot * c.K * 12 +
+                              (int64_t)smem * L.bricks_tot;
+        const bool nt = pipe && bytes > kStreamHintBytes;
+        const BatchAdvFn fn = pipe ? (nt ? batch_advance_fn<true, true>(thermo, r0z)
+                                    : batch_advance_fn<true, false>(thermo, r0z))
+                              : batch_advance_fn<false, false>(thermo, r0z);
         if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
             return HPF_EINVAL;

@@ -95,6 +95,29 @@ __device__ __forceinline__ void store_stream(T* p, T v)
     __builtin_nontemporal_store(v, p);
 }
 
+// kNT selects the hint. It pays only where a pass streams more than the 256 MB Infinity
+// Cache keeps from one step to the next; on smaller systems the next step finds the bead
+// rows there, and the hint would push them out.
+template <bool kNT, class T>
+__device__ __forceinline__ T load_hint(const T* p)
+{
+    if constexpr (kNT)
+        return load_stream(p);
+    else
+        return *p;
+}
+template <bool kNT, class T>
+__device__ __forceinline__ void store_hint(T* p, const T& v)
+{
+    if constexpr (kNT)
+        store_stream(p, v);
+    else
+        *p = v;
+}
+// Bytes a fused pass streams above which it takes the hint: half the Infinity Cache, as the
+// step also reads and writes the mesh arrays and the other position buffer.
+constexpr int64_t kStreamHintBytes = int64_t(128) << 20;
+
 __device__ __forceinline__ int32_t next_wrap(int32_t c, int32_t M) { return c + 1 == M ? 0 : c + 1; }
 __device__ __forceinline__ int32_t prev_wrap(int32_t c, int32_t M) { return c == 0 ? M - 1 : c - 1; }
 

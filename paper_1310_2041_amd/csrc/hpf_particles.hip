@@ -553,20 +553,20 @@ struct BeadIn {
     int32_t j[kPreBonds];
 };
 
-template <bool kThermo>
+template <bool kThermo, bool kNT>
 __device__ __forceinline__ void bead_fetch(BeadIn& p, int64_t i, const float3* __restrict__ R,
                                            const float3* __restrict__ Vel, const uint8_t* __restrict__ T,
                                            const int32_t* __restrict__ bonds, int D, int64_t N,
                                            const float* __restrict__ inv_mass, const ThermoK& th)
 {
     p.r = R[i];                       // also read as bond partners: cached
-    p.v = load_stream(Vel + i);
-    p.t = load_stream(T + i);
+    p.v = load_hint<kNT>(Vel + i);
+    p.t = load_hint<kNT>(T + i);
     p.im = inv_mass ? inv_mass[i] : 1.0f;
     p.tag = (kThermo && th.thr) ? th.tag[i] : 0;
 #pragma unroll
     for (int b = 0; b < kPreBonds; ++b)
-        p.j[b] = b < D ? load_stream(bonds + (int64_t)b * N + i) : -1;
+        p.j[b] = b < D ? load_hint<kNT>(bonds + (int64_t)b * N + i) : -1;
 }
 
 struct BeadLoads {
@@ -594,7 +594,7 @@ __device__ __forceinline__ void bead_issue(BeadLoads& L, const BeadIn& p, int64_
     }
 }
 
-template <bool kR0Zero, bool kThermo>
+template <bool kR0Zero, bool kThermo, bool kNT>
 __device__ __forceinline__ float3 bead_finish(int64_t i, const BeadIn& p, const BeadLoads& L,
                                               float3* __restrict__ R_next, float3* __restrict__ Vel, int64_t N,
                                               int D, float k, float r0, const BoxK& box, float dt, float hdt,
@@ -655,8 +655,8 @@ __device__ __forceinline__ float3 bead_finish(int64_t i, const BeadIn& p, const 
     kick(v, f, p.im, hdt);               // v_{n+1/2}
     drift(r, v, dt, box);                // x_{n+1}
     nonfinite |= !(finite3(r) && finite3(v));
-    store_stream(Vel + i, v);
-    store_stream(R_next + i, r);
+    store_hint<kNT>(Vel + i, v);
+    store_hint<kNT>(R_next + i, r);
     return r;
 }
 
@@ -666,7 +666,7 @@ __device__ __forceinline__ float3 bead_finish(int64_t i, const BeadIn& p, const 
 // (4% faster at 10M beads than 256); the general loop keeps kPThreads.
 constexpr int kAdvPipeThreads = 512;
 
-template <bool kR0Zero, bool kPipe, bool kThermo>
+template <bool kR0Zero, bool kPipe, bool kThermo, bool kNT>
 __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float3* __restrict__ R,
                                                        float3* __restrict__ R_next,
                                                        float3* __restrict__ Vel,
@@ -695,16 +695,16 @@ __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float3* __res
         int64_t i = w.first + threadIdx.x;
         BeadIn cur;
         if (i < w.end)
-            bead_fetch<kThermo>(cur, i, R, Vel, T, bonds, D, N, inv_mass, th);
+            bead_fetch<kThermo, kNT>(cur, i, R, Vel, T, bonds, D, N, inv_mass, th);
         for (; i < w.end; i += w.stride) {
             BeadLoads L;
             bead_issue(L, cur, i, m, K, G, R, N);
             __builtin_amdgcn_sched_barrier(0);
             BeadIn nxt;
-            bead_fetch<kThermo>(nxt, i + w.stride < w.end ? i + w.stride : i, R, Vel, T, bonds, D, N, inv_mass,
+            bead_fetch<kThermo, kNT>(nxt, i + w.stride < w.end ? i + w.stride : i, R, Vel, T, bonds, D, N, inv_mass,
                                 th);
             __builtin_amdgcn_sched_barrier(0);
-            bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt, F_out, acc, e,
+            bead_finish<kR0Zero, kThermo, kNT>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt, F_out, acc, e,
                                           bad_bead, bad_bond, nonfinite, th, tstep);
             cur = nxt;
         }
@@ -743,11 +743,12 @@ __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float3* __res
 // per SIMD); with the software-pipelined loop this measured faster than 256
 // threads at every mesh size tried, and a small mesh still fills the chip.
 // kPipe selects the software-pipelined bead loop (bond tables of at most
-// kPreBonds rows); the plain loop serves wider tables.
+// kPreBonds rows); the plain loop serves wider tables. kNT puts the nontemporal
+// hint on the pipelined loop's streamed data and on the stored deposit boxes.
 constexpr int kASThreadsDefault = 512;
 constexpr int kASThreadsWide = 768;
 
-template <bool kR0Zero, int kASThreads, bool kPipe, bool kThermo>
+template <bool kR0Zero, int kASThreads, bool kPipe, bool kThermo, bool kNT>
 // The second bound is waves per SIMD. The production form (512 threads, r0 = 0, no
 // thermostat) keeps two workgroups per CU, 4 waves per SIMD (at most 128 VGPRs, which it
 // fits without spilling); the others take 3 (at most 168), as does a 768-thread workgroup,
@@ -804,15 +805,15 @@ k_advance_scatter(
                 int64_t i = first + threadIdx.x;
                 BeadIn cur;
                 if (i < last)
-                    bead_fetch<kThermo>(cur, i, R, Vel, T, bonds, D, N, inv_mass, th);
+                    bead_fetch<kThermo, kNT>(cur, i, R, Vel, T, bonds, D, N, inv_mass, th);
                 for (; i < last; i += kASThreads) {
                     BeadLoads L;
                     bead_issue(L, cur, i, m, K, G, R, N);
                     __builtin_amdgcn_sched_barrier(0);
                     BeadIn nxt;
-                    bead_fetch<kThermo>(nxt, min(i + kASThreads, last - 1), R, Vel, T, bonds, D, N, inv_mass, th);
+                    bead_fetch<kThermo, kNT>(nxt, min(i + kASThreads, last - 1), R, Vel, T, bonds, D, N, inv_mass, th);
                     __builtin_amdgcn_sched_barrier(0);
-                    const float3 rn = bead_finish<kR0Zero, kThermo>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt,
+                    const float3 rn = bead_finish<kR0Zero, kThermo, kNT>(i, cur, L, R_next, Vel, N, D, k, r0, box, dt, hdt,
                                                            F_out, acc, e, bad_bead, bad_bond, nonfinite, th,
                                                            tstep);
                     const int t = cur.t;
@@ -843,7 +844,7 @@ k_advance_scatter(
             __syncthreads();
             unsigned long long* out = partials + item * (int64_t)nbox;
             for (int q = threadIdx.x; q < nbox; q += kASThreads)
-                store_stream(out + q, dbox[q]);
+                store_hint<kNT>(out + q, dbox[q]);
         } else {
             const int64_t first = cell_start[tk.NK];
             for (int64_t i = first + threadIdx.x; i < N; i += kASThreads) {
@@ -946,6 +947,24 @@ hpf_status_t launch_verlet(float* R, float* Vel, const float* F, const float* in
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
+// Bytes one fused pass streams: bead rows read and written, the bond slots it
+// prefetches, the gradient mesh and the stored deposit boxes.
+static int64_t streamed_bytes(int64_t N, int D, int K, const MeshK& m, int64_t box_bytes)
+{
+    return N * (49 + 4 * (int64_t)std::min(D, kPreBonds)) + (int64_t)K * m.nm * 12 + box_bytes;
+}
+
+using AdvFn = void (*)(const float3*, float3*, float3*, const uint8_t*, int64_t, MeshK, int, const float3*,
+                       const int32_t*, int, float, float, BoxK, const float*, float, float3*, double*, double*,
+                       ThermoK);
+
+template <bool kPipe, bool kNT>
+static AdvFn advance_fn(bool thermo, bool r0z)
+{
+    return thermo ? (r0z ? k_advance<true, kPipe, true, kNT> : k_advance<false, kPipe, true, kNT>)
+                  : (r0z ? k_advance<true, kPipe, false, kNT> : k_advance<false, kPipe, false, kNT>);
+}
+
 hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
                             const MeshK& m, int K, const float* G, const int32_t* bonds, int D, float k,
                             float r0, const BoxK& box, const float* inv_mass, float dt, float* F_out,
@@ -964,21 +983,16 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
     auto* Vp = reinterpret_cast<float3*>(Vel);
     auto* Gp = reinterpret_cast<const float3*>(G);
     auto* Fo = reinterpret_cast<float3*>(F_out);
-    using AdvFn = void (*)(const float3*, float3*, float3*, const uint8_t*, int64_t, MeshK, int, const float3*,
-                           const int32_t*, int, float, float, BoxK, const float*, float, float3*, double*, double*,
-                           ThermoK);
-    const bool thermo = th.thr != 0;
-    const AdvFn fn =
-        thermo ? (r0 == 0.0f ? (pipe ? k_advance<true, true, true> : k_advance<true, false, true>)
-                             : (pipe ? k_advance<false, true, true> : k_advance<false, false, true>))
-               : (r0 == 0.0f ? (pipe ? k_advance<true, true, false> : k_advance<true, false, false>)
-                             : (pipe ? k_advance<false, true, false> : k_advance<false, false, false>));
+    const bool thermo = th.thr != 0, r0z = r0 == 0.0f;
+    const bool nt = pipe && streamed_bytes(N, D, K, m, 0) > kStreamHintBytes;
+    const AdvFn fn = pipe ? (nt ? advance_fn<true, true>(thermo, r0z) : advance_fn<true, false>(thermo, r0z))
+                          : advance_fn<false, false>(thermo, r0z);
     hipLaunchKernelGGL(fn, g, bl, 0, s, Rp, Rn, Vp, T, N, m, K, Gp, bonds, D, k, r0, box, inv_mass, dt, Fo,
                        e_part, kin_part, th);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
 }
 
-template <bool kR0Zero, int kThreads, bool kPipe, bool kThermo>
+template <bool kR0Zero, int kThreads, bool kPipe, bool kThermo, bool kNT>
 static hpf_status_t launch_advance_scatter_t(const float3* Rp, float3* Rn, float3* Vp, const uint8_t* T, int64_t N,
                                              const TileK& tk, int K, const float3* Gp, const int32_t* bonds, int D,
                                              float k, float r0, const BoxK& box, const float* inv_mass, float dt,
@@ -987,7 +1001,7 @@ static hpf_status_t launch_advance_scatter_t(const float3* Rp, float3* Rn, float
                                              double* kin_part, const ThermoK& th, hipStream_t s)
 {
     const size_t smem = sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P;
-    const void* fn = reinterpret_cast<const void*>(k_advance_scatter<kR0Zero, kThreads, kPipe, kThermo>);
+    const void* fn = reinterpret_cast<const void*>(k_advance_scatter<kR0Zero, kThreads, kPipe, kThermo, kNT>);
     if (smem > 65536 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
         return HPF_EINVAL;
@@ -995,10 +1009,27 @@ static hpf_status_t launch_advance_scatter_t(const float3* Rp, float3* Rn, float
     // uneven bricks; larger meshes walk their bricks with HPF_NPART workgroups
     const int64_t nb = std::min<int64_t>(tk.ntiles + 1, HPF_NPART);
     const dim3 g((unsigned)nb), bl(kThreads);
-    hipLaunchKernelGGL((k_advance_scatter<kR0Zero, kThreads, kPipe, kThermo>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk,
+    hipLaunchKernelGGL((k_advance_scatter<kR0Zero, kThreads, kPipe, kThermo, kNT>), g, bl, smem, s, Rp, Rn, Vp, T, N, tk,
                        K, Gp, bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo, e_part, kin_part,
                        th);
     return hipGetLastError() == hipSuccess ? HPF_OK : HPF_EHIP;
+}
+
+using LaunchFn = hpf_status_t (*)(const float3*, float3*, float3*, const uint8_t*, int64_t, const TileK&, int,
+                                  const float3*, const int32_t*, int, float, float, const BoxK&, const float*, float,
+                                  const uint32_t*, unsigned long long*, unsigned long long*, float3*, double*,
+                                  double*, const ThermoK&, hipStream_t);
+
+template <bool kPipe, bool kNT>
+static LaunchFn scatter_launch_fn(bool wide, bool thermo, bool r0z)
+{
+    if (wide)
+        return launch_advance_scatter_t<true, kASThreadsWide, kPipe, false, kNT>;
+    if (r0z)
+        return thermo ? launch_advance_scatter_t<true, kASThreadsDefault, kPipe, true, kNT>
+                      : launch_advance_scatter_t<true, kASThreadsDefault, kPipe, false, kNT>;
+    return thermo ? launch_advance_scatter_t<false, kASThreadsDefault, kPipe, true, kNT>
+                  : launch_advance_scatter_t<false, kASThreadsDefault, kPipe, false, kNT>;
 }
 
 hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, const uint8_t* T, int64_t N,
@@ -1019,24 +1050,11 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
     // CU: with r0 = 0 and no thermostat the pass then takes 768 threads (3 waves per SIMD;
     // 1024 threads would cap it at 128 VGPRs, which spills); the others keep 512.
     const bool wide = r0z && !thermo && sizeof(unsigned long long) * (size_t)K * tk.P * tk.P * tk.P > 80 * 1024;
-    using LaunchFn = hpf_status_t (*)(const float3*, float3*, float3*, const uint8_t*, int64_t, const TileK&, int,
-                                      const float3*, const int32_t*, int, float, float, const BoxK&, const float*,
-                                      float, const uint32_t*, unsigned long long*, unsigned long long*, float3*,
-                                      double*, double*, const ThermoK&, hipStream_t);
-    LaunchFn launch;
-    if (wide)
-        launch = pipe ? launch_advance_scatter_t<true, kASThreadsWide, true, false>
-                      : launch_advance_scatter_t<true, kASThreadsWide, false, false>;
-    else if (r0z)
-        launch = pipe ? (thermo ? launch_advance_scatter_t<true, kASThreadsDefault, true, true>
-                                : launch_advance_scatter_t<true, kASThreadsDefault, true, false>)
-                      : (thermo ? launch_advance_scatter_t<true, kASThreadsDefault, false, true>
-                                : launch_advance_scatter_t<true, kASThreadsDefault, false, false>);
-    else
-        launch = pipe ? (thermo ? launch_advance_scatter_t<false, kASThreadsDefault, true, true>
-                                : launch_advance_scatter_t<false, kASThreadsDefault, true, false>)
-                      : (thermo ? launch_advance_scatter_t<false, kASThreadsDefault, false, true>
-                                : launch_advance_scatter_t<false, kASThreadsDefault, false, false>);
+    const int64_t box_bytes = (int64_t)sizeof(unsigned long long) * K * tk.P * tk.P * tk.P * tk.ntiles;
+    const bool nt = pipe && streamed_bytes(N, D, K, tk.m, box_bytes) > kStreamHintBytes;
+    const LaunchFn launch = pipe ? (nt ? scatter_launch_fn<true, true>(wide, thermo, r0z)
+                                       : scatter_launch_fn<true, false>(wide, thermo, r0z))
+                                 : scatter_launch_fn<false, false>(wide, thermo, r0z);
     return launch(Rp, Rn, Vp, T, N, tk, K, Gp, bonds, D, k, r0, box, inv_mass, dt, cell_start, partials, counts, Fo,
                   e_part, kin_part, th, s);
 }
