@@ -465,7 +465,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--also", default="c2", help="second workload reported under 'also' ('' = none)")
-    ap.add_argument("--sort-every", type=int, default=20)
+    ap.add_argument("--sort-every", type=int, default=30)
     ap.add_argument("--mode", default="fused", choices=["fused", "api"],
                     help="fused: hpf_advance; api: the six separate calls")
     ap.add_argument("--cpu-steps", type=int, default=8)

@@ -780,8 +780,9 @@ static hpf_status_t batch_particles(hpf_batch* b, bool prime, bool report, hipSt
     if (fused) {
         const int P = c.brick + 1 + 2 * c.halo;
         const size_t smem = sizeof(unsigned long long) * (size_t)c.K * P * P * P;
-        // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
-        const bool pipe = c.D <= kPreBonds;
+        // the software-pipelined bead loop serves bond tables of up to kPreBonds rows and
+        // gradient meshes (all replicas) of up to kBufMeshBytes
+        const bool pipe = c.D <= kPreBonds && L.nm_tot * c.K * 12 <= kBufMeshBytes;
         const bool thermo = th.thr != 0, r0z = c.r0 == 0.0f;
         const int64_t bytes = L.Ntot * (49 + 4 * (int64_t)std::min(c.D, kPreBonds)) + L.nm_tot * c.K * 12 +
                               (int64_t)smem * L.bricks_tot;

@@ -124,6 +124,32 @@ __device__ __forceinline__ void corners_global(const BeadCell& b, int t, const M
     g[7] = Gk[r11 + x1];
 }
 
+// corners_global with 32-bit offsets into one buffer resource over the gradient mesh
+// (at most kBufMeshBytes, which the launches check): the offsets need no 64-bit address
+// arithmetic and keep fewer registers live while the loads are in flight.
+constexpr int64_t kBufMeshBytes = 0x7fffffff;
+
+__device__ __forceinline__ void corners_buffer(const BeadCell& b, int t, const MeshK& m,
+                                               const float3* __restrict__ G, float3 (&g)[8])
+{
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float3*>(G), 0, (int)kBufMeshBytes, 0x00020000);
+    const uint32_t Mx = m.M[0], My = m.M[1];
+    const uint32_t x0 = b.c[0], x1 = next_wrap(b.c[0], m.M[0]);
+    const uint32_t y0 = b.c[1], y1 = next_wrap(b.c[1], m.M[1]);
+    const uint32_t z0 = b.c[2], z1 = next_wrap(b.c[2], m.M[2]);
+    const uint32_t tb = (uint32_t)t * (uint32_t)m.nm;
+    const uint32_t r00 = tb + (z0 * My + y0) * Mx, r10 = tb + (z0 * My + y1) * Mx;
+    const uint32_t r01 = tb + (z1 * My + y0) * Mx, r11 = tb + (z1 * My + y1) * Mx;
+    const uint32_t off[8] = {r00 + x0, r00 + x1, r10 + x0, r10 + x1, r01 + x0, r01 + x1, r11 + x0, r11 + x1};
+    typedef float v3f __attribute__((ext_vector_type(3)));
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const v3f v = __builtin_amdgcn_raw_buffer_load_b96(rs, (int)(off[a] * 12u), 0, 0);
+        g[a] = make_float3(v.x, v.y, v.z);
+    }
+}
+
 // Field force on one bead (eq. 6). False (and zero force) for a bead that
 // cannot be binned or has a type >= K.
 __device__ __forceinline__ bool field_force(const float3& r, int t, const MeshK& m, int K,
@@ -247,7 +273,10 @@ struct KinAcc {
     double ke = 0.0, px = 0.0, py = 0.0, pz = 0.0;
     __device__ __forceinline__ void add(const float3& v, float im)
     {
-        const double mass = 1.0 / (double)im;
+        // beads of unit mass (every bead when no masses are given) skip the FP64 division
+        double mass = 1.0;
+        if (im != 1.0f)
+            mass = 1.0 / (double)im;
         const double vx = v.x, vy = v.y, vz = v.z;
         ke += 0.5 * mass * (vx * vx + vy * vy + vz * vz);
         px += mass * vx;
@@ -576,8 +605,8 @@ struct BeadLoads {
     bool ok;
 };
 
-// Cell of the bead, its 8 corner loads (a bead that cannot be binned loads the
-// corners of cell 0 and gets no field force) and its partner loads (an index
+// Cell of the bead, its 8 corner loads (corners_buffer; a bead that cannot be binned
+// loads the corners of cell 0 and gets no field force) and its partner loads (an index
 // outside [0, N) loads the bead itself; the bond is then skipped or flagged).
 __device__ __forceinline__ void bead_issue(BeadLoads& L, const BeadIn& p, int64_t i, const MeshK& m, int K,
                                            const float3* __restrict__ G, const float3* __restrict__ R, int64_t N)
@@ -586,7 +615,7 @@ __device__ __forceinline__ void bead_issue(BeadLoads& L, const BeadIn& p, int64_
     BeadCell c = L.b;
     if (!L.ok)
         c.c[0] = c.c[1] = c.c[2] = 0;
-    corners_global(c, L.ok ? p.t : 0, m, G, L.g);
+    corners_buffer(c, L.ok ? p.t : 0, m, G, L.g);
 #pragma unroll
     for (int b = 0; b < kPreBonds; ++b) {
         const int32_t j = p.j[b];
@@ -743,8 +772,9 @@ __global__ __launch_bounds__(kAdvPipeThreads) void k_advance(const float3* __res
 // per SIMD); with the software-pipelined loop this measured faster than 256
 // threads at every mesh size tried, and a small mesh still fills the chip.
 // kPipe selects the software-pipelined bead loop (bond tables of at most
-// kPreBonds rows); the plain loop serves wider tables. kNT puts the nontemporal
-// hint on the pipelined loop's streamed data and on the stored deposit boxes.
+// kPreBonds rows, gradient meshes of at most kBufMeshBytes); the plain loop serves
+// the others. kNT puts the nontemporal hint on the pipelined loop's streamed data
+// and on the stored deposit boxes.
 constexpr int kASThreadsDefault = 512;
 constexpr int kASThreadsWide = 768;
 
@@ -972,8 +1002,9 @@ hpf_status_t launch_advance(const float* R, float* R_next, float* Vel, const uin
 {
     if (N == 0 && !e_part && !kin_part)
         return HPF_OK;
-    // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
-    const bool pipe = D <= kPreBonds;
+    // the software-pipelined bead loop serves bond tables of up to kPreBonds rows and
+    // gradient meshes of up to kBufMeshBytes
+    const bool pipe = D <= kPreBonds && (int64_t)K * m.nm * 12 <= kBufMeshBytes;
     const int threads = pipe ? kAdvPipeThreads : kPThreads;
     const int64_t cap = (e_part || kin_part) ? HPF_NPART : (1 << 20);
     const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((N + threads - 1) / threads, cap));
@@ -1044,8 +1075,10 @@ hpf_status_t launch_advance_scatter(const float* R, float* R_next, float* Vel, c
     auto* Vp = reinterpret_cast<float3*>(Vel);
     auto* Gp = reinterpret_cast<const float3*>(G);
     auto* Fo = reinterpret_cast<float3*>(F_out);
-    // the software-pipelined bead loop serves bond tables of up to kPreBonds rows
-    const bool pipe = D <= kPreBonds, thermo = th.thr != 0, r0z = r0 == 0.0f;
+    // the software-pipelined bead loop serves bond tables of up to kPreBonds rows and
+    // gradient meshes of up to kBufMeshBytes
+    const bool pipe = D <= kPreBonds && (int64_t)K * tk.m.nm * 12 <= kBufMeshBytes;
+    const bool thermo = th.thr != 0, r0z = r0 == 0.0f;
     // A deposit box of more than 80 KiB (16-cell bricks) leaves room for one workgroup per
     // CU: with r0 = 0 and no thermostat the pass then takes 768 threads (3 waves per SIMD;
     // 1024 threads would cap it at 128 VGPRs, which spills); the others keep 512.

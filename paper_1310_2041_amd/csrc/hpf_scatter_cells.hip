@@ -80,28 +80,40 @@ __device__ __forceinline__ bool brick_box_cell(const BeadCell& b, const MeshK& m
     return lx >= 0 && lx <= ox - 1 + 2 * h && ly >= 0 && ly <= oy - 1 + 2 * h && lz >= 0 && lz <= oz - 1 + 2 * h;
 }
 
+// yz * q for yz <= 2^32 and q < 2^16, exactly: two products of at most 17 x 16 bits,
+// which the 24-bit multiplier forms at full rate.
+__device__ __forceinline__ uint64_t mul_w16(uint64_t yz, uint32_t q)
+{
+    const uint32_t yh = (uint32_t)(yz >> HPF_FIX_BITS) & 0x1ffffu, yl = (uint32_t)yz & 0xffffu;
+    return ((uint64_t)(yh * q) << HPF_FIX_BITS) + (uint64_t)(yl * q);
+}
+
 // Adds one bead's 8 fixed-point corner weights to species t of an LDS box of
 // P^3 points at local cell (lx, ly, lz). The corner weights come from two
 // products: with w0 = 2^S - w1 per axis, W(0, ., .) = 2^S W_yz - W(1, ., .),
-// and likewise along y and z.
+// and likewise along y and z. Every q is below 2^16 (cell_coord), so the masks
+// change nothing; they let the compiler use the 24-bit multiplier.
+
 __device__ __forceinline__ void box_deposit(unsigned long long* box, int P, int t, int lx, int ly, int lz,
                                             const BeadCell& b)
 {
     const int P2 = P * P;
-    const uint64_t yz11 = (uint64_t)b.q[1] * b.q[2];
-    const uint64_t yz01 = ((uint64_t)b.q[2] << HPF_FIX_BITS) - yz11;   // wy0 wz1
-    const uint64_t yz10 = ((uint64_t)b.q[1] << HPF_FIX_BITS) - yz11;   // wy1 wz0
+    const uint32_t q0 = b.q[0] & 0xffffu, q1 = b.q[1] & 0xffffu, q2 = b.q[2] & 0xffffu;
+    const uint32_t yz11 = q1 * q2;
+    const uint32_t yz01 = (q2 << HPF_FIX_BITS) - yz11;   // wy0 wz1
+    const uint32_t yz10 = (q1 << HPF_FIX_BITS) - yz11;   // wy1 wz0
     const uint64_t yz00 = ((uint64_t)kOne << HPF_FIX_BITS) - yz11 - yz01 - yz10;
     unsigned long long* c0 = box + t * P2 * P + (lz * P + ly) * P + lx;
-    const uint64_t q0 = b.q[0];
-    lds_add_u64(c0, (yz00 << HPF_FIX_BITS) - yz00 * q0);
-    lds_add_u64(c0 + 1, yz00 * q0);
-    lds_add_u64(c0 + P, (yz10 << HPF_FIX_BITS) - yz10 * q0);
-    lds_add_u64(c0 + P + 1, yz10 * q0);
-    lds_add_u64(c0 + P2, (yz01 << HPF_FIX_BITS) - yz01 * q0);
-    lds_add_u64(c0 + P2 + 1, yz01 * q0);
-    lds_add_u64(c0 + P2 + P, (yz11 << HPF_FIX_BITS) - yz11 * q0);
-    lds_add_u64(c0 + P2 + P + 1, yz11 * q0);
+    const uint64_t a00 = mul_w16(yz00, q0), a10 = mul_w16(yz10, q0);
+    const uint64_t a01 = mul_w16(yz01, q0), a11 = mul_w16(yz11, q0);
+    lds_add_u64(c0, (yz00 << HPF_FIX_BITS) - a00);
+    lds_add_u64(c0 + 1, a00);
+    lds_add_u64(c0 + P, ((uint64_t)yz10 << HPF_FIX_BITS) - a10);
+    lds_add_u64(c0 + P + 1, a10);
+    lds_add_u64(c0 + P2, ((uint64_t)yz01 << HPF_FIX_BITS) - a01);
+    lds_add_u64(c0 + P2 + 1, a01);
+    lds_add_u64(c0 + P2 + P, ((uint64_t)yz11 << HPF_FIX_BITS) - a11);
+    lds_add_u64(c0 + P2 + P + 1, a11);
 }
 
 // Pass 1: one workgroup per brick deposits the beads listed in that brick --

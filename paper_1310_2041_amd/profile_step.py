@@ -1,6 +1,6 @@
 """Short fused-step run used as the target of rocprofv3 counter passes.
 
-python -m paper_1310_2041_amd.profile_step [--config c3|c4] [--steps 12] [--halo 2] [--brick 0 (auto)] [--sort-every 20]
+python -m paper_1310_2041_amd.profile_step [--config c3|c4] [--steps 12] [--halo 2] [--brick 0 (auto)] [--sort-every 30]
 
 c1..c3: the workload's start, the first half step and `steps` fused steps
 (reporting energies every step) in the benchmark's configuration (deposit
@@ -29,7 +29,7 @@ def main():
     ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--halo", type=int, default=2)
     ap.add_argument("--brick", type=int, default=0)
-    ap.add_argument("--sort-every", type=int, default=20)
+    ap.add_argument("--sort-every", type=int, default=30)
     args = ap.parse_args()
     import torch
 
