@@ -170,9 +170,12 @@ __device__ __forceinline__ double finish_potential_brick(Cover (&cov)[3][kTcMaxB
         const Cover& cz = cov[2][iz];
         const int64_t dst = ((int64_t)(bxyz[2] * B + iz) * My + (bxyz[1] * B + iy)) * Mx + bxyz[0] * B + ix;
         unsigned long long n[K];
+        bool held = false;
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
             n[k] = counts[(int64_t)k * nm + dst];
+            held |= n[k] != 0ull;
+        }
         if (cover2_ok(cx, cy, cz)) {
             const Cover2 c2 = cover2(cx, cy, cz);
 #pragma unroll
@@ -187,9 +190,12 @@ __device__ __forceinline__ double finish_potential_brick(Cover (&cov)[3][kTcMaxB
                             n[k] += partials[cz.off[a] + cy.off[b2] + cx.off[c] + (int64_t)k * P3];
                     }
         }
+        // the counts are cleared where they held anything (the few points that beads
+        // outside their boxes reached); the others are zero already
+        if (held)
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            counts[(int64_t)k * nm + dst] = 0ull;
+            for (int k = 0; k < K; ++k)
+                counts[(int64_t)k * nm + dst] = 0ull;
         if (present)
             present[dst] = composition<K>(n);
         wsum += potential_values<K>(n, V, nm, dst, m.c_norm, p, over);
