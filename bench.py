@@ -333,6 +333,8 @@ def run_batched_sweep(replays=5, sort_every=10, tune=True):
             "speedup": ms_plain / ms_batched, "tuned": chosen,
             "tune_trial_ms": [round(t, 4) for t in trials],
             "tune_margin": round(srt[1] / srt[0] - 1.0, 4) if len(srt) > 1 else None,
+            "tune_vs_median": round(srt[len(srt) // 2] / srt[0] - 1.0, 4) if srt else None,
+            "tune_vs_worst": round(srt[-1] / srt[0] - 1.0, 4) if srt else None,
             "note": "both paths replayed from HIP graphs of %d steps, sort every %d" %
                     (steps_per_graph, sort_every)}
 
