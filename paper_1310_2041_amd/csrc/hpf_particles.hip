@@ -809,20 +809,7 @@ k_advance_scatter(
     const int B = tk.B, P = tk.P, h = tk.h;
     const int P3 = P * P * P;
     const int nbox = K * P3;
-    // When the pass streams more than the Infinity Cache holds (kNT) and has one item per
-    // workgroup, workgroup b takes item b: the dispatcher then spreads neighbouring bricks
-    // over the XCDs, which balances regions of uneven density (C3: 2 us faster than
-    // contiguous runs per XCD). Otherwise each XCD takes a contiguous run of bricks, which
-    // then share its L2: for a walk over several items (C5: 3.1 against 3.6 ms) and for a
-    // system inside the Infinity Cache (C2: 1 us faster).
-    BrickWalk w;
-    if (kNT && (int64_t)gridDim.x > tk.ntiles) {
-        w.first = blockIdx.x;
-        w.end = tk.ntiles + 1;
-        w.stride = gridDim.x;
-    } else {
-        w = brick_walk(tk.ntiles + 1);
-    }
+    const BrickWalk w = brick_walk(tk.ntiles + 1);
     const float hdt = 0.5f * dt;
     KinAcc acc;
     double e = 0.0;
