@@ -174,6 +174,7 @@ def run_workload(cfg, steps, warmup, sort_every, instrument=True, fused=True, gr
 
     spec = wl.SPECS[cfg]
     s = wl.build(spec)
+    KEEP_SYSTEMS.setdefault(cfg, [s]) if cfg in KEEP_SYSTEMS_FOR else None
     st = engine.HpfState.from_system(s, halo=halo, advance=advance, field_every=field_every,
                                      sort_brick=brick)
     if thermostat > 0.0:
@@ -284,6 +285,7 @@ def run_batched_sweep(replays=5, sort_every=10, tune=True):
 
     specs = wl.replica_specs()
     systems = [wl.build_replica(sp, r) for r, sp in enumerate(specs)]
+    KEEP_SYSTEMS.setdefault("c4", systems) if "c4" in KEEP_SYSTEMS_FOR else None
     n_beads = sum(s.N for s in systems)
 
     batch = engine.BatchState(systems, sort_every=sort_every)
@@ -427,6 +429,54 @@ def cpu_baseline(cfg, n_steps):
                       f"{t1:.1f} s on one thread; host {info['model']}, nproc {info['nproc']}"}
 
 
+# host systems that the GPU runs built, kept for the oracle timings (filled when the oracle
+# timings are requested, so that C4 and C5 are not built twice)
+KEEP_SYSTEMS_FOR = set()
+KEEP_SYSTEMS = {}
+
+
+def oracle_timings(threads=None):
+    """The FP64 oracle on every other workload, on all the threads this process may use:
+    C1 and C2 for 100 steps, the 64 C4 replicas for 10 steps each, C5 for one step; C1 also
+    on one thread. Each figure is the time of run(n) less that of run(0) (the initial force
+    evaluation and set-up), both after an untimed run(0) except for C5."""
+    import oracle
+    from synth import workloads as wl
+
+    threads = threads or int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
+
+    def timed(systems, n_steps, th):
+        total = 0.0
+        for s in systems:
+            if s.N <= 10_000_000:
+                oracle.run(s, 0, threads=th)          # untimed: first-touch of its buffers
+            t0 = time.perf_counter()
+            oracle.run(s, 0, threads=th)
+            t_force = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            oracle.run(s, n_steps, threads=th)
+            total += max(time.perf_counter() - t0 - t_force, 1e-9)
+        return total
+
+    out = {}
+    for cfg, n_steps in (("c1", 100), ("c2", 100), ("c4", 10), ("c5", 1)):
+        systems = KEEP_SYSTEMS.pop(cfg, None)
+        if systems is None and cfg == "c4":
+            systems = [wl.build_replica(sp, r) for r, sp in enumerate(wl.replica_specs())]
+        elif systems is None:
+            systems = [wl.build(wl.SPECS[cfg])]
+        n = sum(s.N for s in systems)
+        t = timed(systems, n_steps, threads)
+        row = {"beads": n, "steps": n_steps, "seconds": round(t, 3), "threads": threads,
+               "value": n * n_steps / t, "unit": "particle-steps/s"}
+        if cfg == "c1":
+            t1 = timed(systems, n_steps, None)
+            row["single_thread_value"] = n * n_steps / t1
+        out[cfg] = row
+        del systems
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -475,7 +525,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batched sweep")
     ap.add_argument("--no-composition", action="store_true",
                     help="skip the composition-list comparison on the dilute five-species system")
-    ap.add_argument("--c5-steps", type=int, default=40,
+    ap.add_argument("--c5-steps", type=int, default=120,
                     help="steps of the 100M-bead three-species system reported under 'c5' (0 = skip)")
     ap.add_argument("--halo", type=int, default=2, help="drift halo (cells) of the brick deposit boxes")
     ap.add_argument("--brick", type=int, default=0,
@@ -502,6 +552,8 @@ def main():
     torch.cuda.set_device(0)
 
     fused = args.mode == "fused"
+    if not args.no_cpu_baseline:
+        KEEP_SYSTEMS_FOR.update({"c4", "c5"})
     log(f"{args.config}: {args.warmup} warm-up + {args.steps} timed steps")
     r = run_workload(args.config, args.steps, args.warmup, args.sort_every, fused=fused,
                      graph=not args.eager, halo=args.halo, advance=args.advance,
@@ -562,8 +614,8 @@ def main():
                                          "value above rebuilds it every step (NVE)"}
         log(f"field interval {args.field_interval}: {r3['ms_total'] / args.steps:.4f} ms/step")
     if args.c5_steps > 0:
-        log(f"c5: building the 100M-bead system, {min(args.warmup, 5)} warm-up + {args.c5_steps} steps")
-        r5 = run_workload("c5", args.c5_steps, min(args.warmup, 5), args.sort_every, instrument=True,
+        log(f"c5: building the 100M-bead system, {args.warmup} warm-up + {args.c5_steps} steps")
+        r5 = run_workload("c5", args.c5_steps, args.warmup, args.sort_every, instrument=True,
                           fused=fused, graph=not args.eager, halo=args.halo, advance=args.advance,
                      brick=args.brick)
         ms5 = r5["ms_total"] / args.c5_steps
@@ -585,6 +637,8 @@ def main():
     if not args.no_cpu_baseline:
         log(f"oracle on the host: {args.cpu_steps} steps of {args.config}")
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps)
+        log("oracle on the host: c1, c2, c4, c5")
+        out["cpu_baseline"]["other_workloads"] = oracle_timings(out["cpu_baseline"]["cores"])
     print(json.dumps(out), flush=True)
 
 
