@@ -614,10 +614,11 @@ hpf_status_t hpf_batch_current(const hpf_batch_t* batch, float** R, float** Vel,
  * not changed, so stepping continues as if the call had not been made. */
 hpf_status_t hpf_batch_density(hpf_batch_t* batch, uint64_t* counts_out, void* stream);
 /* Autotuner of the launch shape on the live system. Candidates: the fused deposit
- * with deposit halo {1, 2} x sort interval {5, 10, 20}, and the separate scatter
- * with halo {1, 2} x bead_chunk {2048, 4096} (sort every 10). Each candidate
- * runs three times from a fresh sort for trial_steps steps rounded up to a
- * multiple of 20; its time is the median of the three, and the fastest is kept.
+ * with deposit halo {1, 2} x sort interval {5, 10, 20, 30, 40}, and the separate
+ * scatter with halo {1, 2} x bead_chunk {2048, 4096} (sort every 10). Each
+ * candidate runs three times from a fresh sort for trial_steps steps (at least
+ * 20) rounded up to a multiple of its sort interval; its time is the median of
+ * the three, and the fastest is kept.
  * trial_ms (nullable, >= 32 floats) receives the medians (ms per step) in
  * candidate order and *n_trials their count. The choice is cached per process
  * by replica set (sizes, meshes, K, D, brick) and device: a later call for the

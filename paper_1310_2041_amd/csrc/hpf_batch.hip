@@ -1094,14 +1094,14 @@ hpf_status_t hpf_batch_tune(hpf_batch_t* b, int32_t trial_steps, void* stream, h
         }
     }
     // Each candidate runs from a fresh sort for a whole number of its sort intervals (trial
-    // steps rounded up to a multiple of 20), three times; its time is the median.
+    // steps, at least 20, rounded up to a multiple of the interval), three times; its time
+    // is the median.
     constexpr int kRepeats = 3;
-    const int steps = ((std::max(trial_steps, 20) + 19) / 20) * 20;
     std::vector<hpf_batch_config_t> cands;
     for (int hb : {1, 2}) {
         if (hb >= b->cfg.brick)
             continue;
-        for (int se : {5, 10, 20}) {
+        for (int se : {5, 10, 20, 30, 40}) {
             hpf_batch_config_t c = b->cfg;
             c.halo = hb;
             c.sort_every = se;
@@ -1134,6 +1134,8 @@ hpf_status_t hpf_batch_tune(hpf_batch_t* b, int32_t trial_steps, void* stream, h
         b->cfg = c;
         if ((st = batch_build_items(b)) != HPF_OK)
             break;
+        const int every = c.sort_every > 0 ? c.sort_every : 1;
+        const int steps = (std::max(trial_steps, 20) + every - 1) / every * every;
         float rep[kRepeats];
         for (int r = 0; r < kRepeats && st == HPF_OK; ++r) {
             b->steps_done = 0;                         // the trial starts with a sort

@@ -110,10 +110,14 @@ def test_batch_tune_keeps_trajectories():
     a.start()
     b.start()
     chosen, times = a.tune(trial_steps=20)
-    assert len(times) == 10 and all(t > 0 for t in times)
+    assert len(times) == 14 and all(t > 0 for t in times)
     assert chosen["halo"] in (1, 2) and chosen["fuse_deposit"] in (0, 1)
-    assert chosen["sort_every"] in (5, 10, 20)
-    b.step(len(times) * 3 * 20, report_last=False)
+    assert chosen["sort_every"] in (5, 10, 20, 30, 40)
+    # per halo: the fused deposit with sort intervals 5, 10, 20, 30, 40 and the separate
+    # scatter with two chunk sizes (sort every 10); each trial runs at least 20 steps,
+    # rounded up to whole sort intervals, three times
+    per_halo = sum(-(-20 // se) * se for se in (5, 10, 20, 30, 40)) + 2 * 20
+    b.step(2 * per_halo * 3, report_last=False)
     for r in range(len(systems)):
         ra, rb = a.replica_beads(r), b.replica_beads(r)
         ta, tb = ra[3], rb[3]
