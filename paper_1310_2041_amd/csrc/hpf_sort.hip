@@ -8,10 +8,10 @@
 // most bond partners are adjacent in memory. The order is produced by a
 // stable counting sort of the beads taken in tag order, so beads of one key
 // come out in tag order with no sorting inside a key:
-//   1. idx[tag[i]] = i;
-//   2. the tag sequence is cut into chunks of S tags; per chunk each bead's
-//      key is formed and a key histogram is counted in LDS and stored as one
-//      row of a chunk x key table;
+//   1. in storage order: idx[tag[i]] = i and key_t[tag[i]] = the key of bead i;
+//   2. the tag sequence is cut into chunks of S tags; per chunk a key
+//      histogram is counted in LDS and stored as one row of a chunk x key
+//      table;
 //   3. a column-wise exclusive scan of that table, taken in key-major order,
 //      gives every (chunk, key) pair its first output slot, and the key
 //      starts (cell_start);
@@ -113,22 +113,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_add(uint32_t* __restrict_
         a[i] += tile_sums[i / kScanTile];
 }
 
-// ------------------------------------------------------ 1. tag -> index --
-
-__global__ __launch_bounds__(kSortThreads) void k_tag_index(const int32_t* __restrict__ tag, int64_t N,
-                                                            int32_t* __restrict__ idx)
-{
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
-    if (i >= N)
-        return;
-    const int32_t t = tag ? tag[i] : (int32_t)i;
-    if (t < 0 || t >= N)
-        raise_flag(HPF_FLAG_SORT_ORDER);
-    else
-        idx[t] = (int32_t)i;
-}
-
-// --------------------------------------------- 2. keys and chunk histograms --
+// ------------------------------------------------------------------ keys --
 
 // Sort key of bead i of one system.
 struct CellKeyer {
@@ -141,8 +126,31 @@ struct CellKeyer {
     }
 };
 
+// ------------------------------------------ 1. tag -> index, and the keys --
+
+// In storage order (coalesced reads of the positions): idx[tag] = i and key_t[tag] = the
+// key of bead i. Tags missing from a broken permutation keep stale entries; the histogram
+// pass finds them by idx < 0 (idx is filled with -1 first) and sets their key to none.
 template <class Keyer>
-__global__ __launch_bounds__(kChunkThreads) void k_sort_hist(Keyer keyer, const int32_t* __restrict__ idx,
+__global__ __launch_bounds__(kSortThreads) void k_tag_index(Keyer keyer, const int32_t* __restrict__ tag,
+                                                            int64_t N, int32_t* __restrict__ idx,
+                                                            uint32_t* __restrict__ key_t)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kSortThreads + threadIdx.x;
+    if (i >= N)
+        return;
+    const int32_t t = tag ? tag[i] : (int32_t)i;
+    if (t < 0 || t >= N) {
+        raise_flag(HPF_FLAG_SORT_ORDER);
+    } else {
+        idx[t] = (int32_t)i;
+        key_t[t] = keyer((int32_t)i);
+    }
+}
+
+// ------------------------------------------------------ 2. chunk histograms --
+
+__global__ __launch_bounds__(kChunkThreads) void k_sort_hist(const int32_t* __restrict__ idx,
                                                              int64_t N, int64_t S, uint32_t nkeys,
                                                              uint32_t* __restrict__ key_t,
                                                              uint32_t* __restrict__ table)
@@ -159,12 +167,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_sort_hist(Keyer keyer, const 
         const int64_t t = base + threadIdx.x;
         uint32_t key = kNoKey;
         if (t < t1) {
-            const int32_t i = idx[t];
-            if (i >= 0)
-                key = keyer(i);
-            else
+            if (idx[t] >= 0) {
+                key = key_t[t];
+            } else {
                 missing = true;
-            key_t[t] = key;
+                key_t[t] = kNoKey;
+            }
         }
         const bool act = key != kNoKey;
         const uint64_t grp = wave_key_group(key, act);
@@ -681,7 +689,7 @@ hpf_status_t run_sort(const SortPlan& pl, Keyer keyer, int64_t N, const float* R
     const uint32_t nk = pl.nkeys;
     const size_t smem = sizeof(uint32_t) * nk;
     if (smem > 65536 &&
-        (hipFuncSetAttribute(reinterpret_cast<const void*>(k_sort_hist<Keyer>),
+        (hipFuncSetAttribute(reinterpret_cast<const void*>(k_sort_hist),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess ||
          hipFuncSetAttribute(reinterpret_cast<const void*>(k_sort_place), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)smem) != hipSuccess))
@@ -692,8 +700,9 @@ hpf_status_t run_sort(const SortPlan& pl, Keyer keyer, int64_t N, const float* R
         hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(grid_for(N), 4096)), dim3(kSortThreads), 0, s,
                            reinterpret_cast<uint32_t*>(idx), N, 0xffffffffu);
         hipLaunchKernelGGL(k_iota, dim3(grid_for(N)), dim3(kSortThreads), 0, s, perm, N);
-        hipLaunchKernelGGL(k_tag_index, dim3(grid_for(N)), dim3(kSortThreads), 0, s, tag_in, N, idx);
-        hipLaunchKernelGGL(k_sort_hist<Keyer>, dim3((unsigned)pl.nchunks), dim3(kChunkThreads), smem, s, keyer, idx,
+        hipLaunchKernelGGL(k_tag_index<Keyer>, dim3(grid_for(N)), dim3(kSortThreads), 0, s, keyer, tag_in, N, idx,
+                           key_t);
+        hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)pl.nchunks), dim3(kChunkThreads), smem, s, idx,
                            N, pl.S, nk, key_t, table);
         const dim3 gcol((nk + kSortThreads - 1) / kSortThreads, (unsigned)pl.ncb);
         hipLaunchKernelGGL(k_col_partial, gcol, dim3(kSortThreads), 0, s, table, pl.nchunks, nk, part);
