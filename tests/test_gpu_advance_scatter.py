@@ -186,3 +186,31 @@ def test_advance_scatter_bond_rows_beyond_two():
     assert torch.equal(Va.view(torch.int32), Vb.view(torch.int32))
     assert torch.equal(ca, cb)
     assert hpf.hpf_get_device_status() == 0
+
+
+def test_fused_step_on_a_gradient_mesh_beyond_2_gib_equals_six_calls():
+    """A gradient mesh of more than 2 GiB (4 species on 384^3 points: 2.7 GB) takes the fused
+    passes' plain bead loop, since the pipelined loop addresses the mesh with 32-bit offsets;
+    the fused steps must still move every bead as the six separate calls do, bit for bit.
+    12-cell bricks keep the sort within its key limit; halo 0 sends every bead that left its
+    brick through the global atomics."""
+    M, K = 384, 4
+    assert K * M ** 3 * 12 > 2 ** 31
+    s = wl.small_system(4000, 10, 300.0, M, K=K, seed=5, n_solvent=10000)
+    a = engine.HpfState.from_system(s, sort_brick=12, halo=0)
+    a.start(sort=True)
+    Ea = a.run(3, report_every=1, sort_every=2)
+    a.prime()
+    b = engine.HpfState.from_system(s, sort_brick=12, halo=0)
+    b.start(sort=True)
+    b.prime()
+    Eb = b.run_fused(3, report_every=1, sort_every=2)
+    assert b.uses_scatter_advance()
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
+    for ea, eb in zip(Ea, Eb):
+        for key in ("KE", "E_bond", "W"):
+            assert eb[key] == pytest.approx(ea[key], rel=1e-12)
+    assert hpf.hpf_get_device_status() == 0
+    del a, b
+    torch.cuda.empty_cache()
