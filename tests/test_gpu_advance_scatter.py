@@ -125,6 +125,27 @@ def test_potential_cells_equals_finish_then_potential(name, make, B, halo):
     assert hpf.hpf_get_device_status() == 0
 
 
+def test_engine_fused_deposit_16_cell_bricks():
+    """The engine's fused deposit with 16-cell bricks (768-thread workgroups) and one-cell
+    halos, over two sort intervals, equals hpf_advance + a fresh scatter every step: beads
+    bit for bit, W to FP64 regrouping; the mesh edge 23 leaves partial bricks."""
+    s = wl.small_system(1500, 12, 26.1, (24, 23, 26), seed=65)
+    a = engine.HpfState.from_system(s, advance="plain", sort_brick=16, halo=1)
+    b = engine.HpfState.from_system(s, advance="scatter", sort_brick=16, halo=1)
+    for st in (a, b):
+        st.start(sort=True)
+        st.prime()
+    ea = a.run_fused(40, report_every=1, sort_every=20)
+    eb = b.run_fused(40, report_every=1, sort_every=20)
+    assert b.uses_scatter_advance() and b.density_pending
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
+    for x, y in zip(ea, eb):
+        for key in ("KE", "E_bond", "W"):
+            assert y[key] == pytest.approx(x[key], rel=1e-12)
+    assert hpf.hpf_get_device_status() == 0
+
+
 @pytest.mark.parametrize("cfg", ["c1", "c2"])
 def test_engine_fused_deposit_matches_plain_steps(cfg):
     """Stepping with the fused deposit equals stepping with hpf_advance + a fresh scatter:
