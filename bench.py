@@ -341,19 +341,21 @@ def run_batched_sweep(replays=5, sort_every=10, tune=True):
                     (steps_per_graph, sort_every)}
 
 
-# rocprofv3 kernel names behind each timed call of the step
+# rocprofv3 kernel names behind each timed call of the step: a template name stands for
+# every instantiation of that kernel ("name<"), a plain name for itself
 ROCPROF_KERNELS = {
-    "advance": ["hpf::k_advance<%s, %s, %s>" % (r0, pipe, th) for r0 in ("true", "false")
-                for pipe in ("true", "false") for th in ("true", "false")] +
-               ["hpf::k_advance_scatter<%s, %d, %s, %s>" % (r0, n, pipe, th) for r0 in ("true", "false")
-                for n in (512, 768) for pipe in ("true", "false") for th in ("true", "false")],
+    "advance": ["hpf::k_advance<", "hpf::k_advance_scatter<"],
     "density_scatter": ["hpf::k_zero_u32_one", "hpf::k_scatter_bricks", "hpf::k_scatter_sum<false>",
                         "hpf::k_scatter_strays"],
     "density_finish": ["hpf::k_scatter_sum<true>"],
-    "finish_potential": ["hpf::k_finish_potential<%d>" % k for k in range(1, 9)],
-    "field_potential": ["hpf::k_field_potential<%d>" % k for k in range(1, 9)],
+    "finish_potential": ["hpf::k_finish_potential<"],
+    "field_potential": ["hpf::k_field_potential<"],
     "field_gradient": ["hpf::k_field_gradient"],
 }
+
+
+def rocprof_matches(pattern: str, name: str) -> bool:
+    return name.startswith(pattern) if pattern.endswith("<") else name == pattern
 
 
 def step_bandwidth(r, ms_step):
@@ -378,9 +380,10 @@ def measured_traffic(workload: str, kernel: str):
     if d is None or d.get("source_hash") != source_hash():
         return None
     tot, found = 0.0, False
-    for k in ROCPROF_KERNELS.get(kernel, []):
-        e = d["kernels"].get(k)
-        if e and e.get("fetch_bytes") is not None and e.get("write_bytes") is not None:
+    for name, e in d["kernels"].items():
+        if not any(rocprof_matches(p, name) for p in ROCPROF_KERNELS.get(kernel, [])):
+            continue
+        if e.get("fetch_bytes") is not None and e.get("write_bytes") is not None:
             tot += e["fetch_bytes"] + e["write_bytes"]
             found = True
     return tot if found else None
