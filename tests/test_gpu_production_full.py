@@ -111,6 +111,32 @@ def test_10m_blend_interval_fused_equals_six_calls_bitwise():
     assert hpf.hpf_get_device_status() == 0
 
 
+@pytest.mark.slow
+def test_10m_blend_every_step_fused_equals_six_calls_bitwise():
+    """The benchmarked configuration: the 10M-bead blend with the field rebuilt every step,
+    16-cell bricks (768-thread depositing workgroups), a deposit halo of 2 and a sort every
+    6 steps, 14 steps: the depositing pass and the fused finish + potential move every bead
+    bit for bit as the six separate calls do, with energies to FP64 regrouping."""
+    s = wl.build(wl.SPECS["c3"])
+    a = engine.HpfState.from_system(s, halo=2)
+    b = engine.HpfState.from_system(s, halo=2)
+    del s
+    assert b.B == 16
+    a.start(sort=True)
+    Ea = a.run(14, report_every=1, sort_every=6)
+    a.prime()
+    b.start(sort=True)
+    b.prime()
+    Eb = b.run_fused(14, report_every=1, sort_every=6)
+    assert b.uses_scatter_advance()
+    for x, y in zip(a.host_beads(), b.host_beads()):
+        assert np.array_equal(x, y)
+    for ea, eb in zip(Ea, Eb):
+        for key in ("KE", "E_bond", "W"):
+            assert eb[key] == pytest.approx(ea[key], rel=1e-12)
+    assert hpf.hpf_get_device_status() == 0
+
+
 def _check_sort(s, B):
     perm, keys = oracle.sort_perm(s.R, s.tag, s.L, s.M, B)
     st = engine.HpfState.from_system(s, sort_brick=B)
