@@ -326,8 +326,12 @@ __global__ __launch_bounds__(kASThreadsBatch) void k_batch_advance_scatter(
                 bead_fetch<kThermo, kNT>(cur, i, R, Vel, T, bonds, D, Ntot, nullptr, th);
             for (; i < last; i += kASThreadsBatch) {
                 BeadLoads L;
+                if constexpr (kNT)
+                    __builtin_amdgcn_s_setprio(1);
                 bead_issue(L, cur, i, m, K, Gr, R, Ntot);
                 __builtin_amdgcn_sched_barrier(0);
+                if constexpr (kNT)
+                    __builtin_amdgcn_s_setprio(0);
                 BeadIn nxt;
                 bead_fetch<kThermo, kNT>(nxt, min(i + kASThreadsBatch, last - 1), R, Vel, T, bonds, D, Ntot, nullptr,
                                     th);
